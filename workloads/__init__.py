@@ -1,0 +1,270 @@
+"""Seeded, synthetic inputs for the nested VSIE problem.
+
+This module builds *inputs only*: voxel meshes of two nested subdomains with
+surface elements that coincide with voxel faces (the paper's cuboid mesh,
+section "Computational domain"), per-cell material values, incidence
+directions and receiver points.  It contains none of the method's arithmetic
+(no alpha/beta, no Green's function, no weights): both the CPU oracle and the
+GPU path consume these arrays and derive everything else on their own.
+
+Conventions
+-----------
+* Unknown order: volume cells of Omega_1, then Omega_2, then surface elements
+  of Gamma_1, then Gamma_2 (the paper's block order of the 4x4 system).
+* Surface normals point out of the inside subdomain (Gamma_1: out of Omega_1,
+  Gamma_2: out of Omega_2), as in the paper's geometry figure.
+* ``srf_cell_in`` / ``srf_cell_out`` index the volume cells on the two sides
+  of a face; ``-1`` marks the exterior Omega_0.
+* ``vol_nb`` holds, per cell, the indices of the 6 face neighbours in the
+  order (-x, +x, -y, +y, -z, +z) that lie in Omega_1 or Omega_2, else -1.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+__all__ = [
+    "Mesh", "Materials", "voxel_mesh", "nested_balls", "cube_with_ellipsoid",
+    "materials_piecewise", "materials_config", "fibonacci_sphere",
+    "lognormal_voxel_field", "seeded_complex", "CONFIGS", "config_problem",
+]
+
+SEED = 2607
+
+
+@dataclasses.dataclass
+class Mesh:
+    h: float
+    vol_xyz: np.ndarray      # (n_vol, 3) centroids
+    vol_w: np.ndarray        # (n_vol,) volumes
+    vol_dom: np.ndarray      # (n_vol,) int32 in {1, 2}
+    vol_nb: np.ndarray       # (n_vol, 6) int32 neighbour indices or -1
+    srf_xyz: np.ndarray      # (n_srf, 3) centroids
+    srf_n: np.ndarray        # (n_srf, 3) unit normals
+    srf_area: np.ndarray     # (n_srf,)
+    srf_iface: np.ndarray    # (n_srf,) int32 in {1, 2}
+    srf_cell_in: np.ndarray  # (n_srf,) int32
+    srf_cell_out: np.ndarray  # (n_srf,) int32, -1 = exterior
+
+    @property
+    def n_vol(self) -> int:
+        return int(self.vol_w.shape[0])
+
+    @property
+    def n_srf(self) -> int:
+        return int(self.srf_area.shape[0])
+
+    @property
+    def n(self) -> int:
+        return self.n_vol + self.n_srf
+
+    def points(self) -> np.ndarray:
+        """All collocation points, (n, 3), in unknown order."""
+        return np.concatenate([self.vol_xyz, self.srf_xyz], axis=0)
+
+    def counts(self) -> dict:
+        return {
+            "omega1": int(np.sum(self.vol_dom == 1)),
+            "omega2": int(np.sum(self.vol_dom == 2)),
+            "gamma1": int(np.sum(self.srf_iface == 1)),
+            "gamma2": int(np.sum(self.srf_iface == 2)),
+            "n": self.n,
+        }
+
+
+@dataclasses.dataclass
+class Materials:
+    rho0: float
+    c0: float
+    vol_rho: np.ndarray  # (n_vol,)
+    vol_c: np.ndarray    # (n_vol,)
+
+
+def voxel_mesh(lo, hi, N, domain_fn) -> Mesh:
+    """Uniform voxel grid of N^3 cells on the box [lo, hi]^3.
+
+    ``domain_fn(xyz) -> int array`` classifies cell centroids into 0 (exterior),
+    1 or 2.  Faces between a cell of Omega_1/Omega_2 and an exterior cell (or
+    the grid boundary) become Gamma_1 elements; faces between an Omega_2 cell
+    and an Omega_1 cell become Gamma_2 elements.
+    """
+    h = (hi - lo) / N
+    c1d = lo + (np.arange(N) + 0.5) * h
+    X, Y, Z = np.meshgrid(c1d, c1d, c1d, indexing="ij")
+    cen = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    dom = np.asarray(domain_fn(cen), dtype=np.int32).reshape(N, N, N)
+    # volume cells: Omega_1 first, then Omega_2 (each in lexicographic ijk order)
+    flat = dom.ravel()
+    order = np.concatenate([np.nonzero(flat == 1)[0], np.nonzero(flat == 2)[0]])
+    cell_of = -np.ones(N ** 3, dtype=np.int64)
+    cell_of[order] = np.arange(order.size)
+    vol_xyz = cen[order].copy()
+    vol_dom = flat[order].astype(np.int32)
+    vol_w = np.full(order.size, h ** 3)
+
+    ijk = np.stack(np.unravel_index(order, (N, N, N)), axis=1)
+    nb = -np.ones((order.size, 6), dtype=np.int32)
+    for ax in range(3):
+        for side, step in ((0, -1), (1, +1)):
+            q = ijk.copy()
+            q[:, ax] += step
+            inside = (q[:, ax] >= 0) & (q[:, ax] < N)
+            lin = np.full(order.size, -1, dtype=np.int64)
+            lin[inside] = np.ravel_multi_index(q[inside].T, (N, N, N))
+            idx = np.where(inside, cell_of[np.maximum(lin, 0)], -1)
+            nb[:, 2 * ax + side] = idx
+
+    # faces
+    faces = {1: [], 2: []}
+    for ax in range(3):
+        for side, step in ((0, -1), (1, +1)):
+            other = nb[:, 2 * ax + side]
+            # exterior faces: this cell inside, neighbour missing (exterior or out of grid)
+            ext = np.nonzero(other < 0)[0]
+            g2 = np.nonzero((other >= 0) & (vol_dom == 2))[0]
+            g2 = g2[vol_dom[other[g2]] == 1]
+            nvec = np.zeros(3)
+            nvec[ax] = float(step)
+            for iface, cells, outs in ((1, ext, np.full(ext.size, -1)),
+                                       (2, g2, other[g2])):
+                if cells.size == 0:
+                    continue
+                if iface == 1 and np.any(vol_dom[cells] != 1):
+                    raise ValueError("an Omega_2 cell touches the exterior; refine the grid")
+                fx = vol_xyz[cells].copy()
+                fx[:, ax] += step * 0.5 * h
+                faces[iface].append((fx, np.tile(nvec, (cells.size, 1)), cells, outs))
+
+    def cat(iface):
+        if not faces[iface]:
+            return (np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0, np.int32), np.zeros(0, np.int32))
+        fx = np.concatenate([f[0] for f in faces[iface]])
+        fn = np.concatenate([f[1] for f in faces[iface]])
+        ci = np.concatenate([f[2] for f in faces[iface]]).astype(np.int32)
+        co = np.concatenate([f[3] for f in faces[iface]]).astype(np.int32)
+        # deterministic order: sort by centroid (z, y, x)
+        o = np.lexsort((fx[:, 0], fx[:, 1], fx[:, 2]))
+        return fx[o], fn[o], ci[o], co[o]
+
+    f1, f2 = cat(1), cat(2)
+    srf_xyz = np.concatenate([f1[0], f2[0]])
+    srf_n = np.concatenate([f1[1], f2[1]])
+    srf_in = np.concatenate([f1[2], f2[2]])
+    srf_out = np.concatenate([f1[3], f2[3]])
+    srf_iface = np.concatenate([np.full(f1[0].shape[0], 1, np.int32),
+                                np.full(f2[0].shape[0], 2, np.int32)])
+    return Mesh(h=h, vol_xyz=vol_xyz, vol_w=vol_w, vol_dom=vol_dom, vol_nb=nb,
+                srf_xyz=srf_xyz, srf_n=srf_n, srf_area=np.full(srf_xyz.shape[0], h * h),
+                srf_iface=srf_iface, srf_cell_in=srf_in, srf_cell_out=srf_out)
+
+
+def nested_balls(N: int, R1: float = 1.0, R2: float = 0.5) -> Mesh:
+    """Staircase voxel mesh of two concentric balls on an N^3 grid over [-R1, R1]^3."""
+    def dom(x):
+        r = np.sqrt(np.sum(x * x, axis=1))
+        return np.where(r < R2, 2, np.where(r < R1, 1, 0))
+    return voxel_mesh(-R1, R1, N, dom)
+
+
+def cube_with_ellipsoid(N: int, centre=(0.05, 0.10, -0.10), axes=(0.4, 0.3, 0.2)) -> Mesh:
+    """Unit cube [-0.5, 0.5]^3 (Omega_1) holding an axis-aligned ellipsoid (Omega_2)."""
+    c = np.asarray(centre)
+    a = np.asarray(axes)
+
+    def dom(x):
+        q = np.sum(((x - c) / a) ** 2, axis=1)
+        return np.where(q < 1.0, 2, 1)
+    return voxel_mesh(-0.5, 0.5, N, dom)
+
+
+def materials_piecewise(mesh: Mesh, rho0, c0, rho1, c1, rho2, c2) -> Materials:
+    """Piecewise values per subdomain; c1/c2/rho1/rho2 may be callables of xyz."""
+    x = mesh.vol_xyz
+    d = mesh.vol_dom
+
+    def ev(v, sel):
+        if callable(v):
+            return np.asarray(v(x[sel]), dtype=np.float64)
+        return np.full(int(np.sum(sel)), float(v))
+
+    rho = np.empty(mesh.n_vol)
+    c = np.empty(mesh.n_vol)
+    for dd, r_, c_ in ((1, rho1, c1), (2, rho2, c2)):
+        sel = d == dd
+        rho[sel] = ev(r_, sel)
+        c[sel] = ev(c_, sel)
+    return Materials(rho0=float(rho0), c0=float(c0), vol_rho=rho, vol_c=c)
+
+
+def fibonacci_sphere(m: int, radius: float = 1.0) -> np.ndarray:
+    """m nearly uniform points on a sphere (golden-angle spiral), (m, 3)."""
+    i = np.arange(m) + 0.5
+    z = 1.0 - 2.0 * i / m
+    r = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    phi = i * math.pi * (3.0 - math.sqrt(5.0))
+    return radius * np.stack([r * np.cos(phi), r * np.sin(phi), z], axis=1)
+
+
+def lognormal_voxel_field(xyz: np.ndarray, lo, hi, grid: int, sigma: float, stream: int,
+                          seed: int = SEED) -> np.ndarray:
+    """exp(sigma * xi) with xi ~ N(0,1) i.i.d. on a grid^3 voxel field over [lo,hi]^3.
+
+    Each point takes the voxel containing it.  ``stream`` selects an independent
+    PCG64 stream (0 for sound speed, 1 for density).
+    """
+    rng = np.random.default_rng([seed, stream])
+    xi = rng.standard_normal((grid, grid, grid))
+    idx = np.clip(np.floor((xyz - lo) / (hi - lo) * grid).astype(np.int64), 0, grid - 1)
+    return np.exp(sigma * xi[idx[:, 0], idx[:, 1], idx[:, 2]])
+
+
+def seeded_complex(shape, seed: int = SEED) -> np.ndarray:
+    """Complex128 array with i.i.d. standard normal real and imaginary parts."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+# ---------------------------------------------------------------------------
+# the five workloads (nested spheres, heterogeneous core, batched incidences,
+# log-normal medium with receivers, large cube + ellipsoid)
+
+def _c_core(x):
+    return 0.8 * (1.0 + 0.2 * np.exp(-np.sum(x * x, axis=1) / 0.05))
+
+
+CONFIGS = {
+    "c0": dict(kind="balls", N=16, k0=[2.0], dirs="z", core="const"),
+    "c1": dict(kind="balls", N=48, k0=[10.0], dirs="z", core="smooth"),
+    "c2": dict(kind="balls", N=57, k0=[16.0], dirs=128, core="smooth"),
+    "c3": dict(kind="balls", N=48, k0=[10.0], dirs=8, core="lognormal", receivers=256),
+    "c4": dict(kind="cube", N=100, k0=[40.0 - 2.0 * i for i in range(8)], dirs=16, core="lognormal4"),
+}
+
+
+def config_problem(name: str, N: int | None = None):
+    """Return (mesh, materials, k0 list, directions (R,3), receivers or None)."""
+    cfg = dict(CONFIGS[name])
+    if N is not None:
+        cfg["N"] = N
+    if cfg["kind"] == "balls":
+        mesh = nested_balls(cfg["N"])
+        if cfg["core"] == "const":
+            mat = materials_piecewise(mesh, 1.0, 1.0, 1.2, 1.5, 2.0, 0.8)
+        else:
+            mat = materials_piecewise(mesh, 1.0, 1.0, 1.2, 1.5, 2.0, _c_core)
+        if cfg["core"] == "lognormal":
+            x = mesh.vol_xyz
+            mat.vol_c = mat.vol_c * lognormal_voxel_field(x, -1.0, 1.0, 32, 0.1, 0)
+            mat.vol_rho = mat.vol_rho * lognormal_voxel_field(x, -1.0, 1.0, 32, 0.1, 1)
+    else:
+        mesh = cube_with_ellipsoid(cfg["N"])
+        mat = materials_piecewise(mesh, 1.0, 1.0, 1.1, 1.3, 2.0, 0.8)
+        mat.vol_c = mat.vol_c * lognormal_voxel_field(mesh.vol_xyz, -0.5, 0.5, 32, 0.1, 0)
+    if cfg["dirs"] == "z":
+        dirs = np.array([[0.0, 0.0, 1.0]])
+    else:
+        dirs = fibonacci_sphere(int(cfg["dirs"]))
+    rec = fibonacci_sphere(cfg["receivers"], 3.0) if cfg.get("receivers") else None
+    return mesh, mat, list(cfg["k0"]), dirs, rec

@@ -364,16 +364,18 @@ def gmres(apply, b, tol=1e-12, restart=200, maxiter=2000, x0=None, callback=None
             H[k + 1, k] = np.linalg.norm(w)
             if H[k + 1, k] != 0:
                 V[:, k + 1] = w / H[k + 1, k]
+            # unitary rotations [[conj(c), conj(s)], [-s, c]] with c = a/rho, s = b/rho
+            # map (a, b) to (rho, 0); the same rotation acts on later columns and on g
             for j in range(k):
-                t = cs[j] * H[j, k] + sn[j] * H[j + 1, k]
-                H[j + 1, k] = -np.conj(sn[j]) * H[j, k] + np.conj(cs[j]) * H[j + 1, k]
+                t = np.conj(cs[j]) * H[j, k] + np.conj(sn[j]) * H[j + 1, k]
+                H[j + 1, k] = -sn[j] * H[j, k] + cs[j] * H[j + 1, k]
                 H[j, k] = t
             den = math.hypot(abs(H[k, k]), abs(H[k + 1, k]))
             cs[k] = H[k, k] / den
             sn[k] = H[k + 1, k] / den
             H[k, k] = den
             H[k + 1, k] = 0
-            g[k + 1] = -np.conj(sn[k]) * g[k]
+            g[k + 1] = -sn[k] * g[k]
             g[k] = np.conj(cs[k]) * g[k]
             it += 1
             k_done = k + 1

@@ -423,3 +423,24 @@ def test_gmres_matches_lu():
     p_lu = O.solve_lu(d, b)
     p_gm, it, res = O.solve_gmres(d, b, tol=1e-12)
     assert res <= 1e-12 and O.rel_error(p_gm, p_lu) < 1e-10
+
+
+def test_gmres_single_cycle_on_random_complex_system():
+    """One GMRES cycle on a random complex system: the Givens residual estimate
+    must equal the true residual of the returned iterate (exact arithmetic
+    identity of GMRES), and the solve must agree with a dense solve."""
+    rng = np.random.default_rng(5)
+    n = 80
+    Am = np.eye(n) + 0.3 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / math.sqrt(n)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    est = []
+    x, it, res = O.gmres(lambda v: Am @ v, b, tol=1e-12, restart=200,
+                         callback=lambda i, r: est.append(r))
+    assert it == len(est) and res <= 1e-12
+    assert abs(est[-1] - res) <= 1e-12
+    assert np.linalg.norm(x - np.linalg.solve(Am, b)) <= 1e-10 * np.linalg.norm(x)
+    # a truncated single cycle: estimate and true residual agree too
+    est = []
+    x5, it5, res5 = O.gmres(lambda v: Am @ v, b, tol=1e-30, restart=15, maxiter=15,
+                            callback=lambda i, r: est.append(r))
+    assert it5 == 15 and abs(est[-1] - res5) <= 1e-12 * max(1.0, res5) + 1e-14

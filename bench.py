@@ -1,0 +1,188 @@
+"""Benchmark of the nested-VSIE hot path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+
+Workload (the heterogeneous nested-sphere configuration): concentric balls of
+radius 1 and 0.5 on a 48^3 voxel grid over [-1, 1]^3 -- 57,856 cells and
+13,512 interface faces, n = 71,368 unknowns -- exterior rho0 = c0 = 1, shell
+rho = 1.2, c = 1.5, core rho = 2, c(x) = 0.8 (1 + 0.2 exp(-|x|^2/0.05)),
+plane wave along +z with k0 = 10.
+
+One step = the whole hot path once: per-element weights from the per-cell
+materials, the plane-wave right-hand side, and the GMRES solve with the FP32
+operator inside FP64 iterative refinement to relative residual 1e-10.  The
+plain FP64 solve is timed beside it.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GMRES solve s and Gpair-evals/s at 1e-8 rel err: FP64 vs FP32+refine, 1 GPU"
+GOLD = os.path.join(ROOT, "tests", "golden", "c1_oracle_solution.npz")
+VALU_PEAK = 256 * 4 * 16 * 2.4e9   # lane-instructions/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+TOL = 1e-10
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="target CPU time of the oracle sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(mesh, mat, k0, n, target_s):
+    """The FP64 oracle's direct summation on a bounded sample of rows."""
+    import oracle as O
+    import workloads as W
+    d = O.discretise(mesh, mat, k0)
+    x = W.seeded_complex(n, seed=31)
+    rng = np.random.default_rng(32)
+    rows = np.sort(rng.choice(n, 1024, replace=False))
+    t = time.perf_counter()
+    O.matvec(d, x, rows=rows)
+    dt = time.perf_counter() - t
+    m = int(min(n, max(1024, 1024 * target_s / max(dt, 1e-3))))
+    rows = np.sort(rng.choice(n, m, replace=False))
+    t = time.perf_counter()
+    O.matvec(d, x, rows=rows)
+    dt = time.perf_counter() - t
+    pairs = float(m) * n
+    return {"value": pairs / dt / 1e9, "unit": "Gpair-evals/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": "FP64 oracle matvec (C, OpenMP, compensated sums) on %d seeded rows of the "
+                      "%d-row operator: %.3g pair evaluations in %.2f s" % (m, n, pairs, dt),
+            "seconds": dt}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: this build has no multi-GPU path (requested --gpus %d)"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2607_06429_amd as V
+    import workloads as W
+
+    assert torch.cuda.is_available(), "needs a GPU"
+    torch.cuda.set_device(0)
+    mesh, mat, k0s, dirs, _ = W.config_problem("c1")
+    k0 = k0s[0]
+    P = V.Problem.from_mesh(mesh, mat, k0s)
+    n = P.n
+    rho = torch.as_tensor(mat.vol_rho, device="cuda")
+    c = torch.as_tensor(mat.vol_c, device="cuda")
+
+    def step(prec):
+        P.set_materials(rho, c)                     # weights from the materials
+        b = P.plane_wave(dirs[0])                   # right-hand side
+        x, info = P.solve(b, prec=prec, tol=TOL)    # GMRES (+ refinement)
+        return x, info
+
+    for _ in range(args.warmup):
+        step(V.VSIE_FP32)
+    torch.cuda.synchronize()
+
+    # timed region: K steps of the FP32 + FP64-refinement path
+    P.profile(True)
+    infos = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        x32, info = step(V.VSIE_FP32)
+        infos.append(info)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    P.profile(False)
+    kstats = P.kernel_stats()
+    ms_per_step = elapsed / args.steps * 1e3
+
+    # the plain FP64 path, same steps
+    ksteps64 = max(1, min(args.steps, 3))
+    step(V.VSIE_FP64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(ksteps64):
+        x64, info64 = step(V.VSIE_FP64)
+    torch.cuda.synchronize()
+    ms64 = (time.perf_counter() - t0) / ksteps64 * 1e3
+
+    # pair evaluations of one step (all operator applications, both precisions)
+    mv32 = infos[-1]["matvecs_fp32"]
+    mv64 = infos[-1]["matvecs_fp64"]
+    pairs_step = float(n) * n * (mv32 + mv64)
+    value = pairs_step * args.steps / elapsed / 1e9
+
+    err = {}
+    if os.path.exists(GOLD):
+        g = np.load(GOLD)["p"]
+        for nm, xv in (("fp32_refine", x32), ("fp64", x64)):
+            xh = xv.cpu().numpy()
+            err[nm] = float(np.linalg.norm(xh - g) / np.linalg.norm(g))
+
+    # roofline of the dominant kernel: the FP32 single-layer pair kernel
+    counts = json.load(open(os.path.join(ROOT, "paper_2607_06429_amd", "isa_counts.json")))
+    dom = max(kstats.items(), key=lambda kv: kv[1]["ms"])
+    dom_name, st = dom
+    per_pair = counts[dom_name + "_R1"]["valu_per_pair"]
+    avg_ms = st["ms"] / st["launches"]
+    pairs_launch = st["pairs"] / st["launches"]
+    achieved = per_pair * pairs_launch / (avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": dom_name, "achieved": achieved,
+                "peak": VALU_PEAK / 1e12, "unit": "T VALU lane-ops/s", "frac": achieved / (VALU_PEAK / 1e12),
+                "traffic": None, "valu_per_pair": per_pair, "avg_launch_ms": avg_ms,
+                "launches": st["launches"], "pairs_per_launch": pairs_launch,
+                "gpairs_per_s": pairs_launch / (avg_ms * 1e-3) / 1e9}
+    kernel_summary = {k: {"launches": v["launches"], "avg_ms": v["ms"] / v["launches"],
+                          "gpairs_per_s": v["pairs"] / v["ms"] * 1e-6} for k, v in kstats.items()}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "Gpair-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "nested balls R=1/0.5, 48^3 voxel grid, n=71368, k0=10, "
+                              "smooth core sound speed, plane wave +z; FP32 operator in "
+                              "FP64 iterative refinement to rel. residual 1e-10",
+                   "n": n, "k0": k0, "tol": TOL},
+        "solve_s_fp32_refine": ms_per_step / 1e3,
+        "solve_s_fp64": ms64 / 1e3,
+        "speedup_fp32_refine_vs_fp64": ms64 / ms_per_step,
+        "iterations": {"fp32_refine": infos[-1], "fp64": info64},
+        "gpairs_per_s_fp64_solve": float(n) * n * (info64["matvecs_fp64"]) / (ms64 * 1e-3) / 1e9,
+        "rel_err_vs_oracle": err or None,
+        "kernels": kernel_summary,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(mesh, mat, k0, n, args.cpu_seconds)
+        cb["solve_s_extrapolated_fp64"] = float(n) * n * info64["matvecs_fp64"] / (cb["value"] * 1e9)
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+    P.close()
+
+
+if __name__ == "__main__":
+    main()

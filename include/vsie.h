@@ -1,0 +1,203 @@
+/*
+ * vsie.h -- C ABI of libvsie.so, the MI355X (gfx950) implementation of the
+ * discretised nested volume-surface integral equation (VSIE) for acoustics.
+ *
+ * The operator is the collocation form of the final VSIE (Theorem 3, eq_vsie,
+ * of "Nested Volume-Surface Integral Equations for Acoustics"):
+ *
+ *     (A p)_i = m_i p_i - (V p)_i + (T p)_i + (K p)_i
+ *
+ * over the unknowns (p_Omega1, p_Omega2, p_Gamma1, p_Gamma2) of the 4x4 block
+ * system (section 2.3.4), with P0 elements, collocation at element centroids,
+ * the one-point (midpoint) rule for every off-diagonal integral and the
+ * weakly singular self-term of V integrated on the sphere of equal volume
+ * (section 2.3.5).  For i != j:
+ *
+ *     A_ij = -G(r_ij) s_j + F(r_ij) (x_i - y_j) . v_j,
+ *     G(r) = exp(i k0 r) / (4 pi r),    F(r) = exp(i k0 r)(i k0 r - 1) / (4 pi r^3)
+ *
+ * volume cell j : s_j = |cell| (beta - k0^2 alpha)(y_j)   (eq_alpha, eq_beta)
+ *                 v_j = |cell| grad alpha(y_j)
+ * surface elt j : s_j = 0,  v_j = -|face| (alpha_inside - alpha_outside) n_j
+ * diagonal      : A_ii = m_i - (s_i/|cell_i|) S(a_i, k0) on cells (eq_mass_function
+ *                 for m; S = integral of G over the ball of radius a_i of equal
+ *                 volume), A_ii = m_i on surface elements.
+ *
+ * Conventions for every call
+ * --------------------------
+ * * Complex vectors live in device memory as interleaved (re, im) doubles
+ *   (complex128), column-major n x nrhs with a leading dimension counted in
+ *   complex elements (ld >= n).  Unknown order: volume cells in the caller's
+ *   order, then surface elements in the caller's order (callers pass Omega_1
+ *   then Omega_2, Gamma_1 then Gamma_2, the paper's block order).
+ * * `stream` is a hipStream_t (NULL selects the null stream).  Calls enqueue
+ *   work on it; vsie_solve synchronises it to read scalars each iteration.
+ * * No exception crosses the ABI: every call returns a vsie_status, and
+ *   vsie_last_error() gives a message for the calling thread's last failure.
+ * * Memory: input host arrays are copied during vsie_assemble; the problem
+ *   owns its device arrays (geometry, weights, work buffers) until
+ *   vsie_destroy.  Vectors x, y, b are owned by the caller.
+ * * A problem handle may be used from one host thread at a time.
+ */
+#ifndef VSIE_H
+#define VSIE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VSIE_OK = 0,
+    VSIE_E_INVALID = 1,   /* bad argument: NULL pointer, size, index, material, normal */
+    VSIE_E_DEVICE = 2,    /* a HIP runtime call failed */
+    VSIE_E_NOMEM = 3,     /* device allocation failed */
+    VSIE_E_NOCONV = 4,    /* solver stopped at max_iter; x holds the last iterate */
+    VSIE_E_NAN = 5        /* a non-finite value appeared in a residual norm */
+} vsie_status;
+
+/* Arithmetic of the operator.
+ * VSIE_FP64: every pair term in FP64.
+ * VSIE_FP32: pair terms and their sums over a tile of sources in FP32, with
+ *   target-source distances and the phase k0 r reduced in FP64, tile sums
+ *   gathered in FP64; the diagonal (mass function and self-terms) stays FP64.
+ *   In vsie_solve this selects FP32 GMRES inner solves inside FP64 iterative
+ *   refinement (residuals b - A x with the FP64 operator). */
+typedef enum { VSIE_FP64 = 0, VSIE_FP32 = 1 } vsie_precision;
+
+typedef struct vsie_problem vsie_problem;
+
+/* Mesh of the nested domains (section 2.3.1: cuboid cells, surface elements
+ * that match cell faces).  All arrays are host memory, read during
+ * vsie_assemble only. */
+typedef struct {
+    int64_t n_vol;                  /* number of volume cells (>= 0) */
+    const double *vx, *vy, *vz;     /* cell centroids */
+    const double *vw;               /* cell volumes (> 0) */
+    const int32_t *vdom;            /* subdomain of each cell: 1 or 2 */
+    const int32_t *vnb;             /* 6*n_vol face neighbours (-x,+x,-y,+y,-z,+z),
+                                       -1 for none; NULL means no neighbours */
+    const double *vgrad_alpha;      /* optional 3*n_vol (x,y,z per cell) grad alpha
+                                       overriding the neighbour stencil; or NULL */
+    int64_t n_srf;                  /* number of surface elements (>= 0) */
+    const double *sx, *sy, *sz;     /* element centroids */
+    const double *snx, *sny, *snz;  /* unit normals pointing out of the inside
+                                       subdomain (|n| = 1 within 1e-12) */
+    const double *sarea;            /* element areas (> 0) */
+    const int32_t *siface;          /* 1 (Gamma_1) or 2 (Gamma_2) */
+    const int32_t *scell_in;        /* cell on the inside of the face */
+    const int32_t *scell_out;       /* cell on the outside, -1 = exterior Omega_0 */
+    double rho0, c0;                /* exterior density and speed of sound (> 0) */
+} vsie_geometry;
+
+/* Build a problem: validate and upload the mesh and the per-cell materials,
+ * and compute the per-element weights for n_freq exterior wavenumbers k0[f]
+ * (omega_f = k0[f] c0).
+ *   vrho, vc : host arrays of n_vol cell densities and sound speeds (> 0).
+ * Interface limit densities are those of the cells on either side of a face.
+ * grad alpha (when vgrad_alpha is NULL) is a per-axis central difference of
+ * alpha = rho0/rho - 1 over the face neighbours in the same subdomain,
+ * one-sided with one such neighbour and zero with none.
+ * On success *out receives a new handle; on failure *out is NULL. */
+vsie_status vsie_assemble(const vsie_geometry *geom, const double *vrho, const double *vc,
+                          const double *k0, int32_t n_freq, void *stream, vsie_problem **out);
+
+/* Replace the per-cell materials from DEVICE arrays (n_vol doubles each) and
+ * recompute every weight (used between solves of an optimisation loop).  The
+ * set of nonzero source terms may change; the call synchronises `stream`. */
+vsie_status vsie_set_materials(vsie_problem *p, const double *vrho_dev, const double *vc_dev,
+                               void *stream);
+
+/* Number of unknowns n = n_vol + n_srf (0 for a NULL handle). */
+int64_t vsie_size(const vsie_problem *p);
+
+/* y = A_f x for nrhs right-hand sides at frequency index f.
+ * x, y: device complex128, n x nrhs, leading dimensions ldx, ldy; x and y
+ * must not overlap. */
+vsie_status vsie_matvec(vsie_problem *p, int32_t f, vsie_precision prec, int64_t nrhs,
+                        const double *x, int64_t ldx, double *y, int64_t ldy, void *stream);
+
+/* y = A_f^H x (conjugate transpose), same layout rules as vsie_matvec. */
+vsie_status vsie_matvec_adjoint(vsie_problem *p, int32_t f, vsie_precision prec, int64_t nrhs,
+                                const double *x, int64_t ldx, double *y, int64_t ldy,
+                                void *stream);
+
+typedef struct {
+    double tol;          /* stop when ||b - A x|| <= tol ||b|| (FP64 residual); default 1e-10 */
+    int32_t max_iter;    /* total GMRES iterations (all cycles, all outer steps); default 3000 */
+    int32_t restart;     /* Krylov dimension per cycle; default 500 */
+    double inner_tol;    /* VSIE_FP32 only: relative tolerance of each inner solve; default 1e-5 */
+    int32_t max_outer;   /* VSIE_FP32 only: refinement steps; default 20 */
+} vsie_solve_opts;
+
+typedef struct {
+    int32_t iterations;     /* GMRES iterations summed over right-hand sides */
+    int32_t outer_steps;    /* refinement steps (VSIE_FP32), 1 for VSIE_FP64 */
+    int32_t matvecs_fp64;   /* operator applications in FP64 (per right-hand side) */
+    int32_t matvecs_fp32;   /* operator applications in FP32 (per right-hand side) */
+    double rel_residual;    /* max over right-hand sides of ||b - A x|| / ||b|| */
+} vsie_solve_info;
+
+/* Solve A_f x = b (adjoint = 0) or A_f^H x = b (adjoint = 1) by GMRES without
+ * preconditioning (section 3.1), restarted every opts->restart iterations.
+ * x holds the initial guess on entry and the solution on exit.  opts may be
+ * NULL (defaults); info may be NULL.  Returns VSIE_E_NOCONV when the
+ * tolerance was not reached (x still holds the last iterate). */
+vsie_status vsie_solve(vsie_problem *p, int32_t f, vsie_precision prec, int32_t adjoint,
+                       int64_t nrhs, const double *b, int64_t ldb, double *x, int64_t ldx,
+                       const vsie_solve_opts *opts, vsie_solve_info *info, void *stream);
+
+/* b[:, r] = exp(i k0_f x_i . d_r) at every collocation point for ndir unit
+ * directions given as a HOST array of 3*ndir doubles (eq_planewave). */
+vsie_status vsie_plane_wave(vsie_problem *p, int32_t f, int64_t ndir, const double *dirs,
+                            double *b, int64_t ldb, void *stream);
+
+/* out[t, r] = sum_j A_f(x_t, j) x[j, r] at n_t arbitrary target points given
+ * as DEVICE arrays tx, ty, tz (the off-diagonal kernel with no self term).
+ * The exterior field of section 2.3.1 is p(x) = p_inc(x) - out. */
+vsie_status vsie_field(vsie_problem *p, int32_t f, vsie_precision prec, int64_t n_t,
+                       const double *tx, const double *ty, const double *tz, int64_t nrhs,
+                       const double *x, int64_t ldx, double *out, int64_t ldo, void *stream);
+
+/* Source-side sums for adjoint-state gradients:
+ *   z[j, r]      = sum_t conj(G(|x_t - y_j|)) lam[t, r]
+ *   Z[j, r, a]   = sum_t conj(F(|x_t - y_j|)) (x_t - y_j)_a lam[t, r]
+ * Targets are the collocation points themselves (t != j) when tx is NULL
+ * (n_t must then equal n), otherwise n_t DEVICE points.  z: n x nrhs,
+ * ldz >= n; Z: n x (3 nrhs), column 3 r + a, ldZ >= n. */
+vsie_status vsie_source_sums(vsie_problem *p, int32_t f, int64_t n_t, const double *tx,
+                             const double *ty, const double *tz, int64_t nrhs,
+                             const double *lam, int64_t ldl, double *z, int64_t ldz, double *Z,
+                             int64_t ldZ, void *stream);
+
+/* Kernel timing.  vsie_profile(p, 1) clears the counters and starts recording
+ * a pair of HIP events around every pair-kernel launch made for p (on the
+ * stream of the call that launches it); vsie_profile(p, 0) stops recording.
+ * vsie_profile_read synchronises the recorded events and reports, for one
+ * kernel kind, the number of launches, their summed duration in ms and the
+ * summed pair evaluations (thread points x streamed points per launch; a
+ * launch with R right-hand sides counts its pairs once and R in rhs_pairs).
+ * kind = 2 * mode + precision with mode 0 forward single layer, 1 forward
+ * double layers (T and K), 2 adjoint double layers, 3 adjoint source sums,
+ * and precision VSIE_FP64 or VSIE_FP32. */
+typedef struct {
+    int64_t launches;
+    double ms;
+    double pairs;
+    double rhs_pairs;
+} vsie_kernel_stats;
+vsie_status vsie_profile(vsie_problem *p, int32_t enable);
+vsie_status vsie_profile_read(vsie_problem *p, int32_t kind, vsie_kernel_stats *out);
+
+/* Free the problem and all device memory it owns.  NULL is ignored. */
+void vsie_destroy(vsie_problem *p);
+
+/* Message of the calling thread's most recent failed call ("" if none). */
+const char *vsie_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VSIE_H */

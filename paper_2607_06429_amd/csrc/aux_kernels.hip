@@ -1,0 +1,481 @@
+// O(n) kernels of the VSIE path: per-element weights, charge packing,
+// reduction of pair-kernel partial sums with the diagonal, plane waves, and
+// the dense complex vector operations of the Krylov solver.
+#include "vsie_internal.h"
+
+namespace vsie {
+namespace {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+constexpr double kInv4Pi = 1.0 / (4.0 * kPi);
+constexpr int kT = 256;
+
+inline unsigned blocks_for(int64_t n, int per = kT) {
+    return static_cast<unsigned>((n + per - 1) / per);
+}
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Integral of G_k(0, y) over the ball of radius a (the paper's equal-volume
+// sphere self-term): ((1 - i k a) exp(i k a) - 1) / k^2, evaluated through its
+// power series (1/k^2) sum_{n>=2} (i k a)^n (1 - n) / n! when k a < 0.5.
+__device__ double2 ball_self_integral(double a, double k) {
+    const double ka = k * a;
+    if (ka < 0.5) {
+        // term_n = (i k a)^n / n!, starting at n = 2
+        double2 t = make_double2(-0.5 * ka * ka, 0.0);
+        double2 acc = make_double2(-t.x, -t.y);  // (1 - 2) * term_2
+        for (int n = 3; n < 30; ++n) {
+            t = cmul(t, make_double2(0.0, ka / n));
+            acc.x += (1 - n) * t.x;
+            acc.y += (1 - n) * t.y;
+        }
+        return make_double2(acc.x / (k * k), acc.y / (k * k));
+    }
+    double sn, cs;
+    sincos(ka, &sn, &cs);
+    // (1 - i ka)(cs + i sn) - 1
+    const double re = cs + ka * sn - 1.0;
+    const double im = sn - ka * cs;
+    return make_double2(re / (k * k), im / (k * k));
+}
+
+__global__ void weights_kernel(DeviceMesh m, const double *__restrict__ k0, int n_freq) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+    if (e >= m.n) return;
+    const double rho0 = m.rho0, c0 = m.c0;
+    if (e < m.n_vol) {
+        const double rho = m.vrho[e], c = m.vc[e], w = m.vw[e];
+        const double contrast = rho0 / rho;              // 1 + alpha
+        const double mass = contrast;                    // mass function inside a subdomain
+        // grad alpha: explicit, or per-axis differences over same-subdomain neighbours
+        double ga[3] = {0.0, 0.0, 0.0};
+        if (m.vga) {
+            for (int ax = 0; ax < 3; ++ax) ga[ax] = m.vga[3 * e + ax];
+        } else if (m.vnb) {
+            const double *pc[3] = {m.px, m.py, m.pz};
+            const int dom = m.vdom[e];
+            for (int ax = 0; ax < 3; ++ax) {
+                const int lo = m.vnb[6 * e + 2 * ax], hi = m.vnb[6 * e + 2 * ax + 1];
+                const bool lok = lo >= 0 && m.vdom[lo] == dom;
+                const bool hok = hi >= 0 && m.vdom[hi] == dom;
+                if (!lok && !hok) continue;
+                const int64_t a = lok ? lo : e, b = hok ? hi : e;
+                const double aa = rho0 / m.vrho[a] - 1.0, ab = rho0 / m.vrho[b] - 1.0;
+                ga[ax] = (ab - aa) / (pc[ax][b] - pc[ax][a]);
+            }
+        }
+        m.vpx[e] = w * ga[0] * kInv4Pi;
+        m.vpy[e] = w * ga[1] * kInv4Pi;
+        m.vpz[e] = w * ga[2] * kInv4Pi;
+        m.mass[e] = mass;
+        const double a_eq = cbrt(3.0 * w / (4.0 * kPi));
+        const double cr = c0 / c;
+        for (int f = 0; f < n_freq; ++f) {
+            const double k = k0[f];
+            // |cell| (beta - k0^2 alpha) = |cell| (rho0/rho)(k_c^2 - k0^2), k_c = k0 c0 / c
+            const double wt = contrast * k * k * (cr * cr - 1.0);
+            m.sp[f * m.n + e] = w * wt * kInv4Pi;
+            const double2 S = ball_self_integral(a_eq, k);
+            m.diag[f * m.n + e] = make_double2(mass - wt * S.x, -wt * S.y);
+        }
+    } else {
+        const int64_t q = e - m.n_vol;
+        const double rin = m.vrho[m.scin[q]];
+        const int co = m.scout[q];
+        const double rout = co >= 0 ? m.vrho[co] : rho0;
+        // alpha_inside - alpha_outside and the averaged contrast (mass function on Gamma)
+        const double jump = rho0 / rin - rho0 / rout;
+        const double mass = 0.5 * (rho0 / rin + rho0 / rout);
+        const double g = -m.sarea[q] * jump * kInv4Pi;
+        m.vpx[e] = g * m.snx[q];
+        m.vpy[e] = g * m.sny[q];
+        m.vpz[e] = g * m.snz[q];
+        m.mass[e] = mass;
+        for (int f = 0; f < n_freq; ++f) {
+            m.sp[f * m.n + e] = 0.0;
+            m.diag[f * m.n + e] = make_double2(mass, 0.0);
+        }
+    }
+}
+
+template <typename C2>
+__device__ inline C2 to_c2(double re, double im);
+template <> __device__ inline double2 to_c2<double2>(double re, double im) { return make_double2(re, im); }
+template <> __device__ inline float2 to_c2<float2>(double re, double im) {
+    return make_float2(static_cast<float>(re), static_cast<float>(im));
+}
+
+// charge[r * count + jj] = scale_jj * x[idx[jj] + r ldx] (conjugated first when conj_in),
+// with scale_jj = -s'[idx[jj]] for the single-layer class, 1 otherwise.
+template <typename C2>
+__global__ void pack_kernel(int64_t count, const int32_t *__restrict__ idx,
+                            const double *__restrict__ sp, int nrhs,
+                            const double2 *__restrict__ x, int64_t ldx, bool conj_in,
+                            C2 *__restrict__ out) {
+    const int64_t jj = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+    if (jj >= count) return;
+    const int64_t j = idx ? idx[jj] : jj;
+    const double sc = sp ? -sp[j] : 1.0;
+    for (int r = 0; r < nrhs; ++r) {
+        double2 v = x[j + r * ldx];
+        if (conj_in) v.y = -v.y;
+        out[jj + r * count] = to_c2<C2>(sc * v.x, sc * v.y);
+    }
+}
+
+// y[i + r ldy] = d_i x[i + r ldx] + sum_c partial[(c nrhs + r) n_t + i],
+// d_i = diag[i] (conjugated when conj_diag); diag == nullptr means d_i = 0.
+__global__ void reduce_kernel(int64_t n_t, int nrhs, int n_parts, const double2 *__restrict__ part,
+                              const double2 *__restrict__ diag, bool conj_diag,
+                              const double2 *__restrict__ x, int64_t ldx, double2 *__restrict__ y,
+                              int64_t ldy) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+    if (i >= n_t) return;
+    double2 d = diag ? diag[i] : make_double2(0.0, 0.0);
+    if (conj_diag) d.y = -d.y;
+    for (int r = 0; r < nrhs; ++r) {
+        double2 acc = make_double2(0.0, 0.0);
+        if (diag) acc = cmul(d, x[i + r * ldx]);
+        for (int c = 0; c < n_parts; ++c) {
+            const double2 p = part[(static_cast<int64_t>(c) * nrhs + r) * n_t + i];
+            acc.x += p.x;
+            acc.y += p.y;
+        }
+        y[i + r * ldy] = acc;
+    }
+}
+
+// y[idx[jj] + r ldy] += conj(scale_jj * sum_c partial[(c nrhs + r) count + jj]),
+// scale_jj = -s'[idx[jj]] (single-layer class) or 1.
+__global__ void scatter_conj_kernel(int64_t count, const int32_t *__restrict__ idx,
+                                    const double *__restrict__ sp, int nrhs, int n_parts,
+                                    const double2 *__restrict__ part, double2 *__restrict__ y,
+                                    int64_t ldy) {
+    const int64_t jj = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+    if (jj >= count) return;
+    const int64_t j = idx[jj];
+    const double sc = sp ? -sp[j] : 1.0;
+    for (int r = 0; r < nrhs; ++r) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int c = 0; c < n_parts; ++c) {
+            const double2 p = part[(static_cast<int64_t>(c) * nrhs + r) * count + jj];
+            acc.x += p.x;
+            acc.y += p.y;
+        }
+        double2 v = y[j + r * ldy];
+        v.x += sc * acc.x;
+        v.y -= sc * acc.y;
+        y[j + r * ldy] = v;
+    }
+}
+
+// z[j + r ldz] = conj(sum_c P[c][4r][j]) / (4 pi),
+// Z[j + (3r + a) ldZ] = conj(sum_c P[c][4r + 1 + a][j]) / (4 pi).
+__global__ void sums_reduce_kernel(int64_t n, int nrhs, int n_parts, const double2 *__restrict__ part,
+                                   double2 *__restrict__ z, int64_t ldz, double2 *__restrict__ Z,
+                                   int64_t ldZ) {
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+    if (j >= n) return;
+    for (int r = 0; r < nrhs; ++r) {
+        for (int comp = 0; comp < 4; ++comp) {
+            double2 acc = make_double2(0.0, 0.0);
+            for (int c = 0; c < n_parts; ++c) {
+                const double2 p = part[(static_cast<int64_t>(c) * nrhs * 4 + 4 * r + comp) * n + j];
+                acc.x += p.x;
+                acc.y += p.y;
+            }
+            const double2 v = make_double2(acc.x * kInv4Pi, -acc.y * kInv4Pi);
+            if (comp == 0) z[j + r * ldz] = v;
+            else Z[j + (3 * r + comp - 1) * ldZ] = v;
+        }
+    }
+}
+
+__global__ void plane_wave_kernel(int64_t n, const double *__restrict__ px, const double *__restrict__ py,
+                                  const double *__restrict__ pz, double k, double dx, double dy,
+                                  double dz, double2 *__restrict__ b) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+    if (i >= n) return;
+    double sn, cs;
+    sincos(k * (px[i] * dx + py[i] * dy + pz[i] * dz), &sn, &cs);
+    b[i] = make_double2(cs, sn);
+}
+
+// --- Krylov vector kernels (complex128, column-major) ------------------------
+
+template <int BS>
+__device__ inline double2 block_sum2(double2 v, double2 *sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = BS / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            sh[threadIdx.x].x += sh[threadIdx.x + s].x;
+            sh[threadIdx.x].y += sh[threadIdx.x + s].y;
+        }
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+// partial[j * n_chunks + c] = sum over rows of chunk c of conj(V[i, j]) w[i]
+__global__ __launch_bounds__(kT) void dots_kernel(int64_t n, int64_t rows_per_chunk,
+                                                  const double2 *__restrict__ V, int64_t ldv,
+                                                  const double2 *__restrict__ w,
+                                                  double2 *__restrict__ partial, int n_chunks) {
+    __shared__ double2 sh[kT];
+    const int c = blockIdx.x, j = blockIdx.y;
+    const int64_t r0 = static_cast<int64_t>(c) * rows_per_chunk;
+    const int64_t r1 = (r0 + rows_per_chunk < n) ? r0 + rows_per_chunk : n;
+    double2 acc = make_double2(0.0, 0.0);
+    const double2 *__restrict__ col = V + j * ldv;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kT) {
+        const double2 a = col[i], b = w[i];
+        acc.x += a.x * b.x + a.y * b.y;
+        acc.y += a.x * b.y - a.y * b.x;
+    }
+    const double2 s = block_sum2<kT>(acc, sh);
+    if (threadIdx.x == 0) partial[static_cast<int64_t>(j) * n_chunks + c] = s;
+}
+
+__global__ void dots_final_kernel(int k, const double2 *__restrict__ partial, int n_chunks,
+                                  double2 *__restrict__ h) {
+    const int j = blockIdx.x * kT + threadIdx.x;
+    if (j >= k) return;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int c = 0; c < n_chunks; ++c) {
+        acc.x += partial[static_cast<int64_t>(j) * n_chunks + c].x;
+        acc.y += partial[static_cast<int64_t>(j) * n_chunks + c].y;
+    }
+    h[j] = acc;
+}
+
+// w[i] += sign * sum_j V[i, j] h[j]
+__global__ void gemv_kernel(int64_t n, int k, const double2 *__restrict__ V, int64_t ldv,
+                            const double2 *__restrict__ h, double sign, double2 *__restrict__ w) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+    if (i >= n) return;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int j = 0; j < k; ++j) {
+        const double2 a = V[i + j * ldv], b = h[j];
+        acc.x += a.x * b.x - a.y * b.y;
+        acc.y += a.x * b.y + a.y * b.x;
+    }
+    double2 v = w[i];
+    v.x += sign * acc.x;
+    v.y += sign * acc.y;
+    w[i] = v;
+}
+
+__global__ __launch_bounds__(kT) void norm_kernel(int64_t n, int64_t rows_per_chunk,
+                                                  const double2 *__restrict__ w,
+                                                  double *__restrict__ partial) {
+    __shared__ double2 sh[kT];
+    const int c = blockIdx.x;
+    const int64_t r0 = static_cast<int64_t>(c) * rows_per_chunk;
+    const int64_t r1 = (r0 + rows_per_chunk < n) ? r0 + rows_per_chunk : n;
+    double acc = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kT) acc += w[i].x * w[i].x + w[i].y * w[i].y;
+    const double2 s = block_sum2<kT>(make_double2(acc, 0.0), sh);
+    if (threadIdx.x == 0) partial[c] = s.x;
+}
+
+__global__ void norm_final_kernel(const double *__restrict__ partial, int n_chunks,
+                                  double *__restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double acc = 0.0;
+    for (int c = 0; c < n_chunks; ++c) acc += partial[c];
+    out[0] = sqrt(acc);
+}
+
+__global__ void scale_copy_kernel(int64_t n, const double2 *__restrict__ w,
+                                  const double *__restrict__ nrm, double2 *__restrict__ v) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+    if (i >= n) return;
+    const double s = nrm[0];
+    const double inv = s > 0.0 ? 1.0 / s : 0.0;
+    v[i] = make_double2(w[i].x * inv, w[i].y * inv);
+}
+
+__global__ void scale_kernel(int64_t n, const double2 *__restrict__ w, double sc,
+                             double2 *__restrict__ v) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+    if (i >= n) return;
+    v[i] = make_double2(w[i].x * sc, w[i].y * sc);
+}
+
+__global__ void zero_kernel(int64_t n, double2 *__restrict__ v) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+    if (i >= n) return;
+    v[i] = make_double2(0.0, 0.0);
+}
+
+__global__ void sub_kernel(int64_t n, const double2 *__restrict__ b, const double2 *__restrict__ ax,
+                           double2 *__restrict__ r) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+    if (i >= n) return;
+    r[i] = make_double2(b[i].x - ax[i].x, b[i].y - ax[i].y);
+}
+
+__global__ void add_kernel(int64_t n, const double2 *__restrict__ d, double2 *__restrict__ x) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+    if (i >= n) return;
+    x[i] = make_double2(x[i].x + d[i].x, x[i].y + d[i].y);
+}
+
+__global__ void copy_kernel(int64_t n, int ncols, const double2 *__restrict__ a, int64_t lda,
+                            double2 *__restrict__ b, int64_t ldb) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+    if (i >= n) return;
+    for (int c = 0; c < ncols; ++c) b[i + c * ldb] = a[i + c * lda];
+}
+
+}  // namespace
+
+#define LAUNCH_CHECK() VSIE_HIP(hipGetLastError())
+
+void launch_weights(const DeviceMesh &m, const double *k0, int n_freq, hipStream_t s) {
+    if (m.n == 0) return;
+    hipLaunchKernelGGL(weights_kernel, dim3(blocks_for(m.n)), dim3(kT), 0, s, m, k0, n_freq);
+    LAUNCH_CHECK();
+}
+
+void launch_pack_charges(SrcClass cls, vsie_precision prec, const SourceSet &src,
+                         const double *sp_f, int nrhs, const double2 *x, int64_t ldx,
+                         bool conj_in, void *charge, hipStream_t s) {
+    if (src.count == 0) return;
+    const double *sc = (cls == kClassG) ? sp_f : nullptr;
+    if (prec == VSIE_FP64)
+        hipLaunchKernelGGL(pack_kernel<double2>, dim3(blocks_for(src.count)), dim3(kT), 0, s,
+                           src.count, src.idx, sc, nrhs, x, ldx, conj_in,
+                           static_cast<double2 *>(charge));
+    else
+        hipLaunchKernelGGL(pack_kernel<float2>, dim3(blocks_for(src.count)), dim3(kT), 0, s,
+                           src.count, src.idx, sc, nrhs, x, ldx, conj_in,
+                           static_cast<float2 *>(charge));
+    LAUNCH_CHECK();
+}
+
+void launch_pack_plain(vsie_precision prec, int64_t n, int nrhs, const double2 *x, int64_t ldx,
+                       bool conj_in, void *charge, hipStream_t s) {
+    if (n == 0) return;
+    if (prec == VSIE_FP64)
+        hipLaunchKernelGGL(pack_kernel<double2>, dim3(blocks_for(n)), dim3(kT), 0, s, n,
+                           static_cast<const int32_t *>(nullptr), static_cast<const double *>(nullptr),
+                           nrhs, x, ldx, conj_in, static_cast<double2 *>(charge));
+    else
+        hipLaunchKernelGGL(pack_kernel<float2>, dim3(blocks_for(n)), dim3(kT), 0, s, n,
+                           static_cast<const int32_t *>(nullptr), static_cast<const double *>(nullptr),
+                           nrhs, x, ldx, conj_in, static_cast<float2 *>(charge));
+    LAUNCH_CHECK();
+}
+
+void launch_reduce_partials(int64_t n_t, int nrhs, int n_parts, const double2 *partial,
+                            const double2 *diag, bool conj_diag, const double2 *x, int64_t ldx,
+                            double2 *y, int64_t ldy, double2 *, hipStream_t s) {
+    if (n_t == 0) return;
+    hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(n_t)), dim3(kT), 0, s, n_t, nrhs, n_parts,
+                       partial, diag, conj_diag, x, ldx, y, ldy);
+    LAUNCH_CHECK();
+}
+
+void launch_scatter_conj(int64_t count, const int32_t *idx, const double *sp, int nrhs,
+                         int n_parts, const double2 *partial, double2 *y, int64_t ldy,
+                         hipStream_t s) {
+    if (count == 0) return;
+    hipLaunchKernelGGL(scatter_conj_kernel, dim3(blocks_for(count)), dim3(kT), 0, s, count, idx, sp,
+                       nrhs, n_parts, partial, y, ldy);
+    LAUNCH_CHECK();
+}
+
+void launch_sums_reduce(int64_t n, int nrhs, int n_parts, const double2 *partial, double2 *z,
+                        int64_t ldz, double2 *Z, int64_t ldZ, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(sums_reduce_kernel, dim3(blocks_for(n)), dim3(kT), 0, s, n, nrhs, n_parts,
+                       partial, z, ldz, Z, ldZ);
+    LAUNCH_CHECK();
+}
+
+void launch_plane_wave(int64_t n, const double *px, const double *py, const double *pz, double k,
+                       double dx, double dy, double dz, double2 *b, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(plane_wave_kernel, dim3(blocks_for(n)), dim3(kT), 0, s, n, px, py, pz, k,
+                       dx, dy, dz, b);
+    LAUNCH_CHECK();
+}
+
+static int64_t rows_per_chunk(int64_t n, int n_chunks) { return (n + n_chunks - 1) / n_chunks; }
+
+void blas_dots(int64_t n, int k, const double2 *V, int64_t ldv, const double2 *w, double2 *partial,
+               int n_chunks, double2 *h, hipStream_t s) {
+    if (k == 0) return;
+    hipLaunchKernelGGL(dots_kernel, dim3(n_chunks, k), dim3(kT), 0, s, n, rows_per_chunk(n, n_chunks),
+                       V, ldv, w, partial, n_chunks);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(dots_final_kernel, dim3(blocks_for(k)), dim3(kT), 0, s, k, partial, n_chunks, h);
+    LAUNCH_CHECK();
+}
+
+void blas_gemv_sub(int64_t n, int k, const double2 *V, int64_t ldv, const double2 *h, double2 *w,
+                   hipStream_t s) {
+    if (k == 0 || n == 0) return;
+    hipLaunchKernelGGL(gemv_kernel, dim3(blocks_for(n)), dim3(kT), 0, s, n, k, V, ldv, h, -1.0, w);
+    LAUNCH_CHECK();
+}
+
+void blas_gemv_add(int64_t n, int k, const double2 *V, int64_t ldv, const double2 *yv, double2 *x,
+                   hipStream_t s) {
+    if (k == 0 || n == 0) return;
+    hipLaunchKernelGGL(gemv_kernel, dim3(blocks_for(n)), dim3(kT), 0, s, n, k, V, ldv, yv, 1.0, x);
+    LAUNCH_CHECK();
+}
+
+void blas_norm2(int64_t n, const double2 *w, double *partial, int n_chunks, double *out,
+                hipStream_t s) {
+    hipLaunchKernelGGL(norm_kernel, dim3(n_chunks), dim3(kT), 0, s, n, rows_per_chunk(n, n_chunks), w,
+                       partial);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(norm_final_kernel, dim3(1), dim3(64), 0, s, partial, n_chunks, out);
+    LAUNCH_CHECK();
+}
+
+void blas_scale_copy(int64_t n, const double2 *w, const double *nrm, double2 *v, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(scale_copy_kernel, dim3(blocks_for(n)), dim3(kT), 0, s, n, w, nrm, v);
+    LAUNCH_CHECK();
+}
+
+void blas_scale(int64_t n, const double2 *w, double sc, double2 *v, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(scale_kernel, dim3(blocks_for(n)), dim3(kT), 0, s, n, w, sc, v);
+    LAUNCH_CHECK();
+}
+
+void blas_zero(int64_t n, double2 *v, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(zero_kernel, dim3(blocks_for(n)), dim3(kT), 0, s, n, v);
+    LAUNCH_CHECK();
+}
+
+void blas_sub(int64_t n, const double2 *b, const double2 *ax, double2 *r, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(sub_kernel, dim3(blocks_for(n)), dim3(kT), 0, s, n, b, ax, r);
+    LAUNCH_CHECK();
+}
+
+void blas_add(int64_t n, const double2 *d, double2 *x, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(add_kernel, dim3(blocks_for(n)), dim3(kT), 0, s, n, d, x);
+    LAUNCH_CHECK();
+}
+
+void blas_copy(int64_t n, const double2 *a, int64_t lda, double2 *b, int64_t ldb, int ncols,
+               hipStream_t s) {
+    if (n == 0 || ncols == 0) return;
+    hipLaunchKernelGGL(copy_kernel, dim3(blocks_for(n)), dim3(kT), 0, s, n, ncols, a, lda, b, ldb);
+    LAUNCH_CHECK();
+}
+
+}  // namespace vsie

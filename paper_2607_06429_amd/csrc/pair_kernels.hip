@@ -1,0 +1,327 @@
+// Pair-sum kernels of the discretised VSIE operator on gfx950.
+//
+// One thread owns one "thread point" (a collocation target in the forward
+// product, a source element in the adjoint sums) and streams a chunk of
+// "streamed points".  The streamed index is the same for every lane of a
+// wave, so their coordinates, weights and charges are read with wave-uniform
+// (scalar) loads straight from global memory: no LDS staging and no
+// barriers.  Chunks of streamed points are spread over blockIdx.y so that a
+// launch holds many more waves than the chip has SIMDs; each (thread point,
+// chunk) writes one FP64 partial sum per right-hand side and a separate
+// kernel adds the partials in a fixed order (deterministic results).
+//
+// Per pair, with d = x_thread - y_streamed, r = |d| (paper: the midpoint rule
+// applied to the kernels of Theorem 3, eq_vsie, with G = exp(i k r)/(4 pi r)):
+//   e      = exp(i k r) / r                  (the 1/(4 pi) lives in the weights)
+//   FWD_G  : acc += e * u_j                  single layer, u_j = -s'_j x_j
+//   FWD_F  : acc += e (i k r - 1) q * x_j,   q = d . v'_j / r^2   (T and K terms)
+//   ADJ_F  : acc += e (i k r - 1) q * c_j,   q = -d . v'_thread / r^2
+//   SUMS   : z   += e * c_j,  Zvec += e (i k r - 1)/r^2 (-d) * c_j
+// A pair with r = 0 (the thread point itself) contributes exactly zero.
+//
+// Phase: the angle k r is carried in revolutions t = r k/(2 pi), reduced as
+// t - rint(t) in FP64 on both precision paths, so the argument of sin/cos
+// never exceeds half a turn.
+#include "vsie_internal.h"
+
+namespace vsie {
+namespace {
+
+enum Mode { FWD_G = 0, FWD_F = 1, ADJ_F = 2, SUMS = 3 };
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// ---------------------------------------------------------------------------
+// FP64 sin and cos of 2 pi f for |f| <= 1/2.
+// f = q/4 + g with q = rint(4 f) and |g| <= 1/8 (exact by Sterbenz' lemma);
+// x = 2 pi g lies in [-pi/4, pi/4] where the Maclaurin series of sin (through
+// x^15) and cos (through x^16) have truncation errors below 7e-17; the
+// quadrant q rotates the pair by q quarter turns.
+__device__ __forceinline__ void sincos_turns_f64(double f, double &sn, double &cs) {
+    const double q = rint(4.0 * f);
+    const double g = fma(q, -0.25, f);
+    const double x = g * kTwoPi;
+    const double z = x * x;
+    double ps = -1.0 / 1307674368000.0;               // -1/15!
+    ps = fma(ps, z, 1.0 / 6227020800.0);              //  1/13!
+    ps = fma(ps, z, -1.0 / 39916800.0);               // -1/11!
+    ps = fma(ps, z, 1.0 / 362880.0);                  //  1/9!
+    ps = fma(ps, z, -1.0 / 5040.0);                   // -1/7!
+    ps = fma(ps, z, 1.0 / 120.0);                     //  1/5!
+    ps = fma(ps, z, -1.0 / 6.0);                      // -1/3!
+    const double s = fma(ps * z, x, x);
+    double pc = 1.0 / 20922789888000.0;               //  1/16!
+    pc = fma(pc, z, -1.0 / 87178291200.0);            // -1/14!
+    pc = fma(pc, z, 1.0 / 479001600.0);               //  1/12!
+    pc = fma(pc, z, -1.0 / 3628800.0);                // -1/10!
+    pc = fma(pc, z, 1.0 / 40320.0);                   //  1/8!
+    pc = fma(pc, z, -1.0 / 720.0);                    // -1/6!
+    pc = fma(pc, z, 1.0 / 24.0);                      //  1/4!
+    pc = fma(pc, z, -0.5);                            // -1/2!
+    const double c = fma(pc, z, 1.0);
+    const int qi = static_cast<int>(q) & 3;
+    const double a = (qi & 1) ? c : s;
+    const double b = (qi & 1) ? s : c;
+    sn = (qi & 2) ? -a : a;
+    cs = ((qi + 1) & 2) ? -b : b;
+}
+
+// FP64 1/sqrt(x) for x > 0: hardware estimate plus two Newton steps.
+__device__ __forceinline__ double rsq_f64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double h = x * y;
+    double e = fma(-h, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    h = x * y;
+    e = fma(-h, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
+// Geometry of one pair in FP64: e = exp(i k r)/r, ir2 = 1/r^2 and k r.
+__device__ __forceinline__ void geom_f64(double dx, double dy, double dz, double k, double kr2pi,
+                                         double &er, double &ei, double &ir2, double &kr) {
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const double ir = (r2 > 0.0) ? rsq_f64(r2) : 0.0;
+    const double r = r2 * ir;
+    const double t = r * kr2pi;
+    double sn, cs;
+    sincos_turns_f64(t - rint(t), sn, cs);
+    er = cs * ir;
+    ei = sn * ir;
+    ir2 = ir * ir;
+    kr = k * r;
+}
+
+// Geometry of one pair for the FP32 operator: FP64 coordinate differences and
+// phase reduction, FP32 amplitude and trigonometric functions.  r is formed
+// from an FP32 reciprocal square root and one FP64 Newton correction, which
+// is accurate to ~1e-14 relative: enough to keep the phase error far below
+// the FP32 rounding of everything else.
+__device__ __forceinline__ void geom_f32(double dx, double dy, double dz, float k, double kr2pi,
+                                         float &er, float &ei, float &ir2, float &kr) {
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const float r2f = static_cast<float>(r2);
+    const float yf = (r2 > 0.0) ? __builtin_amdgcn_rsqf(r2f) : 0.0f;
+    const float rf = r2f * yf;
+    const double rd = static_cast<double>(rf);
+    const double e = fma(-rd, rd, r2);
+    const double r = fma(e, static_cast<double>(0.5f * yf), rd);
+    const double t = r * kr2pi;
+    const float f = static_cast<float>(t - rint(t));
+    // v_sin_f32 / v_cos_f32 take their argument in turns
+    const float sn = __builtin_amdgcn_sinf(f);
+    const float cs = __builtin_amdgcn_cosf(f);
+    er = cs * yf;
+    ei = sn * yf;
+    ir2 = yf * yf;
+    kr = k * rf;
+}
+
+template <typename CT, typename AT>
+struct PairArgs {
+    int64_t n_t;
+    const CT *__restrict__ tx;
+    const CT *__restrict__ ty;
+    const CT *__restrict__ tz;
+    const AT *__restrict__ tvx;  // ADJ_F: v' of the thread points
+    const AT *__restrict__ tvy;
+    const AT *__restrict__ tvz;
+    int64_t n_s;
+    const CT *__restrict__ sx;
+    const CT *__restrict__ sy;
+    const CT *__restrict__ sz;
+    const AT *__restrict__ svx;  // FWD_F: v' of the streamed points
+    const AT *__restrict__ svy;
+    const AT *__restrict__ svz;
+    const void *__restrict__ q;  // charges, complex pairs of AT: q[r * ldq + j]
+    int64_t ldq;
+    int64_t chunk;
+    double k;
+    double kr2pi;
+    double2 *__restrict__ out;   // out[c * chunk_stride + (r * ncomp + comp) * n_t + i]
+    int64_t chunk_stride;
+};
+
+template <typename AT> struct cplx_t;
+template <> struct cplx_t<double> { using type = double2; };
+template <> struct cplx_t<float> { using type = float2; };
+
+// Sources per FP32 sub-tile: FP32 sums over at most this many pairs are
+// added into the FP64 accumulators.
+constexpr int kSubTile = 128;
+
+template <int MODE, int R, typename CT, typename AT>
+__global__ __launch_bounds__(kBlock) void pair_sum_kernel(PairArgs<CT, AT> a) {
+    using C2 = typename cplx_t<AT>::type;
+    constexpr int NC = (MODE == SUMS) ? 4 : 1;   // complex accumulators per right-hand side
+    constexpr bool F32 = sizeof(AT) == 4;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= a.n_t) return;
+    const int c = blockIdx.y;
+    const int64_t j0 = static_cast<int64_t>(c) * a.chunk;
+    const int64_t j1 = (j0 + a.chunk < a.n_s) ? j0 + a.chunk : a.n_s;
+
+    const double xi = a.tx[i], yi = a.ty[i], zi = a.tz[i];
+    AT tv0 = 0, tv1 = 0, tv2 = 0;
+    if constexpr (MODE == ADJ_F) {
+        tv0 = a.tvx[i];
+        tv1 = a.tvy[i];
+        tv2 = a.tvz[i];
+    }
+    const C2 *__restrict__ q = static_cast<const C2 *>(a.q);
+
+    double accr[R * NC], acci[R * NC];
+#pragma unroll
+    for (int r = 0; r < R * NC; ++r) accr[r] = acci[r] = 0.0;
+
+    const AT k = static_cast<AT>(a.k);
+    for (int64_t jt = j0; jt < j1; jt += (F32 ? kSubTile : (j1 - j0))) {
+        const int64_t je = F32 ? ((jt + kSubTile < j1) ? jt + kSubTile : j1) : j1;
+        AT sr[R * NC], si[R * NC];
+#pragma unroll
+        for (int r = 0; r < R * NC; ++r) sr[r] = si[r] = 0;
+#pragma unroll 2
+        for (int64_t j = jt; j < je; ++j) {
+            const double dx = xi - static_cast<double>(a.sx[j]);
+            const double dy = yi - static_cast<double>(a.sy[j]);
+            const double dz = zi - static_cast<double>(a.sz[j]);
+            AT er, ei, ir2, kr;
+            if constexpr (F32) geom_f32(dx, dy, dz, k, a.kr2pi, er, ei, ir2, kr);
+            else geom_f64(dx, dy, dz, a.k, a.kr2pi, er, ei, ir2, kr);
+            if constexpr (MODE == FWD_G) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const C2 u = q[r * a.ldq + j];
+                    sr[r] = fma(er, u.x, fma(-ei, u.y, sr[r]));
+                    si[r] = fma(er, u.y, fma(ei, u.x, si[r]));
+                }
+            } else if constexpr (MODE == FWD_F || MODE == ADJ_F) {
+                AT dv;
+                if constexpr (MODE == FWD_F) {
+                    dv = static_cast<AT>(fma(dx, static_cast<double>(a.svx[j]),
+                                             fma(dy, static_cast<double>(a.svy[j]),
+                                                 dz * static_cast<double>(a.svz[j]))));
+                } else {
+                    dv = -static_cast<AT>(fma(dx, static_cast<double>(tv0),
+                                              fma(dy, static_cast<double>(tv1),
+                                                  dz * static_cast<double>(tv2))));
+                }
+                const AT qq = dv * ir2;
+                // e (i k r - 1) q
+                const AT cr = qq * fma(-ei, kr, -er);
+                const AT ci = qq * fma(er, kr, -ei);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const C2 u = q[r * a.ldq + j];
+                    sr[r] = fma(cr, u.x, fma(-ci, u.y, sr[r]));
+                    si[r] = fma(cr, u.y, fma(ci, u.x, si[r]));
+                }
+            } else {  // SUMS
+                const AT cr = ir2 * fma(-ei, kr, -er);
+                const AT ci = ir2 * fma(er, kr, -ei);
+                const AT md[3] = {static_cast<AT>(-dx), static_cast<AT>(-dy), static_cast<AT>(-dz)};
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const C2 u = q[r * a.ldq + j];
+                    sr[4 * r] = fma(er, u.x, fma(-ei, u.y, sr[4 * r]));
+                    si[4 * r] = fma(er, u.y, fma(ei, u.x, si[4 * r]));
+                    const AT wr = fma(cr, u.x, -ci * u.y);
+                    const AT wi = fma(cr, u.y, ci * u.x);
+#pragma unroll
+                    for (int ax = 0; ax < 3; ++ax) {
+                        sr[4 * r + 1 + ax] = fma(md[ax], wr, sr[4 * r + 1 + ax]);
+                        si[4 * r + 1 + ax] = fma(md[ax], wi, si[4 * r + 1 + ax]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R * NC; ++r) {
+            accr[r] += static_cast<double>(sr[r]);
+            acci[r] += static_cast<double>(si[r]);
+        }
+    }
+    double2 *__restrict__ o = a.out + c * a.chunk_stride + i;
+#pragma unroll
+    for (int r = 0; r < R * NC; ++r) o[r * a.n_t] = make_double2(accr[r], acci[r]);
+}
+
+template <int MODE, typename CT, typename AT>
+void launch_mode(const PairArgs<CT, AT> &a, int nrhs, int n_chunks, hipStream_t s) {
+    dim3 grid(static_cast<unsigned>((a.n_t + kBlock - 1) / kBlock), static_cast<unsigned>(n_chunks));
+    switch (nrhs) {
+        case 1: hipLaunchKernelGGL((pair_sum_kernel<MODE, 1, CT, AT>), grid, dim3(kBlock), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((pair_sum_kernel<MODE, 2, CT, AT>), grid, dim3(kBlock), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((pair_sum_kernel<MODE, 4, CT, AT>), grid, dim3(kBlock), 0, s, a); break;
+        case 8: hipLaunchKernelGGL((pair_sum_kernel<MODE, 8, CT, AT>), grid, dim3(kBlock), 0, s, a); break;
+        case 16: hipLaunchKernelGGL((pair_sum_kernel<MODE, 16, CT, AT>), grid, dim3(kBlock), 0, s, a); break;
+        default: fail(VSIE_E_INVALID, "pair kernel: unsupported right-hand-side block " + std::to_string(nrhs));
+    }
+    VSIE_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+// Splits nrhs into launches of 16, 8, 4, 2, 1 right-hand sides.
+template <int MODE>
+static void run_pairs(const PairJob &J, hipStream_t s) {
+    constexpr int NC = (MODE == SUMS) ? 4 : 1;
+    const double kr2pi = J.k / kTwoPi;
+    int r0 = 0;
+    while (r0 < J.nrhs) {
+        const int left = J.nrhs - r0;
+        const int blk = left >= 16 ? 16 : left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+        double2 *out = J.out + static_cast<int64_t>(r0) * NC * J.n_t;
+        if (J.prec == VSIE_FP64) {
+            PairArgs<double, double> a{J.n_t, J.tx, J.ty, J.tz, J.tv[0], J.tv[1], J.tv[2],
+                                       J.n_s, J.sx, J.sy, J.sz, J.sv[0], J.sv[1], J.sv[2],
+                                       static_cast<const double2 *>(J.charge) + r0 * J.ldq, J.ldq,
+                                       J.chunk, J.k, kr2pi, out, J.chunk_stride};
+            launch_mode<MODE>(a, blk, J.n_chunks, s);
+        } else {
+            PairArgs<double, float> a{J.n_t, J.tx, J.ty, J.tz, J.tvf[0], J.tvf[1], J.tvf[2],
+                                      J.n_s, J.sx, J.sy, J.sz, J.svf[0], J.svf[1], J.svf[2],
+                                      static_cast<const float2 *>(J.charge) + r0 * J.ldq, J.ldq,
+                                      J.chunk, J.k, kr2pi, out, J.chunk_stride};
+            launch_mode<MODE>(a, blk, J.n_chunks, s);
+        }
+        r0 += blk;
+    }
+}
+
+static hipEvent_t take_event(PairProfiler *prof) {
+    if (!prof->pool.empty()) {
+        hipEvent_t e = prof->pool.back();
+        prof->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    VSIE_HIP(hipEventCreate(&e));
+    return e;
+}
+
+void launch_pairs(const PairJob &J, hipStream_t s, PairProfiler *prof) {
+    if (J.n_t == 0 || J.n_s == 0) return;
+    if (J.chunk <= 0 || J.n_chunks <= 0 || (J.n_chunks - 1) * J.chunk >= J.n_s)
+        fail(VSIE_E_INVALID, "pair kernel: inconsistent source chunking");
+    if (prof && prof->on) {
+        PairProfiler::Rec r{take_event(prof), take_event(prof), 2 * J.mode + (J.prec == VSIE_FP32 ? 1 : 0),
+                            static_cast<double>(J.n_t) * J.n_s,
+                            static_cast<double>(J.n_t) * J.n_s * J.nrhs};
+        VSIE_HIP(hipEventRecord(r.a, s));
+        PairJob K = J;
+        launch_pairs(K, s, nullptr);
+        VSIE_HIP(hipEventRecord(r.b, s));
+        prof->recs.push_back(r);
+        return;
+    }
+    switch (J.mode) {
+        case PAIR_FWD_G: run_pairs<FWD_G>(J, s); break;
+        case PAIR_FWD_F: run_pairs<FWD_F>(J, s); break;
+        case PAIR_ADJ_F: run_pairs<ADJ_F>(J, s); break;
+        case PAIR_SUMS: run_pairs<SUMS>(J, s); break;
+        default: fail(VSIE_E_INVALID, "pair kernel: unknown mode");
+    }
+}
+
+}  // namespace vsie

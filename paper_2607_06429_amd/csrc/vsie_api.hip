@@ -1,0 +1,793 @@
+// C ABI of libvsie.so: validation, device data, operator application and the
+// GMRES solver with FP64 iterative refinement.  See include/vsie.h.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "vsie_internal.h"
+
+namespace vsie {
+
+thread_local std::string g_last_error;
+
+void fail(vsie_status code, const std::string &msg) { throw Error{code, msg}; }
+
+void check_hip(hipError_t e, const char *what) {
+    if (e == hipSuccess) return;
+    const vsie_status code = (e == hipErrorOutOfMemory) ? VSIE_E_NOMEM : VSIE_E_DEVICE;
+    fail(code, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Grow-only device buffer.
+struct Scratch {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void *get(size_t b) {
+        if (b <= bytes) return p;
+        if (p) {
+            // queued kernels may still read the old buffer
+            VSIE_HIP(hipDeviceSynchronize());
+            VSIE_HIP(hipFree(p));
+        }
+        p = nullptr;
+        bytes = 0;
+        VSIE_HIP(hipMalloc(&p, b));
+        bytes = b;
+        return p;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
+
+// Source chunking of one pair launch: enough (thread-block, chunk) waves to
+// keep every SIMD busy, but chunks of at least kMinChunk streamed points.
+constexpr int64_t kTargetWaves = 32768;
+constexpr int64_t kMinChunk = 256;
+
+void choose_chunks(int64_t n_t, int64_t n_s, int64_t &chunk, int &n_chunks) {
+    if (n_s <= 0) {
+        chunk = 1;
+        n_chunks = 0;
+        return;
+    }
+    const int64_t waves = std::max<int64_t>(1, (n_t + 63) / 64);
+    int64_t want = (kTargetWaves + waves - 1) / waves;
+    const int64_t max_chunks = std::max<int64_t>(1, n_s / kMinChunk);
+    want = std::min<int64_t>(std::max<int64_t>(want, 1), std::min<int64_t>(max_chunks, 4096));
+    chunk = (n_s + want - 1) / want;
+    n_chunks = static_cast<int>((n_s + chunk - 1) / chunk);
+}
+
+}  // namespace vsie
+
+using namespace vsie;
+
+struct vsie_problem {
+    int device = 0;
+    DeviceMesh m;
+    std::vector<double> k0;
+    double *d_k0 = nullptr;
+    SourceSet G, F;
+    std::vector<void *> owned;  // permanent device allocations
+    Scratch partial, chargeG, chargeF, chargeAll, sums_part;
+    // Krylov workspace
+    Scratch V, w, r, ax, h1, h2, nrm, dpart, npart, yv;
+    PairProfiler prof;
+
+    template <typename T>
+    T *alloc(int64_t count) {
+        if (count <= 0) return nullptr;
+        void *p = nullptr;
+        VSIE_HIP(hipMalloc(&p, sizeof(T) * static_cast<size_t>(count)));
+        owned.push_back(p);
+        return static_cast<T *>(p);
+    }
+    template <typename T>
+    T *upload(const T *host, int64_t count) {
+        if (count <= 0 || host == nullptr) return nullptr;
+        T *d = alloc<T>(count);
+        VSIE_HIP(hipMemcpy(d, host, sizeof(T) * static_cast<size_t>(count), hipMemcpyHostToDevice));
+        return d;
+    }
+    void free_sources(SourceSet &S) {
+        void *ps[] = {S.idx, S.x, S.y, S.z, S.vx, S.vy, S.vz, S.vxf, S.vyf, S.vzf};
+        for (void *q : ps) {
+            if (!q) continue;
+            auto it = std::find(owned.begin(), owned.end(), q);
+            if (it != owned.end()) owned.erase(it);
+            (void)hipFree(q);
+        }
+        S = SourceSet{};
+    }
+    ~vsie_problem() {
+        for (auto &r : prof.recs) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        for (hipEvent_t e : prof.pool) (void)hipEventDestroy(e);
+        for (void *p : owned) (void)hipFree(p);
+        for (Scratch *s : {&partial, &chargeG, &chargeF, &chargeAll, &sums_part, &V, &w, &r, &ax,
+                           &h1, &h2, &nrm, &dpart, &npart, &yv})
+            s->release();
+    }
+};
+
+namespace {
+
+template <typename F>
+vsie_status guarded(F &&fn) {
+    try {
+        fn();
+        return VSIE_OK;
+    } catch (const Error &e) {
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return VSIE_E_NOMEM;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return VSIE_E_INVALID;
+    }
+}
+
+inline hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+void require(bool ok, const std::string &msg) {
+    if (!ok) fail(VSIE_E_INVALID, msg);
+}
+
+void validate_geometry(const vsie_geometry *g, const double *vrho, const double *vc) {
+    require(g != nullptr, "geometry is NULL");
+    require(g->n_vol >= 0 && g->n_srf >= 0, "negative element count");
+    require(g->n_vol + g->n_srf >= 1, "empty problem");
+    require(g->n_vol <= INT32_MAX && g->n_srf <= INT32_MAX, "too many elements");
+    require(std::isfinite(g->rho0) && g->rho0 > 0 && std::isfinite(g->c0) && g->c0 > 0,
+            "rho0 and c0 must be positive");
+    const int64_t nv = g->n_vol, ns = g->n_srf;
+    if (nv > 0) {
+        require(g->vx && g->vy && g->vz && g->vw && g->vdom, "volume arrays must not be NULL");
+        require(vrho && vc, "material arrays must not be NULL");
+        for (int64_t e = 0; e < nv; ++e) {
+            require(std::isfinite(g->vx[e]) && std::isfinite(g->vy[e]) && std::isfinite(g->vz[e]),
+                    "non-finite cell centroid at " + std::to_string(e));
+            require(g->vw[e] > 0 && std::isfinite(g->vw[e]), "cell volume must be positive at " + std::to_string(e));
+            require(g->vdom[e] == 1 || g->vdom[e] == 2, "cell subdomain must be 1 or 2 at " + std::to_string(e));
+            require(vrho[e] > 0 && std::isfinite(vrho[e]) && vc[e] > 0 && std::isfinite(vc[e]),
+                    "density and sound speed must be positive at cell " + std::to_string(e));
+            if (g->vnb)
+                for (int a = 0; a < 6; ++a) {
+                    const int32_t q = g->vnb[6 * e + a];
+                    require(q >= -1 && q < nv && q != e, "bad neighbour index at cell " + std::to_string(e));
+                }
+            if (g->vgrad_alpha)
+                for (int a = 0; a < 3; ++a)
+                    require(std::isfinite(g->vgrad_alpha[3 * e + a]), "non-finite grad alpha");
+        }
+    }
+    if (ns > 0) {
+        require(g->sx && g->sy && g->sz && g->snx && g->sny && g->snz && g->sarea && g->siface &&
+                    g->scell_in && g->scell_out,
+                "surface arrays must not be NULL");
+        require(nv > 0, "surface elements need adjacent volume cells");
+        for (int64_t q = 0; q < ns; ++q) {
+            require(std::isfinite(g->sx[q]) && std::isfinite(g->sy[q]) && std::isfinite(g->sz[q]),
+                    "non-finite face centroid at " + std::to_string(q));
+            const double nn = g->snx[q] * g->snx[q] + g->sny[q] * g->sny[q] + g->snz[q] * g->snz[q];
+            require(std::fabs(std::sqrt(nn) - 1.0) <= 1e-12, "face normal not of unit length at " + std::to_string(q));
+            require(g->sarea[q] > 0 && std::isfinite(g->sarea[q]), "face area must be positive");
+            require(g->siface[q] == 1 || g->siface[q] == 2, "face interface must be 1 or 2");
+            require(g->scell_in[q] >= 0 && g->scell_in[q] < nv, "bad inside cell of face " + std::to_string(q));
+            require(g->scell_out[q] >= -1 && g->scell_out[q] < nv, "bad outside cell of face " + std::to_string(q));
+            if (g->siface[q] == 1)
+                require(g->scell_out[q] == -1, "a Gamma_1 face must have the exterior outside");
+            else
+                require(g->scell_out[q] >= 0, "a Gamma_2 face needs a cell outside");
+        }
+    }
+}
+
+// Rebuild the class lists (which elements carry a single-layer weight, which a
+// v' weight) from the device weights, and pack their coordinates and v'.
+void build_sources(vsie_problem *p) {
+    const int64_t n = p->m.n;
+    const int nf = static_cast<int>(p->k0.size());
+    std::vector<double> sp(static_cast<size_t>(n) * nf), vp(3 * static_cast<size_t>(n));
+    VSIE_HIP(hipMemcpy(sp.data(), p->m.sp, sizeof(double) * sp.size(), hipMemcpyDeviceToHost));
+    VSIE_HIP(hipMemcpy(vp.data(), p->m.vpx, sizeof(double) * n, hipMemcpyDeviceToHost));
+    VSIE_HIP(hipMemcpy(vp.data() + n, p->m.vpy, sizeof(double) * n, hipMemcpyDeviceToHost));
+    VSIE_HIP(hipMemcpy(vp.data() + 2 * n, p->m.vpz, sizeof(double) * n, hipMemcpyDeviceToHost));
+    std::vector<double> px(n), py(n), pz(n);
+    VSIE_HIP(hipMemcpy(px.data(), p->m.px, sizeof(double) * n, hipMemcpyDeviceToHost));
+    VSIE_HIP(hipMemcpy(py.data(), p->m.py, sizeof(double) * n, hipMemcpyDeviceToHost));
+    VSIE_HIP(hipMemcpy(pz.data(), p->m.pz, sizeof(double) * n, hipMemcpyDeviceToHost));
+    for (double v : sp) require(std::isfinite(v), "non-finite single-layer weight");
+    for (double v : vp) require(std::isfinite(v), "non-finite double-layer weight");
+    std::vector<int32_t> gi, fi;
+    for (int64_t e = 0; e < n; ++e) {
+        bool g = false;
+        for (int f = 0; f < nf; ++f) g = g || sp[static_cast<size_t>(f) * n + e] != 0.0;
+        if (g) gi.push_back(static_cast<int32_t>(e));
+        if (vp[e] != 0.0 || vp[n + e] != 0.0 || vp[2 * n + e] != 0.0) fi.push_back(static_cast<int32_t>(e));
+    }
+    p->free_sources(p->G);
+    p->free_sources(p->F);
+    auto fill = [&](SourceSet &S, const std::vector<int32_t> &ix, bool with_v) {
+        S.count = static_cast<int64_t>(ix.size());
+        if (S.count == 0) return;
+        std::vector<double> a(S.count), b(S.count), c(S.count);
+        for (int64_t j = 0; j < S.count; ++j) {
+            a[j] = px[ix[j]];
+            b[j] = py[ix[j]];
+            c[j] = pz[ix[j]];
+        }
+        S.idx = p->upload(ix.data(), S.count);
+        S.x = p->upload(a.data(), S.count);
+        S.y = p->upload(b.data(), S.count);
+        S.z = p->upload(c.data(), S.count);
+        if (!with_v) return;
+        std::vector<double> va(S.count), vb(S.count), vc(S.count);
+        std::vector<float> fa(S.count), fb(S.count), fc(S.count);
+        for (int64_t j = 0; j < S.count; ++j) {
+            va[j] = vp[ix[j]];
+            vb[j] = vp[n + ix[j]];
+            vc[j] = vp[2 * n + ix[j]];
+            fa[j] = static_cast<float>(va[j]);
+            fb[j] = static_cast<float>(vb[j]);
+            fc[j] = static_cast<float>(vc[j]);
+        }
+        S.vx = p->upload(va.data(), S.count);
+        S.vy = p->upload(vb.data(), S.count);
+        S.vz = p->upload(vc.data(), S.count);
+        S.vxf = p->upload(fa.data(), S.count);
+        S.vyf = p->upload(fb.data(), S.count);
+        S.vzf = p->upload(fc.data(), S.count);
+    };
+    fill(p->G, gi, false);
+    fill(p->F, fi, true);
+}
+
+void check_problem(const vsie_problem *p, int32_t f) {
+    require(p != nullptr, "problem handle is NULL");
+    require(f >= 0 && f < static_cast<int32_t>(p->k0.size()), "frequency index out of range");
+}
+
+void check_vec(const double *v, int64_t ld, int64_t n, const char *name) {
+    require(v != nullptr, std::string(name) + " is NULL");
+    require(ld >= n, std::string("leading dimension of ") + name + " is smaller than n");
+}
+
+size_t csize(vsie_precision prec) { return prec == VSIE_FP64 ? sizeof(double2) : sizeof(float2); }
+
+// y = A_f x (forward operator) for at most kMaxRhsPerLaunch columns.
+void apply_forward_block(vsie_problem *p, int f, vsie_precision prec, int nrhs, const double2 *x,
+                         int64_t ldx, double2 *y, int64_t ldy, hipStream_t s) {
+    const int64_t n = p->m.n;
+    int64_t chG, chF;
+    int ncG, ncF;
+    choose_chunks(n, p->G.count, chG, ncG);
+    choose_chunks(n, p->F.count, chF, ncF);
+    const int n_parts = ncG + ncF;
+    double2 *part = static_cast<double2 *>(
+        p->partial.get(sizeof(double2) * static_cast<size_t>(std::max(1, n_parts)) * nrhs * n));
+    void *qG = p->chargeG.get(csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->G.count)) * nrhs);
+    void *qF = p->chargeF.get(csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->F.count)) * nrhs);
+    const double *spf = p->m.sp + static_cast<int64_t>(f) * n;
+    launch_pack_charges(kClassG, prec, p->G, spf, nrhs, x, ldx, false, qG, s);
+    launch_pack_charges(kClassF, prec, p->F, spf, nrhs, x, ldx, false, qF, s);
+    const double k = p->k0[f];
+    if (ncG > 0) {
+        PairJob J{PAIR_FWD_G, prec, n, p->m.px, p->m.py, p->m.pz, {}, {}, p->G.count,
+                  p->G.x, p->G.y, p->G.z, {}, {}, qG, p->G.count, nrhs, chG, ncG, k,
+                  part, static_cast<int64_t>(nrhs) * n};
+        launch_pairs(J, s, &p->prof);
+    }
+    if (ncF > 0) {
+        PairJob J{PAIR_FWD_F, prec, n, p->m.px, p->m.py, p->m.pz, {}, {}, p->F.count,
+                  p->F.x, p->F.y, p->F.z, {p->F.vx, p->F.vy, p->F.vz}, {p->F.vxf, p->F.vyf, p->F.vzf},
+                  qF, p->F.count, nrhs, chF, ncF, k,
+                  part + static_cast<int64_t>(ncG) * nrhs * n, static_cast<int64_t>(nrhs) * n};
+        launch_pairs(J, s, &p->prof);
+    }
+    launch_reduce_partials(n, nrhs, n_parts, part, p->m.diag + static_cast<int64_t>(f) * n, false, x,
+                           ldx, y, ldy, nullptr, s);
+}
+
+void apply_forward(vsie_problem *p, int f, vsie_precision prec, int nrhs, const double2 *x,
+                   int64_t ldx, double2 *y, int64_t ldy, hipStream_t s) {
+    for (int r0 = 0; r0 < nrhs; r0 += kMaxRhsPerLaunch) {
+        const int blk = std::min(kMaxRhsPerLaunch, nrhs - r0);
+        apply_forward_block(p, f, prec, blk, x + static_cast<int64_t>(r0) * ldx, ldx,
+                            y + static_cast<int64_t>(r0) * ldy, ldy, s);
+    }
+}
+
+// y = A_f^H x for at most kMaxRhsPerLaunch columns:
+// (A^H x)_j = conj(A_jj) x_j + sum_{i != j} conj(A_ij) x_i, evaluated per source
+// class with the roles of targets and sources exchanged.
+void apply_adjoint_block(vsie_problem *p, int f, vsie_precision prec, int nrhs, const double2 *x,
+                         int64_t ldx, double2 *y, int64_t ldy, hipStream_t s) {
+    const int64_t n = p->m.n;
+    void *q = p->chargeAll.get(csize(prec) * static_cast<size_t>(n) * nrhs);
+    launch_pack_plain(prec, n, nrhs, x, ldx, true, q, s);
+    // y = conj(diag) x
+    launch_reduce_partials(n, nrhs, 0, nullptr, p->m.diag + static_cast<int64_t>(f) * n, true, x, ldx,
+                           y, ldy, nullptr, s);
+    const double k = p->k0[f];
+    const double *spf = p->m.sp + static_cast<int64_t>(f) * n;
+    int64_t chG = 1, chF = 1;
+    int ncG = 0, ncF = 0;
+    if (p->G.count > 0) choose_chunks(p->G.count, n, chG, ncG);
+    if (p->F.count > 0) choose_chunks(p->F.count, n, chF, ncF);
+    const size_t need = std::max(static_cast<size_t>(ncG) * p->G.count, static_cast<size_t>(ncF) * p->F.count);
+    double2 *part = static_cast<double2 *>(p->partial.get(sizeof(double2) * std::max<size_t>(1, need) * nrhs));
+    if (ncG > 0) {
+        PairJob J{PAIR_FWD_G, prec, p->G.count, p->G.x, p->G.y, p->G.z, {}, {}, n,
+                  p->m.px, p->m.py, p->m.pz, {}, {}, q, n, nrhs, chG, ncG, k, part,
+                  static_cast<int64_t>(nrhs) * p->G.count};
+        launch_pairs(J, s, &p->prof);
+        launch_scatter_conj(p->G.count, p->G.idx, spf, nrhs, ncG, part, y, ldy, s);
+    }
+    if (ncF > 0) {
+        PairJob J{PAIR_ADJ_F, prec, p->F.count, p->F.x, p->F.y, p->F.z,
+                  {p->F.vx, p->F.vy, p->F.vz}, {p->F.vxf, p->F.vyf, p->F.vzf}, n,
+                  p->m.px, p->m.py, p->m.pz, {}, {}, q, n, nrhs, chF, ncF, k, part,
+                  static_cast<int64_t>(nrhs) * p->F.count};
+        launch_pairs(J, s, &p->prof);
+        launch_scatter_conj(p->F.count, p->F.idx, nullptr, nrhs, ncF, part, y, ldy, s);
+    }
+}
+
+void apply_adjoint(vsie_problem *p, int f, vsie_precision prec, int nrhs, const double2 *x,
+                   int64_t ldx, double2 *y, int64_t ldy, hipStream_t s) {
+    for (int r0 = 0; r0 < nrhs; r0 += kMaxRhsPerLaunch) {
+        const int blk = std::min(kMaxRhsPerLaunch, nrhs - r0);
+        apply_adjoint_block(p, f, prec, blk, x + static_cast<int64_t>(r0) * ldx, ldx,
+                            y + static_cast<int64_t>(r0) * ldy, ldy, s);
+    }
+}
+
+void apply_op(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int nrhs,
+              const double2 *x, int64_t ldx, double2 *y, int64_t ldy, hipStream_t s) {
+    if (adjoint) apply_adjoint(p, f, prec, nrhs, x, ldx, y, ldy, s);
+    else apply_forward(p, f, prec, nrhs, x, ldx, y, ldy, s);
+}
+
+// ---------------------------------------------------------------------------
+// GMRES
+
+struct SolveCounters {
+    int iterations = 0, mv64 = 0, mv32 = 0, outer = 0;
+};
+
+double device_norm(vsie_problem *p, const double2 *v, hipStream_t s) {
+    const int64_t n = p->m.n;
+    const int nch = static_cast<int>(std::min<int64_t>(1024, std::max<int64_t>(1, n / 1024)));
+    double *part = static_cast<double *>(p->npart.get(sizeof(double) * nch));
+    double *out = static_cast<double *>(p->nrm.get(sizeof(double) * 2));
+    blas_norm2(n, v, part, nch, out, s);
+    double h = 0;
+    VSIE_HIP(hipMemcpyAsync(&h, out, sizeof(double), hipMemcpyDeviceToHost, s));
+    VSIE_HIP(hipStreamSynchronize(s));
+    return h;
+}
+
+// One GMRES cycle on op(prec) for rhs r (norm rnorm), adding the correction
+// to x.  Stops after `m` iterations, at the iteration cap, or when the
+// residual estimate falls to cycle_tol * rnorm.
+int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const double2 *r,
+                double rnorm, double cycle_tol, int m, int iter_cap, double2 *x,
+                SolveCounters &cnt, hipStream_t s) {
+    using cd = std::complex<double>;
+    const int64_t n = p->m.n;
+    double2 *V = static_cast<double2 *>(p->V.get(sizeof(double2) * static_cast<size_t>(n) * (m + 1)));
+    double2 *w = static_cast<double2 *>(p->w.get(sizeof(double2) * n));
+    double2 *h1 = static_cast<double2 *>(p->h1.get(sizeof(double2) * (m + 2)));
+    double2 *h2 = static_cast<double2 *>(p->h2.get(sizeof(double2) * (m + 2)));
+    double *nrm = static_cast<double *>(p->nrm.get(sizeof(double) * 2));
+    const int nch = static_cast<int>(std::min<int64_t>(256, std::max<int64_t>(1, n / 2048)));
+    double2 *dpart = static_cast<double2 *>(p->dpart.get(sizeof(double2) * static_cast<size_t>(nch) * (m + 1)));
+    double *npart = static_cast<double *>(p->npart.get(sizeof(double) * std::max(nch, 1024)));
+    double2 *yv = static_cast<double2 *>(p->yv.get(sizeof(double2) * (m + 1)));
+
+    std::vector<cd> H(static_cast<size_t>(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0);
+    auto Hat = [&](int i, int j) -> cd & { return H[static_cast<size_t>(j) * (m + 1) + i]; };
+    std::vector<double2> hb(2 * (m + 1) + 1);
+
+    // v0 = r / rnorm
+    blas_scale(n, r, 1.0 / rnorm, V, s);
+    g[0] = rnorm;
+    int kdone = 0;
+    for (int k = 0; k < m && cnt.iterations < iter_cap; ++k) {
+        apply_op(p, f, prec, adjoint, 1, V + static_cast<int64_t>(k) * n, n, w, n, s);
+        (prec == VSIE_FP64 ? cnt.mv64 : cnt.mv32)++;
+        // classical Gram-Schmidt, twice
+        blas_dots(n, k + 1, V, n, w, dpart, nch, h1, s);
+        blas_gemv_sub(n, k + 1, V, n, h1, w, s);
+        blas_dots(n, k + 1, V, n, w, dpart, nch, h2, s);
+        blas_gemv_sub(n, k + 1, V, n, h2, w, s);
+        blas_norm2(n, w, npart, nch, nrm, s);
+        blas_scale_copy(n, w, nrm, V + static_cast<int64_t>(k + 1) * n, s);
+        VSIE_HIP(hipMemcpyAsync(hb.data(), h1, sizeof(double2) * (k + 1), hipMemcpyDeviceToHost, s));
+        VSIE_HIP(hipMemcpyAsync(hb.data() + (m + 1), h2, sizeof(double2) * (k + 1), hipMemcpyDeviceToHost, s));
+        VSIE_HIP(hipMemcpyAsync(hb.data() + 2 * (m + 1), nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+        VSIE_HIP(hipStreamSynchronize(s));
+        const double beta = reinterpret_cast<const double *>(hb.data() + 2 * (m + 1))[0];
+        if (!std::isfinite(beta)) fail(VSIE_E_NAN, "non-finite value in the Krylov basis");
+        for (int j = 0; j <= k; ++j)
+            Hat(j, k) = cd(hb[j].x + hb[m + 1 + j].x, hb[j].y + hb[m + 1 + j].y);
+        Hat(k + 1, k) = beta;
+        // unitary rotations [[conj(c), conj(s)], [-s, c]]
+        for (int j = 0; j < k; ++j) {
+            const cd a = Hat(j, k), b = Hat(j + 1, k);
+            Hat(j, k) = std::conj(cs[j]) * a + std::conj(sn[j]) * b;
+            Hat(j + 1, k) = -sn[j] * a + cs[j] * b;
+        }
+        const cd a = Hat(k, k), b = Hat(k + 1, k);
+        const double den = std::hypot(std::abs(a), std::abs(b));
+        if (den == 0.0) {  // w and the basis column are both zero: nothing more to gain
+            kdone = k;
+            break;
+        }
+        cs[k] = a / den;
+        sn[k] = b / den;
+        Hat(k, k) = den;
+        Hat(k + 1, k) = 0.0;
+        g[k + 1] = -sn[k] * g[k];
+        g[k] = std::conj(cs[k]) * g[k];
+        ++cnt.iterations;
+        kdone = k + 1;
+        if (std::abs(g[k + 1]) <= cycle_tol * rnorm || beta == 0.0) break;
+    }
+    if (kdone == 0) return 0;
+    // back substitution H y = g
+    std::vector<cd> y(kdone);
+    for (int i = kdone - 1; i >= 0; --i) {
+        cd acc = g[i];
+        for (int j = i + 1; j < kdone; ++j) acc -= Hat(i, j) * y[j];
+        y[i] = acc / Hat(i, i);
+    }
+    std::vector<double2> yh(kdone);
+    for (int i = 0; i < kdone; ++i) yh[i] = make_double2(y[i].real(), y[i].imag());
+    VSIE_HIP(hipMemcpyAsync(yv, yh.data(), sizeof(double2) * kdone, hipMemcpyHostToDevice, s));
+    blas_gemv_add(n, kdone, V, n, yv, x, s);
+    VSIE_HIP(hipStreamSynchronize(s));  // yh is a host temporary
+    return kdone;
+}
+
+vsie_status solve_one(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const double2 *b,
+                      double2 *x, const vsie_solve_opts &o, SolveCounters &cnt, double &relres,
+                      hipStream_t s) {
+    const int64_t n = p->m.n;
+    double2 *r = static_cast<double2 *>(p->r.get(sizeof(double2) * n));
+    double2 *ax = static_cast<double2 *>(p->ax.get(sizeof(double2) * n));
+    const double bnorm = device_norm(p, b, s);
+    if (!std::isfinite(bnorm)) fail(VSIE_E_NAN, "right-hand side is not finite");
+    if (bnorm == 0.0) {
+        blas_zero(n, x, s);
+        relres = 0.0;
+        return VSIE_OK;
+    }
+    const double xnorm = device_norm(p, x, s);
+    if (!std::isfinite(xnorm)) fail(VSIE_E_NAN, "initial guess is not finite");
+    bool x_zero = xnorm == 0.0;
+    const int m = std::max(1, o.restart);
+    for (;;) {
+        // residual of the current iterate with the FP64 operator
+        if (x_zero) {
+            blas_copy(n, b, n, r, n, 1, s);
+        } else {
+            apply_op(p, f, VSIE_FP64, adjoint, 1, x, n, ax, n, s);
+            ++cnt.mv64;
+            blas_sub(n, b, ax, r, s);
+        }
+        const double rn = device_norm(p, r, s);
+        if (!std::isfinite(rn)) fail(VSIE_E_NAN, "non-finite residual");
+        relres = rn / bnorm;
+        if (relres <= o.tol) return VSIE_OK;
+        if (cnt.iterations >= o.max_iter) return VSIE_E_NOCONV;
+        if (prec == VSIE_FP32 && cnt.outer >= o.max_outer) return VSIE_E_NOCONV;
+        double cycle_tol = o.tol * bnorm / rn;
+        if (prec == VSIE_FP32) cycle_tol = std::max(cycle_tol, o.inner_tol);
+        ++cnt.outer;
+        const int done = gmres_cycle(p, f, prec, adjoint, r, rn, cycle_tol, m, o.max_iter, x, cnt, s);
+        if (done == 0) return VSIE_E_NOCONV;  // no progress possible (breakdown at the first step)
+        x_zero = false;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// ABI
+
+extern "C" {
+
+const char *vsie_last_error(void) { return g_last_error.c_str(); }
+
+int64_t vsie_size(const vsie_problem *p) { return p ? p->m.n : 0; }
+
+void vsie_destroy(vsie_problem *p) { delete p; }
+
+vsie_status vsie_assemble(const vsie_geometry *geom, const double *vrho, const double *vc,
+                          const double *k0, int32_t n_freq, void *stream, vsie_problem **out) {
+    if (out) *out = nullptr;
+    return guarded([&] {
+        require(out != nullptr, "output handle pointer is NULL");
+        validate_geometry(geom, vrho, vc);
+        require(k0 != nullptr && n_freq >= 1, "need at least one wavenumber");
+        for (int f = 0; f < n_freq; ++f)
+            require(std::isfinite(k0[f]) && k0[f] > 0, "wavenumbers must be positive");
+        std::unique_ptr<vsie_problem> p(new vsie_problem());
+        VSIE_HIP(hipGetDevice(&p->device));
+        hipStream_t s = as_stream(stream);
+        const vsie_geometry &g = *geom;
+        DeviceMesh &m = p->m;
+        m.n_vol = g.n_vol;
+        m.n_srf = g.n_srf;
+        m.n = g.n_vol + g.n_srf;
+        m.rho0 = g.rho0;
+        m.c0 = g.c0;
+        std::vector<double> px(m.n), py(m.n), pz(m.n);
+        for (int64_t e = 0; e < g.n_vol; ++e) {
+            px[e] = g.vx[e];
+            py[e] = g.vy[e];
+            pz[e] = g.vz[e];
+        }
+        for (int64_t q = 0; q < g.n_srf; ++q) {
+            px[g.n_vol + q] = g.sx[q];
+            py[g.n_vol + q] = g.sy[q];
+            pz[g.n_vol + q] = g.sz[q];
+        }
+        m.px = p->upload(px.data(), m.n);
+        m.py = p->upload(py.data(), m.n);
+        m.pz = p->upload(pz.data(), m.n);
+        m.vw = p->upload(g.vw, g.n_vol);
+        m.vdom = p->upload(g.vdom, g.n_vol);
+        m.vnb = g.vnb ? p->upload(g.vnb, 6 * g.n_vol) : nullptr;
+        m.vga = g.vgrad_alpha ? p->upload(g.vgrad_alpha, 3 * g.n_vol) : nullptr;
+        m.vrho = p->upload(vrho, g.n_vol);
+        m.vc = p->upload(vc, g.n_vol);
+        m.snx = p->upload(g.snx, g.n_srf);
+        m.sny = p->upload(g.sny, g.n_srf);
+        m.snz = p->upload(g.snz, g.n_srf);
+        m.sarea = p->upload(g.sarea, g.n_srf);
+        m.siface = p->upload(g.siface, g.n_srf);
+        m.scin = p->upload(g.scell_in, g.n_srf);
+        m.scout = p->upload(g.scell_out, g.n_srf);
+        m.vpx = p->alloc<double>(m.n);
+        m.vpy = p->alloc<double>(m.n);
+        m.vpz = p->alloc<double>(m.n);
+        m.mass = p->alloc<double>(m.n);
+        m.sp = p->alloc<double>(m.n * n_freq);
+        m.diag = p->alloc<double2>(m.n * n_freq);
+        p->k0.assign(k0, k0 + n_freq);
+        p->d_k0 = p->upload(k0, n_freq);
+        launch_weights(m, p->d_k0, n_freq, s);
+        VSIE_HIP(hipStreamSynchronize(s));
+        build_sources(p.get());
+        *out = p.release();
+    });
+}
+
+vsie_status vsie_set_materials(vsie_problem *p, const double *vrho_dev, const double *vc_dev,
+                               void *stream) {
+    return guarded([&] {
+        require(p != nullptr, "problem handle is NULL");
+        require(p->m.n_vol == 0 || (vrho_dev && vc_dev), "material arrays must not be NULL");
+        hipStream_t s = as_stream(stream);
+        if (p->m.n_vol > 0) {
+            VSIE_HIP(hipMemcpyAsync(p->m.vrho, vrho_dev, sizeof(double) * p->m.n_vol, hipMemcpyDeviceToDevice, s));
+            VSIE_HIP(hipMemcpyAsync(p->m.vc, vc_dev, sizeof(double) * p->m.n_vol, hipMemcpyDeviceToDevice, s));
+            std::vector<double> hr(p->m.n_vol), hc(p->m.n_vol);
+            VSIE_HIP(hipMemcpyAsync(hr.data(), p->m.vrho, sizeof(double) * p->m.n_vol, hipMemcpyDeviceToHost, s));
+            VSIE_HIP(hipMemcpyAsync(hc.data(), p->m.vc, sizeof(double) * p->m.n_vol, hipMemcpyDeviceToHost, s));
+            VSIE_HIP(hipStreamSynchronize(s));
+            for (int64_t e = 0; e < p->m.n_vol; ++e)
+                require(hr[e] > 0 && std::isfinite(hr[e]) && hc[e] > 0 && std::isfinite(hc[e]),
+                        "density and sound speed must be positive at cell " + std::to_string(e));
+        }
+        launch_weights(p->m, p->d_k0, static_cast<int>(p->k0.size()), s);
+        VSIE_HIP(hipStreamSynchronize(s));
+        build_sources(p);
+    });
+}
+
+vsie_status vsie_matvec(vsie_problem *p, int32_t f, vsie_precision prec, int64_t nrhs,
+                        const double *x, int64_t ldx, double *y, int64_t ldy, void *stream) {
+    return guarded([&] {
+        check_problem(p, f);
+        require(prec == VSIE_FP64 || prec == VSIE_FP32, "unknown precision");
+        require(nrhs >= 1 && nrhs <= 4096, "nrhs must be in [1, 4096]");
+        check_vec(x, ldx, p->m.n, "x");
+        check_vec(y, ldy, p->m.n, "y");
+        apply_forward(p, f, prec, static_cast<int>(nrhs), reinterpret_cast<const double2 *>(x), ldx,
+                      reinterpret_cast<double2 *>(y), ldy, as_stream(stream));
+    });
+}
+
+vsie_status vsie_matvec_adjoint(vsie_problem *p, int32_t f, vsie_precision prec, int64_t nrhs,
+                                const double *x, int64_t ldx, double *y, int64_t ldy,
+                                void *stream) {
+    return guarded([&] {
+        check_problem(p, f);
+        require(prec == VSIE_FP64 || prec == VSIE_FP32, "unknown precision");
+        require(nrhs >= 1 && nrhs <= 4096, "nrhs must be in [1, 4096]");
+        check_vec(x, ldx, p->m.n, "x");
+        check_vec(y, ldy, p->m.n, "y");
+        apply_adjoint(p, f, prec, static_cast<int>(nrhs), reinterpret_cast<const double2 *>(x), ldx,
+                      reinterpret_cast<double2 *>(y), ldy, as_stream(stream));
+    });
+}
+
+vsie_status vsie_solve(vsie_problem *p, int32_t f, vsie_precision prec, int32_t adjoint,
+                       int64_t nrhs, const double *b, int64_t ldb, double *x, int64_t ldx,
+                       const vsie_solve_opts *opts, vsie_solve_info *info, void *stream) {
+    if (info) *info = vsie_solve_info{0, 0, 0, 0, 0.0};
+    vsie_status result = VSIE_OK;
+    const vsie_status st = guarded([&] {
+        check_problem(p, f);
+        require(prec == VSIE_FP64 || prec == VSIE_FP32, "unknown precision");
+        require(adjoint == 0 || adjoint == 1, "adjoint must be 0 or 1");
+        require(nrhs >= 1, "nrhs must be >= 1");
+        check_vec(b, ldb, p->m.n, "b");
+        check_vec(x, ldx, p->m.n, "x");
+        vsie_solve_opts o{1e-10, 3000, 500, 1e-5, 20};
+        if (opts) o = *opts;
+        require(o.tol > 0 && o.max_iter >= 0 && o.restart >= 1 && o.restart <= 20000 &&
+                    o.inner_tol > 0 && o.inner_tol < 1 && o.max_outer >= 1,
+                "invalid solver options");
+        hipStream_t s = as_stream(stream);
+        double worst = 0.0;
+        SolveCounters total;
+        for (int64_t c = 0; c < nrhs; ++c) {
+            SolveCounters cnt;
+            double rr = 0.0;
+            const vsie_status one = solve_one(p, f, prec, adjoint != 0,
+                                              reinterpret_cast<const double2 *>(b) + c * ldb,
+                                              reinterpret_cast<double2 *>(x) + c * ldx, o, cnt, rr, s);
+            if (one != VSIE_OK) result = one;
+            worst = std::max(worst, rr);
+            total.iterations += cnt.iterations;
+            total.mv64 += cnt.mv64;
+            total.mv32 += cnt.mv32;
+            total.outer = std::max(total.outer, cnt.outer);
+        }
+        if (info) *info = vsie_solve_info{total.iterations, total.outer, total.mv64, total.mv32, worst};
+        if (result == VSIE_E_NOCONV) g_last_error = "GMRES did not reach the tolerance";
+    });
+    return st != VSIE_OK ? st : result;
+}
+
+vsie_status vsie_plane_wave(vsie_problem *p, int32_t f, int64_t ndir, const double *dirs, double *b,
+                            int64_t ldb, void *stream) {
+    return guarded([&] {
+        check_problem(p, f);
+        require(ndir >= 1 && dirs != nullptr, "need at least one direction");
+        check_vec(b, ldb, p->m.n, "b");
+        for (int64_t d = 0; d < ndir; ++d) {
+            const double *u = dirs + 3 * d;
+            const double nn = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            require(std::fabs(nn - 1.0) <= 1e-12, "direction not of unit length");
+            launch_plane_wave(p->m.n, p->m.px, p->m.py, p->m.pz, p->k0[f], u[0], u[1], u[2],
+                              reinterpret_cast<double2 *>(b) + d * ldb, as_stream(stream));
+        }
+    });
+}
+
+vsie_status vsie_field(vsie_problem *p, int32_t f, vsie_precision prec, int64_t n_t, const double *tx,
+                       const double *ty, const double *tz, int64_t nrhs, const double *x, int64_t ldx,
+                       double *out, int64_t ldo, void *stream) {
+    return guarded([&] {
+        check_problem(p, f);
+        require(prec == VSIE_FP64 || prec == VSIE_FP32, "unknown precision");
+        require(n_t >= 1 && tx && ty && tz, "need target points");
+        require(nrhs >= 1 && nrhs <= 4096, "nrhs must be in [1, 4096]");
+        check_vec(x, ldx, p->m.n, "x");
+        check_vec(out, ldo, n_t, "out");
+        hipStream_t s = as_stream(stream);
+        const int R = static_cast<int>(nrhs);
+        const int64_t n = p->m.n;
+        int64_t chG, chF;
+        int ncG, ncF;
+        choose_chunks(n_t, p->G.count, chG, ncG);
+        choose_chunks(n_t, p->F.count, chF, ncF);
+        double2 *part = static_cast<double2 *>(
+            p->partial.get(sizeof(double2) * static_cast<size_t>(std::max(1, ncG + ncF)) * R * n_t));
+        void *qG = p->chargeG.get(csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->G.count)) * R);
+        void *qF = p->chargeF.get(csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->F.count)) * R);
+        const double *spf = p->m.sp + static_cast<int64_t>(f) * n;
+        const double2 *xv = reinterpret_cast<const double2 *>(x);
+        launch_pack_charges(kClassG, prec, p->G, spf, R, xv, ldx, false, qG, s);
+        launch_pack_charges(kClassF, prec, p->F, spf, R, xv, ldx, false, qF, s);
+        if (ncG > 0) {
+            PairJob J{PAIR_FWD_G, prec, n_t, tx, ty, tz, {}, {}, p->G.count, p->G.x, p->G.y, p->G.z,
+                      {}, {}, qG, p->G.count, R, chG, ncG, p->k0[f], part, static_cast<int64_t>(R) * n_t};
+            launch_pairs(J, s, &p->prof);
+        }
+        if (ncF > 0) {
+            PairJob J{PAIR_FWD_F, prec, n_t, tx, ty, tz, {}, {}, p->F.count, p->F.x, p->F.y, p->F.z,
+                      {p->F.vx, p->F.vy, p->F.vz}, {p->F.vxf, p->F.vyf, p->F.vzf}, qF, p->F.count, R,
+                      chF, ncF, p->k0[f], part + static_cast<int64_t>(ncG) * R * n_t,
+                      static_cast<int64_t>(R) * n_t};
+            launch_pairs(J, s, &p->prof);
+        }
+        launch_reduce_partials(n_t, R, ncG + ncF, part, nullptr, false, nullptr, 0,
+                               reinterpret_cast<double2 *>(out), ldo, nullptr, s);
+    });
+}
+
+vsie_status vsie_source_sums(vsie_problem *p, int32_t f, int64_t n_t, const double *tx,
+                             const double *ty, const double *tz, int64_t nrhs, const double *lam,
+                             int64_t ldl, double *z, int64_t ldz, double *Z, int64_t ldZ,
+                             void *stream) {
+    return guarded([&] {
+        check_problem(p, f);
+        require(nrhs >= 1 && nrhs <= 4096, "nrhs must be in [1, 4096]");
+        const int64_t n = p->m.n;
+        const bool colloc = tx == nullptr;
+        if (colloc) require(n_t == n && ty == nullptr && tz == nullptr, "collocation targets need n_t == n");
+        else require(n_t >= 1 && ty && tz, "need target points");
+        check_vec(lam, ldl, n_t, "lam");
+        check_vec(z, ldz, n, "z");
+        check_vec(Z, ldZ, n, "Z");
+        hipStream_t s = as_stream(stream);
+        const int R = static_cast<int>(nrhs);
+        void *q = p->chargeAll.get(sizeof(double2) * static_cast<size_t>(n_t) * R);
+        launch_pack_plain(VSIE_FP64, n_t, R, reinterpret_cast<const double2 *>(lam), ldl, true, q, s);
+        int64_t ch;
+        int nc;
+        choose_chunks(n, n_t, ch, nc);
+        double2 *part = static_cast<double2 *>(
+            p->sums_part.get(sizeof(double2) * static_cast<size_t>(nc) * R * 4 * n));
+        PairJob J{PAIR_SUMS, VSIE_FP64, n, p->m.px, p->m.py, p->m.pz, {}, {}, n_t,
+                  colloc ? p->m.px : tx, colloc ? p->m.py : ty, colloc ? p->m.pz : tz, {}, {}, q, n_t, R,
+                  ch, nc, p->k0[f], part, static_cast<int64_t>(R) * 4 * n};
+        launch_pairs(J, s, &p->prof);
+        launch_sums_reduce(n, R, nc, part, reinterpret_cast<double2 *>(z), ldz,
+                           reinterpret_cast<double2 *>(Z), ldZ, s);
+    });
+}
+
+vsie_status vsie_profile(vsie_problem *p, int32_t enable) {
+    return guarded([&] {
+        require(p != nullptr, "problem handle is NULL");
+        if (enable) {
+            VSIE_HIP(hipDeviceSynchronize());
+            for (auto &r : p->prof.recs) {
+                p->prof.pool.push_back(r.a);
+                p->prof.pool.push_back(r.b);
+            }
+            p->prof.recs.clear();
+        }
+        p->prof.on = enable != 0;
+    });
+}
+
+vsie_status vsie_profile_read(vsie_problem *p, int32_t kind, vsie_kernel_stats *out) {
+    return guarded([&] {
+        require(p != nullptr && out != nullptr, "NULL argument");
+        require(kind >= 0 && kind < 8, "kernel kind out of range");
+        vsie_kernel_stats st{0, 0.0, 0.0, 0.0};
+        for (auto &r : p->prof.recs) {
+            if (r.kind != kind) continue;
+            VSIE_HIP(hipEventSynchronize(r.b));
+            float ms = 0.f;
+            VSIE_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+            st.launches += 1;
+            st.ms += ms;
+            st.pairs += r.pairs;
+            st.rhs_pairs += r.rhs_pairs;
+        }
+        *out = st;
+    });
+}
+
+}  // extern "C"

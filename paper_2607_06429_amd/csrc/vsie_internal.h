@@ -1,0 +1,143 @@
+// Internal declarations shared by the HIP translation units of libvsie.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/vsie.h"
+
+namespace vsie {
+
+constexpr int kBlock = 256;          // threads per workgroup of the pair kernels (4 wave64)
+constexpr int kMaxRhsPerLaunch = 16; // right-hand sides one pair-kernel launch accumulates
+
+// Error raised inside the library and turned into a vsie_status at the ABI.
+struct Error {
+    vsie_status code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(vsie_status code, const std::string &msg);
+void check_hip(hipError_t e, const char *what);
+#define VSIE_HIP(call) ::vsie::check_hip((call), #call)
+
+// Source classes of the pair sum.  A volume cell with both a single-layer
+// weight and a grad-alpha weight appears in both lists.
+//   G: contribution  exp(i k r)/r * u_j,                    u_j = -s'_j x_j
+//   F: contribution  exp(i k r)/r * q_ij (i k r - 1) x_j,    q_ij = (x_i - y_j).v'_j / r^2
+// with s' = s / (4 pi) and v' = v / (4 pi).
+enum SrcClass { kClassG = 0, kClassF = 1 };
+
+// Device buffers of a problem.  Everything is in canonical unknown order
+// unless marked "class order".
+struct DeviceMesh {
+    int64_t n_vol = 0, n_srf = 0, n = 0;
+    double rho0 = 1, c0 = 1;
+    // collocation points (all n), FP64 and FP32 copies
+    double *px = nullptr, *py = nullptr, *pz = nullptr;
+    // volume data
+    double *vw = nullptr;
+    int32_t *vdom = nullptr, *vnb = nullptr;
+    double *vga = nullptr;  // optional explicit grad alpha (3 n_vol, xyz interleaved)
+    double *vrho = nullptr, *vc = nullptr;
+    // surface data
+    double *snx = nullptr, *sny = nullptr, *snz = nullptr, *sarea = nullptr;
+    int32_t *siface = nullptr, *scin = nullptr, *scout = nullptr;
+    // frequency independent weights: v' (3 x n SoA), mass function m (n)
+    double *vpx = nullptr, *vpy = nullptr, *vpz = nullptr, *mass = nullptr;
+    // per frequency: s' (n_freq x n), diagonal m - D (n_freq x n complex)
+    double *sp = nullptr;
+    double2 *diag = nullptr;
+};
+
+// Packed sources of one class in class order.
+struct SourceSet {
+    int64_t count = 0;
+    int32_t *idx = nullptr;                 // canonical index of each class entry
+    double *x = nullptr, *y = nullptr, *z = nullptr;    // FP64 centroids
+    float *xf = nullptr, *yf = nullptr, *zf = nullptr;  // FP32 centroids
+    double *vx = nullptr, *vy = nullptr, *vz = nullptr; // v' (F class only)
+    float *vxf = nullptr, *vyf = nullptr, *vzf = nullptr;
+};
+
+// One pair-sum pass (pair_kernels.hip).  Thread points t (n_t) each sum over
+// a chunk of streamed points s (n_s); out receives one FP64 partial per
+// (chunk, right-hand side, component, thread point):
+//   out[c * chunk_stride + (r * ncomp + comp) * n_t + i],  ncomp = 4 for SUMS, else 1.
+enum PairMode { PAIR_FWD_G = 0, PAIR_FWD_F = 1, PAIR_ADJ_F = 2, PAIR_SUMS = 3 };
+struct PairJob {
+    int mode;
+    vsie_precision prec;
+    int64_t n_t;
+    const double *tx, *ty, *tz;
+    const double *tv[3];      // ADJ_F, FP64: v' of thread points
+    const float *tvf[3];      // ADJ_F, FP32
+    int64_t n_s;
+    const double *sx, *sy, *sz;
+    const double *sv[3];      // FWD_F, FP64: v' of streamed points
+    const float *svf[3];      // FWD_F, FP32
+    const void *charge;       // complex charges (double2 or float2), charge[r * ldq + j]
+    int64_t ldq;
+    int nrhs;
+    int64_t chunk;            // streamed points per chunk
+    int n_chunks;             // ceil(n_s / chunk)
+    double k;
+    double2 *out;
+    int64_t chunk_stride;
+};
+// Optional timing of pair launches (one event pair per launch).
+struct PairProfiler {
+    bool on = false;
+    struct Rec {
+        hipEvent_t a, b;
+        int kind;
+        double pairs, rhs_pairs;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+};
+void launch_pairs(const PairJob &J, hipStream_t s, PairProfiler *prof = nullptr);
+
+// auxiliary kernels (aux_kernels.hip)
+void launch_weights(const DeviceMesh &m, const double *k0, int n_freq, hipStream_t s);
+// charge[r * count + jj] = scale * x[idx[jj] + r ldx], scale = -s'_f for class G, else 1
+void launch_pack_charges(SrcClass cls, vsie_precision prec, const SourceSet &src,
+                         const double *sp_f, int nrhs, const double2 *x, int64_t ldx,
+                         bool conj_in, void *charge, hipStream_t s);
+// charge[r * n + j] = x[j + r ldx] (conjugated when conj_in)
+void launch_pack_plain(vsie_precision prec, int64_t n, int nrhs, const double2 *x, int64_t ldx,
+                       bool conj_in, void *charge, hipStream_t s);
+// y = diag * x + sum of n_parts partial blocks (diag may be null)
+void launch_reduce_partials(int64_t n_t, int nrhs, int n_parts, const double2 *partial,
+                            const double2 *diag, bool conj_diag, const double2 *x, int64_t ldx,
+                            double2 *y, int64_t ldy, double2 *unused, hipStream_t s);
+// y[idx[jj]] += conj(scale * sum of partials), scale = -s' (sp != null) or 1
+void launch_scatter_conj(int64_t count, const int32_t *idx, const double *sp, int nrhs,
+                         int n_parts, const double2 *partial, double2 *y, int64_t ldy,
+                         hipStream_t s);
+void launch_sums_reduce(int64_t n, int nrhs, int n_parts, const double2 *partial, double2 *z,
+                        int64_t ldz, double2 *Z, int64_t ldZ, hipStream_t s);
+void launch_plane_wave(int64_t n, const double *px, const double *py, const double *pz, double k,
+                       double dx, double dy, double dz, double2 *b, hipStream_t s);
+
+// dense vector kernels for the Krylov solver (aux_kernels.hip)
+void blas_dots(int64_t n, int k, const double2 *V, int64_t ldv, const double2 *w,
+               double2 *partial, int n_chunks, double2 *h, hipStream_t s);
+void blas_gemv_sub(int64_t n, int k, const double2 *V, int64_t ldv, const double2 *h,
+                   double2 *w, hipStream_t s);
+void blas_gemv_add(int64_t n, int k, const double2 *V, int64_t ldv, const double2 *yv,
+                   double2 *x, hipStream_t s);
+void blas_norm2(int64_t n, const double2 *w, double *partial, int n_chunks, double *out,
+                hipStream_t s);
+void blas_scale_copy(int64_t n, const double2 *w, const double *nrm, double2 *v, hipStream_t s);
+void blas_scale(int64_t n, const double2 *w, double sc, double2 *v, hipStream_t s);
+void blas_zero(int64_t n, double2 *v, hipStream_t s);
+void blas_sub(int64_t n, const double2 *b, const double2 *ax, double2 *r, hipStream_t s);
+void blas_add(int64_t n, const double2 *d, double2 *x, hipStream_t s);
+void blas_copy(int64_t n, const double2 *a, int64_t lda, double2 *b, int64_t ldb, int ncols,
+               hipStream_t s);
+
+}  // namespace vsie

@@ -1,0 +1,257 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Bars: FP64 operator <= 1e-12 relative (2-norm over all entries), FP32 operator
+<= 1e-5, solutions of the refined FP32 path and of the FP64 path <= 1e-8
+against the oracle solution.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+TOL_SOLVE = 1e-8
+
+
+@pytest.fixture(scope="module")
+def V():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2607_06429_amd as V
+    return V
+
+
+def dev(a):
+    import torch
+    a = np.asarray(a, dtype=np.complex128)
+    if a.ndim == 1:
+        return torch.as_tensor(a, device="cuda")
+    return torch.as_tensor(np.ascontiguousarray(a.T), device="cuda")
+
+
+def host(t):
+    a = t.cpu().numpy()
+    return a if a.ndim == 1 else a.T
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def case(name):
+    """(mesh, materials, k0) of the small parity cases."""
+    if name == "c0":
+        m, mat, k0, _, _ = W.config_problem("c0")
+        return m, mat, k0[0]
+    if name == "ragged":          # 7^3 grid: n not a multiple of any tile
+        m = W.nested_balls(7)
+        return m, W.materials_piecewise(m, 1.0, 1.0, 1.2, 1.5, 2.0, 0.8), 3.0
+    if name == "lognormal":       # per-cell rho and c: grad alpha (T terms) active
+        m = W.nested_balls(10)
+        mat = W.materials_piecewise(m, 1.0, 1.0, 1.2, 1.5, 2.0, 0.8)
+        mat.vol_c = mat.vol_c * W.lognormal_voxel_field(m.vol_xyz, -1, 1, 32, 0.1, 0)
+        mat.vol_rho = mat.vol_rho * W.lognormal_voxel_field(m.vol_xyz, -1, 1, 32, 0.1, 1)
+        return m, mat, 5.0
+    if name == "single":          # Omega_2 with Omega_1's material
+        m = W.nested_balls(9)
+        return m, W.materials_piecewise(m, 1.0, 1.0, 1.4, 1.3, 1.4, 1.3), 2.5
+    if name == "cube":            # cube + ellipsoid, small grid
+        m = W.cube_with_ellipsoid(12)
+        mat = W.materials_piecewise(m, 1.0, 1.0, 1.1, 1.3, 2.0, 0.8)
+        mat.vol_c = mat.vol_c * W.lognormal_voxel_field(m.vol_xyz, -0.5, 0.5, 32, 0.1, 0)
+        return m, mat, 12.0
+    raise KeyError(name)
+
+
+CASES = ["c0", "ragged", "lognormal", "single", "cube"]
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("R", [1, 3, 17])
+def test_matvec_parity(V, name, R):
+    say("matvec parity", name, "R", R)
+    mesh, mat, k0 = case(name)
+    d = O.discretise(mesh, mat, k0)
+    P = V.Problem.from_mesh(mesh, mat, [k0])
+    x = W.seeded_complex((d.n, R), seed=11)
+    ref = O.matvec(d, x)
+    y64 = host(P.matvec(dev(x).contiguous(), prec=V.VSIE_FP64)).reshape(d.n, R)
+    y32 = host(P.matvec(dev(x).contiguous(), prec=V.VSIE_FP32)).reshape(d.n, R)
+    e64, e32 = O.rel_error(y64, ref), O.rel_error(y32, ref)
+    say("  rel err fp64 %.3e fp32 %.3e" % (e64, e32))
+    assert e64 <= TOL64
+    assert e32 <= TOL32
+
+
+@pytest.mark.parametrize("name", ["c0", "lognormal", "cube"])
+def test_adjoint_parity(V, name):
+    say("adjoint parity", name)
+    mesh, mat, k0 = case(name)
+    d = O.discretise(mesh, mat, k0)
+    P = V.Problem.from_mesh(mesh, mat, [k0])
+    lam = W.seeded_complex((d.n, 2), seed=12)
+    ref = O.adjoint_matvec(d, lam)
+    y64 = host(P.matvec_adjoint(dev(lam).contiguous(), prec=V.VSIE_FP64))
+    y32 = host(P.matvec_adjoint(dev(lam).contiguous(), prec=V.VSIE_FP32))
+    e64, e32 = O.rel_error(y64, ref), O.rel_error(y32, ref)
+    say("  rel err fp64 %.3e fp32 %.3e" % (e64, e32))
+    assert e64 <= TOL64 and e32 <= TOL32
+
+
+def test_homogeneous_medium_is_identity(V):
+    say("homogeneous medium")
+    mesh = W.nested_balls(8)
+    mat = W.materials_piecewise(mesh, 1.3, 0.7, 1.3, 0.7, 1.3, 0.7)
+    P = V.Problem.from_mesh(mesh, mat, [3.0])
+    x = W.seeded_complex(mesh.n, seed=3)
+    for prec in (V.VSIE_FP64, V.VSIE_FP32):
+        assert np.array_equal(host(P.matvec(dev(x), prec=prec)), x)
+
+
+def test_multi_frequency_weights(V):
+    say("multi-frequency problem")
+    mesh, mat, _ = case("lognormal")
+    ks = [2.0, 5.0, 7.5]
+    P = V.Problem.from_mesh(mesh, mat, ks)
+    x = W.seeded_complex(mesh.n, seed=4)
+    for f, k in enumerate(ks):
+        ref = O.matvec(O.discretise(mesh, mat, k), x)
+        assert O.rel_error(host(P.matvec(dev(x), f=f)), ref) <= TOL64
+
+
+def test_field_and_source_sums(V):
+    say("field and source sums")
+    mesh, mat, k0 = case("lognormal")
+    d = O.discretise(mesh, mat, k0)
+    P = V.Problem.from_mesh(mesh, mat, [k0])
+    p = W.seeded_complex((d.n, 2), seed=5)
+    rec = W.fibonacci_sphere(64, 2.5)
+    ref = O.offdiag_apply(d, p, targets=rec, exclude_self=False)
+    got = host(P.field(rec, dev(p).contiguous()))
+    assert O.rel_error(got, ref) <= TOL64
+    # collocation targets
+    z, Z = P.source_sums(dev(p).contiguous())
+    zr, Zr = O.source_sums(d, p)
+    assert O.rel_error(host(z), zr) <= TOL64
+    Zg = Z.cpu().numpy().transpose(2, 1, 0)   # (n, 3, R)
+    assert O.rel_error(Zg, Zr) <= TOL64
+    # receiver targets
+    rho = W.seeded_complex((64, 2), seed=6)
+    z, Z = P.source_sums(dev(rho).contiguous(), targets=rec)
+    zr, Zr = O.source_sums(d, rho, targets=rec, exclude_self=False)
+    assert O.rel_error(host(z), zr) <= TOL64
+    assert O.rel_error(Z.cpu().numpy().transpose(2, 1, 0), Zr) <= TOL64
+
+
+def test_plane_wave(V):
+    mesh, mat, k0 = case("c0")
+    P = V.Problem.from_mesh(mesh, mat, [k0])
+    dirs = W.fibonacci_sphere(5)
+    b = host(P.plane_wave(dirs))
+    ref = O.plane_wave(mesh.points(), k0, dirs)
+    assert O.rel_error(b, ref) <= 1e-14
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_solve_c0_against_oracle_lu(V, prec):
+    say("solve c0", prec)
+    mesh, mat, k0s, dirs, _ = W.config_problem("c0")
+    d = O.discretise(mesh, mat, k0s[0])
+    b = O.plane_wave(d.pts, k0s[0], dirs[0])
+    p_ref = O.solve_lu(d, b)
+    P = V.Problem.from_mesh(mesh, mat, k0s)
+    pr = V.VSIE_FP64 if prec == "fp64" else V.VSIE_FP32
+    x, info = P.solve(dev(b), prec=pr, tol=1e-10)
+    err = O.rel_error(host(x), p_ref)
+    say("  info", info, "err %.3e" % err)
+    assert info["status"] == V.VSIE_OK and info["rel_residual"] <= 1e-10
+    assert err <= TOL_SOLVE
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_adjoint_solve(V, prec):
+    say("adjoint solve", prec)
+    mesh, mat, k0 = case("lognormal")
+    d = O.discretise(mesh, mat, k0)
+    b = W.seeded_complex(d.n, seed=8)
+    import scipy.linalg as sla
+    ref = sla.solve(O.assemble(d).conj().T, b)
+    P = V.Problem.from_mesh(mesh, mat, [k0])
+    pr = V.VSIE_FP64 if prec == "fp64" else V.VSIE_FP32
+    x, info = P.solve(dev(b), prec=pr, adjoint=True, tol=1e-10)
+    assert info["status"] == V.VSIE_OK
+    assert O.rel_error(host(x), ref) <= TOL_SOLVE
+
+
+def test_multi_rhs_solve_and_restart(V):
+    say("multi-rhs solve with short restarts")
+    mesh, mat, k0 = case("ragged")
+    d = O.discretise(mesh, mat, k0)
+    dirs = W.fibonacci_sphere(3)
+    b = O.plane_wave(d.pts, k0, dirs)
+    ref = O.solve_lu(d, b)
+    P = V.Problem.from_mesh(mesh, mat, [k0])
+    x, info = P.solve(dev(b).contiguous(), prec=V.VSIE_FP64, tol=1e-11, restart=5)
+    assert info["status"] == V.VSIE_OK
+    assert O.rel_error(host(x), ref) <= TOL_SOLVE
+
+
+def test_solver_reports_nonconvergence(V):
+    mesh, mat, k0 = case("c0")
+    P = V.Problem.from_mesh(mesh, mat, [k0])
+    b = P.plane_wave([0.0, 0.0, 1.0])
+    x, info = P.solve(b, tol=1e-12, max_iter=2, restart=2, allow_noconv=True)
+    assert info["status"] == V.VSIE_E_NOCONV and info["iterations"] == 2
+    import torch
+    assert torch.isfinite(torch.view_as_real(x)).all()
+
+
+# ---------------------------------------------------------------------------
+# full-size c1 (n = 71,368): sampled rows and the stored oracle solution
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "c1_oracle_solution.npz")
+
+
+@pytest.fixture(scope="module")
+def c1(V):
+    mesh, mat, k0s, dirs, _ = W.config_problem("c1")
+    return mesh, mat, k0s, dirs, V.Problem.from_mesh(mesh, mat, k0s)
+
+
+def test_c1_matvec_sampled_rows(V, c1):
+    mesh, mat, k0s, dirs, P = c1
+    say("c1 matvec, sampled rows, n", P.n)
+    d = O.discretise(mesh, mat, k0s[0])
+    x = W.seeded_complex((d.n, 2), seed=21)
+    rows = np.sort(np.random.default_rng(22).choice(d.n, 384, replace=False))
+    rows = np.unique(np.concatenate([rows, [0, d.n_vol - 1, d.n_vol, d.n - 1]]))
+    ref = O.matvec(d, x, rows=rows)
+    y64 = host(P.matvec(dev(x).contiguous(), prec=V.VSIE_FP64))[rows]
+    y32 = host(P.matvec(dev(x).contiguous(), prec=V.VSIE_FP32))[rows]
+    e64, e32 = O.rel_error(y64, ref), O.rel_error(y32, ref)
+    say("  rel err fp64 %.3e fp32 %.3e" % (e64, e32))
+    assert e64 <= TOL64 and e32 <= TOL32
+
+
+@pytest.mark.skipif(not os.path.exists(GOLD), reason="c1 oracle solution not generated")
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_c1_solve_against_oracle_solution(V, c1, prec):
+    mesh, mat, k0s, dirs, P = c1
+    say("c1 solve", prec)
+    g = np.load(GOLD)
+    b = P.plane_wave(dirs[0])
+    pr = V.VSIE_FP64 if prec == "fp64" else V.VSIE_FP32
+    x, info = P.solve(b, prec=pr, tol=1e-10)
+    err = O.rel_error(host(x), g["p"])
+    say("  info", info, "err vs oracle %.3e" % err)
+    assert info["status"] == V.VSIE_OK
+    assert err <= TOL_SOLVE

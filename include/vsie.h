@@ -127,21 +127,26 @@ vsie_status vsie_matvec_adjoint(vsie_problem *p, int32_t f, vsie_precision prec,
 typedef struct {
     double tol;          /* stop when ||b - A x|| <= tol ||b|| (FP64 residual); default 1e-10 */
     int32_t max_iter;    /* total GMRES iterations (all cycles, all outer steps); default 3000 */
-    int32_t restart;     /* Krylov dimension per cycle; default 500 */
+    int32_t restart;     /* Krylov dimension per cycle; default 500, lowered when the
+                            basis of all nrhs right-hand sides would exceed 48 GiB */
     double inner_tol;    /* VSIE_FP32 only: relative tolerance of each inner solve; default 1e-5 */
     int32_t max_outer;   /* VSIE_FP32 only: refinement steps; default 20 */
 } vsie_solve_opts;
 
 typedef struct {
     int32_t iterations;     /* GMRES iterations summed over right-hand sides */
-    int32_t outer_steps;    /* refinement steps (VSIE_FP32), 1 for VSIE_FP64 */
-    int32_t matvecs_fp64;   /* operator applications in FP64 (per right-hand side) */
-    int32_t matvecs_fp32;   /* operator applications in FP32 (per right-hand side) */
+    int32_t outer_steps;    /* most GMRES cycles of any right-hand side (refinement steps
+                               for VSIE_FP32, restart cycles for VSIE_FP64) */
+    int32_t matvecs_fp64;   /* single-column operator applications in FP64, summed over
+                               right-hand sides */
+    int32_t matvecs_fp32;   /* the same in FP32 */
     double rel_residual;    /* max over right-hand sides of ||b - A x|| / ||b|| */
 } vsie_solve_info;
 
 /* Solve A_f x = b (adjoint = 0) or A_f^H x = b (adjoint = 1) by GMRES without
  * preconditioning (section 3.1), restarted every opts->restart iterations.
+ * The nrhs right-hand sides run independent GMRES processes in lockstep: each
+ * iteration applies the operator to all unconverged columns in one launch.
  * x holds the initial guess on entry and the solution on exit.  opts may be
  * NULL (defaults); info may be NULL.  Returns VSIE_E_NOCONV when the
  * tolerance was not reached (x still holds the last iterate). */
@@ -171,6 +176,39 @@ vsie_status vsie_source_sums(vsie_problem *p, int32_t f, int64_t n_t, const doub
                              const double *ty, const double *tz, int64_t nrhs,
                              const double *lam, int64_t ldl, double *z, int64_t ldz, double *Z,
                              int64_t ldZ, void *stream);
+
+/* b[:, r] = exp(i k0_f t . d_r) at n_t DEVICE points (tx, ty, tz), for ndir
+ * unit directions given as a HOST array of 3*ndir doubles (eq_planewave). */
+vsie_status vsie_plane_wave_at(vsie_problem *p, int32_t f, int64_t ndir, const double *dirs,
+                               int64_t n_t, const double *tx, const double *ty, const double *tz,
+                               double *out, int64_t ldo, void *stream);
+
+/* Right-hand side of the adjoint system of a receiver misfit:
+ *   out[j, r] = s_j zR[j, r] - v_j . ZR[j, r]
+ * (s_j, v_j the single-layer and double-layer weights of element j, see the
+ * top of this file; zR, ZR from vsie_source_sums over the receivers with the
+ * receiver residuals as lam).  All arrays on the device, layouts as in
+ * vsie_source_sums; out is n x nrhs. */
+vsie_status vsie_adjoint_rhs(vsie_problem *p, int32_t f, int64_t nrhs, const double *zR, int64_t ldz,
+                             const double *ZR, int64_t ldZ, double *out, int64_t ldo, void *stream);
+
+/* Gradient of a real receiver misfit J with respect to the per-cell sound
+ * speed and density of the problem's current materials, for nrhs forward
+ * solutions P (A_f P = b) and adjoint solutions lam (A_f^H lam = E^H rho,
+ * rho the conjugate-Wirtinger gradient of J with respect to the receiver
+ * pressures p_rec = p_inc - E P).  z, Z: vsie_source_sums of lam over the
+ * collocation points; zR, ZR: vsie_source_sums of rho over the receivers.
+ * Writes grad_c and grad_rho (DEVICE, n_vol doubles each), summed over the
+ * right-hand sides:
+ *   dJ = Re sum_r [ rho_r^H dE P_r - lam_r^H dA P_r ].
+ * The density enters through alpha = rho0/rho - 1 in the single-layer
+ * weights, the mass function, the interface jump weights and the grad-alpha
+ * neighbour stencil (not differentiated when vgrad_alpha was given). */
+vsie_status vsie_param_gradient(vsie_problem *p, int32_t f, int64_t nrhs, const double *P, int64_t ldp,
+                                const double *lam, int64_t ldl, const double *z, int64_t ldz,
+                                const double *Z, int64_t ldZ, const double *zR, int64_t ldzr,
+                                const double *ZR, int64_t ldZr, double *grad_c, double *grad_rho,
+                                void *stream);
 
 /* Kernel timing.  vsie_profile(p, 1) clears the counters and starts recording
  * a pair of HIP events around every pair-kernel launch made for p (on the

@@ -393,3 +393,21 @@ def gmres(apply, b, tol=1e-12, restart=200, maxiter=2000, x0=None, callback=None
 def solve_gmres(d: Discretisation, b, tol=1e-12, restart=200, maxiter=3000, callback=None):
     return gmres(lambda v: matvec(d, v), b, tol=tol, restart=restart, maxiter=maxiter,
                  callback=callback)
+
+
+# ---------------------------------------------------------------------------
+# receiver misfit (for finite-difference checks of adjoint gradients)
+
+def receiver_pressures(mesh, mat, k0, dirs, receivers):
+    """p_rec (n_rec, Q) for the plane waves `dirs` (Q, 3): dense LU solve of the
+    collocation system, then the representation formula at the receivers."""
+    d = discretise(mesh, mat, k0)
+    D = np.atleast_2d(dirs)
+    P = solve_lu(d, plane_wave(d.pts, k0, D))
+    return exterior_field(d, receivers, P, D)
+
+
+def receiver_misfit(mesh, mat, k0, dirs, receivers, data):
+    """J = 1/2 sum |p_rec - data|^2 over receivers and incidences."""
+    pr = receiver_pressures(mesh, mat, k0, dirs, receivers)
+    return 0.5 * float(np.sum(np.abs(pr - data) ** 2))

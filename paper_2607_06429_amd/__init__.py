@@ -20,8 +20,9 @@ import numpy as np
 __all__ = [
     "VSIE_OK", "VSIE_FP64", "VSIE_FP32", "VsieError", "Problem", "lib", "library_path",
     "vsie_assemble", "vsie_set_materials", "vsie_matvec", "vsie_matvec_adjoint", "vsie_solve",
-    "vsie_plane_wave", "vsie_field", "vsie_source_sums", "vsie_profile", "vsie_profile_read",
-    "vsie_destroy", "vsie_last_error", "vsie_size",
+    "vsie_plane_wave", "vsie_field", "vsie_source_sums", "vsie_plane_wave_at", "vsie_adjoint_rhs",
+    "vsie_param_gradient", "vsie_profile", "vsie_profile_read", "vsie_destroy", "vsie_last_error",
+    "vsie_size",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -87,6 +88,9 @@ def _load():
     L.vsie_field.argtypes = [_P, _I32, _I32, _I64, _P, _P, _P, _I64, _P, _I64, _P, _I64, _P]
     L.vsie_source_sums.argtypes = [_P, _I32, _I64, _P, _P, _P, _I64, _P, _I64, _P, _I64, _P,
                                    _I64, _P]
+    L.vsie_plane_wave_at.argtypes = [_P, _I32, _I64, _P, _I64, _P, _P, _P, _P, _I64, _P]
+    L.vsie_adjoint_rhs.argtypes = [_P, _I32, _I64, _P, _I64, _P, _I64, _P, _I64, _P]
+    L.vsie_param_gradient.argtypes = [_P, _I32, _I64] + [_P, _I64] * 6 + [_P, _P, _P]
     L.vsie_profile.argtypes = [_P, _I32]
     L.vsie_profile_read.argtypes = [_P, _I32, ctypes.POINTER(KernelStats)]
     L.vsie_destroy.argtypes = [_P]
@@ -94,7 +98,8 @@ def _load():
     L.vsie_last_error.restype = ctypes.c_char_p
     for name in ("vsie_assemble", "vsie_set_materials", "vsie_matvec", "vsie_matvec_adjoint",
                  "vsie_solve", "vsie_plane_wave", "vsie_field", "vsie_source_sums",
-                 "vsie_profile", "vsie_profile_read"):
+                 "vsie_profile", "vsie_profile_read", "vsie_plane_wave_at", "vsie_adjoint_rhs",
+                 "vsie_param_gradient"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -103,8 +108,8 @@ lib = _load()
 
 EXPORTED = ("vsie_assemble", "vsie_set_materials", "vsie_size", "vsie_matvec",
             "vsie_matvec_adjoint", "vsie_solve", "vsie_plane_wave", "vsie_field",
-            "vsie_source_sums", "vsie_profile", "vsie_profile_read", "vsie_destroy",
-            "vsie_last_error")
+            "vsie_source_sums", "vsie_plane_wave_at", "vsie_adjoint_rhs", "vsie_param_gradient",
+            "vsie_profile", "vsie_profile_read", "vsie_destroy", "vsie_last_error")
 
 # pair-kernel kinds reported by vsie_profile_read: 2 * mode + precision
 KIND_NAMES = {0: "fwd_single_layer_fp64", 1: "fwd_single_layer_fp32", 2: "fwd_double_layers_fp64",
@@ -277,6 +282,42 @@ def vsie_source_sums(h, f, lam, z, Z, targets=None, stream=None):
     _check(lib.vsie_source_sums(h, f, nt, tx, ty, tz, R, pl, ldl, pz, ldz, pZ, ldZ, _stream(stream)))
 
 
+def vsie_plane_wave_at(h, f, dirs, tx, ty, tz, out, stream=None):
+    nt = tx.shape[0]
+    po, R, ldo = _cols(out, nt)
+    D = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
+    if D.shape != (R, 3):
+        raise ValueError("need one unit direction per column of out")
+    _check(lib.vsie_plane_wave_at(h, f, R, _ptr(D), nt, _dptr(tx), _dptr(ty), _dptr(tz), po, ldo,
+                                  _stream(stream)))
+
+
+def vsie_adjoint_rhs(h, f, zR, ZR, out, stream=None):
+    """zR: (R, n), ZR: (3R, n), out: (R, n), complex128 CUDA tensors."""
+    n = vsie_size(h)
+    pz, R, ldz = _cols(zR, n)
+    pZ, R3, ldZ = _cols(ZR, n)
+    po, Ro, ldo = _cols(out, n)
+    if R3 != 3 * R or Ro != R:
+        raise ValueError("inconsistent right-hand-side counts")
+    _check(lib.vsie_adjoint_rhs(h, f, R, pz, ldz, pZ, ldZ, po, ldo, _stream(stream)))
+
+
+def vsie_param_gradient(h, f, P, lam, z, Z, zR, ZR, grad_c, grad_rho, stream=None):
+    """P, lam, z, zR: (R, n); Z, ZR: (3R, n); grad_c, grad_rho: float64 (n_vol,)."""
+    n = vsie_size(h)
+    args = []
+    R = None
+    for t, mult in ((P, 1), (lam, 1), (z, 1), (Z, 3), (zR, 1), (ZR, 3)):
+        pt, r, ld = _cols(t, n)
+        if R is None:
+            R = r
+        if r != mult * R:
+            raise ValueError("inconsistent right-hand-side counts")
+        args += [pt, ld]
+    _check(lib.vsie_param_gradient(h, f, R, *args, _dptr(grad_c), _dptr(grad_rho), _stream(stream)))
+
+
 def vsie_profile(h, enable):
     _check(lib.vsie_profile(h, 1 if enable else 0))
 
@@ -383,6 +424,32 @@ class Problem:
 
     def set_materials(self, rho_dev, c_dev):
         vsie_set_materials(self.handle, rho_dev, c_dev)
+
+    def plane_wave_at(self, targets, dirs, f=0):
+        import torch
+        T = torch.as_tensor(np.ascontiguousarray(targets, dtype=np.float64), device="cuda")
+        D = np.atleast_2d(dirs)
+        out = torch.empty((D.shape[0], T.shape[0]), dtype=torch.complex128, device="cuda")
+        vsie_plane_wave_at(self.handle, f, D, *(T[:, a].contiguous() for a in range(3)), out)
+        return out
+
+    def adjoint_rhs(self, zR, ZR, f=0):
+        """zR: (R, n); ZR: (R, 3, n) or (3R, n)."""
+        import torch
+        R = zR.shape[0]
+        out = torch.empty((R, self.n), dtype=torch.complex128, device="cuda")
+        vsie_adjoint_rhs(self.handle, f, zR.contiguous(), ZR.reshape(3 * R, self.n).contiguous(), out)
+        return out
+
+    def param_gradient(self, P, lam, z, Z, zR, ZR, n_vol, f=0):
+        import torch
+        R = P.shape[0]
+        gc = torch.empty(n_vol, dtype=torch.float64, device="cuda")
+        gr = torch.empty(n_vol, dtype=torch.float64, device="cuda")
+        vsie_param_gradient(self.handle, f, P.contiguous(), lam.contiguous(), z.contiguous(),
+                            Z.reshape(3 * R, self.n).contiguous(), zR.contiguous(),
+                            ZR.reshape(3 * R, self.n).contiguous(), gc, gr)
+        return gc, gr
 
     def profile(self, enable=True):
         vsie_profile(self.handle, enable)

@@ -332,6 +332,142 @@ __global__ void copy_kernel(int64_t n, int ncols, const double2 *__restrict__ a,
     for (int c = 0; c < ncols; ++c) b[i + c * ldb] = a[i + c * lda];
 }
 
+// --- batched Krylov kernels ---------------------------------------------------
+// The basis of right-hand side r (of R) stores vector j at V + (j R + r) n, so
+// the j-th vectors of all right-hand sides form one contiguous n x R block.
+// "slots" are the active right-hand sides of a launch: slot s is rhs act[s].
+
+__global__ __launch_bounds__(kT) void bdots_kernel(int64_t n, int64_t rows_per_chunk, int k, int R,
+                                                   const int32_t *__restrict__ act,
+                                                   const double2 *__restrict__ V,
+                                                   const double2 *__restrict__ W,
+                                                   double2 *__restrict__ partial, int n_chunks) {
+    __shared__ double2 sh[kT];
+    const int c = blockIdx.x, j = blockIdx.y, sl = blockIdx.z;
+    const int r = act[sl];
+    const int64_t r0 = static_cast<int64_t>(c) * rows_per_chunk;
+    const int64_t r1 = (r0 + rows_per_chunk < n) ? r0 + rows_per_chunk : n;
+    const double2 *__restrict__ col = V + (static_cast<int64_t>(j) * R + r) * n;
+    const double2 *__restrict__ w = W + static_cast<int64_t>(sl) * n;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kT) {
+        const double2 a = col[i], b = w[i];
+        acc.x += a.x * b.x + a.y * b.y;
+        acc.y += a.x * b.y - a.y * b.x;
+    }
+    const double2 sum = block_sum2<kT>(acc, sh);
+    if (threadIdx.x == 0) partial[(static_cast<int64_t>(sl) * k + j) * n_chunks + c] = sum;
+}
+
+// h[sl * hstride + j] = sum_c partial[(sl k + j) n_chunks + c]
+__global__ void bdots_final_kernel(int k, int nslots, const double2 *__restrict__ partial, int n_chunks,
+                                   double2 *__restrict__ h, int hstride) {
+    const int t = blockIdx.x * kT + threadIdx.x;
+    if (t >= k * nslots) return;
+    const int sl = t / k, j = t % k;
+    double2 acc = make_double2(0.0, 0.0);
+    const double2 *p = partial + (static_cast<int64_t>(sl) * k + j) * n_chunks;
+    for (int c = 0; c < n_chunks; ++c) {
+        acc.x += p[c].x;
+        acc.y += p[c].y;
+    }
+    h[sl * hstride + j] = acc;
+}
+
+// W[sl] -= sum_{j<k} V(j, act[sl]) h[sl * hstride + j]
+__global__ void bgemv_sub_kernel(int64_t n, int k, int R, const int32_t *__restrict__ act,
+                                 const double2 *__restrict__ V, const double2 *__restrict__ h,
+                                 int hstride, double2 *__restrict__ W) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+    const int sl = blockIdx.y;
+    if (i >= n) return;
+    const int r = act[sl];
+    double2 acc = make_double2(0.0, 0.0);
+    for (int j = 0; j < k; ++j) {
+        const double2 a = V[(static_cast<int64_t>(j) * R + r) * n + i], b = h[sl * hstride + j];
+        acc.x += a.x * b.x - a.y * b.y;
+        acc.y += a.x * b.y + a.y * b.x;
+    }
+    double2 *w = W + static_cast<int64_t>(sl) * n;
+    w[i] = make_double2(w[i].x - acc.x, w[i].y - acc.y);
+}
+
+// partial[sl * n_chunks + c] = sum over rows of chunk c of |W[sl][i]|^2
+__global__ __launch_bounds__(kT) void bnorm_kernel(int64_t n, int64_t rows_per_chunk,
+                                                   const double2 *__restrict__ W,
+                                                   double *__restrict__ partial, int n_chunks) {
+    __shared__ double2 sh[kT];
+    const int c = blockIdx.x, sl = blockIdx.y;
+    const int64_t r0 = static_cast<int64_t>(c) * rows_per_chunk;
+    const int64_t r1 = (r0 + rows_per_chunk < n) ? r0 + rows_per_chunk : n;
+    const double2 *w = W + static_cast<int64_t>(sl) * n;
+    double acc = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kT) acc += w[i].x * w[i].x + w[i].y * w[i].y;
+    const double2 sum = block_sum2<kT>(make_double2(acc, 0.0), sh);
+    if (threadIdx.x == 0) partial[static_cast<int64_t>(sl) * n_chunks + c] = sum.x;
+}
+
+__global__ void bnorm_final_kernel(int nslots, const double *__restrict__ partial, int n_chunks,
+                                   double *__restrict__ out) {
+    const int sl = blockIdx.x * kT + threadIdx.x;
+    if (sl >= nslots) return;
+    double acc = 0.0;
+    for (int c = 0; c < n_chunks; ++c) acc += partial[static_cast<int64_t>(sl) * n_chunks + c];
+    out[sl] = sqrt(acc);
+}
+
+// V(kcol, act[sl]) = W[sl] / nrm[sl]   (zero when nrm[sl] == 0)
+__global__ void bscale_into_basis_kernel(int64_t n, int kcol, int R, const int32_t *__restrict__ act,
+                                         const double2 *__restrict__ W, const double *__restrict__ nrm,
+                                         double2 *__restrict__ V) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+    const int sl = blockIdx.y;
+    if (i >= n) return;
+    const double s = nrm[sl];
+    const double inv = s > 0.0 ? 1.0 / s : 0.0;
+    const double2 w = W[static_cast<int64_t>(sl) * n + i];
+    V[(static_cast<int64_t>(kcol) * R + act[sl]) * n + i] = make_double2(w.x * inv, w.y * inv);
+}
+
+// X[sl] = src[act[sl] * ld + i]  (gather columns of a column-major block)
+__global__ void bgather_kernel(int64_t n, const int32_t *__restrict__ act,
+                               const double2 *__restrict__ src, int64_t ld, double2 *__restrict__ X) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+    const int sl = blockIdx.y;
+    if (i >= n) return;
+    X[static_cast<int64_t>(sl) * n + i] = src[static_cast<int64_t>(act[sl]) * ld + i];
+}
+
+// x[act[sl] * ldx + i] += sum_{j < kd[sl]} V(j, act[sl]) y[sl * ystride + j]
+__global__ void bupdate_kernel(int64_t n, int R, const int32_t *__restrict__ act,
+                               const int32_t *__restrict__ kd, const double2 *__restrict__ V,
+                               const double2 *__restrict__ y, int ystride, double2 *__restrict__ x,
+                               int64_t ldx) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+    const int sl = blockIdx.y;
+    if (i >= n) return;
+    const int r = act[sl];
+    double2 acc = make_double2(0.0, 0.0);
+    for (int j = 0; j < kd[sl]; ++j) {
+        const double2 a = V[(static_cast<int64_t>(j) * R + r) * n + i], b = y[sl * ystride + j];
+        acc.x += a.x * b.x - a.y * b.y;
+        acc.y += a.x * b.y + a.y * b.x;
+    }
+    double2 *xc = x + static_cast<int64_t>(r) * ldx;
+    xc[i] = make_double2(xc[i].x + acc.x, xc[i].y + acc.y);
+}
+
+// out[sl] = b[act[sl]] - ax[sl]   (ax and out hold slots contiguously)
+__global__ void bsub_kernel(int64_t n, const int32_t *__restrict__ act, const double2 *__restrict__ b,
+                            int64_t ldb, const double2 *__restrict__ ax, double2 *__restrict__ out) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+    const int sl = blockIdx.y;
+    if (i >= n) return;
+    const double2 bv = b[static_cast<int64_t>(act[sl]) * ldb + i];
+    const double2 av = ax[static_cast<int64_t>(sl) * n + i];
+    out[static_cast<int64_t>(sl) * n + i] = make_double2(bv.x - av.x, bv.y - av.y);
+}
+
 }  // namespace
 
 #define LAUNCH_CHECK() VSIE_HIP(hipGetLastError())
@@ -475,6 +611,73 @@ void blas_copy(int64_t n, const double2 *a, int64_t lda, double2 *b, int64_t ldb
                hipStream_t s) {
     if (n == 0 || ncols == 0) return;
     hipLaunchKernelGGL(copy_kernel, dim3(blocks_for(n)), dim3(kT), 0, s, n, ncols, a, lda, b, ldb);
+    LAUNCH_CHECK();
+}
+
+}  // namespace vsie
+
+namespace vsie {
+
+static int64_t rpc(int64_t n, int n_chunks) { return (n + n_chunks - 1) / n_chunks; }
+
+void bblas_dots(int64_t n, int k, int R, int nslots, const int32_t *act, const double2 *V,
+                const double2 *W, double2 *partial, int n_chunks, double2 *h, int hstride,
+                hipStream_t s) {
+    if (k == 0 || nslots == 0) return;
+    hipLaunchKernelGGL(bdots_kernel, dim3(n_chunks, k, nslots), dim3(kT), 0, s, n, rpc(n, n_chunks), k,
+                       R, act, V, W, partial, n_chunks);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(bdots_final_kernel, dim3(blocks_for(static_cast<int64_t>(k) * nslots)), dim3(kT),
+                       0, s, k, nslots, partial, n_chunks, h, hstride);
+    LAUNCH_CHECK();
+}
+
+void bblas_gemv_sub(int64_t n, int k, int R, int nslots, const int32_t *act, const double2 *V,
+                    const double2 *h, int hstride, double2 *W, hipStream_t s) {
+    if (k == 0 || nslots == 0) return;
+    hipLaunchKernelGGL(bgemv_sub_kernel, dim3(blocks_for(n), nslots), dim3(kT), 0, s, n, k, R, act, V,
+                       h, hstride, W);
+    LAUNCH_CHECK();
+}
+
+void bblas_norm(int64_t n, int nslots, const double2 *W, double *partial, int n_chunks, double *out,
+                hipStream_t s) {
+    if (nslots == 0) return;
+    hipLaunchKernelGGL(bnorm_kernel, dim3(n_chunks, nslots), dim3(kT), 0, s, n, rpc(n, n_chunks), W,
+                       partial, n_chunks);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(bnorm_final_kernel, dim3(blocks_for(nslots)), dim3(kT), 0, s, nslots, partial,
+                       n_chunks, out);
+    LAUNCH_CHECK();
+}
+
+void bblas_scale_into_basis(int64_t n, int kcol, int R, int nslots, const int32_t *act,
+                            const double2 *W, const double *nrm, double2 *V, hipStream_t s) {
+    if (nslots == 0) return;
+    hipLaunchKernelGGL(bscale_into_basis_kernel, dim3(blocks_for(n), nslots), dim3(kT), 0, s, n, kcol, R,
+                       act, W, nrm, V);
+    LAUNCH_CHECK();
+}
+
+void bblas_gather(int64_t n, int nslots, const int32_t *act, const double2 *src, int64_t ld,
+                  double2 *X, hipStream_t s) {
+    if (nslots == 0) return;
+    hipLaunchKernelGGL(bgather_kernel, dim3(blocks_for(n), nslots), dim3(kT), 0, s, n, act, src, ld, X);
+    LAUNCH_CHECK();
+}
+
+void bblas_update(int64_t n, int R, int nslots, const int32_t *act, const int32_t *kd, const double2 *V,
+                  const double2 *y, int ystride, double2 *x, int64_t ldx, hipStream_t s) {
+    if (nslots == 0) return;
+    hipLaunchKernelGGL(bupdate_kernel, dim3(blocks_for(n), nslots), dim3(kT), 0, s, n, R, act, kd, V, y,
+                       ystride, x, ldx);
+    LAUNCH_CHECK();
+}
+
+void bblas_sub(int64_t n, int nslots, const int32_t *act, const double2 *b, int64_t ldb,
+               const double2 *ax, double2 *out, hipStream_t s) {
+    if (nslots == 0) return;
+    hipLaunchKernelGGL(bsub_kernel, dim3(blocks_for(n), nslots), dim3(kT), 0, s, n, act, b, ldb, ax, out);
     LAUNCH_CHECK();
 }
 

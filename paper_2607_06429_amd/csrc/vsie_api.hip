@@ -75,10 +75,11 @@ struct vsie_problem {
     std::vector<double> k0;
     double *d_k0 = nullptr;
     SourceSet G, F;
+    int32_t *cf_off = nullptr, *cf_idx = nullptr;  // cell -> adjacent faces (CSR)
     std::vector<void *> owned;  // permanent device allocations
-    Scratch partial, chargeG, chargeF, chargeAll, sums_part;
+    Scratch partial, chargeG, chargeF, chargeAll, sums_part, grad_work;
     // Krylov workspace
-    Scratch V, w, r, ax, h1, h2, nrm, dpart, npart, yv;
+    Scratch V, w, r, ax, h1, h2, nrm, dpart, npart, yv, act, act2, live, kd, xa, axa, rres;
     PairProfiler prof;
 
     template <typename T>
@@ -113,8 +114,8 @@ struct vsie_problem {
         }
         for (hipEvent_t e : prof.pool) (void)hipEventDestroy(e);
         for (void *p : owned) (void)hipFree(p);
-        for (Scratch *s : {&partial, &chargeG, &chargeF, &chargeAll, &sums_part, &V, &w, &r, &ax,
-                           &h1, &h2, &nrm, &dpart, &npart, &yv})
+        for (Scratch *s : {&partial, &chargeG, &chargeF, &chargeAll, &sums_part, &grad_work, &V, &w, &r, &ax,
+                           &h1, &h2, &nrm, &dpart, &npart, &yv, &act, &act2, &live, &kd, &xa, &axa, &rres})
             s->release();
     }
 };
@@ -361,146 +362,257 @@ void apply_op(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int nrh
 }
 
 // ---------------------------------------------------------------------------
-// GMRES
+// GMRES over a batch of right-hand sides
+//
+// Every right-hand side runs its own GMRES(m); the batch advances in lockstep
+// so that each iteration applies the operator to all live right-hand sides in
+// one multi-RHS pair launch.  The Krylov basis of rhs r keeps vector j at
+// V + (j R + r) n.  Arnoldi uses classical Gram-Schmidt twice (CGS2); the
+// Hessenberg columns come to the host once per iteration for the Givens
+// rotations and the convergence test of each rhs.
 
 struct SolveCounters {
-    int iterations = 0, mv64 = 0, mv32 = 0, outer = 0;
+    std::vector<int> it, mv64, mv32, outer;
+    explicit SolveCounters(int R) : it(R, 0), mv64(R, 0), mv32(R, 0), outer(R, 0) {}
 };
 
-double device_norm(vsie_problem *p, const double2 *v, hipStream_t s) {
-    const int64_t n = p->m.n;
-    const int nch = static_cast<int>(std::min<int64_t>(1024, std::max<int64_t>(1, n / 1024)));
-    double *part = static_cast<double *>(p->npart.get(sizeof(double) * nch));
-    double *out = static_cast<double *>(p->nrm.get(sizeof(double) * 2));
-    blas_norm2(n, v, part, nch, out, s);
-    double h = 0;
-    VSIE_HIP(hipMemcpyAsync(&h, out, sizeof(double), hipMemcpyDeviceToHost, s));
+// host copy of a small device array, after the stream has drained
+template <typename T>
+void to_host(std::vector<T> &h, const T *d, size_t count, hipStream_t s) {
+    h.resize(count);
+    if (count) VSIE_HIP(hipMemcpyAsync(h.data(), d, sizeof(T) * count, hipMemcpyDeviceToHost, s));
     VSIE_HIP(hipStreamSynchronize(s));
+}
+
+template <typename T>
+void to_device(T *d, const std::vector<T> &h, hipStream_t s) {
+    if (h.empty()) return;
+    VSIE_HIP(hipMemcpyAsync(d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, s));
+    VSIE_HIP(hipStreamSynchronize(s));  // h may change right after
+}
+
+constexpr int64_t kKrylovBytes = int64_t(48) << 30;  // cap on the Krylov basis (48 GiB)
+
+int norm_chunks(int64_t n) { return static_cast<int>(std::min<int64_t>(256, std::max<int64_t>(1, n / 2048))); }
+
+// 2-norms of nslots contiguous columns of length n
+std::vector<double> column_norms(vsie_problem *p, const double2 *W, int nslots, hipStream_t s) {
+    const int64_t n = p->m.n;
+    const int nch = norm_chunks(n);
+    double *part = static_cast<double *>(p->npart.get(sizeof(double) * nch * std::max(1, nslots)));
+    double *out = static_cast<double *>(p->nrm.get(sizeof(double) * std::max(1, nslots)));
+    bblas_norm(n, nslots, W, part, nch, out, s);
+    std::vector<double> h;
+    to_host(h, out, nslots, s);
     return h;
 }
 
-// One GMRES cycle on op(prec) for rhs r (norm rnorm), adding the correction
-// to x.  Stops after `m` iterations, at the iteration cap, or when the
-// residual estimate falls to cycle_tol * rnorm.
-int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const double2 *r,
-                double rnorm, double cycle_tol, int m, int iter_cap, double2 *x,
+// One GMRES cycle for the right-hand sides rhs[0..ns) (slot order), with
+// residual block Rres (ns x n, norms rn) and per-slot stopping tolerances;
+// adds the corrections to x.  Returns the number of iterations performed.
+int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R,
+                const std::vector<int32_t> &rhs, const double2 *Rres, const std::vector<double> &rn,
+                const std::vector<double> &ctol, int m, int iter_cap, double2 *x, int64_t ldx,
                 SolveCounters &cnt, hipStream_t s) {
     using cd = std::complex<double>;
     const int64_t n = p->m.n;
-    double2 *V = static_cast<double2 *>(p->V.get(sizeof(double2) * static_cast<size_t>(n) * (m + 1)));
-    double2 *w = static_cast<double2 *>(p->w.get(sizeof(double2) * n));
-    double2 *h1 = static_cast<double2 *>(p->h1.get(sizeof(double2) * (m + 2)));
-    double2 *h2 = static_cast<double2 *>(p->h2.get(sizeof(double2) * (m + 2)));
-    double *nrm = static_cast<double *>(p->nrm.get(sizeof(double) * 2));
-    const int nch = static_cast<int>(std::min<int64_t>(256, std::max<int64_t>(1, n / 2048)));
-    double2 *dpart = static_cast<double2 *>(p->dpart.get(sizeof(double2) * static_cast<size_t>(nch) * (m + 1)));
-    double *npart = static_cast<double *>(p->npart.get(sizeof(double) * std::max(nch, 1024)));
-    double2 *yv = static_cast<double2 *>(p->yv.get(sizeof(double2) * (m + 1)));
+    const int ns = static_cast<int>(rhs.size());
+    const int hs = m + 2;  // stride of per-slot Hessenberg columns
+    double2 *V = static_cast<double2 *>(p->V.get(sizeof(double2) * static_cast<size_t>(n) * R * (m + 1)));
+    double2 *W = static_cast<double2 *>(p->w.get(sizeof(double2) * static_cast<size_t>(n) * ns));
+    double2 *X = static_cast<double2 *>(p->ax.get(sizeof(double2) * static_cast<size_t>(n) * ns));
+    double2 *h1 = static_cast<double2 *>(p->h1.get(sizeof(double2) * static_cast<size_t>(hs) * ns));
+    double2 *h2 = static_cast<double2 *>(p->h2.get(sizeof(double2) * static_cast<size_t>(hs) * ns));
+    const int nch = norm_chunks(n);
+    double2 *dpart = static_cast<double2 *>(
+        p->dpart.get(sizeof(double2) * static_cast<size_t>(nch) * (m + 1) * ns));
+    double *npart = static_cast<double *>(p->npart.get(sizeof(double) * nch * ns));
+    double *nrm = static_cast<double *>(p->nrm.get(sizeof(double) * ns));
+    int32_t *act = static_cast<int32_t *>(p->act.get(sizeof(int32_t) * ns));
+    int32_t *live_d = static_cast<int32_t *>(p->live.get(sizeof(int32_t) * ns));
+    double2 *yv = static_cast<double2 *>(p->yv.get(sizeof(double2) * static_cast<size_t>(m + 1) * ns));
+    int32_t *kd_d = static_cast<int32_t *>(p->kd.get(sizeof(int32_t) * ns));
 
-    std::vector<cd> H(static_cast<size_t>(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0);
-    auto Hat = [&](int i, int j) -> cd & { return H[static_cast<size_t>(j) * (m + 1) + i]; };
-    std::vector<double2> hb(2 * (m + 1) + 1);
+    // v0 = r / |r|
+    to_device(act, rhs, s);
+    to_device(nrm, rn, s);
+    bblas_scale_into_basis(n, 0, R, ns, act, Rres, nrm, V, s);
 
-    // v0 = r / rnorm
-    blas_scale(n, r, 1.0 / rnorm, V, s);
-    g[0] = rnorm;
-    int kdone = 0;
-    for (int k = 0; k < m && cnt.iterations < iter_cap; ++k) {
-        apply_op(p, f, prec, adjoint, 1, V + static_cast<int64_t>(k) * n, n, w, n, s);
-        (prec == VSIE_FP64 ? cnt.mv64 : cnt.mv32)++;
-        // classical Gram-Schmidt, twice
-        blas_dots(n, k + 1, V, n, w, dpart, nch, h1, s);
-        blas_gemv_sub(n, k + 1, V, n, h1, w, s);
-        blas_dots(n, k + 1, V, n, w, dpart, nch, h2, s);
-        blas_gemv_sub(n, k + 1, V, n, h2, w, s);
-        blas_norm2(n, w, npart, nch, nrm, s);
-        blas_scale_copy(n, w, nrm, V + static_cast<int64_t>(k + 1) * n, s);
-        VSIE_HIP(hipMemcpyAsync(hb.data(), h1, sizeof(double2) * (k + 1), hipMemcpyDeviceToHost, s));
-        VSIE_HIP(hipMemcpyAsync(hb.data() + (m + 1), h2, sizeof(double2) * (k + 1), hipMemcpyDeviceToHost, s));
-        VSIE_HIP(hipMemcpyAsync(hb.data() + 2 * (m + 1), nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<std::vector<cd>> H(ns, std::vector<cd>(static_cast<size_t>(m + 1) * m, 0.0));
+    std::vector<std::vector<cd>> cs(ns, std::vector<cd>(m)), sn(ns, std::vector<cd>(m)),
+        g(ns, std::vector<cd>(m + 1, 0.0));
+    std::vector<int> kdone(ns, 0);
+    std::vector<char> done(ns, 0);
+    for (int sl = 0; sl < ns; ++sl) g[sl][0] = rn[sl];
+    std::vector<double2> hb1, hb2;
+    std::vector<double> hbeta;
+    int total = 0;
+    for (int k = 0; k < m; ++k) {
+        std::vector<int32_t> live_rhs, live_slot;
+        for (int sl = 0; sl < ns; ++sl)
+            if (!done[sl] && cnt.it[rhs[sl]] < iter_cap) {
+                live_rhs.push_back(rhs[sl]);
+                live_slot.push_back(sl);
+            }
+        const int nl = static_cast<int>(live_rhs.size());
+        if (nl == 0) break;
+        to_device(live_d, live_rhs, s);
+        // W = A v_k for the live right-hand sides
+        bblas_gather(n, nl, live_d, V + static_cast<int64_t>(k) * R * n, n, X, s);
+        apply_op(p, f, prec, adjoint, nl, X, n, W, n, s);
+        for (int r : live_rhs) (prec == VSIE_FP64 ? cnt.mv64 : cnt.mv32)[r]++;
+        bblas_dots(n, k + 1, R, nl, live_d, V, W, dpart, nch, h1, hs, s);
+        bblas_gemv_sub(n, k + 1, R, nl, live_d, V, h1, hs, W, s);
+        bblas_dots(n, k + 1, R, nl, live_d, V, W, dpart, nch, h2, hs, s);
+        bblas_gemv_sub(n, k + 1, R, nl, live_d, V, h2, hs, W, s);
+        bblas_norm(n, nl, W, npart, nch, nrm, s);
+        bblas_scale_into_basis(n, k + 1, R, nl, live_d, W, nrm, V, s);
+        hb1.resize(static_cast<size_t>(hs) * nl);
+        hb2.resize(static_cast<size_t>(hs) * nl);
+        hbeta.resize(nl);
+        VSIE_HIP(hipMemcpyAsync(hb1.data(), h1, sizeof(double2) * hs * nl, hipMemcpyDeviceToHost, s));
+        VSIE_HIP(hipMemcpyAsync(hb2.data(), h2, sizeof(double2) * hs * nl, hipMemcpyDeviceToHost, s));
+        VSIE_HIP(hipMemcpyAsync(hbeta.data(), nrm, sizeof(double) * nl, hipMemcpyDeviceToHost, s));
         VSIE_HIP(hipStreamSynchronize(s));
-        const double beta = reinterpret_cast<const double *>(hb.data() + 2 * (m + 1))[0];
-        if (!std::isfinite(beta)) fail(VSIE_E_NAN, "non-finite value in the Krylov basis");
-        for (int j = 0; j <= k; ++j)
-            Hat(j, k) = cd(hb[j].x + hb[m + 1 + j].x, hb[j].y + hb[m + 1 + j].y);
-        Hat(k + 1, k) = beta;
-        // unitary rotations [[conj(c), conj(s)], [-s, c]]
-        for (int j = 0; j < k; ++j) {
-            const cd a = Hat(j, k), b = Hat(j + 1, k);
-            Hat(j, k) = std::conj(cs[j]) * a + std::conj(sn[j]) * b;
-            Hat(j + 1, k) = -sn[j] * a + cs[j] * b;
+        for (int l = 0; l < nl; ++l) {
+            const int sl = live_slot[l];
+            auto Hat = [&](int i, int j) -> cd & { return H[sl][static_cast<size_t>(j) * (m + 1) + i]; };
+            const double beta = hbeta[l];
+            if (!std::isfinite(beta)) fail(VSIE_E_NAN, "non-finite value in the Krylov basis");
+            for (int j = 0; j <= k; ++j)
+                Hat(j, k) = cd(hb1[l * hs + j].x + hb2[l * hs + j].x, hb1[l * hs + j].y + hb2[l * hs + j].y);
+            Hat(k + 1, k) = beta;
+            // unitary rotations [[conj(c), conj(s)], [-s, c]]
+            for (int j = 0; j < k; ++j) {
+                const cd a = Hat(j, k), b = Hat(j + 1, k);
+                Hat(j, k) = std::conj(cs[sl][j]) * a + std::conj(sn[sl][j]) * b;
+                Hat(j + 1, k) = -sn[sl][j] * a + cs[sl][j] * b;
+            }
+            const cd a = Hat(k, k), b = Hat(k + 1, k);
+            const double den = std::hypot(std::abs(a), std::abs(b));
+            if (den == 0.0) {  // no new direction: keep the first k columns
+                done[sl] = 1;
+                continue;
+            }
+            cs[sl][k] = a / den;
+            sn[sl][k] = b / den;
+            Hat(k, k) = den;
+            Hat(k + 1, k) = 0.0;
+            g[sl][k + 1] = -sn[sl][k] * g[sl][k];
+            g[sl][k] = std::conj(cs[sl][k]) * g[sl][k];
+            cnt.it[rhs[sl]]++;
+            ++total;
+            kdone[sl] = k + 1;
+            if (std::abs(g[sl][k + 1]) <= ctol[sl] * rn[sl] || beta == 0.0) done[sl] = 1;
         }
-        const cd a = Hat(k, k), b = Hat(k + 1, k);
-        const double den = std::hypot(std::abs(a), std::abs(b));
-        if (den == 0.0) {  // w and the basis column are both zero: nothing more to gain
-            kdone = k;
-            break;
+    }
+    // x += V y with H y = g (back substitution per slot)
+    std::vector<double2> yh(static_cast<size_t>(m + 1) * ns, make_double2(0.0, 0.0));
+    std::vector<int32_t> kdh(ns);
+    for (int sl = 0; sl < ns; ++sl) {
+        const int kk = kdone[sl];
+        kdh[sl] = kk;
+        auto Hat = [&](int i, int j) -> cd & { return H[sl][static_cast<size_t>(j) * (m + 1) + i]; };
+        std::vector<cd> y(kk);
+        for (int i = kk - 1; i >= 0; --i) {
+            cd acc = g[sl][i];
+            for (int j = i + 1; j < kk; ++j) acc -= Hat(i, j) * y[j];
+            y[i] = acc / Hat(i, i);
         }
-        cs[k] = a / den;
-        sn[k] = b / den;
-        Hat(k, k) = den;
-        Hat(k + 1, k) = 0.0;
-        g[k + 1] = -sn[k] * g[k];
-        g[k] = std::conj(cs[k]) * g[k];
-        ++cnt.iterations;
-        kdone = k + 1;
-        if (std::abs(g[k + 1]) <= cycle_tol * rnorm || beta == 0.0) break;
+        for (int i = 0; i < kk; ++i) yh[static_cast<size_t>(sl) * (m + 1) + i] = make_double2(y[i].real(), y[i].imag());
     }
-    if (kdone == 0) return 0;
-    // back substitution H y = g
-    std::vector<cd> y(kdone);
-    for (int i = kdone - 1; i >= 0; --i) {
-        cd acc = g[i];
-        for (int j = i + 1; j < kdone; ++j) acc -= Hat(i, j) * y[j];
-        y[i] = acc / Hat(i, i);
-    }
-    std::vector<double2> yh(kdone);
-    for (int i = 0; i < kdone; ++i) yh[i] = make_double2(y[i].real(), y[i].imag());
-    VSIE_HIP(hipMemcpyAsync(yv, yh.data(), sizeof(double2) * kdone, hipMemcpyHostToDevice, s));
-    blas_gemv_add(n, kdone, V, n, yv, x, s);
-    VSIE_HIP(hipStreamSynchronize(s));  // yh is a host temporary
-    return kdone;
+    to_device(yv, yh, s);
+    to_device(kd_d, kdh, s);
+    bblas_update(n, R, ns, act, kd_d, V, yv, m + 1, x, ldx, s);
+    return total;
 }
 
-vsie_status solve_one(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const double2 *b,
-                      double2 *x, const vsie_solve_opts &o, SolveCounters &cnt, double &relres,
-                      hipStream_t s) {
+// Solve op(A) x_r = b_r for r < R.  FP64: restarted GMRES(m), each restart
+// from the true FP64 residual.  FP32: the same loop is iterative refinement --
+// residuals with the FP64 operator, corrections from one GMRES cycle with the
+// FP32 operator to the inner tolerance.
+vsie_status solve_batch(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R,
+                        const double2 *b, int64_t ldb, double2 *x, int64_t ldx,
+                        const vsie_solve_opts &o, SolveCounters &cnt, std::vector<double> &relres,
+                        hipStream_t s) {
     const int64_t n = p->m.n;
-    double2 *r = static_cast<double2 *>(p->r.get(sizeof(double2) * n));
-    double2 *ax = static_cast<double2 *>(p->ax.get(sizeof(double2) * n));
-    const double bnorm = device_norm(p, b, s);
-    if (!std::isfinite(bnorm)) fail(VSIE_E_NAN, "right-hand side is not finite");
-    if (bnorm == 0.0) {
-        blas_zero(n, x, s);
-        relres = 0.0;
-        return VSIE_OK;
+    // restart length: as asked, but the basis of all R right-hand sides must fit kKrylovBytes
+    const int64_t col_bytes = static_cast<int64_t>(sizeof(double2)) * n * R;
+    const int m = static_cast<int>(std::max<int64_t>(
+        1, std::min<int64_t>(std::max(1, o.restart), kKrylovBytes / col_bytes - 1)));
+    relres.assign(R, 0.0);
+    std::vector<int32_t> all(R);
+    for (int r = 0; r < R; ++r) all[r] = r;
+    int32_t *act = static_cast<int32_t *>(p->act2.get(sizeof(int32_t) * R));
+    double2 *blk = static_cast<double2 *>(p->r.get(sizeof(double2) * static_cast<size_t>(n) * R));
+    double2 *Xa = static_cast<double2 *>(p->xa.get(sizeof(double2) * static_cast<size_t>(n) * R));
+    double2 *AX = static_cast<double2 *>(p->axa.get(sizeof(double2) * static_cast<size_t>(n) * R));
+    double2 *Rres = static_cast<double2 *>(p->rres.get(sizeof(double2) * static_cast<size_t>(n) * R));
+    to_device(act, all, s);
+    bblas_gather(n, R, act, b, ldb, blk, s);
+    const std::vector<double> bn = column_norms(p, blk, R, s);
+    bblas_gather(n, R, act, x, ldx, blk, s);
+    const std::vector<double> xn = column_norms(p, blk, R, s);
+    std::vector<char> xzero(R);
+    std::vector<int32_t> active;
+    for (int r = 0; r < R; ++r) {
+        if (!std::isfinite(bn[r])) fail(VSIE_E_NAN, "right-hand side is not finite");
+        if (!std::isfinite(xn[r])) fail(VSIE_E_NAN, "initial guess is not finite");
+        xzero[r] = xn[r] == 0.0;
+        if (bn[r] == 0.0) blas_zero(n, x + static_cast<int64_t>(r) * ldx, s);
+        else active.push_back(r);
     }
-    const double xnorm = device_norm(p, x, s);
-    if (!std::isfinite(xnorm)) fail(VSIE_E_NAN, "initial guess is not finite");
-    bool x_zero = xnorm == 0.0;
-    const int m = std::max(1, o.restart);
-    for (;;) {
-        // residual of the current iterate with the FP64 operator
-        if (x_zero) {
-            blas_copy(n, b, n, r, n, 1, s);
+    vsie_status status = VSIE_OK;
+    while (!active.empty()) {
+        const int na = static_cast<int>(active.size());
+        to_device(act, active, s);
+        bool any_x = false;
+        for (int r : active) any_x = any_x || !xzero[r];
+        if (any_x) {
+            bblas_gather(n, na, act, x, ldx, Xa, s);
+            apply_op(p, f, VSIE_FP64, adjoint, na, Xa, n, AX, n, s);
+            for (int r : active) cnt.mv64[r]++;
+            bblas_sub(n, na, act, b, ldb, AX, Rres, s);
         } else {
-            apply_op(p, f, VSIE_FP64, adjoint, 1, x, n, ax, n, s);
-            ++cnt.mv64;
-            blas_sub(n, b, ax, r, s);
+            bblas_gather(n, na, act, b, ldb, Rres, s);
         }
-        const double rn = device_norm(p, r, s);
-        if (!std::isfinite(rn)) fail(VSIE_E_NAN, "non-finite residual");
-        relres = rn / bnorm;
-        if (relres <= o.tol) return VSIE_OK;
-        if (cnt.iterations >= o.max_iter) return VSIE_E_NOCONV;
-        if (prec == VSIE_FP32 && cnt.outer >= o.max_outer) return VSIE_E_NOCONV;
-        double cycle_tol = o.tol * bnorm / rn;
-        if (prec == VSIE_FP32) cycle_tol = std::max(cycle_tol, o.inner_tol);
-        ++cnt.outer;
-        const int done = gmres_cycle(p, f, prec, adjoint, r, rn, cycle_tol, m, o.max_iter, x, cnt, s);
-        if (done == 0) return VSIE_E_NOCONV;  // no progress possible (breakdown at the first step)
-        x_zero = false;
+        const std::vector<double> rn = column_norms(p, Rres, na, s);
+        std::vector<int32_t> next, keep_slot;
+        std::vector<double> next_rn, next_tol;
+        for (int sl = 0; sl < na; ++sl) {
+            const int r = active[sl];
+            if (!std::isfinite(rn[sl])) fail(VSIE_E_NAN, "non-finite residual");
+            relres[r] = rn[sl] / bn[r];
+            if (relres[r] <= o.tol) continue;
+            if (cnt.it[r] >= o.max_iter || (prec == VSIE_FP32 && cnt.outer[r] >= o.max_outer)) {
+                status = VSIE_E_NOCONV;
+                continue;
+            }
+            double t = o.tol * bn[r] / rn[sl];
+            if (prec == VSIE_FP32) t = std::max(t, o.inner_tol);
+            next.push_back(r);
+            keep_slot.push_back(sl);
+            next_rn.push_back(rn[sl]);
+            next_tol.push_back(t);
+        }
+        if (next.empty()) break;
+        double2 *cyc_res = Rres;
+        if (static_cast<int>(next.size()) != na) {  // compact the residual block
+            to_device(act, keep_slot, s);
+            bblas_gather(n, static_cast<int>(next.size()), act, Rres, n, Xa, s);
+            cyc_res = Xa;
+        }
+        for (int r : next) cnt.outer[r]++;
+        const int done = gmres_cycle(p, f, prec, adjoint, R, next, cyc_res, next_rn, next_tol, m,
+                                     o.max_iter, x, ldx, cnt, s);
+        for (int r : next) xzero[r] = 0;
+        if (done == 0) {  // breakdown at the first step for every rhs: no progress possible
+            status = VSIE_E_NOCONV;
+            break;
+        }
+        active = next;
     }
+    return status;
 }
 
 }  // namespace
@@ -568,6 +680,23 @@ vsie_status vsie_assemble(const vsie_geometry *geom, const double *vrho, const d
         m.mass = p->alloc<double>(m.n);
         m.sp = p->alloc<double>(m.n * n_freq);
         m.diag = p->alloc<double2>(m.n * n_freq);
+        // cell -> adjacent faces, for the density gradient through interface weights
+        {
+            std::vector<int32_t> off(g.n_vol + 1, 0), idx;
+            for (int64_t q = 0; q < g.n_srf; ++q) {
+                off[g.scell_in[q] + 1]++;
+                if (g.scell_out[q] >= 0) off[g.scell_out[q] + 1]++;
+            }
+            for (int64_t e = 0; e < g.n_vol; ++e) off[e + 1] += off[e];
+            idx.resize(off[g.n_vol]);
+            std::vector<int32_t> fill(off.begin(), off.end() - 1);
+            for (int64_t q = 0; q < g.n_srf; ++q) {
+                idx[fill[g.scell_in[q]]++] = static_cast<int32_t>(q);
+                if (g.scell_out[q] >= 0) idx[fill[g.scell_out[q]]++] = static_cast<int32_t>(q);
+            }
+            if (g.n_vol > 0) p->cf_off = p->upload(off.data(), g.n_vol + 1);
+            if (!idx.empty()) p->cf_idx = p->upload(idx.data(), static_cast<int64_t>(idx.size()));
+        }
         p->k0.assign(k0, k0 + n_freq);
         p->d_k0 = p->upload(k0, n_freq);
         launch_weights(m, p->d_k0, n_freq, s);
@@ -645,22 +774,21 @@ vsie_status vsie_solve(vsie_problem *p, int32_t f, vsie_precision prec, int32_t 
                     o.inner_tol > 0 && o.inner_tol < 1 && o.max_outer >= 1,
                 "invalid solver options");
         hipStream_t s = as_stream(stream);
-        double worst = 0.0;
-        SolveCounters total;
-        for (int64_t c = 0; c < nrhs; ++c) {
-            SolveCounters cnt;
-            double rr = 0.0;
-            const vsie_status one = solve_one(p, f, prec, adjoint != 0,
-                                              reinterpret_cast<const double2 *>(b) + c * ldb,
-                                              reinterpret_cast<double2 *>(x) + c * ldx, o, cnt, rr, s);
-            if (one != VSIE_OK) result = one;
-            worst = std::max(worst, rr);
-            total.iterations += cnt.iterations;
-            total.mv64 += cnt.mv64;
-            total.mv32 += cnt.mv32;
-            total.outer = std::max(total.outer, cnt.outer);
+        const int R = static_cast<int>(nrhs);
+        SolveCounters cnt(R);
+        std::vector<double> rr;
+        result = solve_batch(p, f, prec, adjoint != 0, R, reinterpret_cast<const double2 *>(b), ldb,
+                             reinterpret_cast<double2 *>(x), ldx, o, cnt, rr, s);
+        VSIE_HIP(hipStreamSynchronize(s));
+        vsie_solve_info total{0, 0, 0, 0, 0.0};
+        for (int r = 0; r < R; ++r) {
+            total.iterations += cnt.it[r];
+            total.matvecs_fp64 += cnt.mv64[r];
+            total.matvecs_fp32 += cnt.mv32[r];
+            total.outer_steps = std::max(total.outer_steps, cnt.outer[r]);
+            total.rel_residual = std::max(total.rel_residual, rr[r]);
         }
-        if (info) *info = vsie_solve_info{total.iterations, total.outer, total.mv64, total.mv32, worst};
+        if (info) *info = total;
         if (result == VSIE_E_NOCONV) g_last_error = "GMRES did not reach the tolerance";
     });
     return st != VSIE_OK ? st : result;
@@ -753,6 +881,62 @@ vsie_status vsie_source_sums(vsie_problem *p, int32_t f, int64_t n_t, const doub
         launch_pairs(J, s, &p->prof);
         launch_sums_reduce(n, R, nc, part, reinterpret_cast<double2 *>(z), ldz,
                            reinterpret_cast<double2 *>(Z), ldZ, s);
+    });
+}
+
+vsie_status vsie_plane_wave_at(vsie_problem *p, int32_t f, int64_t ndir, const double *dirs,
+                               int64_t n_t, const double *tx, const double *ty, const double *tz,
+                               double *out, int64_t ldo, void *stream) {
+    return guarded([&] {
+        check_problem(p, f);
+        require(ndir >= 1 && dirs != nullptr, "need at least one direction");
+        require(n_t >= 1 && tx && ty && tz, "need target points");
+        check_vec(out, ldo, n_t, "out");
+        for (int64_t d = 0; d < ndir; ++d) {
+            const double *u = dirs + 3 * d;
+            const double nn = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            require(std::fabs(nn - 1.0) <= 1e-12, "direction not of unit length");
+            launch_plane_wave_at(n_t, tx, ty, tz, p->k0[f], u[0], u[1], u[2],
+                                 reinterpret_cast<double2 *>(out) + d * ldo, as_stream(stream));
+        }
+    });
+}
+
+vsie_status vsie_adjoint_rhs(vsie_problem *p, int32_t f, int64_t nrhs, const double *zR, int64_t ldz,
+                             const double *ZR, int64_t ldZ, double *out, int64_t ldo, void *stream) {
+    return guarded([&] {
+        check_problem(p, f);
+        require(nrhs >= 1, "nrhs must be >= 1");
+        check_vec(zR, ldz, p->m.n, "zR");
+        check_vec(ZR, ldZ, p->m.n, "ZR");
+        check_vec(out, ldo, p->m.n, "out");
+        launch_adjoint_rhs(p->m, f, static_cast<int>(nrhs), reinterpret_cast<const double2 *>(zR), ldz,
+                           reinterpret_cast<const double2 *>(ZR), ldZ, reinterpret_cast<double2 *>(out),
+                           ldo, as_stream(stream));
+    });
+}
+
+vsie_status vsie_param_gradient(vsie_problem *p, int32_t f, int64_t nrhs, const double *P, int64_t ldp,
+                                const double *lam, int64_t ldl, const double *z, int64_t ldz,
+                                const double *Z, int64_t ldZ, const double *zR, int64_t ldzr,
+                                const double *ZR, int64_t ldZr, double *grad_c, double *grad_rho,
+                                void *stream) {
+    return guarded([&] {
+        check_problem(p, f);
+        require(nrhs >= 1, "nrhs must be >= 1");
+        const int64_t n = p->m.n;
+        check_vec(P, ldp, n, "p");
+        check_vec(lam, ldl, n, "lam");
+        check_vec(z, ldz, n, "z");
+        check_vec(Z, ldZ, n, "Z");
+        check_vec(zR, ldzr, n, "zR");
+        check_vec(ZR, ldZr, n, "ZR");
+        require(p->m.n_vol == 0 || (grad_c && grad_rho), "gradient outputs must not be NULL");
+        double *work = static_cast<double *>(p->grad_work.get(sizeof(double) * 5 * static_cast<size_t>(n)));
+        auto c2 = [](const double *v) { return reinterpret_cast<const double2 *>(v); };
+        launch_param_gradient(p->m, p->cf_off, p->cf_idx, p->k0[f], static_cast<int>(nrhs), c2(P), ldp,
+                              c2(lam), ldl, c2(z), ldz, c2(Z), ldZ, c2(zR), ldzr, c2(ZR), ldZr, work,
+                              grad_c, grad_rho, as_stream(stream));
     });
 }
 

@@ -123,6 +123,17 @@ void launch_sums_reduce(int64_t n, int nrhs, int n_parts, const double2 *partial
 void launch_plane_wave(int64_t n, const double *px, const double *py, const double *pz, double k,
                        double dx, double dy, double dz, double2 *b, hipStream_t s);
 
+// adjoint-state gradient (gradient.hip)
+void launch_adjoint_rhs(const DeviceMesh &m, int f, int nrhs, const double2 *zR, int64_t ldz,
+                        const double2 *ZR, int64_t ldZ, double2 *out, int64_t ldo, hipStream_t s);
+void launch_param_gradient(const DeviceMesh &m, const int32_t *cf_off, const int32_t *cf_idx,
+                           double k, int nrhs, const double2 *P, int64_t ldp, const double2 *L,
+                           int64_t ldl, const double2 *z, int64_t ldz, const double2 *Z, int64_t ldZ,
+                           const double2 *zR, int64_t ldzr, const double2 *ZR, int64_t ldZr,
+                           double *work, double *grad_c, double *grad_rho, hipStream_t s);
+void launch_plane_wave_at(int64_t n, const double *tx, const double *ty, const double *tz, double k,
+                          double dx, double dy, double dz, double2 *b, hipStream_t s);
+
 // dense vector kernels for the Krylov solver (aux_kernels.hip)
 void blas_dots(int64_t n, int k, const double2 *V, int64_t ldv, const double2 *w,
                double2 *partial, int n_chunks, double2 *h, hipStream_t s);
@@ -139,5 +150,22 @@ void blas_sub(int64_t n, const double2 *b, const double2 *ax, double2 *r, hipStr
 void blas_add(int64_t n, const double2 *d, double2 *x, hipStream_t s);
 void blas_copy(int64_t n, const double2 *a, int64_t lda, double2 *b, int64_t ldb, int ncols,
                hipStream_t s);
+
+// batched Krylov kernels (aux_kernels.hip); basis vector j of rhs r at V + (j R + r) n
+void bblas_dots(int64_t n, int k, int R, int nslots, const int32_t *act, const double2 *V,
+                const double2 *W, double2 *partial, int n_chunks, double2 *h, int hstride,
+                hipStream_t s);
+void bblas_gemv_sub(int64_t n, int k, int R, int nslots, const int32_t *act, const double2 *V,
+                    const double2 *h, int hstride, double2 *W, hipStream_t s);
+void bblas_norm(int64_t n, int nslots, const double2 *W, double *partial, int n_chunks, double *out,
+                hipStream_t s);
+void bblas_scale_into_basis(int64_t n, int kcol, int R, int nslots, const int32_t *act,
+                            const double2 *W, const double *nrm, double2 *V, hipStream_t s);
+void bblas_gather(int64_t n, int nslots, const int32_t *act, const double2 *src, int64_t ld,
+                  double2 *X, hipStream_t s);
+void bblas_update(int64_t n, int R, int nslots, const int32_t *act, const int32_t *kd, const double2 *V,
+                  const double2 *y, int ystride, double2 *x, int64_t ldx, hipStream_t s);
+void bblas_sub(int64_t n, int nslots, const int32_t *act, const double2 *b, int64_t ldb,
+               const double2 *ax, double2 *out, hipStream_t s);
 
 }  // namespace vsie

@@ -1,0 +1,120 @@
+"""Adjoint-state gradient of a receiver misfit on the GPU against finite
+differences of the FP64 oracle's misfit (dense LU solves), and the adjoint
+pieces against the oracle's own sums."""
+import copy
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def V():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2607_06429_amd as V
+    return V
+
+
+def medium(N, seed_shift=0):
+    mesh = W.nested_balls(N)
+    mat = W.materials_piecewise(mesh, 1.0, 1.0, 1.2, 1.5, 2.0, 0.8)
+    mat.vol_c = mat.vol_c * W.lognormal_voxel_field(mesh.vol_xyz, -1, 1, 32, 0.1, 0)
+    mat.vol_rho = mat.vol_rho * W.lognormal_voxel_field(mesh.vol_xyz, -1, 1, 32, 0.1, 1)
+    return mesh, mat
+
+
+def gpu_gradient(V, mesh, mat, k0, dirs, rec, data, prec=0, tol=1e-13):
+    import torch
+    from paper_2607_06429_amd.autograd import receiver_pressure
+    P = V.Problem.from_mesh(mesh, mat, [k0])
+    c = torch.tensor(mat.vol_c, device="cuda", requires_grad=True)
+    rho = torch.tensor(mat.vol_rho, device="cuda", requires_grad=True)
+    pr = receiver_pressure(P, mesh.n_vol, c, rho, dirs, rec, prec=prec, tol=tol)
+    dt = torch.as_tensor(np.ascontiguousarray(data.T), device="cuda")
+    loss = 0.5 * (pr - dt).abs().pow(2).sum()
+    loss.backward()
+    return float(loss), c.grad.cpu().numpy(), rho.grad.cpu().numpy(), pr.detach().cpu().numpy().T
+
+
+def fd(mesh, mat, k0, dirs, rec, data, which, cells, eps=1e-5):
+    out = []
+    for j in cells:
+        vals = []
+        for sgn in (1, -1):
+            m2 = copy.deepcopy(mat)
+            arr = m2.vol_c if which == "c" else m2.vol_rho
+            h = eps * arr[j]
+            arr[j] += sgn * h
+            vals.append(O.receiver_misfit(mesh, m2, k0, dirs, rec, data))
+        out.append((vals[0] - vals[1]) / (2 * h))
+    return np.array(out)
+
+
+def test_receiver_pressures_match_oracle(V):
+    mesh, mat = medium(7)
+    k0, dirs, rec = 4.0, W.fibonacci_sphere(2), W.fibonacci_sphere(12, 2.0)
+    ref = O.receiver_pressures(mesh, mat, k0, dirs, rec)
+    data = np.zeros_like(ref)
+    _, _, _, pr = gpu_gradient(V, mesh, mat, k0, dirs, rec, data)
+    assert O.rel_error(pr, ref) < 1e-11
+
+
+def test_gradient_all_parameters_tiny_mesh(V):
+    """Every cell's c and rho on a 6^3 staircase mesh (T terms, both
+    interfaces): the full oracle finite-difference gradient."""
+    mesh, mat = medium(6)
+    k0, dirs, rec = 3.0, W.fibonacci_sphere(2), W.fibonacci_sphere(10, 2.0)
+    data = 0.5 * W.seeded_complex((10, 2), seed=41)
+    say("tiny gradient: cells", mesh.n_vol, "faces", mesh.n_srf)
+    J, gc, gr, _ = gpu_gradient(V, mesh, mat, k0, dirs, rec, data)
+    J0 = O.receiver_misfit(mesh, mat, k0, dirs, rec, data)
+    assert abs(J - J0) <= 1e-11 * abs(J0)
+    cells = np.arange(mesh.n_vol)
+    fc = fd(mesh, mat, k0, dirs, rec, data, "c", cells)
+    fr = fd(mesh, mat, k0, dirs, rec, data, "rho", cells)
+    ec, er = O.rel_error(gc, fc), O.rel_error(gr, fr)
+    say("  rel err grad c %.2e  grad rho %.2e" % (ec, er))
+    assert ec < 1e-6 and er < 1e-6
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gradient_random_cells(V, prec):
+    """16 seeded cells of a 10^3 mesh; FP64 and FP32+refinement solves."""
+    mesh, mat = medium(10)
+    k0, dirs, rec = 5.0, W.fibonacci_sphere(3), W.fibonacci_sphere(24, 2.5)
+    data = 0.3 * W.seeded_complex((24, 3), seed=42)
+    J, gc, gr, _ = gpu_gradient(V, mesh, mat, k0, dirs, rec, data, prec=prec, tol=1e-12)
+    cells = np.random.default_rng(43).choice(mesh.n_vol, 16, replace=False)
+    fc = fd(mesh, mat, k0, dirs, rec, data, "c", cells)
+    fr = fd(mesh, mat, k0, dirs, rec, data, "rho", cells)
+    ec, er = O.rel_error(gc[cells], fc), O.rel_error(gr[cells], fr)
+    say("  prec %d rel err grad c %.2e  grad rho %.2e" % (prec, ec, er))
+    assert ec < 1e-6 and er < 1e-6
+
+
+def test_adjoint_rhs_and_source_sums_match_oracle(V):
+    import torch
+    mesh, mat = medium(8)
+    k0, rec = 4.0, W.fibonacci_sphere(16, 2.0)
+    d = O.discretise(mesh, mat, k0)
+    P = V.Problem.from_mesh(mesh, mat, [k0])
+    rho = W.seeded_complex((16, 2), seed=44)
+    zR, ZR = P.source_sums(torch.as_tensor(np.ascontiguousarray(rho.T), device="cuda"), targets=rec)
+    rhs = P.adjoint_rhs(zR, ZR).cpu().numpy().T
+    # oracle: (E^H rho)_j = sum_r conj(E_rj) rho_r with E_rj = -kappa(x_r, j), by columns of the
+    # off-diagonal operator at the receivers
+    E = -np.stack([O.offdiag_apply(d, np.eye(d.n)[:, j], targets=rec, exclude_self=False)
+                   for j in range(d.n)], axis=1)
+    ref = E.conj().T @ rho
+    assert O.rel_error(rhs, ref) < 1e-12

@@ -255,3 +255,61 @@ def test_c1_solve_against_oracle_solution(V, c1, prec):
     say("  info", info, "err vs oracle %.3e" % err)
     assert info["status"] == V.VSIE_OK
     assert err <= TOL_SOLVE
+
+
+# ---------------------------------------------------------------------------
+# the other full-size workloads: sampled rows of the operator
+
+def _sampled_rows(V, name, R, n_rows, f=0, seed=51):
+    mesh, mat, k0s, dirs, _ = W.config_problem(name)
+    say(name, "sampled rows: n", mesh.n, "R", R, "k0", k0s[f])
+    d = O.discretise(mesh, mat, k0s[f])
+    P = V.Problem.from_mesh(mesh, mat, k0s)
+    x = W.seeded_complex((d.n, R), seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    rows = np.unique(np.concatenate([rng.choice(d.n, n_rows, replace=False),
+                                     [0, d.n_vol - 1, d.n_vol, d.n - 1]]))
+    ref = O.matvec(d, x, rows=rows)
+    out = {}
+    for nm, pr in (("fp64", V.VSIE_FP64), ("fp32", V.VSIE_FP32)):
+        y = host(P.matvec(dev(x).contiguous(), f=f, prec=pr)).reshape(d.n, R)[rows]
+        out[nm] = O.rel_error(y, ref)
+    say("  rel err fp64 %.3e fp32 %.3e" % (out["fp64"], out["fp32"]))
+    P.close()
+    return out
+
+
+def test_c2_matvec_sampled_rows(V):
+    e = _sampled_rows(V, "c2", 4, 256)
+    assert e["fp64"] <= TOL64 and e["fp32"] <= TOL32
+
+
+@pytest.mark.parametrize("f", [0, 7])
+def test_c4_matvec_sampled_rows(V, f):
+    """Cube + ellipsoid on a 100^3 grid, n = 1,076,336, at k0 = 40 and 26."""
+    e = _sampled_rows(V, "c4", 2, 192, f=f)
+    assert e["fp64"] <= TOL64 and e["fp32"] <= TOL32
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batched_solve_mixed_columns(V, prec):
+    """One batch holding two plane waves, a zero column and a random column,
+    with a nonzero initial guess in one column and short restarts."""
+    import torch
+    say("batched solve, mixed columns", prec)
+    mesh, mat, k0 = case("lognormal")
+    d = O.discretise(mesh, mat, k0)
+    b = np.concatenate([O.plane_wave(d.pts, k0, W.fibonacci_sphere(2)),
+                        np.zeros((d.n, 1)), W.seeded_complex((d.n, 1), seed=61)], axis=1)
+    ref = O.solve_lu(d, b)
+    P = V.Problem.from_mesh(mesh, mat, [k0])
+    x0 = np.zeros_like(b)
+    x0[:, 1] = 0.9 * ref[:, 1] + 0.01
+    pr = V.VSIE_FP64 if prec == "fp64" else V.VSIE_FP32
+    x, info = P.solve(dev(b).contiguous(), prec=pr, tol=1e-11, restart=12, x0=dev(x0).contiguous())
+    say("  info", info)
+    got = host(x)
+    assert info["status"] == V.VSIE_OK
+    assert np.all(got[:, 2] == 0)
+    for c in (0, 1, 3):
+        assert O.rel_error(got[:, c], ref[:, c]) <= TOL_SOLVE

@@ -374,16 +374,17 @@ __global__ void bdots_final_kernel(int k, int nslots, const double2 *__restrict_
     h[sl * hstride + j] = acc;
 }
 
-// W[sl] -= sum_{j<k} V(j, act[sl]) h[sl * hstride + j]
+// W[sl] -= sum_{j<k_sl} V(j, act[sl]) h[sl * hstride + j], k_sl = min(k, kd[sl]) (kd may be null)
 __global__ void bgemv_sub_kernel(int64_t n, int k, int R, const int32_t *__restrict__ act,
-                                 const double2 *__restrict__ V, const double2 *__restrict__ h,
-                                 int hstride, double2 *__restrict__ W) {
+                                 const int32_t *__restrict__ kd, const double2 *__restrict__ V,
+                                 const double2 *__restrict__ h, int hstride, double2 *__restrict__ W) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
     const int sl = blockIdx.y;
     if (i >= n) return;
     const int r = act[sl];
+    const int kk = kd ? (kd[sl] < k ? kd[sl] : k) : k;
     double2 acc = make_double2(0.0, 0.0);
-    for (int j = 0; j < k; ++j) {
+    for (int j = 0; j < kk; ++j) {
         const double2 a = V[(static_cast<int64_t>(j) * R + r) * n + i], b = h[sl * hstride + j];
         acc.x += a.x * b.x - a.y * b.y;
         acc.y += a.x * b.y + a.y * b.x;
@@ -633,10 +634,10 @@ void bblas_dots(int64_t n, int k, int R, int nslots, const int32_t *act, const d
 }
 
 void bblas_gemv_sub(int64_t n, int k, int R, int nslots, const int32_t *act, const double2 *V,
-                    const double2 *h, int hstride, double2 *W, hipStream_t s) {
+                    const double2 *h, int hstride, double2 *W, hipStream_t s, const int32_t *kd) {
     if (k == 0 || nslots == 0) return;
-    hipLaunchKernelGGL(bgemv_sub_kernel, dim3(blocks_for(n), nslots), dim3(kT), 0, s, n, k, R, act, V,
-                       h, hstride, W);
+    hipLaunchKernelGGL(bgemv_sub_kernel, dim3(blocks_for(n), nslots), dim3(kT), 0, s, n, k, R, act, kd,
+                       V, h, hstride, W);
     LAUNCH_CHECK();
 }
 

@@ -22,6 +22,8 @@
 // Phase: the angle k r is carried in revolutions t = r k/(2 pi), reduced as
 // t - rint(t) in FP64 on both precision paths, so the argument of sin/cos
 // never exceeds half a turn.
+#include <type_traits>
+
 #include "vsie_internal.h"
 
 namespace vsie {
@@ -30,65 +32,68 @@ namespace {
 enum Mode { FWD_G = 0, FWD_F = 1, ADJ_F = 2, SUMS = 3 };
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kPi = 3.1415926535897932384626433832795;
 
 // ---------------------------------------------------------------------------
-// FP64 sin and cos of 2 pi f for |f| <= 1/2.
-// f = q/4 + g with q = rint(4 f) and |g| <= 1/8 (exact by Sterbenz' lemma);
-// x = 2 pi g lies in [-pi/4, pi/4] where the Maclaurin series of sin (through
-// x^15) and cos (through x^16) have truncation errors below 7e-17; the
-// quadrant q rotates the pair by q quarter turns.
-__device__ __forceinline__ void sincos_turns_f64(double f, double &sn, double &cs) {
-    const double q = rint(4.0 * f);
-    const double g = fma(q, -0.25, f);
-    const double x = g * kTwoPi;
+// FP64 sin and cos of pi g for |g| <= 1/2 (x = pi g in [-pi/2, pi/2]):
+// Maclaurin series of sin through x^21 and of cos through x^22; the first
+// omitted terms, (pi/2)^23/23! and (pi/2)^24/24!, are below 2e-18.
+__device__ __forceinline__ void sincos_halfturn_f64(double g, double &sn, double &cs) {
+    const double x = g * kPi;
     const double z = x * x;
-    double ps = -1.0 / 1307674368000.0;               // -1/15!
-    ps = fma(ps, z, 1.0 / 6227020800.0);              //  1/13!
-    ps = fma(ps, z, -1.0 / 39916800.0);               // -1/11!
-    ps = fma(ps, z, 1.0 / 362880.0);                  //  1/9!
-    ps = fma(ps, z, -1.0 / 5040.0);                   // -1/7!
-    ps = fma(ps, z, 1.0 / 120.0);                     //  1/5!
-    ps = fma(ps, z, -1.0 / 6.0);                      // -1/3!
-    const double s = fma(ps * z, x, x);
-    double pc = 1.0 / 20922789888000.0;               //  1/16!
-    pc = fma(pc, z, -1.0 / 87178291200.0);            // -1/14!
-    pc = fma(pc, z, 1.0 / 479001600.0);               //  1/12!
-    pc = fma(pc, z, -1.0 / 3628800.0);                // -1/10!
-    pc = fma(pc, z, 1.0 / 40320.0);                   //  1/8!
-    pc = fma(pc, z, -1.0 / 720.0);                    // -1/6!
-    pc = fma(pc, z, 1.0 / 24.0);                      //  1/4!
-    pc = fma(pc, z, -0.5);                            // -1/2!
-    const double c = fma(pc, z, 1.0);
-    const int qi = static_cast<int>(q) & 3;
-    const double a = (qi & 1) ? c : s;
-    const double b = (qi & 1) ? s : c;
-    sn = (qi & 2) ? -a : a;
-    cs = ((qi + 1) & 2) ? -b : b;
+    double ps = -1.0 / 51090942171709440000.0;        // -1/21!
+    ps = fma(ps, z, 1.0 / 121645100408832000.0);       //  1/19!
+    ps = fma(ps, z, -1.0 / 355687428096000.0);         // -1/17!
+    ps = fma(ps, z, 1.0 / 1307674368000.0);            //  1/15!
+    ps = fma(ps, z, -1.0 / 6227020800.0);              // -1/13!
+    ps = fma(ps, z, 1.0 / 39916800.0);                 //  1/11!
+    ps = fma(ps, z, -1.0 / 362880.0);                  // -1/9!
+    ps = fma(ps, z, 1.0 / 5040.0);                     //  1/7!
+    ps = fma(ps, z, -1.0 / 120.0);                     // -1/5!
+    ps = fma(ps, z, 1.0 / 6.0);                        //  1/3!
+    sn = fma(-ps * z, x, x);
+    double pc = 1.0 / 1124000727777607680000.0;        //  1/22!
+    pc = fma(pc, z, -1.0 / 2432902008176640000.0);     // -1/20!
+    pc = fma(pc, z, 1.0 / 6402373705728000.0);         //  1/18!
+    pc = fma(pc, z, -1.0 / 20922789888000.0);          // -1/16!
+    pc = fma(pc, z, 1.0 / 87178291200.0);              //  1/14!
+    pc = fma(pc, z, -1.0 / 479001600.0);               // -1/12!
+    pc = fma(pc, z, 1.0 / 3628800.0);                  //  1/10!
+    pc = fma(pc, z, -1.0 / 40320.0);                   // -1/8!
+    pc = fma(pc, z, 1.0 / 720.0);                      //  1/6!
+    pc = fma(pc, z, -1.0 / 24.0);                      // -1/4!
+    pc = fma(pc, z, 0.5);                              //  1/2!
+    cs = fma(-pc, z, 1.0);
 }
 
-// FP64 1/sqrt(x) for x > 0: hardware estimate plus two Newton steps.
-__device__ __forceinline__ double rsq_f64(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    double h = x * y;
-    double e = fma(-h, y, 1.0);
-    y = fma(0.5 * y, e, y);
-    h = x * y;
-    e = fma(-h, y, 1.0);
-    return fma(0.5 * y, e, y);
+// Flip the sign of v when the integer-valued double q is odd.
+__device__ __forceinline__ double flip_if_odd(double v, double q) {
+    const int qi = static_cast<int>(q);
+    return __longlong_as_double(__double_as_longlong(v) ^ (static_cast<long long>(qi & 1) << 63));
 }
 
 // Geometry of one pair in FP64: e = exp(i k r)/r, ir2 = 1/r^2 and k r.
-__device__ __forceinline__ void geom_f64(double dx, double dy, double dz, double k, double kr2pi,
+// The phase is carried in half turns u = k r / pi = q + g with q = rint(u):
+// exp(i pi u) = (-1)^q exp(i pi g), and the sign (-1)^q is folded into 1/r.
+// 1/sqrt(r^2): v_rsq_f64 (max relative error 5e-8 measured) and one Newton
+// step (error below 3e-15).  MASK selects zero for the pair r = 0.
+template <bool MASK>
+__device__ __forceinline__ void geom_f64(double dx, double dy, double dz, double k, double khalf,
                                          double &er, double &ei, double &ir2, double &kr) {
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-    const double ir = (r2 > 0.0) ? rsq_f64(r2) : 0.0;
-    const double r = r2 * ir;
-    const double t = r * kr2pi;
+    double y = __builtin_amdgcn_rsq(r2);
+    const double e = fma(-r2 * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    if (MASK) y = (r2 > 0.0) ? y : 0.0;
+    const double r = r2 * y;
+    const double u = r * khalf;
+    const double q = rint(u);
     double sn, cs;
-    sincos_turns_f64(t - rint(t), sn, cs);
-    er = cs * ir;
-    ei = sn * ir;
-    ir2 = ir * ir;
+    sincos_halfturn_f64(u - q, sn, cs);
+    const double ys = flip_if_odd(y, q);
+    er = cs * ys;
+    ei = sn * ys;
+    ir2 = y * y;
     kr = k * r;
 }
 
@@ -96,18 +101,20 @@ __device__ __forceinline__ void geom_f64(double dx, double dy, double dz, double
 // phase reduction, FP32 amplitude and trigonometric functions.  r is formed
 // from an FP32 reciprocal square root and one FP64 Newton correction, which
 // is accurate to ~1e-14 relative: enough to keep the phase error far below
-// the FP32 rounding of everything else.
+// the FP32 rounding of everything else.  The phase in turns is reduced with
+// v_fract_f64 (exact) before it is rounded to FP32.
+template <bool MASK>
 __device__ __forceinline__ void geom_f32(double dx, double dy, double dz, float k, double kr2pi,
                                          float &er, float &ei, float &ir2, float &kr) {
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
     const float r2f = static_cast<float>(r2);
-    const float yf = (r2 > 0.0) ? __builtin_amdgcn_rsqf(r2f) : 0.0f;
+    float yf = __builtin_amdgcn_rsqf(r2f);
+    if (MASK) yf = (r2 > 0.0) ? yf : 0.0f;
     const float rf = r2f * yf;
     const double rd = static_cast<double>(rf);
     const double e = fma(-rd, rd, r2);
     const double r = fma(e, static_cast<double>(0.5f * yf), rd);
-    const double t = r * kr2pi;
-    const float f = static_cast<float>(t - rint(t));
+    const float f = static_cast<float>(__builtin_amdgcn_fract(r * kr2pi));
     // v_sin_f32 / v_cos_f32 take their argument in turns
     const float sn = __builtin_amdgcn_sinf(f);
     const float cs = __builtin_amdgcn_cosf(f);
@@ -137,9 +144,11 @@ struct PairArgs {
     int64_t ldq;
     int64_t chunk;
     double k;
-    double kr2pi;
+    double kphase;               // k/pi (FP64: half turns) or k/(2 pi) (FP32: turns)
     double2 *__restrict__ out;   // out[c * chunk_stride + (r * ncomp + comp) * n_t + i]
     int64_t chunk_stride;
+    int self_mode;               // which streamed points may coincide with a thread point
+    const int32_t *__restrict__ self_idx;  // canonical indices of the class entries
 };
 
 template <typename AT> struct cplx_t;
@@ -150,23 +159,55 @@ template <> struct cplx_t<float> { using type = float2; };
 // added into the FP64 accumulators.
 constexpr int kSubTile = 128;
 
+// first position in the increasing array a[0..n) holding a value >= v
+__device__ int64_t lower_bound_u(const int32_t *__restrict__ a, int64_t n, int64_t v) {
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 template <int MODE, int R, typename CT, typename AT>
 __global__ __launch_bounds__(kBlock) void pair_sum_kernel(PairArgs<CT, AT> a) {
     using C2 = typename cplx_t<AT>::type;
     constexpr int NC = (MODE == SUMS) ? 4 : 1;   // complex accumulators per right-hand side
     constexpr bool F32 = sizeof(AT) == 4;
+    const int64_t wave0 = static_cast<int64_t>(blockIdx.x) * kBlock +
+                          64 * __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (i >= a.n_t) return;
+    if (wave0 >= a.n_t) return;  // whole wave outside (a partial wave clamps below)
+    const bool active = i < a.n_t;
+    const int64_t ii = active ? i : a.n_t - 1;
     const int c = blockIdx.y;
     const int64_t j0 = static_cast<int64_t>(c) * a.chunk;
     const int64_t j1 = (j0 + a.chunk < a.n_s) ? j0 + a.chunk : a.n_s;
 
-    const double xi = a.tx[i], yi = a.ty[i], zi = a.tz[i];
+    // Streamed indices [sr0, sr1) that may coincide with one of this wave's
+    // thread points; only there is the pair r = 0 masked.
+    const int64_t wlast = (wave0 + 63 < a.n_t) ? wave0 + 63 : a.n_t - 1;
+    int64_t sr0 = 0, sr1 = 0;
+    switch (a.self_mode) {
+        case SELF_NONE: sr0 = 0; sr1 = a.n_s; break;   // unknown targets: mask everything
+        case SELF_IDENT: sr0 = wave0; sr1 = wlast + 1; break;
+        case SELF_STREAM_IDX:
+            sr0 = lower_bound_u(a.self_idx, a.n_s, wave0);
+            sr1 = lower_bound_u(a.self_idx, a.n_s, wlast + 1);
+            break;
+        case SELF_THREAD_IDX: sr0 = a.self_idx[wave0]; sr1 = a.self_idx[wlast] + 1; break;
+        default: break;
+    }
+    const int64_t m0 = sr0 > j0 ? sr0 : j0;
+    const int64_t m1 = sr1 < j1 ? sr1 : j1;
+
+    const double xi = a.tx[ii], yi = a.ty[ii], zi = a.tz[ii];
     AT tv0 = 0, tv1 = 0, tv2 = 0;
     if constexpr (MODE == ADJ_F) {
-        tv0 = a.tvx[i];
-        tv1 = a.tvy[i];
-        tv2 = a.tvz[i];
+        tv0 = a.tvx[ii];
+        tv1 = a.tvy[ii];
+        tv2 = a.tvz[ii];
     }
     const C2 *__restrict__ q = static_cast<const C2 *>(a.q);
 
@@ -175,72 +216,84 @@ __global__ __launch_bounds__(kBlock) void pair_sum_kernel(PairArgs<CT, AT> a) {
     for (int r = 0; r < R * NC; ++r) accr[r] = acci[r] = 0.0;
 
     const AT k = static_cast<AT>(a.k);
-    for (int64_t jt = j0; jt < j1; jt += (F32 ? kSubTile : (j1 - j0))) {
-        const int64_t je = F32 ? ((jt + kSubTile < j1) ? jt + kSubTile : j1) : j1;
-        AT sr[R * NC], si[R * NC];
+    // Sum over streamed points [ja, jb), in FP32 sub-tiles on the FP32 path.
+    auto run = [&](int64_t ja, int64_t jb, auto mask_tag) {
+        constexpr bool MASK = decltype(mask_tag)::value;
+        for (int64_t jt = ja; jt < jb; jt += (F32 ? kSubTile : (jb - ja))) {
+            const int64_t je = F32 ? ((jt + kSubTile < jb) ? jt + kSubTile : jb) : jb;
+            AT sr[R * NC], si[R * NC];
 #pragma unroll
-        for (int r = 0; r < R * NC; ++r) sr[r] = si[r] = 0;
+            for (int r = 0; r < R * NC; ++r) sr[r] = si[r] = 0;
 #pragma unroll 2
-        for (int64_t j = jt; j < je; ++j) {
-            const double dx = xi - static_cast<double>(a.sx[j]);
-            const double dy = yi - static_cast<double>(a.sy[j]);
-            const double dz = zi - static_cast<double>(a.sz[j]);
-            AT er, ei, ir2, kr;
-            if constexpr (F32) geom_f32(dx, dy, dz, k, a.kr2pi, er, ei, ir2, kr);
-            else geom_f64(dx, dy, dz, a.k, a.kr2pi, er, ei, ir2, kr);
-            if constexpr (MODE == FWD_G) {
+            for (int64_t j = jt; j < je; ++j) {
+                const double dx = xi - static_cast<double>(a.sx[j]);
+                const double dy = yi - static_cast<double>(a.sy[j]);
+                const double dz = zi - static_cast<double>(a.sz[j]);
+                AT er, ei, ir2, kr;
+                if constexpr (F32) geom_f32<MASK>(dx, dy, dz, k, a.kphase, er, ei, ir2, kr);
+                else geom_f64<MASK>(dx, dy, dz, a.k, a.kphase, er, ei, ir2, kr);
+                if constexpr (MODE == FWD_G) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const C2 u = q[r * a.ldq + j];
-                    sr[r] = fma(er, u.x, fma(-ei, u.y, sr[r]));
-                    si[r] = fma(er, u.y, fma(ei, u.x, si[r]));
-                }
-            } else if constexpr (MODE == FWD_F || MODE == ADJ_F) {
-                AT dv;
-                if constexpr (MODE == FWD_F) {
-                    dv = static_cast<AT>(fma(dx, static_cast<double>(a.svx[j]),
-                                             fma(dy, static_cast<double>(a.svy[j]),
-                                                 dz * static_cast<double>(a.svz[j]))));
-                } else {
-                    dv = -static_cast<AT>(fma(dx, static_cast<double>(tv0),
-                                              fma(dy, static_cast<double>(tv1),
-                                                  dz * static_cast<double>(tv2))));
-                }
-                const AT qq = dv * ir2;
-                // e (i k r - 1) q
-                const AT cr = qq * fma(-ei, kr, -er);
-                const AT ci = qq * fma(er, kr, -ei);
+                    for (int r = 0; r < R; ++r) {
+                        const C2 u = q[r * a.ldq + j];
+                        sr[r] = fma(er, u.x, fma(-ei, u.y, sr[r]));
+                        si[r] = fma(er, u.y, fma(ei, u.x, si[r]));
+                    }
+                } else if constexpr (MODE == FWD_F || MODE == ADJ_F) {
+                    AT dv;
+                    if constexpr (MODE == FWD_F) {
+                        dv = static_cast<AT>(fma(dx, static_cast<double>(a.svx[j]),
+                                                 fma(dy, static_cast<double>(a.svy[j]),
+                                                     dz * static_cast<double>(a.svz[j]))));
+                    } else {
+                        dv = -static_cast<AT>(fma(dx, static_cast<double>(tv0),
+                                                  fma(dy, static_cast<double>(tv1),
+                                                      dz * static_cast<double>(tv2))));
+                    }
+                    const AT qq = dv * ir2;
+                    // e (i k r - 1) q
+                    const AT cr = qq * fma(-ei, kr, -er);
+                    const AT ci = qq * fma(er, kr, -ei);
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const C2 u = q[r * a.ldq + j];
-                    sr[r] = fma(cr, u.x, fma(-ci, u.y, sr[r]));
-                    si[r] = fma(cr, u.y, fma(ci, u.x, si[r]));
-                }
-            } else {  // SUMS
-                const AT cr = ir2 * fma(-ei, kr, -er);
-                const AT ci = ir2 * fma(er, kr, -ei);
-                const AT md[3] = {static_cast<AT>(-dx), static_cast<AT>(-dy), static_cast<AT>(-dz)};
+                    for (int r = 0; r < R; ++r) {
+                        const C2 u = q[r * a.ldq + j];
+                        sr[r] = fma(cr, u.x, fma(-ci, u.y, sr[r]));
+                        si[r] = fma(cr, u.y, fma(ci, u.x, si[r]));
+                    }
+                } else {  // SUMS
+                    const AT cr = ir2 * fma(-ei, kr, -er);
+                    const AT ci = ir2 * fma(er, kr, -ei);
+                    const AT md[3] = {static_cast<AT>(-dx), static_cast<AT>(-dy), static_cast<AT>(-dz)};
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const C2 u = q[r * a.ldq + j];
-                    sr[4 * r] = fma(er, u.x, fma(-ei, u.y, sr[4 * r]));
-                    si[4 * r] = fma(er, u.y, fma(ei, u.x, si[4 * r]));
-                    const AT wr = fma(cr, u.x, -ci * u.y);
-                    const AT wi = fma(cr, u.y, ci * u.x);
+                    for (int r = 0; r < R; ++r) {
+                        const C2 u = q[r * a.ldq + j];
+                        sr[4 * r] = fma(er, u.x, fma(-ei, u.y, sr[4 * r]));
+                        si[4 * r] = fma(er, u.y, fma(ei, u.x, si[4 * r]));
+                        const AT wr = fma(cr, u.x, -ci * u.y);
+                        const AT wi = fma(cr, u.y, ci * u.x);
 #pragma unroll
-                    for (int ax = 0; ax < 3; ++ax) {
-                        sr[4 * r + 1 + ax] = fma(md[ax], wr, sr[4 * r + 1 + ax]);
-                        si[4 * r + 1 + ax] = fma(md[ax], wi, si[4 * r + 1 + ax]);
+                        for (int ax = 0; ax < 3; ++ax) {
+                            sr[4 * r + 1 + ax] = fma(md[ax], wr, sr[4 * r + 1 + ax]);
+                            si[4 * r + 1 + ax] = fma(md[ax], wi, si[4 * r + 1 + ax]);
+                        }
                     }
                 }
             }
-        }
 #pragma unroll
-        for (int r = 0; r < R * NC; ++r) {
-            accr[r] += static_cast<double>(sr[r]);
-            acci[r] += static_cast<double>(si[r]);
+            for (int r = 0; r < R * NC; ++r) {
+                accr[r] += static_cast<double>(sr[r]);
+                acci[r] += static_cast<double>(si[r]);
+            }
         }
+    };
+    if (m0 >= m1) {
+        run(j0, j1, std::false_type{});
+    } else {
+        run(j0, m0, std::false_type{});
+        run(m0, m1, std::true_type{});
+        run(m1, j1, std::false_type{});
     }
+    if (!active) return;
     double2 *__restrict__ o = a.out + c * a.chunk_stride + i;
 #pragma unroll
     for (int r = 0; r < R * NC; ++r) o[r * a.n_t] = make_double2(accr[r], acci[r]);
@@ -266,7 +319,7 @@ void launch_mode(const PairArgs<CT, AT> &a, int nrhs, int n_chunks, hipStream_t 
 template <int MODE>
 static void run_pairs(const PairJob &J, hipStream_t s) {
     constexpr int NC = (MODE == SUMS) ? 4 : 1;
-    const double kr2pi = J.k / kTwoPi;
+    const double kphase = (J.prec == VSIE_FP64) ? J.k / kPi : J.k / kTwoPi;
     int r0 = 0;
     while (r0 < J.nrhs) {
         const int left = J.nrhs - r0;
@@ -276,13 +329,15 @@ static void run_pairs(const PairJob &J, hipStream_t s) {
             PairArgs<double, double> a{J.n_t, J.tx, J.ty, J.tz, J.tv[0], J.tv[1], J.tv[2],
                                        J.n_s, J.sx, J.sy, J.sz, J.sv[0], J.sv[1], J.sv[2],
                                        static_cast<const double2 *>(J.charge) + r0 * J.ldq, J.ldq,
-                                       J.chunk, J.k, kr2pi, out, J.chunk_stride};
+                                       J.chunk, J.k, kphase, out, J.chunk_stride, J.self_mode,
+                                       J.self_idx};
             launch_mode<MODE>(a, blk, J.n_chunks, s);
         } else {
             PairArgs<double, float> a{J.n_t, J.tx, J.ty, J.tz, J.tvf[0], J.tvf[1], J.tvf[2],
                                       J.n_s, J.sx, J.sy, J.sz, J.svf[0], J.svf[1], J.svf[2],
                                       static_cast<const float2 *>(J.charge) + r0 * J.ldq, J.ldq,
-                                      J.chunk, J.k, kr2pi, out, J.chunk_stride};
+                                      J.chunk, J.k, kphase, out, J.chunk_stride, J.self_mode,
+                                      J.self_idx};
             launch_mode<MODE>(a, blk, J.n_chunks, s);
         }
         r0 += blk;

@@ -79,7 +79,7 @@ struct vsie_problem {
     std::vector<void *> owned;  // permanent device allocations
     Scratch partial, chargeG, chargeF, chargeAll, sums_part, grad_work;
     // Krylov workspace
-    Scratch V, w, r, ax, h1, h2, nrm, dpart, npart, yv, act, act2, live, kd, xa, axa, rres;
+    Scratch V, V2, w, r, ax, h1, h2, tc, nrm, dpart, npart, yv, act, act2, live, kd, kc, xa, axa, rres;
     PairProfiler prof;
 
     template <typename T>
@@ -114,8 +114,9 @@ struct vsie_problem {
         }
         for (hipEvent_t e : prof.pool) (void)hipEventDestroy(e);
         for (void *p : owned) (void)hipFree(p);
-        for (Scratch *s : {&partial, &chargeG, &chargeF, &chargeAll, &sums_part, &grad_work, &V, &w, &r, &ax,
-                           &h1, &h2, &nrm, &dpart, &npart, &yv, &act, &act2, &live, &kd, &xa, &axa, &rres})
+        for (Scratch *s : {&partial, &chargeG, &chargeF, &chargeAll, &sums_part, &grad_work, &V, &V2, &w, &r, &ax,
+                           &h1, &h2, &tc, &nrm, &dpart, &npart, &yv, &act, &act2, &live, &kd, &kc, &xa, &axa,
+                           &rres})
             s->release();
     }
 };
@@ -287,14 +288,15 @@ void apply_forward_block(vsie_problem *p, int f, vsie_precision prec, int nrhs, 
     if (ncG > 0) {
         PairJob J{PAIR_FWD_G, prec, n, p->m.px, p->m.py, p->m.pz, {}, {}, p->G.count,
                   p->G.x, p->G.y, p->G.z, {}, {}, qG, p->G.count, nrhs, chG, ncG, k,
-                  part, static_cast<int64_t>(nrhs) * n};
+                  part, static_cast<int64_t>(nrhs) * n, SELF_STREAM_IDX, p->G.idx};
         launch_pairs(J, s, &p->prof);
     }
     if (ncF > 0) {
         PairJob J{PAIR_FWD_F, prec, n, p->m.px, p->m.py, p->m.pz, {}, {}, p->F.count,
                   p->F.x, p->F.y, p->F.z, {p->F.vx, p->F.vy, p->F.vz}, {p->F.vxf, p->F.vyf, p->F.vzf},
                   qF, p->F.count, nrhs, chF, ncF, k,
-                  part + static_cast<int64_t>(ncG) * nrhs * n, static_cast<int64_t>(nrhs) * n};
+                  part + static_cast<int64_t>(ncG) * nrhs * n, static_cast<int64_t>(nrhs) * n,
+                  SELF_STREAM_IDX, p->F.idx};
         launch_pairs(J, s, &p->prof);
     }
     launch_reduce_partials(n, nrhs, n_parts, part, p->m.diag + static_cast<int64_t>(f) * n, false, x,
@@ -332,7 +334,7 @@ void apply_adjoint_block(vsie_problem *p, int f, vsie_precision prec, int nrhs, 
     if (ncG > 0) {
         PairJob J{PAIR_FWD_G, prec, p->G.count, p->G.x, p->G.y, p->G.z, {}, {}, n,
                   p->m.px, p->m.py, p->m.pz, {}, {}, q, n, nrhs, chG, ncG, k, part,
-                  static_cast<int64_t>(nrhs) * p->G.count};
+                  static_cast<int64_t>(nrhs) * p->G.count, SELF_THREAD_IDX, p->G.idx};
         launch_pairs(J, s, &p->prof);
         launch_scatter_conj(p->G.count, p->G.idx, spf, nrhs, ncG, part, y, ldy, s);
     }
@@ -340,7 +342,7 @@ void apply_adjoint_block(vsie_problem *p, int f, vsie_precision prec, int nrhs, 
         PairJob J{PAIR_ADJ_F, prec, p->F.count, p->F.x, p->F.y, p->F.z,
                   {p->F.vx, p->F.vy, p->F.vz}, {p->F.vxf, p->F.vyf, p->F.vzf}, n,
                   p->m.px, p->m.py, p->m.pz, {}, {}, q, n, nrhs, chF, ncF, k, part,
-                  static_cast<int64_t>(nrhs) * p->F.count};
+                  static_cast<int64_t>(nrhs) * p->F.count, SELF_THREAD_IDX, p->F.idx};
         launch_pairs(J, s, &p->prof);
         launch_scatter_conj(p->F.count, p->F.idx, nullptr, nrhs, ncF, part, y, ldy, s);
     }
@@ -391,7 +393,7 @@ void to_device(T *d, const std::vector<T> &h, hipStream_t s) {
     VSIE_HIP(hipStreamSynchronize(s));  // h may change right after
 }
 
-constexpr int64_t kKrylovBytes = int64_t(48) << 30;  // cap on the Krylov basis (48 GiB)
+constexpr int64_t kKrylovBytes = int64_t(48) << 30;  // cap on the two Krylov bases (48 GiB)
 
 int norm_chunks(int64_t n) { return static_cast<int>(std::min<int64_t>(256, std::max<int64_t>(1, n / 2048))); }
 
@@ -407,35 +409,127 @@ std::vector<double> column_norms(vsie_problem *p, const double2 *W, int nslots, 
     return h;
 }
 
+using cd = std::complex<double>;
+
+// The Krylov space of a finished cycle, kept to deflate later cycles (GCRO):
+// the cycle's Arnoldi relation A V_k = V_{k+1} Hbar with Hbar = Q R by the
+// cycle's own Givens rotations gives C = V_{k+1} Q (orthonormal) and
+// U = V_k R^{-1} with A U = C.  Later cycles solve with (I - C C^H) A, start
+// from the correction U C^H r, and correct their result by -U B y.
+struct RecycleRhs {
+    int k = 0;
+    std::vector<cd> cs, sn;  // rotations 0..k-1
+    std::vector<cd> Rm;      // k x k upper triangle, column-major
+};
+struct Recycle {
+    const double2 *V = nullptr;  // basis buffer of the recycled cycle (layout of gmres_cycle)
+    std::vector<RecycleRhs> rhs;  // indexed by right-hand side
+};
+
+// t <- G_{k-1} ... G_0 t for t of length k + 1 (G_j = [[conj c, conj s], [-s, c]] on rows j, j+1)
+void rot_fwd(const RecycleRhs &q, std::vector<cd> &t) {
+    for (int j = 0; j < q.k; ++j) {
+        const cd a = t[j], b = t[j + 1];
+        t[j] = std::conj(q.cs[j]) * a + std::conj(q.sn[j]) * b;
+        t[j + 1] = -q.sn[j] * a + q.cs[j] * b;
+    }
+}
+// v <- G_0^H ... G_{k-1}^H v
+void rot_bwd(const RecycleRhs &q, std::vector<cd> &v) {
+    for (int j = q.k - 1; j >= 0; --j) {
+        const cd a = v[j], b = v[j + 1];
+        v[j] = q.cs[j] * a - std::conj(q.sn[j]) * b;
+        v[j + 1] = q.sn[j] * a + std::conj(q.cs[j]) * b;
+    }
+}
+// R y = c
+std::vector<cd> r_solve(const RecycleRhs &q, const std::vector<cd> &c) {
+    std::vector<cd> y(q.k);
+    for (int i = q.k - 1; i >= 0; --i) {
+        cd acc = c[i];
+        for (int j = i + 1; j < q.k; ++j) acc -= q.Rm[static_cast<size_t>(j) * q.k + i] * y[j];
+        y[i] = acc / q.Rm[static_cast<size_t>(i) * q.k + i];
+    }
+    return y;
+}
+
 // One GMRES cycle for the right-hand sides rhs[0..ns) (slot order), with
-// residual block Rres (ns x n, norms rn) and per-slot stopping tolerances;
-// adds the corrections to x.  Returns the number of iterations performed.
+// residual block Rres (ns x n, norms rn; overwritten when `use` projects it)
+// and per-slot stopping tolerances; adds the corrections to x.  The basis is
+// written to Vb.  `save` receives this cycle's space for later deflation;
+// `use` deflates this cycle with an earlier one.  Returns the iterations done.
 int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R,
-                const std::vector<int32_t> &rhs, const double2 *Rres, const std::vector<double> &rn,
+                const std::vector<int32_t> &rhs, double2 *Rres, const std::vector<double> &rn,
                 const std::vector<double> &ctol, int m, int iter_cap, double2 *x, int64_t ldx,
-                SolveCounters &cnt, hipStream_t s) {
-    using cd = std::complex<double>;
+                SolveCounters &cnt, hipStream_t s, double2 *Vb, Recycle *save, const Recycle *use) {
     const int64_t n = p->m.n;
     const int ns = static_cast<int>(rhs.size());
-    const int hs = m + 2;  // stride of per-slot Hessenberg columns
-    double2 *V = static_cast<double2 *>(p->V.get(sizeof(double2) * static_cast<size_t>(n) * R * (m + 1)));
+    const int hs = m + 2;  // stride of per-slot coefficient vectors
+    int kmax = 0;          // largest recycled dimension in this batch
+    if (use)
+        for (int r : rhs) kmax = std::max(kmax, use->rhs[r].k);
+    const int cs_ = std::max(hs, kmax + 2);
+    double2 *V = Vb;
     double2 *W = static_cast<double2 *>(p->w.get(sizeof(double2) * static_cast<size_t>(n) * ns));
     double2 *X = static_cast<double2 *>(p->ax.get(sizeof(double2) * static_cast<size_t>(n) * ns));
     double2 *h1 = static_cast<double2 *>(p->h1.get(sizeof(double2) * static_cast<size_t>(hs) * ns));
     double2 *h2 = static_cast<double2 *>(p->h2.get(sizeof(double2) * static_cast<size_t>(hs) * ns));
+    double2 *tc = static_cast<double2 *>(p->tc.get(sizeof(double2) * static_cast<size_t>(cs_) * ns));
     const int nch = norm_chunks(n);
     double2 *dpart = static_cast<double2 *>(
-        p->dpart.get(sizeof(double2) * static_cast<size_t>(nch) * (m + 1) * ns));
+        p->dpart.get(sizeof(double2) * static_cast<size_t>(nch) * std::max(m + 1, kmax + 1) * ns));
     double *npart = static_cast<double *>(p->npart.get(sizeof(double) * nch * ns));
     double *nrm = static_cast<double *>(p->nrm.get(sizeof(double) * ns));
     int32_t *act = static_cast<int32_t *>(p->act.get(sizeof(int32_t) * ns));
     int32_t *live_d = static_cast<int32_t *>(p->live.get(sizeof(int32_t) * ns));
-    double2 *yv = static_cast<double2 *>(p->yv.get(sizeof(double2) * static_cast<size_t>(m + 1) * ns));
+    int32_t *kc_d = static_cast<int32_t *>(p->kc.get(sizeof(int32_t) * ns));
+    // coefficient uploads use strides up to cs_ (>= max(m + 1, kmax + 1))
+    double2 *yv = static_cast<double2 *>(p->yv.get(sizeof(double2) * static_cast<size_t>(cs_) * ns));
     int32_t *kd_d = static_cast<int32_t *>(p->kd.get(sizeof(int32_t) * ns));
 
-    // v0 = r / |r|
     to_device(act, rhs, s);
-    to_device(nrm, rn, s);
+    std::vector<double> beta0(rn);
+    std::vector<std::vector<cd>> Bc;  // per slot: C^H A v_j, column j at [j * kmax]
+    std::vector<double2> hcoef;
+    std::vector<int32_t> kcnt(ns, 0);
+    if (use && kmax > 0) {
+        // project the residuals: x += U C^H r, r -= C C^H r
+        for (int sl = 0; sl < ns; ++sl) {
+            const int kr = use->rhs[rhs[sl]].k;
+            kcnt[sl] = kr > 0 ? kr + 1 : 0;
+        }
+        to_device(kc_d, kcnt, s);
+        bblas_dots(n, kmax + 1, R, ns, act, use->V, Rres, dpart, nch, tc, cs_, s);
+        std::vector<double2> th;
+        to_host(th, tc, static_cast<size_t>(cs_) * ns, s);
+        std::vector<double2> sv(static_cast<size_t>(cs_) * ns, make_double2(0, 0)), uv(sv);
+        std::vector<int32_t> ku(ns, 0);
+        for (int sl = 0; sl < ns; ++sl) {
+            const RecycleRhs &q = use->rhs[rhs[sl]];
+            if (q.k == 0) continue;
+            std::vector<cd> t(q.k + 1);
+            for (int j = 0; j <= q.k; ++j) t[j] = cd(th[sl * cs_ + j].x, th[sl * cs_ + j].y);
+            rot_fwd(q, t);
+            std::vector<cd> c(t.begin(), t.begin() + q.k);
+            const std::vector<cd> y0 = r_solve(q, c);
+            std::vector<cd> v(q.k + 1, 0.0);
+            for (int j = 0; j < q.k; ++j) v[j] = c[j];
+            rot_bwd(q, v);
+            for (int j = 0; j <= q.k; ++j) sv[sl * cs_ + j] = make_double2(v[j].real(), v[j].imag());
+            for (int j = 0; j < q.k; ++j) uv[sl * cs_ + j] = make_double2(y0[j].real(), y0[j].imag());
+            ku[sl] = q.k;
+        }
+        to_device(tc, sv, s);
+        bblas_gemv_sub(n, kmax + 1, R, ns, act, use->V, tc, cs_, Rres, s, kc_d);
+        to_device(yv, uv, s);
+        to_device(kd_d, ku, s);
+        bblas_update(n, R, ns, act, kd_d, use->V, yv, cs_, x, ldx, s);
+        const std::vector<double> b2 = column_norms(p, Rres, ns, s);
+        beta0 = b2;
+        Bc.assign(ns, std::vector<cd>(static_cast<size_t>(kmax) * m, 0.0));
+    }
+    // v0 = r / |r| (a zero projected residual gives a zero vector and stops at once)
+    to_device(nrm, beta0, s);
     bblas_scale_into_basis(n, 0, R, ns, act, Rres, nrm, V, s);
 
     std::vector<std::vector<cd>> H(ns, std::vector<cd>(static_cast<size_t>(m + 1) * m, 0.0));
@@ -443,16 +537,20 @@ int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
         g(ns, std::vector<cd>(m + 1, 0.0));
     std::vector<int> kdone(ns, 0);
     std::vector<char> done(ns, 0);
-    for (int sl = 0; sl < ns; ++sl) g[sl][0] = rn[sl];
+    for (int sl = 0; sl < ns; ++sl) {
+        g[sl][0] = beta0[sl];
+        if (beta0[sl] <= ctol[sl] * rn[sl]) done[sl] = 1;  // the projection already solved it
+    }
     std::vector<double2> hb1, hb2;
     std::vector<double> hbeta;
     int total = 0;
     for (int k = 0; k < m; ++k) {
-        std::vector<int32_t> live_rhs, live_slot;
+        std::vector<int32_t> live_rhs, live_slot, live_kc;
         for (int sl = 0; sl < ns; ++sl)
             if (!done[sl] && cnt.it[rhs[sl]] < iter_cap) {
                 live_rhs.push_back(rhs[sl]);
                 live_slot.push_back(sl);
+                live_kc.push_back(kcnt[sl]);
             }
         const int nl = static_cast<int>(live_rhs.size());
         if (nl == 0) break;
@@ -461,10 +559,36 @@ int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
         bblas_gather(n, nl, live_d, V + static_cast<int64_t>(k) * R * n, n, X, s);
         apply_op(p, f, prec, adjoint, nl, X, n, W, n, s);
         for (int r : live_rhs) (prec == VSIE_FP64 ? cnt.mv64 : cnt.mv32)[r]++;
-        bblas_dots(n, k + 1, R, nl, live_d, V, W, dpart, nch, h1, hs, s);
-        bblas_gemv_sub(n, k + 1, R, nl, live_d, V, h1, hs, W, s);
-        bblas_dots(n, k + 1, R, nl, live_d, V, W, dpart, nch, h2, hs, s);
-        bblas_gemv_sub(n, k + 1, R, nl, live_d, V, h2, hs, W, s);
+        if (use && kmax > 0) to_device(kc_d, live_kc, s);
+        for (int pass = 0; pass < 2; ++pass) {
+            double2 *h = pass == 0 ? h1 : h2;
+            if (use && kmax > 0) {
+                // deflation: W -= C (C^H W), with C^H W = first k entries of G (V1^H W)
+                bblas_dots(n, kmax + 1, R, nl, live_d, use->V, W, dpart, nch, tc, cs_, s);
+                std::vector<double2> th;
+                to_host(th, tc, static_cast<size_t>(cs_) * nl, s);
+                hcoef.assign(static_cast<size_t>(cs_) * nl, make_double2(0, 0));
+                for (int l = 0; l < nl; ++l) {
+                    const int sl = live_slot[l];
+                    const RecycleRhs &q = use->rhs[live_rhs[l]];
+                    if (q.k == 0) continue;
+                    std::vector<cd> t(q.k + 1);
+                    for (int j = 0; j <= q.k; ++j) t[j] = cd(th[l * cs_ + j].x, th[l * cs_ + j].y);
+                    rot_fwd(q, t);
+                    std::vector<cd> v(q.k + 1, 0.0);
+                    for (int j = 0; j < q.k; ++j) {
+                        v[j] = t[j];
+                        Bc[sl][static_cast<size_t>(k) * kmax + j] += t[j];
+                    }
+                    rot_bwd(q, v);
+                    for (int j = 0; j <= q.k; ++j) hcoef[l * cs_ + j] = make_double2(v[j].real(), v[j].imag());
+                }
+                to_device(tc, hcoef, s);
+                bblas_gemv_sub(n, kmax + 1, R, nl, live_d, use->V, tc, cs_, W, s, kc_d);
+            }
+            bblas_dots(n, k + 1, R, nl, live_d, V, W, dpart, nch, h, hs, s);
+            bblas_gemv_sub(n, k + 1, R, nl, live_d, V, h, hs, W, s);
+        }
         bblas_norm(n, nl, W, npart, nch, nrm, s);
         bblas_scale_into_basis(n, k + 1, R, nl, live_d, W, nrm, V, s);
         hb1.resize(static_cast<size_t>(hs) * nl);
@@ -506,9 +630,11 @@ int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
             if (std::abs(g[sl][k + 1]) <= ctol[sl] * rn[sl] || beta == 0.0) done[sl] = 1;
         }
     }
-    // x += V y with H y = g (back substitution per slot)
-    std::vector<double2> yh(static_cast<size_t>(m + 1) * ns, make_double2(0.0, 0.0));
+    // x += V y with H y = g (back substitution per slot), then x -= U (B y)
+    std::vector<double2> yh(static_cast<size_t>(std::max(m + 1, kmax + 1)) * ns, make_double2(0.0, 0.0));
+    const int ys = std::max(m + 1, kmax + 1);
     std::vector<int32_t> kdh(ns);
+    std::vector<std::vector<cd>> ys_all(ns);
     for (int sl = 0; sl < ns; ++sl) {
         const int kk = kdone[sl];
         kdh[sl] = kk;
@@ -519,11 +645,43 @@ int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
             for (int j = i + 1; j < kk; ++j) acc -= Hat(i, j) * y[j];
             y[i] = acc / Hat(i, i);
         }
-        for (int i = 0; i < kk; ++i) yh[static_cast<size_t>(sl) * (m + 1) + i] = make_double2(y[i].real(), y[i].imag());
+        for (int i = 0; i < kk; ++i) yh[static_cast<size_t>(sl) * ys + i] = make_double2(y[i].real(), y[i].imag());
+        ys_all[sl] = y;
     }
     to_device(yv, yh, s);
     to_device(kd_d, kdh, s);
-    bblas_update(n, R, ns, act, kd_d, V, yv, m + 1, x, ldx, s);
+    bblas_update(n, R, ns, act, kd_d, V, yv, ys, x, ldx, s);
+    if (use && kmax > 0) {
+        std::vector<double2> uh(static_cast<size_t>(ys) * ns, make_double2(0.0, 0.0));
+        std::vector<int32_t> ku(ns, 0);
+        for (int sl = 0; sl < ns; ++sl) {
+            const RecycleRhs &q = use->rhs[rhs[sl]];
+            if (q.k == 0 || kdone[sl] == 0) continue;
+            std::vector<cd> by(q.k, 0.0);
+            for (int j = 0; j < kdone[sl]; ++j)
+                for (int i = 0; i < q.k; ++i) by[i] += Bc[sl][static_cast<size_t>(j) * kmax + i] * ys_all[sl][j];
+            const std::vector<cd> u = r_solve(q, by);
+            for (int i = 0; i < q.k; ++i) uh[static_cast<size_t>(sl) * ys + i] = make_double2(-u[i].real(), -u[i].imag());
+            ku[sl] = q.k;
+        }
+        to_device(yv, uh, s);
+        to_device(kd_d, ku, s);
+        bblas_update(n, R, ns, act, kd_d, use->V, yv, ys, x, ldx, s);
+    }
+    if (save) {
+        save->V = V;
+        save->rhs.assign(R, RecycleRhs{});
+        for (int sl = 0; sl < ns; ++sl) {
+            RecycleRhs &q = save->rhs[rhs[sl]];
+            q.k = kdone[sl];
+            q.cs.assign(cs[sl].begin(), cs[sl].begin() + q.k);
+            q.sn.assign(sn[sl].begin(), sn[sl].begin() + q.k);
+            q.Rm.assign(static_cast<size_t>(q.k) * q.k, 0.0);
+            for (int j = 0; j < q.k; ++j)
+                for (int i = 0; i <= j; ++i) q.Rm[static_cast<size_t>(j) * q.k + i] = H[sl][static_cast<size_t>(j) * (m + 1) + i];
+        }
+    }
+    VSIE_HIP(hipStreamSynchronize(s));
     return total;
 }
 
@@ -539,7 +697,10 @@ vsie_status solve_batch(vsie_problem *p, int f, vsie_precision prec, bool adjoin
     // restart length: as asked, but the basis of all R right-hand sides must fit kKrylovBytes
     const int64_t col_bytes = static_cast<int64_t>(sizeof(double2)) * n * R;
     const int m = static_cast<int>(std::max<int64_t>(
-        1, std::min<int64_t>(std::max(1, o.restart), kKrylovBytes / col_bytes - 1)));
+        1, std::min<int64_t>(std::max(1, o.restart), kKrylovBytes / 2 / col_bytes - 1)));
+    double2 *V1 = static_cast<double2 *>(p->V.get(static_cast<size_t>(col_bytes) * (m + 1)));
+    Recycle first;            // space of the first cycle, deflates every later cycle
+    bool have_first = false;
     relres.assign(R, 0.0);
     std::vector<int32_t> all(R);
     for (int r = 0; r < R; ++r) all[r] = r;
@@ -603,8 +764,16 @@ vsie_status solve_batch(vsie_problem *p, int f, vsie_precision prec, bool adjoin
             cyc_res = Xa;
         }
         for (int r : next) cnt.outer[r]++;
-        const int done = gmres_cycle(p, f, prec, adjoint, R, next, cyc_res, next_rn, next_tol, m,
-                                     o.max_iter, x, ldx, cnt, s);
+        int done;
+        if (!have_first) {
+            done = gmres_cycle(p, f, prec, adjoint, R, next, cyc_res, next_rn, next_tol, m, o.max_iter,
+                               x, ldx, cnt, s, V1, &first, nullptr);
+            have_first = true;
+        } else {
+            double2 *V2 = static_cast<double2 *>(p->V2.get(static_cast<size_t>(col_bytes) * (m + 1)));
+            done = gmres_cycle(p, f, prec, adjoint, R, next, cyc_res, next_rn, next_tol, m, o.max_iter,
+                               x, ldx, cnt, s, V2, nullptr, &first);
+        }
         for (int r : next) xzero[r] = 0;
         if (done == 0) {  // breakdown at the first step for every rhs: no progress possible
             status = VSIE_E_NOCONV;
@@ -877,7 +1046,8 @@ vsie_status vsie_source_sums(vsie_problem *p, int32_t f, int64_t n_t, const doub
             p->sums_part.get(sizeof(double2) * static_cast<size_t>(nc) * R * 4 * n));
         PairJob J{PAIR_SUMS, VSIE_FP64, n, p->m.px, p->m.py, p->m.pz, {}, {}, n_t,
                   colloc ? p->m.px : tx, colloc ? p->m.py : ty, colloc ? p->m.pz : tz, {}, {}, q, n_t, R,
-                  ch, nc, p->k0[f], part, static_cast<int64_t>(R) * 4 * n};
+                  ch, nc, p->k0[f], part, static_cast<int64_t>(R) * 4 * n,
+                  colloc ? SELF_IDENT : SELF_NONE, nullptr};
         launch_pairs(J, s, &p->prof);
         launch_sums_reduce(n, R, nc, part, reinterpret_cast<double2 *>(z), ldz,
                            reinterpret_cast<double2 *>(Z), ldZ, s);

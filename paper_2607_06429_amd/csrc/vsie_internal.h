@@ -68,6 +68,16 @@ struct SourceSet {
 // (chunk, right-hand side, component, thread point):
 //   out[c * chunk_stride + (r * ncomp + comp) * n_t + i],  ncomp = 4 for SUMS, else 1.
 enum PairMode { PAIR_FWD_G = 0, PAIR_FWD_F = 1, PAIR_ADJ_F = 2, PAIR_SUMS = 3 };
+// Which streamed points can coincide with a thread point (the r = 0 pair that
+// contributes zero):
+//   SELF_NONE        unknown (arbitrary targets): every pair is checked
+//   SELF_IDENT       thread and streamed points are the same list
+//   SELF_STREAM_IDX  thread points are the collocation points in canonical
+//                    order; streamed point j is canonical point self_idx[j]
+//                    (self_idx increasing)
+//   SELF_THREAD_IDX  streamed points are the collocation points; thread point
+//                    t is canonical point self_idx[t] (self_idx increasing)
+enum SelfMode { SELF_NONE = 0, SELF_IDENT = 1, SELF_STREAM_IDX = 2, SELF_THREAD_IDX = 3 };
 struct PairJob {
     int mode;
     vsie_precision prec;
@@ -87,6 +97,8 @@ struct PairJob {
     double k;
     double2 *out;
     int64_t chunk_stride;
+    int self_mode = SELF_NONE;
+    const int32_t *self_idx = nullptr;
 };
 // Optional timing of pair launches (one event pair per launch).
 struct PairProfiler {
@@ -156,7 +168,8 @@ void bblas_dots(int64_t n, int k, int R, int nslots, const int32_t *act, const d
                 const double2 *W, double2 *partial, int n_chunks, double2 *h, int hstride,
                 hipStream_t s);
 void bblas_gemv_sub(int64_t n, int k, int R, int nslots, const int32_t *act, const double2 *V,
-                    const double2 *h, int hstride, double2 *W, hipStream_t s);
+                    const double2 *h, int hstride, double2 *W, hipStream_t s,
+                    const int32_t *kd = nullptr);
 void bblas_norm(int64_t n, int nslots, const double2 *W, double *partial, int n_chunks, double *out,
                 hipStream_t s);
 void bblas_scale_into_basis(int64_t n, int kcol, int R, int nslots, const int32_t *act,

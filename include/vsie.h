@@ -210,6 +210,19 @@ vsie_status vsie_param_gradient(vsie_problem *p, int32_t f, int64_t nrhs, const 
                                 const double *ZR, int64_t ldZr, double *grad_c, double *grad_rho,
                                 void *stream);
 
+/* Assembled FP32 operator (the dense block system of section 2.3.4 written
+ * once to memory).  Fills `dense`, caller-owned DEVICE memory of ld * n
+ * complex64 values (interleaved float re, im; column-major, ld >= n), with
+ * the off-diagonal entries A_ij of frequency f, computed with the FP64 pair
+ * terms and rounded to FP32 (diagonal entries 0).  Until vsie_release_dense
+ * or vsie_set_materials, every VSIE_FP32 product at frequency f (vsie_matvec,
+ * vsie_matvec_adjoint and the inner solves of vsie_solve) multiplies by this
+ * matrix with a complex GEMM (rocBLAS, matrix cores): FP32 partial products
+ * over chunks of 8192 columns, added in FP64 with the FP64 diagonal.  The
+ * memory must stay valid while in use; n and ld must be below 2^31. */
+vsie_status vsie_assemble_dense(vsie_problem *p, int32_t f, void *dense, int64_t ld, void *stream);
+vsie_status vsie_release_dense(vsie_problem *p, int32_t f);
+
 /* Kernel timing.  vsie_profile(p, 1) clears the counters and starts recording
  * a pair of HIP events around every pair-kernel launch made for p (on the
  * stream of the call that launches it); vsie_profile(p, 0) stops recording.

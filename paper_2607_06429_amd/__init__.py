@@ -21,7 +21,8 @@ __all__ = [
     "VSIE_OK", "VSIE_FP64", "VSIE_FP32", "VsieError", "Problem", "lib", "library_path",
     "vsie_assemble", "vsie_set_materials", "vsie_matvec", "vsie_matvec_adjoint", "vsie_solve",
     "vsie_plane_wave", "vsie_field", "vsie_source_sums", "vsie_plane_wave_at", "vsie_adjoint_rhs",
-    "vsie_param_gradient", "vsie_profile", "vsie_profile_read", "vsie_destroy", "vsie_last_error",
+    "vsie_param_gradient", "vsie_assemble_dense", "vsie_release_dense", "vsie_profile",
+    "vsie_profile_read", "vsie_destroy", "vsie_last_error",
     "vsie_size",
 ]
 
@@ -91,6 +92,8 @@ def _load():
     L.vsie_plane_wave_at.argtypes = [_P, _I32, _I64, _P, _I64, _P, _P, _P, _P, _I64, _P]
     L.vsie_adjoint_rhs.argtypes = [_P, _I32, _I64, _P, _I64, _P, _I64, _P, _I64, _P]
     L.vsie_param_gradient.argtypes = [_P, _I32, _I64] + [_P, _I64] * 6 + [_P, _P, _P]
+    L.vsie_assemble_dense.argtypes = [_P, _I32, _P, _I64, _P]
+    L.vsie_release_dense.argtypes = [_P, _I32]
     L.vsie_profile.argtypes = [_P, _I32]
     L.vsie_profile_read.argtypes = [_P, _I32, ctypes.POINTER(KernelStats)]
     L.vsie_destroy.argtypes = [_P]
@@ -99,7 +102,7 @@ def _load():
     for name in ("vsie_assemble", "vsie_set_materials", "vsie_matvec", "vsie_matvec_adjoint",
                  "vsie_solve", "vsie_plane_wave", "vsie_field", "vsie_source_sums",
                  "vsie_profile", "vsie_profile_read", "vsie_plane_wave_at", "vsie_adjoint_rhs",
-                 "vsie_param_gradient"):
+                 "vsie_param_gradient", "vsie_assemble_dense", "vsie_release_dense"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -109,7 +112,8 @@ lib = _load()
 EXPORTED = ("vsie_assemble", "vsie_set_materials", "vsie_size", "vsie_matvec",
             "vsie_matvec_adjoint", "vsie_solve", "vsie_plane_wave", "vsie_field",
             "vsie_source_sums", "vsie_plane_wave_at", "vsie_adjoint_rhs", "vsie_param_gradient",
-            "vsie_profile", "vsie_profile_read", "vsie_destroy", "vsie_last_error")
+            "vsie_assemble_dense", "vsie_release_dense", "vsie_profile", "vsie_profile_read",
+            "vsie_destroy", "vsie_last_error")
 
 # pair-kernel kinds reported by vsie_profile_read: 2 * mode + precision
 KIND_NAMES = {0: "fwd_single_layer_fp64", 1: "fwd_single_layer_fp32", 2: "fwd_double_layers_fp64",
@@ -318,6 +322,20 @@ def vsie_param_gradient(h, f, P, lam, z, Z, zR, ZR, grad_c, grad_rho, stream=Non
     _check(lib.vsie_param_gradient(h, f, R, *args, _dptr(grad_c), _dptr(grad_rho), _stream(stream)))
 
 
+def vsie_assemble_dense(h, f, dense, ld, stream=None):
+    """dense: CUDA tensor of at least ld * n complex64 values (any shape)."""
+    import torch
+    if dense.dtype != torch.complex64 or not dense.is_cuda or not dense.is_contiguous():
+        raise ValueError("expected a contiguous complex64 CUDA tensor")
+    if dense.numel() < ld * vsie_size(h):
+        raise ValueError("dense buffer too small")
+    _check(lib.vsie_assemble_dense(h, f, _P(dense.data_ptr()), ld, _stream(stream)))
+
+
+def vsie_release_dense(h, f):
+    _check(lib.vsie_release_dense(h, f))
+
+
 def vsie_profile(h, enable):
     _check(lib.vsie_profile(h, 1 if enable else 0))
 
@@ -450,6 +468,18 @@ class Problem:
                             Z.reshape(3 * R, self.n).contiguous(), zR.contiguous(),
                             ZR.reshape(3 * R, self.n).contiguous(), gc, gr)
         return gc, gr
+
+    def assemble_dense(self, f=0, ld=None):
+        """Allocate and fill the FP32 operator of frequency f; returns the tensor
+        (keep it alive while FP32 products should use it)."""
+        import torch
+        ld = self.n if ld is None else ld
+        A = torch.empty((self.n, ld), dtype=torch.complex64, device="cuda")
+        vsie_assemble_dense(self.handle, f, A, ld)
+        return A
+
+    def release_dense(self, f=0):
+        vsie_release_dense(self.handle, f)
 
     def profile(self, enable=True):
         vsie_profile(self.handle, enable)

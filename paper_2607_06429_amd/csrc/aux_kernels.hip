@@ -148,6 +148,27 @@ __global__ void reduce_kernel(int64_t n_t, int nrhs, int n_parts, const double2 
     }
 }
 
+// y[i + r ldy] = d_i x[i + r ldx] + sum_c part[(c nrhs + r) n_t + i] with FP32 partials
+// added in FP64 (d_i = diag[i], conjugated when conj_diag).
+__global__ void reduce32_kernel(int64_t n_t, int nrhs, int n_parts, const float2 *__restrict__ part,
+                                const double2 *__restrict__ diag, bool conj_diag,
+                                const double2 *__restrict__ x, int64_t ldx, double2 *__restrict__ y,
+                                int64_t ldy) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+    if (i >= n_t) return;
+    double2 d = diag[i];
+    if (conj_diag) d.y = -d.y;
+    for (int r = 0; r < nrhs; ++r) {
+        double2 acc = cmul(d, x[i + r * ldx]);
+        for (int c = 0; c < n_parts; ++c) {
+            const float2 p = part[(static_cast<int64_t>(c) * nrhs + r) * n_t + i];
+            acc.x += static_cast<double>(p.x);
+            acc.y += static_cast<double>(p.y);
+        }
+        y[i + r * ldy] = acc;
+    }
+}
+
 // y[idx[jj] + r ldy] += conj(scale_jj * sum_c partial[(c nrhs + r) count + jj]),
 // scale_jj = -s'[idx[jj]] (single-layer class) or 1.
 __global__ void scatter_conj_kernel(int64_t count, const int32_t *__restrict__ idx,
@@ -514,6 +535,15 @@ void launch_reduce_partials(int64_t n_t, int nrhs, int n_parts, const double2 *p
                             double2 *y, int64_t ldy, double2 *, hipStream_t s) {
     if (n_t == 0) return;
     hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(n_t)), dim3(kT), 0, s, n_t, nrhs, n_parts,
+                       partial, diag, conj_diag, x, ldx, y, ldy);
+    LAUNCH_CHECK();
+}
+
+void launch_reduce32(int64_t n_t, int nrhs, int n_parts, const float2 *partial, const double2 *diag,
+                     bool conj_diag, const double2 *x, int64_t ldx, double2 *y, int64_t ldy,
+                     hipStream_t s) {
+    if (n_t == 0) return;
+    hipLaunchKernelGGL(reduce32_kernel, dim3(blocks_for(n_t)), dim3(kT), 0, s, n_t, nrhs, n_parts,
                        partial, diag, conj_diag, x, ldx, y, ldy);
     LAUNCH_CHECK();
 }

@@ -130,16 +130,16 @@ struct PairArgs {
     const CT *__restrict__ tx;
     const CT *__restrict__ ty;
     const CT *__restrict__ tz;
-    const AT *__restrict__ tvx;  // ADJ_F: v' of the thread points
-    const AT *__restrict__ tvy;
-    const AT *__restrict__ tvz;
+    const double *__restrict__ tvx;  // ADJ_F: v' of the thread points
+    const double *__restrict__ tvy;
+    const double *__restrict__ tvz;
     int64_t n_s;
     const CT *__restrict__ sx;
     const CT *__restrict__ sy;
     const CT *__restrict__ sz;
-    const AT *__restrict__ svx;  // FWD_F: v' of the streamed points
-    const AT *__restrict__ svy;
-    const AT *__restrict__ svz;
+    const double *__restrict__ svx;  // FWD_F: v' of the streamed points
+    const double *__restrict__ svy;
+    const double *__restrict__ svz;
     const void *__restrict__ q;  // charges, complex pairs of AT: q[r * ldq + j]
     int64_t ldq;
     int64_t chunk;
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void pair_sum_kernel(PairArgs<CT, AT> a) {
     const int64_t m1 = sr1 < j1 ? sr1 : j1;
 
     const double xi = a.tx[ii], yi = a.ty[ii], zi = a.tz[ii];
-    AT tv0 = 0, tv1 = 0, tv2 = 0;
+    double tv0 = 0, tv1 = 0, tv2 = 0;
     if constexpr (MODE == ADJ_F) {
         tv0 = a.tvx[ii];
         tv1 = a.tvy[ii];
@@ -241,14 +241,11 @@ __global__ __launch_bounds__(kBlock) void pair_sum_kernel(PairArgs<CT, AT> a) {
                     }
                 } else if constexpr (MODE == FWD_F || MODE == ADJ_F) {
                     AT dv;
+                    // (x_thread - y_streamed) . v' in FP64 (v' kept in FP64 on both paths)
                     if constexpr (MODE == FWD_F) {
-                        dv = static_cast<AT>(fma(dx, static_cast<double>(a.svx[j]),
-                                                 fma(dy, static_cast<double>(a.svy[j]),
-                                                     dz * static_cast<double>(a.svz[j]))));
+                        dv = static_cast<AT>(fma(dx, a.svx[j], fma(dy, a.svy[j], dz * a.svz[j])));
                     } else {
-                        dv = -static_cast<AT>(fma(dx, static_cast<double>(tv0),
-                                                  fma(dy, static_cast<double>(tv1),
-                                                      dz * static_cast<double>(tv2))));
+                        dv = -static_cast<AT>(fma(dx, tv0, fma(dy, tv1, dz * tv2)));
                     }
                     const AT qq = dv * ir2;
                     // e (i k r - 1) q
@@ -313,7 +310,44 @@ void launch_mode(const PairArgs<CT, AT> &a, int nrhs, int n_chunks, hipStream_t 
     VSIE_HIP(hipGetLastError());
 }
 
+// Dense FP32 off-diagonal operator: A[i + j ld] = kappa(x_i, y_j) for the
+// sources j in [j0, j0 + jcount) of this launch, kappa = e (-s'_j + q_ij (i k r - 1)),
+// e = exp(i k r)/r, q_ij = (x_i - y_j).v'_j / r^2, computed with the FP64 pair
+// geometry and rounded once to FP32; the diagonal entries are 0.
+__global__ __launch_bounds__(kBlock) void assemble_kernel(
+    int64_t n, const double *__restrict__ px, const double *__restrict__ py,
+    const double *__restrict__ pz, const double *__restrict__ sp, const double *__restrict__ vpx,
+    const double *__restrict__ vpy, const double *__restrict__ vpz, double k, double khalf,
+    float2 *__restrict__ A, int64_t ld, int64_t chunk) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j0 = static_cast<int64_t>(blockIdx.y) * chunk;
+    const int64_t j1 = (j0 + chunk < n) ? j0 + chunk : n;
+    const double xi = px[i], yi = py[i], zi = pz[i];
+    for (int64_t j = j0; j < j1; ++j) {
+        const double dx = xi - px[j], dy = yi - py[j], dz = zi - pz[j];
+        double er, ei, ir2, kr;
+        geom_f64<true>(dx, dy, dz, k, khalf, er, ei, ir2, kr);
+        const double q = fma(dx, vpx[j], fma(dy, vpy[j], dz * vpz[j])) * ir2;
+        // e * (-s' - q + i k r q)
+        const double br = -sp[j] - q, bi = kr * q;
+        A[i + j * ld] = make_float2(static_cast<float>(er * br - ei * bi),
+                                    static_cast<float>(er * bi + ei * br));
+    }
+}
+
 }  // namespace
+
+void launch_assemble_dense(int64_t n, const double *px, const double *py, const double *pz,
+                           const double *sp, const double *vpx, const double *vpy, const double *vpz,
+                           double k, float2 *A, int64_t ld, hipStream_t s) {
+    if (n == 0) return;
+    const int64_t chunk = 512;
+    dim3 grid(static_cast<unsigned>((n + kBlock - 1) / kBlock), static_cast<unsigned>((n + chunk - 1) / chunk));
+    hipLaunchKernelGGL(assemble_kernel, grid, dim3(kBlock), 0, s, n, px, py, pz, sp, vpx, vpy, vpz, k,
+                       k / kPi, A, ld, chunk);
+    VSIE_HIP(hipGetLastError());
+}
 
 // Splits nrhs into launches of 16, 8, 4, 2, 1 right-hand sides.
 template <int MODE>
@@ -333,8 +367,8 @@ static void run_pairs(const PairJob &J, hipStream_t s) {
                                        J.self_idx};
             launch_mode<MODE>(a, blk, J.n_chunks, s);
         } else {
-            PairArgs<double, float> a{J.n_t, J.tx, J.ty, J.tz, J.tvf[0], J.tvf[1], J.tvf[2],
-                                      J.n_s, J.sx, J.sy, J.sz, J.svf[0], J.svf[1], J.svf[2],
+            PairArgs<double, float> a{J.n_t, J.tx, J.ty, J.tz, J.tv[0], J.tv[1], J.tv[2],
+                                      J.n_s, J.sx, J.sy, J.sz, J.sv[0], J.sv[1], J.sv[2],
                                       static_cast<const float2 *>(J.charge) + r0 * J.ldq, J.ldq,
                                       J.chunk, J.k, kphase, out, J.chunk_stride, J.self_mode,
                                       J.self_idx};

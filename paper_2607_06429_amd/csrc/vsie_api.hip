@@ -8,11 +8,19 @@
 #include <string>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+
 #include "vsie_internal.h"
 
 namespace vsie {
 
 thread_local std::string g_last_error;
+
+void check_blas(rocblas_status st, const char *what) {
+    if (st == rocblas_status_success) return;
+    fail(st == rocblas_status_memory_error ? VSIE_E_NOMEM : VSIE_E_DEVICE,
+         std::string(what) + ": " + rocblas_status_to_string(st));
+}
 
 void fail(vsie_status code, const std::string &msg) { throw Error{code, msg}; }
 
@@ -81,6 +89,14 @@ struct vsie_problem {
     // Krylov workspace
     Scratch V, V2, w, r, ax, h1, h2, tc, nrm, dpart, npart, yv, act, act2, live, kd, kc, xa, axa, rres;
     PairProfiler prof;
+    // dense FP32 off-diagonal operator per frequency (caller-owned memory)
+    struct Dense {
+        float2 *A = nullptr;
+        int64_t ld = 0;
+    };
+    std::vector<Dense> dense;
+    rocblas_handle blas = nullptr;
+    Scratch dense_x, dense_part;
 
     template <typename T>
     T *alloc(int64_t count) {
@@ -98,7 +114,7 @@ struct vsie_problem {
         return d;
     }
     void free_sources(SourceSet &S) {
-        void *ps[] = {S.idx, S.x, S.y, S.z, S.vx, S.vy, S.vz, S.vxf, S.vyf, S.vzf};
+        void *ps[] = {S.idx, S.x, S.y, S.z, S.vx, S.vy, S.vz};
         for (void *q : ps) {
             if (!q) continue;
             auto it = std::find(owned.begin(), owned.end(), q);
@@ -113,6 +129,9 @@ struct vsie_problem {
             (void)hipEventDestroy(r.b);
         }
         for (hipEvent_t e : prof.pool) (void)hipEventDestroy(e);
+        if (blas) (void)rocblas_destroy_handle(blas);
+        dense_x.release();
+        dense_part.release();
         for (void *p : owned) (void)hipFree(p);
         for (Scratch *s : {&partial, &chargeG, &chargeF, &chargeAll, &sums_part, &grad_work, &V, &V2, &w, &r, &ax,
                            &h1, &h2, &tc, &nrm, &dpart, &npart, &yv, &act, &act2, &live, &kd, &kc, &xa, &axa,
@@ -236,21 +255,14 @@ void build_sources(vsie_problem *p) {
         S.z = p->upload(c.data(), S.count);
         if (!with_v) return;
         std::vector<double> va(S.count), vb(S.count), vc(S.count);
-        std::vector<float> fa(S.count), fb(S.count), fc(S.count);
         for (int64_t j = 0; j < S.count; ++j) {
             va[j] = vp[ix[j]];
             vb[j] = vp[n + ix[j]];
             vc[j] = vp[2 * n + ix[j]];
-            fa[j] = static_cast<float>(va[j]);
-            fb[j] = static_cast<float>(vb[j]);
-            fc[j] = static_cast<float>(vc[j]);
         }
         S.vx = p->upload(va.data(), S.count);
         S.vy = p->upload(vb.data(), S.count);
         S.vz = p->upload(vc.data(), S.count);
-        S.vxf = p->upload(fa.data(), S.count);
-        S.vyf = p->upload(fb.data(), S.count);
-        S.vzf = p->upload(fc.data(), S.count);
     };
     fill(p->G, gi, false);
     fill(p->F, fi, true);
@@ -286,14 +298,14 @@ void apply_forward_block(vsie_problem *p, int f, vsie_precision prec, int nrhs, 
     launch_pack_charges(kClassF, prec, p->F, spf, nrhs, x, ldx, false, qF, s);
     const double k = p->k0[f];
     if (ncG > 0) {
-        PairJob J{PAIR_FWD_G, prec, n, p->m.px, p->m.py, p->m.pz, {}, {}, p->G.count,
-                  p->G.x, p->G.y, p->G.z, {}, {}, qG, p->G.count, nrhs, chG, ncG, k,
+        PairJob J{PAIR_FWD_G, prec, n, p->m.px, p->m.py, p->m.pz, {}, p->G.count,
+                  p->G.x, p->G.y, p->G.z, {}, qG, p->G.count, nrhs, chG, ncG, k,
                   part, static_cast<int64_t>(nrhs) * n, SELF_STREAM_IDX, p->G.idx};
         launch_pairs(J, s, &p->prof);
     }
     if (ncF > 0) {
-        PairJob J{PAIR_FWD_F, prec, n, p->m.px, p->m.py, p->m.pz, {}, {}, p->F.count,
-                  p->F.x, p->F.y, p->F.z, {p->F.vx, p->F.vy, p->F.vz}, {p->F.vxf, p->F.vyf, p->F.vzf},
+        PairJob J{PAIR_FWD_F, prec, n, p->m.px, p->m.py, p->m.pz, {}, p->F.count,
+                  p->F.x, p->F.y, p->F.z, {p->F.vx, p->F.vy, p->F.vz},
                   qF, p->F.count, nrhs, chF, ncF, k,
                   part + static_cast<int64_t>(ncG) * nrhs * n, static_cast<int64_t>(nrhs) * n,
                   SELF_STREAM_IDX, p->F.idx};
@@ -332,16 +344,16 @@ void apply_adjoint_block(vsie_problem *p, int f, vsie_precision prec, int nrhs, 
     const size_t need = std::max(static_cast<size_t>(ncG) * p->G.count, static_cast<size_t>(ncF) * p->F.count);
     double2 *part = static_cast<double2 *>(p->partial.get(sizeof(double2) * std::max<size_t>(1, need) * nrhs));
     if (ncG > 0) {
-        PairJob J{PAIR_FWD_G, prec, p->G.count, p->G.x, p->G.y, p->G.z, {}, {}, n,
-                  p->m.px, p->m.py, p->m.pz, {}, {}, q, n, nrhs, chG, ncG, k, part,
+        PairJob J{PAIR_FWD_G, prec, p->G.count, p->G.x, p->G.y, p->G.z, {}, n,
+                  p->m.px, p->m.py, p->m.pz, {}, q, n, nrhs, chG, ncG, k, part,
                   static_cast<int64_t>(nrhs) * p->G.count, SELF_THREAD_IDX, p->G.idx};
         launch_pairs(J, s, &p->prof);
         launch_scatter_conj(p->G.count, p->G.idx, spf, nrhs, ncG, part, y, ldy, s);
     }
     if (ncF > 0) {
         PairJob J{PAIR_ADJ_F, prec, p->F.count, p->F.x, p->F.y, p->F.z,
-                  {p->F.vx, p->F.vy, p->F.vz}, {p->F.vxf, p->F.vyf, p->F.vzf}, n,
-                  p->m.px, p->m.py, p->m.pz, {}, {}, q, n, nrhs, chF, ncF, k, part,
+                  {p->F.vx, p->F.vy, p->F.vz}, n,
+                  p->m.px, p->m.py, p->m.pz, {}, q, n, nrhs, chF, ncF, k, part,
                   static_cast<int64_t>(nrhs) * p->F.count, SELF_THREAD_IDX, p->F.idx};
         launch_pairs(J, s, &p->prof);
         launch_scatter_conj(p->F.count, p->F.idx, nullptr, nrhs, ncF, part, y, ldy, s);
@@ -357,9 +369,54 @@ void apply_adjoint(vsie_problem *p, int f, vsie_precision prec, int nrhs, const 
     }
 }
 
+// FP32 product with the assembled operator of frequency f (rocBLAS complex
+// GEMM on the matrix cores): y = d x + A x (or conj(d) x + A^H x).  The
+// contraction is split into chunks of kDenseChunk sources (targets for the
+// adjoint) whose FP32 partial products are added in FP64.
+constexpr int64_t kDenseChunk = 8192;
+
+void apply_dense(vsie_problem *p, int f, bool adjoint, int nrhs, const double2 *x, int64_t ldx,
+                 double2 *y, int64_t ldy, hipStream_t s) {
+    const int64_t n = p->m.n;
+    const auto &D = p->dense[f];
+    if (!p->blas) check_blas(rocblas_create_handle(&p->blas), "rocblas_create_handle");
+    check_blas(rocblas_set_stream(p->blas, s), "rocblas_set_stream");
+    const int nc = static_cast<int>((n + kDenseChunk - 1) / kDenseChunk);
+    float2 *X = static_cast<float2 *>(p->dense_x.get(sizeof(float2) * static_cast<size_t>(n) * nrhs));
+    float2 *Y = static_cast<float2 *>(
+        p->dense_part.get(sizeof(float2) * static_cast<size_t>(n) * nrhs * nc));
+    launch_pack_plain(VSIE_FP32, n, nrhs, x, ldx, false, X, s);
+    const rocblas_float_complex one{1.0f, 0.0f}, zero{0.0f, 0.0f};
+    using C = rocblas_float_complex;
+    for (int c = 0; c < nc; ++c) {
+        const int64_t k0 = static_cast<int64_t>(c) * kDenseChunk;
+        const int kk = static_cast<int>(std::min<int64_t>(kDenseChunk, n - k0));
+        C *Yc = reinterpret_cast<C *>(Y + static_cast<int64_t>(c) * nrhs * n);
+        if (!adjoint) {
+            // columns k0.. of A times rows k0.. of X
+            check_blas(rocblas_cgemm(p->blas, rocblas_operation_none, rocblas_operation_none,
+                                     static_cast<rocblas_int>(n), nrhs, kk, &one,
+                                     reinterpret_cast<const C *>(D.A + k0 * D.ld),
+                                     static_cast<rocblas_int>(D.ld), reinterpret_cast<const C *>(X + k0),
+                                     static_cast<rocblas_int>(n), &zero, Yc, static_cast<rocblas_int>(n)),
+                       "rocblas_cgemm");
+        } else {
+            // (rows k0.. of A)^H times rows k0.. of X
+            check_blas(rocblas_cgemm(p->blas, rocblas_operation_conjugate_transpose,
+                                     rocblas_operation_none, static_cast<rocblas_int>(n), nrhs, kk, &one,
+                                     reinterpret_cast<const C *>(D.A + k0), static_cast<rocblas_int>(D.ld),
+                                     reinterpret_cast<const C *>(X + k0), static_cast<rocblas_int>(n), &zero,
+                                     Yc, static_cast<rocblas_int>(n)),
+                       "rocblas_cgemm");
+        }
+    }
+    launch_reduce32(n, nrhs, nc, Y, p->m.diag + static_cast<int64_t>(f) * n, adjoint, x, ldx, y, ldy, s);
+}
+
 void apply_op(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int nrhs,
               const double2 *x, int64_t ldx, double2 *y, int64_t ldy, hipStream_t s) {
-    if (adjoint) apply_adjoint(p, f, prec, nrhs, x, ldx, y, ldy, s);
+    if (prec == VSIE_FP32 && p->dense[f].A) apply_dense(p, f, adjoint, nrhs, x, ldx, y, ldy, s);
+    else if (adjoint) apply_adjoint(p, f, prec, nrhs, x, ldx, y, ldy, s);
     else apply_forward(p, f, prec, nrhs, x, ldx, y, ldy, s);
 }
 
@@ -867,6 +924,7 @@ vsie_status vsie_assemble(const vsie_geometry *geom, const double *vrho, const d
             if (!idx.empty()) p->cf_idx = p->upload(idx.data(), static_cast<int64_t>(idx.size()));
         }
         p->k0.assign(k0, k0 + n_freq);
+        p->dense.assign(n_freq, vsie_problem::Dense{});
         p->d_k0 = p->upload(k0, n_freq);
         launch_weights(m, p->d_k0, n_freq, s);
         VSIE_HIP(hipStreamSynchronize(s));
@@ -895,6 +953,8 @@ vsie_status vsie_set_materials(vsie_problem *p, const double *vrho_dev, const do
         launch_weights(p->m, p->d_k0, static_cast<int>(p->k0.size()), s);
         VSIE_HIP(hipStreamSynchronize(s));
         build_sources(p);
+        // assembled operators describe the old materials
+        for (auto &d : p->dense) d = vsie_problem::Dense{};
     });
 }
 
@@ -906,8 +966,8 @@ vsie_status vsie_matvec(vsie_problem *p, int32_t f, vsie_precision prec, int64_t
         require(nrhs >= 1 && nrhs <= 4096, "nrhs must be in [1, 4096]");
         check_vec(x, ldx, p->m.n, "x");
         check_vec(y, ldy, p->m.n, "y");
-        apply_forward(p, f, prec, static_cast<int>(nrhs), reinterpret_cast<const double2 *>(x), ldx,
-                      reinterpret_cast<double2 *>(y), ldy, as_stream(stream));
+        apply_op(p, f, prec, false, static_cast<int>(nrhs), reinterpret_cast<const double2 *>(x), ldx,
+                 reinterpret_cast<double2 *>(y), ldy, as_stream(stream));
     });
 }
 
@@ -920,8 +980,8 @@ vsie_status vsie_matvec_adjoint(vsie_problem *p, int32_t f, vsie_precision prec,
         require(nrhs >= 1 && nrhs <= 4096, "nrhs must be in [1, 4096]");
         check_vec(x, ldx, p->m.n, "x");
         check_vec(y, ldy, p->m.n, "y");
-        apply_adjoint(p, f, prec, static_cast<int>(nrhs), reinterpret_cast<const double2 *>(x), ldx,
-                      reinterpret_cast<double2 *>(y), ldy, as_stream(stream));
+        apply_op(p, f, prec, true, static_cast<int>(nrhs), reinterpret_cast<const double2 *>(x), ldx,
+                 reinterpret_cast<double2 *>(y), ldy, as_stream(stream));
     });
 }
 
@@ -1005,13 +1065,13 @@ vsie_status vsie_field(vsie_problem *p, int32_t f, vsie_precision prec, int64_t 
         launch_pack_charges(kClassG, prec, p->G, spf, R, xv, ldx, false, qG, s);
         launch_pack_charges(kClassF, prec, p->F, spf, R, xv, ldx, false, qF, s);
         if (ncG > 0) {
-            PairJob J{PAIR_FWD_G, prec, n_t, tx, ty, tz, {}, {}, p->G.count, p->G.x, p->G.y, p->G.z,
-                      {}, {}, qG, p->G.count, R, chG, ncG, p->k0[f], part, static_cast<int64_t>(R) * n_t};
+            PairJob J{PAIR_FWD_G, prec, n_t, tx, ty, tz, {}, p->G.count, p->G.x, p->G.y, p->G.z,
+                      {}, qG, p->G.count, R, chG, ncG, p->k0[f], part, static_cast<int64_t>(R) * n_t};
             launch_pairs(J, s, &p->prof);
         }
         if (ncF > 0) {
-            PairJob J{PAIR_FWD_F, prec, n_t, tx, ty, tz, {}, {}, p->F.count, p->F.x, p->F.y, p->F.z,
-                      {p->F.vx, p->F.vy, p->F.vz}, {p->F.vxf, p->F.vyf, p->F.vzf}, qF, p->F.count, R,
+            PairJob J{PAIR_FWD_F, prec, n_t, tx, ty, tz, {}, p->F.count, p->F.x, p->F.y, p->F.z,
+                      {p->F.vx, p->F.vy, p->F.vz}, qF, p->F.count, R,
                       chF, ncF, p->k0[f], part + static_cast<int64_t>(ncG) * R * n_t,
                       static_cast<int64_t>(R) * n_t};
             launch_pairs(J, s, &p->prof);
@@ -1044,8 +1104,8 @@ vsie_status vsie_source_sums(vsie_problem *p, int32_t f, int64_t n_t, const doub
         choose_chunks(n, n_t, ch, nc);
         double2 *part = static_cast<double2 *>(
             p->sums_part.get(sizeof(double2) * static_cast<size_t>(nc) * R * 4 * n));
-        PairJob J{PAIR_SUMS, VSIE_FP64, n, p->m.px, p->m.py, p->m.pz, {}, {}, n_t,
-                  colloc ? p->m.px : tx, colloc ? p->m.py : ty, colloc ? p->m.pz : tz, {}, {}, q, n_t, R,
+        PairJob J{PAIR_SUMS, VSIE_FP64, n, p->m.px, p->m.py, p->m.pz, {}, n_t,
+                  colloc ? p->m.px : tx, colloc ? p->m.py : ty, colloc ? p->m.pz : tz, {}, q, n_t, R,
                   ch, nc, p->k0[f], part, static_cast<int64_t>(R) * 4 * n,
                   colloc ? SELF_IDENT : SELF_NONE, nullptr};
         launch_pairs(J, s, &p->prof);
@@ -1107,6 +1167,27 @@ vsie_status vsie_param_gradient(vsie_problem *p, int32_t f, int64_t nrhs, const 
         launch_param_gradient(p->m, p->cf_off, p->cf_idx, p->k0[f], static_cast<int>(nrhs), c2(P), ldp,
                               c2(lam), ldl, c2(z), ldz, c2(Z), ldZ, c2(zR), ldzr, c2(ZR), ldZr, work,
                               grad_c, grad_rho, as_stream(stream));
+    });
+}
+
+vsie_status vsie_assemble_dense(vsie_problem *p, int32_t f, void *dense, int64_t ld, void *stream) {
+    return guarded([&] {
+        check_problem(p, f);
+        require(dense != nullptr, "dense matrix memory is NULL");
+        require(ld >= p->m.n, "leading dimension smaller than n");
+        require(p->m.n <= INT32_MAX && ld <= INT32_MAX, "dense operator too large for the GEMM");
+        hipStream_t s = as_stream(stream);
+        const double *vp[3] = {p->m.vpx, p->m.vpy, p->m.vpz};
+        launch_assemble_dense(p->m.n, p->m.px, p->m.py, p->m.pz, p->m.sp + static_cast<int64_t>(f) * p->m.n,
+                              vp[0], vp[1], vp[2], p->k0[f], static_cast<float2 *>(dense), ld, s);
+        p->dense[f] = vsie_problem::Dense{static_cast<float2 *>(dense), ld};
+    });
+}
+
+vsie_status vsie_release_dense(vsie_problem *p, int32_t f) {
+    return guarded([&] {
+        check_problem(p, f);
+        p->dense[f] = vsie_problem::Dense{};
     });
 }
 

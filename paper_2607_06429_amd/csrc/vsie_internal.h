@@ -58,9 +58,7 @@ struct SourceSet {
     int64_t count = 0;
     int32_t *idx = nullptr;                 // canonical index of each class entry
     double *x = nullptr, *y = nullptr, *z = nullptr;    // FP64 centroids
-    float *xf = nullptr, *yf = nullptr, *zf = nullptr;  // FP32 centroids
     double *vx = nullptr, *vy = nullptr, *vz = nullptr; // v' (F class only)
-    float *vxf = nullptr, *vyf = nullptr, *vzf = nullptr;
 };
 
 // One pair-sum pass (pair_kernels.hip).  Thread points t (n_t) each sum over
@@ -83,12 +81,10 @@ struct PairJob {
     vsie_precision prec;
     int64_t n_t;
     const double *tx, *ty, *tz;
-    const double *tv[3];      // ADJ_F, FP64: v' of thread points
-    const float *tvf[3];      // ADJ_F, FP32
+    const double *tv[3];      // ADJ_F: v' of thread points
     int64_t n_s;
     const double *sx, *sy, *sz;
-    const double *sv[3];      // FWD_F, FP64: v' of streamed points
-    const float *svf[3];      // FWD_F, FP32
+    const double *sv[3];      // FWD_F: v' of streamed points
     const void *charge;       // complex charges (double2 or float2), charge[r * ldq + j]
     int64_t ldq;
     int nrhs;
@@ -126,6 +122,14 @@ void launch_pack_plain(vsie_precision prec, int64_t n, int nrhs, const double2 *
 void launch_reduce_partials(int64_t n_t, int nrhs, int n_parts, const double2 *partial,
                             const double2 *diag, bool conj_diag, const double2 *x, int64_t ldx,
                             double2 *y, int64_t ldy, double2 *unused, hipStream_t s);
+// y = diag * x + sum of n_parts FP32 partial blocks (added in FP64)
+void launch_reduce32(int64_t n_t, int nrhs, int n_parts, const float2 *partial, const double2 *diag,
+                     bool conj_diag, const double2 *x, int64_t ldx, double2 *y, int64_t ldy,
+                     hipStream_t s);
+// dense FP32 off-diagonal operator, column-major with leading dimension ld (pair_kernels.hip)
+void launch_assemble_dense(int64_t n, const double *px, const double *py, const double *pz,
+                           const double *sp, const double *vpx, const double *vpy, const double *vpz,
+                           double k, float2 *A, int64_t ld, hipStream_t s);
 // y[idx[jj]] += conj(scale * sum of partials), scale = -s' (sp != null) or 1
 void launch_scatter_conj(int64_t count, const int32_t *idx, const double *sp, int nrhs,
                          int n_parts, const double2 *partial, double2 *y, int64_t ldy,

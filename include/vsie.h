@@ -131,6 +131,11 @@ typedef struct {
                             basis of all nrhs right-hand sides would exceed 48 GiB */
     double inner_tol;    /* VSIE_FP32 only: relative tolerance of each inner solve; default 1e-5 */
     int32_t max_outer;   /* VSIE_FP32 only: refinement steps; default 20 */
+    int32_t block;       /* 0: an independent GMRES per right-hand side, advanced in
+                            lockstep (later cycles deflated by the first cycle's space);
+                            1: block GMRES -- one block Krylov space for all right-hand
+                            sides of a cycle, restart counted in block steps and capped
+                            so that (steps x nrhs) <= 11585; default 0 */
 } vsie_solve_opts;
 
 typedef struct {

@@ -490,6 +490,17 @@ __global__ void bsub_kernel(int64_t n, const int32_t *__restrict__ act, const do
     out[static_cast<int64_t>(sl) * n + i] = make_double2(bv.x - av.x, bv.y - av.y);
 }
 
+// x[act[sl] * ldx + i] += W[sl * n + i]
+__global__ void scatter_add_kernel(int64_t n, const int32_t *__restrict__ act, const double2 *__restrict__ W,
+                                   double2 *__restrict__ x, int64_t ldx) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+    const int sl = blockIdx.y;
+    if (i >= n) return;
+    const double2 w = W[static_cast<int64_t>(sl) * n + i];
+    double2 *xc = x + static_cast<int64_t>(act[sl]) * ldx;
+    xc[i] = make_double2(xc[i].x + w.x, xc[i].y + w.y);
+}
+
 }  // namespace
 
 #define LAUNCH_CHECK() VSIE_HIP(hipGetLastError())
@@ -712,4 +723,13 @@ void bblas_sub(int64_t n, int nslots, const int32_t *act, const double2 *b, int6
     LAUNCH_CHECK();
 }
 
+}  // namespace vsie
+
+namespace vsie {
+void blas_scatter_add(int64_t n, int nslots, const int32_t *act, const double2 *W, double2 *x, int64_t ldx,
+                      hipStream_t s) {
+    if (nslots == 0 || n == 0) return;
+    hipLaunchKernelGGL(scatter_add_kernel, dim3(blocks_for(n), nslots), dim3(kT), 0, s, n, act, W, x, ldx);
+    LAUNCH_CHECK();
+}
 }  // namespace vsie

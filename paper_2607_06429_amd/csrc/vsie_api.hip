@@ -5,6 +5,7 @@
 #include <complex>
 #include <cstring>
 #include <memory>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -88,6 +89,7 @@ struct vsie_problem {
     Scratch partial, chargeG, chargeF, chargeAll, sums_part, grad_work;
     // Krylov workspace
     Scratch V, V2, w, r, ax, h1, h2, tc, nrm, dpart, npart, yv, act, act2, live, kd, kc, xa, axa, rres;
+    Scratch bh, bg;  // block GMRES: Hessenberg block column, Gram / inverse factor
     PairProfiler prof;
     // dense FP32 off-diagonal operator per frequency (caller-owned memory)
     struct Dense {
@@ -135,7 +137,7 @@ struct vsie_problem {
         for (void *p : owned) (void)hipFree(p);
         for (Scratch *s : {&partial, &chargeG, &chargeF, &chargeAll, &sums_part, &grad_work, &V, &V2, &w, &r, &ax,
                            &h1, &h2, &tc, &nrm, &dpart, &npart, &yv, &act, &act2, &live, &kd, &kc, &xa, &axa,
-                           &rres})
+                           &rres, &bh, &bg})
             s->release();
     }
 };
@@ -742,6 +744,10 @@ int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
     return total;
 }
 
+int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const std::vector<int32_t> &rhs,
+                double2 *Rres, const std::vector<double> &rn, const std::vector<double> &ctol, int m,
+                int iter_cap, double2 *x, int64_t ldx, SolveCounters &cnt, hipStream_t s);
+
 // Solve op(A) x_r = b_r for r < R.  FP64: restarted GMRES(m), each restart
 // from the true FP64 residual.  FP32: the same loop is iterative refinement --
 // residuals with the FP64 operator, corrections from one GMRES cycle with the
@@ -822,7 +828,16 @@ vsie_status solve_batch(vsie_problem *p, int f, vsie_precision prec, bool adjoin
         }
         for (int r : next) cnt.outer[r]++;
         int done;
-        if (!have_first) {
+        if (o.block) {
+            // block steps per cycle: the requested restart, but the host R factor of the block
+            // Hessenberg ((m Ra)^2 complex) stays near 2 GB and the basis within the budget
+            const int Ra = static_cast<int>(next.size());
+            const int64_t mb_host = std::max<int64_t>(1, 11585 / Ra);
+            const int64_t mb_dev = std::max<int64_t>(1, kKrylovBytes / (static_cast<int64_t>(sizeof(double2)) * n * Ra) - 1);
+            const int mb = static_cast<int>(std::min<int64_t>({static_cast<int64_t>(std::max(1, o.restart)), mb_host, mb_dev}));
+            done = block_cycle(p, f, prec, adjoint, next, cyc_res, next_rn, next_tol, mb, o.max_iter, x, ldx,
+                               cnt, s);
+        } else if (!have_first) {
             done = gmres_cycle(p, f, prec, adjoint, R, next, cyc_res, next_rn, next_tol, m, o.max_iter,
                                x, ldx, cnt, s, V1, &first, nullptr);
             have_first = true;
@@ -839,6 +854,254 @@ vsie_status solve_batch(vsie_problem *p, int f, vsie_precision prec, bool adjoin
         active = next;
     }
     return status;
+}
+
+// ---------------------------------------------------------------------------
+// Block GMRES: one block Krylov space for all right-hand sides of a cycle.
+//
+// Block Arnoldi with classical Gram-Schmidt twice as complex GEMMs (rocBLAS
+// zgemm, FP64 matrix cores), CholeskyQR2 for each new block, and an
+// incremental Householder QR of the block upper Hessenberg matrix on the host
+// (one reflector per column, Ra + 1 rows long) that yields each column's
+// residual norm after every block step.
+
+// run fn(i) for i in [0, count) on up to 16 host threads
+template <typename Fn>
+void parallel_for(int count, Fn fn) {
+    const int nt = std::max(1, std::min<int>({count, 16, static_cast<int>(std::thread::hardware_concurrency())}));
+    if (nt <= 1) {
+        for (int i = 0; i < count; ++i) fn(i);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&, t] {
+            for (int i = t; i < count; i += nt) fn(i);
+        });
+    for (auto &x : th) x.join();
+}
+
+// G = T^H T with T upper triangular (G Hermitian r x r, column-major).  A
+// diagonal shift is added when a pivot is not safely positive (a nearly
+// rank-deficient block); the second CholeskyQR pass restores orthogonality.
+void chol_upper(int r, const std::vector<cd> &G, std::vector<cd> &T) {
+    double dmax = 0.0;
+    for (int i = 0; i < r; ++i) dmax = std::max(dmax, G[static_cast<size_t>(i) * r + i].real());
+    if (!(dmax > 0.0) || !std::isfinite(dmax)) fail(VSIE_E_NAN, "block QR: zero or non-finite block");
+    for (double shift = 0.0;; shift = shift == 0.0 ? 1e-14 * dmax : shift * 100.0) {
+        if (shift > 1e-4 * dmax) fail(VSIE_E_NAN, "block QR: Cholesky failed");
+        T.assign(static_cast<size_t>(r) * r, 0.0);
+        bool ok = true;
+        for (int j = 0; j < r && ok; ++j) {
+            for (int i = 0; i <= j; ++i) {
+                cd acc = G[static_cast<size_t>(j) * r + i];
+                if (i == j) acc += shift;
+                for (int k = 0; k < i; ++k)
+                    acc -= std::conj(T[static_cast<size_t>(i) * r + k]) * T[static_cast<size_t>(j) * r + k];
+                if (i == j) {
+                    if (!(acc.real() > 1e-15 * dmax)) {
+                        ok = false;
+                        break;
+                    }
+                    T[static_cast<size_t>(j) * r + j] = std::sqrt(acc.real());
+                } else {
+                    T[static_cast<size_t>(j) * r + i] = acc / T[static_cast<size_t>(i) * r + i];
+                }
+            }
+        }
+        if (ok) return;
+    }
+}
+
+// inverse of an upper triangular r x r matrix (column-major)
+void tri_inv_upper(int r, const std::vector<cd> &T, std::vector<cd> &Ti) {
+    Ti.assign(static_cast<size_t>(r) * r, 0.0);
+    for (int j = 0; j < r; ++j) {
+        Ti[static_cast<size_t>(j) * r + j] = 1.0 / T[static_cast<size_t>(j) * r + j];
+        for (int i = j - 1; i >= 0; --i) {
+            cd acc = 0.0;
+            for (int k = i + 1; k <= j; ++k) acc += T[static_cast<size_t>(k) * r + i] * Ti[static_cast<size_t>(j) * r + k];
+            Ti[static_cast<size_t>(j) * r + i] = -acc / T[static_cast<size_t>(i) * r + i];
+        }
+    }
+}
+
+using zc = rocblas_double_complex;
+inline const zc *zcp(const double2 *p) { return reinterpret_cast<const zc *>(p); }
+inline zc *zcp(double2 *p) { return reinterpret_cast<zc *>(p); }
+
+// C = op(A) B with plain column-major operands (rocBLAS zgemm)
+void zgemm(vsie_problem *p, bool conjA, int64_t m, int64_t nn, int64_t k, cd alpha, const double2 *A,
+           int64_t lda, const double2 *B, int64_t ldb, cd beta, double2 *C, int64_t ldc) {
+    require(m <= INT32_MAX && nn <= INT32_MAX && k <= INT32_MAX && lda <= INT32_MAX &&
+                ldb <= INT32_MAX && ldc <= INT32_MAX,
+            "block GEMM too large");
+    const zc a{alpha.real(), alpha.imag()}, b{beta.real(), beta.imag()};
+    check_blas(rocblas_zgemm(p->blas, conjA ? rocblas_operation_conjugate_transpose : rocblas_operation_none,
+                             rocblas_operation_none, static_cast<rocblas_int>(m), static_cast<rocblas_int>(nn),
+                             static_cast<rocblas_int>(k), &a, zcp(A), static_cast<rocblas_int>(lda), zcp(B),
+                             static_cast<rocblas_int>(ldb), &b, zcp(C), static_cast<rocblas_int>(ldc)),
+               "rocblas_zgemm");
+}
+
+// CholeskyQR2 of the n x r block Wsrc: dst = Wsrc T^{-1} with orthonormal
+// columns and T upper triangular (host).  tmp is an n x r scratch block.
+void cholqr2(vsie_problem *p, int64_t n, int r, const double2 *Wsrc, double2 *tmp, double2 *dst,
+             std::vector<cd> &T, hipStream_t s) {
+    double2 *Gd = static_cast<double2 *>(p->bg.get(sizeof(double2) * static_cast<size_t>(r) * r));
+    std::vector<double2> gh;
+    std::vector<cd> G(static_cast<size_t>(r) * r), T1, T2, Ti;
+    const double2 *src = Wsrc;
+    for (int pass = 0; pass < 2; ++pass) {
+        double2 *out = pass == 0 ? tmp : dst;
+        zgemm(p, true, r, r, n, 1.0, src, n, src, n, 0.0, Gd, r);
+        to_host(gh, Gd, static_cast<size_t>(r) * r, s);
+        for (size_t t = 0; t < G.size(); ++t) G[t] = cd(gh[t].x, gh[t].y);
+        std::vector<cd> &Tp = pass == 0 ? T1 : T2;
+        chol_upper(r, G, Tp);
+        tri_inv_upper(r, Tp, Ti);
+        std::vector<double2> th(Ti.size());
+        for (size_t t = 0; t < Ti.size(); ++t) th[t] = make_double2(Ti[t].real(), Ti[t].imag());
+        to_device(Gd, th, s);
+        zgemm(p, false, n, r, r, 1.0, src, n, Gd, r, 0.0, out, n);
+        src = out;
+    }
+    // T = T2 T1
+    T.assign(static_cast<size_t>(r) * r, 0.0);
+    for (int j = 0; j < r; ++j)
+        for (int i = 0; i <= j; ++i) {
+            cd acc = 0.0;
+            for (int k = i; k <= j; ++k) acc += T2[static_cast<size_t>(k) * r + i] * T1[static_cast<size_t>(j) * r + k];
+            T[static_cast<size_t>(j) * r + i] = acc;
+        }
+}
+
+// Householder reflector P = I - 2 u u^H / (u^H u) with P x = alpha e_1; u overwrites x.
+// Returns u^H u (0 when x = 0: P = I).
+double make_reflector(cd *x, int len, cd &alpha) {
+    double nx = 0.0;
+    for (int i = 0; i < len; ++i) nx += std::norm(x[i]);
+    nx = std::sqrt(nx);
+    if (nx == 0.0) {
+        alpha = 0.0;
+        return 0.0;
+    }
+    const cd ph = std::abs(x[0]) > 0.0 ? x[0] / std::abs(x[0]) : cd(1.0, 0.0);
+    alpha = -ph * nx;
+    x[0] -= alpha;
+    double uu = 0.0;
+    for (int i = 0; i < len; ++i) uu += std::norm(x[i]);
+    return uu;
+}
+
+inline void apply_reflector(const cd *u, double uu, int len, cd *y) {
+    if (uu == 0.0) return;
+    cd d = 0.0;
+    for (int i = 0; i < len; ++i) d += std::conj(u[i]) * y[i];
+    d *= 2.0 / uu;
+    for (int i = 0; i < len; ++i) y[i] -= d * u[i];
+}
+
+// One block GMRES cycle for the right-hand sides rhs[0..Ra) with residual
+// block Rres (n x Ra, column norms rn) and per-column tolerances; adds the
+// corrections to x.  Returns the number of block steps.
+int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const std::vector<int32_t> &rhs,
+                double2 *Rres, const std::vector<double> &rn, const std::vector<double> &ctol, int m,
+                int iter_cap, double2 *x, int64_t ldx, SolveCounters &cnt, hipStream_t s) {
+    const int64_t n = p->m.n;
+    const int Ra = static_cast<int>(rhs.size());
+    const int64_t ldH = static_cast<int64_t>(m + 1) * Ra;  // rows of the block Hessenberg / G
+    double2 *V = static_cast<double2 *>(p->V.get(sizeof(double2) * static_cast<size_t>(n) * Ra * (m + 1)));
+    double2 *W = static_cast<double2 *>(p->w.get(sizeof(double2) * static_cast<size_t>(n) * Ra));
+    double2 *Z = static_cast<double2 *>(p->ax.get(sizeof(double2) * static_cast<size_t>(n) * Ra));
+    double2 *Hd = static_cast<double2 *>(p->bh.get(sizeof(double2) * static_cast<size_t>(ldH) * Ra));
+    if (!p->blas) check_blas(rocblas_create_handle(&p->blas), "rocblas_create_handle");
+    check_blas(rocblas_set_stream(p->blas, s), "rocblas_set_stream");
+
+    std::vector<cd> S0;
+    cholqr2(p, n, Ra, Rres, Z, V, S0, s);
+    // transformed right-hand sides and the R factor of the block Hessenberg (column-major)
+    std::vector<cd> G(static_cast<size_t>(ldH) * Ra, 0.0);
+    for (int c = 0; c < Ra; ++c)
+        for (int i = 0; i <= c; ++i) G[static_cast<size_t>(c) * ldH + i] = S0[static_cast<size_t>(c) * Ra + i];
+    std::vector<cd> Rf(static_cast<size_t>(m) * Ra * m * Ra, 0.0);
+    const int64_t ldR = static_cast<int64_t>(m) * Ra;
+    std::vector<cd> U(static_cast<size_t>(m) * Ra * (Ra + 1), 0.0);  // reflector of column c at c (Ra + 1)
+    std::vector<double> UU(static_cast<size_t>(m) * Ra, 0.0);
+    std::vector<double2> hh;
+    int jdone = 0;
+    for (int j = 0; j < m; ++j) {
+        bool capped = false;
+        for (int r : rhs) capped = capped || cnt.it[r] >= iter_cap;
+        if (capped) break;
+        apply_op(p, f, prec, adjoint, Ra, V + static_cast<int64_t>(j) * Ra * n, n, W, n, s);
+        for (int r : rhs) (prec == VSIE_FP64 ? cnt.mv64 : cnt.mv32)[r]++;
+        const int64_t kb = static_cast<int64_t>(j + 1) * Ra;
+        std::vector<cd> Hc(static_cast<size_t>(kb + Ra) * Ra, 0.0);  // new block column, rows 0..kb+Ra
+        for (int pass = 0; pass < 2; ++pass) {
+            zgemm(p, true, kb, Ra, n, 1.0, V, n, W, n, 0.0, Hd, kb);
+            zgemm(p, false, n, Ra, kb, -1.0, V, n, Hd, kb, 1.0, W, n);
+            to_host(hh, Hd, static_cast<size_t>(kb) * Ra, s);
+            for (int c = 0; c < Ra; ++c)
+                for (int64_t i = 0; i < kb; ++i)
+                    Hc[static_cast<size_t>(c) * (kb + Ra) + i] += cd(hh[c * kb + i].x, hh[c * kb + i].y);
+        }
+        std::vector<cd> T;
+        cholqr2(p, n, Ra, W, Z, V + kb * n, T, s);
+        for (int c = 0; c < Ra; ++c)
+            for (int i = 0; i <= c; ++i) Hc[static_cast<size_t>(c) * (kb + Ra) + kb + i] = T[static_cast<size_t>(c) * Ra + i];
+        // previous reflectors on the new columns (independent per column)
+        const int64_t c0 = static_cast<int64_t>(j) * Ra;
+        parallel_for(Ra, [&](int c) {
+            cd *h = &Hc[static_cast<size_t>(c) * (kb + Ra)];
+            for (int64_t k = 0; k < c0; ++k) apply_reflector(&U[static_cast<size_t>(k) * (Ra + 1)], UU[k], Ra + 1, h + k);
+        });
+        // this block's reflectors, column by column
+        for (int cl = 0; cl < Ra; ++cl) {
+            const int64_t c = c0 + cl;
+            cd *h = &Hc[static_cast<size_t>(cl) * (kb + Ra)];
+            for (int64_t k = c0; k < c; ++k) apply_reflector(&U[static_cast<size_t>(k) * (Ra + 1)], UU[k], Ra + 1, h + k);
+            cd *u = &U[static_cast<size_t>(c) * (Ra + 1)];
+            for (int t = 0; t <= Ra; ++t) u[t] = h[c + t];
+            cd alpha;
+            UU[c] = make_reflector(u, Ra + 1, alpha);
+            for (int64_t i = 0; i < c; ++i) Rf[static_cast<size_t>(c) * ldR + i] = h[i];
+            Rf[static_cast<size_t>(c) * ldR + c] = UU[c] == 0.0 ? h[c] : alpha;
+            for (int rc = 0; rc < Ra; ++rc) apply_reflector(u, UU[c], Ra + 1, &G[static_cast<size_t>(rc) * ldH + c]);
+        }
+        for (int r : rhs) cnt.it[r]++;
+        jdone = j + 1;
+        bool all = true;
+        for (int rc = 0; rc < Ra; ++rc) {
+            double res = 0.0;
+            for (int t = 0; t < Ra; ++t) res += std::norm(G[static_cast<size_t>(rc) * ldH + kb + t]);
+            if (!std::isfinite(res)) fail(VSIE_E_NAN, "non-finite block residual");
+            all = all && std::sqrt(res) <= ctol[rc] * rn[rc];
+        }
+        if (all) break;
+    }
+    if (jdone == 0) return 0;
+    // Y = R^{-1} G(0 : jdone Ra, :), per column
+    const int64_t kk = static_cast<int64_t>(jdone) * Ra;
+    std::vector<double2> Yh(static_cast<size_t>(kk) * Ra);
+    parallel_for(Ra, [&](int rc) {
+        std::vector<cd> y(kk);
+        for (int64_t i = kk - 1; i >= 0; --i) {
+            cd acc = G[static_cast<size_t>(rc) * ldH + i];
+            for (int64_t t = i + 1; t < kk; ++t) acc -= Rf[static_cast<size_t>(t) * ldR + i] * y[t];
+            const cd d = Rf[static_cast<size_t>(i) * ldR + i];
+            y[i] = d == 0.0 ? 0.0 : acc / d;
+        }
+        for (int64_t i = 0; i < kk; ++i) Yh[static_cast<size_t>(rc) * kk + i] = make_double2(y[i].real(), y[i].imag());
+    });
+    double2 *Yd = static_cast<double2 *>(p->bh.get(sizeof(double2) * static_cast<size_t>(std::max(kk, ldH)) * Ra));
+    to_device(Yd, Yh, s);
+    zgemm(p, false, n, Ra, kk, 1.0, V, n, Yd, kk, 0.0, W, n);
+    int32_t *act = static_cast<int32_t *>(p->act.get(sizeof(int32_t) * Ra));
+    to_device(act, rhs, s);
+    blas_scatter_add(n, Ra, act, W, x, ldx, s);
+    VSIE_HIP(hipStreamSynchronize(s));
+    return jdone;
 }
 
 }  // namespace
@@ -997,10 +1260,10 @@ vsie_status vsie_solve(vsie_problem *p, int32_t f, vsie_precision prec, int32_t 
         require(nrhs >= 1, "nrhs must be >= 1");
         check_vec(b, ldb, p->m.n, "b");
         check_vec(x, ldx, p->m.n, "x");
-        vsie_solve_opts o{1e-10, 3000, 500, 1e-5, 20};
+        vsie_solve_opts o{1e-10, 3000, 500, 1e-5, 20, 0};
         if (opts) o = *opts;
         require(o.tol > 0 && o.max_iter >= 0 && o.restart >= 1 && o.restart <= 20000 &&
-                    o.inner_tol > 0 && o.inner_tol < 1 && o.max_outer >= 1,
+                    o.inner_tol > 0 && o.inner_tol < 1 && o.max_outer >= 1 && (o.block == 0 || o.block == 1),
                 "invalid solver options");
         hipStream_t s = as_stream(stream);
         const int R = static_cast<int>(nrhs);

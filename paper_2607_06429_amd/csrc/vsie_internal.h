@@ -182,6 +182,8 @@ void bblas_gather(int64_t n, int nslots, const int32_t *act, const double2 *src,
                   double2 *X, hipStream_t s);
 void bblas_update(int64_t n, int R, int nslots, const int32_t *act, const int32_t *kd, const double2 *V,
                   const double2 *y, int ystride, double2 *x, int64_t ldx, hipStream_t s);
+void blas_scatter_add(int64_t n, int nslots, const int32_t *act, const double2 *W, double2 *x, int64_t ldx,
+                      hipStream_t s);
 void bblas_sub(int64_t n, int nslots, const int32_t *act, const double2 *b, int64_t ldb,
                const double2 *ax, double2 *out, hipStream_t s);
 

@@ -359,3 +359,41 @@ def test_c2_dense_sampled_rows(V):
     P.release_dense(0)
     del A
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("restart", [2, 100])
+def test_block_gmres(V, prec, restart):
+    """Block GMRES over 6 columns (plane waves, a random column, a zero column)
+    against LU; restart=2 forces several block cycles."""
+    say("block gmres", prec, "restart", restart)
+    mesh, mat, k0 = case("lognormal")
+    d = O.discretise(mesh, mat, k0)
+    b = np.concatenate([O.plane_wave(d.pts, k0, W.fibonacci_sphere(4)),
+                        W.seeded_complex((d.n, 1), seed=81), np.zeros((d.n, 1))], axis=1)
+    ref = O.solve_lu(d, b)
+    P = V.Problem.from_mesh(mesh, mat, [k0])
+    pr = V.VSIE_FP64 if prec == "fp64" else V.VSIE_FP32
+    # every short FP32 cycle is one refinement step: allow as many as the FP64 run needs cycles
+    x, info = P.solve(dev(b).contiguous(), prec=pr, tol=1e-11, restart=restart, block=True,
+                      max_outer=400)
+    say("  info", info)
+    got = host(x)
+    assert info["status"] == V.VSIE_OK
+    assert np.all(got[:, 5] == 0)
+    assert O.rel_error(got[:, :5], ref[:, :5]) <= TOL_SOLVE
+
+
+def test_block_gmres_dense_adjoint(V):
+    say("block gmres, assembled FP32, adjoint")
+    mesh, mat, k0 = case("cube")
+    d = O.discretise(mesh, mat, k0)
+    b = W.seeded_complex((d.n, 3), seed=82)
+    import scipy.linalg as sla
+    ref = sla.solve(O.assemble(d).conj().T, b)
+    P = V.Problem.from_mesh(mesh, mat, [k0])
+    A = P.assemble_dense(0)
+    x, info = P.solve(dev(b).contiguous(), prec=V.VSIE_FP32, adjoint=True, tol=1e-11, block=True)
+    assert info["status"] == V.VSIE_OK
+    assert O.rel_error(host(x), ref) <= TOL_SOLVE
+    del A

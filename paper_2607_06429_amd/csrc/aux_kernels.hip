@@ -501,6 +501,21 @@ __global__ void scatter_add_kernel(int64_t n, const int32_t *__restrict__ act, c
     xc[i] = make_double2(xc[i].x + w.x, xc[i].y + w.y);
 }
 
+// C[j * ldc + i] = sum over slabs t (in order) of P[t * cnt + j * m + i], cnt = m * nn
+__global__ void sum_slabs_kernel(int64_t m, int64_t cnt, int parts, const double2 *__restrict__ P,
+                                 double2 *__restrict__ C, int64_t ldc) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+    if (e >= cnt) return;
+    double sx = 0.0, sy = 0.0;
+    for (int t = 0; t < parts; ++t) {
+        const double2 v = P[static_cast<int64_t>(t) * cnt + e];
+        sx += v.x;
+        sy += v.y;
+    }
+    const int64_t j = e / m, i = e - j * m;
+    C[j * ldc + i] = make_double2(sx, sy);
+}
+
 }  // namespace
 
 #define LAUNCH_CHECK() VSIE_HIP(hipGetLastError())
@@ -730,6 +745,13 @@ void blas_scatter_add(int64_t n, int nslots, const int32_t *act, const double2 *
                       hipStream_t s) {
     if (nslots == 0 || n == 0) return;
     hipLaunchKernelGGL(scatter_add_kernel, dim3(blocks_for(n), nslots), dim3(kT), 0, s, n, act, W, x, ldx);
+    LAUNCH_CHECK();
+}
+
+void blas_sum_slabs(int64_t m, int64_t nn, int parts, const double2 *P, double2 *C, int64_t ldc, hipStream_t s) {
+    const int64_t cnt = m * nn;
+    if (cnt == 0) return;
+    hipLaunchKernelGGL(sum_slabs_kernel, dim3(blocks_for(cnt)), dim3(kT), 0, s, m, cnt, parts, P, C, ldc);
     LAUNCH_CHECK();
 }
 }  // namespace vsie

@@ -89,7 +89,7 @@ struct vsie_problem {
     Scratch partial, chargeG, chargeF, chargeAll, sums_part, grad_work;
     // Krylov workspace
     Scratch V, V2, w, r, ax, h1, h2, tc, nrm, dpart, npart, yv, act, act2, live, kd, kc, xa, axa, rres;
-    Scratch bh, bg;  // block GMRES: Hessenberg block column, Gram / inverse factor
+    Scratch bh, bg, bsk;  // block GMRES: Hessenberg block column, Gram / inverse factor, slab partials
     PairProfiler prof;
     // dense FP32 off-diagonal operator per frequency (caller-owned memory)
     struct Dense {
@@ -137,7 +137,7 @@ struct vsie_problem {
         for (void *p : owned) (void)hipFree(p);
         for (Scratch *s : {&partial, &chargeG, &chargeF, &chargeAll, &sums_part, &grad_work, &V, &V2, &w, &r, &ax,
                            &h1, &h2, &tc, &nrm, &dpart, &npart, &yv, &act, &act2, &live, &kd, &kc, &xa, &axa,
-                           &rres, &bh, &bg})
+                           &rres, &bh, &bg, &bsk})
             s->release();
     }
 };
@@ -944,6 +944,41 @@ void zgemm(vsie_problem *p, bool conjA, int64_t m, int64_t nn, int64_t k, cd alp
                "rocblas_zgemm");
 }
 
+// C = A^H B for tall A (k x m) and B (k x nn), k >> m, nn.  A single GEMM
+// would give only ceil(m/64) ceil(nn/64) output tiles, each running the whole
+// k loop, so the rows are cut into slabs: one strided-batched GEMM makes the
+// product of every slab, a second call the ragged last slab, and the slab
+// partials are summed in slab order (deterministic).
+constexpr int64_t kTallTargetTiles = 2048;
+constexpr int64_t kTallMinSlab = 512;
+
+void zgemm_tall_cn(vsie_problem *p, int64_t m, int64_t nn, int64_t k, const double2 *A, int64_t lda,
+                   const double2 *B, int64_t ldb, double2 *C, int64_t ldc, hipStream_t s) {
+    const int64_t tiles = ((m + 63) / 64) * ((nn + 63) / 64);
+    int64_t slabs = std::min((kTallTargetTiles + tiles - 1) / tiles, std::max<int64_t>(1, k / kTallMinSlab));
+    if (slabs <= 1) {
+        zgemm(p, true, m, nn, k, 1.0, A, lda, B, ldb, 0.0, C, ldc);
+        return;
+    }
+    const int64_t rows = (k + slabs - 1) / slabs;
+    const int64_t full = k / rows, tail = k - full * rows;
+    const int parts = static_cast<int>(full + (tail > 0 ? 1 : 0));
+    const int64_t cnt = m * nn;
+    double2 *P = static_cast<double2 *>(p->bsk.get(sizeof(double2) * static_cast<size_t>(cnt) * parts));
+    require(m <= INT32_MAX && nn <= INT32_MAX && rows <= INT32_MAX && lda <= INT32_MAX && ldb <= INT32_MAX,
+            "block GEMM too large");
+    const zc one{1.0, 0.0}, zero{0.0, 0.0};
+    check_blas(rocblas_zgemm_strided_batched(
+                   p->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none,
+                   static_cast<rocblas_int>(m), static_cast<rocblas_int>(nn), static_cast<rocblas_int>(rows), &one,
+                   zcp(A), static_cast<rocblas_int>(lda), rows, zcp(B), static_cast<rocblas_int>(ldb), rows, &zero,
+                   zcp(P), static_cast<rocblas_int>(m), cnt, static_cast<rocblas_int>(full)),
+               "rocblas_zgemm_strided_batched");
+    if (tail > 0)
+        zgemm(p, true, m, nn, tail, 1.0, A + full * rows, lda, B + full * rows, ldb, 0.0, P + full * cnt, m);
+    blas_sum_slabs(m, nn, parts, P, C, ldc, s);
+}
+
 // CholeskyQR2 of the n x r block Wsrc: dst = Wsrc T^{-1} with orthonormal
 // columns and T upper triangular (host).  tmp is an n x r scratch block.
 void cholqr2(vsie_problem *p, int64_t n, int r, const double2 *Wsrc, double2 *tmp, double2 *dst,
@@ -954,7 +989,7 @@ void cholqr2(vsie_problem *p, int64_t n, int r, const double2 *Wsrc, double2 *tm
     const double2 *src = Wsrc;
     for (int pass = 0; pass < 2; ++pass) {
         double2 *out = pass == 0 ? tmp : dst;
-        zgemm(p, true, r, r, n, 1.0, src, n, src, n, 0.0, Gd, r);
+        zgemm_tall_cn(p, r, r, n, src, n, src, n, Gd, r, s);
         to_host(gh, Gd, static_cast<size_t>(r) * r, s);
         for (size_t t = 0; t < G.size(); ++t) G[t] = cd(gh[t].x, gh[t].y);
         std::vector<cd> &Tp = pass == 0 ? T1 : T2;
@@ -1039,7 +1074,7 @@ int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const
         const int64_t kb = static_cast<int64_t>(j + 1) * Ra;
         std::vector<cd> Hc(static_cast<size_t>(kb + Ra) * Ra, 0.0);  // new block column, rows 0..kb+Ra
         for (int pass = 0; pass < 2; ++pass) {
-            zgemm(p, true, kb, Ra, n, 1.0, V, n, W, n, 0.0, Hd, kb);
+            zgemm_tall_cn(p, kb, Ra, n, V, n, W, n, Hd, kb, s);
             zgemm(p, false, n, Ra, kb, -1.0, V, n, Hd, kb, 1.0, W, n);
             to_host(hh, Hd, static_cast<size_t>(kb) * Ra, s);
             for (int c = 0; c < Ra; ++c)

@@ -184,6 +184,8 @@ void bblas_update(int64_t n, int R, int nslots, const int32_t *act, const int32_
                   const double2 *y, int ystride, double2 *x, int64_t ldx, hipStream_t s);
 void blas_scatter_add(int64_t n, int nslots, const int32_t *act, const double2 *W, double2 *x, int64_t ldx,
                       hipStream_t s);
+// C (m x nn, leading dimension ldc) = sum of parts consecutive m x nn column-major slabs of P
+void blas_sum_slabs(int64_t m, int64_t nn, int parts, const double2 *P, double2 *C, int64_t ldc, hipStream_t s);
 void bblas_sub(int64_t n, int nslots, const int32_t *act, const double2 *b, int64_t ldb,
                const double2 *ax, double2 *out, hipStream_t s);
 

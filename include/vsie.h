@@ -124,6 +124,46 @@ vsie_status vsie_matvec_adjoint(vsie_problem *p, int32_t f, vsie_precision prec,
                                 const double *x, int64_t ldx, double *y, int64_t ldy,
                                 void *stream);
 
+/* y_t = A_{f0+t} x_t for the nf frequencies f0 .. f0 + nf - 1 at once: x and
+ * y hold nf consecutive blocks of nrhs columns, block t (frequency f0 + t)
+ * starting at column t nrhs (same layout rules as vsie_matvec).  With
+ * VSIE_FP32 and nrhs >= the tuning's mfma_min_rhs, each source class runs in
+ * one persistent matrix-core launch over all nf frequencies; otherwise the
+ * frequencies are applied one after the other. */
+vsie_status vsie_matvec_multi(vsie_problem *p, int32_t f0, int32_t nf, vsie_precision prec, int64_t nrhs,
+                              const double *x, int64_t ldx, double *y, int64_t ldy, void *stream);
+
+/* Launch configuration of the pair products of one problem.
+ *
+ * FP32 forward products (vsie_matvec, vsie_matvec_multi, the inner solves of
+ * vsie_solve) with at least mfma_min_rhs right-hand sides evaluate each pair
+ * kernel once on the vector ALUs and apply it to 16-column blocks of
+ * right-hand sides on the matrix cores (v_mfma_f32_16x16x4_f32, FP32
+ * accumulation over tiles of 128 sources, then FP64), in a persistent grid
+ * whose work items are (frequency, column block, source chunk, target tile).
+ * Other products use the vector pair kernel, one thread per target. */
+typedef struct {
+    int32_t mfma_min_rhs;      /* 0 = never use the matrix cores; default 8 */
+    int32_t mfma_tg;           /* 16-target groups per wave: 2 or 4; default 2 */
+    int32_t mfma_nb;           /* 16-column blocks per work item: 1 or 2; default 1 */
+    int32_t items_per_wave;    /* work items per wave of the persistent grid, which
+                                  sets the source chunk length (>= 1); default 16 */
+    int64_t vec_target_waves;  /* waves per vector pair launch, which sets its source
+                                  chunk length (>= 1024); default 32768 */
+} vsie_tuning;
+
+vsie_status vsie_get_tuning(const vsie_problem *p, vsie_tuning *out);
+/* Rejects values outside the ranges above (VSIE_E_INVALID, tuning unchanged). */
+vsie_status vsie_set_tuning(vsie_problem *p, const vsie_tuning *t);
+
+/* Autotuner: times every candidate configuration of the FP32 forward product
+ * with nrhs right-hand sides at frequency f (the vector kernel at three chunk
+ * lengths; the matrix-core kernel at each (mfma_tg, mfma_nb) and three
+ * items_per_wave when nrhs >= 8), two launches each after a warm-up, keeps the
+ * fastest in the problem's tuning and copies it to *best (may be NULL).
+ * Allocates and frees its own input and output blocks; synchronises stream. */
+vsie_status vsie_autotune(vsie_problem *p, int32_t f, int64_t nrhs, vsie_tuning *best, void *stream);
+
 typedef struct {
     double tol;          /* stop when ||b - A x|| <= tol ||b|| (FP64 residual); default 1e-10 */
     int32_t max_iter;    /* total GMRES iterations (all cycles, all outer steps); default 3000 */
@@ -237,7 +277,9 @@ vsie_status vsie_release_dense(vsie_problem *p, int32_t f);
  * launch with R right-hand sides counts its pairs once and R in rhs_pairs).
  * kind = 2 * mode + precision with mode 0 forward single layer, 1 forward
  * double layers (T and K), 2 adjoint double layers, 3 adjoint source sums,
- * and precision VSIE_FP64 or VSIE_FP32. */
+ * and precision VSIE_FP64 or VSIE_FP32; kind 8 and 9 are the matrix-core
+ * forward single layer and double layers (FP32; a launch over nf frequencies
+ * counts nf times its pairs). */
 typedef struct {
     int64_t launches;
     double ms;

@@ -23,7 +23,7 @@ __all__ = [
     "vsie_plane_wave", "vsie_field", "vsie_source_sums", "vsie_plane_wave_at", "vsie_adjoint_rhs",
     "vsie_param_gradient", "vsie_assemble_dense", "vsie_release_dense", "vsie_profile",
     "vsie_profile_read", "vsie_destroy", "vsie_last_error",
-    "vsie_size",
+    "vsie_size", "vsie_matvec_multi", "vsie_get_tuning", "vsie_set_tuning", "vsie_autotune",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -65,6 +65,14 @@ class SolveOpts(ctypes.Structure):
                 ("max_outer", _I32), ("block", _I32)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("mfma_min_rhs", _I32), ("mfma_tg", _I32), ("mfma_nb", _I32),
+                ("items_per_wave", _I32), ("vec_target_waves", _I64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", _I32), ("outer_steps", _I32), ("matvecs_fp64", _I32),
                 ("matvecs_fp32", _I32), ("rel_residual", _D)]
@@ -96,13 +104,18 @@ def _load():
     L.vsie_release_dense.argtypes = [_P, _I32]
     L.vsie_profile.argtypes = [_P, _I32]
     L.vsie_profile_read.argtypes = [_P, _I32, ctypes.POINTER(KernelStats)]
+    L.vsie_matvec_multi.argtypes = [_P, _I32, _I32, _I32, _I64, _P, _I64, _P, _I64, _P]
+    L.vsie_get_tuning.argtypes = [_P, ctypes.POINTER(Tuning)]
+    L.vsie_set_tuning.argtypes = [_P, ctypes.POINTER(Tuning)]
+    L.vsie_autotune.argtypes = [_P, _I32, _I64, ctypes.POINTER(Tuning), _P]
     L.vsie_destroy.argtypes = [_P]
     L.vsie_destroy.restype = None
     L.vsie_last_error.restype = ctypes.c_char_p
     for name in ("vsie_assemble", "vsie_set_materials", "vsie_matvec", "vsie_matvec_adjoint",
                  "vsie_solve", "vsie_plane_wave", "vsie_field", "vsie_source_sums",
                  "vsie_profile", "vsie_profile_read", "vsie_plane_wave_at", "vsie_adjoint_rhs",
-                 "vsie_param_gradient", "vsie_assemble_dense", "vsie_release_dense"):
+                 "vsie_param_gradient", "vsie_assemble_dense", "vsie_release_dense",
+                 "vsie_matvec_multi", "vsie_get_tuning", "vsie_set_tuning", "vsie_autotune"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -113,12 +126,14 @@ EXPORTED = ("vsie_assemble", "vsie_set_materials", "vsie_size", "vsie_matvec",
             "vsie_matvec_adjoint", "vsie_solve", "vsie_plane_wave", "vsie_field",
             "vsie_source_sums", "vsie_plane_wave_at", "vsie_adjoint_rhs", "vsie_param_gradient",
             "vsie_assemble_dense", "vsie_release_dense", "vsie_profile", "vsie_profile_read",
-            "vsie_destroy", "vsie_last_error")
+            "vsie_destroy", "vsie_last_error", "vsie_matvec_multi", "vsie_get_tuning",
+            "vsie_set_tuning", "vsie_autotune")
 
 # pair-kernel kinds reported by vsie_profile_read: 2 * mode + precision
 KIND_NAMES = {0: "fwd_single_layer_fp64", 1: "fwd_single_layer_fp32", 2: "fwd_double_layers_fp64",
               3: "fwd_double_layers_fp32", 4: "adj_double_layers_fp64", 5: "adj_double_layers_fp32",
-              6: "source_sums_fp64", 7: "source_sums_fp32"}
+              6: "source_sums_fp64", 7: "source_sums_fp32",
+              8: "mfma_fwd_single_layer_fp32", 9: "mfma_fwd_double_layers_fp32"}
 
 
 def vsie_last_error() -> str:
@@ -227,6 +242,38 @@ def vsie_matvec_adjoint(h, f, prec, x, y, stream=None):
     if Ry != R:
         raise ValueError("x and y hold different numbers of columns")
     _check(lib.vsie_matvec_adjoint(h, f, prec, R, px, ldx, py, ldy, _stream(stream)))
+
+
+def vsie_matvec_multi(h, f0, nf, prec, x, y, stream=None):
+    """x, y: (nf * R, n) -- rows t R .. t R + R - 1 belong to frequency f0 + t."""
+    n = vsie_size(h)
+    px, C, ldx = _cols(x, n)
+    py, Cy, ldy = _cols(y, n)
+    if Cy != C or C % nf:
+        raise ValueError("x and y must hold nf blocks of equally many columns")
+    _check(lib.vsie_matvec_multi(h, f0, nf, prec, C // nf, px, ldx, py, ldy, _stream(stream)))
+
+
+def vsie_get_tuning(h) -> dict:
+    t = Tuning()
+    _check(lib.vsie_get_tuning(h, ctypes.byref(t)))
+    return t.as_dict()
+
+
+def vsie_set_tuning(h, **kw):
+    t = Tuning()
+    _check(lib.vsie_get_tuning(h, ctypes.byref(t)))
+    for k, v in kw.items():
+        if k not in dict(Tuning._fields_):
+            raise KeyError(k)
+        setattr(t, k, v)
+    _check(lib.vsie_set_tuning(h, ctypes.byref(t)))
+
+
+def vsie_autotune(h, f, nrhs, stream=None) -> dict:
+    t = Tuning()
+    _check(lib.vsie_autotune(h, f, nrhs, ctypes.byref(t), _stream(stream)))
+    return t.as_dict()
 
 
 def vsie_solve(h, f, prec, adjoint, b, x, tol=1e-10, max_iter=3000, restart=500, inner_tol=1e-5,
@@ -404,6 +451,21 @@ class Problem:
         y = self._out(x) if out is None else out
         vsie_matvec_adjoint(self.handle, f, prec, x, y)
         return y
+
+    def matvec_multi(self, x, f0=0, nf=1, prec=VSIE_FP32, out=None):
+        y = self._out(x) if out is None else out
+        vsie_matvec_multi(self.handle, f0, nf, prec, x, y)
+        return y
+
+    @property
+    def tuning(self) -> dict:
+        return vsie_get_tuning(self.handle)
+
+    def set_tuning(self, **kw):
+        vsie_set_tuning(self.handle, **kw)
+
+    def autotune(self, nrhs, f=0) -> dict:
+        return vsie_autotune(self.handle, f, nrhs)
 
     def solve(self, b, f=0, prec=VSIE_FP64, adjoint=False, x0=None, **kw):
         import torch

@@ -55,19 +55,19 @@ struct Scratch {
     }
 };
 
-// Source chunking of one pair launch: enough (thread-block, chunk) waves to
-// keep every SIMD busy, but chunks of at least kMinChunk streamed points.
-constexpr int64_t kTargetWaves = 32768;
+// Source chunking of one vector pair launch: about target_waves (thread-block,
+// chunk) waves to keep every SIMD busy, but chunks of at least kMinChunk
+// streamed points.
 constexpr int64_t kMinChunk = 256;
 
-void choose_chunks(int64_t n_t, int64_t n_s, int64_t &chunk, int &n_chunks) {
+void choose_chunks(int64_t n_t, int64_t n_s, int64_t target_waves, int64_t &chunk, int &n_chunks) {
     if (n_s <= 0) {
         chunk = 1;
         n_chunks = 0;
         return;
     }
     const int64_t waves = std::max<int64_t>(1, (n_t + 63) / 64);
-    int64_t want = (kTargetWaves + waves - 1) / waves;
+    int64_t want = (target_waves + waves - 1) / waves;
     const int64_t max_chunks = std::max<int64_t>(1, n_s / kMinChunk);
     want = std::min<int64_t>(std::max<int64_t>(want, 1), std::min<int64_t>(max_chunks, 4096));
     chunk = (n_s + want - 1) / want;
@@ -91,6 +91,7 @@ struct vsie_problem {
     Scratch V, V2, w, r, ax, h1, h2, tc, nrm, dpart, npart, yv, act, act2, live, kd, kc, xa, axa, rres;
     Scratch bh, bg, bsk;  // block GMRES: Hessenberg block column, Gram / inverse factor, slab partials
     PairProfiler prof;
+    vsie_tuning tune{8, 2, 1, 16, 32768};
     // dense FP32 off-diagonal operator per frequency (caller-owned memory)
     struct Dense {
         float2 *A = nullptr;
@@ -116,7 +117,7 @@ struct vsie_problem {
         return d;
     }
     void free_sources(SourceSet &S) {
-        void *ps[] = {S.idx, S.x, S.y, S.z, S.vx, S.vy, S.vz};
+        void *ps[] = {S.idx, S.x, S.y, S.z, S.vx, S.vy, S.vz, S.pk, S.pv};
         for (void *q : ps) {
             if (!q) continue;
             auto it = std::find(owned.begin(), owned.end(), q);
@@ -242,29 +243,49 @@ void build_sources(vsie_problem *p) {
     }
     p->free_sources(p->G);
     p->free_sources(p->F);
+    // padding point of the matrix-core layout: farther than the extent of the
+    // mesh from every point (its pairs are finite and meet zero charges)
+    double lo3[3] = {px[0], py[0], pz[0]}, hi3[3] = {px[0], py[0], pz[0]};
+    for (int64_t e = 0; e < n; ++e) {
+        const double q[3] = {px[e], py[e], pz[e]};
+        for (int d = 0; d < 3; ++d) {
+            lo3[d] = std::min(lo3[d], q[d]);
+            hi3[d] = std::max(hi3[d], q[d]);
+        }
+    }
+    const double ext = std::max({hi3[0] - lo3[0], hi3[1] - lo3[1], hi3[2] - lo3[2]}) + 1.0;
     auto fill = [&](SourceSet &S, const std::vector<int32_t> &ix, bool with_v) {
         S.count = static_cast<int64_t>(ix.size());
         if (S.count == 0) return;
         std::vector<double> a(S.count), b(S.count), c(S.count);
+        std::vector<double4> pk(S.count + kMfmaPad), pv(S.count + kMfmaPad);
         for (int64_t j = 0; j < S.count; ++j) {
             a[j] = px[ix[j]];
             b[j] = py[ix[j]];
             c[j] = pz[ix[j]];
+            pk[j] = make_double4(a[j], b[j], c[j], 0.0);
+        }
+        for (int t = 0; t < kMfmaPad; ++t) {
+            pk[S.count + t] = make_double4(hi3[0] + ext, hi3[1] + ext, hi3[2] + ext, 0.0);
+            pv[S.count + t] = make_double4(0.0, 0.0, 0.0, 0.0);
         }
         S.idx = p->upload(ix.data(), S.count);
         S.x = p->upload(a.data(), S.count);
         S.y = p->upload(b.data(), S.count);
         S.z = p->upload(c.data(), S.count);
+        S.pk = p->upload(pk.data(), S.count + kMfmaPad);
         if (!with_v) return;
         std::vector<double> va(S.count), vb(S.count), vc(S.count);
         for (int64_t j = 0; j < S.count; ++j) {
             va[j] = vp[ix[j]];
             vb[j] = vp[n + ix[j]];
             vc[j] = vp[2 * n + ix[j]];
+            pv[j] = make_double4(va[j], vb[j], vc[j], 0.0);
         }
         S.vx = p->upload(va.data(), S.count);
         S.vy = p->upload(vb.data(), S.count);
         S.vz = p->upload(vc.data(), S.count);
+        S.pv = p->upload(pv.data(), S.count + kMfmaPad);
     };
     fill(p->G, gi, false);
     fill(p->F, fi, true);
@@ -288,8 +309,8 @@ void apply_forward_block(vsie_problem *p, int f, vsie_precision prec, int nrhs, 
     const int64_t n = p->m.n;
     int64_t chG, chF;
     int ncG, ncF;
-    choose_chunks(n, p->G.count, chG, ncG);
-    choose_chunks(n, p->F.count, chF, ncF);
+    choose_chunks(n, p->G.count, p->tune.vec_target_waves, chG, ncG);
+    choose_chunks(n, p->F.count, p->tune.vec_target_waves, chF, ncF);
     const int n_parts = ncG + ncF;
     double2 *part = static_cast<double2 *>(
         p->partial.get(sizeof(double2) * static_cast<size_t>(std::max(1, n_parts)) * nrhs * n));
@@ -341,8 +362,8 @@ void apply_adjoint_block(vsie_problem *p, int f, vsie_precision prec, int nrhs, 
     const double *spf = p->m.sp + static_cast<int64_t>(f) * n;
     int64_t chG = 1, chF = 1;
     int ncG = 0, ncF = 0;
-    if (p->G.count > 0) choose_chunks(p->G.count, n, chG, ncG);
-    if (p->F.count > 0) choose_chunks(p->F.count, n, chF, ncF);
+    if (p->G.count > 0) choose_chunks(p->G.count, n, p->tune.vec_target_waves, chG, ncG);
+    if (p->F.count > 0) choose_chunks(p->F.count, n, p->tune.vec_target_waves, chF, ncF);
     const size_t need = std::max(static_cast<size_t>(ncG) * p->G.count, static_cast<size_t>(ncF) * p->F.count);
     double2 *part = static_cast<double2 *>(p->partial.get(sizeof(double2) * std::max<size_t>(1, need) * nrhs));
     if (ncG > 0) {
@@ -415,10 +436,92 @@ void apply_dense(vsie_problem *p, int f, bool adjoint, int nrhs, const double2 *
     launch_reduce32(n, nrhs, nc, Y, p->m.diag + static_cast<int64_t>(f) * n, adjoint, x, ldx, y, ldy, s);
 }
 
+// FP32 forward products on the matrix cores for the nf frequencies f0 ..:
+// y_t = A_{f0+t} x_t, x_t = x + t xfs, y_t = y + t yfs, at most kMfmaMaxCols
+// columns per pass.  Each source class is one persistent launch over all
+// frequencies; the partial sums of every frequency are then reduced with its
+// FP64 diagonal.
+constexpr int kMfmaMaxCols = 128;
+
+void apply_forward_mfma_block(vsie_problem *p, int f0, int nf, int nrhs, const double2 *x, int64_t ldx,
+                              int64_t xfs, double2 *y, int64_t ldy, int64_t yfs, hipStream_t s) {
+    const int64_t n = p->m.n;
+    const int tg = p->tune.mfma_tg, nb = p->tune.mfma_nb;
+    const int cbw = 16 * nb;
+    const int ncol = (nrhs + cbw - 1) / cbw * cbw;
+    const int grid = mfma_grid(tg, nb);
+    const int64_t want = static_cast<int64_t>(grid) * (kBlock / 64) * p->tune.items_per_wave;
+    const int64_t tiles = (n + 16 * tg - 1) / (16 * tg);
+    const int64_t items_per_chunk = static_cast<int64_t>(nf) * (ncol / cbw) * tiles;
+    auto chunking = [&](int64_t ns, int64_t &chunk, int &nc) {
+        if (ns <= 0) {
+            chunk = 4;
+            nc = 0;
+            return;
+        }
+        int64_t c = (want + items_per_chunk - 1) / items_per_chunk;
+        c = std::max<int64_t>(1, std::min<int64_t>(c, std::max<int64_t>(1, ns / 512)));
+        chunk = ((ns + c - 1) / c + 3) / 4 * 4;
+        nc = static_cast<int>((ns + chunk - 1) / chunk);
+    };
+    int64_t chG, chF;
+    int ncG, ncF;
+    chunking(p->G.count, chG, ncG);
+    chunking(p->F.count, chF, ncF);
+    const int parts = ncG + ncF;
+    const int64_t fstride = static_cast<int64_t>(parts) * nrhs * n;
+    double2 *part = static_cast<double2 *>(
+        p->partial.get(sizeof(double2) * static_cast<size_t>(std::max<int64_t>(1, fstride * nf))));
+    const int64_t ldqG = (p->G.count + kMfmaPad) * ncol, ldqF = (p->F.count + kMfmaPad) * ncol;
+    float2 *qG = static_cast<float2 *>(p->chargeG.get(sizeof(float2) * static_cast<size_t>(ldqG * nf)));
+    float2 *qF = static_cast<float2 *>(p->chargeF.get(sizeof(float2) * static_cast<size_t>(ldqF * nf)));
+    const double *kf = p->d_k0 + f0;
+    if (ncG > 0) {
+        launch_pack_mfma(kClassG, p->G, p->m.sp + static_cast<int64_t>(f0) * n, n, nf, nrhs, ncol, x, ldx, xfs,
+                         qG, ldqG, s);
+        MfmaJob J{kClassG, n, p->m.px, p->m.py, p->m.pz, p->G.count, p->G.pk, nullptr, qG, ldqG, ncol, nrhs,
+                  kf, nf, chG, ncG, part, fstride, 0, tg, nb, grid};
+        launch_mfma_forward(J, s, &p->prof);
+    }
+    if (ncF > 0) {
+        launch_pack_mfma(kClassF, p->F, nullptr, n, nf, nrhs, ncol, x, ldx, xfs, qF, ldqF, s);
+        MfmaJob J{kClassF, n, p->m.px, p->m.py, p->m.pz, p->F.count, p->F.pk, p->F.pv, qF, ldqF, ncol, nrhs,
+                  kf, nf, chF, ncF, part, fstride, ncG, tg, nb, grid};
+        launch_mfma_forward(J, s, &p->prof);
+    }
+    for (int t = 0; t < nf; ++t)
+        launch_reduce_partials(n, nrhs, parts, part + t * fstride, p->m.diag + static_cast<int64_t>(f0 + t) * n,
+                               false, x + t * xfs, ldx, y + t * yfs, ldy, nullptr, s);
+}
+
+void apply_forward_mfma(vsie_problem *p, int f0, int nf, int nrhs, const double2 *x, int64_t ldx, int64_t xfs,
+                        double2 *y, int64_t ldy, int64_t yfs, hipStream_t s) {
+    for (int r0 = 0; r0 < nrhs; r0 += kMfmaMaxCols) {
+        const int blk = std::min(kMfmaMaxCols, nrhs - r0);
+        apply_forward_mfma_block(p, f0, nf, blk, x + static_cast<int64_t>(r0) * ldx, ldx, xfs,
+                                 y + static_cast<int64_t>(r0) * ldy, ldy, yfs, s);
+    }
+}
+
+bool use_mfma(const vsie_problem *p, vsie_precision prec, int nrhs) {
+    return prec == VSIE_FP32 && p->tune.mfma_min_rhs > 0 && nrhs >= p->tune.mfma_min_rhs;
+}
+
+void check_tuning(const vsie_tuning &t) {
+    require(t.mfma_min_rhs >= 0, "mfma_min_rhs must be >= 0");
+    require((t.mfma_tg == 2 || t.mfma_tg == 4) && (t.mfma_nb == 1 || t.mfma_nb == 2) &&
+                mfma_variant_ok(t.mfma_tg, t.mfma_nb),
+            "unsupported (mfma_tg, mfma_nb)");
+    require(t.items_per_wave >= 1 && t.items_per_wave <= 4096, "items_per_wave must be in [1, 4096]");
+    require(t.vec_target_waves >= 1024 && t.vec_target_waves <= (int64_t(1) << 24),
+            "vec_target_waves must be in [1024, 2^24]");
+}
+
 void apply_op(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int nrhs,
               const double2 *x, int64_t ldx, double2 *y, int64_t ldy, hipStream_t s) {
     if (prec == VSIE_FP32 && p->dense[f].A) apply_dense(p, f, adjoint, nrhs, x, ldx, y, ldy, s);
     else if (adjoint) apply_adjoint(p, f, prec, nrhs, x, ldx, y, ldy, s);
+    else if (use_mfma(p, prec, nrhs)) apply_forward_mfma(p, f, 1, nrhs, x, ldx, 0, y, ldy, 0, s);
     else apply_forward(p, f, prec, nrhs, x, ldx, y, ldy, s);
 }
 
@@ -1283,6 +1386,131 @@ vsie_status vsie_matvec_adjoint(vsie_problem *p, int32_t f, vsie_precision prec,
     });
 }
 
+vsie_status vsie_matvec_multi(vsie_problem *p, int32_t f0, int32_t nf, vsie_precision prec, int64_t nrhs,
+                              const double *x, int64_t ldx, double *y, int64_t ldy, void *stream) {
+    return guarded([&] {
+        require(p != nullptr, "problem handle is NULL");
+        require(nf >= 1 && f0 >= 0 && static_cast<int64_t>(f0) + nf <= static_cast<int64_t>(p->k0.size()),
+                "frequency range out of bounds");
+        require(prec == VSIE_FP64 || prec == VSIE_FP32, "unknown precision");
+        require(nrhs >= 1 && nrhs <= 4096, "nrhs must be in [1, 4096]");
+        check_vec(x, ldx, p->m.n, "x");
+        check_vec(y, ldy, p->m.n, "y");
+        hipStream_t s = as_stream(stream);
+        const double2 *xv = reinterpret_cast<const double2 *>(x);
+        double2 *yv = reinterpret_cast<double2 *>(y);
+        const int R = static_cast<int>(nrhs);
+        bool dense = false;
+        for (int t = 0; t < nf; ++t) dense = dense || p->dense[f0 + t].A != nullptr;
+        if (use_mfma(p, prec, R) && !dense) {
+            apply_forward_mfma(p, f0, nf, R, xv, ldx, nrhs * ldx, yv, ldy, nrhs * ldy, s);
+            return;
+        }
+        for (int t = 0; t < nf; ++t)
+            apply_op(p, f0 + t, prec, false, R, xv + t * nrhs * ldx, ldx, yv + t * nrhs * ldy, ldy, s);
+    });
+}
+
+vsie_status vsie_get_tuning(const vsie_problem *p, vsie_tuning *out) {
+    return guarded([&] {
+        require(p != nullptr && out != nullptr, "NULL argument");
+        *out = p->tune;
+    });
+}
+
+vsie_status vsie_set_tuning(vsie_problem *p, const vsie_tuning *t) {
+    return guarded([&] {
+        require(p != nullptr && t != nullptr, "NULL argument");
+        check_tuning(*t);
+        p->tune = *t;
+    });
+}
+
+vsie_status vsie_autotune(vsie_problem *p, int32_t f, int64_t nrhs, vsie_tuning *best, void *stream) {
+    return guarded([&] {
+        check_problem(p, f);
+        require(nrhs >= 1 && nrhs <= 4096, "nrhs must be in [1, 4096]");
+        hipStream_t s = as_stream(stream);
+        const int64_t n = p->m.n;
+        const int R = static_cast<int>(nrhs);
+        struct Buf {
+            void *d = nullptr;
+            ~Buf() {
+                if (d) (void)hipFree(d);
+            }
+        } X, Y;
+        VSIE_HIP(hipMalloc(&X.d, sizeof(double2) * static_cast<size_t>(n) * R));
+        VSIE_HIP(hipMalloc(&Y.d, sizeof(double2) * static_cast<size_t>(n) * R));
+        double2 *xd = static_cast<double2 *>(X.d), *yd = static_cast<double2 *>(Y.d);
+        // inputs: plane waves along a spread of directions
+        for (int r = 0; r < R; ++r) {
+            const double t = (r + 0.5) / R, z = 1.0 - 2.0 * t, rho = std::sqrt(std::max(0.0, 1.0 - z * z));
+            const double ph = 2.399963229728653 * r;
+            launch_plane_wave(n, p->m.px, p->m.py, p->m.pz, p->k0[f], rho * std::cos(ph), rho * std::sin(ph), z,
+                              xd + static_cast<int64_t>(r) * n, s);
+        }
+        std::vector<vsie_tuning> cand;
+        const vsie_tuning base = p->tune;
+        for (int64_t tw : {16384, 32768, 65536}) {
+            vsie_tuning t = base;
+            t.mfma_min_rhs = 0;
+            t.vec_target_waves = tw;
+            cand.push_back(t);
+        }
+        if (R >= 8)
+            for (auto tn : {std::make_pair(2, 1), std::make_pair(4, 1), std::make_pair(2, 2)})
+                for (int ipw : {8, 16, 32}) {
+                    vsie_tuning t = base;
+                    t.mfma_min_rhs = std::min(8, R);
+                    t.mfma_tg = tn.first;
+                    t.mfma_nb = tn.second;
+                    t.items_per_wave = ipw;
+                    cand.push_back(t);
+                }
+        hipEvent_t e0, e1;
+        VSIE_HIP(hipEventCreate(&e0));
+        VSIE_HIP(hipEventCreate(&e1));
+        double best_ms = 1e300;
+        vsie_tuning pick = base;
+        const bool prof_on = p->prof.on;
+        p->prof.on = false;
+        try {
+            for (const auto &t : cand) {
+                p->tune = t;
+                auto run = [&] {
+                    if (use_mfma(p, VSIE_FP32, R)) apply_forward_mfma(p, f, 1, R, xd, n, 0, yd, n, 0, s);
+                    else apply_forward(p, f, VSIE_FP32, R, xd, n, yd, n, s);
+                };
+                run();  // warm-up (buffers, code objects)
+                VSIE_HIP(hipEventRecord(e0, s));
+                run();
+                run();
+                VSIE_HIP(hipEventRecord(e1, s));
+                VSIE_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                VSIE_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    pick = t;
+                }
+            }
+        } catch (...) {
+            p->tune = base;
+            p->prof.on = prof_on;
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            throw;
+        }
+        p->prof.on = prof_on;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        // the vector kernel won: keep the matrix cores for wider blocks only
+        if (pick.mfma_min_rhs == 0 && base.mfma_min_rhs > 0) pick.mfma_min_rhs = std::max(base.mfma_min_rhs, R + 1);
+        p->tune = pick;
+        if (best) *best = pick;
+    });
+}
+
 vsie_status vsie_solve(vsie_problem *p, int32_t f, vsie_precision prec, int32_t adjoint,
                        int64_t nrhs, const double *b, int64_t ldb, double *x, int64_t ldx,
                        const vsie_solve_opts *opts, vsie_solve_info *info, void *stream) {
@@ -1352,8 +1580,8 @@ vsie_status vsie_field(vsie_problem *p, int32_t f, vsie_precision prec, int64_t 
         const int64_t n = p->m.n;
         int64_t chG, chF;
         int ncG, ncF;
-        choose_chunks(n_t, p->G.count, chG, ncG);
-        choose_chunks(n_t, p->F.count, chF, ncF);
+        choose_chunks(n_t, p->G.count, p->tune.vec_target_waves, chG, ncG);
+        choose_chunks(n_t, p->F.count, p->tune.vec_target_waves, chF, ncF);
         double2 *part = static_cast<double2 *>(
             p->partial.get(sizeof(double2) * static_cast<size_t>(std::max(1, ncG + ncF)) * R * n_t));
         void *qG = p->chargeG.get(csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->G.count)) * R);
@@ -1399,7 +1627,7 @@ vsie_status vsie_source_sums(vsie_problem *p, int32_t f, int64_t n_t, const doub
         launch_pack_plain(VSIE_FP64, n_t, R, reinterpret_cast<const double2 *>(lam), ldl, true, q, s);
         int64_t ch;
         int nc;
-        choose_chunks(n, n_t, ch, nc);
+        choose_chunks(n, n_t, p->tune.vec_target_waves, ch, nc);
         double2 *part = static_cast<double2 *>(
             p->sums_part.get(sizeof(double2) * static_cast<size_t>(nc) * R * 4 * n));
         PairJob J{PAIR_SUMS, VSIE_FP64, n, p->m.px, p->m.py, p->m.pz, {}, n_t,
@@ -1507,7 +1735,7 @@ vsie_status vsie_profile(vsie_problem *p, int32_t enable) {
 vsie_status vsie_profile_read(vsie_problem *p, int32_t kind, vsie_kernel_stats *out) {
     return guarded([&] {
         require(p != nullptr && out != nullptr, "NULL argument");
-        require(kind >= 0 && kind < 8, "kernel kind out of range");
+        require(kind >= 0 && kind < 10, "kernel kind out of range");
         vsie_kernel_stats st{0, 0.0, 0.0, 0.0};
         for (auto &r : p->prof.recs) {
             if (r.kind != kind) continue;

@@ -59,7 +59,11 @@ struct SourceSet {
     int32_t *idx = nullptr;                 // canonical index of each class entry
     double *x = nullptr, *y = nullptr, *z = nullptr;    // FP64 centroids
     double *vx = nullptr, *vy = nullptr, *vz = nullptr; // v' (F class only)
+    // matrix-core layout: (x, y, z, 0) and (v'x, v'y, v'z, 0) per source, then
+    // kMfmaPad entries far from every point with v' = 0
+    double4 *pk = nullptr, *pv = nullptr;
 };
+constexpr int kMfmaPad = 8;
 
 // One pair-sum pass (pair_kernels.hip).  Thread points t (n_t) each sum over
 // a chunk of streamed points s (n_s); out receives one FP64 partial per
@@ -108,6 +112,44 @@ struct PairProfiler {
     std::vector<hipEvent_t> pool;
 };
 void launch_pairs(const PairJob &J, hipStream_t s, PairProfiler *prof = nullptr);
+hipEvent_t prof_take_event(PairProfiler *prof);
+
+// FP32 forward pair sums of one source class on the matrix cores
+// (mfma_kernels.hip), for nf frequencies and a block of right-hand sides in
+// one persistent launch.  Targets are the n_t collocation points.  Charges
+// are source-major, ncol (a multiple of 16 nb) columns per source,
+// q[fl * ldq_f + j * ncol + col], with kMfmaPad zero rows after n_s; chunk
+// is a multiple of 4.  Output, for
+// chunk c, column col < nrhs and target i:
+//   out[fl * out_fstride + (part0 + c) * nrhs * n_t + col * n_t + i].
+// tg: 16-target groups per wave (2 or 4); nb: 16-column blocks per item (1 or 2);
+// grid: workgroups (a multiple of 8; 0 = occupancy-filling).
+struct MfmaJob {
+    int cls;
+    int64_t n_t;
+    const double *tx, *ty, *tz;
+    int64_t n_s;
+    const double4 *pk, *pv;       // SourceSet::pk, pv
+    const float2 *q;
+    int64_t ldq_f;                // >= (n_s + kMfmaPad) ncol
+    int ncol, nrhs;
+    const double *kf;  // device array: k of each local frequency
+    int nf;
+    int64_t chunk;
+    int n_chunks;
+    double2 *out;
+    int64_t out_fstride;
+    int part0;
+    int tg, nb, grid;
+};
+void launch_mfma_forward(const MfmaJob &J, hipStream_t s, PairProfiler *prof);
+bool mfma_variant_ok(int tg, int nb);
+int mfma_grid(int tg, int nb);
+// q[fl * ldq_f + jj * ncol + col] = scale x[fl * xfs + col * ldx + idx[jj]] for col < nrhs, else 0;
+// scale = -s'_f for class G (sp + fl * sp_fstride), 1 for class F
+void launch_pack_mfma(SrcClass cls, const SourceSet &src, const double *sp, int64_t sp_fstride, int nf,
+                      int nrhs, int ncol, const double2 *x, int64_t ldx, int64_t xfs, float2 *q, int64_t ldq_f,
+                      hipStream_t s);
 
 // auxiliary kernels (aux_kernels.hip)
 void launch_weights(const DeviceMesh &m, const double *k0, int n_freq, hipStream_t s);

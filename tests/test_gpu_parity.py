@@ -13,6 +13,7 @@ import pytest
 
 import oracle as O
 import workloads as W
+from gpu_cases import CASES, case, dev, host, say
 
 pytestmark = pytest.mark.gpu
 
@@ -28,51 +29,6 @@ def V():
     import paper_2607_06429_amd as V
     return V
 
-
-def dev(a):
-    import torch
-    a = np.asarray(a, dtype=np.complex128)
-    if a.ndim == 1:
-        return torch.as_tensor(a, device="cuda")
-    return torch.as_tensor(np.ascontiguousarray(a.T), device="cuda")
-
-
-def host(t):
-    a = t.cpu().numpy()
-    return a if a.ndim == 1 else a.T
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
-
-
-def case(name):
-    """(mesh, materials, k0) of the small parity cases."""
-    if name == "c0":
-        m, mat, k0, _, _ = W.config_problem("c0")
-        return m, mat, k0[0]
-    if name == "ragged":          # 7^3 grid: n not a multiple of any tile
-        m = W.nested_balls(7)
-        return m, W.materials_piecewise(m, 1.0, 1.0, 1.2, 1.5, 2.0, 0.8), 3.0
-    if name == "lognormal":       # per-cell rho and c: grad alpha (T terms) active
-        m = W.nested_balls(10)
-        mat = W.materials_piecewise(m, 1.0, 1.0, 1.2, 1.5, 2.0, 0.8)
-        mat.vol_c = mat.vol_c * W.lognormal_voxel_field(m.vol_xyz, -1, 1, 32, 0.1, 0)
-        mat.vol_rho = mat.vol_rho * W.lognormal_voxel_field(m.vol_xyz, -1, 1, 32, 0.1, 1)
-        return m, mat, 5.0
-    if name == "single":          # Omega_2 with Omega_1's material
-        m = W.nested_balls(9)
-        return m, W.materials_piecewise(m, 1.0, 1.0, 1.4, 1.3, 1.4, 1.3), 2.5
-    if name == "cube":            # cube + ellipsoid, small grid
-        m = W.cube_with_ellipsoid(12)
-        mat = W.materials_piecewise(m, 1.0, 1.0, 1.1, 1.3, 2.0, 0.8)
-        mat.vol_c = mat.vol_c * W.lognormal_voxel_field(m.vol_xyz, -0.5, 0.5, 32, 0.1, 0)
-        return m, mat, 12.0
-    raise KeyError(name)
-
-
-CASES = ["c0", "ragged", "lognormal", "single", "cube"]
 
 
 @pytest.mark.parametrize("name", CASES)

@@ -1,14 +1,25 @@
-"""Count VALU instructions per pair in the compiled pair-kernel inner loops.
+"""Count instructions and SIMD issue cycles per pair in the compiled pair
+kernels' inner loops.
 
     python paper_2607_06429_amd/isa_count.py
 
-Compiles csrc/pair_kernels.hip to gfx950 assembly (the same flags as the
-library build) and, for each kernel variant, finds the innermost loop that
-evaluates the most pairs per trip (the unrolled steady-state loop; one v_rsq
-per pair), counts its vector
-ALU instructions and divides by the number of pairs per trip (the number of
-v_rsq instructions in the loop).  Writes isa_counts.json beside this file;
-bench.py reads it to convert measured pair rates into VALU lane-operations.
+Compiles csrc/pair_kernels.hip and csrc/mfma_kernels.hip to gfx950 assembly
+(the same flags as the library build) and, for each kernel variant, finds the
+innermost loop that evaluates the most pairs per trip (the unrolled
+steady-state loop; one v_rsq per pair and lane), counts its instructions and
+divides by the pairs per trip.
+
+Issue-cycle model (SIMD cycles one wave64 instruction occupies; the chip has
+256 CUs x 4 SIMDs at 2.4 GHz):
+  FP32 and 32-bit integer VALU      2   (157.3 TFLOP/s FP32 = 64 FLOP/cycle/SIMD)
+  FP64 and 64-bit integer VALU      4   (78.6 TFLOP/s FP64)
+  FP32 transcendental (rsq sin cos) 8   (quarter of the FP32 rate)
+  FP64 transcendental (rsq_f64)    16
+  v_mfma_f32_16x16x4_f32           32   (2048 FLOP at 64 FLOP/cycle/SIMD)
+Microbenchmarks on MI355X give 2.5-2.8, 4.4-5.8, 8.5, 16.3 and 32.5 cycles
+with 8 independent chains per lane, and show matrix-core and VALU time adding
+up (no overlap) for FP32.  Writes isa_counts.json beside this file; bench.py
+reads it to turn measured pair rates into issue cycles per second.
 """
 from __future__ import annotations
 
@@ -27,12 +38,25 @@ import build as B  # noqa: E402
 MODES = {0: "fwd_single_layer", 1: "fwd_double_layers", 2: "adj_double_layers", 3: "source_sums"}
 
 
-def assemble() -> str:
-    out = os.path.join(tempfile.mkdtemp(), "pair.s")
+def assemble(src: str) -> str:
+    out = os.path.join(tempfile.mkdtemp(), src + ".s")
     cmd = [B._hipcc(), *B.FLAGS, "--cuda-device-only", "-S",
-           os.path.join(B.CSRC, "pair_kernels.hip"), "-o", out]
+           os.path.join(B.CSRC, src), "-o", out]
     subprocess.run(cmd, check=True, capture_output=True)
     return open(out).read()
+
+
+def cycles(op: str) -> int:
+    """Issue cycles of one wave64 instruction (the model above)."""
+    if op.startswith("v_mfma"):
+        return 32
+    if re.match(r"v_(rsq|rcp|sqrt)_f64", op):
+        return 16
+    if re.match(r"v_(rsq|sin|cos|rcp|sqrt|exp|log)_", op):
+        return 8
+    if re.search(r"_(f64|u64|i64|b64)", op) or op.startswith("v_mad_u64") or op.startswith("v_mad_i64"):
+        return 4
+    return 2
 
 
 def inner_loops(body_lines):
@@ -54,10 +78,19 @@ def inner_loops(body_lines):
             if not any(a < a2 <= b and (a2, b2) != (a, b) for a2, b2 in loops)]
 
 
-def count(asm: str) -> dict:
-    res = {}
+def kernels(asm: str):
+    """(symbol, result key, right-hand sides per trip) of every pair kernel."""
     for nm in re.findall(r"^(_Z\w+pair_sum_kernel\w+):", asm, re.M):
         mode, R, acc = re.search(r"kernelILi(\d)ELi(\d+)Ed(\w)", nm).groups()
+        yield nm, "%s_%s_R%s" % (MODES[int(mode)], "fp64" if acc == "d" else "fp32", R), int(R)
+    for nm in re.findall(r"^(_Z\w+mfma_fwd_kernel\w+):", asm, re.M):
+        cls, tg, nb = re.search(r"kernelILi(\d)ELi(\d)ELi(\d)E", nm).groups()
+        yield nm, "mfma_%s_fp32_tg%s_nb%s" % (MODES[int(cls)], tg, nb), 16 * int(nb)
+
+
+def count(asm: str) -> dict:
+    res = {}
+    for nm, key, R in kernels(asm):
         i = asm.index(nm + ":")
         lines = asm[i:asm.index(".Lfunc_end", i)].split("\n")
         best = None
@@ -77,6 +110,10 @@ def count(asm: str) -> dict:
         for x in body:
             op = x.split()[0]
             if op.startswith("v_"):
+                c["cycles"] += cycles(op)
+            if op.startswith("v_mfma"):
+                c["mfma"] += 1
+            elif op.startswith("v_"):
                 c["valu"] += 1
                 if re.match(r"v_(rsq|sin|cos|rcp|sqrt|exp|log)", op):
                     c["trans"] += 1
@@ -86,8 +123,10 @@ def count(asm: str) -> dict:
                 c["smem"] += 1
             elif op.startswith("s_"):
                 c["salu"] += 1
-        key = "%s_%s_R%s" % (MODES[int(mode)], "fp64" if acc == "d" else "fp32", R)
         res[key] = {"pairs_per_trip": nrsq,
+                    "rhs_per_trip": R,
+                    "cycles_per_pair": c["cycles"] / (64.0 * nrsq),
+                    "mfma_per_pair": c["mfma"] / nrsq,
                     "valu_per_pair": c["valu"] / nrsq,
                     "f64_per_pair": c["f64"] / nrsq,
                     "trans_per_pair": c["trans"] / nrsq,
@@ -97,7 +136,8 @@ def count(asm: str) -> dict:
 
 
 def main():
-    res = count(assemble())
+    res = count(assemble("pair_kernels.hip"))
+    res.update(count(assemble("mfma_kernels.hip")))
     out = os.path.join(HERE, "isa_counts.json")
     with open(out, "w") as f:
         json.dump(res, f, indent=1, sort_keys=True)

@@ -49,7 +49,28 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched workloads")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="before the steps, copy MIB MiB device-to-device three times (a kernel of "
+                         "known traffic for scaling HBM byte counters)")
     return ap.parse_args()
+
+
+def measured_traffic(key):
+    """HBM bytes per launch of a pair kernel from the rocprofv3 FETCH_SIZE and
+    WRITE_SIZE runs (scaled by the same counters' reading for a copy of known
+    size), or None when no record exists or the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "paper_2607_06429_amd", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(key)
+    if rec is None:
+        return None
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return rec["hbm_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
 
 
 def batched_workloads(V, W):
@@ -161,6 +182,13 @@ def main():
         x, info = P.solve(b, prec=prec, tol=TOL)    # GMRES (+ refinement)
         return x, info
 
+    if args.calibrate_copy > 0:
+        src = torch.empty(args.calibrate_copy << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step(V.VSIE_FP32)
     torch.cuda.synchronize()
@@ -214,7 +242,7 @@ def main():
     achieved = per_pair * pairs_launch / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": dom_name, "achieved": achieved,
                 "peak": ISSUE_PEAK / 1e12, "unit": "T SIMD issue-cycles/s", "frac": achieved / (ISSUE_PEAK / 1e12),
-                "traffic": None, "cycles_per_pair": per_pair,
+                "traffic": measured_traffic(dom_name + "_R1"), "cycles_per_pair": per_pair,
                 "valu_per_pair": counts[dom_name + "_R1"]["valu_per_pair"], "avg_launch_ms": avg_ms,
                 "launches": st["launches"], "pairs_per_launch": pairs_launch,
                 "gpairs_per_s": pairs_launch / (avg_ms * 1e-3) / 1e9}

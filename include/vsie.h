@@ -150,6 +150,12 @@ typedef struct {
                                   sets the source chunk length (>= 1); default 16 */
     int64_t vec_target_waves;  /* waves per vector pair launch, which sets its source
                                   chunk length (>= 1024); default 32768 */
+    int32_t graph;             /* 1: inside vsie_solve, each operator application of
+                                  the matrix-free paths (pack, pair and reduction
+                                  launches) is captured once into a hipGraph and
+                                  replayed every iteration; 0: launched one by one;
+                                  default 1 */
+    int32_t reserved;          /* must be 0 */
 } vsie_tuning;
 
 vsie_status vsie_get_tuning(const vsie_problem *p, vsie_tuning *out);

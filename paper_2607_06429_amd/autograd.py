@@ -20,13 +20,13 @@ from . import VSIE_FP64, Problem
 class ReceiverPressure(torch.autograd.Function):
     @staticmethod
     def forward(ctx, c, rho, problem: Problem, n_vol: int, dirs, receivers, f: int, prec: int,
-                tol: float):
+                tol: float, block: bool):
         problem.set_materials(rho.detach().contiguous(), c.detach().contiguous())
         b = problem.plane_wave(np.atleast_2d(dirs), f=f)
-        P, info = problem.solve(b, f=f, prec=prec, tol=tol)
+        P, info = problem.solve(b, f=f, prec=prec, tol=tol, block=block)
         p_rec = problem.plane_wave_at(receivers, dirs, f=f) - problem.field(receivers, P, f=f)
-        ctx.problem, ctx.n_vol, ctx.receivers, ctx.f, ctx.prec, ctx.tol = (
-            problem, n_vol, receivers, f, prec, tol)
+        ctx.problem, ctx.n_vol, ctx.receivers, ctx.f, ctx.prec, ctx.tol, ctx.block = (
+            problem, n_vol, receivers, f, prec, tol, block)
         ctx.info = info
         ctx.save_for_backward(P)
         return p_rec
@@ -38,13 +38,15 @@ class ReceiverPressure(torch.autograd.Function):
         resid = grad_out.contiguous()
         zR, ZR = pb.source_sums(resid, f=ctx.f, targets=ctx.receivers)
         rhs = pb.adjoint_rhs(zR, ZR, f=ctx.f)
-        lam, _ = pb.solve(rhs, f=ctx.f, prec=ctx.prec, adjoint=True, tol=ctx.tol)
+        lam, ctx.adj_info = pb.solve(rhs, f=ctx.f, prec=ctx.prec, adjoint=True, tol=ctx.tol, block=ctx.block)
         z, Z = pb.source_sums(lam, f=ctx.f)
         gc, grho = pb.param_gradient(P, lam, z, Z, zR, ZR, ctx.n_vol, f=ctx.f)
-        return gc, grho, None, None, None, None, None, None, None
+        return gc, grho, None, None, None, None, None, None, None, None
 
 
 def receiver_pressure(problem: Problem, n_vol: int, c, rho, dirs, receivers, f=0, prec=VSIE_FP64,
-                      tol=1e-12):
-    """Receiver pressures (Q, n_rec) for Q plane waves; differentiable in c, rho."""
-    return ReceiverPressure.apply(c, rho, problem, n_vol, np.atleast_2d(dirs), receivers, f, prec, tol)
+                      tol=1e-12, block=False):
+    """Receiver pressures (Q, n_rec) for Q plane waves; differentiable in c, rho.
+    block selects block GMRES for the forward and adjoint solves."""
+    return ReceiverPressure.apply(c, rho, problem, n_vol, np.atleast_2d(dirs), receivers, f, prec, tol,
+                                  block)

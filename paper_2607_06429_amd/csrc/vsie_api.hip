@@ -1,6 +1,7 @@
 // C ABI of libvsie.so: validation, device data, operator application and the
 // GMRES solver with FP64 iterative refinement.  See include/vsie.h.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -31,6 +32,12 @@ void check_hip(hipError_t e, const char *what) {
     fail(code, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Epoch of every device address a captured operator graph may hold: bumped
+// whenever a work buffer is reallocated or a problem's sources, tuning or
+// assembled operators change.  A graph captured in an older epoch is never
+// launched again.
+std::atomic<uint64_t> g_graph_epoch{0};
+
 // Grow-only device buffer.
 struct Scratch {
     void *p = nullptr;
@@ -44,6 +51,7 @@ struct Scratch {
         }
         p = nullptr;
         bytes = 0;
+        ++g_graph_epoch;
         VSIE_HIP(hipMalloc(&p, b));
         bytes = b;
         return p;
@@ -91,7 +99,7 @@ struct vsie_problem {
     Scratch V, V2, w, r, ax, h1, h2, tc, nrm, dpart, npart, yv, act, act2, live, kd, kc, xa, axa, rres;
     Scratch bh, bg, bsk;  // block GMRES: Hessenberg block column, Gram / inverse factor, slab partials
     PairProfiler prof;
-    vsie_tuning tune{8, 2, 1, 16, 32768};
+    vsie_tuning tune{8, 2, 1, 16, 32768, 1, 0};
     // dense FP32 off-diagonal operator per frequency (caller-owned memory)
     struct Dense {
         float2 *A = nullptr;
@@ -100,6 +108,27 @@ struct vsie_problem {
     std::vector<Dense> dense;
     rocblas_handle blas = nullptr;
     Scratch dense_x, dense_part;
+    // captured operator applications (vsie_tuning::graph), keyed by their arguments
+    struct OpGraph {
+        int f, prec, nrhs;
+        bool adjoint;
+        const double2 *x;
+        int64_t ldx;
+        double2 *y;
+        int64_t ldy;
+        uint64_t epoch;
+        hipGraph_t g;
+        hipGraphExec_t e;
+    };
+    std::vector<OpGraph> graphs;
+    hipStream_t capture_stream = nullptr;  // graphs are captured here and launched on the caller's stream
+    void clear_graphs() {
+        for (auto &q : graphs) {
+            if (q.e) (void)hipGraphExecDestroy(q.e);
+            if (q.g) (void)hipGraphDestroy(q.g);
+        }
+        graphs.clear();
+    }
 
     template <typename T>
     T *alloc(int64_t count) {
@@ -127,6 +156,8 @@ struct vsie_problem {
         S = SourceSet{};
     }
     ~vsie_problem() {
+        clear_graphs();
+        if (capture_stream) (void)hipStreamDestroy(capture_stream);
         for (auto &r : prof.recs) {
             (void)hipEventDestroy(r.a);
             (void)hipEventDestroy(r.b);
@@ -515,6 +546,8 @@ void check_tuning(const vsie_tuning &t) {
     require(t.items_per_wave >= 1 && t.items_per_wave <= 4096, "items_per_wave must be in [1, 4096]");
     require(t.vec_target_waves >= 1024 && t.vec_target_waves <= (int64_t(1) << 24),
             "vec_target_waves must be in [1024, 2^24]");
+    require(t.graph == 0 || t.graph == 1, "graph must be 0 or 1");
+    require(t.reserved == 0, "reserved must be 0");
 }
 
 void apply_op(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int nrhs,
@@ -523,6 +556,57 @@ void apply_op(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int nrh
     else if (adjoint) apply_adjoint(p, f, prec, nrhs, x, ldx, y, ldy, s);
     else if (use_mfma(p, prec, nrhs)) apply_forward_mfma(p, f, 1, nrhs, x, ldx, 0, y, ldy, 0, s);
     else apply_forward(p, f, prec, nrhs, x, ldx, y, ldy, s);
+}
+
+// apply_op through a hipGraph of its launches, for the fixed work buffers the
+// solver applies the operator to every iteration.  The first call with a key
+// runs eagerly (which sizes every work buffer and gives this call's product)
+// and then captures the same launches; later calls launch the graph.  The
+// matrix-free paths launch kernels only (no memset or copy nodes).  Profiled
+// products and the assembled (rocBLAS) path stay eager.
+constexpr size_t kMaxGraphs = 16;
+
+void apply_op_graph(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int nrhs,
+                    const double2 *x, int64_t ldx, double2 *y, int64_t ldy, hipStream_t s) {
+    if (!p->tune.graph || p->prof.on || (prec == VSIE_FP32 && p->dense[f].A)) {
+        apply_op(p, f, prec, adjoint, nrhs, x, ldx, y, ldy, s);
+        return;
+    }
+    const uint64_t ep = g_graph_epoch.load();
+    for (auto &q : p->graphs)
+        if (q.epoch != ep) {
+            p->clear_graphs();
+            break;
+        }
+    for (auto &q : p->graphs)
+        if (q.f == f && q.prec == prec && q.adjoint == adjoint && q.nrhs == nrhs && q.x == x && q.ldx == ldx &&
+            q.y == y && q.ldy == ldy) {
+            VSIE_HIP(hipGraphLaunch(q.e, s));
+            return;
+        }
+    apply_op(p, f, prec, adjoint, nrhs, x, ldx, y, ldy, s);
+    if (g_graph_epoch.load() != ep) return;  // buffers were resized on the way: capture next time
+    if (p->graphs.size() >= kMaxGraphs) p->clear_graphs();
+    // the caller's stream may be the legacy null stream, which cannot be captured
+    if (!p->capture_stream) VSIE_HIP(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
+    hipStream_t cs = p->capture_stream;
+    VSIE_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipGraph_t g = nullptr;
+    try {
+        apply_op(p, f, prec, adjoint, nrhs, x, ldx, y, ldy, cs);
+    } catch (...) {
+        (void)hipStreamEndCapture(cs, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    VSIE_HIP(hipStreamEndCapture(cs, &g));
+    hipGraphExec_t e = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        check_hip(ie, "hipGraphInstantiate");
+    }
+    p->graphs.push_back(vsie_problem::OpGraph{f, static_cast<int>(prec), nrhs, adjoint, x, ldx, y, ldy, ep, g, e});
 }
 
 // ---------------------------------------------------------------------------
@@ -719,7 +803,7 @@ int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
         to_device(live_d, live_rhs, s);
         // W = A v_k for the live right-hand sides
         bblas_gather(n, nl, live_d, V + static_cast<int64_t>(k) * R * n, n, X, s);
-        apply_op(p, f, prec, adjoint, nl, X, n, W, n, s);
+        apply_op_graph(p, f, prec, adjoint, nl, X, n, W, n, s);
         for (int r : live_rhs) (prec == VSIE_FP64 ? cnt.mv64 : cnt.mv32)[r]++;
         if (use && kmax > 0) to_device(kc_d, live_kc, s);
         for (int pass = 0; pass < 2; ++pass) {
@@ -897,7 +981,7 @@ vsie_status solve_batch(vsie_problem *p, int f, vsie_precision prec, bool adjoin
         for (int r : active) any_x = any_x || !xzero[r];
         if (any_x) {
             bblas_gather(n, na, act, x, ldx, Xa, s);
-            apply_op(p, f, VSIE_FP64, adjoint, na, Xa, n, AX, n, s);
+            apply_op_graph(p, f, VSIE_FP64, adjoint, na, Xa, n, AX, n, s);
             for (int r : active) cnt.mv64[r]++;
             bblas_sub(n, na, act, b, ldb, AX, Rres, s);
         } else {
@@ -1356,6 +1440,7 @@ vsie_status vsie_set_materials(vsie_problem *p, const double *vrho_dev, const do
         build_sources(p);
         // assembled operators describe the old materials
         for (auto &d : p->dense) d = vsie_problem::Dense{};
+        ++g_graph_epoch;
     });
 }
 
@@ -1423,6 +1508,7 @@ vsie_status vsie_set_tuning(vsie_problem *p, const vsie_tuning *t) {
         require(p != nullptr && t != nullptr, "NULL argument");
         check_tuning(*t);
         p->tune = *t;
+        ++g_graph_epoch;
     });
 }
 
@@ -1507,6 +1593,7 @@ vsie_status vsie_autotune(vsie_problem *p, int32_t f, int64_t nrhs, vsie_tuning 
         // the vector kernel won: keep the matrix cores for wider blocks only
         if (pick.mfma_min_rhs == 0 && base.mfma_min_rhs > 0) pick.mfma_min_rhs = std::max(base.mfma_min_rhs, R + 1);
         p->tune = pick;
+        ++g_graph_epoch;
         if (best) *best = pick;
     });
 }
@@ -1707,6 +1794,7 @@ vsie_status vsie_assemble_dense(vsie_problem *p, int32_t f, void *dense, int64_t
         launch_assemble_dense(p->m.n, p->m.px, p->m.py, p->m.pz, p->m.sp + static_cast<int64_t>(f) * p->m.n,
                               vp[0], vp[1], vp[2], p->k0[f], static_cast<float2 *>(dense), ld, s);
         p->dense[f] = vsie_problem::Dense{static_cast<float2 *>(dense), ld};
+        ++g_graph_epoch;
     });
 }
 
@@ -1714,6 +1802,7 @@ vsie_status vsie_release_dense(vsie_problem *p, int32_t f) {
     return guarded([&] {
         check_problem(p, f);
         p->dense[f] = vsie_problem::Dense{};
+        ++g_graph_epoch;
     });
 }
 

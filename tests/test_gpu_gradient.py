@@ -118,3 +118,56 @@ def test_adjoint_rhs_and_source_sums_match_oracle(V):
                    for j in range(d.n)], axis=1)
     ref = E.conj().T @ rho
     assert O.rel_error(rhs, ref) < 1e-12
+
+
+def test_c3_gradient_full_size_finite_differences(V):
+    """The c3 workload at full size (c1 mesh, n = 71,368, log-normal c and rho,
+    k0 = 10, 8 incidences, 256 receivers on |x| = 3; data = receiver pressures
+    of the unperturbed c1 medium).  The adjoint gradient against central
+    differences of the misfit on 16 seeded cells x {c, rho}; every misfit
+    evaluation is an FP64 GPU solve to relative residual 1e-13, and the step is
+    1e-3 of the parameter (truncation ~1e-6 relative, solve noise ~1e-6)."""
+    import torch
+    from paper_2607_06429_amd.autograd import receiver_pressure
+    mesh, mat, k0s, dirs, rec = W.config_problem("c3")
+    mesh1, mat1, _, _, _ = W.config_problem("c1")
+    k0 = k0s[0]
+    P = V.Problem.from_mesh(mesh, mat, [k0])
+    say("c3 gradient: n", P.n, "incidences", len(dirs), "receivers", len(rec))
+
+    def pressures(c, rho, tol=1e-13):
+        P.set_materials(torch.as_tensor(rho, device="cuda"), torch.as_tensor(c, device="cuda"))
+        b = P.plane_wave(dirs)
+        x, info = P.solve(b, prec=V.VSIE_FP64, tol=tol, block=True)
+        assert info["status"] == V.VSIE_OK
+        return P.plane_wave_at(rec, dirs) - P.field(rec, x)
+
+    data = pressures(mat1.vol_c, mat1.vol_rho)
+    c = torch.tensor(mat.vol_c, device="cuda", requires_grad=True)
+    rho = torch.tensor(mat.vol_rho, device="cuda", requires_grad=True)
+    pr = receiver_pressure(P, mesh.n_vol, c, rho, dirs, rec, tol=1e-13, block=True)
+    loss = 0.5 * (pr - data).abs().pow(2).sum()
+    loss.backward()
+    gc, gr = c.grad.cpu().numpy(), rho.grad.cpu().numpy()
+
+    def misfit(cv, rv):
+        return float(0.5 * (pressures(cv, rv) - data).abs().pow(2).sum())
+
+    cells = np.random.default_rng(2607).choice(mesh.n_vol, 16, replace=False)
+    out = {}
+    for which, g in (("c", gc), ("rho", gr)):
+        fdv = []
+        for j in cells:
+            vals = []
+            for sgn in (1, -1):
+                cv, rv = mat.vol_c.copy(), mat.vol_rho.copy()
+                arr = cv if which == "c" else rv
+                h = 1e-3 * arr[j]
+                arr[j] += sgn * h
+                vals.append(misfit(cv, rv))
+            fdv.append((vals[0] - vals[1]) / (2 * h))
+        fdv = np.array(fdv)
+        out[which] = O.rel_error(g[cells], fdv)
+        say("  grad %s: rel err vs central differences %.2e (|fd| max %.3e)" % (which, out[which], np.abs(fdv).max()))
+    assert out["c"] < 1e-4 and out["rho"] < 1e-4
+    P.close()

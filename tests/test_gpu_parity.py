@@ -353,3 +353,80 @@ def test_block_gmres_dense_adjoint(V):
     assert info["status"] == V.VSIE_OK
     assert O.rel_error(host(x), ref) <= TOL_SOLVE
     del A
+
+
+# ---------------------------------------------------------------------------
+# hipGraph replay of the operator applications inside the solver
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_graph_replay_solve(V, prec):
+    """With tuning graph=1 every operator application of the solve after the
+    first is a replay of a captured hipGraph, with the solver's own eager
+    kernels and host synchronisations between replays.  The graph holds the
+    same kernels in the same order, so solves must match the eager ones
+    bitwise, over several solves in a row (forward, adjoint, the matrix-core
+    path); new materials and tuning changes must retire the graphs."""
+    import time
+    import torch
+    say("graph replay", prec)
+    mesh, mat, k0 = case("lognormal")
+    d = O.discretise(mesh, mat, k0)
+    P = V.Problem.from_mesh(mesh, mat, [k0])
+    pr = V.VSIE_FP64 if prec == "fp64" else V.VSIE_FP32
+    b = P.plane_wave(W.fibonacci_sphere(3))
+    P.set_tuning(graph=0)
+    t0 = time.perf_counter()
+    x0, i0 = P.solve(b, prec=pr, tol=1e-11, restart=20)
+    a0, j0 = P.solve(b, prec=pr, adjoint=True, tol=1e-11)
+    torch.cuda.synchronize()
+    te = time.perf_counter() - t0
+    P.set_tuning(graph=1)
+    for rep in range(3):
+        t0 = time.perf_counter()
+        x1, i1 = P.solve(b, prec=pr, tol=1e-11, restart=20)
+        a1, j1 = P.solve(b, prec=pr, adjoint=True, tol=1e-11)
+        torch.cuda.synchronize()
+        say("  replay %d: eager %.1f ms, graph %.1f ms" % (rep, te * 1e3, (time.perf_counter() - t0) * 1e3))
+        assert i1 == i0 and j1 == j0
+        assert torch.equal(x1, x0) and torch.equal(a1, a0)
+    # new materials: graphs captured for the old sources must not be replayed
+    mat2 = W.materials_piecewise(mesh, 1.0, 1.0, 1.3, 1.4, 1.9, 0.9)
+    P.set_materials(torch.as_tensor(mat2.vol_rho, device="cuda"), torch.as_tensor(mat2.vol_c, device="cuda"))
+    d2 = O.discretise(mesh, mat2, k0)
+    x2, _ = P.solve(b, prec=pr, tol=1e-11)
+    assert O.rel_error(host(x2), O.solve_lu(d2, host(b))) <= TOL_SOLVE
+    # blocks of 8 columns: the matrix-core path on FP32, captured as well
+    b8 = P.plane_wave(W.fibonacci_sphere(8))
+    P.set_tuning(graph=0)
+    y0, k_0 = P.solve(b8, prec=pr, tol=1e-11)
+    P.set_tuning(graph=1)
+    for rep in range(2):
+        y1, k_1 = P.solve(b8, prec=pr, tol=1e-11)
+        assert k_1 == k_0 and torch.equal(y1, y0)
+    assert O.rel_error(host(y1), O.solve_lu(d2, host(b8))) <= TOL_SOLVE
+    P.close()
+
+
+def test_graph_small_problem_timing(V):
+    """c0 (n = 3,736), FP64 and FP32: solve time with and without graphs
+    (reported), identical solutions."""
+    import time
+    import torch
+    mesh, mat, k0s, dirs, _ = W.config_problem("c0")
+    P = V.Problem.from_mesh(mesh, mat, k0s)
+    b = P.plane_wave(dirs[0])
+    for pr in (V.VSIE_FP64, V.VSIE_FP32):
+        res = {}
+        for g in (0, 1):
+            P.set_tuning(graph=g)
+            x, info = P.solve(b, prec=pr, tol=1e-10)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                x, info = P.solve(b, prec=pr, tol=1e-10)
+            torch.cuda.synchronize()
+            res[g] = ((time.perf_counter() - t0) / 3, x)
+        say("  c0 prec %d: eager %.2f ms, graph %.2f ms (%d iterations)"
+            % (pr, res[0][0] * 1e3, res[1][0] * 1e3, info["iterations"]))
+        assert torch.equal(res[0][1], res[1][1])
+    P.close()

@@ -155,7 +155,11 @@ typedef struct {
                                   launches) is captured once into a hipGraph and
                                   replayed every iteration; 0: launched one by one;
                                   default 1 */
-    int32_t reserved;          /* must be 0 */
+    int32_t sym_groups;        /* one-column forward products: when every cell is a
+                                  single-layer source, the cell-cell single layer runs
+                                  once per unordered pair (e_ij = e_ji), in work items
+                                  of sym_groups x sym_groups 64-cell tiles; 0 = off,
+                                  2, 4 or 8; default 4 */
 } vsie_tuning;
 
 vsie_status vsie_get_tuning(const vsie_problem *p, vsie_tuning *out);
@@ -285,7 +289,8 @@ vsie_status vsie_release_dense(vsie_problem *p, int32_t f);
  * double layers (T and K), 2 adjoint double layers, 3 adjoint source sums,
  * and precision VSIE_FP64 or VSIE_FP32; kind 8 and 9 are the matrix-core
  * forward single layer and double layers (FP32; a launch over nf frequencies
- * counts nf times its pairs). */
+ * counts nf times its pairs); kind 10 and 11 the symmetric cell-cell single
+ * layer in FP64 and FP32 (pairs = ordered cell pairs, n_vol (n_vol - 1)). */
 typedef struct {
     int64_t launches;
     double ms;

@@ -1,0 +1,338 @@
+// Single-layer sums between volume cells, one kernel evaluation per
+// unordered pair (one right-hand side).
+//
+// The single-layer term of the operator pairs every cell i with every cell j
+// through e_ij = exp(i k r)/r, which is symmetric (paper: the midpoint rule
+// applied to eq_vsie; G(r) depends on |x_i - y_j| only).  With charges
+// u_j = -s'_j x_j the two contributions of a pair are
+//   y_i += e_ij u_j   and   y_j += e_ij u_i,
+// so one evaluation of e_ij (the FP64 distance and phase and the sine and
+// cosine, which dominate the cost) serves both.
+//
+// Lanes and rotation: a wave pairs a 64-point tile A with a 64-point tile B.
+// Lane l keeps point a_l (position, charge, accumulator).  In step k it meets
+// B point (l - k) mod 64: the B positions and charges sit in the wave's own
+// LDS slice (written once per tile pair; the LDS executes one wave's
+// operations in order, so no barrier is needed), and the B point's
+// source-side accumulator moves one lane along the wave after every step
+// (DPP wavefront rotate).  After 64 steps each B accumulator is back in its
+// home lane: both sides are lane-local, with no cross-lane reduction and no
+// atomics.  A tile paired with itself runs 63 steps with the target side
+// only.
+//
+// Work: the tiles are grouped G at a time.  A work item is a pair of groups
+// (I, J), I <= J, and covers every tile pair between them (for I = J the
+// tile pairs ta <= tb).  The points of group I receive their partial sum
+// from the item in slot J and the points of group J in slot I, so every cell
+// gets exactly one partial per group: part[slot * ldp + p].  A reduction
+// kernel adds them in slot order (deterministic).
+//
+// Schedule: persistent grid, items cut into 8 contiguous ranges (one per
+// XCD, workgroup b runs on XCD b mod 8), every wave takes every W-th item of
+// its range.
+#include "pair_geom.h"
+#include "vsie_internal.h"
+
+namespace vsie {
+namespace {
+
+using namespace geom;
+
+constexpr int kXcds = 8;
+constexpr int kWavesPerBlock = kBlock / 64;
+constexpr int kDppWaveRor1 = 0x13C;  // DPP control: rotate the whole wave right by one lane
+
+// every lane has a source lane under a whole-wave rotate, so no "old" value is needed
+__device__ __forceinline__ float rot1(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), kDppWaveRor1, 0xF, 0xF, true));
+}
+__device__ __forceinline__ double rot1(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp(static_cast<int>(b), kDppWaveRor1, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(static_cast<int>(b >> 32), kDppWaveRor1, 0xF, 0xF, true);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+template <typename AT> struct c2_of;
+template <> struct c2_of<double> { using type = double2; };
+template <> struct c2_of<float> { using type = float2; };
+
+struct SymArgs {
+    int64_t ng;                     // cells (canonical points 0 .. ng-1)
+    const double *__restrict__ px;
+    const double *__restrict__ py;
+    const double *__restrict__ pz;
+    const void *__restrict__ q;     // charges u, complex AT, ng entries
+    double k;
+    double kphase;                  // k/pi (FP64: half turns) or k/(2 pi) (FP32: turns)
+    double far[3];                  // padding position, farther than the mesh extent from every point
+    double far_step;                // distance between padding positions
+    int tiles;
+    int groups;
+    int64_t items;
+    double2 *__restrict__ part;
+    int64_t ldp;
+};
+
+// position and charge of point p of a tile (padding lanes: distinct far points, zero charge)
+template <typename AT>
+__device__ __forceinline__ void load_point(const SymArgs &a, int64_t p, int lane, double &x, double &y,
+                                           double &z, AT &ur, AT &ui) {
+    using C2 = typename c2_of<AT>::type;
+    if (p < a.ng) {
+        x = a.px[p];
+        y = a.py[p];
+        z = a.pz[p];
+        const C2 u = static_cast<const C2 *>(a.q)[p];
+        ur = u.x;
+        ui = u.y;
+    } else {
+        x = a.far[0] + a.far_step * lane;
+        y = a.far[1];
+        z = a.far[2];
+        ur = 0;
+        ui = 0;
+    }
+}
+
+template <typename AT>
+__device__ __forceinline__ void pair_e(double dx, double dy, double dz, const SymArgs &a, AT kk, AT &er, AT &ei) {
+    AT ir2, kr;
+    if constexpr (sizeof(AT) == 4) geom_f32<false>(dx, dy, dz, kk, a.kphase, er, ei, ir2, kr);
+    else geom_f64<false>(dx, dy, dz, a.k, a.kphase, er, ei, ir2, kr);
+}
+
+template <int G, typename AT>
+__global__ __launch_bounds__(kBlock) void sym_kernel(SymArgs a) {
+    using C2 = typename c2_of<AT>::type;
+    // per-wave copies of the B tile, stored twice in a row (entries 0..127) so
+    // that step st reads entry lane + 64 - st without wrapping; one block per
+    // wave, so the four arrays sit at fixed offsets from one address
+    struct BTile {
+        double x[128], y[128], z[128];
+        C2 u[128];
+    };
+    __shared__ BTile lb[kWavesPerBlock];
+    const int lane = threadIdx.x & 63;
+    const int wib = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    const int xcd = blockIdx.x % kXcds;
+    const int64_t waves_x = static_cast<int64_t>(gridDim.x / kXcds) * kWavesPerBlock;
+    const int64_t w = static_cast<int64_t>(blockIdx.x / kXcds) * kWavesPerBlock + wib;
+    const int64_t lo = a.items * xcd / kXcds, hi = a.items * (xcd + 1) / kXcds;
+    const AT kk = static_cast<AT>(a.k);
+    BTile &B = lb[wib];
+
+    for (int64_t it = lo + w; it < hi; it += waves_x) {
+        // item -> (I, J), I <= J, row by row: row I holds groups - I items
+        int I = 0;
+        int64_t rem = it;
+        while (rem >= a.groups - I) {
+            rem -= a.groups - I;
+            ++I;
+        }
+        const int J = I + static_cast<int>(rem);
+
+        double accAr[G], accAi[G], accBr[G], accBi[G];
+#pragma unroll
+        for (int t = 0; t < G; ++t) accAr[t] = accAi[t] = accBr[t] = accBi[t] = 0.0;
+
+        for (int ta = 0; ta < G; ++ta) {
+            const int at = I * G + ta;
+            if (at >= a.tiles) break;
+            double xa, ya, za;
+            AT uar, uai;
+            load_point<AT>(a, static_cast<int64_t>(at) * 64 + lane, lane, xa, ya, za, uar, uai);
+            for (int tb = (I == J) ? ta : 0; tb < G; ++tb) {
+                const int bt = J * G + tb;
+                if (bt >= a.tiles) break;
+                {
+                    double xb, yb, zb;
+                    AT ubr, ubi;
+                    load_point<AT>(a, static_cast<int64_t>(bt) * 64 + lane, lane, xb, yb, zb, ubr, ubi);
+                    C2 u;
+                    u.x = ubr;
+                    u.y = ubi;
+                    B.x[lane] = B.x[lane + 64] = xb;
+                    B.y[lane] = B.y[lane + 64] = yb;
+                    B.z[lane] = B.z[lane + 64] = zb;
+                    B.u[lane] = B.u[lane + 64] = u;
+                }
+                AT sAr = 0, sAi = 0, sBr = 0, sBi = 0;
+                if (at == bt) {
+                    // the tile with itself: the 63 other points, target side only
+                    for (int st = 1; st < 64; ++st) {
+                        const int j = lane + 64 - st;
+                        AT er, ei;
+                        pair_e<AT>(xa - B.x[j], ya - B.y[j], za - B.z[j], a, kk, er, ei);
+                        const C2 u = B.u[j];
+                        sAr = fma(er, u.x, fma(-ei, u.y, sAr));
+                        sAi = fma(er, u.y, fma(ei, u.x, sAi));
+                    }
+                } else {
+                    for (int st = 0; st < 64; ++st) {
+                        // B point (lane - st) mod 64; its accumulator has moved st lanes up
+                        const int j = lane + 64 - st;
+                        AT er, ei;
+                        pair_e<AT>(xa - B.x[j], ya - B.y[j], za - B.z[j], a, kk, er, ei);
+                        const C2 u = B.u[j];
+                        sAr = fma(er, u.x, fma(-ei, u.y, sAr));
+                        sAi = fma(er, u.y, fma(ei, u.x, sAi));
+                        sBr = rot1(fma(er, uar, fma(-ei, uai, sBr)));
+                        sBi = rot1(fma(er, uai, fma(ei, uar, sBi)));
+                    }
+                    // 64 rotations: every B point's sum is back in its home lane
+                }
+                // tile-indexed accumulators with compile-time register indices
+#pragma unroll
+                for (int t = 0; t < G; ++t) {
+                    if (t == ta) {
+                        accAr[t] += static_cast<double>(sAr);
+                        accAi[t] += static_cast<double>(sAi);
+                    }
+                    if (t == tb) {
+                        accBr[t] += static_cast<double>(sBr);
+                        accBi[t] += static_cast<double>(sBi);
+                    }
+                }
+            }
+        }
+        // group I receives slot J, group J receives slot I (one slot for I = J)
+#pragma unroll
+        for (int t = 0; t < G; ++t) {
+            const int at = I * G + t;
+            const int64_t pa = static_cast<int64_t>(at) * 64 + lane;
+            if (at < a.tiles && pa < a.ng) {
+                double r = accAr[t], i = accAi[t];
+                if (I == J) {
+                    r += accBr[t];
+                    i += accBi[t];
+                }
+                a.part[static_cast<int64_t>(J) * a.ldp + pa] = make_double2(r, i);
+            }
+            if (I != J) {
+                const int bt = J * G + t;
+                const int64_t pb = static_cast<int64_t>(bt) * 64 + lane;
+                if (bt < a.tiles && pb < a.ng) a.part[static_cast<int64_t>(I) * a.ldp + pb] = make_double2(accBr[t], accBi[t]);
+            }
+        }
+    }
+}
+
+// y = diag x + (cells: sum of the symmetric slots; faces: sum of the one-sided
+// single-layer chunk partials) + sum of the double-layer chunk partials
+__global__ void sym_reduce_kernel(int64_t n, int64_t n_vol, int n_slots, const double2 *__restrict__ sym,
+                                  int64_t ldp, int n_face_parts, const double2 *__restrict__ face, int n_f_parts,
+                                  const double2 *__restrict__ fpart, const double2 *__restrict__ diag,
+                                  const double2 *__restrict__ x, double2 *__restrict__ y) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double sr = 0.0, si = 0.0;
+    if (i < n_vol) {
+        for (int t = 0; t < n_slots; ++t) {
+            const double2 v = sym[static_cast<int64_t>(t) * ldp + i];
+            sr += v.x;
+            si += v.y;
+        }
+    } else {
+        const int64_t nf = n - n_vol;
+        for (int c = 0; c < n_face_parts; ++c) {
+            const double2 v = face[static_cast<int64_t>(c) * nf + (i - n_vol)];
+            sr += v.x;
+            si += v.y;
+        }
+    }
+    for (int c = 0; c < n_f_parts; ++c) {
+        const double2 v = fpart[static_cast<int64_t>(c) * n + i];
+        sr += v.x;
+        si += v.y;
+    }
+    const double2 d = diag[i], xv = x[i];
+    y[i] = make_double2(d.x * xv.x - d.y * xv.y + sr, d.x * xv.y + d.y * xv.x + si);
+}
+
+template <int G, typename AT>
+const void *sym_ptr() {
+    return reinterpret_cast<const void *>(&sym_kernel<G, AT>);
+}
+
+const void *pick_sym(int g, bool f32) {
+    if (g == 2) return f32 ? sym_ptr<2, float>() : sym_ptr<2, double>();
+    if (g == 4) return f32 ? sym_ptr<4, float>() : sym_ptr<4, double>();
+    if (g == 8) return f32 ? sym_ptr<8, float>() : sym_ptr<8, double>();
+    return nullptr;
+}
+
+}  // namespace
+
+bool sym_groups_ok(int g) { return g == 2 || g == 4 || g == 8; }
+
+int64_t sym_slots(int64_t ng, int g) {
+    const int64_t tiles = (ng + 63) / 64;
+    return (tiles + g - 1) / g;
+}
+
+void launch_sym(const SymJob &J, hipStream_t s, PairProfiler *prof) {
+    if (J.ng <= 0) return;
+    if (!sym_groups_ok(J.g)) fail(VSIE_E_INVALID, "symmetric pair kernel: unsupported group size");
+    const bool f32 = J.prec == VSIE_FP32;
+    SymArgs a{};
+    a.ng = J.ng;
+    a.px = J.px;
+    a.py = J.py;
+    a.pz = J.pz;
+    a.q = J.q;
+    a.k = J.k;
+    a.kphase = f32 ? J.k / kTwoPi : J.k / kPi;
+    for (int d = 0; d < 3; ++d) a.far[d] = J.far[d];
+    a.far_step = J.far_step;
+    a.tiles = static_cast<int>((J.ng + 63) / 64);
+    a.groups = static_cast<int>(sym_slots(J.ng, J.g));
+    a.items = static_cast<int64_t>(a.groups) * (a.groups + 1) / 2;
+    a.part = J.part;
+    a.ldp = J.ldp;
+    if (J.ldp < J.ng) fail(VSIE_E_INVALID, "symmetric pair kernel: partial stride below the cell count");
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        VSIE_HIP(hipGetDevice(&dev));
+        VSIE_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    }
+    const void *kp = pick_sym(J.g, f32);
+    static int occ_cache[9][2] = {};
+    int &occ = occ_cache[J.g][f32 ? 1 : 0];
+    if (!occ) {
+        VSIE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kp, kBlock, 0));
+        occ = std::max(1, occ);
+    }
+    // every resident wave (fewer, evenly loaded waves measured slower), but no
+    // more waves than items
+    int64_t grid = static_cast<int64_t>(cus) * occ;
+    const int64_t need = (a.items + kWavesPerBlock - 1) / kWavesPerBlock;
+    grid = std::min<int64_t>(grid, ((need + kXcds - 1) / kXcds) * kXcds);
+    grid = std::max<int64_t>(kXcds, (grid / kXcds) * kXcds);
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (prof && prof->on) {
+        ev0 = prof_take_event(prof);
+        ev1 = prof_take_event(prof);
+        VSIE_HIP(hipEventRecord(ev0, s));
+    }
+    hipLaunchKernelGGL(reinterpret_cast<void (*)(SymArgs)>(const_cast<void *>(kp)), dim3(static_cast<unsigned>(grid)),
+                       dim3(kBlock), 0, s, a);
+    VSIE_HIP(hipGetLastError());
+    if (prof && prof->on) {
+        VSIE_HIP(hipEventRecord(ev1, s));
+        const double pairs = static_cast<double>(J.ng) * (J.ng - 1);
+        prof->recs.push_back(PairProfiler::Rec{ev0, ev1, 10 + (f32 ? 1 : 0), pairs, pairs});
+    }
+}
+
+void launch_sym_reduce(int64_t n, int64_t n_vol, int n_slots, const double2 *sym, int64_t ldp, int n_face_parts,
+                       const double2 *face, int n_f_parts, const double2 *fpart, const double2 *diag,
+                       const double2 *x, double2 *y, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(sym_reduce_kernel, dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       n, n_vol, n_slots, sym, ldp, n_face_parts, face, n_f_parts, fpart, diag, x, y);
+    VSIE_HIP(hipGetLastError());
+}
+
+}  // namespace vsie

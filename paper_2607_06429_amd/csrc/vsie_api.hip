@@ -99,7 +99,11 @@ struct vsie_problem {
     Scratch V, V2, w, r, ax, h1, h2, tc, nrm, dpart, npart, yv, act, act2, live, kd, kc, xa, axa, rres;
     Scratch bh, bg, bsk;  // block GMRES: Hessenberg block column, Gram / inverse factor, slab partials
     PairProfiler prof;
-    vsie_tuning tune{8, 2, 1, 16, 32768, 1, 0};
+    vsie_tuning tune{8, 2, 1, 16, 32768, 1, 4};
+    // every cell is a single-layer source and the sources are the cells in
+    // canonical order (the symmetric cell-cell kernel applies)
+    bool g_is_cells = false;
+    double far[3] = {0, 0, 0}, far_step = 1;  // padding points of the tiled kernels
     // dense FP32 off-diagonal operator per frequency (caller-owned memory)
     struct Dense {
         float2 *A = nullptr;
@@ -285,6 +289,9 @@ void build_sources(vsie_problem *p) {
         }
     }
     const double ext = std::max({hi3[0] - lo3[0], hi3[1] - lo3[1], hi3[2] - lo3[2]}) + 1.0;
+    for (int d = 0; d < 3; ++d) p->far[d] = hi3[d] + ext;
+    p->far_step = ext;
+    p->g_is_cells = static_cast<int64_t>(gi.size()) == p->m.n_vol && p->m.n_vol > 0;
     auto fill = [&](SourceSet &S, const std::vector<int32_t> &ix, bool with_v) {
         S.count = static_cast<int64_t>(ix.size());
         if (S.count == 0) return;
@@ -369,8 +376,53 @@ void apply_forward_block(vsie_problem *p, int f, vsie_precision prec, int nrhs, 
                            ldx, y, ldy, nullptr, s);
 }
 
+// y = A_f x for one right-hand side with the cell-cell single layer evaluated
+// once per unordered pair: the symmetric kernel for cell targets, the vector
+// kernel for face targets (no face is a single-layer source, so nothing is
+// masked there), the double layers over every target, one reduction.
+void apply_forward_sym(vsie_problem *p, int f, vsie_precision prec, const double2 *x, double2 *y,
+                       hipStream_t s) {
+    const int64_t n = p->m.n, nv = p->m.n_vol, ns = n - nv;
+    const int g = p->tune.sym_groups;
+    const int64_t slots = sym_slots(nv, g);
+    int64_t chGf = 1, chF = 1;
+    int ncGf = 0, ncF = 0;
+    if (ns > 0) choose_chunks(ns, p->G.count, p->tune.vec_target_waves, chGf, ncGf);
+    choose_chunks(n, p->F.count, p->tune.vec_target_waves, chF, ncF);
+    const size_t total = static_cast<size_t>(slots * nv + static_cast<int64_t>(ncGf) * ns + static_cast<int64_t>(ncF) * n);
+    double2 *part = static_cast<double2 *>(p->partial.get(sizeof(double2) * std::max<size_t>(1, total)));
+    double2 *psym = part, *pface = psym + slots * nv, *pF = pface + static_cast<int64_t>(ncGf) * ns;
+    void *qG = p->chargeG.get(csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->G.count)));
+    void *qF = p->chargeF.get(csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->F.count)));
+    const double *spf = p->m.sp + static_cast<int64_t>(f) * n;
+    launch_pack_charges(kClassG, prec, p->G, spf, 1, x, n, false, qG, s);
+    launch_pack_charges(kClassF, prec, p->F, spf, 1, x, n, false, qF, s);
+    const double k = p->k0[f];
+    SymJob J{prec, nv, p->m.px, p->m.py, p->m.pz, qG, k, {p->far[0], p->far[1], p->far[2]}, p->far_step, g, psym, nv};
+    launch_sym(J, s, &p->prof);
+    if (ncGf > 0) {
+        PairJob Jf{PAIR_FWD_G, prec, ns, p->m.px + nv, p->m.py + nv, p->m.pz + nv, {}, p->G.count,
+                   p->G.x, p->G.y, p->G.z, {}, qG, p->G.count, 1, chGf, ncGf, k, pface, ns, SELF_DISJOINT, nullptr};
+        launch_pairs(Jf, s, &p->prof);
+    }
+    if (ncF > 0) {
+        PairJob JF{PAIR_FWD_F, prec, n, p->m.px, p->m.py, p->m.pz, {}, p->F.count,
+                   p->F.x, p->F.y, p->F.z, {p->F.vx, p->F.vy, p->F.vz}, qF, p->F.count, 1, chF, ncF, k,
+                   pF, n, SELF_STREAM_IDX, p->F.idx};
+        launch_pairs(JF, s, &p->prof);
+    }
+    launch_sym_reduce(n, nv, static_cast<int>(slots), psym, nv, ncGf, pface, ncF, pF,
+                      p->m.diag + static_cast<int64_t>(f) * n, x, y, s);
+}
+
+bool use_sym(const vsie_problem *p, int nrhs) { return nrhs == 1 && p->tune.sym_groups > 0 && p->g_is_cells; }
+
 void apply_forward(vsie_problem *p, int f, vsie_precision prec, int nrhs, const double2 *x,
                    int64_t ldx, double2 *y, int64_t ldy, hipStream_t s) {
+    if (use_sym(p, nrhs)) {
+        apply_forward_sym(p, f, prec, x, y, s);
+        return;
+    }
     for (int r0 = 0; r0 < nrhs; r0 += kMaxRhsPerLaunch) {
         const int blk = std::min(kMaxRhsPerLaunch, nrhs - r0);
         apply_forward_block(p, f, prec, blk, x + static_cast<int64_t>(r0) * ldx, ldx,
@@ -547,7 +599,7 @@ void check_tuning(const vsie_tuning &t) {
     require(t.vec_target_waves >= 1024 && t.vec_target_waves <= (int64_t(1) << 24),
             "vec_target_waves must be in [1024, 2^24]");
     require(t.graph == 0 || t.graph == 1, "graph must be 0 or 1");
-    require(t.reserved == 0, "reserved must be 0");
+    require(t.sym_groups == 0 || sym_groups_ok(t.sym_groups), "sym_groups must be 0, 2, 4 or 8");
 }
 
 void apply_op(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int nrhs,
@@ -1824,7 +1876,7 @@ vsie_status vsie_profile(vsie_problem *p, int32_t enable) {
 vsie_status vsie_profile_read(vsie_problem *p, int32_t kind, vsie_kernel_stats *out) {
     return guarded([&] {
         require(p != nullptr && out != nullptr, "NULL argument");
-        require(kind >= 0 && kind < 10, "kernel kind out of range");
+        require(kind >= 0 && kind < 12, "kernel kind out of range");
         vsie_kernel_stats st{0, 0.0, 0.0, 0.0};
         for (auto &r : p->prof.recs) {
             if (r.kind != kind) continue;

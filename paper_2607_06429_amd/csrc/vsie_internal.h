@@ -79,7 +79,8 @@ enum PairMode { PAIR_FWD_G = 0, PAIR_FWD_F = 1, PAIR_ADJ_F = 2, PAIR_SUMS = 3 };
 //                    (self_idx increasing)
 //   SELF_THREAD_IDX  streamed points are the collocation points; thread point
 //                    t is canonical point self_idx[t] (self_idx increasing)
-enum SelfMode { SELF_NONE = 0, SELF_IDENT = 1, SELF_STREAM_IDX = 2, SELF_THREAD_IDX = 3 };
+//   SELF_DISJOINT    no streamed point is a thread point: nothing is masked
+enum SelfMode { SELF_NONE = 0, SELF_IDENT = 1, SELF_STREAM_IDX = 2, SELF_THREAD_IDX = 3, SELF_DISJOINT = 4 };
 struct PairJob {
     int mode;
     vsie_precision prec;
@@ -150,6 +151,35 @@ int mfma_grid(int tg, int nb);
 void launch_pack_mfma(SrcClass cls, const SourceSet &src, const double *sp, int64_t sp_fstride, int nf,
                       int nrhs, int ncol, const double2 *x, int64_t ldx, int64_t xfs, float2 *q, int64_t ldq_f,
                       hipStream_t s);
+
+// Single-layer sums among the cells with one evaluation per unordered pair,
+// one right-hand side (sym_kernels.hip).  The cells are the canonical points
+// 0 .. ng-1 and q their single-layer charges u = -s' x (complex, FP64 or FP32
+// per prec).  Cell p receives one partial per group of g 64-point tiles:
+// part[slot * ldp + p], slot = 0 .. sym_slots(ng, g) - 1.  Tiles are padded
+// with points at far + far_step * lane (farther than the mesh extent from
+// every point) and zero charge.
+struct SymJob {
+    vsie_precision prec;
+    int64_t ng;
+    const double *px, *py, *pz;
+    const void *q;
+    double k;
+    double far[3];
+    double far_step;
+    int g;
+    double2 *part;
+    int64_t ldp;
+};
+bool sym_groups_ok(int g);
+int64_t sym_slots(int64_t ng, int g);
+void launch_sym(const SymJob &J, hipStream_t s, PairProfiler *prof);
+// y = diag x + (i < n_vol: sum of the n_slots symmetric partials; i >= n_vol:
+// sum of n_face_parts partials over the faces, face[c * (n - n_vol) + i - n_vol])
+// + sum of n_f_parts partials fpart[c * n + i]; one right-hand side
+void launch_sym_reduce(int64_t n, int64_t n_vol, int n_slots, const double2 *sym, int64_t ldp, int n_face_parts,
+                       const double2 *face, int n_f_parts, const double2 *fpart, const double2 *diag,
+                       const double2 *x, double2 *y, hipStream_t s);
 
 // auxiliary kernels (aux_kernels.hip)
 void launch_weights(const DeviceMesh &m, const double *k0, int n_freq, hipStream_t s);

@@ -3,11 +3,13 @@ kernels' inner loops.
 
     python paper_2607_06429_amd/isa_count.py
 
-Compiles csrc/pair_kernels.hip and csrc/mfma_kernels.hip to gfx950 assembly
+Compiles csrc/pair_kernels.hip, csrc/mfma_kernels.hip and csrc/sym_kernels.hip
+to gfx950 assembly
 (the same flags as the library build) and, for each kernel variant, finds the
 innermost loop that evaluates the most pairs per trip (the unrolled
 steady-state loop; one v_rsq per pair and lane), counts its instructions and
-divides by the pairs per trip.
+divides by the pairs per trip (ordered pairs: an evaluation of the
+symmetric cell-cell kernel counts twice).
 
 Issue-cycle model (SIMD cycles one wave64 instruction occupies; the chip has
 256 CUs x 4 SIMDs at 2.4 GHz):
@@ -16,7 +18,8 @@ Issue-cycle model (SIMD cycles one wave64 instruction occupies; the chip has
   FP32 transcendental (rsq sin cos) 8   (quarter of the FP32 rate)
   FP64 transcendental (rsq_f64)    16
   v_mfma_f32_16x16x4_f32           32   (2048 FLOP at 64 FLOP/cycle/SIMD)
-Microbenchmarks on MI355X give 2.5-2.8, 4.4-5.8, 8.5, 16.3 and 32.5 cycles
+  DPP moves (v_mov_b32_dpp)         4   (measured)
+Microbenchmarks on MI355X give 2.5-2.8, 4.4-5.8, 8.5, 16.3, 32.5 and 4.1 cycles
 with 8 independent chains per lane, and show matrix-core and VALU time adding
 up (no overlap) for FP32.  Writes isa_counts.json beside this file; bench.py
 reads it to turn measured pair rates into issue cycles per second.
@@ -50,6 +53,8 @@ def cycles(op: str) -> int:
     """Issue cycles of one wave64 instruction (the model above)."""
     if op.startswith("v_mfma"):
         return 32
+    if "_dpp" in op:
+        return 4
     if re.match(r"v_(rsq|rcp|sqrt)_f64", op):
         return 16
     if re.match(r"v_(rsq|sin|cos|rcp|sqrt|exp|log)_", op):
@@ -86,6 +91,10 @@ def kernels(asm: str):
     for nm in re.findall(r"^(_Z\w+mfma_fwd_kernel\w+):", asm, re.M):
         cls, tg, nb = re.search(r"kernelILi(\d)ELi(\d)ELi(\d)E", nm).groups()
         yield nm, "mfma_%s_fp32_tg%s_nb%s" % (MODES[int(cls)], tg, nb), 16 * int(nb)
+    for nm in re.findall(r"^(_Z\w+sym_kernel\w+):", asm, re.M):
+        g, acc = re.search(r"sym_kernelILi(\d)E(\w)E", nm).groups()
+        if g == "4":   # the default group size; the inner loop is the same for every size
+            yield nm, "sym_single_layer_%s_R1" % ("fp64" if acc == "d" else "fp32"), 1
 
 
 def count(asm: str) -> dict:
@@ -93,6 +102,7 @@ def count(asm: str) -> dict:
     for nm, key, R in kernels(asm):
         i = asm.index(nm + ":")
         lines = asm[i:asm.index(".Lfunc_end", i)].split("\n")
+        sym = "sym_kernel" in nm
         best = None
         for a, b in inner_loops(lines):
             body = [x.strip() for x in lines[a:b + 1]
@@ -100,12 +110,21 @@ def count(asm: str) -> dict:
             nrsq = sum(1 for x in body if x.startswith("v_rsq"))
             if nrsq == 0:
                 continue
+            if sym:
+                # the tile-pair loop (source side carried along: the most DPP moves per pair),
+                # not the 63-step loop of a tile with itself
+                rank = (sum(1 for x in body if "_dpp" in x.split()[0]) / nrsq, nrsq)
+                if best is None or rank > best[2]:
+                    best = (nrsq, body, rank)
+                continue
             # the unrolled steady-state loop evaluates the most pairs per trip
             if best is None or nrsq > best[0] or (nrsq == best[0] and len(body) < len(best[1])):
                 best = (nrsq, body)
         if best is None:
             continue
-        nrsq, body = best
+        nrsq, body = best[0], best[1]
+        # each evaluation of the symmetric kernel serves two ordered pairs
+        per_eval = 2 if sym else 1
         c = collections.Counter()
         for x in body:
             op = x.split()[0]
@@ -123,9 +142,9 @@ def count(asm: str) -> dict:
                 c["smem"] += 1
             elif op.startswith("s_"):
                 c["salu"] += 1
-        res[key] = {"pairs_per_trip": nrsq,
+        res[key] = {"pairs_per_trip": nrsq * per_eval,
                     "rhs_per_trip": R,
-                    "cycles_per_pair": c["cycles"] / (64.0 * nrsq),
+                    "cycles_per_pair": c["cycles"] / (64.0 * nrsq * per_eval),
                     "mfma_per_pair": c["mfma"] / nrsq,
                     "valu_per_pair": c["valu"] / nrsq,
                     "f64_per_pair": c["f64"] / nrsq,
@@ -138,6 +157,7 @@ def count(asm: str) -> dict:
 def main():
     res = count(assemble("pair_kernels.hip"))
     res.update(count(assemble("mfma_kernels.hip")))
+    res.update(count(assemble("sym_kernels.hip")))
     out = os.path.join(HERE, "isa_counts.json")
     with open(out, "w") as f:
         json.dump(res, f, indent=1, sort_keys=True)

@@ -430,3 +430,52 @@ def test_graph_small_problem_timing(V):
             % (pr, res[0][0] * 1e3, res[1][0] * 1e3, info["iterations"]))
         assert torch.equal(res[0][1], res[1][1])
     P.close()
+
+
+# ---------------------------------------------------------------------------
+# cell-cell single layer evaluated once per unordered pair (one column)
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_symmetric_single_layer(V, name, prec):
+    """One-column products with the symmetric cell-cell kernel, for every group
+    size, against the oracle and against the one-sided kernels; ragged tiles
+    (no case has a multiple of 64 cells) and the padding lanes included."""
+    mesh, mat, k0 = case(name)
+    d = O.discretise(mesh, mat, k0)
+    P = V.Problem.from_mesh(mesh, mat, [k0])
+    pr = V.VSIE_FP64 if prec == "fp64" else V.VSIE_FP32
+    tol = TOL64 if prec == "fp64" else TOL32
+    x = W.seeded_complex(d.n, seed=95)
+    ref = O.matvec(d, x[:, None])[:, 0]
+    P.set_tuning(sym_groups=0)
+    y0 = host(P.matvec(dev(x), prec=pr))
+    for g in (2, 4, 8):
+        P.set_tuning(sym_groups=g)
+        P.profile(True)
+        y = host(P.matvec(dev(x), prec=pr))
+        st = P.kernel_stats()
+        P.profile(False)
+        e, e0 = O.rel_error(y, ref), O.rel_error(y, y0)
+        say("  %s %s groups %d: n_vol %d rel err %.2e, vs one-sided %.2e" % (name, prec, g, mesh.n_vol, e, e0))
+        assert ("sym_single_layer_" + prec) in st
+        assert e <= tol and e0 <= 2 * tol
+    P.close()
+
+
+def test_symmetric_kernel_falls_back_when_some_cells_have_no_single_layer(V):
+    """Shell sound speed equal to c0: its cells carry no single-layer weight, so
+    the cells are not all single-layer sources and the one-sided kernels run."""
+    mesh = W.nested_balls(9)
+    mat = W.materials_piecewise(mesh, 1.0, 1.0, 1.3, 1.0, 2.0, 0.8)
+    d = O.discretise(mesh, mat, 3.0)
+    assert np.any(d.sV == 0) and np.any(d.sV != 0)
+    P = V.Problem.from_mesh(mesh, mat, [3.0])
+    x = W.seeded_complex(d.n, seed=96)
+    P.profile(True)
+    y = host(P.matvec(dev(x), prec=V.VSIE_FP64))
+    st = P.kernel_stats()
+    P.profile(False)
+    assert not any(k.startswith("sym_") for k in st)
+    assert O.rel_error(y, O.matvec(d, x[:, None])[:, 0]) <= TOL64
+    P.close()

@@ -160,6 +160,11 @@ typedef struct {
                                   once per unordered pair (e_ij = e_ji), in work items
                                   of sym_groups x sym_groups 64-cell tiles; 0 = off,
                                   2, 4 or 8; default 4 */
+    int32_t cell_face;         /* with sym_groups on and every double-layer source a
+                                  face: the cell-face pairs also run once per pair
+                                  (single layer at the face, double layers at the
+                                  cell); 0 = off, 1 = on; default 1 */
+    int32_t reserved;          /* must be 0 */
 } vsie_tuning;
 
 vsie_status vsie_get_tuning(const vsie_problem *p, vsie_tuning *out);
@@ -290,7 +295,9 @@ vsie_status vsie_release_dense(vsie_problem *p, int32_t f);
  * and precision VSIE_FP64 or VSIE_FP32; kind 8 and 9 are the matrix-core
  * forward single layer and double layers (FP32; a launch over nf frequencies
  * counts nf times its pairs); kind 10 and 11 the symmetric cell-cell single
- * layer in FP64 and FP32 (pairs = ordered cell pairs, n_vol (n_vol - 1)). */
+ * layer in FP64 and FP32 (pairs = ordered cell pairs, n_vol (n_vol - 1));
+ * kind 12 and 13 the cell-face kernel in FP64 and FP32 (pairs = 2 n_vol n_srf,
+ * both directions). */
 typedef struct {
     int64_t launches;
     double ms;

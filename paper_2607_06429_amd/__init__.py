@@ -68,7 +68,7 @@ class SolveOpts(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("mfma_min_rhs", _I32), ("mfma_tg", _I32), ("mfma_nb", _I32),
                 ("items_per_wave", _I32), ("vec_target_waves", _I64), ("graph", _I32),
-                ("sym_groups", _I32)]
+                ("sym_groups", _I32), ("cell_face", _I32), ("reserved", _I32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -135,7 +135,8 @@ KIND_NAMES = {0: "fwd_single_layer_fp64", 1: "fwd_single_layer_fp32", 2: "fwd_do
               3: "fwd_double_layers_fp32", 4: "adj_double_layers_fp64", 5: "adj_double_layers_fp32",
               6: "source_sums_fp64", 7: "source_sums_fp32",
               8: "mfma_fwd_single_layer_fp32", 9: "mfma_fwd_double_layers_fp32",
-              10: "sym_single_layer_fp64", 11: "sym_single_layer_fp32"}
+              10: "sym_single_layer_fp64", 11: "sym_single_layer_fp32",
+              12: "cell_face_fp64", 13: "cell_face_fp32"}
 
 
 def vsie_last_error() -> str:

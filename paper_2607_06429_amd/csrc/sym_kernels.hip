@@ -250,6 +250,195 @@ __global__ void sym_reduce_kernel(int64_t n, int64_t n_vol, int n_slots, const d
     y[i] = make_double2(d.x * xv.x - d.y * xv.y + sr, d.x * xv.y + d.y * xv.x + si);
 }
 
+// ---------------------------------------------------------------------------
+// Cell-face pairs, one evaluation per pair (one right-hand side): the single
+// layer of cell c at face target f and the double layer (T and K terms) of
+// face f at cell target c share the pair's distance, phase, sine and cosine:
+//   y_f += e u_c,                 u_c = -s'_c x_c
+//   y_c += e (i k r - 1) q x_f,   q = (x_c - y_f).v'_f / r^2
+// Lanes hold cells (tile A); the face tile B (positions, v', values) sits in
+// the wave's LDS slice and the faces' single-layer sums rotate by DPP, as in
+// sym_kernel.  Work items are (cell group I, face group J), every pair of
+// groups.  Cells receive one partial per face group (slot J), faces one per
+// cell group (slot I).
+struct CfArgs {
+    int64_t nc, nf;                  // cells (points 0 .. nc-1), faces (points nc .. nc+nf-1)
+    const double *__restrict__ px;
+    const double *__restrict__ py;
+    const double *__restrict__ pz;
+    const double *__restrict__ vx;   // v' of the faces (nf entries)
+    const double *__restrict__ vy;
+    const double *__restrict__ vz;
+    const void *__restrict__ qc;     // single-layer charges of the cells, complex AT
+    const void *__restrict__ qf;     // values of the faces (double-layer charges), complex AT
+    double k;
+    double kphase;
+    double far[3];
+    double far_step;
+    int ctiles, ftiles;
+    int cgroups, fgroups;
+    int64_t items;
+    double2 *__restrict__ pc;        // pc[slot * ldc + c], slot = face group
+    int64_t ldc;
+    double2 *__restrict__ pf;        // pf[slot * ldf + f], slot = cell group
+    int64_t ldf;
+};
+
+template <int G, typename AT>
+__global__ __launch_bounds__(kBlock) void cf_kernel(CfArgs a) {
+    using C2 = typename c2_of<AT>::type;
+    struct FTile {
+        double x[128], y[128], z[128], vx[128], vy[128], vz[128];
+        C2 u[128];
+    };
+    __shared__ FTile lb[kWavesPerBlock];
+    const int lane = threadIdx.x & 63;
+    const int wib = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    const int xcd = blockIdx.x % kXcds;
+    const int64_t waves_x = static_cast<int64_t>(gridDim.x / kXcds) * kWavesPerBlock;
+    const int64_t w = static_cast<int64_t>(blockIdx.x / kXcds) * kWavesPerBlock + wib;
+    const int64_t lo = a.items * xcd / kXcds, hi = a.items * (xcd + 1) / kXcds;
+    const AT kk = static_cast<AT>(a.k);
+    FTile &B = lb[wib];
+
+    for (int64_t it = lo + w; it < hi; it += waves_x) {
+        const int I = static_cast<int>(it / a.fgroups);
+        const int J = static_cast<int>(it - static_cast<int64_t>(I) * a.fgroups);
+        double accAr[G], accAi[G], accBr[G], accBi[G];
+#pragma unroll
+        for (int t = 0; t < G; ++t) accAr[t] = accAi[t] = accBr[t] = accBi[t] = 0.0;
+
+        for (int ta = 0; ta < G; ++ta) {
+            const int at = I * G + ta;
+            if (at >= a.ctiles) break;
+            const int64_t c = static_cast<int64_t>(at) * 64 + lane;
+            double xa, ya, za;
+            AT uar, uai;
+            if (c < a.nc) {
+                xa = a.px[c];
+                ya = a.py[c];
+                za = a.pz[c];
+                const C2 u = static_cast<const C2 *>(a.qc)[c];
+                uar = u.x;
+                uai = u.y;
+            } else {
+                xa = a.far[0] + a.far_step * lane;
+                ya = a.far[1];
+                za = a.far[2];
+                uar = uai = 0;
+            }
+            for (int tb = 0; tb < G; ++tb) {
+                const int bt = J * G + tb;
+                if (bt >= a.ftiles) break;
+                {
+                    const int64_t f = static_cast<int64_t>(bt) * 64 + lane;
+                    double xb, yb, zb, wx = 0, wy = 0, wz = 0;
+                    C2 u;
+                    if (f < a.nf) {
+                        xb = a.px[a.nc + f];
+                        yb = a.py[a.nc + f];
+                        zb = a.pz[a.nc + f];
+                        wx = a.vx[f];
+                        wy = a.vy[f];
+                        wz = a.vz[f];
+                        u = static_cast<const C2 *>(a.qf)[f];
+                    } else {
+                        // padding faces: far points apart from the padding cells, v' = 0, value 0
+                        xb = a.far[0] + a.far_step * (lane + 64);
+                        yb = a.far[1];
+                        zb = a.far[2];
+                        u.x = 0;
+                        u.y = 0;
+                    }
+                    B.x[lane] = B.x[lane + 64] = xb;
+                    B.y[lane] = B.y[lane + 64] = yb;
+                    B.z[lane] = B.z[lane + 64] = zb;
+                    B.vx[lane] = B.vx[lane + 64] = wx;
+                    B.vy[lane] = B.vy[lane + 64] = wy;
+                    B.vz[lane] = B.vz[lane + 64] = wz;
+                    B.u[lane] = B.u[lane + 64] = u;
+                }
+                AT sAr = 0, sAi = 0, sBr = 0, sBi = 0;
+                for (int st = 0; st < 64; ++st) {
+                    // face (lane - st) mod 64; its single-layer sum has moved st lanes up
+                    const int j = lane + 64 - st;
+                    const double dx = xa - B.x[j], dy = ya - B.y[j], dz = za - B.z[j];
+                    AT er, ei, ir2, kr;
+                    if constexpr (sizeof(AT) == 4) geom_f32<false>(dx, dy, dz, kk, a.kphase, er, ei, ir2, kr);
+                    else geom_f64<false>(dx, dy, dz, a.k, a.kphase, er, ei, ir2, kr);
+                    // double layer of the face at the cell
+                    const AT qq = static_cast<AT>(fma(dx, B.vx[j], fma(dy, B.vy[j], dz * B.vz[j]))) * ir2;
+                    const AT cr = qq * fma(-ei, kr, -er);
+                    const AT ci = qq * fma(er, kr, -ei);
+                    const C2 u = B.u[j];
+                    sAr = fma(cr, u.x, fma(-ci, u.y, sAr));
+                    sAi = fma(cr, u.y, fma(ci, u.x, sAi));
+                    // single layer of the cell at the face
+                    sBr = rot1(fma(er, uar, fma(-ei, uai, sBr)));
+                    sBi = rot1(fma(er, uai, fma(ei, uar, sBi)));
+                }
+#pragma unroll
+                for (int t = 0; t < G; ++t) {
+                    if (t == ta) {
+                        accAr[t] += static_cast<double>(sAr);
+                        accAi[t] += static_cast<double>(sAi);
+                    }
+                    if (t == tb) {
+                        accBr[t] += static_cast<double>(sBr);
+                        accBi[t] += static_cast<double>(sBi);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < G; ++t) {
+            const int at = I * G + t;
+            const int64_t c = static_cast<int64_t>(at) * 64 + lane;
+            if (at < a.ctiles && c < a.nc) a.pc[static_cast<int64_t>(J) * a.ldc + c] = make_double2(accAr[t], accAi[t]);
+            const int bt = J * G + t;
+            const int64_t f = static_cast<int64_t>(bt) * 64 + lane;
+            if (bt < a.ftiles && f < a.nf) a.pf[static_cast<int64_t>(I) * a.ldf + f] = make_double2(accBr[t], accBi[t]);
+        }
+    }
+}
+
+// y = diag x + (cells: symmetric slots + cell-face slots; faces: cell-face
+// slots + face-face chunk partials); one right-hand side
+__global__ void cf_reduce_kernel(int64_t n, int64_t nc, int n_sym, const double2 *__restrict__ sym, int n_cs,
+                                 const double2 *__restrict__ pc, int n_fs, const double2 *__restrict__ pf,
+                                 int n_ff, const double2 *__restrict__ ff, const double2 *__restrict__ diag,
+                                 const double2 *__restrict__ x, double2 *__restrict__ y) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double sr = 0.0, si = 0.0;
+    if (i < nc) {
+        for (int t = 0; t < n_sym; ++t) {
+            const double2 v = sym[static_cast<int64_t>(t) * nc + i];
+            sr += v.x;
+            si += v.y;
+        }
+        for (int t = 0; t < n_cs; ++t) {
+            const double2 v = pc[static_cast<int64_t>(t) * nc + i];
+            sr += v.x;
+            si += v.y;
+        }
+    } else {
+        const int64_t nf = n - nc, f = i - nc;
+        for (int t = 0; t < n_fs; ++t) {
+            const double2 v = pf[static_cast<int64_t>(t) * nf + f];
+            sr += v.x;
+            si += v.y;
+        }
+        for (int c = 0; c < n_ff; ++c) {
+            const double2 v = ff[static_cast<int64_t>(c) * nf + f];
+            sr += v.x;
+            si += v.y;
+        }
+    }
+    const double2 d = diag[i], xv = x[i];
+    y[i] = make_double2(d.x * xv.x - d.y * xv.y + sr, d.x * xv.y + d.y * xv.x + si);
+}
+
 template <int G, typename AT>
 const void *sym_ptr() {
     return reinterpret_cast<const void *>(&sym_kernel<G, AT>);
@@ -332,6 +521,78 @@ void launch_sym_reduce(int64_t n, int64_t n_vol, int n_slots, const double2 *sym
     if (n == 0) return;
     hipLaunchKernelGGL(sym_reduce_kernel, dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
                        n, n_vol, n_slots, sym, ldp, n_face_parts, face, n_f_parts, fpart, diag, x, y);
+    VSIE_HIP(hipGetLastError());
+}
+
+int64_t cf_groups(int64_t count) { return ((count + 63) / 64 + kCfGroup - 1) / kCfGroup; }
+
+void launch_cf(const CfJob &J, hipStream_t s, PairProfiler *prof) {
+    if (J.nc <= 0 || J.nf <= 0) return;
+    const bool f32 = J.prec == VSIE_FP32;
+    CfArgs a{};
+    a.nc = J.nc;
+    a.nf = J.nf;
+    a.px = J.px;
+    a.py = J.py;
+    a.pz = J.pz;
+    a.vx = J.vx;
+    a.vy = J.vy;
+    a.vz = J.vz;
+    a.qc = J.qc;
+    a.qf = J.qf;
+    a.k = J.k;
+    a.kphase = f32 ? J.k / kTwoPi : J.k / kPi;
+    for (int d = 0; d < 3; ++d) a.far[d] = J.far[d];
+    a.far_step = J.far_step;
+    a.ctiles = static_cast<int>((J.nc + 63) / 64);
+    a.ftiles = static_cast<int>((J.nf + 63) / 64);
+    a.cgroups = static_cast<int>(cf_groups(J.nc));
+    a.fgroups = static_cast<int>(cf_groups(J.nf));
+    a.items = static_cast<int64_t>(a.cgroups) * a.fgroups;
+    a.pc = J.pc;
+    a.ldc = J.nc;
+    a.pf = J.pf;
+    a.ldf = J.nf;
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        VSIE_HIP(hipGetDevice(&dev));
+        VSIE_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    }
+    const void *kp = f32 ? reinterpret_cast<const void *>(&cf_kernel<kCfGroup, float>)
+                         : reinterpret_cast<const void *>(&cf_kernel<kCfGroup, double>);
+    static int occ_cache[2] = {0, 0};
+    int &occ = occ_cache[f32 ? 1 : 0];
+    if (!occ) {
+        VSIE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kp, kBlock, 0));
+        occ = std::max(1, occ);
+    }
+    int64_t grid = static_cast<int64_t>(cus) * occ;
+    const int64_t need = (a.items + kWavesPerBlock - 1) / kWavesPerBlock;
+    grid = std::min<int64_t>(grid, ((need + kXcds - 1) / kXcds) * kXcds);
+    grid = std::max<int64_t>(kXcds, (grid / kXcds) * kXcds);
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (prof && prof->on) {
+        ev0 = prof_take_event(prof);
+        ev1 = prof_take_event(prof);
+        VSIE_HIP(hipEventRecord(ev0, s));
+    }
+    hipLaunchKernelGGL(reinterpret_cast<void (*)(CfArgs)>(const_cast<void *>(kp)), dim3(static_cast<unsigned>(grid)),
+                       dim3(kBlock), 0, s, a);
+    VSIE_HIP(hipGetLastError());
+    if (prof && prof->on) {
+        VSIE_HIP(hipEventRecord(ev1, s));
+        const double pairs = 2.0 * static_cast<double>(J.nc) * J.nf;
+        prof->recs.push_back(PairProfiler::Rec{ev0, ev1, 12 + (f32 ? 1 : 0), pairs, pairs});
+    }
+}
+
+void launch_cf_reduce(int64_t n, int64_t nc, int n_sym, const double2 *sym, int n_cs, const double2 *pc, int n_fs,
+                      const double2 *pf, int n_ff, const double2 *ff, const double2 *diag, const double2 *x,
+                      double2 *y, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(cf_reduce_kernel, dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       n, nc, n_sym, sym, n_cs, pc, n_fs, pf, n_ff, ff, diag, x, y);
     VSIE_HIP(hipGetLastError());
 }
 

@@ -99,10 +99,13 @@ struct vsie_problem {
     Scratch V, V2, w, r, ax, h1, h2, tc, nrm, dpart, npart, yv, act, act2, live, kd, kc, xa, axa, rres;
     Scratch bh, bg, bsk;  // block GMRES: Hessenberg block column, Gram / inverse factor, slab partials
     PairProfiler prof;
-    vsie_tuning tune{8, 2, 1, 16, 32768, 1, 4};
+    vsie_tuning tune{8, 2, 1, 16, 32768, 1, 4, 1, 0};
     // every cell is a single-layer source and the sources are the cells in
     // canonical order (the symmetric cell-cell kernel applies)
     bool g_is_cells = false;
+    // the double-layer sources are exactly the faces (no cell has grad alpha):
+    // the fused cell-face kernel applies
+    bool f_is_faces = false;
     double far[3] = {0, 0, 0}, far_step = 1;  // padding points of the tiled kernels
     // dense FP32 off-diagonal operator per frequency (caller-owned memory)
     struct Dense {
@@ -292,6 +295,7 @@ void build_sources(vsie_problem *p) {
     for (int d = 0; d < 3; ++d) p->far[d] = hi3[d] + ext;
     p->far_step = ext;
     p->g_is_cells = static_cast<int64_t>(gi.size()) == p->m.n_vol && p->m.n_vol > 0;
+    p->f_is_faces = static_cast<int64_t>(fi.size()) == p->m.n_srf && p->m.n_srf > 0 && fi[0] == p->m.n_vol;
     auto fill = [&](SourceSet &S, const std::vector<int32_t> &ix, bool with_v) {
         S.count = static_cast<int64_t>(ix.size());
         if (S.count == 0) return;
@@ -380,8 +384,47 @@ void apply_forward_block(vsie_problem *p, int f, vsie_precision prec, int nrhs, 
 // once per unordered pair: the symmetric kernel for cell targets, the vector
 // kernel for face targets (no face is a single-layer source, so nothing is
 // masked there), the double layers over every target, one reduction.
+// The same with the cell-face pairs fused as well (every double-layer source
+// is a face): symmetric cell-cell single layer, cell-face kernel (single layer
+// at faces, double layers at cells), face-face double layers one-sided, one
+// reduction.
+void apply_forward_cf(vsie_problem *p, int f, vsie_precision prec, const double2 *x, double2 *y, hipStream_t s) {
+    const int64_t n = p->m.n, nv = p->m.n_vol, ns = n - nv;
+    const int g = p->tune.sym_groups;
+    const int64_t slots = sym_slots(nv, g), cs = cf_groups(ns), fs = cf_groups(nv);
+    int64_t chFF = 1;
+    int ncFF = 0;
+    choose_chunks(ns, p->F.count, p->tune.vec_target_waves, chFF, ncFF);
+    const size_t total = static_cast<size_t>(slots * nv + cs * nv + fs * ns + static_cast<int64_t>(ncFF) * ns);
+    double2 *part = static_cast<double2 *>(p->partial.get(sizeof(double2) * std::max<size_t>(1, total)));
+    double2 *psym = part, *pc = psym + slots * nv, *pf = pc + cs * nv, *pff = pf + fs * ns;
+    void *qG = p->chargeG.get(csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->G.count)));
+    void *qF = p->chargeF.get(csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->F.count)));
+    const double *spf = p->m.sp + static_cast<int64_t>(f) * n;
+    launch_pack_charges(kClassG, prec, p->G, spf, 1, x, n, false, qG, s);
+    launch_pack_charges(kClassF, prec, p->F, spf, 1, x, n, false, qF, s);
+    const double k = p->k0[f];
+    SymJob J{prec, nv, p->m.px, p->m.py, p->m.pz, qG, k, {p->far[0], p->far[1], p->far[2]}, p->far_step, g, psym, nv};
+    launch_sym(J, s, &p->prof);
+    CfJob C{prec, nv, ns, p->m.px, p->m.py, p->m.pz, p->F.vx, p->F.vy, p->F.vz, qG, qF, k,
+            {p->far[0], p->far[1], p->far[2]}, p->far_step, pc, pf};
+    launch_cf(C, s, &p->prof);
+    if (ncFF > 0) {
+        PairJob Jf{PAIR_FWD_F, prec, ns, p->m.px + nv, p->m.py + nv, p->m.pz + nv, {}, p->F.count,
+                   p->F.x, p->F.y, p->F.z, {p->F.vx, p->F.vy, p->F.vz}, qF, p->F.count, 1, chFF, ncFF, k,
+                   pff, ns, SELF_IDENT, nullptr};
+        launch_pairs(Jf, s, &p->prof);
+    }
+    launch_cf_reduce(n, nv, static_cast<int>(slots), psym, static_cast<int>(cs), pc, static_cast<int>(fs), pf, ncFF,
+                     pff, p->m.diag + static_cast<int64_t>(f) * n, x, y, s);
+}
+
 void apply_forward_sym(vsie_problem *p, int f, vsie_precision prec, const double2 *x, double2 *y,
                        hipStream_t s) {
+    if (p->tune.cell_face && p->f_is_faces) {
+        apply_forward_cf(p, f, prec, x, y, s);
+        return;
+    }
     const int64_t n = p->m.n, nv = p->m.n_vol, ns = n - nv;
     const int g = p->tune.sym_groups;
     const int64_t slots = sym_slots(nv, g);
@@ -600,6 +643,8 @@ void check_tuning(const vsie_tuning &t) {
             "vec_target_waves must be in [1024, 2^24]");
     require(t.graph == 0 || t.graph == 1, "graph must be 0 or 1");
     require(t.sym_groups == 0 || sym_groups_ok(t.sym_groups), "sym_groups must be 0, 2, 4 or 8");
+    require(t.cell_face == 0 || t.cell_face == 1, "cell_face must be 0 or 1");
+    require(t.reserved == 0, "reserved must be 0");
 }
 
 void apply_op(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int nrhs,
@@ -1876,7 +1921,7 @@ vsie_status vsie_profile(vsie_problem *p, int32_t enable) {
 vsie_status vsie_profile_read(vsie_problem *p, int32_t kind, vsie_kernel_stats *out) {
     return guarded([&] {
         require(p != nullptr && out != nullptr, "NULL argument");
-        require(kind >= 0 && kind < 12, "kernel kind out of range");
+        require(kind >= 0 && kind < 14, "kernel kind out of range");
         vsie_kernel_stats st{0, 0.0, 0.0, 0.0};
         for (auto &r : p->prof.recs) {
             if (r.kind != kind) continue;

@@ -181,6 +181,32 @@ void launch_sym_reduce(int64_t n, int64_t n_vol, int n_slots, const double2 *sym
                        const double2 *face, int n_f_parts, const double2 *fpart, const double2 *diag,
                        const double2 *x, double2 *y, hipStream_t s);
 
+// Cell-face pairs with one evaluation per pair, one right-hand side
+// (sym_kernels.hip): cells are the points 0 .. nc-1, faces nc .. nc+nf-1; qc
+// the cells' single-layer charges, qf the faces' values (double-layer
+// charges), vx.. the faces' v'.  Cell c receives the faces' double layers in
+// pc[slot * nc + c] (one slot per group of kCfGroup face tiles), face f the
+// cells' single layers in pf[slot * nf + f] (one slot per group of cell tiles).
+constexpr int kCfGroup = 2;
+struct CfJob {
+    vsie_precision prec;
+    int64_t nc, nf;
+    const double *px, *py, *pz;
+    const double *vx, *vy, *vz;
+    const void *qc, *qf;
+    double k;
+    double far[3];
+    double far_step;
+    double2 *pc, *pf;
+};
+int64_t cf_groups(int64_t count);  // slots for count cells or faces
+void launch_cf(const CfJob &J, hipStream_t s, PairProfiler *prof);
+// y = diag x + (i < nc: n_sym symmetric slots + n_cs cell slots of pc;
+// i >= nc: n_fs face slots of pf + n_ff face-face chunk partials ff[c * nf + i - nc])
+void launch_cf_reduce(int64_t n, int64_t nc, int n_sym, const double2 *sym, int n_cs, const double2 *pc, int n_fs,
+                      const double2 *pf, int n_ff, const double2 *ff, const double2 *diag, const double2 *x,
+                      double2 *y, hipStream_t s);
+
 // auxiliary kernels (aux_kernels.hip)
 void launch_weights(const DeviceMesh &m, const double *k0, int n_freq, hipStream_t s);
 // charge[r * count + jj] = scale * x[idx[jj] + r ldx], scale = -s'_f for class G, else 1

@@ -9,7 +9,7 @@ to gfx950 assembly
 innermost loop that evaluates the most pairs per trip (the unrolled
 steady-state loop; one v_rsq per pair and lane), counts its instructions and
 divides by the pairs per trip (ordered pairs: an evaluation of the
-symmetric cell-cell kernel counts twice).
+symmetric cell-cell kernel and of the cell-face kernel counts twice).
 
 Issue-cycle model (SIMD cycles one wave64 instruction occupies; the chip has
 256 CUs x 4 SIMDs at 2.4 GHz):
@@ -95,6 +95,9 @@ def kernels(asm: str):
         g, acc = re.search(r"sym_kernelILi(\d)E(\w)E", nm).groups()
         if g == "4":   # the default group size; the inner loop is the same for every size
             yield nm, "sym_single_layer_%s_R1" % ("fp64" if acc == "d" else "fp32"), 1
+    for nm in re.findall(r"^(_Z\w+cf_kernel\w+):", asm, re.M):
+        acc = re.search(r"cf_kernelILi\d+E(\w)E", nm).group(1)
+        yield nm, "cell_face_%s_R1" % ("fp64" if acc == "d" else "fp32"), 1
 
 
 def count(asm: str) -> dict:
@@ -102,7 +105,7 @@ def count(asm: str) -> dict:
     for nm, key, R in kernels(asm):
         i = asm.index(nm + ":")
         lines = asm[i:asm.index(".Lfunc_end", i)].split("\n")
-        sym = "sym_kernel" in nm
+        sym = "sym_kernel" in nm or "cf_kernel" in nm
         best = None
         for a, b in inner_loops(lines):
             body = [x.strip() for x in lines[a:b + 1]
@@ -112,8 +115,8 @@ def count(asm: str) -> dict:
                 continue
             if sym:
                 # the tile-pair loop (source side carried along: the most DPP moves per pair),
-                # not the 63-step loop of a tile with itself
-                rank = (sum(1 for x in body if "_dpp" in x.split()[0]) / nrsq, nrsq)
+                # not the 63-step loop of a tile with itself; among equals, the shortest copy
+                rank = (sum(1 for x in body if "_dpp" in x.split()[0]) / nrsq, nrsq, -len(body))
                 if best is None or rank > best[2]:
                     best = (nrsq, body, rank)
                 continue

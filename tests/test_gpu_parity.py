@@ -479,3 +479,34 @@ def test_symmetric_kernel_falls_back_when_some_cells_have_no_single_layer(V):
     assert not any(k.startswith("sym_") for k in st)
     assert O.rel_error(y, O.matvec(d, x[:, None])[:, 0]) <= TOL64
     P.close()
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_cell_face_pairs(V, name, prec):
+    """One-column products with the cell-face pairs evaluated once per pair (the
+    single layer at the face and the double layers at the cell), against the
+    oracle and against the separate one-sided kernels.  It applies when every
+    double-layer source is a face (c0, ragged, cube); cells with grad alpha
+    (lognormal) or faces without a density jump (single) keep the separate
+    kernels."""
+    mesh, mat, k0 = case(name)
+    d = O.discretise(mesh, mat, k0)
+    P = V.Problem.from_mesh(mesh, mat, [k0])
+    pr = V.VSIE_FP64 if prec == "fp64" else V.VSIE_FP32
+    tol = TOL64 if prec == "fp64" else TOL32
+    x = W.seeded_complex(d.n, seed=97)
+    ref = O.matvec(d, x[:, None])[:, 0]
+    P.set_tuning(cell_face=0)
+    y0 = host(P.matvec(dev(x), prec=pr))
+    P.set_tuning(cell_face=1)
+    P.profile(True)
+    y = host(P.matvec(dev(x), prec=pr))
+    st = P.kernel_stats()
+    P.profile(False)
+    fused = ("cell_face_" + prec) in st
+    e, e0 = O.rel_error(y, ref), O.rel_error(y, y0)
+    say("  %s %s fused %s: rel err %.2e, vs separate kernels %.2e" % (name, prec, fused, e, e0))
+    assert fused == (name in ("c0", "ragged", "cube"))
+    assert e <= tol and e0 <= 2 * tol
+    P.close()

@@ -191,6 +191,16 @@ typedef struct {
                             1: block GMRES -- one block Krylov space for all right-hand
                             sides of a cycle, restart counted in block steps and capped
                             so that (steps x nrhs) <= 11585; default 0 */
+    double relax;        /* VSIE_FP32 with block = 0 only.  0: iterative refinement, every
+                            GMRES iteration with the FP32 operator (default).  > 0: relaxed
+                            products -- each cycle aims at the final tolerance and an
+                            iteration applies the FP64 operator while the cycle's residual
+                            estimate exceeds (cycle tolerance / relax) x its starting
+                            residual, the FP32 operator after that.  relax is the relative
+                            error assumed for an FP32 product (e.g. 1e-6): a product may be
+                            that inexact once the residual has fallen far enough that its
+                            error can no longer lift the final residual above the
+                            tolerance (inexact Krylov methods). */
 } vsie_solve_opts;
 
 typedef struct {

@@ -63,6 +63,27 @@ struct Scratch {
     }
 };
 
+// Grow-only pinned host buffer (hipHostMalloc): device-to-host copies into it
+// are truly asynchronous.
+struct HostPinned {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void *get(size_t b) {
+        if (b <= bytes) return p;
+        if (p) VSIE_HIP(hipHostFree(p));
+        p = nullptr;
+        bytes = 0;
+        VSIE_HIP(hipHostMalloc(&p, b, hipHostMallocDefault));
+        bytes = b;
+        return p;
+    }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
+
 // Source chunking of one vector pair launch: about target_waves (thread-block,
 // chunk) waves to keep every SIMD busy, but chunks of at least kMinChunk
 // streamed points.
@@ -98,6 +119,7 @@ struct vsie_problem {
     // Krylov workspace
     Scratch V, V2, w, r, ax, h1, h2, tc, nrm, dpart, npart, yv, act, act2, live, kd, kc, xa, axa, rres;
     Scratch bh, bg, bsk;  // block GMRES: Hessenberg block column, Gram / inverse factor, slab partials
+    HostPinned hpin;      // per-iteration Hessenberg columns and norms on their way to the host
     PairProfiler prof;
     vsie_tuning tune{8, 2, 1, 16, 32768, 1, 4, 1, 0};
     // every cell is a single-layer source and the sources are the cells in
@@ -173,6 +195,7 @@ struct vsie_problem {
         if (blas) (void)rocblas_destroy_handle(blas);
         dense_x.release();
         dense_part.release();
+        hpin.release();
         for (void *p : owned) (void)hipFree(p);
         for (Scratch *s : {&partial, &chargeG, &chargeF, &chargeAll, &sums_part, &grad_work, &V, &V2, &w, &r, &ax,
                            &h1, &h2, &tc, &nrm, &dpart, &npart, &yv, &act, &act2, &live, &kd, &kc, &xa, &axa,
@@ -804,7 +827,8 @@ std::vector<cd> r_solve(const RecycleRhs &q, const std::vector<cd> &c) {
 int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R,
                 const std::vector<int32_t> &rhs, double2 *Rres, const std::vector<double> &rn,
                 const std::vector<double> &ctol, int m, int iter_cap, double2 *x, int64_t ldx,
-                SolveCounters &cnt, hipStream_t s, double2 *Vb, Recycle *save, const Recycle *use) {
+                SolveCounters &cnt, hipStream_t s, double2 *Vb, Recycle *save, const Recycle *use,
+                double relax) {
     const int64_t n = p->m.n;
     const int ns = static_cast<int>(rhs.size());
     const int hs = m + 2;  // stride of per-slot coefficient vectors
@@ -884,7 +908,7 @@ int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
         g[sl][0] = beta0[sl];
         if (beta0[sl] <= ctol[sl] * rn[sl]) done[sl] = 1;  // the projection already solved it
     }
-    std::vector<double2> hb1, hb2;
+    std::vector<int32_t> live_prev;  // live list last uploaded to live_d
     std::vector<double> hbeta;
     int total = 0;
     for (int k = 0; k < m; ++k) {
@@ -897,11 +921,21 @@ int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
             }
         const int nl = static_cast<int>(live_rhs.size());
         if (nl == 0) break;
-        to_device(live_d, live_rhs, s);
-        // W = A v_k for the live right-hand sides
+        if (live_rhs != live_prev) {
+            to_device(live_d, live_rhs, s);
+            live_prev = live_rhs;
+        }
+        // W = A v_k for the live right-hand sides; with relaxed products the FP64
+        // operator while any live residual estimate is above its switch point
+        vsie_precision iprec = prec;
+        if (prec == VSIE_FP32 && relax > 0)
+            for (int l = 0; l < nl; ++l) {
+                const int sl = live_slot[l];
+                if (std::abs(g[sl][k]) > ctol[sl] * rn[sl] / relax) iprec = VSIE_FP64;
+            }
         bblas_gather(n, nl, live_d, V + static_cast<int64_t>(k) * R * n, n, X, s);
-        apply_op_graph(p, f, prec, adjoint, nl, X, n, W, n, s);
-        for (int r : live_rhs) (prec == VSIE_FP64 ? cnt.mv64 : cnt.mv32)[r]++;
+        apply_op_graph(p, f, iprec, adjoint, nl, X, n, W, n, s);
+        for (int r : live_rhs) (iprec == VSIE_FP64 ? cnt.mv64 : cnt.mv32)[r]++;
         if (use && kmax > 0) to_device(kc_d, live_kc, s);
         for (int pass = 0; pass < 2; ++pass) {
             double2 *h = pass == 0 ? h1 : h2;
@@ -934,12 +968,13 @@ int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
         }
         bblas_norm(n, nl, W, npart, nch, nrm, s);
         bblas_scale_into_basis(n, k + 1, R, nl, live_d, W, nrm, V, s);
-        hb1.resize(static_cast<size_t>(hs) * nl);
-        hb2.resize(static_cast<size_t>(hs) * nl);
-        hbeta.resize(nl);
-        VSIE_HIP(hipMemcpyAsync(hb1.data(), h1, sizeof(double2) * hs * nl, hipMemcpyDeviceToHost, s));
-        VSIE_HIP(hipMemcpyAsync(hb2.data(), h2, sizeof(double2) * hs * nl, hipMemcpyDeviceToHost, s));
-        VSIE_HIP(hipMemcpyAsync(hbeta.data(), nrm, sizeof(double) * nl, hipMemcpyDeviceToHost, s));
+        // both Gram-Schmidt passes' coefficients and the new norm, in one round trip
+        double2 *hb1 = static_cast<double2 *>(p->hpin.get(sizeof(double2) * (2 * static_cast<size_t>(hs) * nl + nl)));
+        double2 *hb2 = hb1 + static_cast<size_t>(hs) * nl;
+        double *hbeta = reinterpret_cast<double *>(hb2 + static_cast<size_t>(hs) * nl);
+        VSIE_HIP(hipMemcpyAsync(hb1, h1, sizeof(double2) * hs * nl, hipMemcpyDeviceToHost, s));
+        VSIE_HIP(hipMemcpyAsync(hb2, h2, sizeof(double2) * hs * nl, hipMemcpyDeviceToHost, s));
+        VSIE_HIP(hipMemcpyAsync(hbeta, nrm, sizeof(double) * nl, hipMemcpyDeviceToHost, s));
         VSIE_HIP(hipStreamSynchronize(s));
         for (int l = 0; l < nl; ++l) {
             const int sl = live_slot[l];
@@ -1097,7 +1132,7 @@ vsie_status solve_batch(vsie_problem *p, int f, vsie_precision prec, bool adjoin
                 continue;
             }
             double t = o.tol * bn[r] / rn[sl];
-            if (prec == VSIE_FP32) t = std::max(t, o.inner_tol);
+            if (prec == VSIE_FP32 && !(o.relax > 0 && !o.block)) t = std::max(t, o.inner_tol);
             next.push_back(r);
             keep_slot.push_back(sl);
             next_rn.push_back(rn[sl]);
@@ -1123,12 +1158,12 @@ vsie_status solve_batch(vsie_problem *p, int f, vsie_precision prec, bool adjoin
                                cnt, s);
         } else if (!have_first) {
             done = gmres_cycle(p, f, prec, adjoint, R, next, cyc_res, next_rn, next_tol, m, o.max_iter,
-                               x, ldx, cnt, s, V1, &first, nullptr);
+                               x, ldx, cnt, s, V1, &first, nullptr, o.relax);
             have_first = true;
         } else {
             double2 *V2 = static_cast<double2 *>(p->V2.get(static_cast<size_t>(col_bytes) * (m + 1)));
             done = gmres_cycle(p, f, prec, adjoint, R, next, cyc_res, next_rn, next_tol, m, o.max_iter,
-                               x, ldx, cnt, s, V2, nullptr, &first);
+                               x, ldx, cnt, s, V2, nullptr, &first, o.relax);
         }
         for (int r : next) xzero[r] = 0;
         if (done == 0) {  // breakdown at the first step for every rhs: no progress possible
@@ -1707,10 +1742,11 @@ vsie_status vsie_solve(vsie_problem *p, int32_t f, vsie_precision prec, int32_t 
         require(nrhs >= 1, "nrhs must be >= 1");
         check_vec(b, ldb, p->m.n, "b");
         check_vec(x, ldx, p->m.n, "x");
-        vsie_solve_opts o{1e-10, 3000, 500, 1e-5, 20, 0};
+        vsie_solve_opts o{1e-10, 3000, 500, 1e-5, 20, 0, 0.0};
         if (opts) o = *opts;
         require(o.tol > 0 && o.max_iter >= 0 && o.restart >= 1 && o.restart <= 20000 &&
-                    o.inner_tol > 0 && o.inner_tol < 1 && o.max_outer >= 1 && (o.block == 0 || o.block == 1),
+                    o.inner_tol > 0 && o.inner_tol < 1 && o.max_outer >= 1 && (o.block == 0 || o.block == 1) &&
+                    o.relax >= 0 && o.relax < 1,
                 "invalid solver options");
         hipStream_t s = as_stream(stream);
         const int R = static_cast<int>(nrhs);

@@ -510,3 +510,25 @@ def test_cell_face_pairs(V, name, prec):
     assert fused == (name in ("c0", "ragged", "cube"))
     assert e <= tol and e0 <= 2 * tol
     P.close()
+
+
+@pytest.mark.parametrize("name", ["c0", "lognormal", "cube"])
+def test_relaxed_products_solve(V, name):
+    """FP32 solves with relaxed products (FP64 operator while the residual is
+    high, FP32 after the switch point) reach the oracle's dense solution; both
+    operators are used, and a looser relax switches to FP32 no later."""
+    mesh, mat, k0 = case(name)
+    d = O.discretise(mesh, mat, k0)
+    b = O.plane_wave(d.pts, k0, W.fibonacci_sphere(2))
+    ref = O.solve_lu(d, b)
+    P = V.Problem.from_mesh(mesh, mat, [k0])
+    infos = []
+    for relax in (1e-7, 1e-5):
+        x, info = P.solve(dev(b).contiguous(), prec=V.VSIE_FP32, tol=1e-11, relax=relax)
+        say("  %s relax %.0e: %s" % (name, relax, info))
+        assert info["status"] == V.VSIE_OK
+        assert info["matvecs_fp64"] > 2 and info["matvecs_fp32"] > 0
+        assert O.rel_error(host(x), ref) <= TOL_SOLVE
+        infos.append(info)
+    assert infos[1]["matvecs_fp64"] >= infos[0]["matvecs_fp64"]
+    P.close()

@@ -27,9 +27,11 @@
 // gets exactly one partial per group: part[slot * ldp + p].  A reduction
 // kernel adds them in slot order (deterministic).
 //
-// Schedule: persistent grid, items cut into 8 contiguous ranges (one per
-// XCD, workgroup b runs on XCD b mod 8), every wave takes every W-th item of
-// its range.
+// Schedule: items cut into 8 contiguous ranges (one per XCD, workgroup b
+// runs on XCD b mod 8), one item per wave, so that the hardware dispatcher
+// balances the load.  (A persistent grid with a static split leaves the tail
+// to a few waves: the SIMD issues to its oldest wave first, so waves finish
+// one by one and the last wave on each SIMD runs nearly alone.)
 #include "pair_geom.h"
 #include "vsie_internal.h"
 
@@ -123,14 +125,16 @@ __global__ __launch_bounds__(kBlock) void sym_kernel(SymArgs a) {
     BTile &B = lb[wib];
 
     for (int64_t it = lo + w; it < hi; it += waves_x) {
-        // item -> (I, J), I <= J, row by row: row I holds groups - I items
-        int I = 0;
-        int64_t rem = it;
-        while (rem >= a.groups - I) {
-            rem -= a.groups - I;
-            ++I;
-        }
-        const int J = I + static_cast<int>(rem);
+        // item -> (I, J), I <= J, row by row: row I holds groups - I items and
+        // starts at S(I) = I (2 groups - I + 1) / 2; I is the root of S(I) = it,
+        // rounded down, then corrected in integers
+        const int64_t g2 = 2 * static_cast<int64_t>(a.groups) + 1;
+        int64_t r = static_cast<int64_t>((static_cast<double>(g2) - sqrt(static_cast<double>(g2 * g2 - 8 * it))) * 0.5);
+        r = r < 0 ? 0 : (r >= a.groups ? a.groups - 1 : r);
+        while (r > 0 && r * (g2 - r) / 2 > it) --r;
+        while (r + 1 < a.groups && (r + 1) * (g2 - r - 1) / 2 <= it) ++r;
+        const int I = static_cast<int>(r);
+        const int J = static_cast<int>(r + (it - r * (g2 - r) / 2));
 
         double accAr[G], accAi[G], accBr[G], accBi[G];
 #pragma unroll
@@ -451,6 +455,15 @@ const void *pick_sym(int g, bool f32) {
     return nullptr;
 }
 
+// Workgroups for one item per wave: 8 XCD ranges of at most ceil(items / 8)
+// items, kWavesPerBlock waves per workgroup, workgroup b on range b mod 8.
+int64_t one_item_per_wave_grid(int64_t items) {
+    const int64_t per_xcd = (items + kXcds - 1) / kXcds;
+    const int64_t grid = kXcds * std::max<int64_t>(1, (per_xcd + kWavesPerBlock - 1) / kWavesPerBlock);
+    if (grid > 0x7fffffff) fail(VSIE_E_INVALID, "pair kernel: too many work items for one launch");
+    return grid;
+}
+
 }  // namespace
 
 bool sym_groups_ok(int g) { return g == 2 || g == 4 || g == 8; }
@@ -480,25 +493,8 @@ void launch_sym(const SymJob &J, hipStream_t s, PairProfiler *prof) {
     a.part = J.part;
     a.ldp = J.ldp;
     if (J.ldp < J.ng) fail(VSIE_E_INVALID, "symmetric pair kernel: partial stride below the cell count");
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0;
-        VSIE_HIP(hipGetDevice(&dev));
-        VSIE_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    }
     const void *kp = pick_sym(J.g, f32);
-    static int occ_cache[9][2] = {};
-    int &occ = occ_cache[J.g][f32 ? 1 : 0];
-    if (!occ) {
-        VSIE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kp, kBlock, 0));
-        occ = std::max(1, occ);
-    }
-    // every resident wave (fewer, evenly loaded waves measured slower), but no
-    // more waves than items
-    int64_t grid = static_cast<int64_t>(cus) * occ;
-    const int64_t need = (a.items + kWavesPerBlock - 1) / kWavesPerBlock;
-    grid = std::min<int64_t>(grid, ((need + kXcds - 1) / kXcds) * kXcds);
-    grid = std::max<int64_t>(kXcds, (grid / kXcds) * kXcds);
+    const int64_t grid = one_item_per_wave_grid(a.items);
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (prof && prof->on) {
         ev0 = prof_take_event(prof);
@@ -553,24 +549,9 @@ void launch_cf(const CfJob &J, hipStream_t s, PairProfiler *prof) {
     a.ldc = J.nc;
     a.pf = J.pf;
     a.ldf = J.nf;
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0;
-        VSIE_HIP(hipGetDevice(&dev));
-        VSIE_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    }
     const void *kp = f32 ? reinterpret_cast<const void *>(&cf_kernel<kCfGroup, float>)
                          : reinterpret_cast<const void *>(&cf_kernel<kCfGroup, double>);
-    static int occ_cache[2] = {0, 0};
-    int &occ = occ_cache[f32 ? 1 : 0];
-    if (!occ) {
-        VSIE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kp, kBlock, 0));
-        occ = std::max(1, occ);
-    }
-    int64_t grid = static_cast<int64_t>(cus) * occ;
-    const int64_t need = (a.items + kWavesPerBlock - 1) / kWavesPerBlock;
-    grid = std::min<int64_t>(grid, ((need + kXcds - 1) / kXcds) * kXcds);
-    grid = std::max<int64_t>(kXcds, (grid / kXcds) * kXcds);
+    const int64_t grid = one_item_per_wave_grid(a.items);
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (prof && prof->on) {
         ev0 = prof_take_event(prof);

@@ -481,7 +481,18 @@ void apply_forward_sym(vsie_problem *p, int f, vsie_precision prec, const double
                       p->m.diag + static_cast<int64_t>(f) * n, x, y, s);
 }
 
-bool use_sym(const vsie_problem *p, int nrhs) { return nrhs == 1 && p->tune.sym_groups > 0 && p->g_is_cells; }
+// The once-per-pair kernels write one FP64 partial per point and partner
+// group; above this size (c4-scale meshes) the one-sided kernels are used.
+constexpr double kSymPartialCap = 8.0 * (1 << 30);
+
+bool use_sym(const vsie_problem *p, int nrhs) {
+    if (nrhs != 1 || p->tune.sym_groups <= 0 || !p->g_is_cells) return false;
+    const int64_t nv = p->m.n_vol, ns = p->m.n - nv;
+    double bytes = static_cast<double>(sym_slots(nv, p->tune.sym_groups)) * nv;
+    if (p->tune.cell_face && p->f_is_faces)
+        bytes += static_cast<double>(cf_groups(ns)) * nv + static_cast<double>(cf_groups(nv)) * ns;
+    return bytes * sizeof(double2) <= kSymPartialCap;
+}
 
 void apply_forward(vsie_problem *p, int f, vsie_precision prec, int nrhs, const double2 *x,
                    int64_t ldx, double2 *y, int64_t ldy, hipStream_t s) {

@@ -1,5 +1,5 @@
 // FP32 forward pair sums on the matrix cores of gfx950, for blocks of
-// right-hand sides and several frequencies in one persistent launch.
+// right-hand sides and several frequencies in one launch.
 //
 // The forward product of one source class is a complex matrix product
 //   Y(targets x rhs) = K(targets x sources) Q(sources x rhs)
@@ -14,20 +14,20 @@
 // real products make the complex one:
 //   Yr += Kr Qr - Ki Qi,   Yi += Kr Qi + Ki Qr.
 // The VALU cost per pair (FP64 distance and phase, FP32 amplitude, sin, cos)
-// no longer grows with the number of right-hand sides: the multiply-adds run
-// on the matrix cores, next to the VALU work of the other waves.
+// no longer grows with the number of right-hand sides: one kernel value
+// serves 16 (or 32) columns, whose multiply-adds run on the matrix cores.
 //
 // Accumulation: FP32 inside the matrix core over sub-tiles of kSubTile
 // sources, then added into FP64 registers; one FP64 partial per (frequency,
 // column, chunk, target), summed in chunk order by the reduction kernel.
 //
-// Schedule: a persistent grid of 8 m workgroups.  Work items are (frequency,
-// column block, source chunk, target tile) with the target tile fastest; the
-// item list is cut into 8 contiguous ranges, one per XCD (workgroup b runs on
-// XCD b mod 8), so the waves of one XCD walk neighbouring target tiles of the
-// same source chunk and share its positions and charges in their L2.  Each
-// wave takes every W-th item of its XCD's range (W = waves per XCD): a static
-// schedule with no atomics, so every wave reaches the end of its range.
+// Schedule: work items are (frequency, column block, source chunk, target
+// tile) with the target tile fastest; the item list is cut into 8 contiguous
+// ranges, one per XCD (workgroup b runs on XCD b mod 8), so the waves of one
+// XCD walk neighbouring target tiles of the same source chunk and share its
+// positions and charges in their L2.  Wave w of an XCD takes items w, w + W,
+// ... of its range (W = waves per XCD); by default the grid gives every wave
+// one item and the hardware dispatcher balances the load.
 #include "pair_geom.h"
 #include "vsie_internal.h"
 
@@ -316,7 +316,7 @@ void launch_mfma_forward(const MfmaJob &J, hipStream_t s, PairProfiler *prof) {
     a.out = J.out;
     a.out_fstride = J.out_fstride;
     a.part0 = J.part0;
-    const int grid = J.grid > 0 ? J.grid : mfma_grid(J.tg, J.nb);
+    const int64_t grid = J.grid > 0 ? J.grid : one_item_per_wave_grid(a.items);
     if (grid % kXcds != 0) fail(VSIE_E_INVALID, "matrix-core pair kernel: grid must be a multiple of 8");
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (prof && prof->on) {

@@ -455,6 +455,8 @@ const void *pick_sym(int g, bool f32) {
     return nullptr;
 }
 
+}  // namespace
+
 // Workgroups for one item per wave: 8 XCD ranges of at most ceil(items / 8)
 // items, kWavesPerBlock waves per workgroup, workgroup b on range b mod 8.
 int64_t one_item_per_wave_grid(int64_t items) {
@@ -463,8 +465,6 @@ int64_t one_item_per_wave_grid(int64_t items) {
     if (grid > 0x7fffffff) fail(VSIE_E_INVALID, "pair kernel: too many work items for one launch");
     return grid;
 }
-
-}  // namespace
 
 bool sym_groups_ok(int g) { return g == 2 || g == 4 || g == 8; }
 

@@ -124,7 +124,7 @@ hipEvent_t prof_take_event(PairProfiler *prof);
 // chunk c, column col < nrhs and target i:
 //   out[fl * out_fstride + (part0 + c) * nrhs * n_t + col * n_t + i].
 // tg: 16-target groups per wave (2 or 4); nb: 16-column blocks per item (1 or 2);
-// grid: workgroups (a multiple of 8; 0 = occupancy-filling).
+// grid: workgroups (a multiple of 8; 0 = one item per wave).
 struct MfmaJob {
     int cls;
     int64_t n_t;
@@ -146,6 +146,9 @@ struct MfmaJob {
 void launch_mfma_forward(const MfmaJob &J, hipStream_t s, PairProfiler *prof);
 bool mfma_variant_ok(int tg, int nb);
 int mfma_grid(int tg, int nb);
+// Workgroups (a multiple of 8) that give each wave of an XCD-ranged item list
+// at most one item.
+int64_t one_item_per_wave_grid(int64_t items);
 // q[fl * ldq_f + jj * ncol + col] = scale x[fl * xfs + col * ldx + idx[jj]] for col < nrhs, else 0;
 // scale = -s'_f for class G (sp + fl * sp_fstride), 1 for class F
 void launch_pack_mfma(SrcClass cls, const SourceSet &src, const double *sp, int64_t sp_fstride, int nf,

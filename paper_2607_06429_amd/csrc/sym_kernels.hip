@@ -222,36 +222,64 @@ __global__ __launch_bounds__(kBlock) void sym_kernel(SymArgs a) {
     }
 }
 
-// y = diag x + (cells: sum of the symmetric slots; faces: sum of the one-sided
-// single-layer chunk partials) + sum of the double-layer chunk partials
-__global__ void sym_reduce_kernel(int64_t n, int64_t n_vol, int n_slots, const double2 *__restrict__ sym,
-                                  int64_t ldp, int n_face_parts, const double2 *__restrict__ face, int n_f_parts,
-                                  const double2 *__restrict__ fpart, const double2 *__restrict__ diag,
-                                  const double2 *__restrict__ x, double2 *__restrict__ y) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (i >= n) return;
+// The partial sums a point receives, as one list of slots from two arrays:
+// slot t < na is a[t * lda + offa + p], slot na + t is b[t * ldb + offb + p]
+// (p: index of the point within its class, cells or faces).
+struct SlotList {
+    const double2 *a;
+    int na;
+    int64_t lda, offa;
+    const double2 *b;
+    int nb;
+    int64_t ldb, offb;
+};
+
+// y = diag x + the sum of each point's slots.  A workgroup takes 64 points of
+// one class (cells: workgroups 0 .. cell_blocks-1, then faces); wave w adds
+// the w-th quarter of the slots, and the four quarter sums are added in wave
+// order, so the order of the additions is fixed.  Four waves per 64 points
+// keep enough loads in flight to stream the partials at HBM speed.
+__global__ __launch_bounds__(kBlock) void slot_reduce_kernel(int64_t n, int64_t nc, int64_t cell_blocks,
+                                                             SlotList cells, SlotList faces,
+                                                             const double2 *__restrict__ diag,
+                                                             const double2 *__restrict__ x, double2 *__restrict__ y) {
+    __shared__ double2 red[kWavesPerBlock][64];
+    const int lane = threadIdx.x & 63;
+    const int w = static_cast<int>(threadIdx.x) >> 6;
+    const bool cell = blockIdx.x < cell_blocks;
+    const int64_t p = (cell ? static_cast<int64_t>(blockIdx.x) : static_cast<int64_t>(blockIdx.x) - cell_blocks) * 64 + lane;
+    const int64_t count = cell ? nc : n - nc;
+    const SlotList &L = cell ? cells : faces;
+    const int total = L.na + L.nb;
+    const int t0 = static_cast<int>(static_cast<int64_t>(total) * w / kWavesPerBlock);
+    const int t1 = static_cast<int>(static_cast<int64_t>(total) * (w + 1) / kWavesPerBlock);
     double sr = 0.0, si = 0.0;
-    if (i < n_vol) {
-        for (int t = 0; t < n_slots; ++t) {
-            const double2 v = sym[static_cast<int64_t>(t) * ldp + i];
+    if (p < count) {
+        const int ea = t1 < L.na ? t1 : L.na;
+#pragma unroll 4
+        for (int t = t0; t < ea; ++t) {
+            const double2 v = L.a[static_cast<int64_t>(t) * L.lda + L.offa + p];
             sr += v.x;
             si += v.y;
         }
-    } else {
-        const int64_t nf = n - n_vol;
-        for (int c = 0; c < n_face_parts; ++c) {
-            const double2 v = face[static_cast<int64_t>(c) * nf + (i - n_vol)];
+#pragma unroll 4
+        for (int t = (t0 > L.na ? t0 : L.na); t < t1; ++t) {
+            const double2 v = L.b[static_cast<int64_t>(t - L.na) * L.ldb + L.offb + p];
             sr += v.x;
             si += v.y;
         }
     }
-    for (int c = 0; c < n_f_parts; ++c) {
-        const double2 v = fpart[static_cast<int64_t>(c) * n + i];
-        sr += v.x;
-        si += v.y;
+    red[w][lane] = make_double2(sr, si);
+    __syncthreads();
+    if (w == 0 && p < count) {
+        for (int q = 1; q < kWavesPerBlock; ++q) {
+            sr += red[q][lane].x;
+            si += red[q][lane].y;
+        }
+        const int64_t i = cell ? p : nc + p;
+        const double2 d = diag[i], xv = x[i];
+        y[i] = make_double2(d.x * xv.x - d.y * xv.y + sr, d.x * xv.y + d.y * xv.x + si);
     }
-    const double2 d = diag[i], xv = x[i];
-    y[i] = make_double2(d.x * xv.x - d.y * xv.y + sr, d.x * xv.y + d.y * xv.x + si);
 }
 
 // ---------------------------------------------------------------------------
@@ -406,43 +434,6 @@ __global__ __launch_bounds__(kBlock) void cf_kernel(CfArgs a) {
     }
 }
 
-// y = diag x + (cells: symmetric slots + cell-face slots; faces: cell-face
-// slots + face-face chunk partials); one right-hand side
-__global__ void cf_reduce_kernel(int64_t n, int64_t nc, int n_sym, const double2 *__restrict__ sym, int n_cs,
-                                 const double2 *__restrict__ pc, int n_fs, const double2 *__restrict__ pf,
-                                 int n_ff, const double2 *__restrict__ ff, const double2 *__restrict__ diag,
-                                 const double2 *__restrict__ x, double2 *__restrict__ y) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (i >= n) return;
-    double sr = 0.0, si = 0.0;
-    if (i < nc) {
-        for (int t = 0; t < n_sym; ++t) {
-            const double2 v = sym[static_cast<int64_t>(t) * nc + i];
-            sr += v.x;
-            si += v.y;
-        }
-        for (int t = 0; t < n_cs; ++t) {
-            const double2 v = pc[static_cast<int64_t>(t) * nc + i];
-            sr += v.x;
-            si += v.y;
-        }
-    } else {
-        const int64_t nf = n - nc, f = i - nc;
-        for (int t = 0; t < n_fs; ++t) {
-            const double2 v = pf[static_cast<int64_t>(t) * nf + f];
-            sr += v.x;
-            si += v.y;
-        }
-        for (int c = 0; c < n_ff; ++c) {
-            const double2 v = ff[static_cast<int64_t>(c) * nf + f];
-            sr += v.x;
-            si += v.y;
-        }
-    }
-    const double2 d = diag[i], xv = x[i];
-    y[i] = make_double2(d.x * xv.x - d.y * xv.y + sr, d.x * xv.y + d.y * xv.x + si);
-}
-
 template <int G, typename AT>
 const void *sym_ptr() {
     return reinterpret_cast<const void *>(&sym_kernel<G, AT>);
@@ -453,6 +444,16 @@ const void *pick_sym(int g, bool f32) {
     if (g == 4) return f32 ? sym_ptr<4, float>() : sym_ptr<4, double>();
     if (g == 8) return f32 ? sym_ptr<8, float>() : sym_ptr<8, double>();
     return nullptr;
+}
+
+void launch_slot_reduce(int64_t n, int64_t nc, const SlotList &cells, const SlotList &faces,
+                        const double2 *diag, const double2 *x, double2 *y, hipStream_t s) {
+    const int64_t cell_blocks = (nc + 63) / 64, face_blocks = (n - nc + 63) / 64;
+    const int64_t blocks = cell_blocks + face_blocks;
+    if (blocks > 0x7fffffff) fail(VSIE_E_INVALID, "slot reduction: too many points");
+    hipLaunchKernelGGL(slot_reduce_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, n, nc,
+                       cell_blocks, cells, faces, diag, x, y);
+    VSIE_HIP(hipGetLastError());
 }
 
 }  // namespace
@@ -511,13 +512,16 @@ void launch_sym(const SymJob &J, hipStream_t s, PairProfiler *prof) {
     }
 }
 
+// y = diag x + (cells: symmetric slots; faces: one-sided single-layer chunk
+// partials) + the double-layer chunk partials (stride n, global index)
 void launch_sym_reduce(int64_t n, int64_t n_vol, int n_slots, const double2 *sym, int64_t ldp, int n_face_parts,
                        const double2 *face, int n_f_parts, const double2 *fpart, const double2 *diag,
                        const double2 *x, double2 *y, hipStream_t s) {
     if (n == 0) return;
-    hipLaunchKernelGGL(sym_reduce_kernel, dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                       n, n_vol, n_slots, sym, ldp, n_face_parts, face, n_f_parts, fpart, diag, x, y);
-    VSIE_HIP(hipGetLastError());
+    const int64_t nf = n - n_vol;
+    const SlotList cells{sym, n_slots, ldp, 0, fpart, n_f_parts, n, 0};
+    const SlotList faces{face, n_face_parts, nf, 0, fpart, n_f_parts, n, n_vol};
+    launch_slot_reduce(n, n_vol, cells, faces, diag, x, y, s);
 }
 
 int64_t cf_groups(int64_t count) { return ((count + 63) / 64 + kCfGroup - 1) / kCfGroup; }
@@ -568,13 +572,16 @@ void launch_cf(const CfJob &J, hipStream_t s, PairProfiler *prof) {
     }
 }
 
+// y = diag x + (cells: symmetric slots + cell-face slots; faces: cell-face
+// slots + face-face chunk partials); one right-hand side
 void launch_cf_reduce(int64_t n, int64_t nc, int n_sym, const double2 *sym, int n_cs, const double2 *pc, int n_fs,
                       const double2 *pf, int n_ff, const double2 *ff, const double2 *diag, const double2 *x,
                       double2 *y, hipStream_t s) {
     if (n == 0) return;
-    hipLaunchKernelGGL(cf_reduce_kernel, dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                       n, nc, n_sym, sym, n_cs, pc, n_fs, pf, n_ff, ff, diag, x, y);
-    VSIE_HIP(hipGetLastError());
+    const int64_t nf = n - nc;
+    const SlotList cells{sym, n_sym, nc, 0, pc, n_cs, nc, 0};
+    const SlotList faces{pf, n_fs, nf, 0, ff, n_ff, nf, 0};
+    launch_slot_reduce(n, nc, cells, faces, diag, x, y, s);
 }
 
 }  // namespace vsie

@@ -126,6 +126,29 @@ __global__ void pack_kernel(int64_t count, const int32_t *__restrict__ idx,
     }
 }
 
+// Both source classes in one launch: threads 0 .. cg-1 pack the single-layer
+// charges (as pack_kernel with sp), the next cf threads the double-layer ones.
+template <typename C2>
+__global__ void pack2_kernel(int64_t cg, const int32_t *__restrict__ idxg, const double *__restrict__ sp,
+                             int64_t cf, const int32_t *__restrict__ idxf, int nrhs,
+                             const double2 *__restrict__ x, int64_t ldx, bool conj_in, C2 *__restrict__ outg,
+                             C2 *__restrict__ outf) {
+    int64_t jj = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+    const bool g = jj < cg;
+    if (!g) jj -= cg;
+    if (!g && jj >= cf) return;
+    const int32_t *idx = g ? idxg : idxf;
+    const int64_t count = g ? cg : cf;
+    const int64_t j = idx ? idx[jj] : jj;
+    const double sc = g ? -sp[j] : 1.0;
+    C2 *out = g ? outg : outf;
+    for (int r = 0; r < nrhs; ++r) {
+        double2 v = x[j + r * ldx];
+        if (conj_in) v.y = -v.y;
+        out[jj + r * count] = to_c2<C2>(sc * v.x, sc * v.y);
+    }
+}
+
 // y[i + r ldy] = d_i x[i + r ldx] + sum_c partial[(c nrhs + r) n_t + i],
 // d_i = diag[i] (conjugated when conj_diag); diag == nullptr means d_i = 0.
 __global__ void reduce_kernel(int64_t n_t, int nrhs, int n_parts, const double2 *__restrict__ part,
@@ -539,6 +562,21 @@ void launch_pack_charges(SrcClass cls, vsie_precision prec, const SourceSet &src
         hipLaunchKernelGGL(pack_kernel<float2>, dim3(blocks_for(src.count)), dim3(kT), 0, s,
                            src.count, src.idx, sc, nrhs, x, ldx, conj_in,
                            static_cast<float2 *>(charge));
+    LAUNCH_CHECK();
+}
+
+void launch_pack_both(vsie_precision prec, const SourceSet &G, const SourceSet &F, const double *sp_f, int nrhs,
+                      const double2 *x, int64_t ldx, bool conj_in, void *chargeG, void *chargeF, hipStream_t s) {
+    const int64_t total = G.count + F.count;
+    if (total == 0) return;
+    if (prec == VSIE_FP64)
+        hipLaunchKernelGGL(pack2_kernel<double2>, dim3(blocks_for(total)), dim3(kT), 0, s, G.count, G.idx, sp_f,
+                           F.count, F.idx, nrhs, x, ldx, conj_in, static_cast<double2 *>(chargeG),
+                           static_cast<double2 *>(chargeF));
+    else
+        hipLaunchKernelGGL(pack2_kernel<float2>, dim3(blocks_for(total)), dim3(kT), 0, s, G.count, G.idx, sp_f,
+                           F.count, F.idx, nrhs, x, ldx, conj_in, static_cast<float2 *>(chargeG),
+                           static_cast<float2 *>(chargeF));
     LAUNCH_CHECK();
 }
 

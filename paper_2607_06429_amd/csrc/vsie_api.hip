@@ -117,7 +117,7 @@ struct vsie_problem {
     std::vector<void *> owned;  // permanent device allocations
     Scratch partial, chargeG, chargeF, chargeAll, sums_part, grad_work;
     // Krylov workspace
-    Scratch V, V2, w, r, ax, h1, h2, tc, nrm, dpart, npart, yv, act, act2, live, kd, kc, xa, axa, rres;
+    Scratch V, V2, w, r, ax, h1, tc, nrm, dpart, npart, yv, act, act2, live, kd, kc, xa, axa, rres;
     Scratch bh, bg, bsk;  // block GMRES: Hessenberg block column, Gram / inverse factor, slab partials
     HostPinned hpin;      // per-iteration Hessenberg columns and norms on their way to the host
     PairProfiler prof;
@@ -198,7 +198,7 @@ struct vsie_problem {
         hpin.release();
         for (void *p : owned) (void)hipFree(p);
         for (Scratch *s : {&partial, &chargeG, &chargeF, &chargeAll, &sums_part, &grad_work, &V, &V2, &w, &r, &ax,
-                           &h1, &h2, &tc, &nrm, &dpart, &npart, &yv, &act, &act2, &live, &kd, &kc, &xa, &axa,
+                           &h1, &tc, &nrm, &dpart, &npart, &yv, &act, &act2, &live, &kd, &kc, &xa, &axa,
                            &rres, &bh, &bg, &bsk})
             s->release();
     }
@@ -424,8 +424,7 @@ void apply_forward_cf(vsie_problem *p, int f, vsie_precision prec, const double2
     void *qG = p->chargeG.get(csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->G.count)));
     void *qF = p->chargeF.get(csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->F.count)));
     const double *spf = p->m.sp + static_cast<int64_t>(f) * n;
-    launch_pack_charges(kClassG, prec, p->G, spf, 1, x, n, false, qG, s);
-    launch_pack_charges(kClassF, prec, p->F, spf, 1, x, n, false, qF, s);
+    launch_pack_both(prec, p->G, p->F, spf, 1, x, n, false, qG, qF, s);
     const double k = p->k0[f];
     SymJob J{prec, nv, p->m.px, p->m.py, p->m.pz, qG, k, {p->far[0], p->far[1], p->far[2]}, p->far_step, g, psym, nv};
     launch_sym(J, s, &p->prof);
@@ -461,8 +460,7 @@ void apply_forward_sym(vsie_problem *p, int f, vsie_precision prec, const double
     void *qG = p->chargeG.get(csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->G.count)));
     void *qF = p->chargeF.get(csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->F.count)));
     const double *spf = p->m.sp + static_cast<int64_t>(f) * n;
-    launch_pack_charges(kClassG, prec, p->G, spf, 1, x, n, false, qG, s);
-    launch_pack_charges(kClassF, prec, p->F, spf, 1, x, n, false, qF, s);
+    launch_pack_both(prec, p->G, p->F, spf, 1, x, n, false, qG, qF, s);
     const double k = p->k0[f];
     SymJob J{prec, nv, p->m.px, p->m.py, p->m.pz, qG, k, {p->far[0], p->far[1], p->far[2]}, p->far_step, g, psym, nv};
     launch_sym(J, s, &p->prof);
@@ -850,8 +848,12 @@ int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
     double2 *V = Vb;
     double2 *W = static_cast<double2 *>(p->w.get(sizeof(double2) * static_cast<size_t>(n) * ns));
     double2 *X = static_cast<double2 *>(p->ax.get(sizeof(double2) * static_cast<size_t>(n) * ns));
-    double2 *h1 = static_cast<double2 *>(p->h1.get(sizeof(double2) * static_cast<size_t>(hs) * ns));
-    double2 *h2 = static_cast<double2 *>(p->h2.get(sizeof(double2) * static_cast<size_t>(hs) * ns));
+    // both Gram-Schmidt passes' coefficients and the new norms in one block, so
+    // that one copy brings an iteration's Hessenberg column to the host
+    const size_t hcol_bytes = sizeof(double2) * 2 * static_cast<size_t>(hs) * ns + sizeof(double) * ns;
+    double2 *h1 = static_cast<double2 *>(p->h1.get(hcol_bytes));
+    double2 *h2 = h1 + static_cast<size_t>(hs) * ns;
+    double *hn = reinterpret_cast<double *>(h2 + static_cast<size_t>(hs) * ns);
     double2 *tc = static_cast<double2 *>(p->tc.get(sizeof(double2) * static_cast<size_t>(cs_) * ns));
     const int nch = norm_chunks(n);
     double2 *dpart = static_cast<double2 *>(
@@ -977,15 +979,13 @@ int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
             bblas_dots(n, k + 1, R, nl, live_d, V, W, dpart, nch, h, hs, s);
             bblas_gemv_sub(n, k + 1, R, nl, live_d, V, h, hs, W, s);
         }
-        bblas_norm(n, nl, W, npart, nch, nrm, s);
-        bblas_scale_into_basis(n, k + 1, R, nl, live_d, W, nrm, V, s);
-        // both Gram-Schmidt passes' coefficients and the new norm, in one round trip
-        double2 *hb1 = static_cast<double2 *>(p->hpin.get(sizeof(double2) * (2 * static_cast<size_t>(hs) * nl + nl)));
-        double2 *hb2 = hb1 + static_cast<size_t>(hs) * nl;
-        double *hbeta = reinterpret_cast<double *>(hb2 + static_cast<size_t>(hs) * nl);
-        VSIE_HIP(hipMemcpyAsync(hb1, h1, sizeof(double2) * hs * nl, hipMemcpyDeviceToHost, s));
-        VSIE_HIP(hipMemcpyAsync(hb2, h2, sizeof(double2) * hs * nl, hipMemcpyDeviceToHost, s));
-        VSIE_HIP(hipMemcpyAsync(hbeta, nrm, sizeof(double) * nl, hipMemcpyDeviceToHost, s));
+        bblas_norm(n, nl, W, npart, nch, hn, s);
+        bblas_scale_into_basis(n, k + 1, R, nl, live_d, W, hn, V, s);
+        // both Gram-Schmidt passes' coefficients and the new norm, in one copy
+        double2 *hb1 = static_cast<double2 *>(p->hpin.get(hcol_bytes));
+        double2 *hb2 = hb1 + static_cast<size_t>(hs) * ns;
+        double *hbeta = reinterpret_cast<double *>(hb2 + static_cast<size_t>(hs) * ns);
+        VSIE_HIP(hipMemcpyAsync(hb1, h1, hcol_bytes, hipMemcpyDeviceToHost, s));
         VSIE_HIP(hipStreamSynchronize(s));
         for (int l = 0; l < nl; ++l) {
             const int sl = live_slot[l];

@@ -216,6 +216,9 @@ void launch_weights(const DeviceMesh &m, const double *k0, int n_freq, hipStream
 void launch_pack_charges(SrcClass cls, vsie_precision prec, const SourceSet &src,
                          const double *sp_f, int nrhs, const double2 *x, int64_t ldx,
                          bool conj_in, void *charge, hipStream_t s);
+// launch_pack_charges for both classes (G with sp_f) in one launch
+void launch_pack_both(vsie_precision prec, const SourceSet &G, const SourceSet &F, const double *sp_f, int nrhs,
+                      const double2 *x, int64_t ldx, bool conj_in, void *chargeG, void *chargeF, hipStream_t s);
 // charge[r * n + j] = x[j + r ldx] (conjugated when conj_in)
 void launch_pack_plain(vsie_precision prec, int64_t n, int nrhs, const double2 *x, int64_t ldx,
                        bool conj_in, void *charge, hipStream_t s);

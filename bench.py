@@ -18,7 +18,7 @@ Unless --no-batched is given, the line also carries the batched workloads
 grid (n = 116,445) solved by block GMRES with the assembled FP32 operator and
 matrix-free, and one multi-frequency FP32 product of the cube-with-ellipsoid
 medium on the 100^3 grid (n = 1,076,336), 8 wavenumbers x 16 directions in
-one persistent launch per source class.
+one matrix-core launch per source class.
 """
 from __future__ import annotations
 
@@ -179,7 +179,7 @@ def batched_workloads(V, W):
     P.profile(False)
     out["c4_multi_frequency_product"] = {
         "workload": "cube with ellipsoid, 100^3 grid, n=%d, k0 = %s, %d directions each, FP32 operator, "
-                    "one persistent matrix-core launch per source class" % (n, k0s, R),
+                    "one matrix-core launch per source class" % (n, k0s, R),
         "product_s": dt, "gpair_col_evals_per_s": float(n) * n * nf * R / dt / 1e9,
         "tuning": P.tuning,
         "pair_kernels": {k: {"launches": v["launches"], "ms": v["ms"]} for k, v in st.items()}}

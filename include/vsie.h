@@ -128,7 +128,7 @@ vsie_status vsie_matvec_adjoint(vsie_problem *p, int32_t f, vsie_precision prec,
  * y hold nf consecutive blocks of nrhs columns, block t (frequency f0 + t)
  * starting at column t nrhs (same layout rules as vsie_matvec).  With
  * VSIE_FP32 and nrhs >= the tuning's mfma_min_rhs, each source class runs in
- * one persistent matrix-core launch over all nf frequencies; otherwise the
+ * one matrix-core launch over all nf frequencies; otherwise the
  * frequencies are applied one after the other. */
 vsie_status vsie_matvec_multi(vsie_problem *p, int32_t f0, int32_t nf, vsie_precision prec, int64_t nrhs,
                               const double *x, int64_t ldx, double *y, int64_t ldy, void *stream);
@@ -139,15 +139,17 @@ vsie_status vsie_matvec_multi(vsie_problem *p, int32_t f0, int32_t nf, vsie_prec
  * vsie_solve) with at least mfma_min_rhs right-hand sides evaluate each pair
  * kernel once on the vector ALUs and apply it to 16-column blocks of
  * right-hand sides on the matrix cores (v_mfma_f32_16x16x4_f32, FP32
- * accumulation over tiles of 128 sources, then FP64), in a persistent grid
- * whose work items are (frequency, column block, source chunk, target tile).
+ * accumulation over tiles of 128 sources, then FP64), in one launch whose
+ * work items are (frequency, column block, source chunk, target tile), one
+ * item per wave.
  * Other products use the vector pair kernel, one thread per target. */
 typedef struct {
     int32_t mfma_min_rhs;      /* 0 = never use the matrix cores; default 8 */
     int32_t mfma_tg;           /* 16-target groups per wave: 2 or 4; default 2 */
     int32_t mfma_nb;           /* 16-column blocks per work item: 1 or 2; default 1 */
-    int32_t items_per_wave;    /* work items per wave of the persistent grid, which
-                                  sets the source chunk length (>= 1); default 16 */
+    int32_t items_per_wave;    /* matrix-core work items per wave the chip holds at
+                                  once, which sets the source chunk length (>= 1);
+                                  default 16 */
     int64_t vec_target_waves;  /* waves per vector pair launch, which sets its source
                                   chunk length (>= 1024); default 32768 */
     int32_t graph;             /* 1: inside vsie_solve, each operator application of

@@ -596,7 +596,7 @@ void apply_dense(vsie_problem *p, int f, bool adjoint, int nrhs, const double2 *
 
 // FP32 forward products on the matrix cores for the nf frequencies f0 ..:
 // y_t = A_{f0+t} x_t, x_t = x + t xfs, y_t = y + t yfs, at most kMfmaMaxCols
-// columns per pass.  Each source class is one persistent launch over all
+// columns per pass.  Each source class is one launch over all
 // frequencies; the partial sums of every frequency are then reduced with its
 // FP64 diagonal.
 constexpr int kMfmaMaxCols = 128;

@@ -117,7 +117,7 @@ hipEvent_t prof_take_event(PairProfiler *prof);
 
 // FP32 forward pair sums of one source class on the matrix cores
 // (mfma_kernels.hip), for nf frequencies and a block of right-hand sides in
-// one persistent launch.  Targets are the n_t collocation points.  Charges
+// one launch.  Targets are the n_t collocation points.  Charges
 // are source-major, ncol (a multiple of 16 nb) columns per source,
 // q[fl * ldq_f + j * ncol + col], with kMfmaPad zero rows after n_s; chunk
 // is a multiple of 4.  Output, for

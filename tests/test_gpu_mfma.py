@@ -73,7 +73,7 @@ def test_mfma_zero_and_unit_columns(V):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_matvec_multi_frequency(V, prec):
-    """Three frequencies in one call (one persistent launch per source class
+    """Three frequencies in one call (one launch per source class
     on the FP32 path), each block against the oracle of its frequency."""
     mesh, mat, _ = case("cube")
     ks = [12.0, 9.5, 4.0]

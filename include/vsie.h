@@ -283,15 +283,18 @@ vsie_status vsie_param_gradient(vsie_problem *p, int32_t f, int64_t nrhs, const 
                                 void *stream);
 
 /* Assembled FP32 operator (the dense block system of section 2.3.4 written
- * once to memory).  Fills `dense`, caller-owned DEVICE memory of ld * n
- * complex64 values (interleaved float re, im; column-major, ld >= n), with
- * the off-diagonal entries A_ij of frequency f, computed with the FP64 pair
- * terms and rounded to FP32 (diagonal entries 0).  Until vsie_release_dense
- * or vsie_set_materials, every VSIE_FP32 product at frequency f (vsie_matvec,
- * vsie_matvec_adjoint and the inner solves of vsie_solve) multiplies by this
- * matrix with a complex GEMM (rocBLAS, matrix cores): FP32 partial products
- * over chunks of 8192 columns, added in FP64 with the FP64 diagonal.  The
- * memory must stay valid while in use; n and ld must be below 2^31. */
+ * once to memory).  Fills `dense`, caller-owned DEVICE memory of 2 * ld * n
+ * floats (8 * ld * n bytes), with the off-diagonal entries A_ij of frequency
+ * f, computed with the FP64 pair terms and rounded to FP32 (diagonal entries
+ * 0), in two column-major planes with leading dimension ld >= n: the real
+ * parts at dense[i + j ld], the imaginary parts at dense[ld n + i + j ld].
+ * Until vsie_release_dense or vsie_set_materials, every VSIE_FP32 product at
+ * frequency f (vsie_matvec, vsie_matvec_adjoint and the inner solves of
+ * vsie_solve) multiplies by this matrix: per slab of 8192 columns (rows for
+ * the adjoint) two real GEMMs (rocBLAS, FP32 on the matrix cores), each plane
+ * times [Re x | Im x], whose FP32 products are combined and added in FP64
+ * with the FP64 diagonal.  The memory must stay valid while in use; n and ld
+ * must be below 2^31. */
 vsie_status vsie_assemble_dense(vsie_problem *p, int32_t f, void *dense, int64_t ld, void *stream);
 vsie_status vsie_release_dense(vsie_problem *p, int32_t f);
 

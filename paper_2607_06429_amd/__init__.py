@@ -373,11 +373,12 @@ def vsie_param_gradient(h, f, P, lam, z, Z, zR, ZR, grad_c, grad_rho, stream=Non
 
 
 def vsie_assemble_dense(h, f, dense, ld, stream=None):
-    """dense: CUDA tensor of at least ld * n complex64 values (any shape)."""
+    """dense: CUDA tensor of at least 2 * ld * n float32 values (any shape): the
+    real-part plane, then the imaginary-part plane, each column-major."""
     import torch
-    if dense.dtype != torch.complex64 or not dense.is_cuda or not dense.is_contiguous():
-        raise ValueError("expected a contiguous complex64 CUDA tensor")
-    if dense.numel() < ld * vsie_size(h):
+    if dense.dtype != torch.float32 or not dense.is_cuda or not dense.is_contiguous():
+        raise ValueError("expected a contiguous float32 CUDA tensor")
+    if dense.numel() < 2 * ld * vsie_size(h):
         raise ValueError("dense buffer too small")
     _check(lib.vsie_assemble_dense(h, f, _P(dense.data_ptr()), ld, _stream(stream)))
 
@@ -539,7 +540,7 @@ class Problem:
         (keep it alive while FP32 products should use it)."""
         import torch
         ld = self.n if ld is None else ld
-        A = torch.empty((self.n, ld), dtype=torch.complex64, device="cuda")
+        A = torch.empty((2, self.n, ld), dtype=torch.float32, device="cuda")  # real and imaginary planes
         vsie_assemble_dense(self.handle, f, A, ld)
         return A
 

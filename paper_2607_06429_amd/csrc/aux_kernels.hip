@@ -173,23 +173,43 @@ __global__ void reduce_kernel(int64_t n_t, int nrhs, int n_parts, const double2 
 
 // y[i + r ldy] = d_i x[i + r ldx] + sum_c part[(c nrhs + r) n_t + i] with FP32 partials
 // added in FP64 (d_i = diag[i], conjugated when conj_diag).
-__global__ void reduce32_kernel(int64_t n_t, int nrhs, int n_parts, const float2 *__restrict__ part,
-                                const double2 *__restrict__ diag, bool conj_diag,
-                                const double2 *__restrict__ x, int64_t ldx, double2 *__restrict__ y,
-                                int64_t ldy) {
+// X2[i + r n] = Re x[i + r ldx], X2[i + (nrhs + r) n] = Im x[i + r ldx]  (FP32)
+__global__ void pack_planar_kernel(int64_t n, int nrhs, const double2 *__restrict__ x, int64_t ldx,
+                                   float *__restrict__ X2) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
-    if (i >= n_t) return;
+    const int r = blockIdx.y;
+    if (i >= n) return;
+    const double2 v = x[i + r * ldx];
+    X2[i + static_cast<int64_t>(r) * n] = static_cast<float>(v.x);
+    X2[i + static_cast<int64_t>(nrhs + r) * n] = static_cast<float>(v.y);
+}
+
+// y = d x (conj(d) for the adjoint) + sum over slabs of the planar partials
+// (see launch_reduce_planar), added in FP64
+__global__ void reduce_planar_kernel(int64_t n, int nrhs, int n_parts, const float *__restrict__ part,
+                                     const double2 *__restrict__ diag, bool adjoint,
+                                     const double2 *__restrict__ x, int64_t ldx, double2 *__restrict__ y,
+                                     int64_t ldy) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i >= n) return;
     double2 d = diag[i];
-    if (conj_diag) d.y = -d.y;
-    for (int r = 0; r < nrhs; ++r) {
-        double2 acc = cmul(d, x[i + r * ldx]);
-        for (int c = 0; c < n_parts; ++c) {
-            const float2 p = part[(static_cast<int64_t>(c) * nrhs + r) * n_t + i];
-            acc.x += static_cast<double>(p.x);
-            acc.y += static_cast<double>(p.y);
+    if (adjoint) d.y = -d.y;
+    double2 acc = cmul(d, x[i + r * ldx]);
+    const int64_t blk = static_cast<int64_t>(2) * nrhs * n;  // one n x 2 nrhs product
+    for (int c = 0; c < n_parts; ++c) {
+        const float *P = part + 2 * c * blk, *Q = P + blk;
+        const double pr = P[r * n + i], pi = P[(nrhs + r) * n + i];
+        const double qr = Q[r * n + i], qi = Q[(nrhs + r) * n + i];
+        if (!adjoint) {
+            acc.x += pr - qi;
+            acc.y += pi + qr;
+        } else {
+            acc.x += pr + qi;
+            acc.y += pi - qr;
         }
-        y[i + r * ldy] = acc;
     }
+    y[i + r * ldy] = acc;
 }
 
 // y[idx[jj] + r ldy] += conj(scale_jj * sum_c partial[(c nrhs + r) count + jj]),
@@ -603,12 +623,17 @@ void launch_reduce_partials(int64_t n_t, int nrhs, int n_parts, const double2 *p
     LAUNCH_CHECK();
 }
 
-void launch_reduce32(int64_t n_t, int nrhs, int n_parts, const float2 *partial, const double2 *diag,
-                     bool conj_diag, const double2 *x, int64_t ldx, double2 *y, int64_t ldy,
-                     hipStream_t s) {
-    if (n_t == 0) return;
-    hipLaunchKernelGGL(reduce32_kernel, dim3(blocks_for(n_t)), dim3(kT), 0, s, n_t, nrhs, n_parts,
-                       partial, diag, conj_diag, x, ldx, y, ldy);
+void launch_pack_planar(int64_t n, int nrhs, const double2 *x, int64_t ldx, float *X2, hipStream_t s) {
+    if (n == 0 || nrhs == 0) return;
+    hipLaunchKernelGGL(pack_planar_kernel, dim3(blocks_for(n), nrhs), dim3(kT), 0, s, n, nrhs, x, ldx, X2);
+    LAUNCH_CHECK();
+}
+
+void launch_reduce_planar(int64_t n, int nrhs, int n_parts, const float *partial, const double2 *diag,
+                          bool adjoint, const double2 *x, int64_t ldx, double2 *y, int64_t ldy, hipStream_t s) {
+    if (n == 0 || nrhs == 0) return;
+    hipLaunchKernelGGL(reduce_planar_kernel, dim3(blocks_for(n), nrhs), dim3(kT), 0, s, n, nrhs, n_parts,
+                       partial, diag, adjoint, x, ldx, y, ldy);
     LAUNCH_CHECK();
 }
 

@@ -228,7 +228,7 @@ __global__ __launch_bounds__(kBlock) void assemble_kernel(
     int64_t n, const double *__restrict__ px, const double *__restrict__ py,
     const double *__restrict__ pz, const double *__restrict__ sp, const double *__restrict__ vpx,
     const double *__restrict__ vpy, const double *__restrict__ vpz, double k, double khalf,
-    float2 *__restrict__ A, int64_t ld, int64_t chunk) {
+    float *__restrict__ Ar, float *__restrict__ Ai, int64_t ld, int64_t chunk) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (i >= n) return;
     const int64_t j0 = static_cast<int64_t>(blockIdx.y) * chunk;
@@ -241,8 +241,8 @@ __global__ __launch_bounds__(kBlock) void assemble_kernel(
         const double q = fma(dx, vpx[j], fma(dy, vpy[j], dz * vpz[j])) * ir2;
         // e * (-s' - q + i k r q)
         const double br = -sp[j] - q, bi = kr * q;
-        A[i + j * ld] = make_float2(static_cast<float>(er * br - ei * bi),
-                                    static_cast<float>(er * bi + ei * br));
+        Ar[i + j * ld] = static_cast<float>(er * br - ei * bi);
+        Ai[i + j * ld] = static_cast<float>(er * bi + ei * br);
     }
 }
 
@@ -250,12 +250,12 @@ __global__ __launch_bounds__(kBlock) void assemble_kernel(
 
 void launch_assemble_dense(int64_t n, const double *px, const double *py, const double *pz,
                            const double *sp, const double *vpx, const double *vpy, const double *vpz,
-                           double k, float2 *A, int64_t ld, hipStream_t s) {
+                           double k, float *A, int64_t ld, hipStream_t s) {
     if (n == 0) return;
     const int64_t chunk = 512;
     dim3 grid(static_cast<unsigned>((n + kBlock - 1) / kBlock), static_cast<unsigned>((n + chunk - 1) / chunk));
     hipLaunchKernelGGL(assemble_kernel, grid, dim3(kBlock), 0, s, n, px, py, pz, sp, vpx, vpy, vpz, k,
-                       k / kPi, A, ld, chunk);
+                       k / kPi, A, A + ld * n, ld, chunk);
     VSIE_HIP(hipGetLastError());
 }
 

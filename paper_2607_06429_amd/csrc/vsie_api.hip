@@ -131,7 +131,7 @@ struct vsie_problem {
     double far[3] = {0, 0, 0}, far_step = 1;  // padding points of the tiled kernels
     // dense FP32 off-diagonal operator per frequency (caller-owned memory)
     struct Dense {
-        float2 *A = nullptr;
+        float *A = nullptr;  // real parts; imaginary parts at A + ld n
         int64_t ld = 0;
     };
     std::vector<Dense> dense;
@@ -550,10 +550,12 @@ void apply_adjoint(vsie_problem *p, int f, vsie_precision prec, int nrhs, const 
     }
 }
 
-// FP32 product with the assembled operator of frequency f (rocBLAS complex
-// GEMM on the matrix cores): y = d x + A x (or conj(d) x + A^H x).  The
-// contraction is split into chunks of kDenseChunk sources (targets for the
-// adjoint) whose FP32 partial products are added in FP64.
+// FP32 product with the assembled operator of frequency f: y = d x + A x (or
+// conj(d) x + A^H x).  A is stored as two real planes, so each slab of
+// kDenseChunk sources (targets for the adjoint) takes two real rocBLAS GEMMs,
+// Ar_c [Re x | Im x] and Ai_c [Re x | Im x], with 2 nrhs columns each (FP32
+// on the matrix cores; measured faster than one complex GEMM with nrhs
+// columns); their FP32 products are combined and added in FP64.
 constexpr int64_t kDenseChunk = 8192;
 
 void apply_dense(vsie_problem *p, int f, bool adjoint, int nrhs, const double2 *x, int64_t ldx,
@@ -563,35 +565,28 @@ void apply_dense(vsie_problem *p, int f, bool adjoint, int nrhs, const double2 *
     if (!p->blas) check_blas(rocblas_create_handle(&p->blas), "rocblas_create_handle");
     check_blas(rocblas_set_stream(p->blas, s), "rocblas_set_stream");
     const int nc = static_cast<int>((n + kDenseChunk - 1) / kDenseChunk);
-    float2 *X = static_cast<float2 *>(p->dense_x.get(sizeof(float2) * static_cast<size_t>(n) * nrhs));
-    float2 *Y = static_cast<float2 *>(
-        p->dense_part.get(sizeof(float2) * static_cast<size_t>(n) * nrhs * nc));
-    launch_pack_plain(VSIE_FP32, n, nrhs, x, ldx, false, X, s);
-    const rocblas_float_complex one{1.0f, 0.0f}, zero{0.0f, 0.0f};
-    using C = rocblas_float_complex;
+    const int64_t blk = static_cast<int64_t>(2) * nrhs * n;  // one n x 2 nrhs product
+    float *X2 = static_cast<float *>(p->dense_x.get(sizeof(float) * static_cast<size_t>(blk)));
+    float *Y = static_cast<float *>(p->dense_part.get(sizeof(float) * static_cast<size_t>(2 * blk * nc)));
+    launch_pack_planar(n, nrhs, x, ldx, X2, s);
+    const float one = 1.0f, zero = 0.0f;
+    const float *planes[2] = {D.A, D.A + D.ld * n};
     for (int c = 0; c < nc; ++c) {
         const int64_t k0 = static_cast<int64_t>(c) * kDenseChunk;
         const int kk = static_cast<int>(std::min<int64_t>(kDenseChunk, n - k0));
-        C *Yc = reinterpret_cast<C *>(Y + static_cast<int64_t>(c) * nrhs * n);
-        if (!adjoint) {
-            // columns k0.. of A times rows k0.. of X
-            check_blas(rocblas_cgemm(p->blas, rocblas_operation_none, rocblas_operation_none,
-                                     static_cast<rocblas_int>(n), nrhs, kk, &one,
-                                     reinterpret_cast<const C *>(D.A + k0 * D.ld),
-                                     static_cast<rocblas_int>(D.ld), reinterpret_cast<const C *>(X + k0),
-                                     static_cast<rocblas_int>(n), &zero, Yc, static_cast<rocblas_int>(n)),
-                       "rocblas_cgemm");
-        } else {
-            // (rows k0.. of A)^H times rows k0.. of X
-            check_blas(rocblas_cgemm(p->blas, rocblas_operation_conjugate_transpose,
-                                     rocblas_operation_none, static_cast<rocblas_int>(n), nrhs, kk, &one,
-                                     reinterpret_cast<const C *>(D.A + k0), static_cast<rocblas_int>(D.ld),
-                                     reinterpret_cast<const C *>(X + k0), static_cast<rocblas_int>(n), &zero,
-                                     Yc, static_cast<rocblas_int>(n)),
-                       "rocblas_cgemm");
+        for (int pl = 0; pl < 2; ++pl) {
+            float *Yc = Y + (2 * static_cast<int64_t>(c) + pl) * blk;
+            // forward: columns k0.. of the plane times rows k0.. of X2;
+            // adjoint: (rows k0.. of the plane)^T times rows k0.. of X2
+            const float *Ap = adjoint ? planes[pl] + k0 : planes[pl] + k0 * D.ld;
+            check_blas(rocblas_sgemm(p->blas, adjoint ? rocblas_operation_transpose : rocblas_operation_none,
+                                     rocblas_operation_none, static_cast<rocblas_int>(n), 2 * nrhs, kk, &one,
+                                     Ap, static_cast<rocblas_int>(D.ld), X2 + k0, static_cast<rocblas_int>(n),
+                                     &zero, Yc, static_cast<rocblas_int>(n)),
+                       "rocblas_sgemm");
         }
     }
-    launch_reduce32(n, nrhs, nc, Y, p->m.diag + static_cast<int64_t>(f) * n, adjoint, x, ldx, y, ldy, s);
+    launch_reduce_planar(n, nrhs, nc, Y, p->m.diag + static_cast<int64_t>(f) * n, adjoint, x, ldx, y, ldy, s);
 }
 
 // FP32 forward products on the matrix cores for the nf frequencies f0 ..:
@@ -1936,8 +1931,8 @@ vsie_status vsie_assemble_dense(vsie_problem *p, int32_t f, void *dense, int64_t
         hipStream_t s = as_stream(stream);
         const double *vp[3] = {p->m.vpx, p->m.vpy, p->m.vpz};
         launch_assemble_dense(p->m.n, p->m.px, p->m.py, p->m.pz, p->m.sp + static_cast<int64_t>(f) * p->m.n,
-                              vp[0], vp[1], vp[2], p->k0[f], static_cast<float2 *>(dense), ld, s);
-        p->dense[f] = vsie_problem::Dense{static_cast<float2 *>(dense), ld};
+                              vp[0], vp[1], vp[2], p->k0[f], static_cast<float *>(dense), ld, s);
+        p->dense[f] = vsie_problem::Dense{static_cast<float *>(dense), ld};
         ++g_graph_epoch;
     });
 }

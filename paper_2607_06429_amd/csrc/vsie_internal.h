@@ -226,14 +226,21 @@ void launch_pack_plain(vsie_precision prec, int64_t n, int nrhs, const double2 *
 void launch_reduce_partials(int64_t n_t, int nrhs, int n_parts, const double2 *partial,
                             const double2 *diag, bool conj_diag, const double2 *x, int64_t ldx,
                             double2 *y, int64_t ldy, double2 *unused, hipStream_t s);
-// y = diag * x + sum of n_parts FP32 partial blocks (added in FP64)
-void launch_reduce32(int64_t n_t, int nrhs, int n_parts, const float2 *partial, const double2 *diag,
-                     bool conj_diag, const double2 *x, int64_t ldx, double2 *y, int64_t ldy,
-                     hipStream_t s);
-// dense FP32 off-diagonal operator, column-major with leading dimension ld (pair_kernels.hip)
+// X2 (n x 2 nrhs FP32, column-major, leading dimension n) = [Re x | Im x]
+void launch_pack_planar(int64_t n, int nrhs, const double2 *x, int64_t ldx, float *X2, hipStream_t s);
+// y = d x + the FP64 sum over n_parts slabs of the planar FP32 partial products:
+// slab c holds P = Ar_c X2 and then Q = Ai_c X2 (n x 2 nrhs each, leading
+// dimension n; transposed slabs of A for the adjoint), combined as
+// forward  y = d x + sum_c (P_r - Q_i) + i (P_i + Q_r),
+// adjoint  y = conj(d) x + sum_c (P_r + Q_i) + i (P_i - Q_r),
+// where _r and _i are the column blocks of X2's real and imaginary parts.
+void launch_reduce_planar(int64_t n, int nrhs, int n_parts, const float *partial, const double2 *diag,
+                          bool adjoint, const double2 *x, int64_t ldx, double2 *y, int64_t ldy, hipStream_t s);
+// dense FP32 off-diagonal operator in two planes, real parts A[i + j ld] and
+// imaginary parts A[ld n + i + j ld], column-major (pair_kernels.hip)
 void launch_assemble_dense(int64_t n, const double *px, const double *py, const double *pz,
                            const double *sp, const double *vpx, const double *vpy, const double *vpz,
-                           double k, float2 *A, int64_t ld, hipStream_t s);
+                           double k, float *A, int64_t ld, hipStream_t s);
 // y[idx[jj]] += conj(scale * sum of partials), scale = -s' (sp != null) or 1
 void launch_scatter_conj(int64_t count, const int32_t *idx, const double *sp, int nrhs,
                          int n_parts, const double2 *partial, double2 *y, int64_t ldy,

@@ -15,10 +15,11 @@ plain FP64 solve is timed beside it.  Prints one JSON line.
 
 Unless --no-batched is given, the line also carries the batched workloads
 (outside the timed steps): 128 plane-wave directions at k0 = 16 on the 57^3
-grid (n = 116,445) solved by block GMRES with the assembled FP32 operator and
-matrix-free, and one multi-frequency FP32 product of the cube-with-ellipsoid
-medium on the 100^3 grid (n = 1,076,336), 8 wavenumbers x 16 directions in
-one matrix-core launch per source class.
+grid (n = 116,445) solved by block GMRES with the assembled FP32 operator,
+matrix-free FP32 and matrix-free FP64; the receiver-misfit gradient of the
+log-normal medium with FP32 and with FP64 solves; and one multi-frequency FP32
+product of the cube-with-ellipsoid medium on the 100^3 grid (n = 1,076,336),
+8 wavenumbers x 16 directions in one matrix-core launch per source class.
 """
 from __future__ import annotations
 
@@ -93,14 +94,22 @@ def c3_gradient(V, W, n_cells=3):
     data = pressures(mat1.vol_c, mat1.vol_rho)
     c = torch.tensor(mat.vol_c, device="cuda", requires_grad=True)
     rho = torch.tensor(mat.vol_rho, device="cuda", requires_grad=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    pr = receiver_pressure(P, mesh.n_vol, c, rho, dirs, rec, prec=V.VSIE_FP32, tol=TOL, block=True)
-    loss = 0.5 * (pr - data).abs().pow(2).sum()
-    loss.backward()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    gc, gr = c.grad.cpu().numpy(), rho.grad.cpu().numpy()
+    times, grads = {}, {}
+    for tag, prec in (("fp64", V.VSIE_FP64), ("fp32", V.VSIE_FP32)):
+        c.grad = None
+        rho.grad = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pr = receiver_pressure(P, mesh.n_vol, c, rho, dirs, rec, prec=prec, tol=TOL, block=True)
+        loss = 0.5 * (pr - data).abs().pow(2).sum()
+        loss.backward()
+        torch.cuda.synchronize()
+        times[tag] = time.perf_counter() - t0
+        grads[tag] = (c.grad.cpu().numpy(), rho.grad.cpu().numpy())
+    dt = times["fp32"]
+    gc, gr = grads["fp32"]
+    g64 = np.concatenate(grads["fp64"])
+    diff64 = float(np.linalg.norm(np.concatenate(grads["fp32"]) - g64) / np.linalg.norm(g64))
     cells = np.random.default_rng(2607).choice(mesh.n_vol, n_cells, replace=False)
     errs = {}
     for which, g in (("c", gc), ("rho", gr)):
@@ -119,8 +128,10 @@ def c3_gradient(V, W, n_cells=3):
     P.close()
     return {"workload": "c1 mesh (n=%d) with log-normal c and rho, k0=10, %d incidences, %d receivers on "
                         "|x|=3, misfit to the unperturbed medium's pressures" % (mesh.n, len(dirs), len(rec)),
-            "gradient_s": dt, "loss": float(loss),
-            "solver": "block GMRES, FP32 operator in FP64 refinement to 1e-10 (forward and adjoint)",
+            "gradient_s": dt, "gradient_s_fp64": times["fp64"], "speedup_vs_fp64": times["fp64"] / dt,
+            "rel_diff_vs_fp64_gradient": diff64, "loss": float(loss),
+            "solver": "block GMRES, FP32 operator in FP64 refinement to 1e-10 (forward and adjoint); "
+                      "the FP64 timing uses the FP64 operator",
             "fd_check": {"cells": [int(j) for j in cells], "step": "1e-3 relative, central",
                          "misfit_solves": "FP64 to 1e-13", "rel_err_grad_c": errs["c"],
                          "rel_err_grad_rho": errs["rho"]}}
@@ -136,30 +147,42 @@ def batched_workloads(V, W):
     n = P.n
     B = P.plane_wave(dirs)
     R = B.shape[0]
-    for name in ("assembled_fp32", "matrix_free_fp32"):
+    sols = {}
+    for name, prec in (("assembled_fp32", V.VSIE_FP32), ("matrix_free_fp32", V.VSIE_FP32),
+                       ("matrix_free_fp64", V.VSIE_FP64)):
         A = P.assemble_dense(0) if name == "assembled_fp32" else None
-        if A is None:
+        if name == "matrix_free_fp32":
             P.autotune(R)
         torch.cuda.synchronize()
         P.profile(True)
         t0 = time.perf_counter()
-        x, info = P.solve(B, prec=V.VSIE_FP32, tol=TOL, block=True)
+        x, info = P.solve(B, prec=prec, tol=TOL, block=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         st = P.kernel_stats()
         P.profile(False)
+        sols[name] = x
         mv = info["matvecs_fp32"] + info["matvecs_fp64"]
+        op = ("FP32 operator %s in FP64 refinement" % ("assembled (%.1f GB)" % (8.0 * n * n / 1e9)
+                                                       if A is not None else "matrix-free")
+              if prec == V.VSIE_FP32 else "FP64 operator matrix-free")
         out["c2_block_gmres_" + name] = {
             "workload": "nested balls, 57^3 grid, n=%d, k0=16, %d Fibonacci directions, block GMRES, "
-                        "FP32 operator %s in FP64 refinement to rel. residual 1e-10"
-                        % (n, R, "assembled (%.1f GB)" % (8.0 * n * n / 1e9) if A is not None else "matrix-free"),
+                        "%s to rel. residual 1e-10" % (n, R, op),
             "solve_s": dt, "iterations": info, "gpair_col_evals_per_s": float(n) * n * mv / dt / 1e9,
-            "tuning": P.tuning if A is None else None,
+            "tuning": P.tuning if name == "matrix_free_fp32" else None,
             "pair_kernels": {k: {"launches": v["launches"], "ms": v["ms"]} for k, v in st.items()}}
         if A is not None:
             P.release_dense(0)
             del A
             torch.cuda.empty_cache()
+    ref = sols["matrix_free_fp64"]
+    for name in ("assembled_fp32", "matrix_free_fp32"):
+        out["c2_block_gmres_" + name]["rel_diff_vs_fp64_solution"] = float(
+            torch.linalg.norm(sols[name] - ref) / torch.linalg.norm(ref))
+        out["c2_block_gmres_" + name]["speedup_vs_fp64"] = (out["c2_block_gmres_matrix_free_fp64"]["solve_s"]
+                                                             / out["c2_block_gmres_" + name]["solve_s"])
+    del sols, ref
     P.close()
     del B
     out["c3_adjoint_gradient"] = c3_gradient(V, W)

@@ -166,7 +166,11 @@ typedef struct {
                                   face: the cell-face pairs also run once per pair
                                   (single layer at the face, double layers at the
                                   cell); 0 = off, 1 = on; default 1 */
-    int32_t reserved;          /* must be 0 */
+    int32_t mfma_3m;           /* matrix-core products: 0 = four real products per
+                                  complex multiply-add (Kr Qr, Ki Qi, Kr Qi, Ki Qr),
+                                  1 = three (Kr Qr, Ki Qi, (Kr + Ki)(Qr + Qi); the
+                                  imaginary part as the difference of FP32 sums);
+                                  default 1 */
 } vsie_tuning;
 
 vsie_status vsie_get_tuning(const vsie_problem *p, vsie_tuning *out);

@@ -65,7 +65,7 @@ struct MfmaArgs {
     int part0;
 };
 
-template <int CLS, int TG, int NB>
+template <int CLS, int TG, int NB, bool M3>
 __global__ __launch_bounds__(kBlock) void mfma_fwd_kernel(MfmaArgs a) {
     constexpr int TT = 16 * TG;  // targets per item
     const int lane = threadIdx.x & 63;
@@ -120,8 +120,10 @@ __global__ __launch_bounds__(kBlock) void mfma_fwd_kernel(MfmaArgs a) {
             const int steps = static_cast<int>((je - jt + 3) >> 2);
             uint32_t po = static_cast<uint32_t>(jt + sq) * 32u;
             uint32_t qo = static_cast<uint32_t>(jt + sq) * qrow + static_cast<uint32_t>(tl) * 8u;
-            // one accumulator per real product (Kr Qr, Ki (-Qi), Kr Qi, Ki Qr): no
-            // dependent matrix-core operations within a step
+            // one accumulator per real product, so that no two matrix-core
+            // operations of a step depend on each other: Kr Qr, Ki (-Qi), Kr Qi,
+            // Ki Qr; or, with M3, Kr Qr, Ki Qi, (Kr + Ki)(Qr + Qi), from which
+            // Re = P1 - P2 and Im = P3 - P1 - P2 (three products instead of four)
             v4f d0[TG][NB], d1[TG][NB], d2[TG][NB], d3[TG][NB];
 #pragma unroll
             for (int g = 0; g < TG; ++g)
@@ -144,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void mfma_fwd_kernel(MfmaArgs a) {
                 for (int b = 0; b < NB; ++b) {
                     qr[b] = un[b].x;
                     qi[b] = un[b].y;
-                    qn[b] = -un[b].y;
+                    qn[b] = M3 ? un[b].x + un[b].y : -un[b].y;
                 }
                 po += 128u;
                 qo += 4u * qrow;
@@ -164,12 +166,22 @@ __global__ __launch_bounds__(kBlock) void mfma_fwd_kernel(MfmaArgs a) {
                         kre = qq * fmaf(-ei, kr, -er);
                         kim = qq * fmaf(er, kr, -ei);
                     }
+                    if constexpr (M3) {
+                        const float ks = kre + kim;
 #pragma unroll
-                    for (int b = 0; b < NB; ++b) {
-                        d0[g][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kre, qr[b], d0[g][b], 0, 0, 0);
-                        d1[g][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kim, qn[b], d1[g][b], 0, 0, 0);
-                        d2[g][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kre, qi[b], d2[g][b], 0, 0, 0);
-                        d3[g][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kim, qr[b], d3[g][b], 0, 0, 0);
+                        for (int b = 0; b < NB; ++b) {
+                            d0[g][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kre, qr[b], d0[g][b], 0, 0, 0);
+                            d1[g][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kim, qi[b], d1[g][b], 0, 0, 0);
+                            d2[g][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ks, qn[b], d2[g][b], 0, 0, 0);
+                        }
+                    } else {
+#pragma unroll
+                        for (int b = 0; b < NB; ++b) {
+                            d0[g][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kre, qr[b], d0[g][b], 0, 0, 0);
+                            d1[g][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kim, qn[b], d1[g][b], 0, 0, 0);
+                            d2[g][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kre, qi[b], d2[g][b], 0, 0, 0);
+                            d3[g][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kim, qr[b], d3[g][b], 0, 0, 0);
+                        }
                     }
                 }
                 // the prefetched values are live here: their loads stay inside this step
@@ -184,8 +196,14 @@ __global__ __launch_bounds__(kBlock) void mfma_fwd_kernel(MfmaArgs a) {
                 for (int b = 0; b < NB; ++b)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        accr[g][b][v] += static_cast<double>(d0[g][b][v]) + static_cast<double>(d1[g][b][v]);
-                        acci[g][b][v] += static_cast<double>(d2[g][b][v]) + static_cast<double>(d3[g][b][v]);
+                        const double p0 = d0[g][b][v], p1 = d1[g][b][v], p2 = d2[g][b][v];
+                        if constexpr (M3) {
+                            accr[g][b][v] += p0 - p1;
+                            acci[g][b][v] += p2 - p0 - p1;
+                        } else {
+                            accr[g][b][v] += p0 + p1;
+                            acci[g][b][v] += p2 + static_cast<double>(d3[g][b][v]);
+                        }
                     }
         }
         // D operand: lane l, register v holds target row 4 (l / 16) + v, column l % 16
@@ -226,29 +244,34 @@ __global__ void pack_mfma_kernel(int64_t count, const int32_t *__restrict__ idx,
     q[fl * ldq_f + e] = v;
 }
 
-template <int CLS, int TG, int NB>
+template <int CLS, int TG, int NB, bool M3>
 const void *kernel_ptr() {
-    return reinterpret_cast<const void *>(&mfma_fwd_kernel<CLS, TG, NB>);
+    return reinterpret_cast<const void *>(&mfma_fwd_kernel<CLS, TG, NB, M3>);
 }
 
-const void *pick_kernel(int cls, int tg, int nb) {
+template <bool M3>
+const void *pick_variant(int cls, int tg, int nb) {
     if (cls == kClassG) {
-        if (tg == 4 && nb == 1) return kernel_ptr<kClassG, 4, 1>();
-        if (tg == 2 && nb == 1) return kernel_ptr<kClassG, 2, 1>();
-        if (tg == 2 && nb == 2) return kernel_ptr<kClassG, 2, 2>();
-        if (tg == 4 && nb == 2) return kernel_ptr<kClassG, 4, 2>();
+        if (tg == 4 && nb == 1) return kernel_ptr<kClassG, 4, 1, M3>();
+        if (tg == 2 && nb == 1) return kernel_ptr<kClassG, 2, 1, M3>();
+        if (tg == 2 && nb == 2) return kernel_ptr<kClassG, 2, 2, M3>();
+        if (tg == 4 && nb == 2) return kernel_ptr<kClassG, 4, 2, M3>();
     } else {
-        if (tg == 4 && nb == 1) return kernel_ptr<kClassF, 4, 1>();
-        if (tg == 2 && nb == 1) return kernel_ptr<kClassF, 2, 1>();
-        if (tg == 2 && nb == 2) return kernel_ptr<kClassF, 2, 2>();
-        if (tg == 4 && nb == 2) return kernel_ptr<kClassF, 4, 2>();
+        if (tg == 4 && nb == 1) return kernel_ptr<kClassF, 4, 1, M3>();
+        if (tg == 2 && nb == 1) return kernel_ptr<kClassF, 2, 1, M3>();
+        if (tg == 2 && nb == 2) return kernel_ptr<kClassF, 2, 2, M3>();
+        if (tg == 4 && nb == 2) return kernel_ptr<kClassF, 4, 2, M3>();
     }
     return nullptr;
 }
 
+const void *pick_kernel(int cls, int tg, int nb, bool m3) {
+    return m3 ? pick_variant<true>(cls, tg, nb) : pick_variant<false>(cls, tg, nb);
+}
+
 }  // namespace
 
-bool mfma_variant_ok(int tg, int nb) { return pick_kernel(kClassG, tg, nb) != nullptr; }
+bool mfma_variant_ok(int tg, int nb) { return pick_kernel(kClassG, tg, nb, false) != nullptr; }
 
 int mfma_grid(int tg, int nb) {
     static int cus = 0;
@@ -262,8 +285,8 @@ int mfma_grid(int tg, int nb) {
     int &o = occ[0][ti][bi];
     if (!o) {
         int og = 0, of = 0;
-        VSIE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&og, pick_kernel(kClassG, tg, nb), kBlock, 0));
-        VSIE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&of, pick_kernel(kClassF, tg, nb), kBlock, 0));
+        VSIE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&og, pick_kernel(kClassG, tg, nb, false), kBlock, 0));
+        VSIE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&of, pick_kernel(kClassF, tg, nb, false), kBlock, 0));
         o = std::max(1, std::min(og, of));
     }
     const int g = cus * o;
@@ -324,7 +347,7 @@ void launch_mfma_forward(const MfmaJob &J, hipStream_t s, PairProfiler *prof) {
         ev1 = prof_take_event(prof);
         VSIE_HIP(hipEventRecord(ev0, s));
     }
-    hipLaunchKernelGGL(reinterpret_cast<void (*)(MfmaArgs)>(const_cast<void *>(pick_kernel(J.cls, J.tg, J.nb))),
+    hipLaunchKernelGGL(reinterpret_cast<void (*)(MfmaArgs)>(const_cast<void *>(pick_kernel(J.cls, J.tg, J.nb, J.m3))),
                        dim3(static_cast<unsigned>(grid)), dim3(kBlock), 0, s, a);
     VSIE_HIP(hipGetLastError());
     if (prof && prof->on) {

@@ -121,7 +121,7 @@ struct vsie_problem {
     Scratch bh, bg, bsk;  // block GMRES: Hessenberg block column, Gram / inverse factor, slab partials
     HostPinned hpin;      // per-iteration Hessenberg columns and norms on their way to the host
     PairProfiler prof;
-    vsie_tuning tune{8, 2, 1, 16, 32768, 1, 4, 1, 0};
+    vsie_tuning tune{8, 2, 1, 16, 32768, 1, 4, 1, 1};
     // every cell is a single-layer source and the sources are the cells in
     // canonical order (the symmetric cell-cell kernel applies)
     bool g_is_cells = false;
@@ -633,13 +633,13 @@ void apply_forward_mfma_block(vsie_problem *p, int f0, int nf, int nrhs, const d
         launch_pack_mfma(kClassG, p->G, p->m.sp + static_cast<int64_t>(f0) * n, n, nf, nrhs, ncol, x, ldx, xfs,
                          qG, ldqG, s);
         MfmaJob J{kClassG, n, p->m.px, p->m.py, p->m.pz, p->G.count, p->G.pk, nullptr, qG, ldqG, ncol, nrhs,
-                  kf, nf, chG, ncG, part, fstride, 0, tg, nb, grid};
+                  kf, nf, chG, ncG, part, fstride, 0, tg, nb, 0, p->tune.mfma_3m != 0};
         launch_mfma_forward(J, s, &p->prof);
     }
     if (ncF > 0) {
         launch_pack_mfma(kClassF, p->F, nullptr, n, nf, nrhs, ncol, x, ldx, xfs, qF, ldqF, s);
         MfmaJob J{kClassF, n, p->m.px, p->m.py, p->m.pz, p->F.count, p->F.pk, p->F.pv, qF, ldqF, ncol, nrhs,
-                  kf, nf, chF, ncF, part, fstride, ncG, tg, nb, grid};
+                  kf, nf, chF, ncF, part, fstride, ncG, tg, nb, 0, p->tune.mfma_3m != 0};
         launch_mfma_forward(J, s, &p->prof);
     }
     for (int t = 0; t < nf; ++t)
@@ -671,7 +671,7 @@ void check_tuning(const vsie_tuning &t) {
     require(t.graph == 0 || t.graph == 1, "graph must be 0 or 1");
     require(t.sym_groups == 0 || sym_groups_ok(t.sym_groups), "sym_groups must be 0, 2, 4 or 8");
     require(t.cell_face == 0 || t.cell_face == 1, "cell_face must be 0 or 1");
-    require(t.reserved == 0, "reserved must be 0");
+    require(t.mfma_3m == 0 || t.mfma_3m == 1, "mfma_3m must be 0 or 1");
 }
 
 void apply_op(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int nrhs,

@@ -142,6 +142,7 @@ struct MfmaJob {
     int64_t out_fstride;
     int part0;
     int tg, nb, grid;
+    bool m3;  // three real matrix-core products per complex product instead of four
 };
 void launch_mfma_forward(const MfmaJob &J, hipStream_t s, PairProfiler *prof);
 bool mfma_variant_ok(int tg, int nb);

@@ -89,8 +89,8 @@ def kernels(asm: str):
         mode, R, acc = re.search(r"kernelILi(\d)ELi(\d+)Ed(\w)", nm).groups()
         yield nm, "%s_%s_R%s" % (MODES[int(mode)], "fp64" if acc == "d" else "fp32", R), int(R)
     for nm in re.findall(r"^(_Z\w+mfma_fwd_kernel\w+):", asm, re.M):
-        cls, tg, nb = re.search(r"kernelILi(\d)ELi(\d)ELi(\d)E", nm).groups()
-        yield nm, "mfma_%s_fp32_tg%s_nb%s" % (MODES[int(cls)], tg, nb), 16 * int(nb)
+        cls, tg, nb, m3 = re.search(r"kernelILi(\d)ELi(\d)ELi(\d)ELb(\d)E", nm).groups()
+        yield nm, "mfma_%s_fp32_tg%s_nb%s%s" % (MODES[int(cls)], tg, nb, "_3m" if m3 == "1" else ""), 16 * int(nb)
     for nm in re.findall(r"^(_Z\w+sym_kernel\w+):", asm, re.M):
         g, acc = re.search(r"sym_kernelILi(\d)E(\w)E", nm).groups()
         if g == "4":   # the default group size; the inner loop is the same for every size

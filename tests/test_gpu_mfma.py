@@ -27,8 +27,9 @@ def V():
 @pytest.mark.parametrize("name", CASES)
 @pytest.mark.parametrize("R", [8, 16, 33])
 def test_mfma_matvec_parity(V, name, R):
-    """Every kernel variant, ragged column counts (33 = two full blocks + 1)
-    and ragged target tiles (every case has n not a multiple of 64)."""
+    """Every kernel variant (four or three real products per complex
+    multiply-add), ragged column counts (33 = two full blocks + 1) and ragged
+    target tiles (every case has n not a multiple of 64)."""
     say("mfma matvec", name, "R", R)
     mesh, mat, k0 = case(name)
     d = O.discretise(mesh, mat, k0)
@@ -39,15 +40,15 @@ def test_mfma_matvec_parity(V, name, R):
     yv = host(P.matvec(dev(x).contiguous(), prec=V.VSIE_FP32)).reshape(d.n, R)
     ev = O.rel_error(yv, ref)
     for tg, nb in VARIANTS:
-        for ipw in (1, 16):
-            P.set_tuning(mfma_min_rhs=8, mfma_tg=tg, mfma_nb=nb, items_per_wave=ipw)
+        for ipw, m3 in ((1, 0), (16, 0), (1, 1), (16, 1)):
+            P.set_tuning(mfma_min_rhs=8, mfma_tg=tg, mfma_nb=nb, items_per_wave=ipw, mfma_3m=m3)
             P.profile(True)
             y = host(P.matvec(dev(x).contiguous(), prec=V.VSIE_FP32)).reshape(d.n, R)
             st = P.kernel_stats()
             P.profile(False)
             e = O.rel_error(y, ref)
-            say("  tg %d nb %d ipw %2d: rel err %.3e (vector kernel %.3e), vs vector %.3e"
-                % (tg, nb, ipw, e, ev, O.rel_error(y, yv)))
+            say("  tg %d nb %d ipw %2d 3m %d: rel err %.3e (vector kernel %.3e), vs vector %.3e"
+                % (tg, nb, ipw, m3, e, ev, O.rel_error(y, yv)))
             assert "mfma_fwd_single_layer_fp32" in st and "fwd_single_layer_fp32" not in st
             assert e <= TOL32
             assert O.rel_error(y, yv) <= 2 * TOL32
@@ -144,7 +145,7 @@ def test_tuning_validation(V):
     P = V.Problem.from_mesh(mesh, mat, [k0])
     before = P.tuning
     for bad in (dict(mfma_tg=3), dict(mfma_nb=4), dict(items_per_wave=0), dict(vec_target_waves=10),
-                dict(mfma_min_rhs=-1)):
+                dict(mfma_min_rhs=-1), dict(mfma_3m=2)):
         with pytest.raises(V.VsieError):
             P.set_tuning(**bad)
         assert P.tuning == before

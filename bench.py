@@ -129,7 +129,7 @@ def c3_gradient(V, W, n_cells=3):
     return {"workload": "c1 mesh (n=%d) with log-normal c and rho, k0=10, %d incidences, %d receivers on "
                         "|x|=3, misfit to the unperturbed medium's pressures" % (mesh.n, len(dirs), len(rec)),
             "gradient_s": dt, "gradient_s_fp64": times["fp64"], "speedup_vs_fp64": times["fp64"] / dt,
-            "rel_diff_vs_fp64_gradient": diff64, "loss": float(loss),
+            "rel_diff_vs_fp64_gradient": diff64, "loss": float(loss.detach()),
             "solver": "block GMRES, FP32 operator in FP64 refinement to 1e-10 (forward and adjoint); "
                       "the FP64 timing uses the FP64 operator",
             "fd_check": {"cells": [int(j) for j in cells], "step": "1e-3 relative, central",

@@ -481,6 +481,67 @@ __global__ void bnorm_final_kernel(int nslots, const double *__restrict__ partia
     out[sl] = sqrt(acc);
 }
 
+// The Gram-Schmidt update with the final sum of the projections folded in:
+// every block sums the chunk partials of its slot's k coefficients (in chunk
+// order, as bdots_final_kernel) into LDS, block 0 of the slot also stores them
+// in h for the host, then W[sl] -= sum_j V(j, act[sl]) h_j.  k <= kFusedMaxK.
+constexpr int kFusedMaxK = 1024;
+__global__ __launch_bounds__(kT) void bgemv_sub_partial_kernel(int64_t n, int k, int R, const int32_t *__restrict__ act,
+                                                               const double2 *__restrict__ V,
+                                                               const double2 *__restrict__ partial, int n_chunks,
+                                                               double2 *__restrict__ h, int hstride,
+                                                               double2 *__restrict__ W) {
+    __shared__ double2 hc[kFusedMaxK];
+    const int sl = blockIdx.y;
+    for (int j = threadIdx.x; j < k; j += kT) {
+        double2 acc = make_double2(0.0, 0.0);
+        const double2 *p = partial + (static_cast<int64_t>(sl) * k + j) * n_chunks;
+        for (int c = 0; c < n_chunks; ++c) {
+            acc.x += p[c].x;
+            acc.y += p[c].y;
+        }
+        hc[j] = acc;
+        if (blockIdx.x == 0) h[sl * hstride + j] = acc;
+    }
+    __syncthreads();
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+    if (i >= n) return;
+    const int r = act[sl];
+    double2 acc = make_double2(0.0, 0.0);
+    for (int j = 0; j < k; ++j) {
+        const double2 a = V[(static_cast<int64_t>(j) * R + r) * n + i], b = hc[j];
+        acc.x += a.x * b.x - a.y * b.y;
+        acc.y += a.x * b.y + a.y * b.x;
+    }
+    double2 *w = W + static_cast<int64_t>(sl) * n;
+    w[i] = make_double2(w[i].x - acc.x, w[i].y - acc.y);
+}
+
+// The new basis vector with the final sum of the norm folded in: every block
+// sums its slot's chunk partials (in chunk order, as bnorm_final_kernel),
+// block 0 of the slot stores the norm for the host, then
+// V(kcol, act[sl]) = W[sl] / nrm (zero when nrm == 0).
+__global__ __launch_bounds__(kT) void bnorm_scale_kernel(int64_t n, int kcol, int R, const int32_t *__restrict__ act,
+                                                         const double2 *__restrict__ W,
+                                                         const double *__restrict__ partial, int n_chunks,
+                                                         double *__restrict__ nrm, double2 *__restrict__ V) {
+    __shared__ double snrm;
+    const int sl = blockIdx.y;
+    if (threadIdx.x == 0) {
+        double acc = 0.0;
+        for (int c = 0; c < n_chunks; ++c) acc += partial[static_cast<int64_t>(sl) * n_chunks + c];
+        snrm = sqrt(acc);
+        if (blockIdx.x == 0) nrm[sl] = snrm;
+    }
+    __syncthreads();
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+    if (i >= n) return;
+    const double sc = snrm;
+    const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
+    const double2 w = W[static_cast<int64_t>(sl) * n + i];
+    V[(static_cast<int64_t>(kcol) * R + act[sl]) * n + i] = make_double2(w.x * inv, w.y * inv);
+}
+
 // V(kcol, act[sl]) = W[sl] / nrm[sl]   (zero when nrm[sl] == 0)
 __global__ void bscale_into_basis_kernel(int64_t n, int kcol, int R, const int32_t *__restrict__ act,
                                          const double2 *__restrict__ W, const double *__restrict__ nrm,
@@ -768,6 +829,41 @@ void bblas_norm(int64_t n, int nslots, const double2 *W, double *partial, int n_
     LAUNCH_CHECK();
     hipLaunchKernelGGL(bnorm_final_kernel, dim3(blocks_for(nslots)), dim3(kT), 0, s, nslots, partial,
                        n_chunks, out);
+    LAUNCH_CHECK();
+}
+
+bool bblas_fused_ok(int k) { return k <= kFusedMaxK; }
+
+void bblas_dots_partial(int64_t n, int k, int R, int nslots, const int32_t *act, const double2 *V,
+                        const double2 *W, double2 *partial, int n_chunks, hipStream_t s) {
+    if (k == 0 || nslots == 0) return;
+    hipLaunchKernelGGL(bdots_kernel, dim3(n_chunks, k, nslots), dim3(kT), 0, s, n, rpc(n, n_chunks), k,
+                       R, act, V, W, partial, n_chunks);
+    LAUNCH_CHECK();
+}
+
+void bblas_gemv_sub_partial(int64_t n, int k, int R, int nslots, const int32_t *act, const double2 *V,
+                            const double2 *partial, int n_chunks, double2 *h, int hstride, double2 *W,
+                            hipStream_t s) {
+    if (k == 0 || nslots == 0) return;
+    if (k > kFusedMaxK) fail(VSIE_E_INVALID, "fused Gram-Schmidt update: too many basis vectors");
+    hipLaunchKernelGGL(bgemv_sub_partial_kernel, dim3(blocks_for(n), nslots), dim3(kT), 0, s, n, k, R, act, V,
+                       partial, n_chunks, h, hstride, W);
+    LAUNCH_CHECK();
+}
+
+void bblas_norm_partial(int64_t n, int nslots, const double2 *W, double *partial, int n_chunks, hipStream_t s) {
+    if (nslots == 0) return;
+    hipLaunchKernelGGL(bnorm_kernel, dim3(n_chunks, nslots), dim3(kT), 0, s, n, rpc(n, n_chunks), W,
+                       partial, n_chunks);
+    LAUNCH_CHECK();
+}
+
+void bblas_norm_scale(int64_t n, int kcol, int R, int nslots, const int32_t *act, const double2 *W,
+                      const double *partial, int n_chunks, double *nrm, double2 *V, hipStream_t s) {
+    if (nslots == 0) return;
+    hipLaunchKernelGGL(bnorm_scale_kernel, dim3(blocks_for(n), nslots), dim3(kT), 0, s, n, kcol, R, act, W,
+                       partial, n_chunks, nrm, V);
     LAUNCH_CHECK();
 }
 

@@ -971,11 +971,16 @@ int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
                 to_device(tc, hcoef, s);
                 bblas_gemv_sub(n, kmax + 1, R, nl, live_d, use->V, tc, cs_, W, s, kc_d);
             }
-            bblas_dots(n, k + 1, R, nl, live_d, V, W, dpart, nch, h, hs, s);
-            bblas_gemv_sub(n, k + 1, R, nl, live_d, V, h, hs, W, s);
+            if (bblas_fused_ok(k + 1)) {
+                bblas_dots_partial(n, k + 1, R, nl, live_d, V, W, dpart, nch, s);
+                bblas_gemv_sub_partial(n, k + 1, R, nl, live_d, V, dpart, nch, h, hs, W, s);
+            } else {
+                bblas_dots(n, k + 1, R, nl, live_d, V, W, dpart, nch, h, hs, s);
+                bblas_gemv_sub(n, k + 1, R, nl, live_d, V, h, hs, W, s);
+            }
         }
-        bblas_norm(n, nl, W, npart, nch, hn, s);
-        bblas_scale_into_basis(n, k + 1, R, nl, live_d, W, hn, V, s);
+        bblas_norm_partial(n, nl, W, npart, nch, s);
+        bblas_norm_scale(n, k + 1, R, nl, live_d, W, npart, nch, hn, V, s);
         // both Gram-Schmidt passes' coefficients and the new norm, in one copy
         double2 *hb1 = static_cast<double2 *>(p->hpin.get(hcol_bytes));
         double2 *hb2 = hb1 + static_cast<size_t>(hs) * ns;

@@ -290,6 +290,19 @@ void bblas_norm(int64_t n, int nslots, const double2 *W, double *partial, int n_
                 hipStream_t s);
 void bblas_scale_into_basis(int64_t n, int kcol, int R, int nslots, const int32_t *act,
                             const double2 *W, const double *nrm, double2 *V, hipStream_t s);
+// The same Arnoldi step in fewer launches: projections to chunk partials, then
+// the update that sums them itself (and stores the coefficients in h); norm
+// partials, then the scaling that sums them itself (and stores the norms).
+// The update needs k <= 1024 (bblas_fused_ok).
+bool bblas_fused_ok(int k);
+void bblas_dots_partial(int64_t n, int k, int R, int nslots, const int32_t *act, const double2 *V,
+                        const double2 *W, double2 *partial, int n_chunks, hipStream_t s);
+void bblas_gemv_sub_partial(int64_t n, int k, int R, int nslots, const int32_t *act, const double2 *V,
+                            const double2 *partial, int n_chunks, double2 *h, int hstride, double2 *W,
+                            hipStream_t s);
+void bblas_norm_partial(int64_t n, int nslots, const double2 *W, double *partial, int n_chunks, hipStream_t s);
+void bblas_norm_scale(int64_t n, int kcol, int R, int nslots, const int32_t *act, const double2 *W,
+                      const double *partial, int n_chunks, double *nrm, double2 *V, hipStream_t s);
 void bblas_gather(int64_t n, int nslots, const int32_t *act, const double2 *src, int64_t ld,
                   double2 *X, hipStream_t s);
 void bblas_update(int64_t n, int R, int nslots, const int32_t *act, const int32_t *kd, const double2 *V,

@@ -117,7 +117,7 @@ struct vsie_problem {
     std::vector<void *> owned;  // permanent device allocations
     Scratch partial, chargeG, chargeF, chargeAll, sums_part, grad_work;
     // Krylov workspace
-    Scratch V, V2, w, r, ax, h1, tc, nrm, dpart, npart, yv, act, act2, live, kd, kc, xa, axa, rres;
+    Scratch V, V2, w, r, ax, h1, tc, nrm, dpart, npart, yv, act, act2, live, kd, kc, xa, axa, rres, brc;
     Scratch bh, bg, bsk;  // block GMRES: Hessenberg block column, Gram / inverse factor, slab partials
     HostPinned hpin;      // per-iteration Hessenberg columns and norms on their way to the host
     PairProfiler prof;
@@ -198,7 +198,7 @@ struct vsie_problem {
         hpin.release();
         for (void *p : owned) (void)hipFree(p);
         for (Scratch *s : {&partial, &chargeG, &chargeF, &chargeAll, &sums_part, &grad_work, &V, &V2, &w, &r, &ax,
-                           &h1, &tc, &nrm, &dpart, &npart, &yv, &act, &act2, &live, &kd, &kc, &xa, &axa,
+                           &h1, &tc, &nrm, &dpart, &npart, &yv, &act, &act2, &live, &kd, &kc, &xa, &axa, &brc,
                            &rres, &bh, &bg, &bsk})
             s->release();
     }
@@ -1074,9 +1074,36 @@ int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
     return total;
 }
 
+// The block Krylov space of a finished block cycle, kept to deflate later
+// cycles (block GCRO, as Recycle for one column): the block Arnoldi relation
+// A V_k = V_{k+Ra} Hbar with Hbar = Q R by the cycle's Householder reflectors
+// gives C = V_{k+Ra} Q(:, 0:k) (orthonormal) and U = V_k R^{-1} with A U = C.
+// Kept only while k <= kBlockRecycleMax: the deflation runs on the host at
+// O(k (Ra + 1)) per column and step, and R^{-1} at O(k^2) per column.
+constexpr int64_t kBlockRecycleMax = 1024;
+
+struct BlockRecycle {
+    const double2 *V = nullptr;  // basis of the recycled cycle: n x (k + Ra)
+    int Ra = 0;                  // block width of that cycle
+    int64_t k = 0;               // columns of U and C (0: nothing kept)
+    std::vector<cd> U;           // reflector of column c at c (Ra + 1), rows c .. c + Ra
+    std::vector<double> UU;
+    std::vector<cd> R;           // k x k upper triangle, column-major
+
+    void qh(std::vector<cd> &t) const;               // t <- Q^H t (length k + Ra)
+    void q(std::vector<cd> &v) const;                // v <- Q v (length k + Ra)
+    std::vector<cd> r_solve(const std::vector<cd> &z) const;  // R^{-1} z (length k)
+    // coefficients of the deflation of the n x Ra2 block W (on the stream):
+    // Dd <- V^H W ((k + Ra) x Ra2) on the device; on the host per column
+    // z = C^H w (k entries, returned column-major) and the coefficients
+    // Q [z; 0] of C z in the basis V (written to Dd, (k + Ra) x Ra2)
+    std::vector<cd> deflate_coeffs(vsie_problem *p, int64_t n, int Ra2, const double2 *W, double2 *Dd,
+                                   hipStream_t s) const;
+};
 int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const std::vector<int32_t> &rhs,
                 double2 *Rres, const std::vector<double> &rn, const std::vector<double> &ctol, int m,
-                int iter_cap, double2 *x, int64_t ldx, SolveCounters &cnt, hipStream_t s);
+                int iter_cap, double2 *x, int64_t ldx, SolveCounters &cnt, hipStream_t s, double2 *V,
+                BlockRecycle *save, const BlockRecycle *use);
 
 // Solve op(A) x_r = b_r for r < R.  FP64: restarted GMRES(m), each restart
 // from the true FP64 residual.  FP32: the same loop is iterative refinement --
@@ -1093,6 +1120,7 @@ vsie_status solve_batch(vsie_problem *p, int f, vsie_precision prec, bool adjoin
         1, std::min<int64_t>(std::max(1, o.restart), kKrylovBytes / 2 / col_bytes - 1)));
     double2 *V1 = static_cast<double2 *>(p->V.get(static_cast<size_t>(col_bytes) * (m + 1)));
     Recycle first;            // space of the first cycle, deflates every later cycle
+    BlockRecycle bfirst;      // the same for block GMRES
     bool have_first = false;
     relres.assign(R, 0.0);
     std::vector<int32_t> all(R);
@@ -1161,12 +1189,22 @@ vsie_status solve_batch(vsie_problem *p, int f, vsie_precision prec, bool adjoin
         if (o.block) {
             // block steps per cycle: the requested restart, but the host R factor of the block
             // Hessenberg ((m Ra)^2 complex) stays near 2 GB and the basis within the budget
+            // (half of kKrylovBytes each: the first cycle's basis is kept to deflate the later ones)
             const int Ra = static_cast<int>(next.size());
             const int64_t mb_host = std::max<int64_t>(1, 11585 / Ra);
-            const int64_t mb_dev = std::max<int64_t>(1, kKrylovBytes / (static_cast<int64_t>(sizeof(double2)) * n * Ra) - 1);
+            const int64_t mb_dev =
+                std::max<int64_t>(1, kKrylovBytes / 2 / (static_cast<int64_t>(sizeof(double2)) * n * Ra) - 1);
             const int mb = static_cast<int>(std::min<int64_t>({static_cast<int64_t>(std::max(1, o.restart)), mb_host, mb_dev}));
-            done = block_cycle(p, f, prec, adjoint, next, cyc_res, next_rn, next_tol, mb, o.max_iter, x, ldx,
-                               cnt, s);
+            const size_t vbytes = sizeof(double2) * static_cast<size_t>(n) * Ra * (mb + 1);
+            if (!have_first) {
+                done = block_cycle(p, f, prec, adjoint, next, cyc_res, next_rn, next_tol, mb, o.max_iter, x, ldx,
+                                   cnt, s, static_cast<double2 *>(p->V.get(vbytes)), &bfirst, nullptr);
+                have_first = true;
+            } else {
+                done = block_cycle(p, f, prec, adjoint, next, cyc_res, next_rn, next_tol, mb, o.max_iter, x, ldx,
+                                   cnt, s, static_cast<double2 *>(p->V2.get(vbytes)), nullptr,
+                                   bfirst.k > 0 ? &bfirst : nullptr);
+            }
         } else if (!have_first) {
             done = gmres_cycle(p, f, prec, adjoint, R, next, cyc_res, next_rn, next_tol, m, o.max_iter,
                                x, ldx, cnt, s, V1, &first, nullptr, o.relax);
@@ -1372,16 +1410,38 @@ inline void apply_reflector(const cd *u, double uu, int len, cd *y) {
 // corrections to x.  Returns the number of block steps.
 int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const std::vector<int32_t> &rhs,
                 double2 *Rres, const std::vector<double> &rn, const std::vector<double> &ctol, int m,
-                int iter_cap, double2 *x, int64_t ldx, SolveCounters &cnt, hipStream_t s) {
+                int iter_cap, double2 *x, int64_t ldx, SolveCounters &cnt, hipStream_t s, double2 *V,
+                BlockRecycle *save, const BlockRecycle *use) {
     const int64_t n = p->m.n;
     const int Ra = static_cast<int>(rhs.size());
     const int64_t ldH = static_cast<int64_t>(m + 1) * Ra;  // rows of the block Hessenberg / G
-    double2 *V = static_cast<double2 *>(p->V.get(sizeof(double2) * static_cast<size_t>(n) * Ra * (m + 1)));
     double2 *W = static_cast<double2 *>(p->w.get(sizeof(double2) * static_cast<size_t>(n) * Ra));
     double2 *Z = static_cast<double2 *>(p->ax.get(sizeof(double2) * static_cast<size_t>(n) * Ra));
     double2 *Hd = static_cast<double2 *>(p->bh.get(sizeof(double2) * static_cast<size_t>(ldH) * Ra));
     if (!p->blas) check_blas(rocblas_create_handle(&p->blas), "rocblas_create_handle");
     check_blas(rocblas_set_stream(p->blas, s), "rocblas_set_stream");
+    int32_t *act = static_cast<int32_t *>(p->act.get(sizeof(int32_t) * Ra));
+    to_device(act, rhs, s);
+
+    // deflation by an earlier cycle's space: x += U C^H r, r -= C C^H r, and
+    // Bm = C^H A v for every new basis column (column-major, kr rows)
+    const int64_t kr = use ? use->k : 0, kv = use ? use->k + use->Ra : 0;
+    double2 *Dd = kr > 0 ? static_cast<double2 *>(p->brc.get(sizeof(double2) * static_cast<size_t>(kv) * Ra)) : nullptr;
+    std::vector<cd> Bm;
+    if (kr > 0) {
+        const std::vector<cd> z = use->deflate_coeffs(p, n, Ra, Rres, Dd, s);
+        zgemm(p, false, n, Ra, kv, -1.0, use->V, n, Dd, kv, 1.0, Rres, n);
+        std::vector<double2> yh(static_cast<size_t>(kr) * Ra);
+        parallel_for(Ra, [&](int c) {
+            const std::vector<cd> y0 = use->r_solve(std::vector<cd>(z.begin() + static_cast<size_t>(c) * kr,
+                                                                    z.begin() + static_cast<size_t>(c + 1) * kr));
+            for (int64_t i = 0; i < kr; ++i) yh[static_cast<size_t>(c) * kr + i] = make_double2(y0[i].real(), y0[i].imag());
+        });
+        to_device(Dd, yh, s);
+        zgemm(p, false, n, Ra, kr, 1.0, use->V, n, Dd, kr, 0.0, W, n);
+        blas_scatter_add(n, Ra, act, W, x, ldx, s);
+        Bm.assign(static_cast<size_t>(kr) * m * Ra, 0.0);
+    }
 
     std::vector<cd> S0;
     cholqr2(p, n, Ra, Rres, Z, V, S0, s);
@@ -1404,6 +1464,13 @@ int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const
         const int64_t kb = static_cast<int64_t>(j + 1) * Ra;
         std::vector<cd> Hc(static_cast<size_t>(kb + Ra) * Ra, 0.0);  // new block column, rows 0..kb+Ra
         for (int pass = 0; pass < 2; ++pass) {
+            if (kr > 0) {
+                const std::vector<cd> z = use->deflate_coeffs(p, n, Ra, W, Dd, s);
+                for (int c = 0; c < Ra; ++c)
+                    for (int64_t i = 0; i < kr; ++i)
+                        Bm[(static_cast<size_t>(j) * Ra + c) * kr + i] += z[static_cast<size_t>(c) * kr + i];
+                zgemm(p, false, n, Ra, kv, -1.0, use->V, n, Dd, kv, 1.0, W, n);
+            }
             zgemm_tall_cn(p, kb, Ra, n, V, n, W, n, Hd, kb, s);
             zgemm(p, false, n, Ra, kb, -1.0, V, n, Hd, kb, 1.0, W, n);
             to_host(hh, Hd, static_cast<size_t>(kb) * Ra, s);
@@ -1446,9 +1513,10 @@ int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const
         if (all) break;
     }
     if (jdone == 0) return 0;
-    // Y = R^{-1} G(0 : jdone Ra, :), per column
+    // Y = R^{-1} G(0 : jdone Ra, :), per column; with deflation also
+    // Wc = R_use^{-1} (Bm Y), the coefficients of U (Bm Y) in the recycled basis
     const int64_t kk = static_cast<int64_t>(jdone) * Ra;
-    std::vector<double2> Yh(static_cast<size_t>(kk) * Ra);
+    std::vector<double2> Yh(static_cast<size_t>(kk) * Ra), Wc(static_cast<size_t>(kr) * Ra);
     parallel_for(Ra, [&](int rc) {
         std::vector<cd> y(kk);
         for (int64_t i = kk - 1; i >= 0; --i) {
@@ -1458,15 +1526,77 @@ int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const
             y[i] = d == 0.0 ? 0.0 : acc / d;
         }
         for (int64_t i = 0; i < kk; ++i) Yh[static_cast<size_t>(rc) * kk + i] = make_double2(y[i].real(), y[i].imag());
+        if (kr > 0) {
+            std::vector<cd> by(kr, 0.0);
+            for (int64_t t = 0; t < kk; ++t)
+                for (int64_t i = 0; i < kr; ++i) by[i] += Bm[static_cast<size_t>(t) * kr + i] * y[t];
+            const std::vector<cd> w = use->r_solve(by);
+            for (int64_t i = 0; i < kr; ++i) Wc[static_cast<size_t>(rc) * kr + i] = make_double2(w[i].real(), w[i].imag());
+        }
     });
     double2 *Yd = static_cast<double2 *>(p->bh.get(sizeof(double2) * static_cast<size_t>(std::max(kk, ldH)) * Ra));
     to_device(Yd, Yh, s);
     zgemm(p, false, n, Ra, kk, 1.0, V, n, Yd, kk, 0.0, W, n);
-    int32_t *act = static_cast<int32_t *>(p->act.get(sizeof(int32_t) * Ra));
-    to_device(act, rhs, s);
+    if (kr > 0) {  // x += V y - U (Bm y)
+        to_device(Dd, Wc, s);
+        zgemm(p, false, n, Ra, kr, -1.0, use->V, n, Dd, kr, 1.0, W, n);
+    }
     blas_scatter_add(n, Ra, act, W, x, ldx, s);
     VSIE_HIP(hipStreamSynchronize(s));
+    if (save && kk <= kBlockRecycleMax) {
+        save->V = V;
+        save->Ra = Ra;
+        save->k = kk;
+        save->U.assign(U.begin(), U.begin() + static_cast<size_t>(kk) * (Ra + 1));
+        save->UU.assign(UU.begin(), UU.begin() + kk);
+        save->R.assign(static_cast<size_t>(kk) * kk, 0.0);
+        for (int64_t c = 0; c < kk; ++c)
+            for (int64_t i = 0; i <= c; ++i) save->R[static_cast<size_t>(c) * kk + i] = Rf[static_cast<size_t>(c) * ldR + i];
+    }
     return jdone;
+}
+
+void BlockRecycle::qh(std::vector<cd> &t) const {
+    for (int64_t c = 0; c < k; ++c) apply_reflector(&U[static_cast<size_t>(c) * (Ra + 1)], UU[c], Ra + 1, &t[c]);
+}
+
+void BlockRecycle::q(std::vector<cd> &v) const {
+    for (int64_t c = k - 1; c >= 0; --c) apply_reflector(&U[static_cast<size_t>(c) * (Ra + 1)], UU[c], Ra + 1, &v[c]);
+}
+
+std::vector<cd> BlockRecycle::r_solve(const std::vector<cd> &z) const {
+    std::vector<cd> y(k);
+    for (int64_t i = k - 1; i >= 0; --i) {
+        cd acc = z[i];
+        for (int64_t t = i + 1; t < k; ++t) acc -= R[static_cast<size_t>(t) * k + i] * y[t];
+        const cd d = R[static_cast<size_t>(i) * k + i];
+        y[i] = d == 0.0 ? 0.0 : acc / d;
+    }
+    return y;
+}
+
+std::vector<cd> BlockRecycle::deflate_coeffs(vsie_problem *p, int64_t n, int Ra2, const double2 *W, double2 *Dd,
+                                             hipStream_t s) const {
+    const int64_t kv = k + Ra;
+    zgemm_tall_cn(p, kv, Ra2, n, V, n, W, n, Dd, kv, s);
+    std::vector<double2> th;
+    to_host(th, Dd, static_cast<size_t>(kv) * Ra2, s);
+    std::vector<cd> z(static_cast<size_t>(k) * Ra2);
+    std::vector<double2> vh(static_cast<size_t>(kv) * Ra2);
+    parallel_for(Ra2, [&](int c) {
+        std::vector<cd> t(kv);
+        for (int64_t i = 0; i < kv; ++i) t[i] = cd(th[static_cast<size_t>(c) * kv + i].x, th[static_cast<size_t>(c) * kv + i].y);
+        qh(t);
+        std::vector<cd> v(kv, 0.0);
+        for (int64_t i = 0; i < k; ++i) {
+            z[static_cast<size_t>(c) * k + i] = t[i];
+            v[i] = t[i];
+        }
+        q(v);
+        for (int64_t i = 0; i < kv; ++i) vh[static_cast<size_t>(c) * kv + i] = make_double2(v[i].real(), v[i].imag());
+    });
+    to_device(Dd, vh, s);
+    return z;
 }
 
 }  // namespace

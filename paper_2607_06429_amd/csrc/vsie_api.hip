@@ -1079,8 +1079,8 @@ int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
 // A V_k = V_{k+Ra} Hbar with Hbar = Q R by the cycle's Householder reflectors
 // gives C = V_{k+Ra} Q(:, 0:k) (orthonormal) and U = V_k R^{-1} with A U = C.
 // Kept only while k <= kBlockRecycleMax: the deflation runs on the host at
-// O(k (Ra + 1)) per column and step, and R^{-1} at O(k^2) per column.
-constexpr int64_t kBlockRecycleMax = 1024;
+// O(k (Ra + 1)) per column and step (16 threads), and R^{-1} at O(k^2) per column.
+constexpr int64_t kBlockRecycleMax = 4096;
 
 struct BlockRecycle {
     const double2 *V = nullptr;  // basis of the recycled cycle: n x (k + Ra)
@@ -1440,7 +1440,6 @@ int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const
         to_device(Dd, yh, s);
         zgemm(p, false, n, Ra, kr, 1.0, use->V, n, Dd, kr, 0.0, W, n);
         blas_scatter_add(n, Ra, act, W, x, ldx, s);
-        Bm.assign(static_cast<size_t>(kr) * m * Ra, 0.0);
     }
 
     std::vector<cd> S0;
@@ -1466,6 +1465,7 @@ int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const
         for (int pass = 0; pass < 2; ++pass) {
             if (kr > 0) {
                 const std::vector<cd> z = use->deflate_coeffs(p, n, Ra, W, Dd, s);
+                Bm.resize(static_cast<size_t>(j + 1) * Ra * kr, 0.0);
                 for (int c = 0; c < Ra; ++c)
                     for (int64_t i = 0; i < kr; ++i)
                         Bm[(static_cast<size_t>(j) * Ra + c) * kr + i] += z[static_cast<size_t>(c) * kr + i];

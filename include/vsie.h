@@ -207,6 +207,9 @@ typedef struct {
                             that inexact once the residual has fallen far enough that its
                             error can no longer lift the final residual above the
                             tolerance (inexact Krylov methods). */
+    int32_t progress;    /* 1: one line on stderr per outer step (FP64 residual), per block
+                            step and every 25 GMRES iterations (residual estimate), for long
+                            solves; 0: silent (default) */
 } vsie_solve_opts;
 
 typedef struct {

@@ -62,7 +62,7 @@ class KernelStats(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", _D), ("max_iter", _I32), ("restart", _I32), ("inner_tol", _D),
-                ("max_outer", _I32), ("block", _I32), ("relax", _D)]
+                ("max_outer", _I32), ("block", _I32), ("relax", _D), ("progress", _I32)]
 
 
 class Tuning(ctypes.Structure):
@@ -280,7 +280,7 @@ def vsie_autotune(h, f, nrhs, stream=None) -> dict:
 
 
 def vsie_solve(h, f, prec, adjoint, b, x, tol=1e-10, max_iter=3000, restart=500, inner_tol=1e-5,
-               max_outer=20, block=False, stream=None, allow_noconv=False, relax=0.0):
+               max_outer=20, block=False, stream=None, allow_noconv=False, relax=0.0, progress=False):
     """Solve in place into x (initial guess on entry).  Returns SolveInfo as a dict
     plus the status."""
     n = vsie_size(h)
@@ -288,7 +288,7 @@ def vsie_solve(h, f, prec, adjoint, b, x, tol=1e-10, max_iter=3000, restart=500,
     px, Rx, ldx = _cols(x, n)
     if Rx != R:
         raise ValueError("b and x hold different numbers of columns")
-    o = SolveOpts(tol, max_iter, restart, inner_tol, max_outer, 1 if block else 0, relax)
+    o = SolveOpts(tol, max_iter, restart, inner_tol, max_outer, 1 if block else 0, relax, 1 if progress else 0)
     info = SolveInfo()
     st = _check(lib.vsie_solve(h, f, prec, int(adjoint), R, pb, ldb, px, ldx, ctypes.byref(o),
                                ctypes.byref(info), _stream(stream)),

@@ -4,6 +4,7 @@
 #include <atomic>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <thread>
@@ -120,6 +121,7 @@ struct vsie_problem {
     Scratch V, V2, w, r, ax, h1, tc, nrm, dpart, npart, yv, act, act2, live, kd, kc, xa, axa, rres, brc;
     Scratch bh, bg, bsk;  // block GMRES: Hessenberg block column, Gram / inverse factor, slab partials
     HostPinned hpin;      // per-iteration Hessenberg columns and norms on their way to the host
+    int progress = 0;     // vsie_solve_opts::progress of the running solve
     PairProfiler prof;
     vsie_tuning tune{8, 2, 1, 16, 32768, 1, 4, 1, 1};
     // every cell is a single-layer source and the sources are the cells in
@@ -1018,6 +1020,13 @@ int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
             kdone[sl] = k + 1;
             if (std::abs(g[sl][k + 1]) <= ctol[sl] * rn[sl] || beta == 0.0) done[sl] = 1;
         }
+        if (p->progress && (k + 1) % 25 == 0) {
+            double worst = 0.0;
+            for (int sl = 0; sl < ns; ++sl) worst = std::max(worst, std::abs(g[sl][kdone[sl]]) / rn[sl]);
+            std::fprintf(stderr, "[vsie] GMRES iteration %d: max residual estimate %.3e of the cycle start\n", k + 1,
+                         worst);
+            std::fflush(stderr);
+        }
     }
     // x += V y with H y = g (back substitution per slot), then x -= U (B y)
     std::vector<double2> yh(static_cast<size_t>(std::max(m + 1, kmax + 1)) * ns, make_double2(0.0, 0.0));
@@ -1159,6 +1168,13 @@ vsie_status solve_batch(vsie_problem *p, int f, vsie_precision prec, bool adjoin
             bblas_gather(n, na, act, b, ldb, Rres, s);
         }
         const std::vector<double> rn = column_norms(p, Rres, na, s);
+        if (p->progress) {
+            double worst = 0.0;
+            for (int sl = 0; sl < na; ++sl) worst = std::max(worst, rn[sl] / bn[active[sl]]);
+            std::fprintf(stderr, "[vsie] outer step %d: %d active columns, max FP64 relative residual %.3e\n",
+                         cnt.outer[active[0]], na, worst);
+            std::fflush(stderr);
+        }
         std::vector<int32_t> next, keep_slot;
         std::vector<double> next_rn, next_tol;
         for (int sl = 0; sl < na; ++sl) {
@@ -1504,11 +1520,18 @@ int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const
         for (int r : rhs) cnt.it[r]++;
         jdone = j + 1;
         bool all = true;
+        double worst = 0.0;
         for (int rc = 0; rc < Ra; ++rc) {
             double res = 0.0;
             for (int t = 0; t < Ra; ++t) res += std::norm(G[static_cast<size_t>(rc) * ldH + kb + t]);
             if (!std::isfinite(res)) fail(VSIE_E_NAN, "non-finite block residual");
             all = all && std::sqrt(res) <= ctol[rc] * rn[rc];
+            worst = std::max(worst, std::sqrt(res) / rn[rc]);
+        }
+        if (p->progress) {
+            std::fprintf(stderr, "[vsie] block step %d (%d columns): max residual estimate %.3e of the cycle start\n",
+                         j + 1, Ra, worst);
+            std::fflush(stderr);
         }
         if (all) break;
     }
@@ -1883,12 +1906,13 @@ vsie_status vsie_solve(vsie_problem *p, int32_t f, vsie_precision prec, int32_t 
         require(nrhs >= 1, "nrhs must be >= 1");
         check_vec(b, ldb, p->m.n, "b");
         check_vec(x, ldx, p->m.n, "x");
-        vsie_solve_opts o{1e-10, 3000, 500, 1e-5, 20, 0, 0.0};
+        vsie_solve_opts o{1e-10, 3000, 500, 1e-5, 20, 0, 0.0, 0};
         if (opts) o = *opts;
         require(o.tol > 0 && o.max_iter >= 0 && o.restart >= 1 && o.restart <= 20000 &&
                     o.inner_tol > 0 && o.inner_tol < 1 && o.max_outer >= 1 && (o.block == 0 || o.block == 1) &&
-                    o.relax >= 0 && o.relax < 1,
+                    o.relax >= 0 && o.relax < 1 && (o.progress == 0 || o.progress == 1),
                 "invalid solver options");
+        p->progress = o.progress;
         hipStream_t s = as_stream(stream);
         const int R = static_cast<int>(nrhs);
         SolveCounters cnt(R);

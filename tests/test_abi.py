@@ -90,3 +90,31 @@ def test_null_handles(V):
     h = ctypes.c_void_p(1234)
     st = lib.vsie_assemble(ctypes.byref(g), None, None, None, 0, None, ctypes.byref(h))
     assert st == V.VSIE_E_INVALID and h.value is None
+
+
+def test_struct_layouts_match_header(V, tmp_path):
+    """The ctypes mirrors of the header's structs have the C compiler's size
+    and field offsets (a gcc program built from include/vsie.h prints them)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no host C compiler")
+    structs = {"vsie_geometry": V.Geometry, "vsie_tuning": V.Tuning, "vsie_solve_opts": V.SolveOpts,
+               "vsie_solve_info": V.SolveInfo, "vsie_kernel_stats": V.KernelStats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "vsie.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in cls._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                        text=True).stdout.splitlines())
+    for cname, cls in structs.items():
+        assert int(out["%s size" % cname]) == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert int(out["%s.%s" % (cname, fname)]) == getattr(cls, fname).offset, (cname, fname)

@@ -50,6 +50,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched workloads")
+    ap.add_argument("--c4-solve", action="store_true",
+                    help="instead of the steps: the block GMRES solves of the 100^3 cube-with-ellipsoid "
+                         "medium (n = 1,076,336) at k0 = 40 for 16 plane waves, FP32 operator in FP64 "
+                         "refinement and plain FP64, to rel. residual 1e-10 (about 17 minutes; the "
+                         "solver prints a progress line per block step on stderr)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the steps, copy MIB MiB device-to-device three times (a kernel of "
                          "known traffic for scaling HBM byte counters)")
@@ -135,6 +140,31 @@ def c3_gradient(V, W, n_cells=3):
             "fd_check": {"cells": [int(j) for j in cells], "step": "1e-3 relative, central",
                          "misfit_solves": "FP64 to 1e-13", "rel_err_grad_c": errs["c"],
                          "rel_err_grad_rho": errs["rho"]}}
+
+
+def c4_block_solve(V, W):
+    """The largest configuration solved at its first wavenumber: 16 plane
+    waves by block GMRES, FP32 operator (matrix cores) in FP64 refinement and
+    plain FP64, both to relative residual 1e-10; the two solutions compared."""
+    import torch
+    mesh, mat, k0s, dirs, _ = W.config_problem("c4")
+    P = V.Problem.from_mesh(mesh, mat, k0s)
+    B = P.plane_wave(dirs, f=0).contiguous()
+    out, sols = {}, {}
+    for name, prec in (("fp32_refine", V.VSIE_FP32), ("fp64", V.VSIE_FP64)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = P.solve(B, f=0, prec=prec, tol=TOL, block=True, progress=True)
+        torch.cuda.synchronize()
+        out[name] = {"solve_s": time.perf_counter() - t0, "iterations": info}
+        sols[name] = x
+    out["speedup_fp32_refine_vs_fp64"] = out["fp64"]["solve_s"] / out["fp32_refine"]["solve_s"]
+    out["rel_diff_fp32_refine_vs_fp64_solution"] = float(
+        torch.linalg.norm(sols["fp32_refine"] - sols["fp64"]) / torch.linalg.norm(sols["fp64"]))
+    P.close()
+    return {"c4_block_solve": {
+        "workload": "cube with ellipsoid, 100^3 grid, n=%d, k0=%.0f, %d plane waves, block GMRES to rel. "
+                    "residual 1e-10" % (mesh.n, k0s[0], dirs.shape[0]), **out}}
 
 
 def batched_workloads(V, W):
@@ -246,6 +276,9 @@ def main():
 
     assert torch.cuda.is_available(), "needs a GPU"
     torch.cuda.set_device(0)
+    if args.c4_solve:
+        print(json.dumps(c4_block_solve(V, W)), flush=True)
+        return
     mesh, mat, k0s, dirs, _ = W.config_problem("c1")
     k0 = k0s[0]
     P = V.Problem.from_mesh(mesh, mat, k0s)

@@ -189,7 +189,9 @@ typedef struct {
     double tol;          /* stop when ||b - A x|| <= tol ||b|| (FP64 residual); default 1e-10 */
     int32_t max_iter;    /* total GMRES iterations (all cycles, all outer steps); default 3000 */
     int32_t restart;     /* Krylov dimension per cycle; default 500, lowered when the
-                            basis of all nrhs right-hand sides would exceed 48 GiB */
+                            basis of all nrhs right-hand sides would exceed 48 GiB
+                            (two bases of at most 48 GiB each: the first cycle's is kept
+                            to deflate the later cycles) */
     double inner_tol;    /* VSIE_FP32 only: relative tolerance of each inner solve; default 1e-5 */
     int32_t max_outer;   /* VSIE_FP32 only: refinement steps; default 20 */
     int32_t block;       /* 0: an independent GMRES per right-hand side, advanced in

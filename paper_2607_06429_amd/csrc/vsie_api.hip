@@ -765,7 +765,7 @@ void to_device(T *d, const std::vector<T> &h, hipStream_t s) {
     VSIE_HIP(hipStreamSynchronize(s));  // h may change right after
 }
 
-constexpr int64_t kKrylovBytes = int64_t(48) << 30;  // cap on the two Krylov bases (48 GiB)
+constexpr int64_t kKrylovBytes = int64_t(96) << 30;  // cap on the two Krylov bases (96 GiB of the 288 GB)
 
 int norm_chunks(int64_t n) { return static_cast<int>(std::min<int64_t>(256, std::max<int64_t>(1, n / 2048))); }
 

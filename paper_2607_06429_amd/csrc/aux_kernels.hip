@@ -171,8 +171,6 @@ __global__ void reduce_kernel(int64_t n_t, int nrhs, int n_parts, const double2 
     }
 }
 
-// y[i + r ldy] = d_i x[i + r ldx] + sum_c part[(c nrhs + r) n_t + i] with FP32 partials
-// added in FP64 (d_i = diag[i], conjugated when conj_diag).
 // X2[i + r n] = Re x[i + r ldx], X2[i + (nrhs + r) n] = Im x[i + r ldx]  (FP32)
 __global__ void pack_planar_kernel(int64_t n, int nrhs, const double2 *__restrict__ x, int64_t ldx,
                                    float *__restrict__ X2) {
@@ -284,116 +282,10 @@ __device__ inline double2 block_sum2(double2 v, double2 *sh) {
     return sh[0];
 }
 
-// partial[j * n_chunks + c] = sum over rows of chunk c of conj(V[i, j]) w[i]
-__global__ __launch_bounds__(kT) void dots_kernel(int64_t n, int64_t rows_per_chunk,
-                                                  const double2 *__restrict__ V, int64_t ldv,
-                                                  const double2 *__restrict__ w,
-                                                  double2 *__restrict__ partial, int n_chunks) {
-    __shared__ double2 sh[kT];
-    const int c = blockIdx.x, j = blockIdx.y;
-    const int64_t r0 = static_cast<int64_t>(c) * rows_per_chunk;
-    const int64_t r1 = (r0 + rows_per_chunk < n) ? r0 + rows_per_chunk : n;
-    double2 acc = make_double2(0.0, 0.0);
-    const double2 *__restrict__ col = V + j * ldv;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += kT) {
-        const double2 a = col[i], b = w[i];
-        acc.x += a.x * b.x + a.y * b.y;
-        acc.y += a.x * b.y - a.y * b.x;
-    }
-    const double2 s = block_sum2<kT>(acc, sh);
-    if (threadIdx.x == 0) partial[static_cast<int64_t>(j) * n_chunks + c] = s;
-}
-
-__global__ void dots_final_kernel(int k, const double2 *__restrict__ partial, int n_chunks,
-                                  double2 *__restrict__ h) {
-    const int j = blockIdx.x * kT + threadIdx.x;
-    if (j >= k) return;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int c = 0; c < n_chunks; ++c) {
-        acc.x += partial[static_cast<int64_t>(j) * n_chunks + c].x;
-        acc.y += partial[static_cast<int64_t>(j) * n_chunks + c].y;
-    }
-    h[j] = acc;
-}
-
-// w[i] += sign * sum_j V[i, j] h[j]
-__global__ void gemv_kernel(int64_t n, int k, const double2 *__restrict__ V, int64_t ldv,
-                            const double2 *__restrict__ h, double sign, double2 *__restrict__ w) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
-    if (i >= n) return;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int j = 0; j < k; ++j) {
-        const double2 a = V[i + j * ldv], b = h[j];
-        acc.x += a.x * b.x - a.y * b.y;
-        acc.y += a.x * b.y + a.y * b.x;
-    }
-    double2 v = w[i];
-    v.x += sign * acc.x;
-    v.y += sign * acc.y;
-    w[i] = v;
-}
-
-__global__ __launch_bounds__(kT) void norm_kernel(int64_t n, int64_t rows_per_chunk,
-                                                  const double2 *__restrict__ w,
-                                                  double *__restrict__ partial) {
-    __shared__ double2 sh[kT];
-    const int c = blockIdx.x;
-    const int64_t r0 = static_cast<int64_t>(c) * rows_per_chunk;
-    const int64_t r1 = (r0 + rows_per_chunk < n) ? r0 + rows_per_chunk : n;
-    double acc = 0.0;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += kT) acc += w[i].x * w[i].x + w[i].y * w[i].y;
-    const double2 s = block_sum2<kT>(make_double2(acc, 0.0), sh);
-    if (threadIdx.x == 0) partial[c] = s.x;
-}
-
-__global__ void norm_final_kernel(const double *__restrict__ partial, int n_chunks,
-                                  double *__restrict__ out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double acc = 0.0;
-    for (int c = 0; c < n_chunks; ++c) acc += partial[c];
-    out[0] = sqrt(acc);
-}
-
-__global__ void scale_copy_kernel(int64_t n, const double2 *__restrict__ w,
-                                  const double *__restrict__ nrm, double2 *__restrict__ v) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
-    if (i >= n) return;
-    const double s = nrm[0];
-    const double inv = s > 0.0 ? 1.0 / s : 0.0;
-    v[i] = make_double2(w[i].x * inv, w[i].y * inv);
-}
-
-__global__ void scale_kernel(int64_t n, const double2 *__restrict__ w, double sc,
-                             double2 *__restrict__ v) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
-    if (i >= n) return;
-    v[i] = make_double2(w[i].x * sc, w[i].y * sc);
-}
-
 __global__ void zero_kernel(int64_t n, double2 *__restrict__ v) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
     if (i >= n) return;
     v[i] = make_double2(0.0, 0.0);
-}
-
-__global__ void sub_kernel(int64_t n, const double2 *__restrict__ b, const double2 *__restrict__ ax,
-                           double2 *__restrict__ r) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
-    if (i >= n) return;
-    r[i] = make_double2(b[i].x - ax[i].x, b[i].y - ax[i].y);
-}
-
-__global__ void add_kernel(int64_t n, const double2 *__restrict__ d, double2 *__restrict__ x) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
-    if (i >= n) return;
-    x[i] = make_double2(x[i].x + d[i].x, x[i].y + d[i].y);
-}
-
-__global__ void copy_kernel(int64_t n, int ncols, const double2 *__restrict__ a, int64_t lda,
-                            double2 *__restrict__ b, int64_t ldb) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
-    if (i >= n) return;
-    for (int c = 0; c < ncols; ++c) b[i + c * ldb] = a[i + c * lda];
 }
 
 // --- batched Krylov kernels ---------------------------------------------------
@@ -723,75 +615,9 @@ void launch_plane_wave(int64_t n, const double *px, const double *py, const doub
     LAUNCH_CHECK();
 }
 
-static int64_t rows_per_chunk(int64_t n, int n_chunks) { return (n + n_chunks - 1) / n_chunks; }
-
-void blas_dots(int64_t n, int k, const double2 *V, int64_t ldv, const double2 *w, double2 *partial,
-               int n_chunks, double2 *h, hipStream_t s) {
-    if (k == 0) return;
-    hipLaunchKernelGGL(dots_kernel, dim3(n_chunks, k), dim3(kT), 0, s, n, rows_per_chunk(n, n_chunks),
-                       V, ldv, w, partial, n_chunks);
-    LAUNCH_CHECK();
-    hipLaunchKernelGGL(dots_final_kernel, dim3(blocks_for(k)), dim3(kT), 0, s, k, partial, n_chunks, h);
-    LAUNCH_CHECK();
-}
-
-void blas_gemv_sub(int64_t n, int k, const double2 *V, int64_t ldv, const double2 *h, double2 *w,
-                   hipStream_t s) {
-    if (k == 0 || n == 0) return;
-    hipLaunchKernelGGL(gemv_kernel, dim3(blocks_for(n)), dim3(kT), 0, s, n, k, V, ldv, h, -1.0, w);
-    LAUNCH_CHECK();
-}
-
-void blas_gemv_add(int64_t n, int k, const double2 *V, int64_t ldv, const double2 *yv, double2 *x,
-                   hipStream_t s) {
-    if (k == 0 || n == 0) return;
-    hipLaunchKernelGGL(gemv_kernel, dim3(blocks_for(n)), dim3(kT), 0, s, n, k, V, ldv, yv, 1.0, x);
-    LAUNCH_CHECK();
-}
-
-void blas_norm2(int64_t n, const double2 *w, double *partial, int n_chunks, double *out,
-                hipStream_t s) {
-    hipLaunchKernelGGL(norm_kernel, dim3(n_chunks), dim3(kT), 0, s, n, rows_per_chunk(n, n_chunks), w,
-                       partial);
-    LAUNCH_CHECK();
-    hipLaunchKernelGGL(norm_final_kernel, dim3(1), dim3(64), 0, s, partial, n_chunks, out);
-    LAUNCH_CHECK();
-}
-
-void blas_scale_copy(int64_t n, const double2 *w, const double *nrm, double2 *v, hipStream_t s) {
-    if (n == 0) return;
-    hipLaunchKernelGGL(scale_copy_kernel, dim3(blocks_for(n)), dim3(kT), 0, s, n, w, nrm, v);
-    LAUNCH_CHECK();
-}
-
-void blas_scale(int64_t n, const double2 *w, double sc, double2 *v, hipStream_t s) {
-    if (n == 0) return;
-    hipLaunchKernelGGL(scale_kernel, dim3(blocks_for(n)), dim3(kT), 0, s, n, w, sc, v);
-    LAUNCH_CHECK();
-}
-
 void blas_zero(int64_t n, double2 *v, hipStream_t s) {
     if (n == 0) return;
     hipLaunchKernelGGL(zero_kernel, dim3(blocks_for(n)), dim3(kT), 0, s, n, v);
-    LAUNCH_CHECK();
-}
-
-void blas_sub(int64_t n, const double2 *b, const double2 *ax, double2 *r, hipStream_t s) {
-    if (n == 0) return;
-    hipLaunchKernelGGL(sub_kernel, dim3(blocks_for(n)), dim3(kT), 0, s, n, b, ax, r);
-    LAUNCH_CHECK();
-}
-
-void blas_add(int64_t n, const double2 *d, double2 *x, hipStream_t s) {
-    if (n == 0) return;
-    hipLaunchKernelGGL(add_kernel, dim3(blocks_for(n)), dim3(kT), 0, s, n, d, x);
-    LAUNCH_CHECK();
-}
-
-void blas_copy(int64_t n, const double2 *a, int64_t lda, double2 *b, int64_t ldb, int ncols,
-               hipStream_t s) {
-    if (n == 0 || ncols == 0) return;
-    hipLaunchKernelGGL(copy_kernel, dim3(blocks_for(n)), dim3(kT), 0, s, n, ncols, a, lda, b, ldb);
     LAUNCH_CHECK();
 }
 

@@ -263,21 +263,7 @@ void launch_plane_wave_at(int64_t n, const double *tx, const double *ty, const d
                           double dx, double dy, double dz, double2 *b, hipStream_t s);
 
 // dense vector kernels for the Krylov solver (aux_kernels.hip)
-void blas_dots(int64_t n, int k, const double2 *V, int64_t ldv, const double2 *w,
-               double2 *partial, int n_chunks, double2 *h, hipStream_t s);
-void blas_gemv_sub(int64_t n, int k, const double2 *V, int64_t ldv, const double2 *h,
-                   double2 *w, hipStream_t s);
-void blas_gemv_add(int64_t n, int k, const double2 *V, int64_t ldv, const double2 *yv,
-                   double2 *x, hipStream_t s);
-void blas_norm2(int64_t n, const double2 *w, double *partial, int n_chunks, double *out,
-                hipStream_t s);
-void blas_scale_copy(int64_t n, const double2 *w, const double *nrm, double2 *v, hipStream_t s);
-void blas_scale(int64_t n, const double2 *w, double sc, double2 *v, hipStream_t s);
 void blas_zero(int64_t n, double2 *v, hipStream_t s);
-void blas_sub(int64_t n, const double2 *b, const double2 *ax, double2 *r, hipStream_t s);
-void blas_add(int64_t n, const double2 *d, double2 *x, hipStream_t s);
-void blas_copy(int64_t n, const double2 *a, int64_t lda, double2 *b, int64_t ldb, int ncols,
-               hipStream_t s);
 
 // batched Krylov kernels (aux_kernels.hip); basis vector j of rhs r at V + (j R + r) n
 void bblas_dots(int64_t n, int k, int R, int nslots, const int32_t *act, const double2 *V,

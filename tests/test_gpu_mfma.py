@@ -13,6 +13,7 @@ from gpu_cases import CASES, case, dev, host, say
 pytestmark = pytest.mark.gpu
 
 TOL32 = 1e-5
+TOL64 = 1e-12
 VARIANTS = [(2, 1), (4, 1), (2, 2), (4, 2)]
 
 
@@ -119,6 +120,19 @@ def test_c4_multi_frequency_sampled_rows(V):
         e = O.rel_error(host(Y[f * R:(f + 1) * R])[rows], ref)
         say("  k0 %.0f: rel err %.3e" % (k, e))
         assert e <= TOL32
+    # the FP64 operator at this size (the refinement residual of the c4
+    # solves): one column, where the once-per-pair kernels would need more
+    # than their partial-sum cap and the one-sided kernels run
+    d = O.discretise(mesh, mat, k0s[0])
+    x1 = host(X[:1])
+    P.profile(True)
+    y1 = host(P.matvec(X[:1].contiguous(), f=0, prec=V.VSIE_FP64))
+    st = P.kernel_stats()
+    P.profile(False)
+    e64 = O.rel_error(y1.reshape(-1)[rows], O.matvec(d, x1.reshape(-1, 1), rows=rows)[:, 0])
+    say("  FP64, one column: rel err %.3e, kernels %s" % (e64, sorted(st)))
+    assert e64 <= TOL64
+    assert "fwd_single_layer_fp64" in st and not any(k.startswith("sym_") for k in st)
     P.close()
     del X, Y
     torch.cuda.empty_cache()

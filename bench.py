@@ -17,7 +17,9 @@ Unless --no-batched is given, the line also carries the batched workloads
 (outside the timed steps): 128 plane-wave directions at k0 = 16 on the 57^3
 grid (n = 116,445) solved by block GMRES with the assembled FP32 operator,
 matrix-free FP32 and matrix-free FP64; the receiver-misfit gradient of the
-log-normal medium with FP32 and with FP64 solves; and one multi-frequency FP32
+log-normal medium with FP32 and with FP64 solves; the paper's fourth benchmark
+in 3D (nested cubes, 226,981 cuboids, n = 260,401) in both precisions; and
+one multi-frequency FP32
 product of the cube-with-ellipsoid medium on the 100^3 grid (n = 1,076,336),
 8 wavenumbers x 16 directions in one matrix-core launch per source class.
 """
@@ -167,6 +169,31 @@ def c4_block_solve(V, W):
                     "residual 1e-10" % (mesh.n, k0s[0], dirs.shape[0]), **out}}
 
 
+def benchmark4_solve(V, W):
+    """The paper's largest VSIE system: its fourth benchmark in 3D (nested cubes
+    of 7 and 5 mm, heterogeneous density with a jump, 61^3 = 226,981 cuboids,
+    n = 260,401, exterior wavelength 1.4 mm, incidence (1,1,0)/sqrt 2), solved
+    with the FP32 operator in FP64 refinement and with the FP64 operator."""
+    import torch
+    mesh, mat, k0s, dirs, grad = W.benchmark4_problem()
+    P = V.Problem.from_mesh(mesh, mat, k0s, grad_rho=grad)
+    b = P.plane_wave(dirs)
+    out, sols = {}, {}
+    for name, prec in (("fp32_refine", V.VSIE_FP32), ("fp64", V.VSIE_FP64)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = P.solve(b, prec=prec, tol=TOL)
+        torch.cuda.synchronize()
+        out[name] = {"solve_s": time.perf_counter() - t0, "iterations": info}
+        sols[name] = x
+    out["speedup_fp32_refine_vs_fp64"] = out["fp64"]["solve_s"] / out["fp32_refine"]["solve_s"]
+    out["rel_diff_fp32_refine_vs_fp64_solution"] = float(
+        torch.linalg.norm(sols["fp32_refine"] - sols["fp64"]) / torch.linalg.norm(sols["fp64"]))
+    P.close()
+    return {"workload": "paper's benchmark 4 in 3D: nested cubes 7/5 mm, 61^3 cuboids fitted to both "
+                        "interfaces, n=%d, k0=%.4f/mm, analytic density gradient" % (mesh.n, k0s[0]), **out}
+
+
 def batched_workloads(V, W):
     """Block GMRES over 128 directions (assembled and matrix-free) and one
     multi-frequency product over 8 wavenumbers x 16 directions."""
@@ -216,6 +243,7 @@ def batched_workloads(V, W):
     P.close()
     del B
     out["c3_adjoint_gradient"] = c3_gradient(V, W)
+    out["benchmark4_3d_solve"] = benchmark4_solve(V, W)
     mesh, mat, k0s, dirs, _ = W.config_problem("c4")
     P = V.Problem.from_mesh(mesh, mat, k0s)
     n, nf, R = P.n, len(k0s), dirs.shape[0]

@@ -81,6 +81,10 @@ typedef struct {
                                        -1 for none; NULL means no neighbours */
     const double *vgrad_alpha;      /* optional 3*n_vol (x,y,z per cell) grad alpha
                                        overriding the neighbour stencil; or NULL */
+    const double *vgrad_rho;        /* optional 3*n_vol (x,y,z per cell) gradient of an
+                                       analytic density at the centroids: grad alpha =
+                                       -rho0 grad(rho) / rho^2 (eq_alpha), used when
+                                       vgrad_alpha is NULL, instead of the stencil; or NULL */
     int64_t n_srf;                  /* number of surface elements (>= 0) */
     const double *sx, *sy, *sz;     /* element centroids */
     const double *snx, *sny, *snz;  /* unit normals pointing out of the inside
@@ -284,7 +288,9 @@ vsie_status vsie_adjoint_rhs(vsie_problem *p, int32_t f, int64_t nrhs, const dou
  *   dJ = Re sum_r [ rho_r^H dE P_r - lam_r^H dA P_r ].
  * The density enters through alpha = rho0/rho - 1 in the single-layer
  * weights, the mass function, the interface jump weights and the grad-alpha
- * neighbour stencil (not differentiated when vgrad_alpha was given). */
+ * neighbour stencil (not differentiated when vgrad_alpha was given; with
+ * vgrad_rho, grad alpha = -rho0 grad(rho) / rho^2 varies with the cell's own
+ * density while grad(rho) is held fixed). */
 vsie_status vsie_param_gradient(vsie_problem *p, int32_t f, int64_t nrhs, const double *P, int64_t ldp,
                                 const double *lam, int64_t ldl, const double *z, int64_t ldz,
                                 const double *Z, int64_t ldZ, const double *zR, int64_t ldzr,

@@ -180,9 +180,17 @@ class Discretisation:
         return self.m - self.D
 
 
-def discretise(mesh, mat, k0, grad_alpha=None) -> Discretisation:
+def grad_alpha_from_density_gradient(rho, grad_rho, rho0):
+    """grad alpha of an analytic density: alpha = rho0/rho - 1 (eq_alpha), so
+    grad alpha = -rho0 grad(rho) / rho^2 at each centroid."""
+    rho = np.asarray(rho, dtype=np.float64)
+    return -rho0 * np.asarray(grad_rho, dtype=np.float64) / (rho * rho)[:, None]
+
+
+def discretise(mesh, mat, k0, grad_alpha=None, grad_rho=None) -> Discretisation:
     """Per-element data of the collocation system (Theorem 3 with P0 elements,
-    centroid collocation and the midpoint rule)."""
+    centroid collocation and the midpoint rule).  grad alpha: given, else from
+    an analytic density gradient grad_rho, else the neighbour stencil."""
     rho0, c0 = mat.rho0, mat.c0
     omega = k0 * c0
     rho = mat.vol_rho
@@ -190,7 +198,12 @@ def discretise(mesh, mat, k0, grad_alpha=None) -> Discretisation:
     b_cells = beta(rho, mat.vol_c, rho0, c0, omega)
     w = mesh.vol_w
     sV = w * (b_cells - k0 ** 2 * a_cells)
-    ga = grad_alpha_stencil(mesh, a_cells) if grad_alpha is None else np.asarray(grad_alpha)
+    if grad_alpha is not None:
+        ga = np.asarray(grad_alpha)
+    elif grad_rho is not None:
+        ga = grad_alpha_from_density_gradient(rho, grad_rho, rho0)
+    else:
+        ga = grad_alpha_stencil(mesh, a_cells)
     gT = w[:, None] * ga
 
     # surfaces: limit densities from the adjacent cells; exterior has rho0 (alpha = 0)
@@ -398,16 +411,17 @@ def solve_gmres(d: Discretisation, b, tol=1e-12, restart=200, maxiter=3000, call
 # ---------------------------------------------------------------------------
 # receiver misfit (for finite-difference checks of adjoint gradients)
 
-def receiver_pressures(mesh, mat, k0, dirs, receivers):
+def receiver_pressures(mesh, mat, k0, dirs, receivers, grad_rho=None):
     """p_rec (n_rec, Q) for the plane waves `dirs` (Q, 3): dense LU solve of the
-    collocation system, then the representation formula at the receivers."""
-    d = discretise(mesh, mat, k0)
+    collocation system, then the representation formula at the receivers.
+    grad_rho: analytic density gradient per cell (held fixed), or None."""
+    d = discretise(mesh, mat, k0, grad_rho=grad_rho)
     D = np.atleast_2d(dirs)
     P = solve_lu(d, plane_wave(d.pts, k0, D))
     return exterior_field(d, receivers, P, D)
 
 
-def receiver_misfit(mesh, mat, k0, dirs, receivers, data):
+def receiver_misfit(mesh, mat, k0, dirs, receivers, data, grad_rho=None):
     """J = 1/2 sum |p_rec - data|^2 over receivers and incidences."""
-    pr = receiver_pressures(mesh, mat, k0, dirs, receivers)
+    pr = receiver_pressures(mesh, mat, k0, dirs, receivers, grad_rho)
     return 0.5 * float(np.sum(np.abs(pr - data) ** 2))

@@ -49,7 +49,7 @@ class VsieError(RuntimeError):
 class Geometry(ctypes.Structure):
     _fields_ = [
         ("n_vol", _I64), ("vx", _P), ("vy", _P), ("vz", _P), ("vw", _P), ("vdom", _P),
-        ("vnb", _P), ("vgrad_alpha", _P),
+        ("vnb", _P), ("vgrad_alpha", _P), ("vgrad_rho", _P),
         ("n_srf", _I64), ("sx", _P), ("sy", _P), ("sz", _P), ("snx", _P), ("sny", _P),
         ("snz", _P), ("sarea", _P), ("siface", _P), ("scell_in", _P), ("scell_out", _P),
         ("rho0", _D), ("c0", _D),
@@ -206,7 +206,7 @@ def vsie_assemble(geom: dict, vrho, vc, k0, stream=None):
     g = Geometry()
     g.n_vol = 0 if geom.get("vw") is None else len(geom["vw"])
     g.n_srf = 0 if geom.get("sarea") is None else len(geom["sarea"])
-    for nm in ("vx", "vy", "vz", "vw", "vgrad_alpha", "sx", "sy", "sz", "snx", "sny", "snz", "sarea"):
+    for nm in ("vx", "vy", "vz", "vw", "vgrad_alpha", "vgrad_rho", "sx", "sy", "sz", "snx", "sny", "snz", "sarea"):
         setattr(g, nm, f64(nm))
     for nm in ("vdom", "vnb", "siface", "scell_in", "scell_out"):
         setattr(g, nm, i32(nm))
@@ -425,10 +425,12 @@ class Problem:
         self.n = vsie_size(self.handle)
 
     @classmethod
-    def from_mesh(cls, mesh, mat, k0, stream=None, grad_alpha=None):
+    def from_mesh(cls, mesh, mat, k0, stream=None, grad_alpha=None, grad_rho=None):
         g = geometry_from_mesh(mesh, mat.rho0, mat.c0)
         if grad_alpha is not None:
             g["vgrad_alpha"] = np.ascontiguousarray(grad_alpha, dtype=np.float64).ravel()
+        if grad_rho is not None:
+            g["vgrad_rho"] = np.ascontiguousarray(grad_rho, dtype=np.float64).ravel()
         return cls(g, mat.vol_rho, mat.vol_c, k0, stream)
 
     def close(self):

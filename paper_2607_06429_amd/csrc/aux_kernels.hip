@@ -54,6 +54,9 @@ __global__ void weights_kernel(DeviceMesh m, const double *__restrict__ k0, int 
         double ga[3] = {0.0, 0.0, 0.0};
         if (m.vga) {
             for (int ax = 0; ax < 3; ++ax) ga[ax] = m.vga[3 * e + ax];
+        } else if (m.vgr) {
+            // alpha = rho0/rho - 1 (eq_alpha): grad alpha = -rho0 grad(rho) / rho^2
+            for (int ax = 0; ax < 3; ++ax) ga[ax] = -rho0 * m.vgr[3 * e + ax] / (rho * rho);
         } else if (m.vnb) {
             const double *pc[3] = {m.px, m.py, m.pz};
             const int dom = m.vdom[e];

@@ -176,8 +176,15 @@ __global__ void chain_kernel(ChainArgs a) {
         const double dv = -m.sarea[q] * sgn * dalpha;
         g += dv * (a.gv[f] * m.snx[q] + a.gv[m.n + f] * m.sny[q] + a.gv[2 * m.n + f] * m.snz[q]);
     }
+    // analytic density gradient: grad alpha_k = -rho0 grad(rho)_k / rho_k^2 moves
+    // with rho_k by 2 rho0 grad(rho)_k / rho_k^3 (grad(rho) itself is an input)
+    if (m.vgr) {
+        const double rk = m.vrho[k];
+        for (int ax = 0; ax < 3; ++ax)
+            g += a.gv[ax * m.n + k] * m.vw[k] * (2.0 * m.rho0 * m.vgr[3 * k + ax] / (rk * rk * rk));
+    }
     // grad alpha stencils that read alpha_k (own cell and same-axis neighbours)
-    if (m.vnb && !m.vga) {
+    if (m.vnb && !m.vga && !m.vgr) {
         for (int ax = 0; ax < 3; ++ax) {
             const int64_t cand[3] = {k, m.vnb[6 * k + 2 * ax], m.vnb[6 * k + 2 * ax + 1]};
             for (int t = 0; t < 3; ++t) {

@@ -257,6 +257,9 @@ void validate_geometry(const vsie_geometry *g, const double *vrho, const double 
             if (g->vgrad_alpha)
                 for (int a = 0; a < 3; ++a)
                     require(std::isfinite(g->vgrad_alpha[3 * e + a]), "non-finite grad alpha");
+            if (g->vgrad_rho)
+                for (int a = 0; a < 3; ++a)
+                    require(std::isfinite(g->vgrad_rho[3 * e + a]), "non-finite grad rho");
         }
     }
     if (ns > 0) {
@@ -1672,6 +1675,7 @@ vsie_status vsie_assemble(const vsie_geometry *geom, const double *vrho, const d
         m.vdom = p->upload(g.vdom, g.n_vol);
         m.vnb = g.vnb ? p->upload(g.vnb, 6 * g.n_vol) : nullptr;
         m.vga = g.vgrad_alpha ? p->upload(g.vgrad_alpha, 3 * g.n_vol) : nullptr;
+        m.vgr = (g.vgrad_rho && !g.vgrad_alpha) ? p->upload(g.vgrad_rho, 3 * g.n_vol) : nullptr;
         m.vrho = p->upload(vrho, g.n_vol);
         m.vc = p->upload(vc, g.n_vol);
         m.snx = p->upload(g.snx, g.n_srf);

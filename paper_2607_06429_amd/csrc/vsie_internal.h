@@ -42,6 +42,7 @@ struct DeviceMesh {
     double *vw = nullptr;
     int32_t *vdom = nullptr, *vnb = nullptr;
     double *vga = nullptr;  // optional explicit grad alpha (3 n_vol, xyz interleaved)
+    double *vgr = nullptr;  // optional analytic grad rho (3 n_vol, xyz interleaved)
     double *vrho = nullptr, *vc = nullptr;
     // surface data
     double *snx = nullptr, *sny = nullptr, *snz = nullptr, *sarea = nullptr;

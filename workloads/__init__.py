@@ -26,7 +26,8 @@ import math
 import numpy as np
 
 __all__ = [
-    "Mesh", "Materials", "voxel_mesh", "nested_balls", "cube_with_ellipsoid",
+    "Mesh", "Materials", "voxel_mesh", "tensor_mesh", "nested_balls", "cube_with_ellipsoid", "nested_cubes",
+    "benchmark4_density", "benchmark4_density_gradient", "benchmark4_problem",
     "materials_piecewise", "materials_config", "fibonacci_sphere",
     "lognormal_voxel_field", "seeded_complex", "CONFIGS", "config_problem",
 ]
@@ -160,6 +161,95 @@ def voxel_mesh(lo, hi, N, domain_fn) -> Mesh:
                 srf_iface=srf_iface, srf_cell_in=srf_in, srf_cell_out=srf_out)
 
 
+def tensor_mesh(edges, domain_of_index) -> Mesh:
+    """Cuboid mesh on the tensor grid edges x edges x edges (the same
+    nonuniform 1D grid on every axis): cell (i, j, k) spans
+    [e_i, e_i+1] x [e_j, e_j+1] x [e_k, e_k+1].
+
+    ``domain_of_index(I, J, K) -> int array`` classifies cells by index into 0
+    (exterior), 1 or 2, so that interfaces can sit exactly on grid planes.
+    Faces are built as in voxel_mesh, with the areas and centroids of the
+    cuboids.  ``Mesh.h`` is the largest cell width.
+    """
+    e = np.asarray(edges, dtype=np.float64)
+    N = e.size - 1
+    c1d = 0.5 * (e[:-1] + e[1:])
+    w1d = np.diff(e)
+    I, J, K = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
+    flat = np.asarray(domain_of_index(I.ravel(), J.ravel(), K.ravel()), dtype=np.int32)
+    order = np.concatenate([np.nonzero(flat == 1)[0], np.nonzero(flat == 2)[0]])
+    cell_of = -np.ones(N ** 3, dtype=np.int64)
+    cell_of[order] = np.arange(order.size)
+    ijk = np.stack(np.unravel_index(order, (N, N, N)), axis=1)
+    vol_xyz = c1d[ijk]
+    wid = w1d[ijk]
+    vol_w = wid[:, 0] * wid[:, 1] * wid[:, 2]
+    vol_dom = flat[order].astype(np.int32)
+
+    nb = -np.ones((order.size, 6), dtype=np.int32)
+    for ax in range(3):
+        for side, step in ((0, -1), (1, +1)):
+            q = ijk.copy()
+            q[:, ax] += step
+            inside = (q[:, ax] >= 0) & (q[:, ax] < N)
+            lin = np.full(order.size, -1, dtype=np.int64)
+            lin[inside] = np.ravel_multi_index(q[inside].T, (N, N, N))
+            nb[:, 2 * ax + side] = np.where(inside, cell_of[np.maximum(lin, 0)], -1)
+
+    faces = {1: [], 2: []}
+    for ax in range(3):
+        o1, o2 = [a for a in range(3) if a != ax]
+        for side, step in ((0, -1), (1, +1)):
+            other = nb[:, 2 * ax + side]
+            ext = np.nonzero(other < 0)[0]
+            g2 = np.nonzero((other >= 0) & (vol_dom == 2))[0]
+            g2 = g2[vol_dom[other[g2]] == 1]
+            nvec = np.zeros(3)
+            nvec[ax] = float(step)
+            for iface, cells, outs in ((1, ext, np.full(ext.size, -1)), (2, g2, other[g2])):
+                if cells.size == 0:
+                    continue
+                if iface == 1 and np.any(vol_dom[cells] != 1):
+                    raise ValueError("an Omega_2 cell touches the exterior")
+                fx = vol_xyz[cells].copy()
+                fx[:, ax] += step * 0.5 * wid[cells, ax]
+                area = wid[cells, o1] * wid[cells, o2]
+                faces[iface].append((fx, np.tile(nvec, (cells.size, 1)), cells, outs, area))
+
+    def cat(iface):
+        if not faces[iface]:
+            return (np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0, np.int32), np.zeros(0, np.int32),
+                    np.zeros(0))
+        parts = [np.concatenate([f[t] for f in faces[iface]]) for t in range(5)]
+        o = np.lexsort((parts[0][:, 0], parts[0][:, 1], parts[0][:, 2]))
+        return (parts[0][o], parts[1][o], parts[2][o].astype(np.int32), parts[3][o].astype(np.int32),
+                parts[4][o])
+
+    f1, f2 = cat(1), cat(2)
+    return Mesh(h=float(w1d.max()), vol_xyz=vol_xyz, vol_w=vol_w, vol_dom=vol_dom, vol_nb=nb,
+                srf_xyz=np.concatenate([f1[0], f2[0]]), srf_n=np.concatenate([f1[1], f2[1]]),
+                srf_area=np.concatenate([f1[4], f2[4]]),
+                srf_iface=np.concatenate([np.full(f1[0].shape[0], 1, np.int32),
+                                          np.full(f2[0].shape[0], 2, np.int32)]),
+                srf_cell_in=np.concatenate([f1[2], f2[2]]), srf_cell_out=np.concatenate([f1[3], f2[3]]))
+
+
+def nested_cubes(n_shell: int, n_inner: int, L1: float = 7.0, L2: float = 5.0) -> Mesh:
+    """Concentric cubes of sides L1 (Omega_1) and L2 (Omega_2) centred at the
+    origin, on a nonuniform cuboid grid fitted to both interfaces (the
+    paper's cuboid mesh for nested cubes): per axis n_shell cells across each
+    (L1 - L2)/2 shell slab and n_inner cells across the inner cube."""
+    a, b = 0.5 * L1, 0.5 * L2
+    edges = np.concatenate([np.linspace(-a, -b, n_shell + 1), np.linspace(-b, b, n_inner + 1)[1:],
+                            np.linspace(b, a, n_shell + 1)[1:]])
+
+    def dom(i, j, k):
+        lo, hi = n_shell, n_shell + n_inner
+        inner = (i >= lo) & (i < hi) & (j >= lo) & (j < hi) & (k >= lo) & (k < hi)
+        return np.where(inner, 2, 1)
+    return tensor_mesh(edges, dom)
+
+
 def nested_balls(N: int, R1: float = 1.0, R2: float = 0.5) -> Mesh:
     """Staircase voxel mesh of two concentric balls on an N^3 grid over [-R1, R1]^3."""
     def dom(x):
@@ -224,6 +314,43 @@ def seeded_complex(shape, seed: int = SEED) -> np.ndarray:
     """Complex128 array with i.i.d. standard normal real and imaginary parts."""
     rng = np.random.default_rng(seed)
     return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+# ---------------------------------------------------------------------------
+# the paper's heterogeneous-density benchmark with a density jump (nested
+# cubes of 7 mm and 5 mm, lengths in mm, density relative to the exterior's
+# 1000 kg/m^3, speeds relative to c0)
+
+def benchmark4_density(xyz: np.ndarray) -> np.ndarray:
+    """The inner cube's density: 2 - 0.8 sin(pi x/2.5) sin(pi y/2.5) cos(pi z/5)."""
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    return 2.0 - 0.8 * np.sin(np.pi * x / 2.5) * np.sin(np.pi * y / 2.5) * np.cos(np.pi * z / 5.0)
+
+
+def benchmark4_density_gradient(xyz: np.ndarray) -> np.ndarray:
+    """Analytic gradient of benchmark4_density, (n, 3)."""
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    sx, cx = np.sin(np.pi * x / 2.5), np.cos(np.pi * x / 2.5)
+    sy, cy = np.sin(np.pi * y / 2.5), np.cos(np.pi * y / 2.5)
+    sz, cz = np.sin(np.pi * z / 5.0), np.cos(np.pi * z / 5.0)
+    return -0.8 * np.stack([(np.pi / 2.5) * cx * sy * cz, (np.pi / 2.5) * sx * cy * cz,
+                            -(np.pi / 5.0) * sx * sy * sz], axis=1)
+
+
+def benchmark4_problem(n_shell: int = 9, n_inner: int = 43, lam0: float = 1.4):
+    """The paper's 3D run of its fourth benchmark: exterior wavelength lam0 mm,
+    incidence (1, 1, 0)/sqrt(2), c1 = c2 = c0/1.2, density 1 in Omega_0 and
+    Omega_1 and benchmark4_density in Omega_2.  The default grid, 9 + 43 + 9
+    cells per axis (61^3 = 226,981 cuboids, at most lam0/1.2/10 wide), is the
+    10-voxel-per-interior-wavelength mesh of that run.
+    Returns (mesh, materials, [k0], directions (1, 3), grad rho per cell)."""
+    mesh = nested_cubes(n_shell, n_inner)
+    mat = materials_piecewise(mesh, 1.0, 1.0, 1.0, 1.0 / 1.2, benchmark4_density, 1.0 / 1.2)
+    grad = np.zeros((mesh.n_vol, 3))
+    inner = mesh.vol_dom == 2
+    grad[inner] = benchmark4_density_gradient(mesh.vol_xyz[inner])
+    dirs = np.array([[1.0, 1.0, 0.0]]) / math.sqrt(2.0)
+    return mesh, mat, [2.0 * math.pi / lam0], dirs, grad
 
 
 # ---------------------------------------------------------------------------

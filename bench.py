@@ -17,9 +17,9 @@ Unless --no-batched is given, the line also carries the batched workloads
 (outside the timed steps): 128 plane-wave directions at k0 = 16 on the 57^3
 grid (n = 116,445) solved by block GMRES with the assembled FP32 operator,
 matrix-free FP32 and matrix-free FP64; the receiver-misfit gradient of the
-log-normal medium with FP32 and with FP64 solves; the paper's fourth benchmark
-in 3D (nested cubes, 226,981 cuboids, n = 260,401) in both precisions; and
-one multi-frequency FP32
+log-normal medium with FP32 and with FP64 solves; the paper's four benchmarks
+at the resolutions of its figures, the largest its 3D run of nested cubes
+(226,981 cuboids, n = 260,401), in both precisions; and one multi-frequency FP32
 product of the cube-with-ellipsoid medium on the 100^3 grid (n = 1,076,336),
 8 wavenumbers x 16 directions in one matrix-core launch per source class.
 """
@@ -169,29 +169,42 @@ def c4_block_solve(V, W):
                     "residual 1e-10" % (mesh.n, k0s[0], dirs.shape[0]), **out}}
 
 
-def benchmark4_solve(V, W):
-    """The paper's largest VSIE system: its fourth benchmark in 3D (nested cubes
-    of 7 and 5 mm, heterogeneous density with a jump, 61^3 = 226,981 cuboids,
-    n = 260,401, exterior wavelength 1.4 mm, incidence (1,1,0)/sqrt 2), solved
-    with the FP32 operator in FP64 refinement and with the FP64 operator."""
+def paper_benchmark_solves(V, W):
+    """The paper's four benchmarks (section 3) at the resolutions of its
+    figures, each solved with the FP32 operator in FP64 refinement and with
+    the FP64 operator: the sphere in a cube at 8 cells per interior
+    wavelength, the nested cubes with piecewise-constant density and the
+    heterogeneous single cube at 10, and the largest system, the 3D run of the
+    fourth benchmark (nested cubes with a heterogeneous density and a jump,
+    61^3 = 226,981 cuboids, n = 260,401, exterior wavelength 1.4 mm, incidence
+    (1,1,0)/sqrt 2)."""
     import torch
-    mesh, mat, k0s, dirs, grad = W.benchmark4_problem()
-    P = V.Problem.from_mesh(mesh, mat, k0s, grad_rho=grad)
-    b = P.plane_wave(dirs)
-    out, sols = {}, {}
-    for name, prec in (("fp32_refine", V.VSIE_FP32), ("fp64", V.VSIE_FP64)):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        x, info = P.solve(b, prec=prec, tol=TOL)
-        torch.cuda.synchronize()
-        out[name] = {"solve_s": time.perf_counter() - t0, "iterations": info}
-        sols[name] = x
-    out["speedup_fp32_refine_vs_fp64"] = out["fp64"]["solve_s"] / out["fp32_refine"]["solve_s"]
-    out["rel_diff_fp32_refine_vs_fp64_solution"] = float(
-        torch.linalg.norm(sols["fp32_refine"] - sols["fp64"]) / torch.linalg.norm(sols["fp64"]))
-    P.close()
-    return {"workload": "paper's benchmark 4 in 3D: nested cubes 7/5 mm, 61^3 cuboids fitted to both "
-                        "interfaces, n=%d, k0=%.4f/mm, analytic density gradient" % (mesh.n, k0s[0]), **out}
+    cases = (("b1_sphere_in_cube", W.benchmark1_problem), ("b2_nested_cubes_piecewise", W.benchmark2_problem),
+             ("b3_heterogeneous_cube", W.benchmark3_problem), ("b4_3d_run", W.benchmark4_problem))
+    res = {}
+    for label, make in cases:
+        mesh, mat, k0s, dirs, grad = make()
+        P = V.Problem.from_mesh(mesh, mat, k0s, grad_rho=grad)
+        b = P.plane_wave(dirs)
+        out, sols = {"n": mesh.n, "k0": k0s[0]}, {}
+        if mesh.n < 100000:
+            # untimed first solves (work buffers, captured graphs); the large
+            # system's solves take seconds and are timed cold
+            for prec in (V.VSIE_FP32, V.VSIE_FP64):
+                P.solve(b, prec=prec, tol=TOL)
+        for name, prec in (("fp32_refine", V.VSIE_FP32), ("fp64", V.VSIE_FP64)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, info = P.solve(b, prec=prec, tol=TOL)
+            torch.cuda.synchronize()
+            out[name] = {"solve_s": time.perf_counter() - t0, "iterations": info}
+            sols[name] = x
+        out["speedup_fp32_refine_vs_fp64"] = out["fp64"]["solve_s"] / out["fp32_refine"]["solve_s"]
+        out["rel_diff_fp32_refine_vs_fp64_solution"] = float(
+            torch.linalg.norm(sols["fp32_refine"] - sols["fp64"]) / torch.linalg.norm(sols["fp64"]))
+        P.close()
+        res[label] = out
+    return res
 
 
 def batched_workloads(V, W):
@@ -243,7 +256,7 @@ def batched_workloads(V, W):
     P.close()
     del B
     out["c3_adjoint_gradient"] = c3_gradient(V, W)
-    out["benchmark4_3d_solve"] = benchmark4_solve(V, W)
+    out["paper_benchmarks"] = paper_benchmark_solves(V, W)
     mesh, mat, k0s, dirs, _ = W.config_problem("c4")
     P = V.Problem.from_mesh(mesh, mat, k0s)
     n, nf, R = P.n, len(k0s), dirs.shape[0]

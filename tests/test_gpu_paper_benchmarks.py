@@ -1,0 +1,186 @@
+"""The paper's four benchmarks (section 3) on the GPU.
+
+1. Sphere in a cube (section 3.2): the solution against the spherical-harmonic
+   series, with the paper's bound of 3% at 8 cells per interior wavelength and
+   mesh convergence.
+2. Nested cubes, piecewise-constant density (section 3.3).
+3. One cube, smooth heterogeneous density (section 3.4), grad alpha from the
+   analytic density gradient.
+4. Nested cubes, heterogeneous density with a jump across Gamma_2 and a
+   wavespeed jump across Gamma_1 (section 3.5); its 3D run on 61^3 cuboids.
+
+Benchmarks 2-4 against the FP64 oracle: products and solves on coarse grids,
+sampled rows at the paper's resolutions, and the parameter gradient.
+"""
+import copy
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from gpu_cases import dev, host, say
+from oracle.analytic import mie_layered
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+TOL_SOLVE = 1e-8
+
+
+@pytest.fixture(scope="module")
+def V():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2607_06429_amd as V
+    return V
+
+
+# coarse grids of benchmarks 2-4 (2 + 6 + 2 cuboids per axis for the nested
+# cubes, 9^3 for the single cube)
+SMALL = {
+    "b2": lambda: W.benchmark2_problem(n_shell=2, n_inner=6, lam0=4.0),
+    "b3": lambda: W.benchmark3_problem(N=9, lam0=4.0),
+    "b4": lambda: W.benchmark4_problem(n_shell=2, n_inner=6, lam0=4.0),
+}
+# the resolutions of the paper's figures: 10 cells per interior wavelength
+PAPER = {
+    "b2": lambda: W.benchmark2_problem(),
+    "b3": lambda: W.benchmark3_problem(),
+    "b4": lambda: W.benchmark4_problem(),
+}
+
+
+def small(name="b4"):
+    return SMALL[name]()
+
+
+def _slice_errors(mesh, x, k0, d):
+    """Relative L2 and max-norm errors of the cell values on z = 0 against the
+    series (the paper's error measure on its visualisation slice)."""
+    sl = np.abs(mesh.vol_xyz[:, 2]) < 1e-12
+    assert np.count_nonzero(sl) == round(mesh.n_vol ** (2.0 / 3.0))
+    ref = mie_layered(mesh.vol_xyz[sl], d, k0, 1.0, 1.0, 3.0, 1.0, 1.0, 2.5, 1.0, 5.0 / 6.0)
+    diff = x[:mesh.n_vol][sl] - ref
+    return (float(np.linalg.norm(diff) / np.linalg.norm(ref)),
+            float(np.max(np.abs(diff)) / np.max(np.abs(ref))))
+
+
+def test_benchmark1_sphere_against_series(V):
+    """Staircase sphere of radius 2.5 in [-3, 3]^3, c2 = 5/6, lambda0 = 2: the
+    error of the cell values on z = 0 against the series falls under
+    refinement, and at 8 cells per interior wavelength (N = 29) it is below
+    the 3% the paper reports for both norms."""
+    errs = []
+    for N in (13, 17, 21, 25, 29):
+        mesh, mat, k0, dirs, _ = W.benchmark1_problem(N)
+        P = V.Problem.from_mesh(mesh, mat, k0)
+        x, info = P.solve(P.plane_wave(dirs), prec=V.VSIE_FP32, tol=1e-10)
+        assert info["status"] == V.VSIE_OK
+        e2, einf = _slice_errors(mesh, host(x).reshape(-1), k0[0], dirs[0])
+        errs.append((N, e2, einf))
+        say("  b1 N %d n %d epw %.2f: L2 %.4f max %.4f (%d iterations)"
+            % (N, mesh.n, 2.0 * (5.0 / 6.0) * N / 6.0, e2, einf, info["iterations"]))
+        P.close()
+    l2 = np.array([e[1] for e in errs])
+    assert np.all(np.diff(l2) < 0)
+    slope = np.polyfit(np.log([e[0] for e in errs]), np.log(l2), 1)[0]
+    say("  b1 fitted L2 order %.2f" % -slope)
+    assert slope < -1.5
+    assert errs[-1][1] < 0.03 and errs[-1][2] < 0.03
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["b2", "b3", "b4"])
+def test_small_grid_products_against_oracle(V, prec, name):
+    mesh, mat, k0, dirs, grad = small(name)
+    d = O.discretise(mesh, mat, k0[0], grad_rho=grad)
+    assert (np.count_nonzero(d.gT) > 0) == (name != "b2")   # T only with a smooth density
+    P = V.Problem.from_mesh(mesh, mat, k0, grad_rho=grad)
+    x = W.seeded_complex((d.n, 3), seed=401)
+    pr = V.VSIE_FP64 if prec == "fp64" else V.VSIE_FP32
+    tol = TOL64 if prec == "fp64" else TOL32
+    y = host(P.matvec(dev(x), prec=pr))
+    ya = host(P.matvec_adjoint(dev(x), prec=pr))
+    e, ea = O.rel_error(y, O.matvec(d, x)), O.rel_error(ya, O.adjoint_matvec(d, x))
+    # one column: the once-per-pair cell-cell kernel
+    y1 = host(P.matvec(dev(x[:, 0]), prec=pr))
+    e1 = O.rel_error(y1, O.matvec(d, x[:, :1])[:, 0])
+    say("  %s small %s: n %d rel err %.2e adjoint %.2e one column %.2e" % (name, prec, d.n, e, ea, e1))
+    assert e <= tol and ea <= tol and e1 <= tol
+    P.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["b2", "b3", "b4"])
+def test_small_grid_solve_against_lu(V, prec, name):
+    mesh, mat, k0, dirs, grad = small(name)
+    d = O.discretise(mesh, mat, k0[0], grad_rho=grad)
+    b = O.plane_wave(d.pts, k0[0], dirs)
+    ref = O.solve_lu(d, b)
+    P = V.Problem.from_mesh(mesh, mat, k0, grad_rho=grad)
+    x, info = P.solve(dev(b).contiguous(), prec=V.VSIE_FP64 if prec == "fp64" else V.VSIE_FP32, tol=1e-11)
+    e = O.rel_error(host(x), ref)
+    say("  %s small solve %s: %s rel err %.2e" % (name, prec, info, e))
+    assert info["status"] == V.VSIE_OK and e <= TOL_SOLVE
+    P.close()
+
+
+@pytest.mark.parametrize("name", ["b3", "b4"])
+def test_density_gradient_through_the_adjoint(V, name):
+    """Receiver-misfit gradient w.r.t. per-cell rho and c with the analytic
+    density gradient held fixed (grad alpha = -rho0 grad(rho)/rho^2 moves with
+    rho), against finite differences of the oracle misfit."""
+    import torch
+    from paper_2607_06429_amd.autograd import receiver_pressure
+    mesh, mat, k0, dirs, grad = small(name)
+    rec = W.fibonacci_sphere(12, 8.0)       # outside the 7 mm cube
+    data = 0.4 * W.seeded_complex((12, 1), seed=402)
+    P = V.Problem.from_mesh(mesh, mat, k0, grad_rho=grad)
+    c = torch.tensor(mat.vol_c, device="cuda", requires_grad=True)
+    rho = torch.tensor(mat.vol_rho, device="cuda", requires_grad=True)
+    pr = receiver_pressure(P, mesh.n_vol, c, rho, dirs, rec, prec=V.VSIE_FP64, tol=1e-13)
+    loss = 0.5 * (pr - torch.as_tensor(np.ascontiguousarray(data.T), device="cuda")).abs().pow(2).sum()
+    loss.backward()
+    gc, gr = c.grad.cpu().numpy(), rho.grad.cpu().numpy()
+    inner = np.nonzero(mesh.vol_dom == (2 if name == "b4" else 1))[0]
+    cells = np.concatenate([np.random.default_rng(403).choice(inner, 8, replace=False),
+                            np.random.default_rng(404).choice(np.nonzero(mesh.vol_dom == 1)[0], 4, replace=False)])
+    out = {}
+    for which, g in (("c", gc), ("rho", gr)):
+        fd = []
+        for j in cells:
+            vals = []
+            for sgn in (1, -1):
+                m2 = copy.deepcopy(mat)
+                arr = m2.vol_c if which == "c" else m2.vol_rho
+                h = 1e-5 * arr[j]
+                arr[j] += sgn * h
+                vals.append(O.receiver_misfit(mesh, m2, k0[0], dirs, rec, data, grad_rho=grad))
+            fd.append((vals[0] - vals[1]) / (2 * h))
+        out[which] = O.rel_error(g[cells], np.array(fd))
+    say("  %s gradient vs oracle FD: c %.2e rho %.2e" % (name, out["c"], out["rho"]))
+    assert out["c"] < 1e-6 and out["rho"] < 1e-6
+    P.close()
+
+
+@pytest.mark.parametrize("name", ["b2", "b3", "b4"])
+def test_paper_grid_sampled_rows(V, name):
+    """The paper's grids (for benchmark 4 its 3D run: 61^3 cuboids,
+    n = 260,401): sampled rows of the FP64 and FP32 one-column products
+    against the oracle."""
+    mesh, mat, k0, dirs, grad = PAPER[name]()
+    d = O.discretise(mesh, mat, k0[0], grad_rho=grad)
+    P = V.Problem.from_mesh(mesh, mat, k0, grad_rho=grad)
+    b = P.plane_wave(dirs)
+    rows = np.unique(np.concatenate([np.random.default_rng(405).choice(d.n, 128, replace=False),
+                                     [0, mesh.n_vol - 1, mesh.n_vol, d.n - 1]]))
+    xb = host(b)
+    ref = O.matvec(d, xb.reshape(-1, 1), rows=rows)[:, 0]
+    for pr, tol in ((V.VSIE_FP64, TOL64), (V.VSIE_FP32, TOL32)):
+        y = host(P.matvec(b, prec=pr)).reshape(-1)
+        e = O.rel_error(y[rows], ref)
+        say("  %s n %d prec %d: sampled-row rel err %.2e" % (name, d.n, pr, e))
+        assert e <= tol
+    P.close()

@@ -27,7 +27,8 @@ import numpy as np
 
 __all__ = [
     "Mesh", "Materials", "voxel_mesh", "tensor_mesh", "nested_balls", "cube_with_ellipsoid", "nested_cubes",
-    "benchmark4_density", "benchmark4_density_gradient", "benchmark4_problem",
+    "benchmark1_problem", "benchmark2_problem", "benchmark3_density", "benchmark3_density_gradient",
+    "benchmark3_problem", "benchmark4_density", "benchmark4_density_gradient", "benchmark4_problem",
     "materials_piecewise", "materials_config", "fibonacci_sphere",
     "lognormal_voxel_field", "seeded_complex", "CONFIGS", "config_problem",
 ]
@@ -351,6 +352,62 @@ def benchmark4_problem(n_shell: int = 9, n_inner: int = 43, lam0: float = 1.4):
     grad[inner] = benchmark4_density_gradient(mesh.vol_xyz[inner])
     dirs = np.array([[1.0, 1.0, 0.0]]) / math.sqrt(2.0)
     return mesh, mat, [2.0 * math.pi / lam0], dirs, grad
+
+
+# the paper's other three benchmarks (its first: a sphere in a cube against the
+# spherical-harmonic series; its second: nested cubes with piecewise-constant
+# density; its third: one cube with a smooth heterogeneous density).  Incidence
+# along +x, the paper's default.
+
+def benchmark1_problem(N: int = 29, lam0: float = 2.0):
+    """Sphere of radius 2.5 (Omega_2, c2 = 5/6) inside the cube [-3, 3]^3
+    (Omega_1, the exterior's material), constant density 1, exterior
+    wavelength lam0, on a uniform N^3 staircase grid.  N = 29 gives 8.06 cells
+    per interior wavelength (2 * 5/6 / (6/29)); odd N puts a layer of
+    centroids on z = 0.  Returns (mesh, materials, [k0], directions, None)."""
+    def dom(x):
+        return np.where(np.sum(x * x, axis=1) < 2.5 ** 2, 2, 1)
+    mesh = voxel_mesh(-3.0, 3.0, N, dom)
+    mat = materials_piecewise(mesh, 1.0, 1.0, 1.0, 1.0, 1.0, 5.0 / 6.0)
+    return mesh, mat, [2.0 * math.pi / lam0], np.array([[1.0, 0.0, 0.0]]), None
+
+
+def benchmark2_problem(n_shell: int = 4, n_inner: int = 20, lam0: float = 3.0):
+    """Nested cubes of 7 and 5 mm with density 1 in Omega_0 and Omega_1 and
+    0.5 in Omega_2 (500 over 1000 kg/m^3), c1 = c2 = c0/1.2, exterior
+    wavelength lam0 mm.  The default 4 + 20 + 4 grid has 0.25 mm cells: 10 per
+    interior wavelength (3/1.2 mm)."""
+    mesh = nested_cubes(n_shell, n_inner)
+    mat = materials_piecewise(mesh, 1.0, 1.0, 1.0, 1.0 / 1.2, 0.5, 1.0 / 1.2)
+    return mesh, mat, [2.0 * math.pi / lam0], np.array([[1.0, 0.0, 0.0]]), None
+
+
+def benchmark3_density(xyz: np.ndarray) -> np.ndarray:
+    """1 - 0.8 sin(pi x/3.5) sin(pi y/3.5) cos(pi z/7): continuous with the
+    exterior's 1 on the faces of [-3.5, 3.5]^3."""
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    return 1.0 - 0.8 * np.sin(np.pi * x / 3.5) * np.sin(np.pi * y / 3.5) * np.cos(np.pi * z / 7.0)
+
+
+def benchmark3_density_gradient(xyz: np.ndarray) -> np.ndarray:
+    """Analytic gradient of benchmark3_density, (n, 3)."""
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    sx, cx = np.sin(np.pi * x / 3.5), np.cos(np.pi * x / 3.5)
+    sy, cy = np.sin(np.pi * y / 3.5), np.cos(np.pi * y / 3.5)
+    sz, cz = np.sin(np.pi * z / 7.0), np.cos(np.pi * z / 7.0)
+    return -0.8 * np.stack([(np.pi / 3.5) * cx * sy * cz, (np.pi / 3.5) * sx * cy * cz,
+                            -(np.pi / 7.0) * sx * sy * sz], axis=1)
+
+
+def benchmark3_problem(N: int = 21, lam0: float = 4.0):
+    """One heterogeneous domain Omega_1 = [-3.5, 3.5]^3 mm (no Omega_2), c1 =
+    c0/1.2, density benchmark3_density with its analytic gradient, exterior
+    wavelength lam0 mm, uniform N^3 grid (N = 21: 10 cells per interior
+    wavelength).  Returns (mesh, materials, [k0], directions, grad rho)."""
+    mesh = voxel_mesh(-3.5, 3.5, N, lambda x: np.ones(x.shape[0], dtype=np.int32))
+    mat = materials_piecewise(mesh, 1.0, 1.0, benchmark3_density, 1.0 / 1.2, 1.0, 1.0)
+    grad = benchmark3_density_gradient(mesh.vol_xyz)
+    return mesh, mat, [2.0 * math.pi / lam0], np.array([[1.0, 0.0, 0.0]]), grad
 
 
 # ---------------------------------------------------------------------------

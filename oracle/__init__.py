@@ -22,6 +22,7 @@ Acoustics"):
 * relative error ........................... eq_error
 * GMRES (no preconditioner) ................ section 3.1 ("Computational settings")
 * exterior field by the representation formula (m = 1 in Omega_0) ... section 2.3.1
+* its far-field pattern (leading terms of G and grad G as |x| -> inf) ... section 2.3.1
 
 Readings where the paper is silent (also listed in the design doc):
 
@@ -329,6 +330,34 @@ def exterior_field(d: Discretisation, targets, p, direction):
     """p(x) = p_inc(x) - sum_j kappa(x, j) p_j for x in Omega_0 (eq_vsie with m = 1)."""
     T = np.asarray(targets, dtype=np.float64)
     return plane_wave(T, d.k0, direction) - offdiag_apply(d, p, targets=T, exclude_self=False)
+
+
+def far_field(d: Discretisation, directions, p):
+    """Far-field pattern of the scattered field p_sc = p - p_inc in Omega_0:
+    p_sc(R xhat) = exp(i k0 R)/R pinf(xhat) + O(R^-2) for unit directions xhat.
+
+    The representation formula of section 2.3.1 (the exterior field above,
+    -sum_j kappa(x, j) p_j) with the kernels replaced by their leading terms
+    at |x| = R -> infinity:
+        G(x, y)      ~ exp(i k0 R)/(4 pi R) exp(-i k0 xhat . y)
+        grad_x G     ~  i k0 xhat G,     grad_y G ~ -i k0 xhat G.
+    Cell j (kappa = -G sV + grad_x G . gT) and face j (kappa = dK grad_y G . n)
+    then give
+        pinf(xhat) = 1/(4 pi) sum_j exp(-i k0 xhat . y_j) a_j(xhat) p_j,
+        a_j = sV_j - i k0 xhat . gT_j   (cells),   a_j = i k0 dK_j xhat . n_j   (faces).
+    directions: (m, 3) unit vectors; p: (n,) or (n, R).  Returns (m,) or (m, R)."""
+    X = np.atleast_2d(np.asarray(directions, dtype=np.float64))
+    P, one = _as_cols(p, d.n)
+    out = np.zeros((X.shape[0], P.shape[1]), dtype=np.complex128)
+    nv = d.n_vol
+    for a in range(0, X.shape[0], 256):
+        Xb = X[a:a + 256]
+        E = np.exp(-1j * d.k0 * (Xb @ d.pts.T))
+        amp = np.empty(E.shape, dtype=np.complex128)
+        amp[:, :nv] = d.sV[None, :] - 1j * d.k0 * (Xb @ d.gT.T)
+        amp[:, nv:] = 1j * d.k0 * (Xb @ d.nrm.T) * d.dK[None, :]
+        out[a:a + 256] = (E * amp) @ P / (4.0 * math.pi)
+    return out[:, 0] if one else out
 
 
 def rel_error(num, ref, ord=2):

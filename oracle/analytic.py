@@ -11,6 +11,8 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
   transmission conditions p and (1/rho) dp/dr continuous (eqs.
   eq_transmission_pressure, eq_transmission_velocity) and the outgoing
   radiation condition (eq_sommerfeld), time convention exp(-i omega t).
+* The far-field pattern of that series: the leading term of the exterior
+  scattered field as r -> infinity.
 """
 from __future__ import annotations
 
@@ -112,3 +114,25 @@ def mie_layered(points, direction, k0, rho0, c0, R1, rho1, c1, R2, rho2, c2, nma
             x = k2 * r[reg2]
             out[reg2] += f * D * sp.spherical_jn(n, x) * Pn[reg2]
     return out
+
+
+def mie_far_field(directions, incidence, k0, rho0, c0, R1, rho1, c1, R2, rho2, c2, nmax=None):
+    """Far-field pattern f(xhat) of the scattered field of mie_layered,
+    p - p_inc = exp(i k0 r)/r f(xhat) + O(r^-2) in the exterior.  With the
+    large-argument form h_n(z) ~ (-i)^(n+1) exp(i z)/z of the outgoing
+    spherical Hankel function, each term i^n (2n+1) A_n h_n(k0 r) P_n
+    contributes (-i/k0) (2n+1) A_n P_n(xhat . d)."""
+    X = np.atleast_2d(np.asarray(directions, dtype=np.float64))
+    X = X / np.linalg.norm(X, axis=1, keepdims=True)
+    d = np.asarray(incidence, dtype=np.float64)
+    d = d / np.linalg.norm(d)
+    omega = k0 * c0
+    k1, k2 = omega / c1, omega / c2
+    if nmax is None:
+        nmax = mie_truncation(max(k0, k1, k2) * R1)
+    coef = mie_coefficients(k0, rho0, k1, rho1, R1, k2, rho2, R2, nmax)
+    ct = X @ d
+    out = np.zeros(X.shape[0], dtype=np.complex128)
+    for n in range(nmax + 1):
+        out += (2 * n + 1) * coef[n, 0] * sp.eval_legendre(n, ct)
+    return (-1j / k0) * out

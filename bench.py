@@ -169,6 +169,71 @@ def c4_block_solve(V, W):
                     "residual 1e-10" % (mesh.n, k0s[0], dirs.shape[0]), **out}}
 
 
+def far_field_pattern(V, P, x):
+    """Far-field pattern of the solution x on a 1-degree grid of directions
+    (180 polar x 360 azimuthal = 64,800), FP32 and FP64, with the per-kernel
+    times and issue-cycle rates of the two source classes."""
+    import torch
+    th = (np.arange(180) + 0.5) * (math.pi / 180)
+    ph = np.arange(360) * (2 * math.pi / 360)
+    TH, PH = np.meshgrid(th, ph, indexing="ij")
+    X = np.stack([(np.sin(TH) * np.cos(PH)).ravel(), (np.sin(TH) * np.sin(PH)).ravel(), np.cos(TH).ravel()], axis=1)
+    counts = json.load(open(os.path.join(ROOT, "paper_2607_06429_amd", "isa_counts.json")))
+    res = {"directions": int(X.shape[0])}
+    pats = {}
+    for name, prec in (("fp32", V.VSIE_FP32), ("fp64", V.VSIE_FP64)):
+        P.far_field(X, x, prec=prec)          # untimed first call (work buffers)
+        torch.cuda.synchronize()
+        P.profile(True)
+        t0 = time.perf_counter()
+        pats[name] = P.far_field(X, x, prec=prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = P.kernel_stats()
+        P.profile(False)
+        ker = {}
+        for k, v in st.items():
+            cyc = counts[k + "_R1"]["cycles_per_pair"]
+            rate = v["pairs"] / (v["ms"] * 1e-3)
+            ker[k] = {"ms": v["ms"], "gpairs_per_s": rate / 1e9, "cycles_per_pair": cyc,
+                      "issue_frac": cyc * rate / ISSUE_PEAK}
+        res[name] = {"pattern_s": dt, "kernels": ker}
+    res["rel_diff_fp32_vs_fp64"] = float(torch.linalg.norm(pats["fp32"] - pats["fp64"])
+                                         / torch.linalg.norm(pats["fp64"]))
+    return res
+
+
+def exterior_slice(V, P, x, dirs):
+    """Exterior field of the solution x on the slice z = 0: a 512 x 512 grid
+    over [-7, 7]^2 mm without the points inside the 7 mm cube (the
+    representation formula at 196,608 points), FP32 and FP64."""
+    import torch
+    g = np.linspace(-7.0, 7.0, 512)
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    pts = np.stack([X.ravel(), Y.ravel(), np.zeros(X.size)], axis=1)
+    pts = pts[np.max(np.abs(pts[:, :2]), axis=1) > 3.5]
+    counts = json.load(open(os.path.join(ROOT, "paper_2607_06429_amd", "isa_counts.json")))
+    res = {"points": int(pts.shape[0])}
+    for name, prec in (("fp32", V.VSIE_FP32), ("fp64", V.VSIE_FP64)):
+        P.field(pts, x, prec=prec)
+        torch.cuda.synchronize()
+        P.profile(True)
+        t0 = time.perf_counter()
+        P.field(pts, x, prec=prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = P.kernel_stats()
+        P.profile(False)
+        ker = {}
+        for k, v in st.items():
+            cyc = counts[k + "_R1"]["cycles_per_pair"]
+            rate = v["pairs"] / (v["ms"] * 1e-3)
+            ker[k] = {"ms": v["ms"], "gpairs_per_s": rate / 1e9, "cycles_per_pair": cyc,
+                      "issue_frac": cyc * rate / ISSUE_PEAK}
+        res[name] = {"slice_s": dt, "kernels": ker}
+    return res
+
+
 def paper_benchmark_solves(V, W):
     """The paper's four benchmarks (section 3) at the resolutions of its
     figures, each solved with the FP32 operator in FP64 refinement and with
@@ -202,6 +267,9 @@ def paper_benchmark_solves(V, W):
         out["speedup_fp32_refine_vs_fp64"] = out["fp64"]["solve_s"] / out["fp32_refine"]["solve_s"]
         out["rel_diff_fp32_refine_vs_fp64_solution"] = float(
             torch.linalg.norm(sols["fp32_refine"] - sols["fp64"]) / torch.linalg.norm(sols["fp64"]))
+        if label == "b4_3d_run":
+            out["far_field_pattern"] = far_field_pattern(V, P, sols["fp64"])
+            out["exterior_field_slice"] = exterior_slice(V, P, sols["fp64"].reshape(-1), dirs)
         P.close()
         res[label] = out
     return res

@@ -251,6 +251,21 @@ vsie_status vsie_field(vsie_problem *p, int32_t f, vsie_precision prec, int64_t 
                        const double *tx, const double *ty, const double *tz, int64_t nrhs,
                        const double *x, int64_t ldx, double *out, int64_t ldo, void *stream);
 
+/* Far-field pattern of the scattered pressure: the exterior field of section
+ * 2.3.1 along a unit direction d as |x| = R -> infinity,
+ *   p(R d) - p_inc(R d) = exp(i k0 R)/R pinf(d) + O(R^-2),
+ *   pinf(d) = 1/(4 pi) sum_j exp(-i k0 d.y_j) (s_j - i k0 d.v_j) x[j, r]
+ * (s_j, v_j the single-layer and double-layer weights of element j, see the
+ * top of this file; G and grad G replaced by their leading terms).
+ *   dx, dy, dz : n_d DEVICE doubles, the directions (unit length, not checked)
+ *   x          : n x nrhs DEVICE solution columns, ldx >= n
+ *   out        : n_d x nrhs DEVICE, out[t + r ldo] = pinf(d_t) of column r, ldo >= n_d
+ * FP32 evaluates the amplitudes in FP32 (phase k0 d.y formed and reduced in
+ * FP64) and adds FP32 sums of at most 128 sources in FP64. */
+vsie_status vsie_far_field(vsie_problem *p, int32_t f, vsie_precision prec, int64_t n_d,
+                           const double *dx, const double *dy, const double *dz, int64_t nrhs,
+                           const double *x, int64_t ldx, double *out, int64_t ldo, void *stream);
+
 /* Source-side sums for adjoint-state gradients:
  *   z[j, r]      = sum_t conj(G(|x_t - y_j|)) lam[t, r]
  *   Z[j, r, a]   = sum_t conj(F(|x_t - y_j|)) (x_t - y_j)_a lam[t, r]
@@ -327,7 +342,9 @@ vsie_status vsie_release_dense(vsie_problem *p, int32_t f);
  * counts nf times its pairs); kind 10 and 11 the symmetric cell-cell single
  * layer in FP64 and FP32 (pairs = ordered cell pairs, n_vol (n_vol - 1));
  * kind 12 and 13 the cell-face kernel in FP64 and FP32 (pairs = 2 n_vol n_srf,
- * both directions). */
+ * both directions); kind 14 and 15 the far-field pattern's single-layer
+ * sources, 16 and 17 its double-layer sources, in FP64 and FP32 (pairs =
+ * directions x sources). */
 typedef struct {
     int64_t launches;
     double ms;

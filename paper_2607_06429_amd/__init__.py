@@ -20,7 +20,7 @@ import numpy as np
 __all__ = [
     "VSIE_OK", "VSIE_FP64", "VSIE_FP32", "VsieError", "Problem", "lib", "library_path",
     "vsie_assemble", "vsie_set_materials", "vsie_matvec", "vsie_matvec_adjoint", "vsie_solve",
-    "vsie_plane_wave", "vsie_field", "vsie_source_sums", "vsie_plane_wave_at", "vsie_adjoint_rhs",
+    "vsie_plane_wave", "vsie_field", "vsie_far_field", "vsie_source_sums", "vsie_plane_wave_at", "vsie_adjoint_rhs",
     "vsie_param_gradient", "vsie_assemble_dense", "vsie_release_dense", "vsie_profile",
     "vsie_profile_read", "vsie_destroy", "vsie_last_error",
     "vsie_size", "vsie_matvec_multi", "vsie_get_tuning", "vsie_set_tuning", "vsie_autotune",
@@ -96,6 +96,7 @@ def _load():
                              ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P]
     L.vsie_plane_wave.argtypes = [_P, _I32, _I64, _P, _P, _I64, _P]
     L.vsie_field.argtypes = [_P, _I32, _I32, _I64, _P, _P, _P, _I64, _P, _I64, _P, _I64, _P]
+    L.vsie_far_field.argtypes = [_P, _I32, _I32, _I64, _P, _P, _P, _I64, _P, _I64, _P, _I64, _P]
     L.vsie_source_sums.argtypes = [_P, _I32, _I64, _P, _P, _P, _I64, _P, _I64, _P, _I64, _P,
                                    _I64, _P]
     L.vsie_plane_wave_at.argtypes = [_P, _I32, _I64, _P, _I64, _P, _P, _P, _P, _I64, _P]
@@ -113,7 +114,7 @@ def _load():
     L.vsie_destroy.restype = None
     L.vsie_last_error.restype = ctypes.c_char_p
     for name in ("vsie_assemble", "vsie_set_materials", "vsie_matvec", "vsie_matvec_adjoint",
-                 "vsie_solve", "vsie_plane_wave", "vsie_field", "vsie_source_sums",
+                 "vsie_solve", "vsie_plane_wave", "vsie_field", "vsie_far_field", "vsie_source_sums",
                  "vsie_profile", "vsie_profile_read", "vsie_plane_wave_at", "vsie_adjoint_rhs",
                  "vsie_param_gradient", "vsie_assemble_dense", "vsie_release_dense",
                  "vsie_matvec_multi", "vsie_get_tuning", "vsie_set_tuning", "vsie_autotune"):
@@ -124,7 +125,7 @@ def _load():
 lib = _load()
 
 EXPORTED = ("vsie_assemble", "vsie_set_materials", "vsie_size", "vsie_matvec",
-            "vsie_matvec_adjoint", "vsie_solve", "vsie_plane_wave", "vsie_field",
+            "vsie_matvec_adjoint", "vsie_solve", "vsie_plane_wave", "vsie_field", "vsie_far_field",
             "vsie_source_sums", "vsie_plane_wave_at", "vsie_adjoint_rhs", "vsie_param_gradient",
             "vsie_assemble_dense", "vsie_release_dense", "vsie_profile", "vsie_profile_read",
             "vsie_destroy", "vsie_last_error", "vsie_matvec_multi", "vsie_get_tuning",
@@ -136,7 +137,9 @@ KIND_NAMES = {0: "fwd_single_layer_fp64", 1: "fwd_single_layer_fp32", 2: "fwd_do
               6: "source_sums_fp64", 7: "source_sums_fp32",
               8: "mfma_fwd_single_layer_fp32", 9: "mfma_fwd_double_layers_fp32",
               10: "sym_single_layer_fp64", 11: "sym_single_layer_fp32",
-              12: "cell_face_fp64", 13: "cell_face_fp32"}
+              12: "cell_face_fp64", 13: "cell_face_fp32",
+              14: "far_field_single_layer_fp64", 15: "far_field_single_layer_fp32",
+              16: "far_field_double_layers_fp64", 17: "far_field_double_layers_fp32"}
 
 
 def vsie_last_error() -> str:
@@ -318,6 +321,17 @@ def vsie_field(h, f, prec, tx, ty, tz, x, out, stream=None):
                           _stream(stream)))
 
 
+def vsie_far_field(h, f, prec, dx, dy, dz, x, out, stream=None):
+    n = vsie_size(h)
+    px, R, ldx = _cols(x, n)
+    nd = dx.shape[0]
+    po, Ro, ldo = _cols(out, nd)
+    if Ro != R:
+        raise ValueError("x and out hold different numbers of columns")
+    _check(lib.vsie_far_field(h, f, prec, nd, _dptr(dx), _dptr(dy), _dptr(dz), R, px, ldx, po, ldo,
+                              _stream(stream)))
+
+
 def vsie_source_sums(h, f, lam, z, Z, targets=None, stream=None):
     """z: (R, n) complex128; Z: (3R, n) complex128 (row 3 r + a)."""
     n = vsie_size(h)
@@ -493,6 +507,20 @@ class Problem:
         shape = (T.shape[0],) if x.dim() == 1 else (x.shape[0], T.shape[0])
         out = torch.empty(shape, dtype=torch.complex128, device="cuda")
         vsie_field(self.handle, f, prec, tx, ty, tz, x, out)
+        return out
+
+    def far_field(self, directions, x, f=0, prec=VSIE_FP64):
+        """Far-field pattern pinf(d) of the scattered field of solution x at unit
+        directions (m, 3): p - p_inc = exp(i k0 R)/R pinf(d) + O(R^-2)."""
+        import torch
+        D = np.ascontiguousarray(np.atleast_2d(directions), dtype=np.float64)
+        if D.ndim != 2 or D.shape[1] != 3 or not np.allclose(np.linalg.norm(D, axis=1), 1.0, atol=1e-12):
+            raise ValueError("directions must be unit vectors, shape (m, 3)")
+        T = torch.as_tensor(D, device="cuda")
+        dx, dy, dz = (T[:, a].contiguous() for a in range(3))
+        shape = (D.shape[0],) if x.dim() == 1 else (x.shape[0], D.shape[0])
+        out = torch.empty(shape, dtype=torch.complex128, device="cuda")
+        vsie_far_field(self.handle, f, prec, dx, dy, dz, x, out)
         return out
 
     def source_sums(self, lam, f=0, targets=None):

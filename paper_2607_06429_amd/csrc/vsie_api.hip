@@ -1996,6 +1996,46 @@ vsie_status vsie_field(vsie_problem *p, int32_t f, vsie_precision prec, int64_t 
     });
 }
 
+vsie_status vsie_far_field(vsie_problem *p, int32_t f, vsie_precision prec, int64_t n_d, const double *dx,
+                           const double *dy, const double *dz, int64_t nrhs, const double *x, int64_t ldx,
+                           double *out, int64_t ldo, void *stream) {
+    return guarded([&] {
+        check_problem(p, f);
+        require(prec == VSIE_FP64 || prec == VSIE_FP32, "unknown precision");
+        require(n_d >= 1 && dx && dy && dz, "need directions");
+        require(nrhs >= 1 && nrhs <= 4096, "nrhs must be in [1, 4096]");
+        check_vec(x, ldx, p->m.n, "x");
+        check_vec(out, ldo, n_d, "out");
+        hipStream_t s = as_stream(stream);
+        const int R = static_cast<int>(nrhs);
+        const int64_t n = p->m.n;
+        int64_t chG, chF;
+        int ncG, ncF;
+        const int64_t lanes = (n_d + far_field_lanes(R) - 1) / far_field_lanes(R);
+        choose_chunks(lanes, p->G.count, p->tune.vec_target_waves, chG, ncG);
+        choose_chunks(lanes, p->F.count, p->tune.vec_target_waves, chF, ncF);
+        double2 *part = static_cast<double2 *>(
+            p->partial.get(sizeof(double2) * static_cast<size_t>(std::max(1, ncG + ncF)) * R * n_d));
+        void *qG = p->chargeG.get(csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->G.count)) * R);
+        void *qF = p->chargeF.get(csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->F.count)) * R);
+        const double *spf = p->m.sp + static_cast<int64_t>(f) * n;
+        launch_pack_both(prec, p->G, p->F, spf, R, reinterpret_cast<const double2 *>(x), ldx, false, qG, qF, s);
+        if (ncG > 0) {
+            FarJob J{kClassG, prec, n_d, dx, dy, dz, p->G.count, p->G.pk, nullptr, qG, p->G.count,
+                     R, chG, ncG, p->k0[f], part, static_cast<int64_t>(R) * n_d};
+            launch_far_field(J, s, &p->prof);
+        }
+        if (ncF > 0) {
+            FarJob J{kClassF, prec, n_d, dx, dy, dz, p->F.count, p->F.pk, p->F.pv, qF, p->F.count, R, chF, ncF,
+                     p->k0[f],
+                     part + static_cast<int64_t>(ncG) * R * n_d, static_cast<int64_t>(R) * n_d};
+            launch_far_field(J, s, &p->prof);
+        }
+        launch_reduce_partials(n_d, R, ncG + ncF, part, nullptr, false, nullptr, 0,
+                               reinterpret_cast<double2 *>(out), ldo, nullptr, s);
+    });
+}
+
 vsie_status vsie_source_sums(vsie_problem *p, int32_t f, int64_t n_t, const double *tx,
                              const double *ty, const double *tz, int64_t nrhs, const double *lam,
                              int64_t ldl, double *z, int64_t ldz, double *Z, int64_t ldZ,
@@ -2126,7 +2166,7 @@ vsie_status vsie_profile(vsie_problem *p, int32_t enable) {
 vsie_status vsie_profile_read(vsie_problem *p, int32_t kind, vsie_kernel_stats *out) {
     return guarded([&] {
         require(p != nullptr && out != nullptr, "NULL argument");
-        require(kind >= 0 && kind < 14, "kernel kind out of range");
+        require(kind >= 0 && kind < 18, "kernel kind out of range");
         vsie_kernel_stats st{0, 0.0, 0.0, 0.0};
         for (auto &r : p->prof.recs) {
             if (r.kind != kind) continue;

@@ -116,6 +116,33 @@ struct PairProfiler {
 void launch_pairs(const PairJob &J, hipStream_t s, PairProfiler *prof = nullptr);
 hipEvent_t prof_take_event(PairProfiler *prof);
 
+// Far-field pattern of one source class (far_field.hip): n_d unit directions
+// d, sources with the packed charges of the forward product (class G: u_j =
+// -s'_j x_j; class F: x_j, with v'), one FP64 partial per (chunk, right-hand
+// side, direction) of
+//   G: -sum_j exp(-i k d.y_j) u_j,   F: -sum_j exp(-i k d.y_j) i k (d.v'_j) x_j
+// at out[c * chunk_stride + r * n_d + t].  Profiler kinds 14 + 2 cls + (FP32).
+struct FarJob {
+    int cls;
+    vsie_precision prec;
+    int64_t n_d;
+    const double *dx, *dy, *dz;
+    int64_t n_s;
+    const double4 *pk, *pv;   // SourceSet::pk, pv (pv for class F)
+    const void *charge;       // complex charges (double2 or float2), charge[r * ldq + j]
+    int64_t ldq;
+    int nrhs;
+    int64_t chunk;            // sources per chunk
+    int n_chunks;             // ceil(n_s / chunk)
+    double k;
+    double2 *out;
+    int64_t chunk_stride;
+};
+void launch_far_field(const FarJob &J, hipStream_t s, PairProfiler *prof = nullptr);
+// Directions one lane of the far-field kernel evaluates for nrhs right-hand
+// sides (the launch needs ceil(n_d / that) lanes per source chunk).
+int far_field_lanes(int nrhs);
+
 // FP32 forward pair sums of one source class on the matrix cores
 // (mfma_kernels.hip), for nf frequencies and a block of right-hand sides in
 // one launch.  Targets are the n_t collocation points.  Charges

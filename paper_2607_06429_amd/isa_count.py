@@ -3,13 +3,15 @@ kernels' inner loops.
 
     python paper_2607_06429_amd/isa_count.py
 
-Compiles csrc/pair_kernels.hip, csrc/mfma_kernels.hip and csrc/sym_kernels.hip
-to gfx950 assembly
+Compiles csrc/pair_kernels.hip, csrc/mfma_kernels.hip, csrc/sym_kernels.hip
+and csrc/far_field.hip to gfx950 assembly
 (the same flags as the library build) and, for each kernel variant, finds the
 innermost loop that evaluates the most pairs per trip (the unrolled
-steady-state loop; one v_rsq per pair and lane), counts its instructions and
-divides by the pairs per trip (ordered pairs: an evaluation of the
-symmetric cell-cell kernel and of the cell-face kernel counts twice).
+steady-state loop; one v_rsq per pair and lane, in the far-field kernels one
+phase reduction: v_fract_f64 on the FP32 path, v_rndne_f64 on the FP64 path),
+counts its instructions and divides by the pairs per trip (ordered pairs: an
+evaluation of the symmetric cell-cell kernel and of the cell-face kernel
+counts twice).
 
 Issue-cycle model (SIMD cycles one wave64 instruction occupies; the chip has
 256 CUs x 4 SIMDs at 2.4 GHz):
@@ -83,8 +85,16 @@ def inner_loops(body_lines):
             if not any(a < a2 <= b and (a2, b2) != (a, b) for a2, b2 in loops)]
 
 
+PAIR_MARK = r"v_rsq"
+
+
 def kernels(asm: str):
-    """(symbol, result key, right-hand sides per trip) of every pair kernel."""
+    """(symbol, result key, right-hand sides per trip[, per-pair marker]) of every pair kernel."""
+    for nm in re.findall(r"^(_Z\w+far_field_kernel\w+):", asm, re.M):
+        cls, R, acc = re.search(r"far_field_kernelILi(\d)ELi(\d+)E(\w)E", nm).groups()
+        mark = r"v_fract_f64" if acc == "f" else r"v_rndne_f64"
+        yield (nm, "far_field_%s_%s_R%s" % ("single_layer" if cls == "0" else "double_layers",
+                                            "fp64" if acc == "d" else "fp32", R), int(R), mark)
     for nm in re.findall(r"^(_Z\w+pair_sum_kernel\w+):", asm, re.M):
         mode, R, acc = re.search(r"kernelILi(\d)ELi(\d+)Ed(\w)", nm).groups()
         yield nm, "%s_%s_R%s" % (MODES[int(mode)], "fp64" if acc == "d" else "fp32", R), int(R)
@@ -102,7 +112,9 @@ def kernels(asm: str):
 
 def count(asm: str) -> dict:
     res = {}
-    for nm, key, R in kernels(asm):
+    for item in kernels(asm):
+        nm, key, R = item[:3]
+        mark = item[3] if len(item) > 3 else PAIR_MARK
         i = asm.index(nm + ":")
         lines = asm[i:asm.index(".Lfunc_end", i)].split("\n")
         sym = "sym_kernel" in nm or "cf_kernel" in nm
@@ -110,7 +122,7 @@ def count(asm: str) -> dict:
         for a, b in inner_loops(lines):
             body = [x.strip() for x in lines[a:b + 1]
                     if x.strip() and not x.strip().startswith((";", "."))]
-            nrsq = sum(1 for x in body if x.startswith("v_rsq"))
+            nrsq = sum(1 for x in body if re.match(mark, x))
             if nrsq == 0:
                 continue
             if sym:
@@ -161,6 +173,7 @@ def main():
     res = count(assemble("pair_kernels.hip"))
     res.update(count(assemble("mfma_kernels.hip")))
     res.update(count(assemble("sym_kernels.hip")))
+    res.update(count(assemble("far_field.hip")))
     out = os.path.join(HERE, "isa_counts.json")
     with open(out, "w") as f:
         json.dump(res, f, indent=1, sort_keys=True)

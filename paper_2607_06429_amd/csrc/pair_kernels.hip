@@ -80,6 +80,15 @@ __device__ int64_t lower_bound_u(const int32_t *__restrict__ a, int64_t n, int64
     return lo;
 }
 
+// Streamed points per unrolled step of the pair loop: four while their
+// wave-uniform charges are small (fewer scalar address updates and waits per
+// pair), else two (the charges of more steps would not fit the scalar
+// registers).
+template <int R, typename AT>
+constexpr int pair_unroll() {
+    return R * static_cast<int>(sizeof(AT) / 4) < 4 ? 4 : 2;
+}
+
 template <int MODE, int R, typename CT, typename AT>
 __global__ __launch_bounds__(kBlock) void pair_sum_kernel(PairArgs<CT, AT> a) {
     using C2 = typename cplx_t<AT>::type;
@@ -134,7 +143,7 @@ __global__ __launch_bounds__(kBlock) void pair_sum_kernel(PairArgs<CT, AT> a) {
             AT sr[R * NC], si[R * NC];
 #pragma unroll
             for (int r = 0; r < R * NC; ++r) sr[r] = si[r] = 0;
-#pragma unroll 2
+#pragma unroll pair_unroll<R, AT>()
             for (int64_t j = jt; j < je; ++j) {
                 const double dx = xi - static_cast<double>(a.sx[j]);
                 const double dy = yi - static_cast<double>(a.sy[j]);

@@ -40,6 +40,11 @@ sys.path.insert(0, ROOT)
 METRIC = "GMRES solve s and Gpair-evals/s at 1e-8 rel err: FP64 vs FP32+refine, 1 GPU"
 GOLD = os.path.join(ROOT, "tests", "golden", "c1_oracle_solution.npz")
 ISSUE_PEAK = 256 * 4 * 2.4e9   # SIMD issue cycles/s: 256 CUs x 4 SIMDs x 2.4 GHz
+
+
+def note(msg):
+    """One progress line on stderr as each part of the run ends."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
 TOL = 1e-10
 
 
@@ -267,6 +272,7 @@ def paper_benchmark_solves(V, W):
         out["speedup_fp32_refine_vs_fp64"] = out["fp64"]["solve_s"] / out["fp32_refine"]["solve_s"]
         out["rel_diff_fp32_refine_vs_fp64_solution"] = float(
             torch.linalg.norm(sols["fp32_refine"] - sols["fp64"]) / torch.linalg.norm(sols["fp64"]))
+        note("%s: FP32+refinement %.3f s, FP64 %.3f s" % (label, out["fp32_refine"]["solve_s"], out["fp64"]["solve_s"]))
         if label == "b4_3d_run":
             out["far_field_pattern"] = far_field_pattern(V, P, sols["fp64"])
             out["exterior_field_slice"] = exterior_slice(V, P, sols["fp64"].reshape(-1), dirs)
@@ -304,6 +310,7 @@ def batched_workloads(V, W):
         op = ("FP32 operator %s in FP64 refinement" % ("assembled (%.1f GB)" % (8.0 * n * n / 1e9)
                                                        if A is not None else "matrix-free")
               if prec == V.VSIE_FP32 else "FP64 operator matrix-free")
+        note("c2 block GMRES %s: %.2f s" % (name, dt))
         out["c2_block_gmres_" + name] = {
             "workload": "nested balls, 57^3 grid, n=%d, k0=16, %d Fibonacci directions, block GMRES, "
                         "%s to rel. residual 1e-10" % (n, R, op),
@@ -324,6 +331,7 @@ def batched_workloads(V, W):
     P.close()
     del B
     out["c3_adjoint_gradient"] = c3_gradient(V, W)
+    note("c3 gradient done")
     out["paper_benchmarks"] = paper_benchmark_solves(V, W)
     mesh, mat, k0s, dirs, _ = W.config_problem("c4")
     P = V.Problem.from_mesh(mesh, mat, k0s)
@@ -339,6 +347,7 @@ def batched_workloads(V, W):
     dt = time.perf_counter() - t0
     st = P.kernel_stats()
     P.profile(False)
+    note("c4 multi-frequency product: %.2f s" % dt)
     out["c4_multi_frequency_product"] = {
         "workload": "cube with ellipsoid, 100^3 grid, n=%d, k0 = %s, %d directions each, FP32 operator, "
                     "one matrix-core launch per source class" % (n, k0s, R),
@@ -435,6 +444,7 @@ def main():
         x64, info64 = step(V.VSIE_FP64)
     torch.cuda.synchronize()
     ms64 = (time.perf_counter() - t0) / ksteps64 * 1e3
+    note("c1 steps: FP32+refinement %.1f ms, FP64 %.1f ms" % (ms_per_step, ms64))
 
     # pair evaluations of one step (all operator applications, both precisions)
     mv32 = infos[-1]["matvecs_fp32"]

@@ -381,6 +381,41 @@ __global__ void bnorm_final_kernel(int nslots, const double *__restrict__ partia
 // order, as bdots_final_kernel) into LDS, block 0 of the slot also stores them
 // in h for the host, then W[sl] -= sum_j V(j, act[sl]) h_j.  k <= kFusedMaxK.
 constexpr int kFusedMaxK = 1024;
+// one workgroup per live right-hand side (see bblas_deflate_coef)
+__global__ __launch_bounds__(kT) void bdeflate_coef_kernel(const int32_t *__restrict__ slot,
+                                                           const int32_t *__restrict__ kcount, int cs,
+                                                           const double2 *__restrict__ P,
+                                                           const double2 *__restrict__ M,
+                                                           const double2 *__restrict__ tc, double2 *__restrict__ hc,
+                                                           double2 *__restrict__ B, int col, int kb,
+                                                           int64_t bstride) {
+    const int l = blockIdx.x;
+    const int sl = slot[l];
+    const int kc = kcount[sl];
+    const double2 *t = tc + static_cast<int64_t>(l) * cs;
+    const double2 *Ps = P + static_cast<int64_t>(sl) * cs * cs;
+    const double2 *Ms = M + static_cast<int64_t>(sl) * cs * cs;
+    for (int i = threadIdx.x; i < cs; i += kT) {
+        double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+        for (int j = 0; j < kc; ++j) {
+            const double2 tj = t[j];
+            const double2 pv = Ps[static_cast<int64_t>(j) * cs + i];
+            ar += pv.x * tj.x - pv.y * tj.y;
+            ai += pv.x * tj.y + pv.y * tj.x;
+            if (i + 1 < kc) {
+                const double2 mv = Ms[static_cast<int64_t>(j) * cs + i];
+                br += mv.x * tj.x - mv.y * tj.y;
+                bi += mv.x * tj.y + mv.y * tj.x;
+            }
+        }
+        hc[static_cast<int64_t>(l) * cs + i] = i < kc ? make_double2(ar, ai) : make_double2(0.0, 0.0);
+        if (i + 1 < kc) {
+            double2 *b = B + static_cast<int64_t>(sl) * bstride + static_cast<int64_t>(col) * kb + i;
+            *b = make_double2(b->x + br, b->y + bi);
+        }
+    }
+}
+
 __global__ __launch_bounds__(kT) void bgemv_sub_partial_kernel(int64_t n, int k, int R, const int32_t *__restrict__ act,
                                                                const double2 *__restrict__ V,
                                                                const double2 *__restrict__ partial, int n_chunks,
@@ -668,6 +703,15 @@ void bblas_dots_partial(int64_t n, int k, int R, int nslots, const int32_t *act,
     if (k == 0 || nslots == 0) return;
     hipLaunchKernelGGL(bdots_kernel, dim3(n_chunks, k, nslots), dim3(kT), 0, s, n, rpc(n, n_chunks), k,
                        R, act, V, W, partial, n_chunks);
+    LAUNCH_CHECK();
+}
+
+void bblas_deflate_coef(int nl, const int32_t *slot, const int32_t *kcount, int cs, const double2 *P,
+                        const double2 *M, const double2 *tc, double2 *hc, double2 *B, int col, int kb,
+                        int64_t bstride, hipStream_t s) {
+    if (nl == 0) return;
+    hipLaunchKernelGGL(bdeflate_coef_kernel, dim3(nl), dim3(kT), 0, s, slot, kcount, cs, P, M, tc, hc, B, col, kb,
+                       bstride);
     LAUNCH_CHECK();
 }
 

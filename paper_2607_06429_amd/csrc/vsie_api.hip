@@ -119,6 +119,7 @@ struct vsie_problem {
     Scratch partial, chargeG, chargeF, chargeAll, sums_part, grad_work;
     // Krylov workspace
     Scratch V, V2, w, r, ax, h1, tc, nrm, dpart, npart, yv, act, act2, live, kd, kc, xa, axa, rres, brc;
+    Scratch defP, defM, defB, defk, lslot;  // deflation of GMRES cycles (gmres_cycle)
     Scratch bh, bg, bsk;  // block GMRES: Hessenberg block column, Gram / inverse factor, slab partials
     HostPinned hpin;      // per-iteration Hessenberg columns and norms on their way to the host
     int progress = 0;     // vsie_solve_opts::progress of the running solve
@@ -786,6 +787,23 @@ std::vector<double> column_norms(vsie_problem *p, const double2 *W, int nslots, 
 
 using cd = std::complex<double>;
 
+// run fn(i) for i in [0, count) on up to 16 host threads
+template <typename Fn>
+void parallel_for(int count, Fn fn) {
+    const int nt = std::max(1, std::min<int>({count, 16, static_cast<int>(std::thread::hardware_concurrency())}));
+    if (nt <= 1) {
+        for (int i = 0; i < count; ++i) fn(i);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&, t] {
+            for (int i = t; i < count; i += nt) fn(i);
+        });
+    for (auto &x : th) x.join();
+}
+
+
 // The Krylov space of a finished cycle, kept to deflate later cycles (GCRO):
 // the cycle's Arnoldi relation A V_k = V_{k+1} Hbar with Hbar = Q R by the
 // cycle's own Givens rotations gives C = V_{k+1} Q (orthonormal) and
@@ -869,8 +887,6 @@ int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
 
     to_device(act, rhs, s);
     std::vector<double> beta0(rn);
-    std::vector<std::vector<cd>> Bc;  // per slot: C^H A v_j, column j at [j * kmax]
-    std::vector<double2> hcoef;
     std::vector<int32_t> kcnt(ns, 0);
     if (use && kmax > 0) {
         // project the residuals: x += U C^H r, r -= C C^H r
@@ -906,7 +922,46 @@ int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
         bblas_update(n, R, ns, act, kd_d, use->V, yv, cs_, x, ldx, s);
         const std::vector<double> b2 = column_norms(p, Rres, ns, s);
         beta0 = b2;
-        Bc.assign(ns, std::vector<cd>(static_cast<size_t>(kmax) * m, 0.0));
+    }
+    // Deflation inside the cycle, W -= C C^H W with C = V1 Q (Q: the first k
+    // columns of the recycled cycle's rotations), runs on the device: per slot
+    // P = Q Q^H ((k+1) x (k+1)) turns the projections t = V1^H W into the
+    // update coefficients, and Q^H t (k entries) is summed into B (column j
+    // for step j: B = C^H A V, needed for the final correction).  P and Q^H
+    // are built once per cycle by rotating unit vectors.
+    const size_t pm = static_cast<size_t>(cs_) * cs_;
+    const int64_t bstride = static_cast<int64_t>(m) * kmax;
+    double2 *Pd = nullptr, *Md = nullptr, *Bd = nullptr;
+    int32_t *kcs_d = nullptr, *lslot_d = nullptr;
+    if (use && kmax > 0) {
+        std::vector<double2> Ph(pm * ns, make_double2(0.0, 0.0)), Mh(pm * ns, make_double2(0.0, 0.0));
+        parallel_for(ns, [&](int sl) {
+            const RecycleRhs &q = use->rhs[rhs[sl]];
+            if (q.k == 0) return;
+            std::vector<cd> t(q.k + 1), v(q.k + 1);
+            for (int j = 0; j <= q.k; ++j) {
+                std::fill(t.begin(), t.end(), cd(0.0));
+                t[j] = 1.0;
+                rot_fwd(q, t);
+                for (int i = 0; i < q.k; ++i) {
+                    Mh[sl * pm + static_cast<size_t>(j) * cs_ + i] = make_double2(t[i].real(), t[i].imag());
+                    v[i] = t[i];
+                }
+                v[q.k] = 0.0;
+                rot_bwd(q, v);
+                for (int i = 0; i <= q.k; ++i)
+                    Ph[sl * pm + static_cast<size_t>(j) * cs_ + i] = make_double2(v[i].real(), v[i].imag());
+            }
+        });
+        Pd = static_cast<double2 *>(p->defP.get(sizeof(double2) * pm * ns));
+        Md = static_cast<double2 *>(p->defM.get(sizeof(double2) * pm * ns));
+        Bd = static_cast<double2 *>(p->defB.get(sizeof(double2) * static_cast<size_t>(bstride) * ns));
+        kcs_d = static_cast<int32_t *>(p->defk.get(sizeof(int32_t) * ns));
+        lslot_d = static_cast<int32_t *>(p->lslot.get(sizeof(int32_t) * ns));
+        to_device(Pd, Ph, s);
+        to_device(Md, Mh, s);
+        to_device(kcs_d, kcnt, s);
+        blas_zero(bstride * ns, Bd, s);
     }
     // v0 = r / |r| (a zero projected residual gives a zero vector and stops at once)
     to_device(nrm, beta0, s);
@@ -936,6 +991,11 @@ int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
         if (nl == 0) break;
         if (live_rhs != live_prev) {
             to_device(live_d, live_rhs, s);
+            if (use && kmax > 0) {
+                std::vector<int32_t> ls(live_slot.begin(), live_slot.end());
+                to_device(lslot_d, ls, s);
+                to_device(kc_d, live_kc, s);
+            }
             live_prev = live_rhs;
         }
         // W = A v_k for the live right-hand sides; with relaxed products the FP64
@@ -949,32 +1009,13 @@ int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
         bblas_gather(n, nl, live_d, V + static_cast<int64_t>(k) * R * n, n, X, s);
         apply_op_graph(p, f, iprec, adjoint, nl, X, n, W, n, s);
         for (int r : live_rhs) (iprec == VSIE_FP64 ? cnt.mv64 : cnt.mv32)[r]++;
-        if (use && kmax > 0) to_device(kc_d, live_kc, s);
         for (int pass = 0; pass < 2; ++pass) {
             double2 *h = pass == 0 ? h1 : h2;
             if (use && kmax > 0) {
-                // deflation: W -= C (C^H W), with C^H W = first k entries of G (V1^H W)
+                // deflation: t = V1^H W, W -= V1 (P t), B column k += Q^H t
                 bblas_dots(n, kmax + 1, R, nl, live_d, use->V, W, dpart, nch, tc, cs_, s);
-                std::vector<double2> th;
-                to_host(th, tc, static_cast<size_t>(cs_) * nl, s);
-                hcoef.assign(static_cast<size_t>(cs_) * nl, make_double2(0, 0));
-                for (int l = 0; l < nl; ++l) {
-                    const int sl = live_slot[l];
-                    const RecycleRhs &q = use->rhs[live_rhs[l]];
-                    if (q.k == 0) continue;
-                    std::vector<cd> t(q.k + 1);
-                    for (int j = 0; j <= q.k; ++j) t[j] = cd(th[l * cs_ + j].x, th[l * cs_ + j].y);
-                    rot_fwd(q, t);
-                    std::vector<cd> v(q.k + 1, 0.0);
-                    for (int j = 0; j < q.k; ++j) {
-                        v[j] = t[j];
-                        Bc[sl][static_cast<size_t>(k) * kmax + j] += t[j];
-                    }
-                    rot_bwd(q, v);
-                    for (int j = 0; j <= q.k; ++j) hcoef[l * cs_ + j] = make_double2(v[j].real(), v[j].imag());
-                }
-                to_device(tc, hcoef, s);
-                bblas_gemv_sub(n, kmax + 1, R, nl, live_d, use->V, tc, cs_, W, s, kc_d);
+                bblas_deflate_coef(nl, lslot_d, kcs_d, cs_, Pd, Md, tc, yv, Bd, k, kmax, bstride, s);
+                bblas_gemv_sub(n, kmax + 1, R, nl, live_d, use->V, yv, cs_, W, s, kc_d);
             }
             if (bblas_fused_ok(k + 1)) {
                 bblas_dots_partial(n, k + 1, R, nl, live_d, V, W, dpart, nch, s);
@@ -1053,6 +1094,8 @@ int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
     to_device(kd_d, kdh, s);
     bblas_update(n, R, ns, act, kd_d, V, yv, ys, x, ldx, s);
     if (use && kmax > 0) {
+        std::vector<double2> Bh;
+        to_host(Bh, Bd, static_cast<size_t>(bstride) * ns, s);
         std::vector<double2> uh(static_cast<size_t>(ys) * ns, make_double2(0.0, 0.0));
         std::vector<int32_t> ku(ns, 0);
         for (int sl = 0; sl < ns; ++sl) {
@@ -1060,7 +1103,10 @@ int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
             if (q.k == 0 || kdone[sl] == 0) continue;
             std::vector<cd> by(q.k, 0.0);
             for (int j = 0; j < kdone[sl]; ++j)
-                for (int i = 0; i < q.k; ++i) by[i] += Bc[sl][static_cast<size_t>(j) * kmax + i] * ys_all[sl][j];
+                for (int i = 0; i < q.k; ++i) {
+                    const double2 b = Bh[static_cast<size_t>(sl) * bstride + static_cast<size_t>(j) * kmax + i];
+                    by[i] += cd(b.x, b.y) * ys_all[sl][j];
+                }
             const std::vector<cd> u = r_solve(q, by);
             for (int i = 0; i < q.k; ++i) uh[static_cast<size_t>(sl) * ys + i] = make_double2(-u[i].real(), -u[i].imag());
             ku[sl] = q.k;
@@ -1251,22 +1297,6 @@ vsie_status solve_batch(vsie_problem *p, int f, vsie_precision prec, bool adjoin
 // incremental Householder QR of the block upper Hessenberg matrix on the host
 // (one reflector per column, Ra + 1 rows long) that yields each column's
 // residual norm after every block step.
-
-// run fn(i) for i in [0, count) on up to 16 host threads
-template <typename Fn>
-void parallel_for(int count, Fn fn) {
-    const int nt = std::max(1, std::min<int>({count, 16, static_cast<int>(std::thread::hardware_concurrency())}));
-    if (nt <= 1) {
-        for (int i = 0; i < count; ++i) fn(i);
-        return;
-    }
-    std::vector<std::thread> th;
-    for (int t = 0; t < nt; ++t)
-        th.emplace_back([&, t] {
-            for (int i = t; i < count; i += nt) fn(i);
-        });
-    for (auto &x : th) x.join();
-}
 
 // G = T^H T with T upper triangular (G Hermitian r x r, column-major).  A
 // diagonal shift is added when a pivot is not safely positive (a nearly

@@ -319,6 +319,16 @@ void bblas_norm_scale(int64_t n, int kcol, int R, int nslots, const int32_t *act
                       const double *partial, int n_chunks, double *nrm, double2 *V, hipStream_t s);
 void bblas_gather(int64_t n, int nslots, const int32_t *act, const double2 *src, int64_t ld,
                   double2 *X, hipStream_t s);
+// Deflation coefficients of one Gram-Schmidt pass for nl live right-hand
+// sides: live position l holds slot sl = slot[l] with kc = kcount[sl] recycled
+// vectors (0: none) and projections t = tc[l * cs + 0..kc).  With P and M the
+// slot's kc x kc and (kc - 1) x kc matrices (column-major, leading dimension
+// cs, at P + sl * cs * cs and M + sl * cs * cs):
+//   hc[l * cs + i] = (P t)_i                       i < kc (0 up to cs)
+//   B[sl * bstride + col * kb + i] += (M t)_i      i < kc - 1
+void bblas_deflate_coef(int nl, const int32_t *slot, const int32_t *kcount, int cs, const double2 *P,
+                        const double2 *M, const double2 *tc, double2 *hc, double2 *B, int col, int kb,
+                        int64_t bstride, hipStream_t s);
 void bblas_update(int64_t n, int R, int nslots, const int32_t *act, const int32_t *kd, const double2 *V,
                   const double2 *y, int ystride, double2 *x, int64_t ldx, hipStream_t s);
 void blas_scatter_add(int64_t n, int nslots, const int32_t *act, const double2 *W, double2 *x, int64_t ldx,

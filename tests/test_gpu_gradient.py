@@ -44,7 +44,7 @@ def gpu_gradient(V, mesh, mat, k0, dirs, rec, data, prec=0, tol=1e-13):
     dt = torch.as_tensor(np.ascontiguousarray(data.T), device="cuda")
     loss = 0.5 * (pr - dt).abs().pow(2).sum()
     loss.backward()
-    return float(loss), c.grad.cpu().numpy(), rho.grad.cpu().numpy(), pr.detach().cpu().numpy().T
+    return float(loss.detach()), c.grad.cpu().numpy(), rho.grad.cpu().numpy(), pr.detach().cpu().numpy().T
 
 
 def fd(mesh, mat, k0, dirs, rec, data, which, cells, eps=1e-5):

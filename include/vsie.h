@@ -166,10 +166,14 @@ typedef struct {
                                   once per unordered pair (e_ij = e_ji), in work items
                                   of sym_groups x sym_groups 64-cell tiles; 0 = off,
                                   2, 4 or 8; default 4 */
-    int32_t cell_face;         /* with sym_groups on and every double-layer source a
-                                  face: the cell-face pairs also run once per pair
-                                  (single layer at the face, double layers at the
-                                  cell); 0 = off, 1 = on; default 1 */
+    int32_t cell_face;         /* with sym_groups on: the cell-face pairs also run
+                                  once per pair (single layer and adjoint double
+                                  layer of the cell at the face, double layer of the
+                                  face at the cell), the cells' adjoint double layers
+                                  (grad alpha) ride along the cell-cell single
+                                  layer, and only the faces with a double-layer
+                                  weight are summed over the faces one-sided;
+                                  0 = off, 1 = on; default 1 */
     int32_t mfma_3m;           /* matrix-core products: 0 = four real products per
                                   complex multiply-add (Kr Qr, Ki Qi, Kr Qi, Ki Qr),
                                   1 = three (Kr Qr, Ki Qi, (Kr + Ki)(Qr + Qi); the

@@ -27,11 +27,21 @@
 // gets exactly one partial per group: part[slot * ldp + p].  A reduction
 // kernel adds them in slot order (deterministic).
 //
+// With the adjoint double layer (T, cells with grad alpha, v'_i != 0) the
+// same evaluation also gives F = e (i k r - 1)/r^2 and both directions of
+// that term, q x with q = (x_target - y_source).v'_source:
+//   y_i += F (d.v'_j) x_j   and   y_j += F (-d.v'_i) x_i,   d = x_i - x_j.
+// Items whose tiles hold no such cell run the single-layer loop alone.
+//
 // Schedule: items cut into 8 contiguous ranges (one per XCD, workgroup b
 // runs on XCD b mod 8), one item per wave, so that the hardware dispatcher
-// balances the load.  (A persistent grid with a static split leaves the tail
+// balances the load within an XCD.  The ranges hold equal modelled work: an
+// item with grad-alpha cells counts as its issue cycles per pair relative to
+// a single-layer item (the host computes the boundaries).  (A persistent grid with a static split leaves the tail
 // to a few waves: the SIMD issues to its oldest wave first, so waves finish
 // one by one and the last wave on each SIMD runs nearly alone.)
+#include <type_traits>
+
 #include "pair_geom.h"
 #include "vsie_internal.h"
 
@@ -72,8 +82,16 @@ struct SymArgs {
     int tiles;
     int groups;
     int64_t items;
+    int64_t xr[kXcds + 1];           // item range of XCD x: [xr[x], xr[x + 1])
     double2 *__restrict__ part;
     int64_t ldp;
+    // adjoint double layer (T variant only): v' of the cells, the raw values
+    // x, and per 64-cell tile whether any v' is nonzero
+    const double *__restrict__ vx;
+    const double *__restrict__ vy;
+    const double *__restrict__ vz;
+    const double2 *__restrict__ xv;
+    const int32_t *__restrict__ tile_t;
 };
 
 // position and charge of point p of a tile (padding lanes: distinct far points, zero charge)
@@ -104,23 +122,65 @@ __device__ __forceinline__ void pair_e(double dx, double dy, double dz, const Sy
     else geom_f64<false>(dx, dy, dz, a.k, a.kphase, er, ei, ir2, kr);
 }
 
-template <int G, typename AT>
+// e = exp(i k r)/r and F = e (i k r - 1)/r^2 of one pair
+template <typename AT>
+__device__ __forceinline__ void pair_ef(double dx, double dy, double dz, const SymArgs &a, AT kk, AT &er, AT &ei,
+                                        AT &fr, AT &fi) {
+    AT ir2, kr;
+    if constexpr (sizeof(AT) == 4) geom_f32<false>(dx, dy, dz, kk, a.kphase, er, ei, ir2, kr);
+    else geom_f64<false>(dx, dy, dz, a.k, a.kphase, er, ei, ir2, kr);
+    fr = ir2 * fma(-ei, kr, -er);
+    fi = ir2 * fma(er, kr, -ei);
+}
+
+// v' and value of point p of a tile (padding lanes: zero)
+template <typename AT>
+__device__ __forceinline__ void load_t(const double *__restrict__ vx, const double *__restrict__ vy,
+                                       const double *__restrict__ vz, const double2 *__restrict__ xv, int64_t p,
+                                       int64_t count, AT &v0, AT &v1, AT &v2, AT &wr, AT &wi) {
+    if (p < count) {
+        v0 = static_cast<AT>(vx[p]);
+        v1 = static_cast<AT>(vy[p]);
+        v2 = static_cast<AT>(vz[p]);
+        const double2 w = xv[p];
+        wr = static_cast<AT>(w.x);
+        wi = static_cast<AT>(w.y);
+    } else {
+        v0 = v1 = v2 = wr = wi = 0;
+    }
+}
+
+// d . v' with d the FP64 difference: in FP32 from d rounded once on the FP32
+// path (the product feeds an amplitude, not a phase), in FP64 otherwise
+template <typename AT>
+__device__ __forceinline__ AT dot_v(AT dxa, AT dya, AT dza, AT v0, AT v1, AT v2) {
+    return fma(dxa, v0, fma(dya, v1, dza * v2));
+}
+
+template <int G, typename AT, bool T>
 __global__ __launch_bounds__(kBlock) void sym_kernel(SymArgs a) {
     using C2 = typename c2_of<AT>::type;
     // per-wave copies of the B tile, stored twice in a row (entries 0..127) so
     // that step st reads entry lane + 64 - st without wrapping; one block per
-    // wave, so the four arrays sit at fixed offsets from one address
-    struct BTile {
+    // wave, so the arrays sit at fixed offsets from one address
+    struct BTileS {
         double x[128], y[128], z[128];
         C2 u[128];
     };
+    struct BTileT {
+        double x[128], y[128], z[128];
+        C2 u[128];
+        AT vx[128], vy[128], vz[128];
+        C2 w[128];
+    };
+    using BTile = typename std::conditional<T, BTileT, BTileS>::type;
     __shared__ BTile lb[kWavesPerBlock];
     const int lane = threadIdx.x & 63;
     const int wib = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
     const int xcd = blockIdx.x % kXcds;
     const int64_t waves_x = static_cast<int64_t>(gridDim.x / kXcds) * kWavesPerBlock;
     const int64_t w = static_cast<int64_t>(blockIdx.x / kXcds) * kWavesPerBlock + wib;
-    const int64_t lo = a.items * xcd / kXcds, hi = a.items * (xcd + 1) / kXcds;
+    const int64_t lo = a.xr[xcd], hi = a.xr[xcd + 1];
     const AT kk = static_cast<AT>(a.k);
     BTile &B = lb[wib];
 
@@ -135,6 +195,15 @@ __global__ __launch_bounds__(kBlock) void sym_kernel(SymArgs a) {
         while (r + 1 < a.groups && (r + 1) * (g2 - r - 1) / 2 <= it) ++r;
         const int I = static_cast<int>(r);
         const int J = static_cast<int>(r + (it - r * (g2 - r) / 2));
+        // whether any tile of either group holds a cell with v' != 0 (wave-uniform)
+        bool item_t = false;
+        if constexpr (T) {
+            for (int t = 0; t < G; ++t) {
+                const int ti = I * G + t, tj = J * G + t;
+                if (ti < a.tiles && a.tile_t[ti]) item_t = true;
+                if (tj < a.tiles && a.tile_t[tj]) item_t = true;
+            }
+        }
 
         double accAr[G], accAi[G], accBr[G], accBi[G];
 #pragma unroll
@@ -146,6 +215,10 @@ __global__ __launch_bounds__(kBlock) void sym_kernel(SymArgs a) {
             double xa, ya, za;
             AT uar, uai;
             load_point<AT>(a, static_cast<int64_t>(at) * 64 + lane, lane, xa, ya, za, uar, uai);
+            AT va0 = 0, va1 = 0, va2 = 0, war = 0, wai = 0;
+            if constexpr (T) {
+                if (item_t) load_t<AT>(a.vx, a.vy, a.vz, a.xv, static_cast<int64_t>(at) * 64 + lane, a.ng, va0, va1, va2, war, wai);
+            }
             for (int tb = (I == J) ? ta : 0; tb < G; ++tb) {
                 const int bt = J * G + tb;
                 if (bt >= a.tiles) break;
@@ -160,9 +233,65 @@ __global__ __launch_bounds__(kBlock) void sym_kernel(SymArgs a) {
                     B.y[lane] = B.y[lane + 64] = yb;
                     B.z[lane] = B.z[lane + 64] = zb;
                     B.u[lane] = B.u[lane + 64] = u;
+                    if constexpr (T) {
+                        if (item_t) {
+                            AT v0, v1, v2, wr, wi;
+                            load_t<AT>(a.vx, a.vy, a.vz, a.xv, static_cast<int64_t>(bt) * 64 + lane, a.ng, v0, v1, v2, wr, wi);
+                            C2 w;
+                            w.x = wr;
+                            w.y = wi;
+                            B.vx[lane] = B.vx[lane + 64] = v0;
+                            B.vy[lane] = B.vy[lane + 64] = v1;
+                            B.vz[lane] = B.vz[lane + 64] = v2;
+                            B.w[lane] = B.w[lane + 64] = w;
+                        }
+                    }
                 }
                 AT sAr = 0, sAi = 0, sBr = 0, sBi = 0;
-                if (at == bt) {
+                bool done = false;
+                if constexpr (T) {
+                    if (item_t) {
+                        // single layer and adjoint double layer together
+                        if (at == bt) {
+                            // the tile with itself: the 63 other points, target side only
+                            for (int st = 1; st < 64; ++st) {
+                                const int j = lane + 64 - st;
+                                const double dx = xa - B.x[j], dy = ya - B.y[j], dz = za - B.z[j];
+                                AT er, ei, fr, fi;
+                                pair_ef<AT>(dx, dy, dz, a, kk, er, ei, fr, fi);
+                                const C2 u = B.u[j], w = B.w[j];
+                                const AT qb = dot_v<AT>(static_cast<AT>(dx), static_cast<AT>(dy), static_cast<AT>(dz),
+                                                        B.vx[j], B.vy[j], B.vz[j]);
+                                const AT tbr = qb * w.x, tbi = qb * w.y;
+                                sAr = fma(er, u.x, fma(-ei, u.y, fma(fr, tbr, fma(-fi, tbi, sAr))));
+                                sAi = fma(er, u.y, fma(ei, u.x, fma(fr, tbi, fma(fi, tbr, sAi))));
+                            }
+                        } else {
+                            for (int st = 0; st < 64; ++st) {
+                                const int j = lane + 64 - st;
+                                const double dx = xa - B.x[j], dy = ya - B.y[j], dz = za - B.z[j];
+                                AT er, ei, fr, fi;
+                                pair_ef<AT>(dx, dy, dz, a, kk, er, ei, fr, fi);
+                                const AT dxa = static_cast<AT>(dx), dya = static_cast<AT>(dy), dza = static_cast<AT>(dz);
+                                const C2 u = B.u[j], w = B.w[j];
+                                // target a: e u_b + F (d.v'_b) x_b
+                                const AT qb = dot_v<AT>(dxa, dya, dza, B.vx[j], B.vy[j], B.vz[j]);
+                                const AT tbr = qb * w.x, tbi = qb * w.y;
+                                sAr = fma(er, u.x, fma(-ei, u.y, fma(fr, tbr, fma(-fi, tbi, sAr))));
+                                sAi = fma(er, u.y, fma(ei, u.x, fma(fr, tbi, fma(fi, tbr, sAi))));
+                                // target b: e u_a + F (-d.v'_a) x_a
+                                const AT qa = -dot_v<AT>(dxa, dya, dza, va0, va1, va2);
+                                const AT tar = qa * war, tai = qa * wai;
+                                sBr = rot1(fma(er, uar, fma(-ei, uai, fma(fr, tar, fma(-fi, tai, sBr)))));
+                                sBi = rot1(fma(er, uai, fma(ei, uar, fma(fr, tai, fma(fi, tar, sBi)))));
+                            }
+                        }
+                        done = true;
+                    }
+                }
+                if (done) {
+                    // the adjoint double layer loop above covered this tile pair
+                } else if (at == bt) {
                     // the tile with itself: the 63 other points, target side only
                     for (int st = 1; st < 64; ++st) {
                         const int j = lane + 64 - st;
@@ -288,6 +417,9 @@ __global__ __launch_bounds__(kBlock) void slot_reduce_kernel(int64_t n, int64_t 
 // face f at cell target c share the pair's distance, phase, sine and cosine:
 //   y_f += e u_c,                 u_c = -s'_c x_c
 //   y_c += e (i k r - 1) q x_f,   q = (x_c - y_f).v'_f / r^2
+// and, with cells that carry grad alpha (T variant, items whose cell group
+// holds one), the cell's adjoint double layer at the face:
+//   y_f += e (i k r - 1) q' x_c,  q' = (y_f - x_c).v'_c / r^2
 // Lanes hold cells (tile A); the face tile B (positions, v', values) sits in
 // the wave's LDS slice and the faces' single-layer sums rotate by DPP, as in
 // sym_kernel.  Work items are (cell group I, face group J), every pair of
@@ -298,11 +430,17 @@ struct CfArgs {
     const double *__restrict__ px;
     const double *__restrict__ py;
     const double *__restrict__ pz;
-    const double *__restrict__ vx;   // v' of the faces (nf entries)
+    const double *__restrict__ vx;   // v' of the faces (nf entries, zero where a face has no weight)
     const double *__restrict__ vy;
     const double *__restrict__ vz;
     const void *__restrict__ qc;     // single-layer charges of the cells, complex AT
-    const void *__restrict__ qf;     // values of the faces (double-layer charges), complex AT
+    const double2 *__restrict__ xf;  // values of the faces
+    // T variant: v' of the cells, their values, and per 64-cell tile whether any v' is nonzero
+    const double *__restrict__ cvx;
+    const double *__restrict__ cvy;
+    const double *__restrict__ cvz;
+    const double2 *__restrict__ xc;
+    const int32_t *__restrict__ ctile_t;
     double k;
     double kphase;
     double far[3];
@@ -310,13 +448,14 @@ struct CfArgs {
     int ctiles, ftiles;
     int cgroups, fgroups;
     int64_t items;
+    int64_t xr[kXcds + 1];           // item range of XCD x: [xr[x], xr[x + 1])
     double2 *__restrict__ pc;        // pc[slot * ldc + c], slot = face group
     int64_t ldc;
     double2 *__restrict__ pf;        // pf[slot * ldf + f], slot = cell group
     int64_t ldf;
 };
 
-template <int G, typename AT>
+template <int G, typename AT, bool T>
 __global__ __launch_bounds__(kBlock) void cf_kernel(CfArgs a) {
     using C2 = typename c2_of<AT>::type;
     struct FTile {
@@ -329,13 +468,20 @@ __global__ __launch_bounds__(kBlock) void cf_kernel(CfArgs a) {
     const int xcd = blockIdx.x % kXcds;
     const int64_t waves_x = static_cast<int64_t>(gridDim.x / kXcds) * kWavesPerBlock;
     const int64_t w = static_cast<int64_t>(blockIdx.x / kXcds) * kWavesPerBlock + wib;
-    const int64_t lo = a.items * xcd / kXcds, hi = a.items * (xcd + 1) / kXcds;
+    const int64_t lo = a.xr[xcd], hi = a.xr[xcd + 1];
     const AT kk = static_cast<AT>(a.k);
     FTile &B = lb[wib];
 
     for (int64_t it = lo + w; it < hi; it += waves_x) {
         const int I = static_cast<int>(it / a.fgroups);
         const int J = static_cast<int>(it - static_cast<int64_t>(I) * a.fgroups);
+        bool item_t = false;
+        if constexpr (T) {
+            for (int t = 0; t < G; ++t) {
+                const int ti = I * G + t;
+                if (ti < a.ctiles && a.ctile_t[ti]) item_t = true;
+            }
+        }
         double accAr[G], accAi[G], accBr[G], accBi[G];
 #pragma unroll
         for (int t = 0; t < G; ++t) accAr[t] = accAi[t] = accBr[t] = accBi[t] = 0.0;
@@ -359,6 +505,18 @@ __global__ __launch_bounds__(kBlock) void cf_kernel(CfArgs a) {
                 za = a.far[2];
                 uar = uai = 0;
             }
+            double va0 = 0, va1 = 0, va2 = 0;
+            AT war = 0, wai = 0;
+            if constexpr (T) {
+                if (item_t && c < a.nc) {
+                    va0 = a.cvx[c];
+                    va1 = a.cvy[c];
+                    va2 = a.cvz[c];
+                    const double2 w = a.xc[c];
+                    war = static_cast<AT>(w.x);
+                    wai = static_cast<AT>(w.y);
+                }
+            }
             for (int tb = 0; tb < G; ++tb) {
                 const int bt = J * G + tb;
                 if (bt >= a.ftiles) break;
@@ -373,7 +531,9 @@ __global__ __launch_bounds__(kBlock) void cf_kernel(CfArgs a) {
                         wx = a.vx[f];
                         wy = a.vy[f];
                         wz = a.vz[f];
-                        u = static_cast<const C2 *>(a.qf)[f];
+                        const double2 xv = a.xf[f];
+                        u.x = static_cast<AT>(xv.x);
+                        u.y = static_cast<AT>(xv.y);
                     } else {
                         // padding faces: far points apart from the padding cells, v' = 0, value 0
                         xb = a.far[0] + a.far_step * (lane + 64);
@@ -391,7 +551,34 @@ __global__ __launch_bounds__(kBlock) void cf_kernel(CfArgs a) {
                     B.u[lane] = B.u[lane + 64] = u;
                 }
                 AT sAr = 0, sAi = 0, sBr = 0, sBi = 0;
-                for (int st = 0; st < 64; ++st) {
+                bool done = false;
+                if constexpr (T) {
+                    if (item_t) {
+                        for (int st = 0; st < 64; ++st) {
+                            const int j = lane + 64 - st;
+                            const double dx = xa - B.x[j], dy = ya - B.y[j], dz = za - B.z[j];
+                            AT er, ei, ir2, kr;
+                            if constexpr (sizeof(AT) == 4) geom_f32<false>(dx, dy, dz, kk, a.kphase, er, ei, ir2, kr);
+                            else geom_f64<false>(dx, dy, dz, a.k, a.kphase, er, ei, ir2, kr);
+                            // F = e (i k r - 1) / r^2
+                            const AT fr = ir2 * fma(-ei, kr, -er);
+                            const AT fi = ir2 * fma(er, kr, -ei);
+                            // double layer of the face at the cell
+                            const AT qq = static_cast<AT>(fma(dx, B.vx[j], fma(dy, B.vy[j], dz * B.vz[j])));
+                            const C2 u = B.u[j];
+                            const AT tr = qq * u.x, ti = qq * u.y;
+                            sAr = fma(fr, tr, fma(-fi, ti, sAr));
+                            sAi = fma(fr, ti, fma(fi, tr, sAi));
+                            // single layer and adjoint double layer of the cell at the face
+                            const AT qc = -static_cast<AT>(fma(dx, va0, fma(dy, va1, dz * va2)));
+                            const AT cr = qc * war, ci = qc * wai;
+                            sBr = rot1(fma(er, uar, fma(-ei, uai, fma(fr, cr, fma(-fi, ci, sBr)))));
+                            sBi = rot1(fma(er, uai, fma(ei, uar, fma(fr, ci, fma(fi, cr, sBi)))));
+                        }
+                        done = true;
+                    }
+                }
+                for (int st = 0; st < (done ? 0 : 64); ++st) {
                     // face (lane - st) mod 64; its single-layer sum has moved st lanes up
                     const int j = lane + 64 - st;
                     const double dx = xa - B.x[j], dy = ya - B.y[j], dz = za - B.z[j];
@@ -435,14 +622,15 @@ __global__ __launch_bounds__(kBlock) void cf_kernel(CfArgs a) {
 }
 
 template <int G, typename AT>
-const void *sym_ptr() {
-    return reinterpret_cast<const void *>(&sym_kernel<G, AT>);
+const void *sym_ptr(bool t) {
+    return t ? reinterpret_cast<const void *>(&sym_kernel<G, AT, true>)
+             : reinterpret_cast<const void *>(&sym_kernel<G, AT, false>);
 }
 
-const void *pick_sym(int g, bool f32) {
-    if (g == 2) return f32 ? sym_ptr<2, float>() : sym_ptr<2, double>();
-    if (g == 4) return f32 ? sym_ptr<4, float>() : sym_ptr<4, double>();
-    if (g == 8) return f32 ? sym_ptr<8, float>() : sym_ptr<8, double>();
+const void *pick_sym(int g, bool f32, bool t) {
+    if (g == 2) return f32 ? sym_ptr<2, float>(t) : sym_ptr<2, double>(t);
+    if (g == 4) return f32 ? sym_ptr<4, float>(t) : sym_ptr<4, double>(t);
+    if (g == 8) return f32 ? sym_ptr<8, float>(t) : sym_ptr<8, double>(t);
     return nullptr;
 }
 
@@ -465,6 +653,69 @@ int64_t one_item_per_wave_grid(int64_t items) {
     const int64_t grid = kXcds * std::max<int64_t>(1, (per_xcd + kWavesPerBlock - 1) / kWavesPerBlock);
     if (grid > 0x7fffffff) fail(VSIE_E_INVALID, "pair kernel: too many work items for one launch");
     return grid;
+}
+
+namespace {
+
+// the same for ranges of unequal length: one wave per item of the longest range
+int64_t ranges_grid(const int64_t *xr) {
+    int64_t most = 1;
+    for (int x = 0; x < kXcds; ++x) most = std::max<int64_t>(most, xr[x + 1] - xr[x]);
+    const int64_t grid = kXcds * ((most + kWavesPerBlock - 1) / kWavesPerBlock);
+    if (grid > 0x7fffffff) fail(VSIE_E_INVALID, "pair kernel: too many work items for one launch");
+    return grid;
+}
+
+void equal_ranges(int64_t items, int64_t *xr) {
+    for (int x = 0; x <= kXcds; ++x) xr[x] = items * x / kXcds;
+}
+
+// Boundaries of 8 contiguous item ranges of equal cost, items in order, with
+// cost(it) = weight for flagged items and 1 otherwise; flagged(it) is called
+// once per item in increasing order.
+template <typename Flag>
+void cost_ranges(int64_t items, double weight, Flag flagged, int64_t *xr) {
+    std::vector<unsigned char> f(static_cast<size_t>(items));
+    double total = 0.0;
+    for (int64_t it = 0; it < items; ++it) {
+        f[static_cast<size_t>(it)] = flagged(it) ? 1 : 0;
+        total += f[static_cast<size_t>(it)] ? weight : 1.0;
+    }
+    xr[0] = 0;
+    double acc = 0.0;
+    int x = 1;
+    for (int64_t it = 0; it < items && x < kXcds; ++it) {
+        acc += f[static_cast<size_t>(it)] ? weight : 1.0;
+        while (x < kXcds && acc >= total * x / kXcds) xr[x++] = it + 1;
+    }
+    while (x < kXcds) xr[x++] = items;
+    xr[kXcds] = items;
+}
+
+}  // namespace
+
+void sym_cost_ranges(int64_t ng, int g, const std::vector<int32_t> &tile_t, double weight, int64_t *xr) {
+    const int64_t tiles = (ng + 63) / 64, groups = sym_slots(ng, g);
+    const int64_t items = groups * (groups + 1) / 2;
+    std::vector<char> gt(static_cast<size_t>(groups), 0);
+    for (int64_t t = 0; t < tiles && t < static_cast<int64_t>(tile_t.size()); ++t)
+        if (tile_t[static_cast<size_t>(t)]) gt[static_cast<size_t>(t / g)] = 1;
+    // item order: row I, then J = I .. groups - 1
+    int64_t I = 0, J = 0;
+    cost_ranges(items, weight, [&](int64_t) {
+        const bool r = gt[static_cast<size_t>(I)] || gt[static_cast<size_t>(J)];
+        if (++J == groups) J = ++I;
+        return r;
+    }, xr);
+}
+
+void cf_cost_ranges(int64_t nc, int64_t nf, const std::vector<int32_t> &tile_t, double weight, int64_t *xr) {
+    const int64_t ctiles = (nc + 63) / 64, cgroups = cf_groups(nc), fgroups = cf_groups(nf);
+    std::vector<char> gt(static_cast<size_t>(cgroups), 0);
+    for (int64_t t = 0; t < ctiles && t < static_cast<int64_t>(tile_t.size()); ++t)
+        if (tile_t[static_cast<size_t>(t)]) gt[static_cast<size_t>(t / kCfGroup)] = 1;
+    // item order: cell group I, then face group J
+    cost_ranges(cgroups * fgroups, weight, [&](int64_t it) { return gt[static_cast<size_t>(it / fgroups)] != 0; }, xr);
 }
 
 bool sym_groups_ok(int g) { return g == 2 || g == 4 || g == 8; }
@@ -491,11 +742,26 @@ void launch_sym(const SymJob &J, hipStream_t s, PairProfiler *prof) {
     a.tiles = static_cast<int>((J.ng + 63) / 64);
     a.groups = static_cast<int>(sym_slots(J.ng, J.g));
     a.items = static_cast<int64_t>(a.groups) * (a.groups + 1) / 2;
+    if (J.xr) {
+        if (J.xr[0] != 0 || J.xr[kXcds] != a.items) fail(VSIE_E_INVALID, "symmetric pair kernel: item ranges do not cover the items");
+        for (int x = 0; x < kXcds; ++x)
+            if (J.xr[x] > J.xr[x + 1]) fail(VSIE_E_INVALID, "symmetric pair kernel: item ranges out of order");
+        for (int x = 0; x <= kXcds; ++x) a.xr[x] = J.xr[x];
+    } else {
+        equal_ranges(a.items, a.xr);
+    }
     a.part = J.part;
     a.ldp = J.ldp;
+    a.vx = J.vx;
+    a.vy = J.vy;
+    a.vz = J.vz;
+    a.xv = J.xv;
+    a.tile_t = J.tile_t;
     if (J.ldp < J.ng) fail(VSIE_E_INVALID, "symmetric pair kernel: partial stride below the cell count");
-    const void *kp = pick_sym(J.g, f32);
-    const int64_t grid = one_item_per_wave_grid(a.items);
+    const bool t = J.vx != nullptr;
+    if (t && !(J.vy && J.vz && J.xv && J.tile_t)) fail(VSIE_E_INVALID, "symmetric pair kernel: incomplete T data");
+    const void *kp = pick_sym(J.g, f32, t);
+    const int64_t grid = ranges_grid(a.xr);
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (prof && prof->on) {
         ev0 = prof_take_event(prof);
@@ -539,7 +805,12 @@ void launch_cf(const CfJob &J, hipStream_t s, PairProfiler *prof) {
     a.vy = J.vy;
     a.vz = J.vz;
     a.qc = J.qc;
-    a.qf = J.qf;
+    a.xf = J.xf;
+    a.cvx = J.cvx;
+    a.cvy = J.cvy;
+    a.cvz = J.cvz;
+    a.xc = J.xc;
+    a.ctile_t = J.ctile_t;
     a.k = J.k;
     a.kphase = f32 ? J.k / kTwoPi : J.k / kPi;
     for (int d = 0; d < 3; ++d) a.far[d] = J.far[d];
@@ -549,13 +820,26 @@ void launch_cf(const CfJob &J, hipStream_t s, PairProfiler *prof) {
     a.cgroups = static_cast<int>(cf_groups(J.nc));
     a.fgroups = static_cast<int>(cf_groups(J.nf));
     a.items = static_cast<int64_t>(a.cgroups) * a.fgroups;
+    if (J.xr) {
+        if (J.xr[0] != 0 || J.xr[kXcds] != a.items) fail(VSIE_E_INVALID, "cell-face kernel: item ranges do not cover the items");
+        for (int x = 0; x < kXcds; ++x)
+            if (J.xr[x] > J.xr[x + 1]) fail(VSIE_E_INVALID, "cell-face kernel: item ranges out of order");
+        for (int x = 0; x <= kXcds; ++x) a.xr[x] = J.xr[x];
+    } else {
+        equal_ranges(a.items, a.xr);
+    }
     a.pc = J.pc;
     a.ldc = J.nc;
     a.pf = J.pf;
     a.ldf = J.nf;
-    const void *kp = f32 ? reinterpret_cast<const void *>(&cf_kernel<kCfGroup, float>)
-                         : reinterpret_cast<const void *>(&cf_kernel<kCfGroup, double>);
-    const int64_t grid = one_item_per_wave_grid(a.items);
+    const bool t = J.cvx != nullptr;
+    if (t && !(J.cvy && J.cvz && J.xc && J.ctile_t)) fail(VSIE_E_INVALID, "cell-face kernel: incomplete T data");
+    if (!J.xf || !J.vx || !J.vy || !J.vz) fail(VSIE_E_INVALID, "cell-face kernel: missing face data");
+    const void *kp = f32 ? (t ? reinterpret_cast<const void *>(&cf_kernel<kCfGroup, float, true>)
+                              : reinterpret_cast<const void *>(&cf_kernel<kCfGroup, float, false>))
+                         : (t ? reinterpret_cast<const void *>(&cf_kernel<kCfGroup, double, true>)
+                              : reinterpret_cast<const void *>(&cf_kernel<kCfGroup, double, false>));
+    const int64_t grid = ranges_grid(a.xr);
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (prof && prof->on) {
         ev0 = prof_take_event(prof);

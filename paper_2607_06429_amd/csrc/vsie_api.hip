@@ -128,9 +128,19 @@ struct vsie_problem {
     // every cell is a single-layer source and the sources are the cells in
     // canonical order (the symmetric cell-cell kernel applies)
     bool g_is_cells = false;
-    // the double-layer sources are exactly the faces (no cell has grad alpha):
-    // the fused cell-face kernel applies
+    // the double-layer sources are exactly the faces (no cell has grad alpha)
     bool f_is_faces = false;
+    // double-layer sources that are cells (F holds them first, then the faces)
+    // and, per 64-cell tile, whether any cell in it has grad alpha
+    int64_t f_cells = 0;
+    Scratch ctile;
+    std::vector<int32_t> ctile_h;  // host copy of the tile flags
+    // cached XCD item ranges of the symmetric and cell-face kernels with
+    // grad-alpha cells, per precision (valid for group size g)
+    struct TRanges {
+        int g = -1;
+        int64_t sym[9], cf[9];
+    } tranges[2];
     double far[3] = {0, 0, 0}, far_step = 1;  // padding points of the tiled kernels
     // dense FP32 off-diagonal operator per frequency (caller-owned memory)
     struct Dense {
@@ -202,7 +212,7 @@ struct vsie_problem {
         for (void *p : owned) (void)hipFree(p);
         for (Scratch *s : {&partial, &chargeG, &chargeF, &chargeAll, &sums_part, &grad_work, &V, &V2, &w, &r, &ax,
                            &h1, &tc, &nrm, &dpart, &npart, &yv, &act, &act2, &live, &kd, &kc, &xa, &axa, &brc,
-                           &rres, &bh, &bg, &bsk})
+                           &rres, &bh, &bg, &bsk, &defP, &defM, &defB, &defk, &lslot, &ctile})
             s->release();
     }
 };
@@ -325,6 +335,18 @@ void build_sources(vsie_problem *p) {
     p->far_step = ext;
     p->g_is_cells = static_cast<int64_t>(gi.size()) == p->m.n_vol && p->m.n_vol > 0;
     p->f_is_faces = static_cast<int64_t>(fi.size()) == p->m.n_srf && p->m.n_srf > 0 && fi[0] == p->m.n_vol;
+    p->f_cells = 0;
+    for (int32_t e : fi) p->f_cells += e < p->m.n_vol ? 1 : 0;
+    {
+        const int64_t tiles = (p->m.n_vol + 63) / 64;
+        std::vector<int32_t> flag(static_cast<size_t>(std::max<int64_t>(1, tiles)), 0);
+        for (int64_t e = 0; e < p->m.n_vol; ++e)
+            if (vp[e] != 0.0 || vp[n + e] != 0.0 || vp[2 * n + e] != 0.0) flag[static_cast<size_t>(e / 64)] = 1;
+        void *d = p->ctile.get(sizeof(int32_t) * flag.size());
+        VSIE_HIP(hipMemcpy(d, flag.data(), sizeof(int32_t) * flag.size(), hipMemcpyHostToDevice));
+        p->ctile_h = flag;
+        for (auto &r : p->tranges) r.g = -1;
+    }
     auto fill = [&](SourceSet &S, const std::vector<int32_t> &ix, bool with_v) {
         S.count = static_cast<int64_t>(ix.size());
         if (S.count == 0) return;
@@ -421,9 +443,11 @@ void apply_forward_cf(vsie_problem *p, int f, vsie_precision prec, const double2
     const int64_t n = p->m.n, nv = p->m.n_vol, ns = n - nv;
     const int g = p->tune.sym_groups;
     const int64_t slots = sym_slots(nv, g), cs = cf_groups(ns), fs = cf_groups(nv);
+    // the double-layer sources among the faces: the tail of F
+    const int64_t fo = p->f_cells, nff = p->F.count - p->f_cells;
     int64_t chFF = 1;
     int ncFF = 0;
-    choose_chunks(ns, p->F.count, p->tune.vec_target_waves, chFF, ncFF);
+    if (ns > 0) choose_chunks(ns, nff, p->tune.vec_target_waves, chFF, ncFF);
     const size_t total = static_cast<size_t>(slots * nv + cs * nv + fs * ns + static_cast<int64_t>(ncFF) * ns);
     double2 *part = static_cast<double2 *>(p->partial.get(sizeof(double2) * std::max<size_t>(1, total)));
     double2 *psym = part, *pc = psym + slots * nv, *pf = pc + cs * nv, *pff = pf + fs * ns;
@@ -432,15 +456,48 @@ void apply_forward_cf(vsie_problem *p, int f, vsie_precision prec, const double2
     const double *spf = p->m.sp + static_cast<int64_t>(f) * n;
     launch_pack_both(prec, p->G, p->F, spf, 1, x, n, false, qG, qF, s);
     const double k = p->k0[f];
+    const bool t = p->f_cells > 0;
+    const int32_t *tiles_t = static_cast<const int32_t *>(p->ctile.p);
     SymJob J{prec, nv, p->m.px, p->m.py, p->m.pz, qG, k, {p->far[0], p->far[1], p->far[2]}, p->far_step, g, psym, nv};
+    vsie_problem::TRanges &tr = p->tranges[prec == VSIE_FP32 ? 1 : 0];
+    if (t && tr.g != g) {
+        // issue cycles per pair of the grad-alpha loops relative to the
+        // single-layer ones (counted in the compiled loops): symmetric kernel
+        // 1.53 (FP32) and 1.42 (FP64), cell-face kernel 1.17 and 1.42
+        const bool f32 = prec == VSIE_FP32;
+        sym_cost_ranges(nv, g, p->ctile_h, f32 ? 1.53 : 1.42, tr.sym);
+        cf_cost_ranges(nv, ns, p->ctile_h, f32 ? 1.17 : 1.42, tr.cf);
+        tr.g = g;
+    }
+    if (t) {
+        J.vx = p->m.vpx;
+        J.vy = p->m.vpy;
+        J.vz = p->m.vpz;
+        J.xv = x;
+        J.tile_t = tiles_t;
+        J.xr = tr.sym;
+    }
     launch_sym(J, s, &p->prof);
-    CfJob C{prec, nv, ns, p->m.px, p->m.py, p->m.pz, p->F.vx, p->F.vy, p->F.vz, qG, qF, k,
-            {p->far[0], p->far[1], p->far[2]}, p->far_step, pc, pf};
-    launch_cf(C, s, &p->prof);
+    if (ns > 0) {
+        CfJob C{prec, nv, ns, p->m.px, p->m.py, p->m.pz, p->m.vpx + nv, p->m.vpy + nv, p->m.vpz + nv, qG, x + nv, k,
+                {p->far[0], p->far[1], p->far[2]}, p->far_step, pc, pf};
+        if (t) {
+            C.cvx = p->m.vpx;
+            C.cvy = p->m.vpy;
+            C.cvz = p->m.vpz;
+            C.xc = x;
+            C.ctile_t = tiles_t;
+            C.xr = tr.cf;
+        }
+        launch_cf(C, s, &p->prof);
+    }
     if (ncFF > 0) {
-        PairJob Jf{PAIR_FWD_F, prec, ns, p->m.px + nv, p->m.py + nv, p->m.pz + nv, {}, p->F.count,
-                   p->F.x, p->F.y, p->F.z, {p->F.vx, p->F.vy, p->F.vz}, qF, p->F.count, 1, chFF, ncFF, k,
-                   pff, ns, SELF_IDENT, nullptr};
+        // every face a source in canonical order: streamed face j is target j
+        const bool ident = fo == 0 && nff == ns;
+        PairJob Jf{PAIR_FWD_F, prec, ns, p->m.px + nv, p->m.py + nv, p->m.pz + nv, {}, nff,
+                   p->F.x + fo, p->F.y + fo, p->F.z + fo, {p->F.vx + fo, p->F.vy + fo, p->F.vz + fo},
+                   static_cast<const char *>(qF) + csize(prec) * static_cast<size_t>(fo), p->F.count, 1, chFF, ncFF, k,
+                   pff, ns, ident ? SELF_IDENT : SELF_NONE, nullptr};
         launch_pairs(Jf, s, &p->prof);
     }
     launch_cf_reduce(n, nv, static_cast<int>(slots), psym, static_cast<int>(cs), pc, static_cast<int>(fs), pf, ncFF,
@@ -449,7 +506,7 @@ void apply_forward_cf(vsie_problem *p, int f, vsie_precision prec, const double2
 
 void apply_forward_sym(vsie_problem *p, int f, vsie_precision prec, const double2 *x, double2 *y,
                        hipStream_t s) {
-    if (p->tune.cell_face && p->f_is_faces) {
+    if (p->tune.cell_face) {
         apply_forward_cf(p, f, prec, x, y, s);
         return;
     }
@@ -493,7 +550,7 @@ bool use_sym(const vsie_problem *p, int nrhs) {
     if (nrhs != 1 || p->tune.sym_groups <= 0 || !p->g_is_cells) return false;
     const int64_t nv = p->m.n_vol, ns = p->m.n - nv;
     double bytes = static_cast<double>(sym_slots(nv, p->tune.sym_groups)) * nv;
-    if (p->tune.cell_face && p->f_is_faces)
+    if (p->tune.cell_face)
         bytes += static_cast<double>(cf_groups(ns)) * nv + static_cast<double>(cf_groups(nv)) * ns;
     return bytes * sizeof(double2) <= kSymPartialCap;
 }

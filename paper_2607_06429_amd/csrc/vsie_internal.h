@@ -187,7 +187,9 @@ void launch_pack_mfma(SrcClass cls, const SourceSet &src, const double *sp, int6
 // Single-layer sums among the cells with one evaluation per unordered pair,
 // one right-hand side (sym_kernels.hip).  The cells are the canonical points
 // 0 .. ng-1 and q their single-layer charges u = -s' x (complex, FP64 or FP32
-// per prec).  Cell p receives one partial per group of g 64-point tiles:
+// per prec).  With vx != null the same evaluations also add the cells'
+// adjoint double layer (v' per cell, zero where a cell has none; xv the
+// values x; tile_t[t] nonzero when tile t of 64 cells holds a nonzero v').  Cell p receives one partial per group of g 64-point tiles:
 // part[slot * ldp + p], slot = 0 .. sym_slots(ng, g) - 1.  Tiles are padded
 // with points at far + far_step * lane (farther than the mesh extent from
 // every point) and zero charge.
@@ -202,8 +204,18 @@ struct SymJob {
     int g;
     double2 *part;
     int64_t ldp;
+    const double *vx = nullptr, *vy = nullptr, *vz = nullptr;
+    const double2 *xv = nullptr;
+    const int32_t *tile_t = nullptr;
+    const int64_t *xr = nullptr;  // host: 9 item-range boundaries, one range per XCD (null: equal counts)
 };
 bool sym_groups_ok(int g);
+// Item ranges of the 8 XCDs (9 boundaries) with equal modelled work when the
+// items whose tiles hold grad-alpha cells (tile_t per 64-cell tile, host)
+// cost `weight` times the others: symmetric kernel (ng cells, group size g)
+// and cell-face kernel (nc cells, nf faces).
+void sym_cost_ranges(int64_t ng, int g, const std::vector<int32_t> &tile_t, double weight, int64_t *xr);
+void cf_cost_ranges(int64_t nc, int64_t nf, const std::vector<int32_t> &tile_t, double weight, int64_t *xr);
 int64_t sym_slots(int64_t ng, int g);
 void launch_sym(const SymJob &J, hipStream_t s, PairProfiler *prof);
 // y = diag x + (i < n_vol: sum of the n_slots symmetric partials; i >= n_vol:
@@ -215,8 +227,10 @@ void launch_sym_reduce(int64_t n, int64_t n_vol, int n_slots, const double2 *sym
 
 // Cell-face pairs with one evaluation per pair, one right-hand side
 // (sym_kernels.hip): cells are the points 0 .. nc-1, faces nc .. nc+nf-1; qc
-// the cells' single-layer charges, qf the faces' values (double-layer
-// charges), vx.. the faces' v'.  Cell c receives the faces' double layers in
+// the cells' single-layer charges, xf the faces' values, vx.. the faces' v'
+// (zero where a face has no weight).  With cvx != null the cells' adjoint
+// double layer at the faces is added (cvx.. the cells' v', xc their values,
+// ctile_t as SymJob::tile_t).  Cell c receives the faces' double layers in
 // pc[slot * nc + c] (one slot per group of kCfGroup face tiles), face f the
 // cells' single layers in pf[slot * nf + f] (one slot per group of cell tiles).
 constexpr int kCfGroup = 2;
@@ -225,11 +239,16 @@ struct CfJob {
     int64_t nc, nf;
     const double *px, *py, *pz;
     const double *vx, *vy, *vz;
-    const void *qc, *qf;
+    const void *qc;
+    const double2 *xf;
     double k;
     double far[3];
     double far_step;
     double2 *pc, *pf;
+    const double *cvx = nullptr, *cvy = nullptr, *cvz = nullptr;
+    const double2 *xc = nullptr;
+    const int32_t *ctile_t = nullptr;
+    const int64_t *xr = nullptr;  // as SymJob::xr
 };
 int64_t cf_groups(int64_t count);  // slots for count cells or faces
 void launch_cf(const CfJob &J, hipStream_t s, PairProfiler *prof);

@@ -102,12 +102,13 @@ def kernels(asm: str):
         cls, tg, nb, m3 = re.search(r"kernelILi(\d)ELi(\d)ELi(\d)ELb(\d)E", nm).groups()
         yield nm, "mfma_%s_fp32_tg%s_nb%s%s" % (MODES[int(cls)], tg, nb, "_3m" if m3 == "1" else ""), 16 * int(nb)
     for nm in re.findall(r"^(_Z\w+sym_kernel\w+):", asm, re.M):
-        g, acc = re.search(r"sym_kernelILi(\d)E(\w)E", nm).groups()
+        g, acc, t = re.search(r"sym_kernelILi(\d)E(\w)Lb(\d)E", nm).groups()
         if g == "4":   # the default group size; the inner loop is the same for every size
-            yield nm, "sym_single_layer_%s_R1" % ("fp64" if acc == "d" else "fp32"), 1
+            # T variant: the loop of the items with grad-alpha cells (the most instructions per pair)
+            yield nm, "sym_single_layer%s_%s_R1" % ("_t" if t == "1" else "", "fp64" if acc == "d" else "fp32"), 1
     for nm in re.findall(r"^(_Z\w+cf_kernel\w+):", asm, re.M):
-        acc = re.search(r"cf_kernelILi\d+E(\w)E", nm).group(1)
-        yield nm, "cell_face_%s_R1" % ("fp64" if acc == "d" else "fp32"), 1
+        acc, t = re.search(r"cf_kernelILi\d+E(\w)Lb(\d)E", nm).groups()
+        yield nm, "cell_face%s_%s_R1" % ("_t" if t == "1" else "", "fp64" if acc == "d" else "fp32"), 1
 
 
 def count(asm: str) -> dict:
@@ -127,8 +128,13 @@ def count(asm: str) -> dict:
                 continue
             if sym:
                 # the tile-pair loop (source side carried along: the most DPP moves per pair),
-                # not the 63-step loop of a tile with itself; among equals, the shortest copy
-                rank = (sum(1 for x in body if "_dpp" in x.split()[0]) / nrsq, nrsq, -len(body))
+                # not the 63-step loop of a tile with itself; among equals the shortest copy,
+                # in a T variant the longest (the loop that adds the adjoint double layer)
+                dpp = sum(1 for x in body if "_dpp" in x.split()[0]) / nrsq
+                if "_t_" in key:
+                    rank = (dpp > 0, len(body) / nrsq)
+                else:
+                    rank = (dpp, nrsq, -len(body))
                 if best is None or rank > best[2]:
                     best = (nrsq, body, rank)
                 continue

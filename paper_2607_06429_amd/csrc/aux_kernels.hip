@@ -381,7 +381,9 @@ __global__ void bnorm_final_kernel(int nslots, const double *__restrict__ partia
 // order, as bdots_final_kernel) into LDS, block 0 of the slot also stores them
 // in h for the host, then W[sl] -= sum_j V(j, act[sl]) h_j.  k <= kFusedMaxK.
 constexpr int kFusedMaxK = 1024;
-// one workgroup per live right-hand side (see bblas_deflate_coef)
+// one workgroup per live right-hand side (see bblas_deflate_coef); the
+// projections are staged in LDS in chunks and each thread's column loop is
+// unrolled so that its loads of P and M are in flight together
 __global__ __launch_bounds__(kT) void bdeflate_coef_kernel(const int32_t *__restrict__ slot,
                                                            const int32_t *__restrict__ kcount, int cs,
                                                            const double2 *__restrict__ P,
@@ -389,29 +391,43 @@ __global__ __launch_bounds__(kT) void bdeflate_coef_kernel(const int32_t *__rest
                                                            const double2 *__restrict__ tc, double2 *__restrict__ hc,
                                                            double2 *__restrict__ B, int col, int kb,
                                                            int64_t bstride) {
+    constexpr int kChunk = 512;
+    __shared__ double2 tl[kChunk];
     const int l = blockIdx.x;
     const int sl = slot[l];
     const int kc = kcount[sl];
     const double2 *t = tc + static_cast<int64_t>(l) * cs;
     const double2 *Ps = P + static_cast<int64_t>(sl) * cs * cs;
     const double2 *Ms = M + static_cast<int64_t>(sl) * cs * cs;
-    for (int i = threadIdx.x; i < cs; i += kT) {
+    // rows i = threadIdx.x + q kT, at most ceil(cs / kT) per thread
+    const int rows = (cs + kT - 1) / kT;
+    for (int q = 0; q < rows; ++q) {
+        const int i = threadIdx.x + q * kT;
         double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
-        for (int j = 0; j < kc; ++j) {
-            const double2 tj = t[j];
-            const double2 pv = Ps[static_cast<int64_t>(j) * cs + i];
-            ar += pv.x * tj.x - pv.y * tj.y;
-            ai += pv.x * tj.y + pv.y * tj.x;
-            if (i + 1 < kc) {
-                const double2 mv = Ms[static_cast<int64_t>(j) * cs + i];
-                br += mv.x * tj.x - mv.y * tj.y;
-                bi += mv.x * tj.y + mv.y * tj.x;
+        for (int j0 = 0; j0 < kc; j0 += kChunk) {
+            const int j1 = j0 + kChunk < kc ? j0 + kChunk : kc;
+            __syncthreads();
+            for (int j = j0 + threadIdx.x; j < j1; j += kT) tl[j - j0] = t[j];
+            __syncthreads();
+            if (i < cs) {
+#pragma unroll 8
+                for (int j = j0; j < j1; ++j) {
+                    const double2 tj = tl[j - j0];
+                    const double2 pv = Ps[static_cast<int64_t>(j) * cs + i];
+                    const double2 mv = Ms[static_cast<int64_t>(j) * cs + i];
+                    ar += pv.x * tj.x - pv.y * tj.y;
+                    ai += pv.x * tj.y + pv.y * tj.x;
+                    br += mv.x * tj.x - mv.y * tj.y;
+                    bi += mv.x * tj.y + mv.y * tj.x;
+                }
             }
         }
-        hc[static_cast<int64_t>(l) * cs + i] = i < kc ? make_double2(ar, ai) : make_double2(0.0, 0.0);
-        if (i + 1 < kc) {
-            double2 *b = B + static_cast<int64_t>(sl) * bstride + static_cast<int64_t>(col) * kb + i;
-            *b = make_double2(b->x + br, b->y + bi);
+        if (i < cs) {
+            hc[static_cast<int64_t>(l) * cs + i] = i < kc ? make_double2(ar, ai) : make_double2(0.0, 0.0);
+            if (i + 1 < kc) {
+                double2 *b = B + static_cast<int64_t>(sl) * bstride + static_cast<int64_t>(col) * kb + i;
+                *b = make_double2(b->x + br, b->y + bi);
+            }
         }
     }
 }

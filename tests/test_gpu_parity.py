@@ -389,6 +389,16 @@ def test_graph_replay_solve(V, prec):
         say("  replay %d: eager %.1f ms, graph %.1f ms" % (rep, te * 1e3, (time.perf_counter() - t0) * 1e3))
         assert i1 == i0 and j1 == j0
         assert torch.equal(x1, x0) and torch.equal(a1, a0)
+    # one column: the once-per-pair kernels with the cells' adjoint double
+    # layers (every cell has grad alpha here), captured and replayed
+    b1 = b[0].contiguous()
+    P.set_tuning(graph=0)
+    s0, l0 = P.solve(b1, prec=pr, tol=1e-11)
+    P.set_tuning(graph=1)
+    for rep in range(3):
+        s1, l1 = P.solve(b1, prec=pr, tol=1e-11)
+        assert l1 == l0 and torch.equal(s1, s0)
+    assert O.rel_error(host(s1), O.solve_lu(d, host(b1))) <= TOL_SOLVE
     # new materials: graphs captured for the old sources must not be replayed
     mat2 = W.materials_piecewise(mesh, 1.0, 1.0, 1.3, 1.4, 1.9, 0.9)
     P.set_materials(torch.as_tensor(mat2.vol_rho, device="cuda"), torch.as_tensor(mat2.vol_c, device="cuda"))

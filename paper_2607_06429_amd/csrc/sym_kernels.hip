@@ -368,10 +368,14 @@ struct SlotList {
 // the w-th quarter of the slots, and the four quarter sums are added in wave
 // order, so the order of the additions is fixed.  Four waves per 64 points
 // keep enough loads in flight to stream the partials at HBM speed.
+// The adjoint variant writes y = conj(diag) x + conj(w sum) with w = -s'_i
+// (sp) for cells and 1 for faces.
+template <bool ADJ>
 __global__ __launch_bounds__(kBlock) void slot_reduce_kernel(int64_t n, int64_t nc, int64_t cell_blocks,
                                                              SlotList cells, SlotList faces,
                                                              const double2 *__restrict__ diag,
-                                                             const double2 *__restrict__ x, double2 *__restrict__ y) {
+                                                             const double2 *__restrict__ x, double2 *__restrict__ y,
+                                                             const double *__restrict__ sp) {
     __shared__ double2 red[kWavesPerBlock][64];
     const int lane = threadIdx.x & 63;
     const int w = static_cast<int>(threadIdx.x) >> 6;
@@ -407,7 +411,12 @@ __global__ __launch_bounds__(kBlock) void slot_reduce_kernel(int64_t n, int64_t 
         }
         const int64_t i = cell ? p : nc + p;
         const double2 d = diag[i], xv = x[i];
-        y[i] = make_double2(d.x * xv.x - d.y * xv.y + sr, d.x * xv.y + d.y * xv.x + si);
+        if constexpr (ADJ) {
+            const double w = cell ? -sp[i] : 1.0;
+            y[i] = make_double2(d.x * xv.x + d.y * xv.y + w * sr, d.x * xv.y - d.y * xv.x - w * si);
+        } else {
+            y[i] = make_double2(d.x * xv.x - d.y * xv.y + sr, d.x * xv.y + d.y * xv.x + si);
+        }
     }
 }
 
@@ -420,6 +429,11 @@ __global__ __launch_bounds__(kBlock) void slot_reduce_kernel(int64_t n, int64_t 
 // and, with cells that carry grad alpha (T variant, items whose cell group
 // holds one), the cell's adjoint double layer at the face:
 //   y_f += e (i k r - 1) q' x_c,  q' = (y_f - x_c).v'_c / r^2
+// The adjoint variant (charges mu = conj(lambda), no grad-alpha cells) sums
+// the transposed terms of the same pairs: the single layer at the cell with
+// the face's charge (scaled by the cell's -s' afterwards) and the face's
+// double layer with the cell's charge:
+//   z_c += e mu_f,                z_f += e (i k r - 1) q mu_c
 // Lanes hold cells (tile A); the face tile B (positions, v', values) sits in
 // the wave's LDS slice and the faces' single-layer sums rotate by DPP, as in
 // sym_kernel.  Work items are (cell group I, face group J), every pair of
@@ -435,6 +449,7 @@ struct CfArgs {
     const double *__restrict__ vz;
     const void *__restrict__ qc;     // single-layer charges of the cells, complex AT
     const double2 *__restrict__ xf;  // values of the faces
+    const void *__restrict__ qfa;    // adjoint: charges conj(lambda) of the faces, complex AT
     // T variant: v' of the cells, their values, and per 64-cell tile whether any v' is nonzero
     const double *__restrict__ cvx;
     const double *__restrict__ cvy;
@@ -455,8 +470,9 @@ struct CfArgs {
     int64_t ldf;
 };
 
-template <int G, typename AT, bool T>
+template <int G, typename AT, bool T, bool ADJ>
 __global__ __launch_bounds__(kBlock) void cf_kernel(CfArgs a) {
+    static_assert(!(T && ADJ), "the adjoint variant has no grad-alpha cells");
     using C2 = typename c2_of<AT>::type;
     struct FTile {
         double x[128], y[128], z[128], vx[128], vy[128], vz[128];
@@ -531,9 +547,13 @@ __global__ __launch_bounds__(kBlock) void cf_kernel(CfArgs a) {
                         wx = a.vx[f];
                         wy = a.vy[f];
                         wz = a.vz[f];
-                        const double2 xv = a.xf[f];
-                        u.x = static_cast<AT>(xv.x);
-                        u.y = static_cast<AT>(xv.y);
+                        if constexpr (ADJ) {
+                            u = static_cast<const C2 *>(a.qfa)[f];
+                        } else {
+                            const double2 xv = a.xf[f];
+                            u.x = static_cast<AT>(xv.x);
+                            u.y = static_cast<AT>(xv.y);
+                        }
                     } else {
                         // padding faces: far points apart from the padding cells, v' = 0, value 0
                         xb = a.far[0] + a.far_step * (lane + 64);
@@ -577,6 +597,26 @@ __global__ __launch_bounds__(kBlock) void cf_kernel(CfArgs a) {
                         }
                         done = true;
                     }
+                }
+                if constexpr (ADJ) {
+                    for (int st = 0; st < 64; ++st) {
+                        const int j = lane + 64 - st;
+                        const double dx = xa - B.x[j], dy = ya - B.y[j], dz = za - B.z[j];
+                        AT er, ei, ir2, kr;
+                        if constexpr (sizeof(AT) == 4) geom_f32<false>(dx, dy, dz, kk, a.kphase, er, ei, ir2, kr);
+                        else geom_f64<false>(dx, dy, dz, a.k, a.kphase, er, ei, ir2, kr);
+                        // single layer at the cell, with the face's charge
+                        const C2 u = B.u[j];
+                        sAr = fma(er, u.x, fma(-ei, u.y, sAr));
+                        sAi = fma(er, u.y, fma(ei, u.x, sAi));
+                        // the face's double layer, with the cell's charge
+                        const AT qq = static_cast<AT>(fma(dx, B.vx[j], fma(dy, B.vy[j], dz * B.vz[j]))) * ir2;
+                        const AT cr = qq * fma(-ei, kr, -er);
+                        const AT ci = qq * fma(er, kr, -ei);
+                        sBr = rot1(fma(cr, uar, fma(-ci, uai, sBr)));
+                        sBi = rot1(fma(cr, uai, fma(ci, uar, sBi)));
+                    }
+                    done = true;
                 }
                 for (int st = 0; st < (done ? 0 : 64); ++st) {
                     // face (lane - st) mod 64; its single-layer sum has moved st lanes up
@@ -635,12 +675,17 @@ const void *pick_sym(int g, bool f32, bool t) {
 }
 
 void launch_slot_reduce(int64_t n, int64_t nc, const SlotList &cells, const SlotList &faces,
-                        const double2 *diag, const double2 *x, double2 *y, hipStream_t s) {
+                        const double2 *diag, const double2 *x, double2 *y, hipStream_t s,
+                        const double *adj_sp = nullptr) {
     const int64_t cell_blocks = (nc + 63) / 64, face_blocks = (n - nc + 63) / 64;
     const int64_t blocks = cell_blocks + face_blocks;
     if (blocks > 0x7fffffff) fail(VSIE_E_INVALID, "slot reduction: too many points");
-    hipLaunchKernelGGL(slot_reduce_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, n, nc,
-                       cell_blocks, cells, faces, diag, x, y);
+    if (adj_sp)
+        hipLaunchKernelGGL(slot_reduce_kernel<true>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, n, nc,
+                           cell_blocks, cells, faces, diag, x, y, adj_sp);
+    else
+        hipLaunchKernelGGL(slot_reduce_kernel<false>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, n, nc,
+                           cell_blocks, cells, faces, diag, x, y, adj_sp);
     VSIE_HIP(hipGetLastError());
 }
 
@@ -806,6 +851,7 @@ void launch_cf(const CfJob &J, hipStream_t s, PairProfiler *prof) {
     a.vz = J.vz;
     a.qc = J.qc;
     a.xf = J.xf;
+    a.qfa = J.qfa;
     a.cvx = J.cvx;
     a.cvy = J.cvy;
     a.cvz = J.cvz;
@@ -834,11 +880,16 @@ void launch_cf(const CfJob &J, hipStream_t s, PairProfiler *prof) {
     a.ldf = J.nf;
     const bool t = J.cvx != nullptr;
     if (t && !(J.cvy && J.cvz && J.xc && J.ctile_t)) fail(VSIE_E_INVALID, "cell-face kernel: incomplete T data");
-    if (!J.xf || !J.vx || !J.vy || !J.vz) fail(VSIE_E_INVALID, "cell-face kernel: missing face data");
-    const void *kp = f32 ? (t ? reinterpret_cast<const void *>(&cf_kernel<kCfGroup, float, true>)
-                              : reinterpret_cast<const void *>(&cf_kernel<kCfGroup, float, false>))
-                         : (t ? reinterpret_cast<const void *>(&cf_kernel<kCfGroup, double, true>)
-                              : reinterpret_cast<const void *>(&cf_kernel<kCfGroup, double, false>));
+    if (t && J.adj) fail(VSIE_E_INVALID, "cell-face kernel: no adjoint variant with grad-alpha cells");
+    if (!(J.adj ? J.qfa != nullptr : J.xf != nullptr) || !J.vx || !J.vy || !J.vz)
+        fail(VSIE_E_INVALID, "cell-face kernel: missing face data");
+    const void *kp = nullptr;
+    if (J.adj) kp = f32 ? reinterpret_cast<const void *>(&cf_kernel<kCfGroup, float, false, true>)
+                        : reinterpret_cast<const void *>(&cf_kernel<kCfGroup, double, false, true>);
+    else if (t) kp = f32 ? reinterpret_cast<const void *>(&cf_kernel<kCfGroup, float, true, false>)
+                         : reinterpret_cast<const void *>(&cf_kernel<kCfGroup, double, true, false>);
+    else kp = f32 ? reinterpret_cast<const void *>(&cf_kernel<kCfGroup, float, false, false>)
+                  : reinterpret_cast<const void *>(&cf_kernel<kCfGroup, double, false, false>);
     const int64_t grid = ranges_grid(a.xr);
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (prof && prof->on) {
@@ -860,12 +911,12 @@ void launch_cf(const CfJob &J, hipStream_t s, PairProfiler *prof) {
 // slots + face-face chunk partials); one right-hand side
 void launch_cf_reduce(int64_t n, int64_t nc, int n_sym, const double2 *sym, int n_cs, const double2 *pc, int n_fs,
                       const double2 *pf, int n_ff, const double2 *ff, const double2 *diag, const double2 *x,
-                      double2 *y, hipStream_t s) {
+                      double2 *y, hipStream_t s, const double *adj_sp) {
     if (n == 0) return;
     const int64_t nf = n - nc;
     const SlotList cells{sym, n_sym, nc, 0, pc, n_cs, nc, 0};
     const SlotList faces{pf, n_fs, nf, 0, ff, n_ff, nf, 0};
-    launch_slot_reduce(n, nc, cells, faces, diag, x, y, s);
+    launch_slot_reduce(n, nc, cells, faces, diag, x, y, s, adj_sp);
 }
 
 }  // namespace vsie

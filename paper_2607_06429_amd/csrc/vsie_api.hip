@@ -604,8 +604,58 @@ void apply_adjoint_block(vsie_problem *p, int f, vsie_precision prec, int nrhs, 
     }
 }
 
+// One-column adjoint with the once-per-pair kernels, when every cell is a
+// single-layer source and the double-layer sources are exactly the faces.
+// With mu = conj(lambda): (A^H lambda)_j = conj(d_j) lambda_j + conj(w_j S_j),
+// w_j = -s'_j for cells and 1 for faces, where a cell's S_j sums e_ij mu_i over
+// the other cells (the symmetric kernel with charges mu) and the faces (the
+// cell-face kernel's adjoint variant), and a face's S_j sums its double layer
+// e (i k r - 1) (x_i - y_j).v'_j / r^2 mu_i over the cells (same kernel) and
+// the faces (one-sided).
+bool adjoint_sym_ok(const vsie_problem *p, int nrhs) {
+    return use_sym(p, nrhs) && p->tune.cell_face && p->f_is_faces;
+}
+
+void apply_adjoint_sym(vsie_problem *p, int f, vsie_precision prec, const double2 *x, double2 *y, hipStream_t s) {
+    const int64_t n = p->m.n, nv = p->m.n_vol, ns = n - nv;
+    const int g = p->tune.sym_groups;
+    const int64_t slots = sym_slots(nv, g), cs = cf_groups(ns), fs = cf_groups(nv);
+    int64_t chFF = 1;
+    int ncFF = 0;
+    if (ns > 0) choose_chunks(ns, ns, p->tune.vec_target_waves, chFF, ncFF);
+    const size_t total = static_cast<size_t>(slots * nv + cs * nv + fs * ns + static_cast<int64_t>(ncFF) * ns);
+    double2 *part = static_cast<double2 *>(p->partial.get(sizeof(double2) * std::max<size_t>(1, total)));
+    double2 *psym = part, *pc = psym + slots * nv, *pf = pc + cs * nv, *pff = pf + fs * ns;
+    void *q = p->chargeAll.get(csize(prec) * static_cast<size_t>(n));
+    launch_pack_plain(prec, n, 1, x, n, true, q, s);
+    const void *qf = static_cast<const char *>(q) + csize(prec) * static_cast<size_t>(nv);
+    const double k = p->k0[f];
+    SymJob J{prec, nv, p->m.px, p->m.py, p->m.pz, q, k, {p->far[0], p->far[1], p->far[2]}, p->far_step, g, psym, nv};
+    launch_sym(J, s, &p->prof);
+    if (ns > 0) {
+        CfJob C{prec, nv, ns, p->m.px, p->m.py, p->m.pz, p->m.vpx + nv, p->m.vpy + nv, p->m.vpz + nv, q, nullptr, k,
+                {p->far[0], p->far[1], p->far[2]}, p->far_step, pc, pf};
+        C.adj = true;
+        C.qfa = qf;
+        launch_cf(C, s, &p->prof);
+    }
+    if (ncFF > 0) {
+        // faces (thread points, with v') over the faces (streamed, charges mu)
+        PairJob Jf{PAIR_ADJ_F, prec, ns, p->m.px + nv, p->m.py + nv, p->m.pz + nv,
+                   {p->m.vpx + nv, p->m.vpy + nv, p->m.vpz + nv}, ns, p->m.px + nv, p->m.py + nv, p->m.pz + nv, {},
+                   qf, ns, 1, chFF, ncFF, k, pff, ns, SELF_IDENT, nullptr};
+        launch_pairs(Jf, s, &p->prof);
+    }
+    launch_cf_reduce(n, nv, static_cast<int>(slots), psym, static_cast<int>(cs), pc, static_cast<int>(fs), pf, ncFF,
+                     pff, p->m.diag + static_cast<int64_t>(f) * n, x, y, s, p->m.sp + static_cast<int64_t>(f) * n);
+}
+
 void apply_adjoint(vsie_problem *p, int f, vsie_precision prec, int nrhs, const double2 *x,
                    int64_t ldx, double2 *y, int64_t ldy, hipStream_t s) {
+    if (nrhs == 1 && adjoint_sym_ok(p, nrhs)) {
+        apply_adjoint_sym(p, f, prec, x, y, s);
+        return;
+    }
     for (int r0 = 0; r0 < nrhs; r0 += kMaxRhsPerLaunch) {
         const int blk = std::min(kMaxRhsPerLaunch, nrhs - r0);
         apply_adjoint_block(p, f, prec, blk, x + static_cast<int64_t>(r0) * ldx, ldx,

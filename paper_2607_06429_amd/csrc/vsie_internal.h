@@ -249,14 +249,21 @@ struct CfJob {
     const double2 *xc = nullptr;
     const int32_t *ctile_t = nullptr;
     const int64_t *xr = nullptr;  // as SymJob::xr
+    // adjoint (no grad-alpha cells): qc holds the cells' conj(lambda), qfa the
+    // faces' (complex, per prec); cells receive sum e mu_f, faces the face
+    // double layer with mu_c
+    bool adj = false;
+    const void *qfa = nullptr;
 };
 int64_t cf_groups(int64_t count);  // slots for count cells or faces
 void launch_cf(const CfJob &J, hipStream_t s, PairProfiler *prof);
 // y = diag x + (i < nc: n_sym symmetric slots + n_cs cell slots of pc;
-// i >= nc: n_fs face slots of pf + n_ff face-face chunk partials ff[c * nf + i - nc])
+// i >= nc: n_fs face slots of pf + n_ff face-face chunk partials ff[c * nf + i - nc]);
+// with adj_sp (the frequency's s' of all points): y = conj(diag) x + conj(w sum),
+// w = -s'_i for cells and 1 for faces
 void launch_cf_reduce(int64_t n, int64_t nc, int n_sym, const double2 *sym, int n_cs, const double2 *pc, int n_fs,
                       const double2 *pf, int n_ff, const double2 *ff, const double2 *diag, const double2 *x,
-                      double2 *y, hipStream_t s);
+                      double2 *y, hipStream_t s, const double *adj_sp = nullptr);
 
 // auxiliary kernels (aux_kernels.hip)
 void launch_weights(const DeviceMesh &m, const double *k0, int n_freq, hipStream_t s);

@@ -107,8 +107,9 @@ def kernels(asm: str):
             # T variant: the loop of the items with grad-alpha cells (the most instructions per pair)
             yield nm, "sym_single_layer%s_%s_R1" % ("_t" if t == "1" else "", "fp64" if acc == "d" else "fp32"), 1
     for nm in re.findall(r"^(_Z\w+cf_kernel\w+):", asm, re.M):
-        acc, t = re.search(r"cf_kernelILi\d+E(\w)Lb(\d)E", nm).groups()
-        yield nm, "cell_face%s_%s_R1" % ("_t" if t == "1" else "", "fp64" if acc == "d" else "fp32"), 1
+        acc, t, adj = re.search(r"cf_kernelILi\d+E(\w)Lb(\d)ELb(\d)E", nm).groups()
+        tag = "_t" if t == "1" else "_adj" if adj == "1" else ""
+        yield nm, "cell_face%s_%s_R1" % (tag, "fp64" if acc == "d" else "fp32"), 1
 
 
 def count(asm: str) -> dict:

@@ -33,6 +33,11 @@
 //   y_i += F (d.v'_j) x_j   and   y_j += F (-d.v'_i) x_i,   d = x_i - x_j.
 // Items whose tiles hold no such cell run the single-layer loop alone.
 //
+// The adjoint variant (with T) takes charges mu = conj(lambda) and puts the
+// weights on the target side, (A^H)_ji = conj(A_ij):
+//   z_i += (-s'_i e + F (-d.v'_i)) mu_j   and   z_j += (-s'_j e + F (d.v'_j)) mu_i;
+// items without grad-alpha cells sum e mu and scale by -s' per tile pair.
+//
 // Schedule: items cut into 8 contiguous ranges (one per XCD, workgroup b
 // runs on XCD b mod 8), one item per wave, so that the hardware dispatcher
 // balances the load within an XCD.  The ranges hold equal modelled work: an
@@ -92,6 +97,7 @@ struct SymArgs {
     const double *__restrict__ vz;
     const double2 *__restrict__ xv;
     const int32_t *__restrict__ tile_t;
+    const double *__restrict__ sw;  // adjoint variant: s' of the cells for this frequency
 };
 
 // position and charge of point p of a tile (padding lanes: distinct far points, zero charge)
@@ -157,8 +163,9 @@ __device__ __forceinline__ AT dot_v(AT dxa, AT dya, AT dza, AT v0, AT v1, AT v2)
     return fma(dxa, v0, fma(dya, v1, dza * v2));
 }
 
-template <int G, typename AT, bool T>
+template <int G, typename AT, bool T, bool ADJ>
 __global__ __launch_bounds__(kBlock) void sym_kernel(SymArgs a) {
+    static_assert(T || !ADJ, "the adjoint variant of the symmetric kernel is the grad-alpha one");
     using C2 = typename c2_of<AT>::type;
     // per-wave copies of the B tile, stored twice in a row (entries 0..127) so
     // that step st reads entry lane + 64 - st without wrapping; one block per
@@ -172,6 +179,7 @@ __global__ __launch_bounds__(kBlock) void sym_kernel(SymArgs a) {
         C2 u[128];
         AT vx[128], vy[128], vz[128];
         C2 w[128];
+        AT s[128];  // adjoint: -s' of the B points
     };
     using BTile = typename std::conditional<T, BTileT, BTileS>::type;
     __shared__ BTile lb[kWavesPerBlock];
@@ -219,6 +227,11 @@ __global__ __launch_bounds__(kBlock) void sym_kernel(SymArgs a) {
             if constexpr (T) {
                 if (item_t) load_t<AT>(a.vx, a.vy, a.vz, a.xv, static_cast<int64_t>(at) * 64 + lane, a.ng, va0, va1, va2, war, wai);
             }
+            AT sa = 0;
+            if constexpr (ADJ) {
+                const int64_t pa = static_cast<int64_t>(at) * 64 + lane;
+                sa = pa < a.ng ? -static_cast<AT>(a.sw[pa]) : AT(0);
+            }
             for (int tb = (I == J) ? ta : 0; tb < G; ++tb) {
                 const int bt = J * G + tb;
                 if (bt >= a.tiles) break;
@@ -245,11 +258,54 @@ __global__ __launch_bounds__(kBlock) void sym_kernel(SymArgs a) {
                             B.vz[lane] = B.vz[lane + 64] = v2;
                             B.w[lane] = B.w[lane + 64] = w;
                         }
+                        if constexpr (ADJ) {
+                            const int64_t pb = static_cast<int64_t>(bt) * 64 + lane;
+                            B.s[lane] = B.s[lane + 64] = pb < a.ng ? -static_cast<AT>(a.sw[pb]) : AT(0);
+                        }
                     }
                 }
                 AT sAr = 0, sAi = 0, sBr = 0, sBi = 0;
                 bool done = false;
-                if constexpr (T) {
+                if constexpr (ADJ) {
+                    if (item_t) {
+                        // weights on the target side, charges mu
+                        if (at == bt) {
+                            for (int st = 1; st < 64; ++st) {
+                                const int j = lane + 64 - st;
+                                const double dx = xa - B.x[j], dy = ya - B.y[j], dz = za - B.z[j];
+                                AT er, ei, fr, fi;
+                                pair_ef<AT>(dx, dy, dz, a, kk, er, ei, fr, fi);
+                                const AT qa = dot_v<AT>(static_cast<AT>(dx), static_cast<AT>(dy), static_cast<AT>(dz),
+                                                        va0, va1, va2);
+                                const AT car = fma(sa, er, -qa * fr), cai = fma(sa, ei, -qa * fi);
+                                const C2 u = B.u[j];
+                                sAr = fma(car, u.x, fma(-cai, u.y, sAr));
+                                sAi = fma(car, u.y, fma(cai, u.x, sAi));
+                            }
+                        } else {
+                            for (int st = 0; st < 64; ++st) {
+                                const int j = lane + 64 - st;
+                                const double dx = xa - B.x[j], dy = ya - B.y[j], dz = za - B.z[j];
+                                AT er, ei, fr, fi;
+                                pair_ef<AT>(dx, dy, dz, a, kk, er, ei, fr, fi);
+                                const AT dxa = static_cast<AT>(dx), dya = static_cast<AT>(dy), dza = static_cast<AT>(dz);
+                                // target a: (-s'_a e - F d.v'_a) mu_b
+                                const AT qa = dot_v<AT>(dxa, dya, dza, va0, va1, va2);
+                                const AT car = fma(sa, er, -qa * fr), cai = fma(sa, ei, -qa * fi);
+                                const C2 u = B.u[j];
+                                sAr = fma(car, u.x, fma(-cai, u.y, sAr));
+                                sAi = fma(car, u.y, fma(cai, u.x, sAi));
+                                // target b: (-s'_b e + F d.v'_b) mu_a
+                                const AT qb = dot_v<AT>(dxa, dya, dza, B.vx[j], B.vy[j], B.vz[j]);
+                                const AT sb = B.s[j];
+                                const AT cbr = fma(sb, er, qb * fr), cbi = fma(sb, ei, qb * fi);
+                                sBr = rot1(fma(cbr, uar, fma(-cbi, uai, sBr)));
+                                sBi = rot1(fma(cbr, uai, fma(cbi, uar, sBi)));
+                            }
+                        }
+                        done = true;
+                    }
+                } else if constexpr (T) {
                     if (item_t) {
                         // single layer and adjoint double layer together
                         if (at == bt) {
@@ -314,6 +370,16 @@ __global__ __launch_bounds__(kBlock) void sym_kernel(SymArgs a) {
                         sBi = rot1(fma(er, uai, fma(ei, uar, sBi)));
                     }
                     // 64 rotations: every B point's sum is back in its home lane
+                }
+                if constexpr (ADJ) {
+                    if (!item_t) {
+                        // single layer alone: the targets' weights after the sums
+                        sAr *= sa;
+                        sAi *= sa;
+                        const AT sbh = B.s[lane];
+                        sBr *= sbh;
+                        sBi *= sbh;
+                    }
                 }
                 // tile-indexed accumulators with compile-time register indices
 #pragma unroll
@@ -412,7 +478,7 @@ __global__ __launch_bounds__(kBlock) void slot_reduce_kernel(int64_t n, int64_t 
         const int64_t i = cell ? p : nc + p;
         const double2 d = diag[i], xv = x[i];
         if constexpr (ADJ) {
-            const double w = cell ? -sp[i] : 1.0;
+            const double w = (cell && sp) ? -sp[i] : 1.0;
             y[i] = make_double2(d.x * xv.x + d.y * xv.y + w * sr, d.x * xv.y - d.y * xv.x - w * si);
         } else {
             y[i] = make_double2(d.x * xv.x - d.y * xv.y + sr, d.x * xv.y + d.y * xv.x + si);
@@ -429,11 +495,13 @@ __global__ __launch_bounds__(kBlock) void slot_reduce_kernel(int64_t n, int64_t 
 // and, with cells that carry grad alpha (T variant, items whose cell group
 // holds one), the cell's adjoint double layer at the face:
 //   y_f += e (i k r - 1) q' x_c,  q' = (y_f - x_c).v'_c / r^2
-// The adjoint variant (charges mu = conj(lambda), no grad-alpha cells) sums
-// the transposed terms of the same pairs: the single layer at the cell with
-// the face's charge (scaled by the cell's -s' afterwards) and the face's
-// double layer with the cell's charge:
+// The adjoint variant (charges mu = conj(lambda)) sums the transposed terms
+// of the same pairs: the single layer at the cell with the face's charge
+// (scaled by the cell's -s' afterwards) and the face's double layer with the
+// cell's charge:
 //   z_c += e mu_f,                z_f += e (i k r - 1) q mu_c
+// With grad-alpha cells the cell's weights enter in the kernel:
+//   z_c += (-s'_c e + e (i k r - 1) (y_f - x_c).v'_c / r^2) mu_f
 // Lanes hold cells (tile A); the face tile B (positions, v', values) sits in
 // the wave's LDS slice and the faces' single-layer sums rotate by DPP, as in
 // sym_kernel.  Work items are (cell group I, face group J), every pair of
@@ -450,6 +518,7 @@ struct CfArgs {
     const void *__restrict__ qc;     // single-layer charges of the cells, complex AT
     const double2 *__restrict__ xf;  // values of the faces
     const void *__restrict__ qfa;    // adjoint: charges conj(lambda) of the faces, complex AT
+    const double *__restrict__ sw;   // adjoint with grad-alpha cells: s' of the cells (weights in the kernel)
     // T variant: v' of the cells, their values, and per 64-cell tile whether any v' is nonzero
     const double *__restrict__ cvx;
     const double *__restrict__ cvy;
@@ -472,7 +541,7 @@ struct CfArgs {
 
 template <int G, typename AT, bool T, bool ADJ>
 __global__ __launch_bounds__(kBlock) void cf_kernel(CfArgs a) {
-    static_assert(!(T && ADJ), "the adjoint variant has no grad-alpha cells");
+
     using C2 = typename c2_of<AT>::type;
     struct FTile {
         double x[128], y[128], z[128], vx[128], vy[128], vz[128];
@@ -523,6 +592,10 @@ __global__ __launch_bounds__(kBlock) void cf_kernel(CfArgs a) {
             }
             double va0 = 0, va1 = 0, va2 = 0;
             AT war = 0, wai = 0;
+            AT sa = 0;
+            if constexpr (T && ADJ) {
+                if (c < a.nc) sa = -static_cast<AT>(a.sw[c]);
+            }
             if constexpr (T) {
                 if (item_t && c < a.nc) {
                     va0 = a.cvx[c];
@@ -572,7 +645,31 @@ __global__ __launch_bounds__(kBlock) void cf_kernel(CfArgs a) {
                 }
                 AT sAr = 0, sAi = 0, sBr = 0, sBi = 0;
                 bool done = false;
-                if constexpr (T) {
+                if constexpr (T && ADJ) {
+                    if (item_t) {
+                        for (int st = 0; st < 64; ++st) {
+                            const int j = lane + 64 - st;
+                            const double dx = xa - B.x[j], dy = ya - B.y[j], dz = za - B.z[j];
+                            AT er, ei, ir2, kr;
+                            if constexpr (sizeof(AT) == 4) geom_f32<false>(dx, dy, dz, kk, a.kphase, er, ei, ir2, kr);
+                            else geom_f64<false>(dx, dy, dz, a.k, a.kphase, er, ei, ir2, kr);
+                            const AT fr = ir2 * fma(-ei, kr, -er);
+                            const AT fi = ir2 * fma(er, kr, -ei);
+                            // cell target: (-s'_c e - F d.v'_c) mu_f
+                            const AT qa = static_cast<AT>(fma(dx, va0, fma(dy, va1, dz * va2)));
+                            const AT car = fma(sa, er, -qa * fr), cai = fma(sa, ei, -qa * fi);
+                            const C2 u = B.u[j];
+                            sAr = fma(car, u.x, fma(-cai, u.y, sAr));
+                            sAi = fma(car, u.y, fma(cai, u.x, sAi));
+                            // face target: F (d.v'_f) mu_c
+                            const AT qq = static_cast<AT>(fma(dx, B.vx[j], fma(dy, B.vy[j], dz * B.vz[j])));
+                            const AT cr = qq * fr, ci = qq * fi;
+                            sBr = rot1(fma(cr, uar, fma(-ci, uai, sBr)));
+                            sBi = rot1(fma(cr, uai, fma(ci, uar, sBi)));
+                        }
+                        done = true;
+                    }
+                } else if constexpr (T) {
                     if (item_t) {
                         for (int st = 0; st < 64; ++st) {
                             const int j = lane + 64 - st;
@@ -599,7 +696,7 @@ __global__ __launch_bounds__(kBlock) void cf_kernel(CfArgs a) {
                     }
                 }
                 if constexpr (ADJ) {
-                    for (int st = 0; st < 64; ++st) {
+                    for (int st = 0; st < (done ? 0 : 64); ++st) {
                         const int j = lane + 64 - st;
                         const double dx = xa - B.x[j], dy = ya - B.y[j], dz = za - B.z[j];
                         AT er, ei, ir2, kr;
@@ -615,6 +712,13 @@ __global__ __launch_bounds__(kBlock) void cf_kernel(CfArgs a) {
                         const AT ci = qq * fma(er, kr, -ei);
                         sBr = rot1(fma(cr, uar, fma(-ci, uai, sBr)));
                         sBi = rot1(fma(cr, uai, fma(ci, uar, sBi)));
+                    }
+                    if constexpr (T) {
+                        // items without grad-alpha cells: the cells' weights after the sums
+                        if (!done) {
+                            sAr *= sa;
+                            sAi *= sa;
+                        }
                     }
                     done = true;
                 }
@@ -662,25 +766,26 @@ __global__ __launch_bounds__(kBlock) void cf_kernel(CfArgs a) {
 }
 
 template <int G, typename AT>
-const void *sym_ptr(bool t) {
-    return t ? reinterpret_cast<const void *>(&sym_kernel<G, AT, true>)
-             : reinterpret_cast<const void *>(&sym_kernel<G, AT, false>);
+const void *sym_ptr(bool t, bool adj) {
+    if (adj) return reinterpret_cast<const void *>(&sym_kernel<G, AT, true, true>);
+    return t ? reinterpret_cast<const void *>(&sym_kernel<G, AT, true, false>)
+             : reinterpret_cast<const void *>(&sym_kernel<G, AT, false, false>);
 }
 
-const void *pick_sym(int g, bool f32, bool t) {
-    if (g == 2) return f32 ? sym_ptr<2, float>(t) : sym_ptr<2, double>(t);
-    if (g == 4) return f32 ? sym_ptr<4, float>(t) : sym_ptr<4, double>(t);
-    if (g == 8) return f32 ? sym_ptr<8, float>(t) : sym_ptr<8, double>(t);
+const void *pick_sym(int g, bool f32, bool t, bool adj) {
+    if (g == 2) return f32 ? sym_ptr<2, float>(t, adj) : sym_ptr<2, double>(t, adj);
+    if (g == 4) return f32 ? sym_ptr<4, float>(t, adj) : sym_ptr<4, double>(t, adj);
+    if (g == 8) return f32 ? sym_ptr<8, float>(t, adj) : sym_ptr<8, double>(t, adj);
     return nullptr;
 }
 
 void launch_slot_reduce(int64_t n, int64_t nc, const SlotList &cells, const SlotList &faces,
-                        const double2 *diag, const double2 *x, double2 *y, hipStream_t s,
+                        const double2 *diag, const double2 *x, double2 *y, hipStream_t s, bool adj = false,
                         const double *adj_sp = nullptr) {
     const int64_t cell_blocks = (nc + 63) / 64, face_blocks = (n - nc + 63) / 64;
     const int64_t blocks = cell_blocks + face_blocks;
     if (blocks > 0x7fffffff) fail(VSIE_E_INVALID, "slot reduction: too many points");
-    if (adj_sp)
+    if (adj)
         hipLaunchKernelGGL(slot_reduce_kernel<true>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, n, nc,
                            cell_blocks, cells, faces, diag, x, y, adj_sp);
     else
@@ -802,10 +907,12 @@ void launch_sym(const SymJob &J, hipStream_t s, PairProfiler *prof) {
     a.vz = J.vz;
     a.xv = J.xv;
     a.tile_t = J.tile_t;
+    a.sw = J.sw;
     if (J.ldp < J.ng) fail(VSIE_E_INVALID, "symmetric pair kernel: partial stride below the cell count");
     const bool t = J.vx != nullptr;
     if (t && !(J.vy && J.vz && J.xv && J.tile_t)) fail(VSIE_E_INVALID, "symmetric pair kernel: incomplete T data");
-    const void *kp = pick_sym(J.g, f32, t);
+    if (J.adj && !(t && J.sw)) fail(VSIE_E_INVALID, "symmetric pair kernel: the adjoint variant needs the T data and s'");
+    const void *kp = pick_sym(J.g, f32, t, J.adj);
     const int64_t grid = ranges_grid(a.xr);
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (prof && prof->on) {
@@ -852,6 +959,7 @@ void launch_cf(const CfJob &J, hipStream_t s, PairProfiler *prof) {
     a.qc = J.qc;
     a.xf = J.xf;
     a.qfa = J.qfa;
+    a.sw = J.sw;
     a.cvx = J.cvx;
     a.cvy = J.cvy;
     a.cvz = J.cvz;
@@ -880,12 +988,14 @@ void launch_cf(const CfJob &J, hipStream_t s, PairProfiler *prof) {
     a.ldf = J.nf;
     const bool t = J.cvx != nullptr;
     if (t && !(J.cvy && J.cvz && J.xc && J.ctile_t)) fail(VSIE_E_INVALID, "cell-face kernel: incomplete T data");
-    if (t && J.adj) fail(VSIE_E_INVALID, "cell-face kernel: no adjoint variant with grad-alpha cells");
+    if (t && J.adj && !J.sw) fail(VSIE_E_INVALID, "cell-face kernel: the adjoint with grad-alpha cells needs s'");
     if (!(J.adj ? J.qfa != nullptr : J.xf != nullptr) || !J.vx || !J.vy || !J.vz)
         fail(VSIE_E_INVALID, "cell-face kernel: missing face data");
     const void *kp = nullptr;
-    if (J.adj) kp = f32 ? reinterpret_cast<const void *>(&cf_kernel<kCfGroup, float, false, true>)
-                        : reinterpret_cast<const void *>(&cf_kernel<kCfGroup, double, false, true>);
+    if (J.adj && t) kp = f32 ? reinterpret_cast<const void *>(&cf_kernel<kCfGroup, float, true, true>)
+                             : reinterpret_cast<const void *>(&cf_kernel<kCfGroup, double, true, true>);
+    else if (J.adj) kp = f32 ? reinterpret_cast<const void *>(&cf_kernel<kCfGroup, float, false, true>)
+                             : reinterpret_cast<const void *>(&cf_kernel<kCfGroup, double, false, true>);
     else if (t) kp = f32 ? reinterpret_cast<const void *>(&cf_kernel<kCfGroup, float, true, false>)
                          : reinterpret_cast<const void *>(&cf_kernel<kCfGroup, double, true, false>);
     else kp = f32 ? reinterpret_cast<const void *>(&cf_kernel<kCfGroup, float, false, false>)
@@ -911,12 +1021,12 @@ void launch_cf(const CfJob &J, hipStream_t s, PairProfiler *prof) {
 // slots + face-face chunk partials); one right-hand side
 void launch_cf_reduce(int64_t n, int64_t nc, int n_sym, const double2 *sym, int n_cs, const double2 *pc, int n_fs,
                       const double2 *pf, int n_ff, const double2 *ff, const double2 *diag, const double2 *x,
-                      double2 *y, hipStream_t s, const double *adj_sp) {
+                      double2 *y, hipStream_t s, bool adj, const double *adj_sp) {
     if (n == 0) return;
     const int64_t nf = n - nc;
     const SlotList cells{sym, n_sym, nc, 0, pc, n_cs, nc, 0};
     const SlotList faces{pf, n_fs, nf, 0, ff, n_ff, nf, 0};
-    launch_slot_reduce(n, nc, cells, faces, diag, x, y, s, adj_sp);
+    launch_slot_reduce(n, nc, cells, faces, diag, x, y, s, adj, adj_sp);
 }
 
 }  // namespace vsie

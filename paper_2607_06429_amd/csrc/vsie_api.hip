@@ -439,6 +439,22 @@ void apply_forward_block(vsie_problem *p, int f, vsie_precision prec, int nrhs, 
 // is a face): symmetric cell-cell single layer, cell-face kernel (single layer
 // at faces, double layers at cells), face-face double layers one-sided, one
 // reduction.
+// XCD item ranges of the once-per-pair kernels with grad-alpha cells, cached
+// per precision and group size.  Issue cycles per pair of the grad-alpha loops
+// relative to the single-layer ones (counted in the compiled loops):
+// symmetric kernel 1.53 (FP32) and 1.42 (FP64), cell-face kernel 1.17 and 1.42.
+const vsie_problem::TRanges &t_ranges(vsie_problem *p, vsie_precision prec) {
+    const int g = p->tune.sym_groups;
+    vsie_problem::TRanges &tr = p->tranges[prec == VSIE_FP32 ? 1 : 0];
+    if (tr.g != g) {
+        const bool f32 = prec == VSIE_FP32;
+        sym_cost_ranges(p->m.n_vol, g, p->ctile_h, f32 ? 1.53 : 1.42, tr.sym);
+        cf_cost_ranges(p->m.n_vol, p->m.n - p->m.n_vol, p->ctile_h, f32 ? 1.17 : 1.42, tr.cf);
+        tr.g = g;
+    }
+    return tr;
+}
+
 void apply_forward_cf(vsie_problem *p, int f, vsie_precision prec, const double2 *x, double2 *y, hipStream_t s) {
     const int64_t n = p->m.n, nv = p->m.n_vol, ns = n - nv;
     const int g = p->tune.sym_groups;
@@ -459,17 +475,8 @@ void apply_forward_cf(vsie_problem *p, int f, vsie_precision prec, const double2
     const bool t = p->f_cells > 0;
     const int32_t *tiles_t = static_cast<const int32_t *>(p->ctile.p);
     SymJob J{prec, nv, p->m.px, p->m.py, p->m.pz, qG, k, {p->far[0], p->far[1], p->far[2]}, p->far_step, g, psym, nv};
-    vsie_problem::TRanges &tr = p->tranges[prec == VSIE_FP32 ? 1 : 0];
-    if (t && tr.g != g) {
-        // issue cycles per pair of the grad-alpha loops relative to the
-        // single-layer ones (counted in the compiled loops): symmetric kernel
-        // 1.53 (FP32) and 1.42 (FP64), cell-face kernel 1.17 and 1.42
-        const bool f32 = prec == VSIE_FP32;
-        sym_cost_ranges(nv, g, p->ctile_h, f32 ? 1.53 : 1.42, tr.sym);
-        cf_cost_ranges(nv, ns, p->ctile_h, f32 ? 1.17 : 1.42, tr.cf);
-        tr.g = g;
-    }
     if (t) {
+        const vsie_problem::TRanges &tr = t_ranges(p, prec);
         J.vx = p->m.vpx;
         J.vy = p->m.vpy;
         J.vz = p->m.vpz;
@@ -487,7 +494,7 @@ void apply_forward_cf(vsie_problem *p, int f, vsie_precision prec, const double2
             C.cvz = p->m.vpz;
             C.xc = x;
             C.ctile_t = tiles_t;
-            C.xr = tr.cf;
+            C.xr = t_ranges(p, prec).cf;
         }
         launch_cf(C, s, &p->prof);
     }
@@ -605,15 +612,15 @@ void apply_adjoint_block(vsie_problem *p, int f, vsie_precision prec, int nrhs, 
 }
 
 // One-column adjoint with the once-per-pair kernels, when every cell is a
-// single-layer source and the double-layer sources are exactly the faces.
-// With mu = conj(lambda): (A^H lambda)_j = conj(d_j) lambda_j + conj(w_j S_j),
-// w_j = -s'_j for cells and 1 for faces, where a cell's S_j sums e_ij mu_i over
-// the other cells (the symmetric kernel with charges mu) and the faces (the
-// cell-face kernel's adjoint variant), and a face's S_j sums its double layer
-// e (i k r - 1) (x_i - y_j).v'_j / r^2 mu_i over the cells (same kernel) and
-// the faces (one-sided).
+// single-layer source.  With mu = conj(lambda):
+// (A^H lambda)_j = conj(d_j) lambda_j + conj(S_j), where a cell's S_j sums
+// (-s'_j e_ij + F_ij (x_i - x_j).v'_j) mu_i over the other cells (symmetric
+// kernel) and the faces (cell-face kernel), and a face's S_j sums its double
+// layer F_ij (x_i - x_j).v'_j mu_i over the cells (cell-face kernel) and the
+// faces (one-sided).  Without grad-alpha cells the cells' sums are of e_ij mu_i
+// alone and -s'_j is applied in the reduction.
 bool adjoint_sym_ok(const vsie_problem *p, int nrhs) {
-    return use_sym(p, nrhs) && p->tune.cell_face && p->f_is_faces;
+    return use_sym(p, nrhs) && p->tune.cell_face;
 }
 
 void apply_adjoint_sym(vsie_problem *p, int f, vsie_precision prec, const double2 *x, double2 *y, hipStream_t s) {
@@ -630,13 +637,35 @@ void apply_adjoint_sym(vsie_problem *p, int f, vsie_precision prec, const double
     launch_pack_plain(prec, n, 1, x, n, true, q, s);
     const void *qf = static_cast<const char *>(q) + csize(prec) * static_cast<size_t>(nv);
     const double k = p->k0[f];
+    const double *spf = p->m.sp + static_cast<int64_t>(f) * n;
+    const bool t = p->f_cells > 0;
+    const int32_t *tiles_t = static_cast<const int32_t *>(p->ctile.p);
     SymJob J{prec, nv, p->m.px, p->m.py, p->m.pz, q, k, {p->far[0], p->far[1], p->far[2]}, p->far_step, g, psym, nv};
+    if (t) {
+        J.vx = p->m.vpx;
+        J.vy = p->m.vpy;
+        J.vz = p->m.vpz;
+        J.xv = x;
+        J.tile_t = tiles_t;
+        J.xr = t_ranges(p, prec).sym;
+        J.adj = true;
+        J.sw = spf;
+    }
     launch_sym(J, s, &p->prof);
     if (ns > 0) {
         CfJob C{prec, nv, ns, p->m.px, p->m.py, p->m.pz, p->m.vpx + nv, p->m.vpy + nv, p->m.vpz + nv, q, nullptr, k,
                 {p->far[0], p->far[1], p->far[2]}, p->far_step, pc, pf};
         C.adj = true;
         C.qfa = qf;
+        if (t) {
+            C.cvx = p->m.vpx;
+            C.cvy = p->m.vpy;
+            C.cvz = p->m.vpz;
+            C.xc = x;
+            C.ctile_t = tiles_t;
+            C.xr = t_ranges(p, prec).cf;
+            C.sw = spf;
+        }
         launch_cf(C, s, &p->prof);
     }
     if (ncFF > 0) {
@@ -647,7 +676,7 @@ void apply_adjoint_sym(vsie_problem *p, int f, vsie_precision prec, const double
         launch_pairs(Jf, s, &p->prof);
     }
     launch_cf_reduce(n, nv, static_cast<int>(slots), psym, static_cast<int>(cs), pc, static_cast<int>(fs), pf, ncFF,
-                     pff, p->m.diag + static_cast<int64_t>(f) * n, x, y, s, p->m.sp + static_cast<int64_t>(f) * n);
+                     pff, p->m.diag + static_cast<int64_t>(f) * n, x, y, s, true, t ? nullptr : spf);
 }
 
 void apply_adjoint(vsie_problem *p, int f, vsie_precision prec, int nrhs, const double2 *x,

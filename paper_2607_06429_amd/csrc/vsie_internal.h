@@ -208,6 +208,10 @@ struct SymJob {
     const double2 *xv = nullptr;
     const int32_t *tile_t = nullptr;
     const int64_t *xr = nullptr;  // host: 9 item-range boundaries, one range per XCD (null: equal counts)
+    // adjoint (needs the T data): q holds conj(lambda) and the partials carry
+    // the targets' weights, (-s'_i e + F (x_j - x_i).v'_i) mu_j; sw = s' of the cells
+    bool adj = false;
+    const double *sw = nullptr;
 };
 bool sym_groups_ok(int g);
 // Item ranges of the 8 XCDs (9 boundaries) with equal modelled work when the
@@ -254,16 +258,17 @@ struct CfJob {
     // double layer with mu_c
     bool adj = false;
     const void *qfa = nullptr;
+    const double *sw = nullptr;  // adjoint with cvx: s' of the cells (weights applied in the kernel)
 };
 int64_t cf_groups(int64_t count);  // slots for count cells or faces
 void launch_cf(const CfJob &J, hipStream_t s, PairProfiler *prof);
 // y = diag x + (i < nc: n_sym symmetric slots + n_cs cell slots of pc;
 // i >= nc: n_fs face slots of pf + n_ff face-face chunk partials ff[c * nf + i - nc]);
-// with adj_sp (the frequency's s' of all points): y = conj(diag) x + conj(w sum),
-// w = -s'_i for cells and 1 for faces
+// adj: y = conj(diag) x + conj(w sum) with w = -s'_i for cells when adj_sp
+// (the frequency's s' of all points) is given, else 1
 void launch_cf_reduce(int64_t n, int64_t nc, int n_sym, const double2 *sym, int n_cs, const double2 *pc, int n_fs,
                       const double2 *pf, int n_ff, const double2 *ff, const double2 *diag, const double2 *x,
-                      double2 *y, hipStream_t s, const double *adj_sp = nullptr);
+                      double2 *y, hipStream_t s, bool adj = false, const double *adj_sp = nullptr);
 
 // auxiliary kernels (aux_kernels.hip)
 void launch_weights(const DeviceMesh &m, const double *k0, int n_freq, hipStream_t s);

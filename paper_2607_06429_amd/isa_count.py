@@ -102,13 +102,14 @@ def kernels(asm: str):
         cls, tg, nb, m3 = re.search(r"kernelILi(\d)ELi(\d)ELi(\d)ELb(\d)E", nm).groups()
         yield nm, "mfma_%s_fp32_tg%s_nb%s%s" % (MODES[int(cls)], tg, nb, "_3m" if m3 == "1" else ""), 16 * int(nb)
     for nm in re.findall(r"^(_Z\w+sym_kernel\w+):", asm, re.M):
-        g, acc, t = re.search(r"sym_kernelILi(\d)E(\w)Lb(\d)E", nm).groups()
+        g, acc, t, adj = re.search(r"sym_kernelILi(\d)E(\w)Lb(\d)ELb(\d)E", nm).groups()
         if g == "4":   # the default group size; the inner loop is the same for every size
-            # T variant: the loop of the items with grad-alpha cells (the most instructions per pair)
-            yield nm, "sym_single_layer%s_%s_R1" % ("_t" if t == "1" else "", "fp64" if acc == "d" else "fp32"), 1
+            # T variants: the loop of the items with grad-alpha cells (the most instructions per pair)
+            tag = "_t_adj" if adj == "1" else "_t" if t == "1" else ""
+            yield nm, "sym_single_layer%s_%s_R1" % (tag, "fp64" if acc == "d" else "fp32"), 1
     for nm in re.findall(r"^(_Z\w+cf_kernel\w+):", asm, re.M):
         acc, t, adj = re.search(r"cf_kernelILi\d+E(\w)Lb(\d)ELb(\d)E", nm).groups()
-        tag = "_t" if t == "1" else "_adj" if adj == "1" else ""
+        tag = ("_t" if t == "1" else "") + ("_adj" if adj == "1" else "")
         yield nm, "cell_face%s_%s_R1" % (tag, "fp64" if acc == "d" else "fp32"), 1
 
 

@@ -104,11 +104,14 @@ def test_small_grid_products_against_oracle(V, prec, name):
     y = host(P.matvec(dev(x), prec=pr))
     ya = host(P.matvec_adjoint(dev(x), prec=pr))
     e, ea = O.rel_error(y, O.matvec(d, x)), O.rel_error(ya, O.adjoint_matvec(d, x))
-    # one column: the once-per-pair cell-cell kernel
+    # one column: the once-per-pair kernels, forward and adjoint
     y1 = host(P.matvec(dev(x[:, 0]), prec=pr))
     e1 = O.rel_error(y1, O.matvec(d, x[:, :1])[:, 0])
-    say("  %s small %s: n %d rel err %.2e adjoint %.2e one column %.2e" % (name, prec, d.n, e, ea, e1))
-    assert e <= tol and ea <= tol and e1 <= tol
+    ya1 = host(P.matvec_adjoint(dev(x[:, 1]), prec=pr))
+    ea1 = O.rel_error(ya1, O.adjoint_matvec(d, x[:, 1:2])[:, 0])
+    say("  %s small %s: n %d rel err %.2e adjoint %.2e one column %.2e, adjoint %.2e"
+        % (name, prec, d.n, e, ea, e1, ea1))
+    assert e <= tol and ea <= tol and e1 <= tol and ea1 <= tol
     P.close()
 
 

@@ -88,7 +88,7 @@ struct SymArgs {
     int groups;
     int64_t items;
     int64_t xr[kXcds + 1];           // item range of XCD x: [xr[x], xr[x + 1])
-    double2 *__restrict__ part;
+    void *__restrict__ part;         // slot partials: float2 (FP32 kernels) or double2
     int64_t ldp;
     // adjoint double layer (T variant only): v' of the cells, the raw values
     // x, and per 64-cell tile whether any v' is nonzero
@@ -161,6 +161,17 @@ __device__ __forceinline__ void load_t(const double *__restrict__ vx, const doub
 template <typename AT>
 __device__ __forceinline__ AT dot_v(AT dxa, AT dya, AT dza, AT v0, AT v1, AT v2) {
     return fma(dxa, v0, fma(dya, v1, dza * v2));
+}
+
+// One slot partial, the FP64 sum over a partner group: FP32 kernels store it
+// rounded to float2 (half the bytes written and read back by the reduction),
+// FP64 kernels as double2.
+template <typename AT>
+__device__ __forceinline__ void store_slot(void *base, int64_t i, double re, double im) {
+    if constexpr (sizeof(AT) == 4)
+        static_cast<float2 *>(base)[i] = make_float2(static_cast<float>(re), static_cast<float>(im));
+    else
+        static_cast<double2 *>(base)[i] = make_double2(re, im);
 }
 
 template <int G, typename AT, bool T, bool ADJ>
@@ -406,12 +417,12 @@ __global__ __launch_bounds__(kBlock) void sym_kernel(SymArgs a) {
                     r += accBr[t];
                     i += accBi[t];
                 }
-                a.part[static_cast<int64_t>(J) * a.ldp + pa] = make_double2(r, i);
+                store_slot<AT>(a.part, static_cast<int64_t>(J) * a.ldp + pa, r, i);
             }
             if (I != J) {
                 const int bt = J * G + t;
                 const int64_t pb = static_cast<int64_t>(bt) * 64 + lane;
-                if (bt < a.tiles && pb < a.ng) a.part[static_cast<int64_t>(I) * a.ldp + pb] = make_double2(accBr[t], accBi[t]);
+                if (bt < a.tiles && pb < a.ng) store_slot<AT>(a.part, static_cast<int64_t>(I) * a.ldp + pb, accBr[t], accBi[t]);
             }
         }
     }
@@ -419,15 +430,30 @@ __global__ __launch_bounds__(kBlock) void sym_kernel(SymArgs a) {
 
 // The partial sums a point receives, as one list of slots from two arrays:
 // slot t < na is a[t * lda + offa + p], slot na + t is b[t * ldb + offb + p]
-// (p: index of the point within its class, cells or faces).
+// (p: index of the point within its class, cells or faces); a32 / b32: the
+// array holds float2 partials, else double2.
 struct SlotList {
-    const double2 *a;
+    const void *a;
     int na;
     int64_t lda, offa;
-    const double2 *b;
+    const void *b;
     int nb;
     int64_t ldb, offb;
+    bool a32 = false, b32 = false;
 };
+
+// sr + i si += slots t0 .. t1-1 of one array, added in slot order in FP64
+template <typename P>
+__device__ __forceinline__ void add_slots(const void *base, int64_t ld, int64_t off, int t0, int t1, double &sr,
+                                          double &si) {
+    const P *__restrict__ v = static_cast<const P *>(base) + off;
+#pragma unroll 8
+    for (int t = t0; t < t1; ++t) {
+        const P e = v[static_cast<int64_t>(t) * ld];
+        sr += static_cast<double>(e.x);
+        si += static_cast<double>(e.y);
+    }
+}
 
 // y = diag x + the sum of each point's slots.  A workgroup takes 64 points of
 // one class (cells: workgroups 0 .. cell_blocks-1, then faces); wave w adds
@@ -455,18 +481,11 @@ __global__ __launch_bounds__(kBlock) void slot_reduce_kernel(int64_t n, int64_t 
     double sr = 0.0, si = 0.0;
     if (p < count) {
         const int ea = t1 < L.na ? t1 : L.na;
-#pragma unroll 4
-        for (int t = t0; t < ea; ++t) {
-            const double2 v = L.a[static_cast<int64_t>(t) * L.lda + L.offa + p];
-            sr += v.x;
-            si += v.y;
-        }
-#pragma unroll 4
-        for (int t = (t0 > L.na ? t0 : L.na); t < t1; ++t) {
-            const double2 v = L.b[static_cast<int64_t>(t - L.na) * L.ldb + L.offb + p];
-            sr += v.x;
-            si += v.y;
-        }
+        if (L.a32) add_slots<float2>(L.a, L.lda, L.offa + p, t0, ea, sr, si);
+        else add_slots<double2>(L.a, L.lda, L.offa + p, t0, ea, sr, si);
+        const int b0 = (t0 > L.na ? t0 : L.na) - L.na, b1 = t1 - L.na;
+        if (L.b32) add_slots<float2>(L.b, L.ldb, L.offb + p, b0, b1, sr, si);
+        else add_slots<double2>(L.b, L.ldb, L.offb + p, b0, b1, sr, si);
     }
     red[w][lane] = make_double2(sr, si);
     __syncthreads();
@@ -533,9 +552,9 @@ struct CfArgs {
     int cgroups, fgroups;
     int64_t items;
     int64_t xr[kXcds + 1];           // item range of XCD x: [xr[x], xr[x + 1])
-    double2 *__restrict__ pc;        // pc[slot * ldc + c], slot = face group
+    void *__restrict__ pc;           // pc[slot * ldc + c], slot = face group (float2 or double2 as part)
     int64_t ldc;
-    double2 *__restrict__ pf;        // pf[slot * ldf + f], slot = cell group
+    void *__restrict__ pf;           // pf[slot * ldf + f], slot = cell group
     int64_t ldf;
 };
 
@@ -757,10 +776,10 @@ __global__ __launch_bounds__(kBlock) void cf_kernel(CfArgs a) {
         for (int t = 0; t < G; ++t) {
             const int at = I * G + t;
             const int64_t c = static_cast<int64_t>(at) * 64 + lane;
-            if (at < a.ctiles && c < a.nc) a.pc[static_cast<int64_t>(J) * a.ldc + c] = make_double2(accAr[t], accAi[t]);
+            if (at < a.ctiles && c < a.nc) store_slot<AT>(a.pc, static_cast<int64_t>(J) * a.ldc + c, accAr[t], accAi[t]);
             const int bt = J * G + t;
             const int64_t f = static_cast<int64_t>(bt) * 64 + lane;
-            if (bt < a.ftiles && f < a.nf) a.pf[static_cast<int64_t>(I) * a.ldf + f] = make_double2(accBr[t], accBi[t]);
+            if (bt < a.ftiles && f < a.nf) store_slot<AT>(a.pf, static_cast<int64_t>(I) * a.ldf + f, accBr[t], accBi[t]);
         }
     }
 }
@@ -932,12 +951,12 @@ void launch_sym(const SymJob &J, hipStream_t s, PairProfiler *prof) {
 
 // y = diag x + (cells: symmetric slots; faces: one-sided single-layer chunk
 // partials) + the double-layer chunk partials (stride n, global index)
-void launch_sym_reduce(int64_t n, int64_t n_vol, int n_slots, const double2 *sym, int64_t ldp, int n_face_parts,
-                       const double2 *face, int n_f_parts, const double2 *fpart, const double2 *diag,
-                       const double2 *x, double2 *y, hipStream_t s) {
+void launch_sym_reduce(int64_t n, int64_t n_vol, int n_slots, const void *sym, bool sym32, int64_t ldp,
+                       int n_face_parts, const double2 *face, int n_f_parts, const double2 *fpart,
+                       const double2 *diag, const double2 *x, double2 *y, hipStream_t s) {
     if (n == 0) return;
     const int64_t nf = n - n_vol;
-    const SlotList cells{sym, n_slots, ldp, 0, fpart, n_f_parts, n, 0};
+    const SlotList cells{sym, n_slots, ldp, 0, fpart, n_f_parts, n, 0, sym32, false};
     const SlotList faces{face, n_face_parts, nf, 0, fpart, n_f_parts, n, n_vol};
     launch_slot_reduce(n, n_vol, cells, faces, diag, x, y, s);
 }
@@ -1019,13 +1038,13 @@ void launch_cf(const CfJob &J, hipStream_t s, PairProfiler *prof) {
 
 // y = diag x + (cells: symmetric slots + cell-face slots; faces: cell-face
 // slots + face-face chunk partials); one right-hand side
-void launch_cf_reduce(int64_t n, int64_t nc, int n_sym, const double2 *sym, int n_cs, const double2 *pc, int n_fs,
-                      const double2 *pf, int n_ff, const double2 *ff, const double2 *diag, const double2 *x,
+void launch_cf_reduce(int64_t n, int64_t nc, bool slots32, int n_sym, const void *sym, int n_cs, const void *pc,
+                      int n_fs, const void *pf, int n_ff, const double2 *ff, const double2 *diag, const double2 *x,
                       double2 *y, hipStream_t s, bool adj, const double *adj_sp) {
     if (n == 0) return;
     const int64_t nf = n - nc;
-    const SlotList cells{sym, n_sym, nc, 0, pc, n_cs, nc, 0};
-    const SlotList faces{pf, n_fs, nf, 0, ff, n_ff, nf, 0};
+    const SlotList cells{sym, n_sym, nc, 0, pc, n_cs, nc, 0, slots32, slots32};
+    const SlotList faces{pf, n_fs, nf, 0, ff, n_ff, nf, 0, slots32, false};
     launch_slot_reduce(n, nc, cells, faces, diag, x, y, s, adj, adj_sp);
 }
 

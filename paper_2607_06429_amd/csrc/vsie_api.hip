@@ -6,6 +6,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <memory>
 #include <thread>
 #include <string>
@@ -443,6 +444,31 @@ void apply_forward_block(vsie_problem *p, int f, vsie_precision prec, int nrhs, 
 // per precision and group size.  Issue cycles per pair of the grad-alpha loops
 // relative to the single-layer ones (counted in the compiled loops):
 // symmetric kernel 1.53 (FP32) and 1.42 (FP64), cell-face kernel 1.17 and 1.42.
+// The once-per-pair kernels' slot partials, three arrays of float2 (FP32
+// operator) or double2 entries, then a double2 tail for the one-sided chunk
+// partials; every array starts on a 256-byte boundary.
+struct SlotBuffers {
+    void *s[3];
+    double2 *tail;
+};
+
+SlotBuffers slot_buffers(vsie_problem *p, vsie_precision prec, std::initializer_list<int64_t> counts,
+                         int64_t tail) {
+    if (counts.size() != 3) fail(VSIE_E_INVALID, "slot buffers: three slot arrays expected");
+    const size_t es = prec == VSIE_FP32 ? sizeof(float2) : sizeof(double2);
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    size_t off[4], at = 0;
+    int i = 0;
+    for (int64_t c : counts) {
+        off[i++] = at;
+        at += up(es * static_cast<size_t>(c));
+    }
+    off[3] = at;
+    at += sizeof(double2) * static_cast<size_t>(tail);
+    char *base = static_cast<char *>(p->partial.get(std::max<size_t>(256, at)));
+    return SlotBuffers{{base + off[0], base + off[1], base + off[2]}, reinterpret_cast<double2 *>(base + off[3])};
+}
+
 const vsie_problem::TRanges &t_ranges(vsie_problem *p, vsie_precision prec) {
     const int g = p->tune.sym_groups;
     vsie_problem::TRanges &tr = p->tranges[prec == VSIE_FP32 ? 1 : 0];
@@ -464,9 +490,9 @@ void apply_forward_cf(vsie_problem *p, int f, vsie_precision prec, const double2
     int64_t chFF = 1;
     int ncFF = 0;
     if (ns > 0) choose_chunks(ns, nff, p->tune.vec_target_waves, chFF, ncFF);
-    const size_t total = static_cast<size_t>(slots * nv + cs * nv + fs * ns + static_cast<int64_t>(ncFF) * ns);
-    double2 *part = static_cast<double2 *>(p->partial.get(sizeof(double2) * std::max<size_t>(1, total)));
-    double2 *psym = part, *pc = psym + slots * nv, *pf = pc + cs * nv, *pff = pf + fs * ns;
+    const SlotBuffers sb = slot_buffers(p, prec, {slots * nv, cs * nv, fs * ns}, static_cast<int64_t>(ncFF) * ns);
+    void *psym = sb.s[0], *pc = sb.s[1], *pf = sb.s[2];
+    double2 *pff = sb.tail;
     void *qG = p->chargeG.get(csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->G.count)));
     void *qF = p->chargeF.get(csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->F.count)));
     const double *spf = p->m.sp + static_cast<int64_t>(f) * n;
@@ -507,7 +533,8 @@ void apply_forward_cf(vsie_problem *p, int f, vsie_precision prec, const double2
                    pff, ns, ident ? SELF_IDENT : SELF_NONE, nullptr};
         launch_pairs(Jf, s, &p->prof);
     }
-    launch_cf_reduce(n, nv, static_cast<int>(slots), psym, static_cast<int>(cs), pc, static_cast<int>(fs), pf, ncFF,
+    launch_cf_reduce(n, nv, prec == VSIE_FP32, static_cast<int>(slots), psym, static_cast<int>(cs), pc,
+                     static_cast<int>(fs), pf, ncFF,
                      pff, p->m.diag + static_cast<int64_t>(f) * n, x, y, s);
 }
 
@@ -524,9 +551,10 @@ void apply_forward_sym(vsie_problem *p, int f, vsie_precision prec, const double
     int ncGf = 0, ncF = 0;
     if (ns > 0) choose_chunks(ns, p->G.count, p->tune.vec_target_waves, chGf, ncGf);
     choose_chunks(n, p->F.count, p->tune.vec_target_waves, chF, ncF);
-    const size_t total = static_cast<size_t>(slots * nv + static_cast<int64_t>(ncGf) * ns + static_cast<int64_t>(ncF) * n);
-    double2 *part = static_cast<double2 *>(p->partial.get(sizeof(double2) * std::max<size_t>(1, total)));
-    double2 *psym = part, *pface = psym + slots * nv, *pF = pface + static_cast<int64_t>(ncGf) * ns;
+    const SlotBuffers sb = slot_buffers(p, prec, {slots * nv, 0, 0},
+                                        static_cast<int64_t>(ncGf) * ns + static_cast<int64_t>(ncF) * n);
+    void *psym = sb.s[0];
+    double2 *pface = sb.tail, *pF = pface + static_cast<int64_t>(ncGf) * ns;
     void *qG = p->chargeG.get(csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->G.count)));
     void *qF = p->chargeF.get(csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->F.count)));
     const double *spf = p->m.sp + static_cast<int64_t>(f) * n;
@@ -545,7 +573,7 @@ void apply_forward_sym(vsie_problem *p, int f, vsie_precision prec, const double
                    pF, n, SELF_STREAM_IDX, p->F.idx};
         launch_pairs(JF, s, &p->prof);
     }
-    launch_sym_reduce(n, nv, static_cast<int>(slots), psym, nv, ncGf, pface, ncF, pF,
+    launch_sym_reduce(n, nv, static_cast<int>(slots), psym, prec == VSIE_FP32, nv, ncGf, pface, ncF, pF,
                       p->m.diag + static_cast<int64_t>(f) * n, x, y, s);
 }
 
@@ -630,9 +658,9 @@ void apply_adjoint_sym(vsie_problem *p, int f, vsie_precision prec, const double
     int64_t chFF = 1;
     int ncFF = 0;
     if (ns > 0) choose_chunks(ns, ns, p->tune.vec_target_waves, chFF, ncFF);
-    const size_t total = static_cast<size_t>(slots * nv + cs * nv + fs * ns + static_cast<int64_t>(ncFF) * ns);
-    double2 *part = static_cast<double2 *>(p->partial.get(sizeof(double2) * std::max<size_t>(1, total)));
-    double2 *psym = part, *pc = psym + slots * nv, *pf = pc + cs * nv, *pff = pf + fs * ns;
+    const SlotBuffers sb = slot_buffers(p, prec, {slots * nv, cs * nv, fs * ns}, static_cast<int64_t>(ncFF) * ns);
+    void *psym = sb.s[0], *pc = sb.s[1], *pf = sb.s[2];
+    double2 *pff = sb.tail;
     void *q = p->chargeAll.get(csize(prec) * static_cast<size_t>(n));
     launch_pack_plain(prec, n, 1, x, n, true, q, s);
     const void *qf = static_cast<const char *>(q) + csize(prec) * static_cast<size_t>(nv);
@@ -675,7 +703,8 @@ void apply_adjoint_sym(vsie_problem *p, int f, vsie_precision prec, const double
                    qf, ns, 1, chFF, ncFF, k, pff, ns, SELF_IDENT, nullptr};
         launch_pairs(Jf, s, &p->prof);
     }
-    launch_cf_reduce(n, nv, static_cast<int>(slots), psym, static_cast<int>(cs), pc, static_cast<int>(fs), pf, ncFF,
+    launch_cf_reduce(n, nv, prec == VSIE_FP32, static_cast<int>(slots), psym, static_cast<int>(cs), pc,
+                     static_cast<int>(fs), pf, ncFF,
                      pff, p->m.diag + static_cast<int64_t>(f) * n, x, y, s, true, t ? nullptr : spf);
 }
 

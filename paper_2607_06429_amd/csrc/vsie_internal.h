@@ -202,7 +202,7 @@ struct SymJob {
     double far[3];
     double far_step;
     int g;
-    double2 *part;
+    void *part;  // slot partials part[slot * ldp + i]: float2 for VSIE_FP32, else double2
     int64_t ldp;
     const double *vx = nullptr, *vy = nullptr, *vz = nullptr;
     const double2 *xv = nullptr;
@@ -222,12 +222,13 @@ void sym_cost_ranges(int64_t ng, int g, const std::vector<int32_t> &tile_t, doub
 void cf_cost_ranges(int64_t nc, int64_t nf, const std::vector<int32_t> &tile_t, double weight, int64_t *xr);
 int64_t sym_slots(int64_t ng, int g);
 void launch_sym(const SymJob &J, hipStream_t s, PairProfiler *prof);
-// y = diag x + (i < n_vol: sum of the n_slots symmetric partials; i >= n_vol:
-// sum of n_face_parts partials over the faces, face[c * (n - n_vol) + i - n_vol])
-// + sum of n_f_parts partials fpart[c * n + i]; one right-hand side
-void launch_sym_reduce(int64_t n, int64_t n_vol, int n_slots, const double2 *sym, int64_t ldp, int n_face_parts,
-                       const double2 *face, int n_f_parts, const double2 *fpart, const double2 *diag,
-                       const double2 *x, double2 *y, hipStream_t s);
+// y = diag x + (i < n_vol: sum of the n_slots symmetric partials, float2 when
+// sym32, else double2; i >= n_vol: sum of n_face_parts partials over the faces,
+// face[c * (n - n_vol) + i - n_vol]) + sum of n_f_parts partials
+// fpart[c * n + i]; one right-hand side
+void launch_sym_reduce(int64_t n, int64_t n_vol, int n_slots, const void *sym, bool sym32, int64_t ldp,
+                       int n_face_parts, const double2 *face, int n_f_parts, const double2 *fpart,
+                       const double2 *diag, const double2 *x, double2 *y, hipStream_t s);
 
 // Cell-face pairs with one evaluation per pair, one right-hand side
 // (sym_kernels.hip): cells are the points 0 .. nc-1, faces nc .. nc+nf-1; qc
@@ -248,7 +249,7 @@ struct CfJob {
     double k;
     double far[3];
     double far_step;
-    double2 *pc, *pf;
+    void *pc, *pf;  // float2 partials for VSIE_FP32, else double2
     const double *cvx = nullptr, *cvy = nullptr, *cvz = nullptr;
     const double2 *xc = nullptr;
     const int32_t *ctile_t = nullptr;
@@ -264,10 +265,11 @@ int64_t cf_groups(int64_t count);  // slots for count cells or faces
 void launch_cf(const CfJob &J, hipStream_t s, PairProfiler *prof);
 // y = diag x + (i < nc: n_sym symmetric slots + n_cs cell slots of pc;
 // i >= nc: n_fs face slots of pf + n_ff face-face chunk partials ff[c * nf + i - nc]);
+// sym, pc and pf hold float2 partials when slots32, else double2 (ff: double2);
 // adj: y = conj(diag) x + conj(w sum) with w = -s'_i for cells when adj_sp
 // (the frequency's s' of all points) is given, else 1
-void launch_cf_reduce(int64_t n, int64_t nc, int n_sym, const double2 *sym, int n_cs, const double2 *pc, int n_fs,
-                      const double2 *pf, int n_ff, const double2 *ff, const double2 *diag, const double2 *x,
+void launch_cf_reduce(int64_t n, int64_t nc, bool slots32, int n_sym, const void *sym, int n_cs, const void *pc,
+                      int n_fs, const void *pf, int n_ff, const double2 *ff, const double2 *diag, const double2 *x,
                       double2 *y, hipStream_t s, bool adj = false, const double *adj_sp = nullptr);
 
 // auxiliary kernels (aux_kernels.hip)

@@ -348,7 +348,8 @@ vsie_status vsie_release_dense(vsie_problem *p, int32_t f);
  * kind 12 and 13 the cell-face kernel in FP64 and FP32 (pairs = 2 n_vol n_srf,
  * both directions); kind 14 and 15 the far-field pattern's single-layer
  * sources, 16 and 17 its double-layer sources, in FP64 and FP32 (pairs =
- * directions x sources). */
+ * directions x sources); kind 18 and 19 the face-face double layers once per
+ * pair in FP64 and FP32 (pairs = n_srf (n_srf - 1)). */
 typedef struct {
     int64_t launches;
     double ms;

@@ -945,7 +945,7 @@ void launch_sym(const SymJob &J, hipStream_t s, PairProfiler *prof) {
     if (prof && prof->on) {
         VSIE_HIP(hipEventRecord(ev1, s));
         const double pairs = static_cast<double>(J.ng) * (J.ng - 1);
-        prof->recs.push_back(PairProfiler::Rec{ev0, ev1, 10 + (f32 ? 1 : 0), pairs, pairs});
+        prof->recs.push_back(PairProfiler::Rec{ev0, ev1, J.prof_kind + (f32 ? 1 : 0), pairs, pairs});
     }
 }
 
@@ -1039,12 +1039,12 @@ void launch_cf(const CfJob &J, hipStream_t s, PairProfiler *prof) {
 // y = diag x + (cells: symmetric slots + cell-face slots; faces: cell-face
 // slots + face-face chunk partials); one right-hand side
 void launch_cf_reduce(int64_t n, int64_t nc, bool slots32, int n_sym, const void *sym, int n_cs, const void *pc,
-                      int n_fs, const void *pf, int n_ff, const double2 *ff, const double2 *diag, const double2 *x,
-                      double2 *y, hipStream_t s, bool adj, const double *adj_sp) {
+                      int n_fs, const void *pf, int n_ff, const void *ff, bool ff32, const double2 *diag,
+                      const double2 *x, double2 *y, hipStream_t s, bool adj, const double *adj_sp) {
     if (n == 0) return;
     const int64_t nf = n - nc;
     const SlotList cells{sym, n_sym, nc, 0, pc, n_cs, nc, 0, slots32, slots32};
-    const SlotList faces{pf, n_fs, nf, 0, ff, n_ff, nf, 0, slots32, false};
+    const SlotList faces{pf, n_fs, nf, 0, ff, n_ff, nf, 0, slots32, ff32};
     launch_slot_reduce(n, nc, cells, faces, diag, x, y, s, adj, adj_sp);
 }
 

@@ -136,6 +136,9 @@ struct vsie_problem {
     int64_t f_cells = 0;
     Scratch ctile;
     std::vector<int32_t> ctile_h;  // host copy of the tile flags
+    // face-face pairs on the symmetric kernel: tile flags of the faces (all
+    // set) and zeros (the faces' single-layer charges and weights)
+    Scratch ftile, fzero;
     // cached XCD item ranges of the symmetric and cell-face kernels with
     // grad-alpha cells, per precision (valid for group size g)
     struct TRanges {
@@ -213,7 +216,8 @@ struct vsie_problem {
         for (void *p : owned) (void)hipFree(p);
         for (Scratch *s : {&partial, &chargeG, &chargeF, &chargeAll, &sums_part, &grad_work, &V, &V2, &w, &r, &ax,
                            &h1, &tc, &nrm, &dpart, &npart, &yv, &act, &act2, &live, &kd, &kc, &xa, &axa, &brc,
-                           &rres, &bh, &bg, &bsk, &defP, &defM, &defB, &defk, &lslot, &ctile})
+                           &rres, &bh, &bg, &bsk, &defP, &defM, &defB, &defk, &lslot, &ctile,
+                           &ftile, &fzero})
             s->release();
     }
 };
@@ -348,6 +352,13 @@ void build_sources(vsie_problem *p) {
         p->ctile_h = flag;
         for (auto &r : p->tranges) r.g = -1;
     }
+    if (p->m.n_srf > 0) {
+        const std::vector<int32_t> ones(static_cast<size_t>((p->m.n_srf + 63) / 64), 1);
+        void *d = p->ftile.get(sizeof(int32_t) * ones.size());
+        VSIE_HIP(hipMemcpy(d, ones.data(), sizeof(int32_t) * ones.size(), hipMemcpyHostToDevice));
+        void *z = p->fzero.get(sizeof(double2) * static_cast<size_t>(p->m.n_srf));
+        VSIE_HIP(hipMemset(z, 0, sizeof(double2) * static_cast<size_t>(p->m.n_srf)));
+    }
     auto fill = [&](SourceSet &S, const std::vector<int32_t> &ix, bool with_v) {
         S.count = static_cast<int64_t>(ix.size());
         if (S.count == 0) return;
@@ -444,29 +455,30 @@ void apply_forward_block(vsie_problem *p, int f, vsie_precision prec, int nrhs, 
 // per precision and group size.  Issue cycles per pair of the grad-alpha loops
 // relative to the single-layer ones (counted in the compiled loops):
 // symmetric kernel 1.53 (FP32) and 1.42 (FP64), cell-face kernel 1.17 and 1.42.
-// The once-per-pair kernels' slot partials, three arrays of float2 (FP32
+// The once-per-pair kernels' slot partials, four arrays of float2 (FP32
 // operator) or double2 entries, then a double2 tail for the one-sided chunk
 // partials; every array starts on a 256-byte boundary.
 struct SlotBuffers {
-    void *s[3];
+    void *s[4];
     double2 *tail;
 };
 
 SlotBuffers slot_buffers(vsie_problem *p, vsie_precision prec, std::initializer_list<int64_t> counts,
                          int64_t tail) {
-    if (counts.size() != 3) fail(VSIE_E_INVALID, "slot buffers: three slot arrays expected");
+    if (counts.size() != 4) fail(VSIE_E_INVALID, "slot buffers: four slot arrays expected");
     const size_t es = prec == VSIE_FP32 ? sizeof(float2) : sizeof(double2);
     auto up = [](size_t b) { return (b + 255) / 256 * 256; };
-    size_t off[4], at = 0;
+    size_t off[5], at = 0;
     int i = 0;
     for (int64_t c : counts) {
         off[i++] = at;
         at += up(es * static_cast<size_t>(c));
     }
-    off[3] = at;
+    off[4] = at;
     at += sizeof(double2) * static_cast<size_t>(tail);
     char *base = static_cast<char *>(p->partial.get(std::max<size_t>(256, at)));
-    return SlotBuffers{{base + off[0], base + off[1], base + off[2]}, reinterpret_cast<double2 *>(base + off[3])};
+    return SlotBuffers{{base + off[0], base + off[1], base + off[2], base + off[3]},
+                       reinterpret_cast<double2 *>(base + off[4])};
 }
 
 const vsie_problem::TRanges &t_ranges(vsie_problem *p, vsie_precision prec) {
@@ -481,22 +493,38 @@ const vsie_problem::TRanges &t_ranges(vsie_problem *p, vsie_precision prec) {
     return tr;
 }
 
+// Face-face double layers once per pair: the symmetric kernel's grad-alpha
+// loop over the faces, with the faces' v' (zero where a face carries no jump)
+// and zero single-layer charges (forward) or weights (adjoint); every face
+// tile is flagged.  Group size 2 gives enough work items for the few face
+// tiles.
+constexpr int kFaceGroups = 2;
+
+SymJob face_face_job(vsie_problem *p, vsie_precision prec, double k, const void *q, const double2 *xf, void *part) {
+    const int64_t nv = p->m.n_vol, ns = p->m.n - nv;
+    SymJob J{prec, ns, p->m.px + nv, p->m.py + nv, p->m.pz + nv, q, k, {p->far[0], p->far[1], p->far[2]},
+             p->far_step, kFaceGroups, part, ns};
+    J.vx = p->m.vpx + nv;
+    J.vy = p->m.vpy + nv;
+    J.vz = p->m.vpz + nv;
+    J.xv = xf;
+    J.tile_t = static_cast<const int32_t *>(p->ftile.p);
+    J.prof_kind = 18;
+    return J;
+}
+
 void apply_forward_cf(vsie_problem *p, int f, vsie_precision prec, const double2 *x, double2 *y, hipStream_t s) {
     const int64_t n = p->m.n, nv = p->m.n_vol, ns = n - nv;
     const int g = p->tune.sym_groups;
     const int64_t slots = sym_slots(nv, g), cs = cf_groups(ns), fs = cf_groups(nv);
-    // the double-layer sources among the faces: the tail of F
-    const int64_t fo = p->f_cells, nff = p->F.count - p->f_cells;
-    int64_t chFF = 1;
-    int ncFF = 0;
-    if (ns > 0) choose_chunks(ns, nff, p->tune.vec_target_waves, chFF, ncFF);
-    const SlotBuffers sb = slot_buffers(p, prec, {slots * nv, cs * nv, fs * ns}, static_cast<int64_t>(ncFF) * ns);
-    void *psym = sb.s[0], *pc = sb.s[1], *pf = sb.s[2];
-    double2 *pff = sb.tail;
+    const int64_t ffs = ns > 0 ? sym_slots(ns, kFaceGroups) : 0;
+    const SlotBuffers sb = slot_buffers(p, prec, {slots * nv, cs * nv, fs * ns, ffs * ns}, 0);
+    void *psym = sb.s[0], *pc = sb.s[1], *pf = sb.s[2], *pff = sb.s[3];
+    // the single-layer charges -s' x of the cells; the double layers take the
+    // raw values x
     void *qG = p->chargeG.get(csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->G.count)));
-    void *qF = p->chargeF.get(csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->F.count)));
     const double *spf = p->m.sp + static_cast<int64_t>(f) * n;
-    launch_pack_both(prec, p->G, p->F, spf, 1, x, n, false, qG, qF, s);
+    launch_pack_charges(kClassG, prec, p->G, spf, 1, x, n, false, qG, s);
     const double k = p->k0[f];
     const bool t = p->f_cells > 0;
     const int32_t *tiles_t = static_cast<const int32_t *>(p->ctile.p);
@@ -523,19 +551,12 @@ void apply_forward_cf(vsie_problem *p, int f, vsie_precision prec, const double2
             C.xr = t_ranges(p, prec).cf;
         }
         launch_cf(C, s, &p->prof);
+        const SymJob Jf = face_face_job(p, prec, k, p->fzero.p, x + nv, pff);
+        launch_sym(Jf, s, &p->prof);
     }
-    if (ncFF > 0) {
-        // every face a source in canonical order: streamed face j is target j
-        const bool ident = fo == 0 && nff == ns;
-        PairJob Jf{PAIR_FWD_F, prec, ns, p->m.px + nv, p->m.py + nv, p->m.pz + nv, {}, nff,
-                   p->F.x + fo, p->F.y + fo, p->F.z + fo, {p->F.vx + fo, p->F.vy + fo, p->F.vz + fo},
-                   static_cast<const char *>(qF) + csize(prec) * static_cast<size_t>(fo), p->F.count, 1, chFF, ncFF, k,
-                   pff, ns, ident ? SELF_IDENT : SELF_NONE, nullptr};
-        launch_pairs(Jf, s, &p->prof);
-    }
-    launch_cf_reduce(n, nv, prec == VSIE_FP32, static_cast<int>(slots), psym, static_cast<int>(cs), pc,
-                     static_cast<int>(fs), pf, ncFF,
-                     pff, p->m.diag + static_cast<int64_t>(f) * n, x, y, s);
+    const bool f32 = prec == VSIE_FP32;
+    launch_cf_reduce(n, nv, f32, static_cast<int>(slots), psym, static_cast<int>(cs), pc, static_cast<int>(fs), pf,
+                     static_cast<int>(ffs), pff, f32, p->m.diag + static_cast<int64_t>(f) * n, x, y, s);
 }
 
 void apply_forward_sym(vsie_problem *p, int f, vsie_precision prec, const double2 *x, double2 *y,
@@ -551,7 +572,7 @@ void apply_forward_sym(vsie_problem *p, int f, vsie_precision prec, const double
     int ncGf = 0, ncF = 0;
     if (ns > 0) choose_chunks(ns, p->G.count, p->tune.vec_target_waves, chGf, ncGf);
     choose_chunks(n, p->F.count, p->tune.vec_target_waves, chF, ncF);
-    const SlotBuffers sb = slot_buffers(p, prec, {slots * nv, 0, 0},
+    const SlotBuffers sb = slot_buffers(p, prec, {slots * nv, 0, 0, 0},
                                         static_cast<int64_t>(ncGf) * ns + static_cast<int64_t>(ncF) * n);
     void *psym = sb.s[0];
     double2 *pface = sb.tail, *pF = pface + static_cast<int64_t>(ncGf) * ns;
@@ -585,8 +606,9 @@ bool use_sym(const vsie_problem *p, int nrhs) {
     if (nrhs != 1 || p->tune.sym_groups <= 0 || !p->g_is_cells) return false;
     const int64_t nv = p->m.n_vol, ns = p->m.n - nv;
     double bytes = static_cast<double>(sym_slots(nv, p->tune.sym_groups)) * nv;
-    if (p->tune.cell_face)
-        bytes += static_cast<double>(cf_groups(ns)) * nv + static_cast<double>(cf_groups(nv)) * ns;
+    if (p->tune.cell_face && ns > 0)
+        bytes += static_cast<double>(cf_groups(ns)) * nv + static_cast<double>(cf_groups(nv)) * ns +
+                 static_cast<double>(sym_slots(ns, kFaceGroups)) * ns;
     return bytes * sizeof(double2) <= kSymPartialCap;
 }
 
@@ -655,12 +677,9 @@ void apply_adjoint_sym(vsie_problem *p, int f, vsie_precision prec, const double
     const int64_t n = p->m.n, nv = p->m.n_vol, ns = n - nv;
     const int g = p->tune.sym_groups;
     const int64_t slots = sym_slots(nv, g), cs = cf_groups(ns), fs = cf_groups(nv);
-    int64_t chFF = 1;
-    int ncFF = 0;
-    if (ns > 0) choose_chunks(ns, ns, p->tune.vec_target_waves, chFF, ncFF);
-    const SlotBuffers sb = slot_buffers(p, prec, {slots * nv, cs * nv, fs * ns}, static_cast<int64_t>(ncFF) * ns);
-    void *psym = sb.s[0], *pc = sb.s[1], *pf = sb.s[2];
-    double2 *pff = sb.tail;
+    const int64_t ffs = ns > 0 ? sym_slots(ns, kFaceGroups) : 0;
+    const SlotBuffers sb = slot_buffers(p, prec, {slots * nv, cs * nv, fs * ns, ffs * ns}, 0);
+    void *psym = sb.s[0], *pc = sb.s[1], *pf = sb.s[2], *pff = sb.s[3];
     void *q = p->chargeAll.get(csize(prec) * static_cast<size_t>(n));
     launch_pack_plain(prec, n, 1, x, n, true, q, s);
     const void *qf = static_cast<const char *>(q) + csize(prec) * static_cast<size_t>(nv);
@@ -695,17 +714,17 @@ void apply_adjoint_sym(vsie_problem *p, int f, vsie_precision prec, const double
             C.sw = spf;
         }
         launch_cf(C, s, &p->prof);
+        // faces' charges mu, zero single-layer weights: each face target sums
+        // its own double layer F (x_i - x_j).v'_j mu_i
+        SymJob Jf = face_face_job(p, prec, k, qf, x + nv, pff);
+        Jf.adj = true;
+        Jf.sw = static_cast<const double *>(p->fzero.p);
+        launch_sym(Jf, s, &p->prof);
     }
-    if (ncFF > 0) {
-        // faces (thread points, with v') over the faces (streamed, charges mu)
-        PairJob Jf{PAIR_ADJ_F, prec, ns, p->m.px + nv, p->m.py + nv, p->m.pz + nv,
-                   {p->m.vpx + nv, p->m.vpy + nv, p->m.vpz + nv}, ns, p->m.px + nv, p->m.py + nv, p->m.pz + nv, {},
-                   qf, ns, 1, chFF, ncFF, k, pff, ns, SELF_IDENT, nullptr};
-        launch_pairs(Jf, s, &p->prof);
-    }
-    launch_cf_reduce(n, nv, prec == VSIE_FP32, static_cast<int>(slots), psym, static_cast<int>(cs), pc,
-                     static_cast<int>(fs), pf, ncFF,
-                     pff, p->m.diag + static_cast<int64_t>(f) * n, x, y, s, true, t ? nullptr : spf);
+    const bool f32 = prec == VSIE_FP32;
+    launch_cf_reduce(n, nv, f32, static_cast<int>(slots), psym, static_cast<int>(cs), pc, static_cast<int>(fs), pf,
+                     static_cast<int>(ffs), pff, f32, p->m.diag + static_cast<int64_t>(f) * n, x, y, s, true,
+                     t ? nullptr : spf);
 }
 
 void apply_adjoint(vsie_problem *p, int f, vsie_precision prec, int nrhs, const double2 *x,
@@ -2361,7 +2380,7 @@ vsie_status vsie_profile(vsie_problem *p, int32_t enable) {
 vsie_status vsie_profile_read(vsie_problem *p, int32_t kind, vsie_kernel_stats *out) {
     return guarded([&] {
         require(p != nullptr && out != nullptr, "NULL argument");
-        require(kind >= 0 && kind < 18, "kernel kind out of range");
+        require(kind >= 0 && kind < 20, "kernel kind out of range");
         vsie_kernel_stats st{0, 0.0, 0.0, 0.0};
         for (auto &r : p->prof.recs) {
             if (r.kind != kind) continue;

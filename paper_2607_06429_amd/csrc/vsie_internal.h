@@ -212,6 +212,7 @@ struct SymJob {
     // the targets' weights, (-s'_i e + F (x_j - x_i).v'_i) mu_j; sw = s' of the cells
     bool adj = false;
     const double *sw = nullptr;
+    int prof_kind = 10;  // profiler kind of the FP64 launch (FP32: + 1)
 };
 bool sym_groups_ok(int g);
 // Item ranges of the 8 XCDs (9 boundaries) with equal modelled work when the
@@ -265,12 +266,13 @@ int64_t cf_groups(int64_t count);  // slots for count cells or faces
 void launch_cf(const CfJob &J, hipStream_t s, PairProfiler *prof);
 // y = diag x + (i < nc: n_sym symmetric slots + n_cs cell slots of pc;
 // i >= nc: n_fs face slots of pf + n_ff face-face chunk partials ff[c * nf + i - nc]);
-// sym, pc and pf hold float2 partials when slots32, else double2 (ff: double2);
+// sym, pc and pf hold float2 partials when slots32, else double2; ff holds
+// float2 when ff32, else double2;
 // adj: y = conj(diag) x + conj(w sum) with w = -s'_i for cells when adj_sp
 // (the frequency's s' of all points) is given, else 1
 void launch_cf_reduce(int64_t n, int64_t nc, bool slots32, int n_sym, const void *sym, int n_cs, const void *pc,
-                      int n_fs, const void *pf, int n_ff, const double2 *ff, const double2 *diag, const double2 *x,
-                      double2 *y, hipStream_t s, bool adj = false, const double *adj_sp = nullptr);
+                      int n_fs, const void *pf, int n_ff, const void *ff, bool ff32, const double2 *diag,
+                      const double2 *x, double2 *y, hipStream_t s, bool adj = false, const double *adj_sp = nullptr);
 
 // auxiliary kernels (aux_kernels.hip)
 void launch_weights(const DeviceMesh &m, const double *k0, int n_freq, hipStream_t s);

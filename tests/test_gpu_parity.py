@@ -536,8 +536,8 @@ def test_cell_face_pairs(V, name, prec):
     single layer and the adjoint double layer of the cell at the face, the
     double layer of the face at the cell), the cells' adjoint double layers
     alongside the cell-cell single layer (lognormal: every cell has grad
-    alpha) and the one-sided face-face sum over the weighted faces only
-    (single: the Gamma_2 faces carry no jump), against the oracle and against
+    alpha) and the face-face double layers once per pair (single: the Gamma_2
+    faces carry no jump, so their v' is zero), against the oracle and against
     the separate one-sided kernels."""
     mesh, mat, k0 = case(name)
     d = O.discretise(mesh, mat, k0)
@@ -557,9 +557,10 @@ def test_cell_face_pairs(V, name, prec):
     e, e0 = O.rel_error(y, ref), O.rel_error(y, y0)
     say("  %s %s fused %s: rel err %.2e, vs separate kernels %.2e" % (name, prec, fused, e, e0))
     assert fused
-    # the one-sided double-layer sum runs over face targets and weighted faces only
-    ff = st.get("fwd_double_layers_" + prec, {"pairs": 0.0})["pairs"]
-    assert ff <= float(mesh.n_srf) * mesh.n_srf
+    # the face-face double layers run once per pair on the symmetric kernel
+    # (ordered face pairs), with no one-sided double-layer launch
+    assert st["face_face_" + prec]["pairs"] == float(mesh.n_srf) * (mesh.n_srf - 1)
+    assert ("fwd_double_layers_" + prec) not in st
     assert e <= tol and e0 <= 2 * tol
     P.close()
 

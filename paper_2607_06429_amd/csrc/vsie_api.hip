@@ -971,10 +971,17 @@ std::vector<double> column_norms(vsie_problem *p, const double2 *W, int nslots, 
 
 using cd = std::complex<double>;
 
-// run fn(i) for i in [0, count) on up to 16 host threads
+// run fn(i) for i in [0, count) on up to 16 host threads; `work` is the
+// whole loop's approximate flop count.  Starting and joining the threads
+// costs a few hundred microseconds, so loops below kThreadMinWork (about that
+// much serial work) run on the calling thread.
+constexpr double kThreadMinWork = 1e6;
+
 template <typename Fn>
-void parallel_for(int count, Fn fn) {
-    const int nt = std::max(1, std::min<int>({count, 16, static_cast<int>(std::thread::hardware_concurrency())}));
+void parallel_for(int count, double work, Fn fn) {
+    const int nt = work < kThreadMinWork
+                       ? 1
+                       : std::max(1, std::min<int>({count, 16, static_cast<int>(std::thread::hardware_concurrency())}));
     if (nt <= 1) {
         for (int i = 0; i < count; ++i) fn(i);
         return;
@@ -1119,7 +1126,7 @@ int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
     int32_t *kcs_d = nullptr, *lslot_d = nullptr;
     if (use && kmax > 0) {
         std::vector<double2> Ph(pm * ns, make_double2(0.0, 0.0)), Mh(pm * ns, make_double2(0.0, 0.0));
-        parallel_for(ns, [&](int sl) {
+        parallel_for(ns, 24.0 * ns * (kmax + 1) * kmax, [&](int sl) {
             const RecycleRhs &q = use->rhs[rhs[sl]];
             if (q.k == 0) return;
             std::vector<cd> t(q.k + 1), v(q.k + 1);
@@ -1665,7 +1672,7 @@ int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const
         const std::vector<cd> z = use->deflate_coeffs(p, n, Ra, Rres, Dd, s);
         zgemm(p, false, n, Ra, kv, -1.0, use->V, n, Dd, kv, 1.0, Rres, n);
         std::vector<double2> yh(static_cast<size_t>(kr) * Ra);
-        parallel_for(Ra, [&](int c) {
+        parallel_for(Ra, 4.0 * Ra * kr * kr, [&](int c) {
             const std::vector<cd> y0 = use->r_solve(std::vector<cd>(z.begin() + static_cast<size_t>(c) * kr,
                                                                     z.begin() + static_cast<size_t>(c + 1) * kr));
             for (int64_t i = 0; i < kr; ++i) yh[static_cast<size_t>(c) * kr + i] = make_double2(y0[i].real(), y0[i].imag());
@@ -1717,7 +1724,7 @@ int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const
             for (int i = 0; i <= c; ++i) Hc[static_cast<size_t>(c) * (kb + Ra) + kb + i] = T[static_cast<size_t>(c) * Ra + i];
         // previous reflectors on the new columns (independent per column)
         const int64_t c0 = static_cast<int64_t>(j) * Ra;
-        parallel_for(Ra, [&](int c) {
+        parallel_for(Ra, 8.0 * Ra * c0 * (Ra + 1), [&](int c) {
             cd *h = &Hc[static_cast<size_t>(c) * (kb + Ra)];
             for (int64_t k = 0; k < c0; ++k) apply_reflector(&U[static_cast<size_t>(k) * (Ra + 1)], UU[k], Ra + 1, h + k);
         });
@@ -1757,7 +1764,7 @@ int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const
     // Wc = R_use^{-1} (Bm Y), the coefficients of U (Bm Y) in the recycled basis
     const int64_t kk = static_cast<int64_t>(jdone) * Ra;
     std::vector<double2> Yh(static_cast<size_t>(kk) * Ra), Wc(static_cast<size_t>(kr) * Ra);
-    parallel_for(Ra, [&](int rc) {
+    parallel_for(Ra, 4.0 * Ra * (kk * kk + 2 * kr * kk + kr * kr), [&](int rc) {
         std::vector<cd> y(kk);
         for (int64_t i = kk - 1; i >= 0; --i) {
             cd acc = G[static_cast<size_t>(rc) * ldH + i];
@@ -1823,7 +1830,7 @@ std::vector<cd> BlockRecycle::deflate_coeffs(vsie_problem *p, int64_t n, int Ra2
     to_host(th, Dd, static_cast<size_t>(kv) * Ra2, s);
     std::vector<cd> z(static_cast<size_t>(k) * Ra2);
     std::vector<double2> vh(static_cast<size_t>(kv) * Ra2);
-    parallel_for(Ra2, [&](int c) {
+    parallel_for(Ra2, 16.0 * Ra2 * kv * (Ra + 1), [&](int c) {
         std::vector<cd> t(kv);
         for (int64_t i = 0; i < kv; ++i) t[i] = cd(th[static_cast<size_t>(c) * kv + i].x, th[static_cast<size_t>(c) * kv + i].y);
         qh(t);

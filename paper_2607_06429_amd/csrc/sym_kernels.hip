@@ -792,6 +792,7 @@ const void *sym_ptr(bool t, bool adj) {
 }
 
 const void *pick_sym(int g, bool f32, bool t, bool adj) {
+    if (g == 1) return f32 ? sym_ptr<1, float>(t, adj) : sym_ptr<1, double>(t, adj);
     if (g == 2) return f32 ? sym_ptr<2, float>(t, adj) : sym_ptr<2, double>(t, adj);
     if (g == 4) return f32 ? sym_ptr<4, float>(t, adj) : sym_ptr<4, double>(t, adj);
     if (g == 8) return f32 ? sym_ptr<8, float>(t, adj) : sym_ptr<8, double>(t, adj);
@@ -887,7 +888,7 @@ void cf_cost_ranges(int64_t nc, int64_t nf, const std::vector<int32_t> &tile_t, 
     cost_ranges(cgroups * fgroups, weight, [&](int64_t it) { return gt[static_cast<size_t>(it / fgroups)] != 0; }, xr);
 }
 
-bool sym_groups_ok(int g) { return g == 2 || g == 4 || g == 8; }
+bool sym_groups_ok(int g) { return g == 1 || g == 2 || g == 4 || g == 8; }
 
 int64_t sym_slots(int64_t ng, int g) {
     const int64_t tiles = (ng + 63) / 64;

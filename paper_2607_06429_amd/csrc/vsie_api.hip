@@ -443,18 +443,6 @@ void apply_forward_block(vsie_problem *p, int f, vsie_precision prec, int nrhs, 
                            ldx, y, ldy, nullptr, s);
 }
 
-// y = A_f x for one right-hand side with the cell-cell single layer evaluated
-// once per unordered pair: the symmetric kernel for cell targets, the vector
-// kernel for face targets (no face is a single-layer source, so nothing is
-// masked there), the double layers over every target, one reduction.
-// The same with the cell-face pairs fused as well (every double-layer source
-// is a face): symmetric cell-cell single layer, cell-face kernel (single layer
-// at faces, double layers at cells), face-face double layers one-sided, one
-// reduction.
-// XCD item ranges of the once-per-pair kernels with grad-alpha cells, cached
-// per precision and group size.  Issue cycles per pair of the grad-alpha loops
-// relative to the single-layer ones (counted in the compiled loops):
-// symmetric kernel 1.53 (FP32) and 1.42 (FP64), cell-face kernel 1.17 and 1.42.
 // The once-per-pair kernels' slot partials, four arrays of float2 (FP32
 // operator) or double2 entries, then a double2 tail for the one-sided chunk
 // partials; every array starts on a 256-byte boundary.
@@ -481,6 +469,19 @@ SlotBuffers slot_buffers(vsie_problem *p, vsie_precision prec, std::initializer_
                        reinterpret_cast<double2 *>(base + off[4])};
 }
 
+// y = A_f x for one right-hand side with the cell-cell single layer evaluated
+// once per unordered pair: the symmetric kernel for cell targets, the vector
+// kernel for face targets (no face is a single-layer source, so nothing is
+// masked there), the double layers over every target, one reduction.
+// The same with the cell-face and face-face pairs once per pair as well:
+// symmetric cell-cell single layer (and adjoint double layer of grad-alpha
+// cells), cell-face kernel (single layer at faces, double layers at cells),
+// face-face double layers on the symmetric kernel, one reduction.
+
+// XCD item ranges of the once-per-pair kernels with grad-alpha cells, cached
+// per precision and group size.  Issue cycles per pair of the grad-alpha loops
+// relative to the single-layer ones (counted in the compiled loops):
+// symmetric kernel 1.53 (FP32) and 1.42 (FP64), cell-face kernel 1.17 and 1.42.
 const vsie_problem::TRanges &t_ranges(vsie_problem *p, vsie_precision prec) {
     const int g = p->tune.sym_groups;
     vsie_problem::TRanges &tr = p->tranges[prec == VSIE_FP32 ? 1 : 0];
@@ -599,8 +600,9 @@ void apply_forward_sym(vsie_problem *p, int f, vsie_precision prec, const double
                       p->m.diag + static_cast<int64_t>(f) * n, x, y, s);
 }
 
-// The once-per-pair kernels write one FP64 partial per point and partner
-// group; above this size (c4-scale meshes) the one-sided kernels are used.
+// The once-per-pair kernels write one partial per point and partner group
+// (counted here at the FP64 size); above this size (c4-scale meshes) the
+// one-sided kernels are used.
 constexpr double kSymPartialCap = 8.0 * (1 << 30);
 
 bool use_sym(const vsie_problem *p, int nrhs) {

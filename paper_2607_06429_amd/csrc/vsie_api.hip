@@ -139,6 +139,10 @@ struct vsie_problem {
     // face-face pairs on the symmetric kernel: tile flags of the faces (all
     // set) and zeros (the faces' single-layer charges and weights)
     Scratch ftile, fzero;
+    // host copies of the point positions (fixed at assembly) and of the class
+    // lists the device source sets were built from
+    std::vector<double> hpx, hpy, hpz;
+    std::vector<int32_t> gi_built, fi_built;
     // cached XCD item ranges of the symmetric and cell-face kernels with
     // grad-alpha cells, per precision (valid for group size g)
     struct TRanges {
@@ -310,10 +314,15 @@ void build_sources(vsie_problem *p) {
     VSIE_HIP(hipMemcpy(vp.data(), p->m.vpx, sizeof(double) * n, hipMemcpyDeviceToHost));
     VSIE_HIP(hipMemcpy(vp.data() + n, p->m.vpy, sizeof(double) * n, hipMemcpyDeviceToHost));
     VSIE_HIP(hipMemcpy(vp.data() + 2 * n, p->m.vpz, sizeof(double) * n, hipMemcpyDeviceToHost));
-    std::vector<double> px(n), py(n), pz(n);
-    VSIE_HIP(hipMemcpy(px.data(), p->m.px, sizeof(double) * n, hipMemcpyDeviceToHost));
-    VSIE_HIP(hipMemcpy(py.data(), p->m.py, sizeof(double) * n, hipMemcpyDeviceToHost));
-    VSIE_HIP(hipMemcpy(pz.data(), p->m.pz, sizeof(double) * n, hipMemcpyDeviceToHost));
+    if (static_cast<int64_t>(p->hpx.size()) != n) {
+        p->hpx.resize(n);
+        p->hpy.resize(n);
+        p->hpz.resize(n);
+        VSIE_HIP(hipMemcpy(p->hpx.data(), p->m.px, sizeof(double) * n, hipMemcpyDeviceToHost));
+        VSIE_HIP(hipMemcpy(p->hpy.data(), p->m.py, sizeof(double) * n, hipMemcpyDeviceToHost));
+        VSIE_HIP(hipMemcpy(p->hpz.data(), p->m.pz, sizeof(double) * n, hipMemcpyDeviceToHost));
+    }
+    const std::vector<double> &px = p->hpx, &py = p->hpy, &pz = p->hpz;
     for (double v : sp) require(std::isfinite(v), "non-finite single-layer weight");
     for (double v : vp) require(std::isfinite(v), "non-finite double-layer weight");
     std::vector<int32_t> gi, fi;
@@ -323,8 +332,12 @@ void build_sources(vsie_problem *p) {
         if (g) gi.push_back(static_cast<int32_t>(e));
         if (vp[e] != 0.0 || vp[n + e] != 0.0 || vp[2 * n + e] != 0.0) fi.push_back(static_cast<int32_t>(e));
     }
-    p->free_sources(p->G);
-    p->free_sources(p->F);
+    // the class lists of the previous materials: G keeps its device arrays
+    // (positions only), F its positions with the new v'
+    const bool keep_g = !gi.empty() && gi == p->gi_built && p->G.idx;
+    const bool keep_f = !fi.empty() && fi == p->fi_built && p->F.idx;
+    if (!keep_g) p->free_sources(p->G);
+    if (!keep_f) p->free_sources(p->F);
     // padding point of the matrix-core layout: farther than the extent of the
     // mesh from every point (its pairs are finite and meet zero charges)
     double lo3[3] = {px[0], py[0], pz[0]}, hi3[3] = {px[0], py[0], pz[0]};
@@ -352,7 +365,7 @@ void build_sources(vsie_problem *p) {
         p->ctile_h = flag;
         for (auto &r : p->tranges) r.g = -1;
     }
-    if (p->m.n_srf > 0) {
+    if (p->m.n_srf > 0 && !p->ftile.p) {
         const std::vector<int32_t> ones(static_cast<size_t>((p->m.n_srf + 63) / 64), 1);
         void *d = p->ftile.get(sizeof(int32_t) * ones.size());
         VSIE_HIP(hipMemcpy(d, ones.data(), sizeof(int32_t) * ones.size(), hipMemcpyHostToDevice));
@@ -392,8 +405,29 @@ void build_sources(vsie_problem *p) {
         S.vz = p->upload(vc.data(), S.count);
         S.pv = p->upload(pv.data(), S.count + kMfmaPad);
     };
-    fill(p->G, gi, false);
-    fill(p->F, fi, true);
+    if (!keep_g) fill(p->G, gi, false);
+    if (keep_f) {
+        // same F points: only their v' changed (queued products that read
+        // the old values finish first)
+        VSIE_HIP(hipDeviceSynchronize());
+        const int64_t cnt = p->F.count;
+        std::vector<double> va(cnt), vb(cnt), vc(cnt);
+        std::vector<double4> pv(cnt + kMfmaPad, make_double4(0.0, 0.0, 0.0, 0.0));
+        for (int64_t j = 0; j < cnt; ++j) {
+            va[j] = vp[fi[j]];
+            vb[j] = vp[n + fi[j]];
+            vc[j] = vp[2 * n + fi[j]];
+            pv[j] = make_double4(va[j], vb[j], vc[j], 0.0);
+        }
+        VSIE_HIP(hipMemcpy(p->F.vx, va.data(), sizeof(double) * cnt, hipMemcpyHostToDevice));
+        VSIE_HIP(hipMemcpy(p->F.vy, vb.data(), sizeof(double) * cnt, hipMemcpyHostToDevice));
+        VSIE_HIP(hipMemcpy(p->F.vz, vc.data(), sizeof(double) * cnt, hipMemcpyHostToDevice));
+        VSIE_HIP(hipMemcpy(p->F.pv, pv.data(), sizeof(double4) * (cnt + kMfmaPad), hipMemcpyHostToDevice));
+    } else {
+        fill(p->F, fi, true);
+    }
+    p->gi_built = gi;
+    p->fi_built = fi;
 }
 
 void check_problem(const vsie_problem *p, int32_t f) {

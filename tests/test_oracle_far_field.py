@@ -97,3 +97,60 @@ def test_discrete_far_field_converges_to_the_series():
     # relative to the scattered field alone (the exterior-field check of the
     # same solutions includes the incident wave and reads 0.36% .. 0.17%)
     assert errs[0] > errs[1] > errs[2] and errs[2] < 0.015, errs
+
+
+def _reciprocity_error(N, rho1, rho2, k0=2.0):
+    """max over 6 incidences d and 5 directions x of the far-field pattern of
+    the oracle's discrete solution: |f(x; d) - f(-d; -x)|, relative (2-norm
+    over the 30 pairs)."""
+    mesh = W.nested_balls(N)
+    mat = W.materials_piecewise(mesh, 1.0, 1.0, rho1, 1.5, rho2, 0.8)
+    d = O.discretise(mesh, mat, k0)
+    D = W.fibonacci_sphere(6)
+    X = W.fibonacci_sphere(5) @ np.array([[0.0, 1.0, 0.0], [0.0, 0.0, 1.0], [1.0, 0.0, 0.0]])
+    P = O.solve_lu(d, O.plane_wave(d.pts, k0, np.vstack([D, -X])))
+    f_xd = O.far_field(d, X, P[:, :6])      # f(x_i; d_j)
+    f_rev = O.far_field(d, -D, P[:, 6:])    # f(-d_j; -x_i)
+    return O.rel_error(f_xd, f_rev.T)
+
+
+def test_reciprocity_of_the_discrete_solution():
+    """Reciprocity f(x; d) = f(-d; -x) of the far-field pattern (section 2.3.1
+    representation formula as |x| -> infinity) for the oracle's own LU
+    solutions.  With constant density (the Lippmann-Schwinger case, Remark after
+    Theorem 3) diag(s) A is complex-symmetric, so the discrete pattern is
+    reciprocal up to rounding; with density jumps the interface terms break the
+    discrete symmetry and the defect must fall under refinement (about O(h^2):
+    1.9e-3, 9.1e-4, 4.7e-4 for N = 8, 12, 16)."""
+    for N in (8, 12):
+        assert _reciprocity_error(N, 1.0, 1.0) < 1e-12
+    e = [_reciprocity_error(N, 1.2, 2.0) for N in (8, 12, 16)]
+    assert e[0] > e[1] > e[2] and e[0] / e[2] > 3 and e[2] < 1e-3, e
+
+
+def _discrete_optical_theorem(N, rho1, rho2, k0=2.0):
+    mesh = W.nested_balls(N)
+    mat = W.materials_piecewise(mesh, 1.0, 1.0, rho1, 1.5, rho2, 0.8)
+    d = O.discretise(mesh, mat, k0)
+    inc = np.array([0.0, 0.0, 1.0])
+    p = O.solve_lu(d, O.plane_wave(d.pts, k0, inc))
+    # Gauss-Legendre in cos(theta) x uniform in phi
+    mu, w = np.polynomial.legendre.leggauss(64)
+    ph = np.linspace(0.0, 2 * math.pi, 128, endpoint=False)
+    st = np.sqrt(1 - mu ** 2)
+    X = np.stack([np.outer(st, np.cos(ph)).ravel(), np.outer(st, np.sin(ph)).ravel(),
+                  np.repeat(mu, ph.size)], axis=1)
+    wt = np.repeat(w, ph.size) * (2 * math.pi / ph.size)
+    scat = float(np.sum(wt * np.abs(O.far_field(d, X, p)) ** 2))
+    ext = 4 * math.pi / k0 * O.far_field(d, inc[None, :], p)[0].imag
+    return abs(scat - ext) / ext
+
+
+def test_optical_theorem_of_the_discrete_solution():
+    """Lossless media: int |f|^2 dOmega = (4 pi / k0) Im f(d; d) for the far
+    field of the oracle's discrete solution; a continuous-problem identity, so
+    its defect must fall under refinement (constant density: 2.9e-4, 5.4e-5,
+    1.1e-5; density jumps: 7.8e-4, 3.4e-4, 1.7e-4 for N = 8, 12, 16)."""
+    for rho1, rho2, last in ((1.0, 1.0, 5e-5), (1.2, 2.0, 5e-4)):
+        e = [_discrete_optical_theorem(N, rho1, rho2) for N in (8, 12, 16)]
+        assert e[0] > e[1] > e[2] and e[2] < last, (rho1, rho2, e)

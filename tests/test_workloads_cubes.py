@@ -93,3 +93,40 @@ def test_analytic_and_stencil_grad_alpha_agree_under_refinement():
         far = inner & np.all(np.abs(mesh.vol_xyz) < 1.5, axis=1)
         errs.append(np.sqrt(np.mean((ga[far] - gs[far]) ** 2)))
     assert errs[1] < errs[0] / 3 and errs[2] < errs[1] / 3
+
+
+@pytest.mark.parametrize("mesh_kind", ["balls", "cubes"])
+def test_grad_alpha_stencil_exact_for_linear_alpha(mesh_kind):
+    """A density with alpha = rho0/rho - 1 linear in x: every branch of the
+    neighbour stencil (central, one-sided up, one-sided down) differentiates a
+    linear function exactly, on uniform and nonuniform grids, so grad alpha
+    must equal the constant gradient on every cell and axis with a neighbour in
+    the same subdomain -- including the one-sided cells next to Gamma_1 and
+    Gamma_2 -- and be zero where the axis has none."""
+    if mesh_kind == "balls":
+        mesh = W.nested_balls(10)
+    else:
+        mesh = W.nested_cubes(2, 5, 7.0, 5.0)
+    rho0 = 1.3
+    g = np.array([0.11, -0.07, 0.05])
+    a0 = np.where(mesh.vol_dom == 2, 0.4, 0.2)     # a jump between the subdomains
+    a = a0 + mesh.vol_xyz @ g
+    rho = rho0 / (1.0 + a)
+    assert np.all(rho > 0)
+    ga = O.grad_alpha_stencil(mesh, O.alpha(rho, rho0))
+    dom = mesh.vol_dom
+    seen = {"central": 0, "up": 0, "down": 0, "none": 0}
+    for ax in range(3):
+        lo = mesh.vol_nb[:, 2 * ax].astype(np.int64)
+        hi = mesh.vol_nb[:, 2 * ax + 1].astype(np.int64)
+        lo_ok = (lo >= 0) & (dom[np.maximum(lo, 0)] == dom)
+        hi_ok = (hi >= 0) & (dom[np.maximum(hi, 0)] == dom)
+        has = lo_ok | hi_ok
+        np.testing.assert_allclose(ga[has, ax], g[ax], rtol=0, atol=1e-12)
+        assert np.all(ga[~has, ax] == 0.0)
+        seen["central"] += int(np.sum(lo_ok & hi_ok))
+        seen["up"] += int(np.sum(hi_ok & ~lo_ok))
+        seen["down"] += int(np.sum(lo_ok & ~hi_ok))
+        seen["none"] += int(np.sum(~has))
+    # every branch ran, the one-sided ones at the interfaces
+    assert min(seen["central"], seen["up"], seen["down"]) > 0, seen

@@ -74,7 +74,7 @@ def measured_traffic(key):
     size), or None when no record exists or the kernel source has changed
     since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2607_06429_amd", "pmc_traffic.json")
+    path = os.path.join(ROOT, "measurement", "pmc_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path)).get(key)
@@ -183,7 +183,7 @@ def far_field_pattern(V, P, x):
     ph = np.arange(360) * (2 * math.pi / 360)
     TH, PH = np.meshgrid(th, ph, indexing="ij")
     X = np.stack([(np.sin(TH) * np.cos(PH)).ravel(), (np.sin(TH) * np.sin(PH)).ravel(), np.cos(TH).ravel()], axis=1)
-    counts = json.load(open(os.path.join(ROOT, "paper_2607_06429_amd", "isa_counts.json")))
+    counts = json.load(open(os.path.join(ROOT, "measurement", "isa_counts.json")))
     res = {"directions": int(X.shape[0])}
     pats = {}
     for name, prec in (("fp32", V.VSIE_FP32), ("fp64", V.VSIE_FP64)):
@@ -217,7 +217,7 @@ def exterior_slice(V, P, x, dirs):
     X, Y = np.meshgrid(g, g, indexing="ij")
     pts = np.stack([X.ravel(), Y.ravel(), np.zeros(X.size)], axis=1)
     pts = pts[np.max(np.abs(pts[:, :2]), axis=1) > 3.5]
-    counts = json.load(open(os.path.join(ROOT, "paper_2607_06429_amd", "isa_counts.json")))
+    counts = json.load(open(os.path.join(ROOT, "measurement", "isa_counts.json")))
     res = {"points": int(pts.shape[0])}
     for name, prec in (("fp32", V.VSIE_FP32), ("fp64", V.VSIE_FP64)):
         P.field(pts, x, prec=prec)
@@ -462,7 +462,7 @@ def main():
     # roofline of the dominant kernel (the FP32 single-layer pair kernel):
     # issue cycles per pair counted in its compiled inner loop x pairs per
     # launch / average launch time, against 256 CUs x 4 SIMDs x 2.4 GHz
-    counts = json.load(open(os.path.join(ROOT, "paper_2607_06429_amd", "isa_counts.json")))
+    counts = json.load(open(os.path.join(ROOT, "measurement", "isa_counts.json")))
     dom = max(kstats.items(), key=lambda kv: kv[1]["ms"])
     dom_name, st = dom
     per_pair = counts[dom_name + "_R1"]["cycles_per_pair"]

@@ -110,12 +110,20 @@ vsie_status vsie_assemble(const vsie_geometry *geom, const double *vrho, const d
 
 /* Replace the per-cell materials from DEVICE arrays (n_vol doubles each) and
  * recompute every weight (used between solves of an optimisation loop).  The
- * set of nonzero source terms may change; the call synchronises `stream`. */
+ * set of nonzero source terms may change; the call synchronises `stream`.
+ * Materials that are not positive and finite are rejected with VSIE_E_INVALID
+ * before anything is written: the problem keeps its previous materials,
+ * weights and sources. */
 vsie_status vsie_set_materials(vsie_problem *p, const double *vrho_dev, const double *vc_dev,
                                void *stream);
 
 /* Number of unknowns n = n_vol + n_srf (0 for a NULL handle). */
 int64_t vsie_size(const vsie_problem *p);
+
+/* Number of volume cells n_vol (the length of the material arrays of
+ * vsie_set_materials and of the gradients of vsie_param_gradient; 0 for a
+ * NULL handle). */
+int64_t vsie_num_cells(const vsie_problem *p);
 
 /* y = A_f x for nrhs right-hand sides at frequency index f.
  * x, y: device complex128, n x nrhs, leading dimensions ldx, ldy; x and y

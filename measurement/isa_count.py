@@ -1,7 +1,7 @@
 """Count instructions and SIMD issue cycles per pair in the compiled pair
 kernels' inner loops.
 
-    python paper_2607_06429_amd/isa_count.py
+    python measurement/isa_count.py
 
 Compiles csrc/pair_kernels.hip, csrc/mfma_kernels.hip, csrc/sym_kernels.hip
 and csrc/far_field.hip to gfx950 assembly
@@ -24,7 +24,8 @@ Issue-cycle model (SIMD cycles one wave64 instruction occupies; the chip has
 Microbenchmarks on MI355X give 2.5-2.8, 4.4-5.8, 8.5, 16.3, 32.5 and 4.1 cycles
 with 8 independent chains per lane, and show matrix-core and VALU time adding
 up (no overlap) for FP32.  Writes isa_counts.json beside this file; bench.py
-reads it to turn measured pair rates into issue cycles per second.
+reads it to turn measured pair rates into issue cycles per second.  This is
+measurement tooling for the benchmark, not part of the library.
 """
 from __future__ import annotations
 
@@ -37,7 +38,7 @@ import sys
 import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-sys.path.insert(0, HERE)
+sys.path.insert(0, os.path.join(os.path.dirname(HERE), "paper_2607_06429_amd"))
 import build as B  # noqa: E402
 
 MODES = {0: "fwd_single_layer", 1: "fwd_double_layers", 2: "adj_double_layers", 3: "source_sums"}

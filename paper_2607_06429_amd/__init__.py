@@ -23,7 +23,7 @@ __all__ = [
     "vsie_plane_wave", "vsie_field", "vsie_far_field", "vsie_source_sums", "vsie_plane_wave_at", "vsie_adjoint_rhs",
     "vsie_param_gradient", "vsie_assemble_dense", "vsie_release_dense", "vsie_profile",
     "vsie_profile_read", "vsie_destroy", "vsie_last_error",
-    "vsie_size", "vsie_matvec_multi", "vsie_get_tuning", "vsie_set_tuning", "vsie_autotune",
+    "vsie_size", "vsie_num_cells", "vsie_matvec_multi", "vsie_get_tuning", "vsie_set_tuning", "vsie_autotune",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -90,6 +90,8 @@ def _load():
     L.vsie_set_materials.argtypes = [_P, _P, _P, _P]
     L.vsie_size.argtypes = [_P]
     L.vsie_size.restype = _I64
+    L.vsie_num_cells.argtypes = [_P]
+    L.vsie_num_cells.restype = _I64
     L.vsie_matvec.argtypes = [_P, _I32, _I32, _I64, _P, _I64, _P, _I64, _P]
     L.vsie_matvec_adjoint.argtypes = [_P, _I32, _I32, _I64, _P, _I64, _P, _I64, _P]
     L.vsie_solve.argtypes = [_P, _I32, _I32, _I32, _I64, _P, _I64, _P, _I64,
@@ -124,7 +126,7 @@ def _load():
 
 lib = _load()
 
-EXPORTED = ("vsie_assemble", "vsie_set_materials", "vsie_size", "vsie_matvec",
+EXPORTED = ("vsie_assemble", "vsie_set_materials", "vsie_size", "vsie_num_cells", "vsie_matvec",
             "vsie_matvec_adjoint", "vsie_solve", "vsie_plane_wave", "vsie_field", "vsie_far_field",
             "vsie_source_sums", "vsie_plane_wave_at", "vsie_adjoint_rhs", "vsie_param_gradient",
             "vsie_assemble_dense", "vsie_release_dense", "vsie_profile", "vsie_profile_read",
@@ -226,11 +228,21 @@ def vsie_assemble(geom: dict, vrho, vc, k0, stream=None):
 
 
 def vsie_set_materials(h, vrho_dev, vc_dev, stream=None):
+    """vrho_dev, vc_dev: float64 CUDA tensors of n_vol entries each (the C entry
+    point reads that many from each pointer, so the lengths are checked here)."""
+    nv = vsie_num_cells(h)
+    for name, t in (("rho", vrho_dev), ("c", vc_dev)):
+        if t.numel() != nv:
+            raise ValueError("%s holds %d values, the problem has %d cells" % (name, t.numel(), nv))
     _check(lib.vsie_set_materials(h, _dptr(vrho_dev), _dptr(vc_dev), _stream(stream)))
 
 
 def vsie_size(h) -> int:
     return int(lib.vsie_size(h))
+
+
+def vsie_num_cells(h) -> int:
+    return int(lib.vsie_num_cells(h))
 
 
 def vsie_matvec(h, f, prec, x, y, stream=None):
@@ -438,6 +450,8 @@ class Problem:
         self.k0 = list(np.atleast_1d(k0).astype(float))
         self.handle = vsie_assemble(geom, vrho, vc, self.k0, stream)
         self.n = vsie_size(self.handle)
+        self.n_vol = vsie_num_cells(self.handle)
+        self.material_version = 0   # bumped by every accepted set_materials
 
     @classmethod
     def from_mesh(cls, mesh, mat, k0, stream=None, grad_alpha=None, grad_rho=None):
@@ -539,6 +553,7 @@ class Problem:
 
     def set_materials(self, rho_dev, c_dev):
         vsie_set_materials(self.handle, rho_dev, c_dev)
+        self.material_version += 1
 
     def plane_wave_at(self, targets, dirs, f=0):
         import torch

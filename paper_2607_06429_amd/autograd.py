@@ -21,20 +21,29 @@ class ReceiverPressure(torch.autograd.Function):
     @staticmethod
     def forward(ctx, c, rho, problem: Problem, n_vol: int, dirs, receivers, f: int, prec: int,
                 tol: float, block: bool):
-        problem.set_materials(rho.detach().contiguous(), c.detach().contiguous())
+        rho_f, c_f = rho.detach().contiguous(), c.detach().contiguous()
+        problem.set_materials(rho_f, c_f)
         b = problem.plane_wave(np.atleast_2d(dirs), f=f)
         P, info = problem.solve(b, f=f, prec=prec, tol=tol, block=block)
         p_rec = problem.plane_wave_at(receivers, dirs, f=f) - problem.field(receivers, P, f=f)
         ctx.problem, ctx.n_vol, ctx.receivers, ctx.f, ctx.prec, ctx.tol, ctx.block = (
             problem, n_vol, receivers, f, prec, tol, block)
         ctx.info = info
-        ctx.save_for_backward(P)
+        # the adjoint operator and the chain rule read the problem's current
+        # materials: remember which ones this forward used
+        ctx.version = problem.material_version
+        ctx.save_for_backward(P, rho_f.clone(), c_f.clone())
         return p_rec
 
     @staticmethod
     def backward(ctx, grad_out):
-        (P,) = ctx.saved_tensors
+        P, rho_f, c_f = ctx.saved_tensors
         pb: Problem = ctx.problem
+        if pb.material_version != ctx.version:
+            # another forward (or set_materials) changed the problem since:
+            # restore this forward's materials
+            pb.set_materials(rho_f, c_f)
+            ctx.version = pb.material_version
         resid = grad_out.contiguous()
         zR, ZR = pb.source_sums(resid, f=ctx.f, targets=ctx.receivers)
         rhs = pb.adjoint_rhs(zR, ZR, f=ctx.f)

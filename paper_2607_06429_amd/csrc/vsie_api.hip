@@ -1894,6 +1894,8 @@ const char *vsie_last_error(void) { return g_last_error.c_str(); }
 
 int64_t vsie_size(const vsie_problem *p) { return p ? p->m.n : 0; }
 
+int64_t vsie_num_cells(const vsie_problem *p) { return p ? p->m.n_vol : 0; }
+
 void vsie_destroy(vsie_problem *p) { delete p; }
 
 vsie_status vsie_assemble(const vsie_geometry *geom, const double *vrho, const double *vc,
@@ -1983,15 +1985,18 @@ vsie_status vsie_set_materials(vsie_problem *p, const double *vrho_dev, const do
         require(p->m.n_vol == 0 || (vrho_dev && vc_dev), "material arrays must not be NULL");
         hipStream_t s = as_stream(stream);
         if (p->m.n_vol > 0) {
-            VSIE_HIP(hipMemcpyAsync(p->m.vrho, vrho_dev, sizeof(double) * p->m.n_vol, hipMemcpyDeviceToDevice, s));
-            VSIE_HIP(hipMemcpyAsync(p->m.vc, vc_dev, sizeof(double) * p->m.n_vol, hipMemcpyDeviceToDevice, s));
+            // validate a host copy first: rejected materials leave the problem
+            // (materials, weights, sources) exactly as it was
             std::vector<double> hr(p->m.n_vol), hc(p->m.n_vol);
-            VSIE_HIP(hipMemcpyAsync(hr.data(), p->m.vrho, sizeof(double) * p->m.n_vol, hipMemcpyDeviceToHost, s));
-            VSIE_HIP(hipMemcpyAsync(hc.data(), p->m.vc, sizeof(double) * p->m.n_vol, hipMemcpyDeviceToHost, s));
+            VSIE_HIP(hipMemcpyAsync(hr.data(), vrho_dev, sizeof(double) * p->m.n_vol, hipMemcpyDeviceToHost, s));
+            VSIE_HIP(hipMemcpyAsync(hc.data(), vc_dev, sizeof(double) * p->m.n_vol, hipMemcpyDeviceToHost, s));
             VSIE_HIP(hipStreamSynchronize(s));
             for (int64_t e = 0; e < p->m.n_vol; ++e)
                 require(hr[e] > 0 && std::isfinite(hr[e]) && hc[e] > 0 && std::isfinite(hc[e]),
                         "density and sound speed must be positive at cell " + std::to_string(e));
+            VSIE_HIP(hipMemcpyAsync(p->m.vrho, hr.data(), sizeof(double) * p->m.n_vol, hipMemcpyHostToDevice, s));
+            VSIE_HIP(hipMemcpyAsync(p->m.vc, hc.data(), sizeof(double) * p->m.n_vol, hipMemcpyHostToDevice, s));
+            VSIE_HIP(hipStreamSynchronize(s));
         }
         launch_weights(p->m, p->d_k0, static_cast<int>(p->k0.size()), s);
         VSIE_HIP(hipStreamSynchronize(s));

@@ -50,3 +50,30 @@ def case(name):
 
 
 CASES = ["c0", "ragged", "lognormal", "single", "cube"]
+
+
+def parity_err(num, ref):
+    """Relative error of a GPU result against the oracle (eq_error) in the
+    2-norm and in the max-norm over all entries, max|num - ref| / max|ref|:
+    the larger of the two, so that one bar bounds both (an error confined to a
+    few entries cannot hide in the 2-norm of a long vector)."""
+    import oracle as O
+    return max(O.rel_error(num, ref), O.rel_error(num, ref, ord=np.inf))
+
+
+def oracle_residual(d, x, b, rows):
+    """Residual of a GPU solution x (n or n x R) on sampled rows, computed by
+    the oracle from the Theorem 3 system: ||(b - A x)[rows]|| / ||b[rows]||,
+    the 2-norm over the rows and columns."""
+    import oracle as O
+    X = np.asarray(x).reshape(d.n, -1)
+    B = np.asarray(b).reshape(d.n, -1)
+    r = B[rows] - O.matvec(d, X, rows=rows)
+    return float(np.linalg.norm(r) / np.linalg.norm(B[rows]))
+
+
+def sample_rows(n, n_vol, count, seed):
+    """count seeded rows plus the first and last cell and face."""
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([rng.choice(n, count, replace=False),
+                                     [0, n_vol - 1, n_vol, n - 1]]))

@@ -118,3 +118,14 @@ def test_struct_layouts_match_header(V, tmp_path):
         assert int(out["%s size" % cname]) == ctypes.sizeof(cls), cname
         for fname, _ in cls._fields_:
             assert int(out["%s.%s" % (cname, fname)]) == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_set_materials_lengths_checked_in_binding(V):
+    """The C entry point reads n_vol doubles from each material pointer, so the
+    binding rejects tensors of another length before calling it (NULL handle:
+    n_vol = 0)."""
+    import torch
+    assert V.lib.vsie_num_cells(None) == 0
+    short = torch.zeros(3, dtype=torch.float64)
+    with pytest.raises(ValueError):
+        V.vsie_set_materials(None, short, short)

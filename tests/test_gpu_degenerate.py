@@ -9,7 +9,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from gpu_cases import dev, host, say
+from gpu_cases import dev, host, say, parity_err
 
 pytestmark = pytest.mark.gpu
 
@@ -71,14 +71,14 @@ def test_degenerate_mesh(V, name, prec):
     P = V.Problem.from_mesh(mesh, mat, [k0])
     pr, tol = (V.VSIE_FP64, 1e-12) if prec == "fp64" else (V.VSIE_FP32, 1e-5)
     x = W.seeded_complex((d.n, 3), seed=90)
-    e_fwd = O.rel_error(host(P.matvec(dev(x), prec=pr)), O.matvec(d, x))
-    e_adj = O.rel_error(host(P.matvec_adjoint(dev(x), prec=pr)), O.adjoint_matvec(d, x))
-    e_one = O.rel_error(host(P.matvec(dev(x[:, 0]), prec=pr)), O.matvec(d, x[:, :1])[:, 0])
+    e_fwd = parity_err(host(P.matvec(dev(x), prec=pr)), O.matvec(d, x))
+    e_adj = parity_err(host(P.matvec_adjoint(dev(x), prec=pr)), O.adjoint_matvec(d, x))
+    e_one = parity_err(host(P.matvec(dev(x[:, 0]), prec=pr)), O.matvec(d, x[:, :1])[:, 0])
     b = O.plane_wave(d.pts, k0, [0.0, 0.6, 0.8])
     xs, info = P.solve(dev(b).contiguous(), prec=pr, tol=1e-12)
-    e_sol = O.rel_error(host(xs), O.solve_lu(d, b))
+    e_sol = parity_err(host(xs), O.solve_lu(d, b))
     X = W.fibonacci_sphere(20)
-    e_ff = O.rel_error(host(P.far_field(X, dev(x[:, 0]), prec=pr)), O.far_field(d, X, x[:, 0]))
+    e_ff = parity_err(host(P.far_field(X, dev(x[:, 0]), prec=pr)), O.far_field(d, X, x[:, 0]))
     say("  %s %s: n %d (%d cells, %d faces) fwd %.1e adj %.1e one %.1e solve %.1e (%d it) far %.1e"
         % (name, prec, d.n, mesh.n_vol, mesh.n_srf, e_fwd, e_adj, e_one, e_sol, info["iterations"], e_ff))
     assert max(e_fwd, e_adj, e_one, e_ff) <= tol

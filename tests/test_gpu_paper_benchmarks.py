@@ -19,7 +19,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from gpu_cases import dev, host, say
+from gpu_cases import dev, host, oracle_residual, parity_err, sample_rows, say
 from oracle.analytic import mie_layered
 
 pytestmark = pytest.mark.gpu
@@ -103,12 +103,12 @@ def test_small_grid_products_against_oracle(V, prec, name):
     tol = TOL64 if prec == "fp64" else TOL32
     y = host(P.matvec(dev(x), prec=pr))
     ya = host(P.matvec_adjoint(dev(x), prec=pr))
-    e, ea = O.rel_error(y, O.matvec(d, x)), O.rel_error(ya, O.adjoint_matvec(d, x))
+    e, ea = parity_err(y, O.matvec(d, x)), parity_err(ya, O.adjoint_matvec(d, x))
     # one column: the once-per-pair kernels, forward and adjoint
     y1 = host(P.matvec(dev(x[:, 0]), prec=pr))
-    e1 = O.rel_error(y1, O.matvec(d, x[:, :1])[:, 0])
+    e1 = parity_err(y1, O.matvec(d, x[:, :1])[:, 0])
     ya1 = host(P.matvec_adjoint(dev(x[:, 1]), prec=pr))
-    ea1 = O.rel_error(ya1, O.adjoint_matvec(d, x[:, 1:2])[:, 0])
+    ea1 = parity_err(ya1, O.adjoint_matvec(d, x[:, 1:2])[:, 0])
     say("  %s small %s: n %d rel err %.2e adjoint %.2e one column %.2e, adjoint %.2e"
         % (name, prec, d.n, e, ea, e1, ea1))
     assert e <= tol and ea <= tol and e1 <= tol and ea1 <= tol
@@ -124,7 +124,7 @@ def test_small_grid_solve_against_lu(V, prec, name):
     ref = O.solve_lu(d, b)
     P = V.Problem.from_mesh(mesh, mat, k0, grad_rho=grad)
     x, info = P.solve(dev(b).contiguous(), prec=V.VSIE_FP64 if prec == "fp64" else V.VSIE_FP32, tol=1e-11)
-    e = O.rel_error(host(x), ref)
+    e = parity_err(host(x), ref)
     say("  %s small solve %s: %s rel err %.2e" % (name, prec, info, e))
     assert info["status"] == V.VSIE_OK and e <= TOL_SOLVE
     P.close()
@@ -183,7 +183,22 @@ def test_paper_grid_sampled_rows(V, name):
     ref = O.matvec(d, xb.reshape(-1, 1), rows=rows)[:, 0]
     for pr, tol in ((V.VSIE_FP64, TOL64), (V.VSIE_FP32, TOL32)):
         y = host(P.matvec(b, prec=pr)).reshape(-1)
-        e = O.rel_error(y[rows], ref)
+        e = parity_err(y[rows], ref)
         say("  %s n %d prec %d: sampled-row rel err %.2e" % (name, d.n, pr, e))
         assert e <= tol
+    P.close()
+
+
+def test_b4_3d_run_solve_oracle_residual(V):
+    """The paper's 3D run (61^3 cuboids, n = 260,401) solved with the FP32
+    operator inside FP64 refinement to relative residual 1e-10; the oracle
+    computes the residual of the GPU solution on sampled rows."""
+    mesh, mat, k0, dirs, grad = PAPER["b4"]()
+    d = O.discretise(mesh, mat, k0[0], grad_rho=grad)
+    P = V.Problem.from_mesh(mesh, mat, k0, grad_rho=grad)
+    b = P.plane_wave(dirs)
+    x, info = P.solve(b, prec=V.VSIE_FP32, tol=1e-10)
+    res = oracle_residual(d, host(x), host(b), sample_rows(d.n, d.n_vol, 256, 406))
+    say("  b4 3D run FP32 + refinement: %s, oracle residual on sampled rows %.2e" % (info, res))
+    assert info["status"] == V.VSIE_OK and res <= 1e-9
     P.close()

@@ -35,8 +35,16 @@
  * * No exception crosses the ABI: every call returns a vsie_status, and
  *   vsie_last_error() gives a message for the calling thread's last failure.
  * * Memory: input host arrays are copied during vsie_assemble; the problem
- *   owns its device arrays (geometry, weights, work buffers) until
- *   vsie_destroy.  Vectors x, y, b are owned by the caller.
+ *   owns its device arrays (geometry, weights) until vsie_destroy.  Vectors
+ *   x, y, b are owned by the caller.  Work buffers (partial sums, packed
+ *   charges, Krylov bases) come from the caller's workspace when the call is
+ *   given one (`workspace`, `ws_bytes`: DEVICE memory, 256-byte aligned, at
+ *   least vsie_workspace_size bytes, not touched by anything else while the
+ *   call's work runs on `stream`); with workspace == NULL the problem keeps
+ *   its own grow-only buffers, reused by later calls (growing one waits for
+ *   the whole device, because kernels queued on any stream may still read
+ *   the old buffer).  A call given a workspace allocates no device memory
+ *   for work buffers.
  * * A problem handle may be used from one host thread at a time.
  */
 #ifndef VSIE_H
@@ -55,7 +63,8 @@ typedef enum {
     VSIE_E_DEVICE = 2,    /* a HIP runtime call failed */
     VSIE_E_NOMEM = 3,     /* device allocation failed */
     VSIE_E_NOCONV = 4,    /* solver stopped at max_iter; x holds the last iterate */
-    VSIE_E_NAN = 5        /* a non-finite value appeared in a residual norm */
+    VSIE_E_NAN = 5,       /* a non-finite value appeared in a residual norm */
+    VSIE_E_WORKSPACE = 6  /* the caller's workspace is smaller than the call needs */
 } vsie_status;
 
 /* Arithmetic of the operator.
@@ -127,14 +136,18 @@ int64_t vsie_num_cells(const vsie_problem *p);
 
 /* y = A_f x for nrhs right-hand sides at frequency index f.
  * x, y: device complex128, n x nrhs, leading dimensions ldx, ldy; x and y
- * must not overlap. */
+ * must not overlap.  workspace, ws_bytes: optional caller workspace (see the
+ * conventions above; NULL, 0 for the problem's own buffers); too small gives
+ * VSIE_E_WORKSPACE before any work is queued. */
 vsie_status vsie_matvec(vsie_problem *p, int32_t f, vsie_precision prec, int64_t nrhs,
-                        const double *x, int64_t ldx, double *y, int64_t ldy, void *stream);
+                        const double *x, int64_t ldx, double *y, int64_t ldy, void *workspace,
+                        size_t ws_bytes, void *stream);
 
-/* y = A_f^H x (conjugate transpose), same layout rules as vsie_matvec. */
+/* y = A_f^H x (conjugate transpose), same layout and workspace rules as
+ * vsie_matvec. */
 vsie_status vsie_matvec_adjoint(vsie_problem *p, int32_t f, vsie_precision prec, int64_t nrhs,
                                 const double *x, int64_t ldx, double *y, int64_t ldy,
-                                void *stream);
+                                void *workspace, size_t ws_bytes, void *stream);
 
 /* y_t = A_{f0+t} x_t for the nf frequencies f0 .. f0 + nf - 1 at once: x and
  * y hold nf consecutive blocks of nrhs columns, block t (frequency f0 + t)
@@ -143,7 +156,9 @@ vsie_status vsie_matvec_adjoint(vsie_problem *p, int32_t f, vsie_precision prec,
  * one matrix-core launch over all nf frequencies; otherwise the
  * frequencies are applied one after the other. */
 vsie_status vsie_matvec_multi(vsie_problem *p, int32_t f0, int32_t nf, vsie_precision prec, int64_t nrhs,
-                              const double *x, int64_t ldx, double *y, int64_t ldy, void *stream);
+                              const double *x, int64_t ldx, double *y, int64_t ldy, void *workspace,
+                              size_t ws_bytes, void *stream);
+
 
 /* Launch configuration of the pair products of one problem.
  *
@@ -245,11 +260,32 @@ typedef struct {
  * The nrhs right-hand sides run independent GMRES processes in lockstep: each
  * iteration applies the operator to all unconverged columns in one launch.
  * x holds the initial guess on entry and the solution on exit.  opts may be
- * NULL (defaults); info may be NULL.  Returns VSIE_E_NOCONV when the
- * tolerance was not reached (x still holds the last iterate). */
+ * NULL (defaults); info may be NULL.  nrhs <= 4096.  workspace, ws_bytes: as
+ * for vsie_matvec (bases, residual blocks and the operator's buffers; block
+ * GMRES's rocBLAS handle keeps device memory of its own).  Returns
+ * VSIE_E_NOCONV when the tolerance was not reached (x still holds the last
+ * iterate). */
 vsie_status vsie_solve(vsie_problem *p, int32_t f, vsie_precision prec, int32_t adjoint,
                        int64_t nrhs, const double *b, int64_t ldb, double *x, int64_t ldx,
-                       const vsie_solve_opts *opts, vsie_solve_info *info, void *stream);
+                       const vsie_solve_opts *opts, vsie_solve_info *info, void *workspace, size_t ws_bytes,
+                       void *stream);
+
+/* The calls that take a caller workspace. */
+typedef enum {
+    VSIE_OP_MATVEC = 0,          /* vsie_matvec */
+    VSIE_OP_MATVEC_ADJOINT = 1,  /* vsie_matvec_adjoint */
+    VSIE_OP_MATVEC_MULTI = 2,    /* vsie_matvec_multi over nf frequencies from f */
+    VSIE_OP_SOLVE = 3,           /* vsie_solve, adjoint = 0 */
+    VSIE_OP_SOLVE_ADJOINT = 4    /* vsie_solve, adjoint = 1 */
+} vsie_op;
+
+/* Bytes of workspace the call `op` needs on problem p for frequency f (nf
+ * frequencies for VSIE_OP_MATVEC_MULTI, else 1), precision prec and nrhs
+ * right-hand sides, with solver options opts (solves only; NULL = defaults)
+ * and the problem's current tuning, materials and assembled operators.  A
+ * change of any of these may change the size.  Writes *bytes. */
+vsie_status vsie_workspace_size(vsie_problem *p, vsie_op op, int32_t f, int32_t nf, vsie_precision prec,
+                                int64_t nrhs, const vsie_solve_opts *opts, size_t *bytes);
 
 /* b[:, r] = exp(i k0_f x_i . d_r) at every collocation point for ndir unit
  * directions given as a HOST array of 3*ndir doubles (eq_planewave). */

@@ -24,15 +24,19 @@ __all__ = [
     "vsie_param_gradient", "vsie_assemble_dense", "vsie_release_dense", "vsie_profile",
     "vsie_profile_read", "vsie_destroy", "vsie_last_error",
     "vsie_size", "vsie_num_cells", "vsie_matvec_multi", "vsie_get_tuning", "vsie_set_tuning", "vsie_autotune",
+    "vsie_workspace_size", "VSIE_OP_MATVEC", "VSIE_OP_MATVEC_ADJOINT", "VSIE_OP_MATVEC_MULTI", "VSIE_OP_SOLVE",
+    "VSIE_OP_SOLVE_ADJOINT",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libvsie.so")
 
-VSIE_OK, VSIE_E_INVALID, VSIE_E_DEVICE, VSIE_E_NOMEM, VSIE_E_NOCONV, VSIE_E_NAN = range(6)
+VSIE_OK, VSIE_E_INVALID, VSIE_E_DEVICE, VSIE_E_NOMEM, VSIE_E_NOCONV, VSIE_E_NAN, VSIE_E_WORKSPACE = range(7)
 VSIE_FP64, VSIE_FP32 = 0, 1
+VSIE_OP_MATVEC, VSIE_OP_MATVEC_ADJOINT, VSIE_OP_MATVEC_MULTI, VSIE_OP_SOLVE, VSIE_OP_SOLVE_ADJOINT = range(5)
 _STATUS = {0: "VSIE_OK", 1: "VSIE_E_INVALID", 2: "VSIE_E_DEVICE", 3: "VSIE_E_NOMEM",
-           4: "VSIE_E_NOCONV", 5: "VSIE_E_NAN"}
+           4: "VSIE_E_NOCONV", 5: "VSIE_E_NAN", 6: "VSIE_E_WORKSPACE"}
+_SZ = ctypes.c_size_t
 
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -92,10 +96,12 @@ def _load():
     L.vsie_size.restype = _I64
     L.vsie_num_cells.argtypes = [_P]
     L.vsie_num_cells.restype = _I64
-    L.vsie_matvec.argtypes = [_P, _I32, _I32, _I64, _P, _I64, _P, _I64, _P]
-    L.vsie_matvec_adjoint.argtypes = [_P, _I32, _I32, _I64, _P, _I64, _P, _I64, _P]
+    L.vsie_matvec.argtypes = [_P, _I32, _I32, _I64, _P, _I64, _P, _I64, _P, _SZ, _P]
+    L.vsie_matvec_adjoint.argtypes = [_P, _I32, _I32, _I64, _P, _I64, _P, _I64, _P, _SZ, _P]
     L.vsie_solve.argtypes = [_P, _I32, _I32, _I32, _I64, _P, _I64, _P, _I64,
-                             ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P]
+                             ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P, _SZ, _P]
+    L.vsie_workspace_size.argtypes = [_P, _I32, _I32, _I32, _I32, _I64, ctypes.POINTER(SolveOpts),
+                                      ctypes.POINTER(_SZ)]
     L.vsie_plane_wave.argtypes = [_P, _I32, _I64, _P, _P, _I64, _P]
     L.vsie_field.argtypes = [_P, _I32, _I32, _I64, _P, _P, _P, _I64, _P, _I64, _P, _I64, _P]
     L.vsie_far_field.argtypes = [_P, _I32, _I32, _I64, _P, _P, _P, _I64, _P, _I64, _P, _I64, _P]
@@ -108,7 +114,7 @@ def _load():
     L.vsie_release_dense.argtypes = [_P, _I32]
     L.vsie_profile.argtypes = [_P, _I32]
     L.vsie_profile_read.argtypes = [_P, _I32, ctypes.POINTER(KernelStats)]
-    L.vsie_matvec_multi.argtypes = [_P, _I32, _I32, _I32, _I64, _P, _I64, _P, _I64, _P]
+    L.vsie_matvec_multi.argtypes = [_P, _I32, _I32, _I32, _I64, _P, _I64, _P, _I64, _P, _SZ, _P]
     L.vsie_get_tuning.argtypes = [_P, ctypes.POINTER(Tuning)]
     L.vsie_set_tuning.argtypes = [_P, ctypes.POINTER(Tuning)]
     L.vsie_autotune.argtypes = [_P, _I32, _I64, ctypes.POINTER(Tuning), _P]
@@ -119,7 +125,8 @@ def _load():
                  "vsie_solve", "vsie_plane_wave", "vsie_field", "vsie_far_field", "vsie_source_sums",
                  "vsie_profile", "vsie_profile_read", "vsie_plane_wave_at", "vsie_adjoint_rhs",
                  "vsie_param_gradient", "vsie_assemble_dense", "vsie_release_dense",
-                 "vsie_matvec_multi", "vsie_get_tuning", "vsie_set_tuning", "vsie_autotune"):
+                 "vsie_matvec_multi", "vsie_get_tuning", "vsie_set_tuning", "vsie_autotune",
+                 "vsie_workspace_size"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -131,7 +138,7 @@ EXPORTED = ("vsie_assemble", "vsie_set_materials", "vsie_size", "vsie_num_cells"
             "vsie_source_sums", "vsie_plane_wave_at", "vsie_adjoint_rhs", "vsie_param_gradient",
             "vsie_assemble_dense", "vsie_release_dense", "vsie_profile", "vsie_profile_read",
             "vsie_destroy", "vsie_last_error", "vsie_matvec_multi", "vsie_get_tuning",
-            "vsie_set_tuning", "vsie_autotune")
+            "vsie_set_tuning", "vsie_autotune", "vsie_workspace_size")
 
 # pair-kernel kinds reported by vsie_profile_read: 2 * mode + precision
 KIND_NAMES = {0: "fwd_single_layer_fp64", 1: "fwd_single_layer_fp32", 2: "fwd_double_layers_fp64",
@@ -184,6 +191,16 @@ def _cols(t, n):
     if t.dim() != 2 or t.shape[1] != n:
         raise ValueError("expected shape (R, %d), got %s" % (n, tuple(t.shape)))
     return _P(t.data_ptr()), t.shape[0], n
+
+
+def _ws(workspace):
+    """(pointer, bytes) of an optional caller workspace: a contiguous CUDA
+    tensor of any dtype (its storage is used as raw bytes), or None."""
+    if workspace is None:
+        return None, 0
+    if not workspace.is_cuda or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous CUDA tensor")
+    return _P(workspace.data_ptr()), workspace.numel() * workspace.element_size()
 
 
 def _dptr(t):
@@ -245,32 +262,46 @@ def vsie_num_cells(h) -> int:
     return int(lib.vsie_num_cells(h))
 
 
-def vsie_matvec(h, f, prec, x, y, stream=None):
+def vsie_matvec(h, f, prec, x, y, stream=None, workspace=None):
     n = vsie_size(h)
     px, R, ldx = _cols(x, n)
     py, Ry, ldy = _cols(y, n)
     if Ry != R:
         raise ValueError("x and y hold different numbers of columns")
-    _check(lib.vsie_matvec(h, f, prec, R, px, ldx, py, ldy, _stream(stream)))
+    _check(lib.vsie_matvec(h, f, prec, R, px, ldx, py, ldy, *_ws(workspace), _stream(stream)))
 
 
-def vsie_matvec_adjoint(h, f, prec, x, y, stream=None):
+def vsie_matvec_adjoint(h, f, prec, x, y, stream=None, workspace=None):
     n = vsie_size(h)
     px, R, ldx = _cols(x, n)
     py, Ry, ldy = _cols(y, n)
     if Ry != R:
         raise ValueError("x and y hold different numbers of columns")
-    _check(lib.vsie_matvec_adjoint(h, f, prec, R, px, ldx, py, ldy, _stream(stream)))
+    _check(lib.vsie_matvec_adjoint(h, f, prec, R, px, ldx, py, ldy, *_ws(workspace), _stream(stream)))
 
 
-def vsie_matvec_multi(h, f0, nf, prec, x, y, stream=None):
+def vsie_matvec_multi(h, f0, nf, prec, x, y, stream=None, workspace=None):
     """x, y: (nf * R, n) -- rows t R .. t R + R - 1 belong to frequency f0 + t."""
     n = vsie_size(h)
     px, C, ldx = _cols(x, n)
     py, Cy, ldy = _cols(y, n)
     if Cy != C or C % nf:
         raise ValueError("x and y must hold nf blocks of equally many columns")
-    _check(lib.vsie_matvec_multi(h, f0, nf, prec, C // nf, px, ldx, py, ldy, _stream(stream)))
+    _check(lib.vsie_matvec_multi(h, f0, nf, prec, C // nf, px, ldx, py, ldy, *_ws(workspace), _stream(stream)))
+
+
+def _opts(tol=1e-10, max_iter=3000, restart=500, inner_tol=1e-5, max_outer=20, block=False, relax=0.0,
+          progress=False):
+    return SolveOpts(tol, max_iter, restart, inner_tol, max_outer, 1 if block else 0, relax, 1 if progress else 0)
+
+
+def vsie_workspace_size(h, op, f, prec, nrhs, nf=1, **opts) -> int:
+    """Bytes of caller workspace the call `op` (VSIE_OP_*) needs; opts are the
+    solver options of vsie_solve (solves only)."""
+    o = _opts(**opts)
+    b = _SZ()
+    _check(lib.vsie_workspace_size(h, op, f, nf, prec, nrhs, ctypes.byref(o), ctypes.byref(b)))
+    return int(b.value)
 
 
 def vsie_get_tuning(h) -> dict:
@@ -296,7 +327,8 @@ def vsie_autotune(h, f, nrhs, stream=None) -> dict:
 
 
 def vsie_solve(h, f, prec, adjoint, b, x, tol=1e-10, max_iter=3000, restart=500, inner_tol=1e-5,
-               max_outer=20, block=False, stream=None, allow_noconv=False, relax=0.0, progress=False):
+               max_outer=20, block=False, stream=None, allow_noconv=False, relax=0.0, progress=False,
+               workspace=None):
     """Solve in place into x (initial guess on entry).  Returns SolveInfo as a dict
     plus the status."""
     n = vsie_size(h)
@@ -304,10 +336,10 @@ def vsie_solve(h, f, prec, adjoint, b, x, tol=1e-10, max_iter=3000, restart=500,
     px, Rx, ldx = _cols(x, n)
     if Rx != R:
         raise ValueError("b and x hold different numbers of columns")
-    o = SolveOpts(tol, max_iter, restart, inner_tol, max_outer, 1 if block else 0, relax, 1 if progress else 0)
+    o = _opts(tol, max_iter, restart, inner_tol, max_outer, block, relax, progress)
     info = SolveInfo()
     st = _check(lib.vsie_solve(h, f, prec, int(adjoint), R, pb, ldb, px, ldx, ctypes.byref(o),
-                               ctypes.byref(info), _stream(stream)),
+                               ctypes.byref(info), *_ws(workspace), _stream(stream)),
                 allow=(VSIE_E_NOCONV,) if allow_noconv else ())
     d = info.as_dict()
     d["status"] = st
@@ -477,20 +509,30 @@ class Problem:
         import torch
         return torch.empty_like(x)
 
-    def matvec(self, x, f=0, prec=VSIE_FP64, out=None):
+    def matvec(self, x, f=0, prec=VSIE_FP64, out=None, workspace=None):
         y = self._out(x) if out is None else out
-        vsie_matvec(self.handle, f, prec, x, y)
+        vsie_matvec(self.handle, f, prec, x, y, workspace=workspace)
         return y
 
-    def matvec_adjoint(self, x, f=0, prec=VSIE_FP64, out=None):
+    def matvec_adjoint(self, x, f=0, prec=VSIE_FP64, out=None, workspace=None):
         y = self._out(x) if out is None else out
-        vsie_matvec_adjoint(self.handle, f, prec, x, y)
+        vsie_matvec_adjoint(self.handle, f, prec, x, y, workspace=workspace)
         return y
 
-    def matvec_multi(self, x, f0=0, nf=1, prec=VSIE_FP32, out=None):
+    def matvec_multi(self, x, f0=0, nf=1, prec=VSIE_FP32, out=None, workspace=None):
         y = self._out(x) if out is None else out
-        vsie_matvec_multi(self.handle, f0, nf, prec, x, y)
+        vsie_matvec_multi(self.handle, f0, nf, prec, x, y, workspace=workspace)
         return y
+
+    def workspace_size(self, op, nrhs=1, f=0, prec=VSIE_FP64, nf=1, **opts) -> int:
+        return vsie_workspace_size(self.handle, op, f, prec, nrhs, nf=nf, **opts)
+
+    def workspace(self, op, nrhs=1, f=0, prec=VSIE_FP64, nf=1, **opts):
+        """A torch uint8 CUDA tensor of vsie_workspace_size bytes (the caching
+        allocator's blocks are 512-byte aligned)."""
+        import torch
+        nb = self.workspace_size(op, nrhs, f, prec, nf, **opts)
+        return torch.empty(max(nb, 1), dtype=torch.uint8, device="cuda")
 
     @property
     def tuning(self) -> dict:

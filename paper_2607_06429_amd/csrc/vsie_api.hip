@@ -40,14 +40,27 @@ void check_hip(hipError_t e, const char *what) {
 // launched again.
 std::atomic<uint64_t> g_graph_epoch{0};
 
-// Grow-only device buffer.
+// Grow-only device buffer.  During a call made with a caller workspace the
+// buffer is a planned part of that workspace instead (ov_on): the call then
+// never allocates, and asking for more than was planned is an error.
 struct Scratch {
     void *p = nullptr;
     size_t bytes = 0;
+    void *ov = nullptr;
+    size_t ov_bytes = 0;
+    bool ov_on = false;
     void *get(size_t b) {
+        if (ov_on) {
+            if (b > ov_bytes)
+                fail(VSIE_E_WORKSPACE, "a work buffer needs " + std::to_string(b) + " bytes, its planned part of the "
+                                       "workspace holds " + std::to_string(ov_bytes));
+            return ov;
+        }
         if (b <= bytes) return p;
         if (p) {
-            // queued kernels may still read the old buffer
+            // Kernels queued on any stream the caller used with this problem
+            // may still read the old buffer, so growth waits for the whole
+            // device.  Calls given a workspace never grow a buffer.
             VSIE_HIP(hipDeviceSynchronize());
             VSIE_HIP(hipFree(p));
         }
@@ -63,6 +76,66 @@ struct Scratch {
         p = nullptr;
         bytes = 0;
     }
+};
+
+// The work buffers one call needs (each rounded up to 256 bytes), planned
+// before the call from the same layout functions the call uses.
+constexpr size_t kWsAlign = 256;
+inline size_t ws_round(size_t b) { return (b + kWsAlign - 1) / kWsAlign * kWsAlign; }
+
+struct WsPlan {
+    std::vector<std::pair<Scratch *, size_t>> items;
+    void need(Scratch &sc, size_t b) {
+        for (auto &it : items)
+            if (it.first == &sc) {
+                it.second = std::max(it.second, b);
+                return;
+            }
+        items.emplace_back(&sc, b);
+    }
+    size_t total() const {
+        size_t t = 0;
+        for (const auto &it : items) t += ws_round(it.second);
+        return t;
+    }
+};
+
+// For the duration of one call, the planned buffers live in the caller's
+// workspace [ws, ws + bytes): consecutive 256-byte aligned parts in plan
+// order.  Without a workspace (ws == NULL) nothing changes.
+struct WsScope {
+    std::vector<Scratch *> set;
+    WsScope(const WsPlan &plan, void *ws, size_t bytes) {
+        if (!ws) return;
+        if (reinterpret_cast<uintptr_t>(ws) % kWsAlign != 0)
+            fail(VSIE_E_INVALID, "workspace must be 256-byte aligned");
+        const size_t need = plan.total();
+        if (bytes < need)
+            fail(VSIE_E_WORKSPACE, "workspace of " + std::to_string(bytes) + " bytes, the call needs " +
+                                       std::to_string(need) + " (vsie_workspace_size)");
+        // operator graphs hold work-buffer addresses: those captured before
+        // this call are not replayed into the workspace, and those captured
+        // into it are not replayed after the call (the caller may free it)
+        ++g_graph_epoch;
+        char *at = static_cast<char *>(ws);
+        for (const auto &it : plan.items) {
+            it.first->ov = at;
+            it.first->ov_bytes = ws_round(it.second);
+            it.first->ov_on = true;
+            set.push_back(it.first);
+            at += ws_round(it.second);
+        }
+    }
+    ~WsScope() {
+        if (!set.empty()) ++g_graph_epoch;
+        for (Scratch *sc : set) {
+            sc->ov = nullptr;
+            sc->ov_bytes = 0;
+            sc->ov_on = false;
+        }
+    }
+    WsScope(const WsScope &) = delete;
+    WsScope &operator=(const WsScope &) = delete;
 };
 
 // Grow-only pinned host buffer (hipHostMalloc): device-to-host copies into it
@@ -442,19 +515,40 @@ void check_vec(const double *v, int64_t ld, int64_t n, const char *name) {
 
 size_t csize(vsie_precision prec) { return prec == VSIE_FP64 ? sizeof(double2) : sizeof(float2); }
 
+// Chunking and work-buffer sizes of apply_forward_block.
+struct FwdBlockLayout {
+    int64_t chG, chF;
+    int ncG, ncF;
+    size_t part, qG, qF;
+};
+FwdBlockLayout fwd_block_layout(const vsie_problem *p, vsie_precision prec, int nrhs) {
+    FwdBlockLayout L;
+    const int64_t n = p->m.n;
+    choose_chunks(n, p->G.count, p->tune.vec_target_waves, L.chG, L.ncG);
+    choose_chunks(n, p->F.count, p->tune.vec_target_waves, L.chF, L.ncF);
+    L.part = sizeof(double2) * static_cast<size_t>(std::max(1, L.ncG + L.ncF)) * nrhs * n;
+    L.qG = csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->G.count)) * nrhs;
+    L.qF = csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->F.count)) * nrhs;
+    return L;
+}
+void plan_forward_block(vsie_problem *p, vsie_precision prec, int nrhs, WsPlan &pl) {
+    const FwdBlockLayout L = fwd_block_layout(p, prec, nrhs);
+    pl.need(p->partial, L.part);
+    pl.need(p->chargeG, L.qG);
+    pl.need(p->chargeF, L.qF);
+}
+
 // y = A_f x (forward operator) for at most kMaxRhsPerLaunch columns.
 void apply_forward_block(vsie_problem *p, int f, vsie_precision prec, int nrhs, const double2 *x,
                          int64_t ldx, double2 *y, int64_t ldy, hipStream_t s) {
     const int64_t n = p->m.n;
-    int64_t chG, chF;
-    int ncG, ncF;
-    choose_chunks(n, p->G.count, p->tune.vec_target_waves, chG, ncG);
-    choose_chunks(n, p->F.count, p->tune.vec_target_waves, chF, ncF);
+    const FwdBlockLayout L = fwd_block_layout(p, prec, nrhs);
+    const int64_t chG = L.chG, chF = L.chF;
+    const int ncG = L.ncG, ncF = L.ncF;
     const int n_parts = ncG + ncF;
-    double2 *part = static_cast<double2 *>(
-        p->partial.get(sizeof(double2) * static_cast<size_t>(std::max(1, n_parts)) * nrhs * n));
-    void *qG = p->chargeG.get(csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->G.count)) * nrhs);
-    void *qF = p->chargeF.get(csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->F.count)) * nrhs);
+    double2 *part = static_cast<double2 *>(p->partial.get(L.part));
+    void *qG = p->chargeG.get(L.qG);
+    void *qF = p->chargeF.get(L.qF);
     const double *spf = p->m.sp + static_cast<int64_t>(f) * n;
     launch_pack_charges(kClassG, prec, p->G, spf, nrhs, x, ldx, false, qG, s);
     launch_pack_charges(kClassF, prec, p->F, spf, nrhs, x, ldx, false, qF, s);
@@ -485,20 +579,25 @@ struct SlotBuffers {
     double2 *tail;
 };
 
-SlotBuffers slot_buffers(vsie_problem *p, vsie_precision prec, std::initializer_list<int64_t> counts,
-                         int64_t tail) {
+// Bytes of the slot buffers and the offsets of their five parts.
+size_t slot_layout(vsie_precision prec, std::initializer_list<int64_t> counts, int64_t tail, size_t off[5]) {
     if (counts.size() != 4) fail(VSIE_E_INVALID, "slot buffers: four slot arrays expected");
     const size_t es = prec == VSIE_FP32 ? sizeof(float2) : sizeof(double2);
-    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
-    size_t off[5], at = 0;
+    size_t at = 0;
     int i = 0;
     for (int64_t c : counts) {
         off[i++] = at;
-        at += up(es * static_cast<size_t>(c));
+        at += ws_round(es * static_cast<size_t>(c));
     }
     off[4] = at;
     at += sizeof(double2) * static_cast<size_t>(tail);
-    char *base = static_cast<char *>(p->partial.get(std::max<size_t>(256, at)));
+    return std::max<size_t>(256, at);
+}
+
+SlotBuffers slot_buffers(vsie_problem *p, vsie_precision prec, std::initializer_list<int64_t> counts,
+                         int64_t tail) {
+    size_t off[5];
+    char *base = static_cast<char *>(p->partial.get(slot_layout(prec, counts, tail, off)));
     return SlotBuffers{{base + off[0], base + off[1], base + off[2], base + off[3]},
                        reinterpret_cast<double2 *>(base + off[4])};
 }
@@ -549,11 +648,33 @@ SymJob face_face_job(vsie_problem *p, vsie_precision prec, double k, const void 
     return J;
 }
 
+// Slot counts of the once-per-pair products with the cell-face kernel: the
+// symmetric cell-cell slots per cell, the face-group slots per cell, the
+// cell-group slots per face and the face-face slots per face.
+struct CfCounts {
+    int64_t slots, cs, fs, ffs;
+};
+CfCounts cf_counts(const vsie_problem *p) {
+    const int64_t nv = p->m.n_vol, ns = p->m.n - nv;
+    return CfCounts{sym_slots(nv, p->tune.sym_groups), cf_groups(ns), cf_groups(nv),
+                    ns > 0 ? sym_slots(ns, kFaceGroups) : 0};
+}
+size_t cf_slot_bytes(const vsie_problem *p, vsie_precision prec) {
+    const int64_t nv = p->m.n_vol, ns = p->m.n - nv;
+    const CfCounts c = cf_counts(p);
+    size_t off[5];
+    return slot_layout(prec, {c.slots * nv, c.cs * nv, c.fs * ns, c.ffs * ns}, 0, off);
+}
+void plan_forward_cf(vsie_problem *p, vsie_precision prec, WsPlan &pl) {
+    pl.need(p->partial, cf_slot_bytes(p, prec));
+    pl.need(p->chargeG, csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->G.count)));
+}
+
 void apply_forward_cf(vsie_problem *p, int f, vsie_precision prec, const double2 *x, double2 *y, hipStream_t s) {
     const int64_t n = p->m.n, nv = p->m.n_vol, ns = n - nv;
     const int g = p->tune.sym_groups;
-    const int64_t slots = sym_slots(nv, g), cs = cf_groups(ns), fs = cf_groups(nv);
-    const int64_t ffs = ns > 0 ? sym_slots(ns, kFaceGroups) : 0;
+    const CfCounts cc = cf_counts(p);
+    const int64_t slots = cc.slots, cs = cc.cs, fs = cc.fs, ffs = cc.ffs;
     const SlotBuffers sb = slot_buffers(p, prec, {slots * nv, cs * nv, fs * ns, ffs * ns}, 0);
     void *psym = sb.s[0], *pc = sb.s[1], *pf = sb.s[2], *pff = sb.s[3];
     // the single-layer charges -s' x of the cells; the double layers take the
@@ -595,6 +716,34 @@ void apply_forward_cf(vsie_problem *p, int f, vsie_precision prec, const double2
                      static_cast<int>(ffs), pff, f32, p->m.diag + static_cast<int64_t>(f) * n, x, y, s);
 }
 
+// Chunking of the one-sided parts of apply_forward_sym without the
+// cell-face kernel (single layer at the faces, double layers everywhere).
+struct SymLayout {
+    int64_t slots, chGf = 1, chF = 1;
+    int ncGf = 0, ncF = 0;
+    size_t part;
+};
+SymLayout sym_layout(const vsie_problem *p, vsie_precision prec) {
+    const int64_t n = p->m.n, nv = p->m.n_vol, ns = n - nv;
+    SymLayout L;
+    L.slots = sym_slots(nv, p->tune.sym_groups);
+    if (ns > 0) choose_chunks(ns, p->G.count, p->tune.vec_target_waves, L.chGf, L.ncGf);
+    choose_chunks(n, p->F.count, p->tune.vec_target_waves, L.chF, L.ncF);
+    size_t off[5];
+    L.part = slot_layout(prec, {L.slots * nv, 0, 0, 0}, static_cast<int64_t>(L.ncGf) * ns + static_cast<int64_t>(L.ncF) * n,
+                         off);
+    return L;
+}
+void plan_forward_sym(vsie_problem *p, vsie_precision prec, WsPlan &pl) {
+    if (p->tune.cell_face) {
+        plan_forward_cf(p, prec, pl);
+        return;
+    }
+    pl.need(p->partial, sym_layout(p, prec).part);
+    pl.need(p->chargeG, csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->G.count)));
+    pl.need(p->chargeF, csize(prec) * static_cast<size_t>(std::max<int64_t>(1, p->F.count)));
+}
+
 void apply_forward_sym(vsie_problem *p, int f, vsie_precision prec, const double2 *x, double2 *y,
                        hipStream_t s) {
     if (p->tune.cell_face) {
@@ -603,11 +752,9 @@ void apply_forward_sym(vsie_problem *p, int f, vsie_precision prec, const double
     }
     const int64_t n = p->m.n, nv = p->m.n_vol, ns = n - nv;
     const int g = p->tune.sym_groups;
-    const int64_t slots = sym_slots(nv, g);
-    int64_t chGf = 1, chF = 1;
-    int ncGf = 0, ncF = 0;
-    if (ns > 0) choose_chunks(ns, p->G.count, p->tune.vec_target_waves, chGf, ncGf);
-    choose_chunks(n, p->F.count, p->tune.vec_target_waves, chF, ncF);
+    const SymLayout L = sym_layout(p, prec);
+    const int64_t slots = L.slots, chGf = L.chGf, chF = L.chF;
+    const int ncGf = L.ncGf, ncF = L.ncF;
     const SlotBuffers sb = slot_buffers(p, prec, {slots * nv, 0, 0, 0},
                                         static_cast<int64_t>(ncGf) * ns + static_cast<int64_t>(ncF) * n);
     void *psym = sb.s[0];
@@ -649,6 +796,14 @@ bool use_sym(const vsie_problem *p, int nrhs) {
     return bytes * sizeof(double2) <= kSymPartialCap;
 }
 
+void plan_forward(vsie_problem *p, vsie_precision prec, int nrhs, WsPlan &pl) {
+    if (use_sym(p, nrhs)) {
+        plan_forward_sym(p, prec, pl);
+        return;
+    }
+    for (int r0 = 0; r0 < nrhs; r0 += kMaxRhsPerLaunch) plan_forward_block(p, prec, std::min(kMaxRhsPerLaunch, nrhs - r0), pl);
+}
+
 void apply_forward(vsie_problem *p, int f, vsie_precision prec, int nrhs, const double2 *x,
                    int64_t ldx, double2 *y, int64_t ldy, hipStream_t s) {
     if (use_sym(p, nrhs)) {
@@ -665,22 +820,41 @@ void apply_forward(vsie_problem *p, int f, vsie_precision prec, int nrhs, const 
 // y = A_f^H x for at most kMaxRhsPerLaunch columns:
 // (A^H x)_j = conj(A_jj) x_j + sum_{i != j} conj(A_ij) x_i, evaluated per source
 // class with the roles of targets and sources exchanged.
+struct AdjBlockLayout {
+    int64_t chG = 1, chF = 1;
+    int ncG = 0, ncF = 0;
+    size_t q, part;
+};
+AdjBlockLayout adj_block_layout(const vsie_problem *p, vsie_precision prec, int nrhs) {
+    const int64_t n = p->m.n;
+    AdjBlockLayout L;
+    if (p->G.count > 0) choose_chunks(p->G.count, n, p->tune.vec_target_waves, L.chG, L.ncG);
+    if (p->F.count > 0) choose_chunks(p->F.count, n, p->tune.vec_target_waves, L.chF, L.ncF);
+    const size_t need = std::max(static_cast<size_t>(L.ncG) * p->G.count, static_cast<size_t>(L.ncF) * p->F.count);
+    L.q = csize(prec) * static_cast<size_t>(n) * nrhs;
+    L.part = sizeof(double2) * std::max<size_t>(1, need) * nrhs;
+    return L;
+}
+void plan_adjoint_block(vsie_problem *p, vsie_precision prec, int nrhs, WsPlan &pl) {
+    const AdjBlockLayout L = adj_block_layout(p, prec, nrhs);
+    pl.need(p->chargeAll, L.q);
+    pl.need(p->partial, L.part);
+}
+
 void apply_adjoint_block(vsie_problem *p, int f, vsie_precision prec, int nrhs, const double2 *x,
                          int64_t ldx, double2 *y, int64_t ldy, hipStream_t s) {
     const int64_t n = p->m.n;
-    void *q = p->chargeAll.get(csize(prec) * static_cast<size_t>(n) * nrhs);
+    const AdjBlockLayout L = adj_block_layout(p, prec, nrhs);
+    void *q = p->chargeAll.get(L.q);
     launch_pack_plain(prec, n, nrhs, x, ldx, true, q, s);
     // y = conj(diag) x
     launch_reduce_partials(n, nrhs, 0, nullptr, p->m.diag + static_cast<int64_t>(f) * n, true, x, ldx,
                            y, ldy, nullptr, s);
     const double k = p->k0[f];
     const double *spf = p->m.sp + static_cast<int64_t>(f) * n;
-    int64_t chG = 1, chF = 1;
-    int ncG = 0, ncF = 0;
-    if (p->G.count > 0) choose_chunks(p->G.count, n, p->tune.vec_target_waves, chG, ncG);
-    if (p->F.count > 0) choose_chunks(p->F.count, n, p->tune.vec_target_waves, chF, ncF);
-    const size_t need = std::max(static_cast<size_t>(ncG) * p->G.count, static_cast<size_t>(ncF) * p->F.count);
-    double2 *part = static_cast<double2 *>(p->partial.get(sizeof(double2) * std::max<size_t>(1, need) * nrhs));
+    const int64_t chG = L.chG, chF = L.chF;
+    const int ncG = L.ncG, ncF = L.ncF;
+    double2 *part = static_cast<double2 *>(p->partial.get(L.part));
     if (ncG > 0) {
         PairJob J{PAIR_FWD_G, prec, p->G.count, p->G.x, p->G.y, p->G.z, {}, n,
                   p->m.px, p->m.py, p->m.pz, {}, q, n, nrhs, chG, ncG, k, part,
@@ -710,11 +884,16 @@ bool adjoint_sym_ok(const vsie_problem *p, int nrhs) {
     return use_sym(p, nrhs) && p->tune.cell_face;
 }
 
+void plan_adjoint_sym(vsie_problem *p, vsie_precision prec, WsPlan &pl) {
+    pl.need(p->partial, cf_slot_bytes(p, prec));
+    pl.need(p->chargeAll, csize(prec) * static_cast<size_t>(p->m.n));
+}
+
 void apply_adjoint_sym(vsie_problem *p, int f, vsie_precision prec, const double2 *x, double2 *y, hipStream_t s) {
     const int64_t n = p->m.n, nv = p->m.n_vol, ns = n - nv;
     const int g = p->tune.sym_groups;
-    const int64_t slots = sym_slots(nv, g), cs = cf_groups(ns), fs = cf_groups(nv);
-    const int64_t ffs = ns > 0 ? sym_slots(ns, kFaceGroups) : 0;
+    const CfCounts cc = cf_counts(p);
+    const int64_t slots = cc.slots, cs = cc.cs, fs = cc.fs, ffs = cc.ffs;
     const SlotBuffers sb = slot_buffers(p, prec, {slots * nv, cs * nv, fs * ns, ffs * ns}, 0);
     void *psym = sb.s[0], *pc = sb.s[1], *pf = sb.s[2], *pff = sb.s[3];
     void *q = p->chargeAll.get(csize(prec) * static_cast<size_t>(n));
@@ -764,6 +943,14 @@ void apply_adjoint_sym(vsie_problem *p, int f, vsie_precision prec, const double
                      t ? nullptr : spf);
 }
 
+void plan_adjoint(vsie_problem *p, vsie_precision prec, int nrhs, WsPlan &pl) {
+    if (nrhs == 1 && adjoint_sym_ok(p, nrhs)) {
+        plan_adjoint_sym(p, prec, pl);
+        return;
+    }
+    for (int r0 = 0; r0 < nrhs; r0 += kMaxRhsPerLaunch) plan_adjoint_block(p, prec, std::min(kMaxRhsPerLaunch, nrhs - r0), pl);
+}
+
 void apply_adjoint(vsie_problem *p, int f, vsie_precision prec, int nrhs, const double2 *x,
                    int64_t ldx, double2 *y, int64_t ldy, hipStream_t s) {
     if (nrhs == 1 && adjoint_sym_ok(p, nrhs)) {
@@ -784,6 +971,14 @@ void apply_adjoint(vsie_problem *p, int f, vsie_precision prec, int nrhs, const 
 // on the matrix cores; measured faster than one complex GEMM with nrhs
 // columns); their FP32 products are combined and added in FP64.
 constexpr int64_t kDenseChunk = 8192;
+
+void plan_dense(vsie_problem *p, int nrhs, WsPlan &pl) {
+    const int64_t n = p->m.n;
+    const int nc = static_cast<int>((n + kDenseChunk - 1) / kDenseChunk);
+    const int64_t blk = static_cast<int64_t>(2) * nrhs * n;
+    pl.need(p->dense_x, sizeof(float) * static_cast<size_t>(blk));
+    pl.need(p->dense_part, sizeof(float) * static_cast<size_t>(2 * blk * nc));
+}
 
 void apply_dense(vsie_problem *p, int f, bool adjoint, int nrhs, const double2 *x, int64_t ldx,
                  double2 *y, int64_t ldy, hipStream_t s) {
@@ -823,16 +1018,25 @@ void apply_dense(vsie_problem *p, int f, bool adjoint, int nrhs, const double2 *
 // FP64 diagonal.
 constexpr int kMfmaMaxCols = 128;
 
-void apply_forward_mfma_block(vsie_problem *p, int f0, int nf, int nrhs, const double2 *x, int64_t ldx,
-                              int64_t xfs, double2 *y, int64_t ldy, int64_t yfs, hipStream_t s) {
+// Chunking and work-buffer sizes of apply_forward_mfma_block.
+struct MfmaLayout {
+    int tg, nb, ncol;
+    int64_t chG, chF;
+    int ncG, ncF;
+    int64_t fstride, ldqG, ldqF;
+    size_t part, qG, qF;
+};
+MfmaLayout mfma_layout(const vsie_problem *p, int nf, int nrhs) {
     const int64_t n = p->m.n;
-    const int tg = p->tune.mfma_tg, nb = p->tune.mfma_nb;
-    const int cbw = 16 * nb;
-    const int ncol = (nrhs + cbw - 1) / cbw * cbw;
-    const int grid = mfma_grid(tg, nb);
+    MfmaLayout L;
+    L.tg = p->tune.mfma_tg;
+    L.nb = p->tune.mfma_nb;
+    const int cbw = 16 * L.nb;
+    L.ncol = (nrhs + cbw - 1) / cbw * cbw;
+    const int grid = mfma_grid(L.tg, L.nb);
     const int64_t want = static_cast<int64_t>(grid) * (kBlock / 64) * p->tune.items_per_wave;
-    const int64_t tiles = (n + 16 * tg - 1) / (16 * tg);
-    const int64_t items_per_chunk = static_cast<int64_t>(nf) * (ncol / cbw) * tiles;
+    const int64_t tiles = (n + 16 * L.tg - 1) / (16 * L.tg);
+    const int64_t items_per_chunk = static_cast<int64_t>(nf) * (L.ncol / cbw) * tiles;
     auto chunking = [&](int64_t ns, int64_t &chunk, int &nc) {
         if (ns <= 0) {
             chunk = 4;
@@ -844,17 +1048,30 @@ void apply_forward_mfma_block(vsie_problem *p, int f0, int nf, int nrhs, const d
         chunk = ((ns + c - 1) / c + 3) / 4 * 4;
         nc = static_cast<int>((ns + chunk - 1) / chunk);
     };
-    int64_t chG, chF;
-    int ncG, ncF;
-    chunking(p->G.count, chG, ncG);
-    chunking(p->F.count, chF, ncF);
+    chunking(p->G.count, L.chG, L.ncG);
+    chunking(p->F.count, L.chF, L.ncF);
+    L.fstride = static_cast<int64_t>(L.ncG + L.ncF) * nrhs * n;
+    L.part = sizeof(double2) * static_cast<size_t>(std::max<int64_t>(1, L.fstride * nf));
+    L.ldqG = (p->G.count + kMfmaPad) * L.ncol;
+    L.ldqF = (p->F.count + kMfmaPad) * L.ncol;
+    L.qG = sizeof(float2) * static_cast<size_t>(L.ldqG * nf);
+    L.qF = sizeof(float2) * static_cast<size_t>(L.ldqF * nf);
+    return L;
+}
+
+void apply_forward_mfma_block(vsie_problem *p, int f0, int nf, int nrhs, const double2 *x, int64_t ldx,
+                              int64_t xfs, double2 *y, int64_t ldy, int64_t yfs, hipStream_t s) {
+    const int64_t n = p->m.n;
+    const MfmaLayout L = mfma_layout(p, nf, nrhs);
+    const int tg = L.tg, nb = L.nb, ncol = L.ncol;
+    const int64_t chG = L.chG, chF = L.chF;
+    const int ncG = L.ncG, ncF = L.ncF;
     const int parts = ncG + ncF;
-    const int64_t fstride = static_cast<int64_t>(parts) * nrhs * n;
-    double2 *part = static_cast<double2 *>(
-        p->partial.get(sizeof(double2) * static_cast<size_t>(std::max<int64_t>(1, fstride * nf))));
-    const int64_t ldqG = (p->G.count + kMfmaPad) * ncol, ldqF = (p->F.count + kMfmaPad) * ncol;
-    float2 *qG = static_cast<float2 *>(p->chargeG.get(sizeof(float2) * static_cast<size_t>(ldqG * nf)));
-    float2 *qF = static_cast<float2 *>(p->chargeF.get(sizeof(float2) * static_cast<size_t>(ldqF * nf)));
+    const int64_t fstride = L.fstride;
+    double2 *part = static_cast<double2 *>(p->partial.get(L.part));
+    const int64_t ldqG = L.ldqG, ldqF = L.ldqF;
+    float2 *qG = static_cast<float2 *>(p->chargeG.get(L.qG));
+    float2 *qF = static_cast<float2 *>(p->chargeF.get(L.qF));
     const double *kf = p->d_k0 + f0;
     if (ncG > 0) {
         launch_pack_mfma(kClassG, p->G, p->m.sp + static_cast<int64_t>(f0) * n, n, nf, nrhs, ncol, x, ldx, xfs,
@@ -872,6 +1089,15 @@ void apply_forward_mfma_block(vsie_problem *p, int f0, int nf, int nrhs, const d
     for (int t = 0; t < nf; ++t)
         launch_reduce_partials(n, nrhs, parts, part + t * fstride, p->m.diag + static_cast<int64_t>(f0 + t) * n,
                                false, x + t * xfs, ldx, y + t * yfs, ldy, nullptr, s);
+}
+
+void plan_forward_mfma(vsie_problem *p, int nf, int nrhs, WsPlan &pl) {
+    for (int r0 = 0; r0 < nrhs; r0 += kMfmaMaxCols) {
+        const MfmaLayout L = mfma_layout(p, nf, std::min(kMfmaMaxCols, nrhs - r0));
+        pl.need(p->partial, L.part);
+        pl.need(p->chargeG, L.qG);
+        pl.need(p->chargeF, L.qF);
+    }
 }
 
 void apply_forward_mfma(vsie_problem *p, int f0, int nf, int nrhs, const double2 *x, int64_t ldx, int64_t xfs,
@@ -899,6 +1125,25 @@ void check_tuning(const vsie_tuning &t) {
     require(t.sym_groups == 0 || (t.sym_groups > 1 && sym_groups_ok(t.sym_groups)), "sym_groups must be 0, 2, 4 or 8");
     require(t.cell_face == 0 || t.cell_face == 1, "cell_face must be 0 or 1");
     require(t.mfma_3m == 0 || t.mfma_3m == 1, "mfma_3m must be 0 or 1");
+}
+
+// The work buffers of apply_op (same dispatch).
+void plan_op(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int nrhs, WsPlan &pl) {
+    if (prec == VSIE_FP32 && p->dense[f].A) plan_dense(p, nrhs, pl);
+    else if (adjoint) plan_adjoint(p, prec, nrhs, pl);
+    else if (use_mfma(p, prec, nrhs)) plan_forward_mfma(p, 1, nrhs, pl);
+    else plan_forward(p, prec, nrhs, pl);
+}
+
+// The work buffers of vsie_matvec_multi (same dispatch).
+void plan_multi(vsie_problem *p, int f0, int nf, vsie_precision prec, int nrhs, WsPlan &pl) {
+    bool dense = false;
+    for (int t = 0; t < nf; ++t) dense = dense || p->dense[f0 + t].A != nullptr;
+    if (use_mfma(p, prec, nrhs) && !dense) {
+        plan_forward_mfma(p, nf, nrhs, pl);
+        return;
+    }
+    for (int t = 0; t < nf; ++t) plan_op(p, f0 + t, prec, false, nrhs, pl);
 }
 
 void apply_op(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int nrhs,
@@ -1391,6 +1636,24 @@ int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const
                 int iter_cap, double2 *x, int64_t ldx, SolveCounters &cnt, hipStream_t s, double2 *V,
                 BlockRecycle *save, const BlockRecycle *use);
 
+// Restart length of the independent-GMRES path: as asked, but the two bases
+// of all R right-hand sides must fit kKrylovBytes.
+int gmres_restart(int64_t n, int R, int restart) {
+    const int64_t col_bytes = static_cast<int64_t>(sizeof(double2)) * n * R;
+    return static_cast<int>(std::max<int64_t>(
+        1, std::min<int64_t>(std::max(1, restart), kKrylovBytes / 2 / col_bytes - 1)));
+}
+
+// Block steps per cycle of block GMRES with Ra columns: the requested restart,
+// but the host R factor of the block Hessenberg ((m Ra)^2 complex) stays near
+// 2 GB and the basis within the budget (half of kKrylovBytes each: the first
+// cycle's basis is kept to deflate the later ones).
+int block_restart(int64_t n, int Ra, int restart) {
+    const int64_t mb_host = std::max<int64_t>(1, 11585 / Ra);
+    const int64_t mb_dev = std::max<int64_t>(1, kKrylovBytes / 2 / (static_cast<int64_t>(sizeof(double2)) * n * Ra) - 1);
+    return static_cast<int>(std::min<int64_t>({static_cast<int64_t>(std::max(1, restart)), mb_host, mb_dev}));
+}
+
 // Solve op(A) x_r = b_r for r < R.  FP64: restarted GMRES(m), each restart
 // from the true FP64 residual.  FP32: the same loop is iterative refinement --
 // residuals with the FP64 operator, corrections from one GMRES cycle with the
@@ -1400,10 +1663,8 @@ vsie_status solve_batch(vsie_problem *p, int f, vsie_precision prec, bool adjoin
                         const vsie_solve_opts &o, SolveCounters &cnt, std::vector<double> &relres,
                         hipStream_t s) {
     const int64_t n = p->m.n;
-    // restart length: as asked, but the basis of all R right-hand sides must fit kKrylovBytes
     const int64_t col_bytes = static_cast<int64_t>(sizeof(double2)) * n * R;
-    const int m = static_cast<int>(std::max<int64_t>(
-        1, std::min<int64_t>(std::max(1, o.restart), kKrylovBytes / 2 / col_bytes - 1)));
+    const int m = gmres_restart(n, R, o.restart);
     double2 *V1 = static_cast<double2 *>(p->V.get(static_cast<size_t>(col_bytes) * (m + 1)));
     Recycle first;            // space of the first cycle, deflates every later cycle
     BlockRecycle bfirst;      // the same for block GMRES
@@ -1480,14 +1741,8 @@ vsie_status solve_batch(vsie_problem *p, int f, vsie_precision prec, bool adjoin
         for (int r : next) cnt.outer[r]++;
         int done;
         if (o.block) {
-            // block steps per cycle: the requested restart, but the host R factor of the block
-            // Hessenberg ((m Ra)^2 complex) stays near 2 GB and the basis within the budget
-            // (half of kKrylovBytes each: the first cycle's basis is kept to deflate the later ones)
             const int Ra = static_cast<int>(next.size());
-            const int64_t mb_host = std::max<int64_t>(1, 11585 / Ra);
-            const int64_t mb_dev =
-                std::max<int64_t>(1, kKrylovBytes / 2 / (static_cast<int64_t>(sizeof(double2)) * n * Ra) - 1);
-            const int mb = static_cast<int>(std::min<int64_t>({static_cast<int64_t>(std::max(1, o.restart)), mb_host, mb_dev}));
+            const int mb = block_restart(n, Ra, o.restart);
             const size_t vbytes = sizeof(double2) * static_cast<size_t>(n) * Ra * (mb + 1);
             if (!have_first) {
                 done = block_cycle(p, f, prec, adjoint, next, cyc_res, next_rn, next_tol, mb, o.max_iter, x, ldx,
@@ -1597,10 +1852,22 @@ void zgemm(vsie_problem *p, bool conjA, int64_t m, int64_t nn, int64_t k, cd alp
 constexpr int64_t kTallTargetTiles = 2048;
 constexpr int64_t kTallMinSlab = 512;
 
+int64_t tall_slabs(int64_t m, int64_t nn, int64_t k) {
+    const int64_t tiles = ((m + 63) / 64) * ((nn + 63) / 64);
+    return std::min((kTallTargetTiles + tiles - 1) / tiles, std::max<int64_t>(1, k / kTallMinSlab));
+}
+// bytes of the slab partials of zgemm_tall_cn (0 when one GEMM does it)
+size_t tall_bytes(int64_t m, int64_t nn, int64_t k) {
+    const int64_t slabs = tall_slabs(m, nn, k);
+    if (slabs <= 1) return 0;
+    const int64_t rows = (k + slabs - 1) / slabs;
+    const int64_t full = k / rows, tail = k - full * rows;
+    return sizeof(double2) * static_cast<size_t>(m * nn * (full + (tail > 0 ? 1 : 0)));
+}
+
 void zgemm_tall_cn(vsie_problem *p, int64_t m, int64_t nn, int64_t k, const double2 *A, int64_t lda,
                    const double2 *B, int64_t ldb, double2 *C, int64_t ldc, hipStream_t s) {
-    const int64_t tiles = ((m + 63) / 64) * ((nn + 63) / 64);
-    int64_t slabs = std::min((kTallTargetTiles + tiles - 1) / tiles, std::max<int64_t>(1, k / kTallMinSlab));
+    const int64_t slabs = tall_slabs(m, nn, k);
     if (slabs <= 1) {
         zgemm(p, true, m, nn, k, 1.0, A, lda, B, ldb, 0.0, C, ldc);
         return;
@@ -1883,6 +2150,73 @@ std::vector<cd> BlockRecycle::deflate_coeffs(vsie_problem *p, int64_t n, int Ra2
     return z;
 }
 
+// The work buffers of solve_batch (either path) for R right-hand sides: upper
+// bounds over every cycle, live-column count and refinement step, from the
+// same size rules the solver uses.  Block GMRES's Gram-Schmidt products run
+// on rocBLAS, whose handle keeps device memory of its own.
+void plan_solve(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R, const vsie_solve_opts &o,
+                WsPlan &pl) {
+    const int64_t n = p->m.n;
+    const size_t z = sizeof(double2), nR = z * static_cast<size_t>(n) * R;
+    const int nch = norm_chunks(n);
+    pl.need(p->act2, sizeof(int32_t) * R);
+    for (Scratch *b : {&p->r, &p->xa, &p->axa, &p->rres}) pl.need(*b, nR);
+    pl.need(p->npart, sizeof(double) * nch * R);
+    pl.need(p->nrm, sizeof(double) * R);
+    for (int nl = 1; nl <= R; ++nl) {
+        plan_op(p, f, VSIE_FP64, adjoint, nl, pl);
+        if (prec == VSIE_FP32) plan_op(p, f, VSIE_FP32, adjoint, nl, pl);
+    }
+    if (!o.block) {
+        const int m = gmres_restart(n, R, o.restart);
+        const size_t ns = R, hs = m + 2, cs = m + 2;  // recycled dimensions are at most m
+        pl.need(p->V, nR * (m + 1));
+        pl.need(p->V2, nR * (m + 1));
+        pl.need(p->w, nR);
+        pl.need(p->ax, nR);
+        pl.need(p->h1, z * 2 * hs * ns + sizeof(double) * ns);
+        pl.need(p->tc, z * cs * ns);
+        pl.need(p->dpart, z * nch * (m + 1) * ns);
+        pl.need(p->yv, z * cs * ns);
+        pl.need(p->defP, z * cs * cs * ns);
+        pl.need(p->defM, z * cs * cs * ns);
+        pl.need(p->defB, z * static_cast<size_t>(m) * m * ns);
+        for (Scratch *b : {&p->act, &p->live, &p->kc, &p->kd, &p->defk, &p->lslot}) pl.need(*b, sizeof(int32_t) * ns);
+        return;
+    }
+    int64_t vcols = 0, kmax = 0;
+    for (int Ra = 1; Ra <= R; ++Ra) {
+        const int mb = block_restart(n, Ra, o.restart);
+        vcols = std::max<int64_t>(vcols, static_cast<int64_t>(Ra) * (mb + 1));
+        kmax = std::max<int64_t>(kmax, static_cast<int64_t>(Ra) * mb);
+        pl.need(p->bh, z * static_cast<size_t>(mb + 1) * Ra * Ra);
+        pl.need(p->bg, z * static_cast<size_t>(Ra) * Ra);
+        pl.need(p->bsk, tall_bytes(Ra, Ra, n));
+        for (int j = 0; j < mb; ++j) pl.need(p->bsk, tall_bytes(static_cast<int64_t>(j + 1) * Ra, Ra, n));
+    }
+    // a kept first cycle has at most kBlockRecycleMax columns, from at most R
+    const int64_t kv = std::min(kmax, kBlockRecycleMax) + R;
+    for (int Ra = 1; Ra <= R; ++Ra)
+        for (int64_t k = 1; k <= kv; ++k) pl.need(p->bsk, tall_bytes(k, Ra, n));
+    pl.need(p->brc, z * static_cast<size_t>(kv) * R);
+    pl.need(p->V, z * static_cast<size_t>(n) * vcols);
+    pl.need(p->V2, z * static_cast<size_t>(n) * vcols);
+    pl.need(p->w, nR);
+    pl.need(p->ax, nR);
+    pl.need(p->act, sizeof(int32_t) * R);
+}
+
+// Solver options with defaults, validated.
+vsie_solve_opts solve_options(const vsie_solve_opts *opts) {
+    vsie_solve_opts o{1e-10, 3000, 500, 1e-5, 20, 0, 0.0, 0};
+    if (opts) o = *opts;
+    require(o.tol > 0 && o.max_iter >= 0 && o.restart >= 1 && o.restart <= 20000 && o.inner_tol > 0 &&
+                o.inner_tol < 1 && o.max_outer >= 1 && (o.block == 0 || o.block == 1) && o.relax >= 0 &&
+                o.relax < 1 && (o.progress == 0 || o.progress == 1),
+            "invalid solver options");
+    return o;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -2008,13 +2342,17 @@ vsie_status vsie_set_materials(vsie_problem *p, const double *vrho_dev, const do
 }
 
 vsie_status vsie_matvec(vsie_problem *p, int32_t f, vsie_precision prec, int64_t nrhs,
-                        const double *x, int64_t ldx, double *y, int64_t ldy, void *stream) {
+                        const double *x, int64_t ldx, double *y, int64_t ldy, void *workspace, size_t ws_bytes,
+                        void *stream) {
     return guarded([&] {
         check_problem(p, f);
         require(prec == VSIE_FP64 || prec == VSIE_FP32, "unknown precision");
         require(nrhs >= 1 && nrhs <= 4096, "nrhs must be in [1, 4096]");
         check_vec(x, ldx, p->m.n, "x");
         check_vec(y, ldy, p->m.n, "y");
+        WsPlan pl;
+        if (workspace) plan_op(p, f, prec, false, static_cast<int>(nrhs), pl);
+        WsScope ws(pl, workspace, ws_bytes);
         apply_op(p, f, prec, false, static_cast<int>(nrhs), reinterpret_cast<const double2 *>(x), ldx,
                  reinterpret_cast<double2 *>(y), ldy, as_stream(stream));
     });
@@ -2022,20 +2360,24 @@ vsie_status vsie_matvec(vsie_problem *p, int32_t f, vsie_precision prec, int64_t
 
 vsie_status vsie_matvec_adjoint(vsie_problem *p, int32_t f, vsie_precision prec, int64_t nrhs,
                                 const double *x, int64_t ldx, double *y, int64_t ldy,
-                                void *stream) {
+                                void *workspace, size_t ws_bytes, void *stream) {
     return guarded([&] {
         check_problem(p, f);
         require(prec == VSIE_FP64 || prec == VSIE_FP32, "unknown precision");
         require(nrhs >= 1 && nrhs <= 4096, "nrhs must be in [1, 4096]");
         check_vec(x, ldx, p->m.n, "x");
         check_vec(y, ldy, p->m.n, "y");
+        WsPlan pl;
+        if (workspace) plan_op(p, f, prec, true, static_cast<int>(nrhs), pl);
+        WsScope ws(pl, workspace, ws_bytes);
         apply_op(p, f, prec, true, static_cast<int>(nrhs), reinterpret_cast<const double2 *>(x), ldx,
                  reinterpret_cast<double2 *>(y), ldy, as_stream(stream));
     });
 }
 
 vsie_status vsie_matvec_multi(vsie_problem *p, int32_t f0, int32_t nf, vsie_precision prec, int64_t nrhs,
-                              const double *x, int64_t ldx, double *y, int64_t ldy, void *stream) {
+                              const double *x, int64_t ldx, double *y, int64_t ldy, void *workspace,
+                              size_t ws_bytes, void *stream) {
     return guarded([&] {
         require(p != nullptr, "problem handle is NULL");
         require(nf >= 1 && f0 >= 0 && static_cast<int64_t>(f0) + nf <= static_cast<int64_t>(p->k0.size()),
@@ -2044,6 +2386,9 @@ vsie_status vsie_matvec_multi(vsie_problem *p, int32_t f0, int32_t nf, vsie_prec
         require(nrhs >= 1 && nrhs <= 4096, "nrhs must be in [1, 4096]");
         check_vec(x, ldx, p->m.n, "x");
         check_vec(y, ldy, p->m.n, "y");
+        WsPlan pl;
+        if (workspace) plan_multi(p, f0, nf, prec, static_cast<int>(nrhs), pl);
+        WsScope ws(pl, workspace, ws_bytes);
         hipStream_t s = as_stream(stream);
         const double2 *xv = reinterpret_cast<const double2 *>(x);
         double2 *yv = reinterpret_cast<double2 *>(y);
@@ -2163,25 +2508,24 @@ vsie_status vsie_autotune(vsie_problem *p, int32_t f, int64_t nrhs, vsie_tuning 
 
 vsie_status vsie_solve(vsie_problem *p, int32_t f, vsie_precision prec, int32_t adjoint,
                        int64_t nrhs, const double *b, int64_t ldb, double *x, int64_t ldx,
-                       const vsie_solve_opts *opts, vsie_solve_info *info, void *stream) {
+                       const vsie_solve_opts *opts, vsie_solve_info *info, void *workspace, size_t ws_bytes,
+                       void *stream) {
     if (info) *info = vsie_solve_info{0, 0, 0, 0, 0.0};
     vsie_status result = VSIE_OK;
     const vsie_status st = guarded([&] {
         check_problem(p, f);
         require(prec == VSIE_FP64 || prec == VSIE_FP32, "unknown precision");
         require(adjoint == 0 || adjoint == 1, "adjoint must be 0 or 1");
-        require(nrhs >= 1, "nrhs must be >= 1");
+        require(nrhs >= 1 && nrhs <= 4096, "nrhs must be in [1, 4096]");
         check_vec(b, ldb, p->m.n, "b");
         check_vec(x, ldx, p->m.n, "x");
-        vsie_solve_opts o{1e-10, 3000, 500, 1e-5, 20, 0, 0.0, 0};
-        if (opts) o = *opts;
-        require(o.tol > 0 && o.max_iter >= 0 && o.restart >= 1 && o.restart <= 20000 &&
-                    o.inner_tol > 0 && o.inner_tol < 1 && o.max_outer >= 1 && (o.block == 0 || o.block == 1) &&
-                    o.relax >= 0 && o.relax < 1 && (o.progress == 0 || o.progress == 1),
-                "invalid solver options");
+        const vsie_solve_opts o = solve_options(opts);
+        const int R = static_cast<int>(nrhs);
+        WsPlan pl;
+        if (workspace) plan_solve(p, f, prec, adjoint != 0, R, o, pl);
+        WsScope ws(pl, workspace, ws_bytes);
         p->progress = o.progress;
         hipStream_t s = as_stream(stream);
-        const int R = static_cast<int>(nrhs);
         SolveCounters cnt(R);
         std::vector<double> rr;
         result = solve_batch(p, f, prec, adjoint != 0, R, reinterpret_cast<const double2 *>(b), ldb,
@@ -2199,6 +2543,33 @@ vsie_status vsie_solve(vsie_problem *p, int32_t f, vsie_precision prec, int32_t 
         if (result == VSIE_E_NOCONV) g_last_error = "GMRES did not reach the tolerance";
     });
     return st != VSIE_OK ? st : result;
+}
+
+vsie_status vsie_workspace_size(vsie_problem *p, vsie_op op, int32_t f, int32_t nf, vsie_precision prec,
+                                int64_t nrhs, const vsie_solve_opts *opts, size_t *bytes) {
+    if (bytes) *bytes = 0;
+    return guarded([&] {
+        require(bytes != nullptr, "bytes is NULL");
+        check_problem(p, f);
+        require(prec == VSIE_FP64 || prec == VSIE_FP32, "unknown precision");
+        require(nrhs >= 1 && nrhs <= 4096, "nrhs must be in [1, 4096]");
+        if (op == VSIE_OP_MATVEC_MULTI)
+            require(nf >= 1 && static_cast<int64_t>(f) + nf <= static_cast<int64_t>(p->k0.size()),
+                    "frequency range out of bounds");
+        else
+            require(nf == 1, "nf must be 1 except for VSIE_OP_MATVEC_MULTI");
+        const int R = static_cast<int>(nrhs);
+        WsPlan pl;
+        switch (op) {
+        case VSIE_OP_MATVEC: plan_op(p, f, prec, false, R, pl); break;
+        case VSIE_OP_MATVEC_ADJOINT: plan_op(p, f, prec, true, R, pl); break;
+        case VSIE_OP_MATVEC_MULTI: plan_multi(p, f, nf, prec, R, pl); break;
+        case VSIE_OP_SOLVE:
+        case VSIE_OP_SOLVE_ADJOINT: plan_solve(p, f, prec, op == VSIE_OP_SOLVE_ADJOINT, R, solve_options(opts), pl); break;
+        default: fail(VSIE_E_INVALID, "unknown operation");
+        }
+        *bytes = pl.total();
+    });
 }
 
 vsie_status vsie_plane_wave(vsie_problem *p, int32_t f, int64_t ndir, const double *dirs, double *b,

@@ -81,10 +81,10 @@ def test_null_handles(V):
     lib = V.lib
     assert lib.vsie_size(None) == 0
     lib.vsie_destroy(None)
-    st = lib.vsie_matvec(None, 0, 0, 1, None, 1, None, 1, None)
+    st = lib.vsie_matvec(None, 0, 0, 1, None, 1, None, 1, None, 0, None)
     assert st == V.VSIE_E_INVALID and "NULL" in V.vsie_last_error()
     info = V.SolveInfo()
-    st = lib.vsie_solve(None, 0, 0, 0, 1, None, 1, None, 1, None, ctypes.byref(info), None)
+    st = lib.vsie_solve(None, 0, 0, 0, 1, None, 1, None, 1, None, ctypes.byref(info), None, 0, None)
     assert st == V.VSIE_E_INVALID and info.iterations == 0
     g = V.Geometry()
     h = ctypes.c_void_p(1234)
@@ -129,3 +129,14 @@ def test_set_materials_lengths_checked_in_binding(V):
     short = torch.zeros(3, dtype=torch.float64)
     with pytest.raises(ValueError):
         V.vsie_set_materials(None, short, short)
+
+
+def test_workspace_size_argument_checks(V):
+    """vsie_workspace_size rejects a NULL handle and a NULL output before any
+    device work (and zeroes the output)."""
+    b = ctypes.c_size_t(77)
+    st = V.lib.vsie_workspace_size(None, V.VSIE_OP_SOLVE, 0, 1, 0, 1, None, ctypes.byref(b))
+    assert st == V.VSIE_E_INVALID and b.value == 0
+    st = V.lib.vsie_workspace_size(None, V.VSIE_OP_MATVEC, 0, 1, 0, 1, None, None)
+    assert st == V.VSIE_E_INVALID
+    assert V._STATUS[V.VSIE_E_WORKSPACE] == "VSIE_E_WORKSPACE"

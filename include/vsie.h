@@ -270,6 +270,25 @@ vsie_status vsie_solve(vsie_problem *p, int32_t f, vsie_precision prec, int32_t 
                        const vsie_solve_opts *opts, vsie_solve_info *info, void *workspace, size_t ws_bytes,
                        void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): y = A_f x
+ * exactly as vsie_matvec computes it (same kernels, same results), with its
+ * work buffers in a static device work area of the library instead of
+ * problem-owned or caller memory.  The area holds 256 MiB (268,435,456
+ * bytes) per GPU, is created with the library's code object on each device
+ * it runs on and held until the process ends; its device address is looked
+ * up once per device on the first call there.  A product whose work buffers
+ * (vsie_workspace_size with VSIE_OP_MATVEC) exceed it is refused with
+ * VSIE_E_WORKSPACE before anything is written; the FP32 product with an
+ * assembled operator is refused with VSIE_E_INVALID.  The call allocates no
+ * device memory and records no profiler events.  The problem's device must
+ * be current.  All calls on one GPU share its area: calls that overlap in
+ * time (other streams, other threads, other problems) race; calls ordered
+ * on one stream do not, and nothing in the area needs clearing between
+ * them. */
+vsie_status vsie_matvec_noalloc(vsie_problem *p, int32_t f, vsie_precision prec, int64_t nrhs,
+                                const double *x, int64_t ldx, double *y, int64_t ldy, void *stream);
+
 /* The calls that take a caller workspace. */
 typedef enum {
     VSIE_OP_MATVEC = 0,          /* vsie_matvec */

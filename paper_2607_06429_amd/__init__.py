@@ -25,7 +25,7 @@ __all__ = [
     "vsie_profile_read", "vsie_destroy", "vsie_last_error",
     "vsie_size", "vsie_num_cells", "vsie_matvec_multi", "vsie_get_tuning", "vsie_set_tuning", "vsie_autotune",
     "vsie_workspace_size", "VSIE_OP_MATVEC", "VSIE_OP_MATVEC_ADJOINT", "VSIE_OP_MATVEC_MULTI", "VSIE_OP_SOLVE",
-    "VSIE_OP_SOLVE_ADJOINT",
+    "VSIE_OP_SOLVE_ADJOINT", "vsie_matvec_noalloc",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -98,6 +98,7 @@ def _load():
     L.vsie_num_cells.restype = _I64
     L.vsie_matvec.argtypes = [_P, _I32, _I32, _I64, _P, _I64, _P, _I64, _P, _SZ, _P]
     L.vsie_matvec_adjoint.argtypes = [_P, _I32, _I32, _I64, _P, _I64, _P, _I64, _P, _SZ, _P]
+    L.vsie_matvec_noalloc.argtypes = [_P, _I32, _I32, _I64, _P, _I64, _P, _I64, _P]
     L.vsie_solve.argtypes = [_P, _I32, _I32, _I32, _I64, _P, _I64, _P, _I64,
                              ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P, _SZ, _P]
     L.vsie_workspace_size.argtypes = [_P, _I32, _I32, _I32, _I32, _I64, ctypes.POINTER(SolveOpts),
@@ -126,7 +127,7 @@ def _load():
                  "vsie_profile", "vsie_profile_read", "vsie_plane_wave_at", "vsie_adjoint_rhs",
                  "vsie_param_gradient", "vsie_assemble_dense", "vsie_release_dense",
                  "vsie_matvec_multi", "vsie_get_tuning", "vsie_set_tuning", "vsie_autotune",
-                 "vsie_workspace_size"):
+                 "vsie_workspace_size", "vsie_matvec_noalloc"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -138,7 +139,7 @@ EXPORTED = ("vsie_assemble", "vsie_set_materials", "vsie_size", "vsie_num_cells"
             "vsie_source_sums", "vsie_plane_wave_at", "vsie_adjoint_rhs", "vsie_param_gradient",
             "vsie_assemble_dense", "vsie_release_dense", "vsie_profile", "vsie_profile_read",
             "vsie_destroy", "vsie_last_error", "vsie_matvec_multi", "vsie_get_tuning",
-            "vsie_set_tuning", "vsie_autotune", "vsie_workspace_size")
+            "vsie_set_tuning", "vsie_autotune", "vsie_workspace_size", "vsie_matvec_noalloc")
 
 # pair-kernel kinds reported by vsie_profile_read: 2 * mode + precision
 KIND_NAMES = {0: "fwd_single_layer_fp64", 1: "fwd_single_layer_fp32", 2: "fwd_double_layers_fp64",
@@ -269,6 +270,17 @@ def vsie_matvec(h, f, prec, x, y, stream=None, workspace=None):
     if Ry != R:
         raise ValueError("x and y hold different numbers of columns")
     _check(lib.vsie_matvec(h, f, prec, R, px, ldx, py, ldy, *_ws(workspace), _stream(stream)))
+
+
+def vsie_matvec_noalloc(h, f, prec, x, y, stream=None):
+    """y = A_f x with the work buffers in the library's static device work
+    area (no device allocation; see include/vsie.h)."""
+    n = vsie_size(h)
+    px, R, ldx = _cols(x, n)
+    py, Ry, ldy = _cols(y, n)
+    if Ry != R:
+        raise ValueError("x and y hold different numbers of columns")
+    _check(lib.vsie_matvec_noalloc(h, f, prec, R, px, ldx, py, ldy, _stream(stream)))
 
 
 def vsie_matvec_adjoint(h, f, prec, x, y, stream=None, workspace=None):

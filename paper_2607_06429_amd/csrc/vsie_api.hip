@@ -8,6 +8,7 @@
 #include <cstring>
 #include <initializer_list>
 #include <memory>
+#include <mutex>
 #include <thread>
 #include <string>
 #include <vector>
@@ -2220,9 +2221,78 @@ vsie_solve_opts solve_options(const vsie_solve_opts *opts) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Work area of vsie_matvec_noalloc, for callers that cannot allocate device
+// memory: a static device array, one copy per GPU, held until the process
+// ends.  In host code `scratch` is only a stand-in for the device symbol, not
+// a device address; each device's address comes from hipGetSymbolAddress
+// (taken once per device, with that device current) and only that address is
+// used.  Every work buffer of a product is fully written by the launches that
+// read it, so nothing in the area needs clearing between calls; calls that
+// overlap on one GPU share the area and race.
+constexpr size_t kNoAllocBytes = size_t(256) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kMaxDevices] = {};
+
+void *noalloc_area(int device) {
+    require(device >= 0 && device < kMaxDevices, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[device]) {
+        void *q = nullptr;
+        VSIE_HIP(hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)));
+        require(q != nullptr && reinterpret_cast<uintptr_t>(q) % kWsAlign == 0, "static work area not addressable");
+        g_noalloc_ptr[device] = q;
+    }
+    return g_noalloc_ptr[device];
+}
+
+// Pair-launch timing off for the duration of a call (its events would be
+// created on demand).
+struct ProfilerPause {
+    PairProfiler &pr;
+    bool was;
+    explicit ProfilerPause(vsie_problem *p) : pr(p->prof), was(p->prof.on) { pr.on = false; }
+    ~ProfilerPause() { pr.on = was; }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // ABI
 
 extern "C" {
+
+vsie_status vsie_matvec_noalloc(vsie_problem *p, int32_t f, vsie_precision prec, int64_t nrhs, const double *x,
+                                int64_t ldx, double *y, int64_t ldy, void *stream) {
+    return guarded([&] {
+        check_problem(p, f);
+        require(prec == VSIE_FP64 || prec == VSIE_FP32, "unknown precision");
+        require(nrhs >= 1 && nrhs <= 4096, "nrhs must be in [1, 4096]");
+        check_vec(x, ldx, p->m.n, "x");
+        check_vec(y, ldy, p->m.n, "y");
+        int dev = -1;
+        VSIE_HIP(hipGetDevice(&dev));
+        require(dev == p->device, "the problem's device must be the current device");
+        require(!(prec == VSIE_FP32 && p->dense[f].A),
+                "the assembled FP32 operator's product allocates (rocBLAS); release it or use VSIE_FP64");
+        WsPlan pl;
+        plan_op(p, f, prec, false, static_cast<int>(nrhs), pl);
+        const size_t need = pl.total();
+        if (need > kNoAllocBytes)
+            fail(VSIE_E_WORKSPACE, "the product needs " + std::to_string(need) +
+                                       " bytes of work buffers; the static work area holds " +
+                                       std::to_string(kNoAllocBytes));
+        void *area = noalloc_area(dev);
+        ProfilerPause pause(p);
+        WsScope ws(pl, area, kNoAllocBytes);
+        apply_op(p, f, prec, false, static_cast<int>(nrhs), reinterpret_cast<const double2 *>(x), ldx,
+                 reinterpret_cast<double2 *>(y), ldy, as_stream(stream));
+    });
+}
 
 const char *vsie_last_error(void) { return g_last_error.c_str(); }
 

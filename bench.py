@@ -281,6 +281,21 @@ def paper_benchmark_solves(V, W):
     return res
 
 
+def dense_roofline(st, tuning):
+    """Matrix-core roofline of the product with the assembled FP32 operator:
+    algorithmic FLOP per pass = 8 n^2 R (a complex multiply-add is 8 real
+    FLOP) over the measured launch time, against the FP32 matrix peak; the
+    FLOP the matrix cores execute (6 n^2 R with three real products per
+    complex multiply-add, 8 n^2 R with four) reported beside it."""
+    avg_ms = st["ms"] / st["launches"]
+    macs = st["rhs_pairs"] / st["launches"]          # n^2 R complex multiply-adds per launch
+    alg = 8.0 * macs / (avg_ms * 1e-3) / 1e12
+    mfma = (6.0 if tuning["mfma_3m"] else 8.0) * macs / (avg_ms * 1e-3) / 1e12
+    return {"bound": "mfma", "launches": st["launches"], "avg_launch_ms": avg_ms,
+            "achieved": alg, "peak": 157.3, "unit": "TFLOP/s", "frac": alg / 157.3,
+            "mfma_executed_tflops": mfma, "mfma_busy_frac": mfma / 157.3}
+
+
 def batched_workloads(V, W):
     """Block GMRES over 128 directions (assembled and matrix-free) and one
     multi-frequency product over 8 wavenumbers x 16 directions."""
@@ -317,6 +332,8 @@ def batched_workloads(V, W):
             "solve_s": dt, "iterations": info, "gpair_col_evals_per_s": float(n) * n * mv / dt / 1e9,
             "tuning": P.tuning if name == "matrix_free_fp32" else None,
             "pair_kernels": {k: {"launches": v["launches"], "ms": v["ms"]} for k, v in st.items()}}
+        if A is not None and "dense_product_fp32" in st:
+            out["c2_block_gmres_" + name]["dense_product"] = dense_roofline(st["dense_product_fp32"], P.tuning)
         if A is not None:
             P.release_dense(0)
             del A

@@ -387,11 +387,12 @@ vsie_status vsie_param_gradient(vsie_problem *p, int32_t f, int64_t nrhs, const 
  * parts at dense[i + j ld], the imaginary parts at dense[ld n + i + j ld].
  * Until vsie_release_dense or vsie_set_materials, every VSIE_FP32 product at
  * frequency f (vsie_matvec, vsie_matvec_adjoint and the inner solves of
- * vsie_solve) multiplies by this matrix: per slab of 8192 columns (rows for
- * the adjoint) two real GEMMs (rocBLAS, FP32 on the matrix cores), each plane
- * times [Re x | Im x], whose FP32 products are combined and added in FP64
- * with the FP64 diagonal.  The memory must stay valid while in use; n and ld
- * must be below 2^31. */
+ * vsie_solve) multiplies by this matrix on the matrix cores
+ * (v_mfma_f32_16x16x4_f32), up to 128 columns per pass: per slab of 8192
+ * columns of A (rows for the adjoint) FP32 sums of three real products per
+ * complex multiply-add (four with vsie_tuning.mfma_3m = 0), combined and
+ * added in FP64 in slab order with the FP64 diagonal.  The memory must stay
+ * valid while in use; n and ld must be below 2^31. */
 vsie_status vsie_assemble_dense(vsie_problem *p, int32_t f, void *dense, int64_t ld, void *stream);
 vsie_status vsie_release_dense(vsie_problem *p, int32_t f);
 
@@ -412,7 +413,10 @@ vsie_status vsie_release_dense(vsie_problem *p, int32_t f);
  * both directions); kind 14 and 15 the far-field pattern's single-layer
  * sources, 16 and 17 its double-layer sources, in FP64 and FP32 (pairs =
  * directions x sources); kind 18 and 19 the face-face double layers once per
- * pair in FP64 and FP32 (pairs = n_srf (n_srf - 1)). */
+ * pair in FP64 and FP32 (pairs = n_srf (n_srf - 1)); kind 20 the product with
+ * the assembled FP32 operator on the matrix cores (pairs = n^2 entries,
+ * rhs_pairs = n^2 nrhs complex multiply-adds per pass of at most 128
+ * columns). */
 typedef struct {
     int64_t launches;
     double ms;

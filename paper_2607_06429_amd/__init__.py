@@ -150,7 +150,7 @@ KIND_NAMES = {0: "fwd_single_layer_fp64", 1: "fwd_single_layer_fp32", 2: "fwd_do
               12: "cell_face_fp64", 13: "cell_face_fp32",
               14: "far_field_single_layer_fp64", 15: "far_field_single_layer_fp32",
               16: "far_field_double_layers_fp64", 17: "far_field_double_layers_fp32",
-              18: "face_face_fp64", 19: "face_face_fp32"}
+              18: "face_face_fp64", 19: "face_face_fp32", 20: "dense_product_fp32"}
 
 
 def vsie_last_error() -> str:

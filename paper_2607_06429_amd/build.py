@@ -23,8 +23,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libvsie.so")
 ARCH = os.environ.get("VSIE_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["pair_kernels.hip", "mfma_kernels.hip", "sym_kernels.hip", "far_field.hip", "aux_kernels.hip",
-           "gradient.hip", "vsie_api.hip"]
+SOURCES = ["pair_kernels.hip", "mfma_kernels.hip", "sym_kernels.hip", "far_field.hip", "dense_kernels.hip",
+           "aux_kernels.hip", "gradient.hip", "vsie_api.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -966,50 +966,32 @@ void apply_adjoint(vsie_problem *p, int f, vsie_precision prec, int nrhs, const 
 }
 
 // FP32 product with the assembled operator of frequency f: y = d x + A x (or
-// conj(d) x + A^H x).  A is stored as two real planes, so each slab of
-// kDenseChunk sources (targets for the adjoint) takes two real rocBLAS GEMMs,
-// Ar_c [Re x | Im x] and Ai_c [Re x | Im x], with 2 nrhs columns each (FP32
-// on the matrix cores; measured faster than one complex GEMM with nrhs
-// columns); their FP32 products are combined and added in FP64.
-constexpr int64_t kDenseChunk = 8192;
-
+// conj(d) x + A^H x), in passes of at most kDenseCols columns on the matrix
+// cores (dense_kernels.hip): FP32 sums over slabs of kDenseSlab sources,
+// added in FP64 in slab order with the FP64 diagonal.
 void plan_dense(vsie_problem *p, int nrhs, WsPlan &pl) {
     const int64_t n = p->m.n;
-    const int nc = static_cast<int>((n + kDenseChunk - 1) / kDenseChunk);
-    const int64_t blk = static_cast<int64_t>(2) * nrhs * n;
-    pl.need(p->dense_x, sizeof(float) * static_cast<size_t>(blk));
-    pl.need(p->dense_part, sizeof(float) * static_cast<size_t>(2 * blk * nc));
+    const int blk = std::min(nrhs, kDenseCols);
+    const int64_t slabs = (n + kDenseSlab - 1) / kDenseSlab;
+    pl.need(p->dense_x, sizeof(float) * 2 * static_cast<size_t>(dense_npad(n)) * kDenseCols);
+    pl.need(p->dense_part, sizeof(double2) * static_cast<size_t>(slabs * blk * n));
 }
 
 void apply_dense(vsie_problem *p, int f, bool adjoint, int nrhs, const double2 *x, int64_t ldx,
                  double2 *y, int64_t ldy, hipStream_t s) {
     const int64_t n = p->m.n;
     const auto &D = p->dense[f];
-    if (!p->blas) check_blas(rocblas_create_handle(&p->blas), "rocblas_create_handle");
-    check_blas(rocblas_set_stream(p->blas, s), "rocblas_set_stream");
-    const int nc = static_cast<int>((n + kDenseChunk - 1) / kDenseChunk);
-    const int64_t blk = static_cast<int64_t>(2) * nrhs * n;  // one n x 2 nrhs product
-    float *X2 = static_cast<float *>(p->dense_x.get(sizeof(float) * static_cast<size_t>(blk)));
-    float *Y = static_cast<float *>(p->dense_part.get(sizeof(float) * static_cast<size_t>(2 * blk * nc)));
-    launch_pack_planar(n, nrhs, x, ldx, X2, s);
-    const float one = 1.0f, zero = 0.0f;
-    const float *planes[2] = {D.A, D.A + D.ld * n};
-    for (int c = 0; c < nc; ++c) {
-        const int64_t k0 = static_cast<int64_t>(c) * kDenseChunk;
-        const int kk = static_cast<int>(std::min<int64_t>(kDenseChunk, n - k0));
-        for (int pl = 0; pl < 2; ++pl) {
-            float *Yc = Y + (2 * static_cast<int64_t>(c) + pl) * blk;
-            // forward: columns k0.. of the plane times rows k0.. of X2;
-            // adjoint: (rows k0.. of the plane)^T times rows k0.. of X2
-            const float *Ap = adjoint ? planes[pl] + k0 : planes[pl] + k0 * D.ld;
-            check_blas(rocblas_sgemm(p->blas, adjoint ? rocblas_operation_transpose : rocblas_operation_none,
-                                     rocblas_operation_none, static_cast<rocblas_int>(n), 2 * nrhs, kk, &one,
-                                     Ap, static_cast<rocblas_int>(D.ld), X2 + k0, static_cast<rocblas_int>(n),
-                                     &zero, Yc, static_cast<rocblas_int>(n)),
-                       "rocblas_sgemm");
-        }
+    const int64_t slabs = (n + kDenseSlab - 1) / kDenseSlab;
+    float *xp = static_cast<float *>(
+        p->dense_x.get(sizeof(float) * 2 * static_cast<size_t>(dense_npad(n)) * kDenseCols));
+    for (int r0 = 0; r0 < nrhs; r0 += kDenseCols) {
+        const int blk = std::min(kDenseCols, nrhs - r0);
+        double2 *part = static_cast<double2 *>(p->dense_part.get(sizeof(double2) * static_cast<size_t>(slabs * blk * n)));
+        const DenseJob J{adjoint, p->tune.mfma_3m != 0, n, D.A, D.A + D.ld * n, D.ld, blk,
+                         x + static_cast<int64_t>(r0) * ldx, ldx, xp, part, p->m.diag + static_cast<int64_t>(f) * n,
+                         y + static_cast<int64_t>(r0) * ldy, ldy};
+        launch_dense_product(J, s, &p->prof);
     }
-    launch_reduce_planar(n, nrhs, nc, Y, p->m.diag + static_cast<int64_t>(f) * n, adjoint, x, ldx, y, ldy, s);
 }
 
 // FP32 forward products on the matrix cores for the nf frequencies f0 ..:
@@ -1158,14 +1140,14 @@ void apply_op(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int nrh
 // apply_op through a hipGraph of its launches, for the fixed work buffers the
 // solver applies the operator to every iteration.  The first call with a key
 // runs eagerly (which sizes every work buffer and gives this call's product)
-// and then captures the same launches; later calls launch the graph.  The
-// matrix-free paths launch kernels only (no memset or copy nodes).  Profiled
-// products and the assembled (rocBLAS) path stay eager.
+// and then captures the same launches; later calls launch the graph.  Every
+// path launches kernels only (no memset or copy nodes).  Profiled products
+// stay eager.
 constexpr size_t kMaxGraphs = 16;
 
 void apply_op_graph(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int nrhs,
                     const double2 *x, int64_t ldx, double2 *y, int64_t ldy, hipStream_t s) {
-    if (!p->tune.graph || p->prof.on || (prec == VSIE_FP32 && p->dense[f].A)) {
+    if (!p->tune.graph || p->prof.on) {
         apply_op(p, f, prec, adjoint, nrhs, x, ldx, y, ldy, s);
         return;
     }
@@ -2277,8 +2259,6 @@ vsie_status vsie_matvec_noalloc(vsie_problem *p, int32_t f, vsie_precision prec,
         int dev = -1;
         VSIE_HIP(hipGetDevice(&dev));
         require(dev == p->device, "the problem's device must be the current device");
-        require(!(prec == VSIE_FP32 && p->dense[f].A),
-                "the assembled FP32 operator's product allocates (rocBLAS); release it or use VSIE_FP64");
         WsPlan pl;
         plan_op(p, f, prec, false, static_cast<int>(nrhs), pl);
         const size_t need = pl.total();
@@ -2870,7 +2850,7 @@ vsie_status vsie_profile(vsie_problem *p, int32_t enable) {
 vsie_status vsie_profile_read(vsie_problem *p, int32_t kind, vsie_kernel_stats *out) {
     return guarded([&] {
         require(p != nullptr && out != nullptr, "NULL argument");
-        require(kind >= 0 && kind < 20, "kernel kind out of range");
+        require(kind >= 0 && kind < 21, "kernel kind out of range");
         vsie_kernel_stats st{0, 0.0, 0.0, 0.0};
         for (auto &r : p->prof.recs) {
             if (r.kind != kind) continue;

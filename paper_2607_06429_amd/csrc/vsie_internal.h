@@ -274,6 +274,32 @@ void launch_cf_reduce(int64_t n, int64_t nc, bool slots32, int n_sym, const void
                       int n_fs, const void *pf, int n_ff, const void *ff, bool ff32, const double2 *diag,
                       const double2 *x, double2 *y, hipStream_t s, bool adj = false, const double *adj_sp = nullptr);
 
+// Product with the assembled FP32 operator on the matrix cores
+// (dense_kernels.hip), nrhs <= kDenseCols columns:
+//   forward y = d x + A x,  adjoint y = conj(d) x + A^H x,
+// A in two column-major FP32 planes ar, ai (leading dimension ld).  FP32 sums
+// over slabs of kDenseSlab sources, added in FP64 in slab order.  Work
+// buffers: xp (2 dense_npad(n) kDenseCols floats, the packed columns) and part
+// (ceil(n / kDenseSlab) nrhs n double2, the slab partials).
+constexpr int kDenseCols = 128;
+constexpr int64_t kDenseSlab = 8192;
+struct DenseJob {
+    bool adjoint, m3;
+    int64_t n;
+    const float *ar, *ai;
+    int64_t ld;
+    int nrhs;
+    const double2 *x;
+    int64_t ldx;
+    float *xp;
+    double2 *part;
+    const double2 *diag;
+    double2 *y;
+    int64_t ldy;
+};
+int64_t dense_npad(int64_t n);
+void launch_dense_product(const DenseJob &J, hipStream_t s, PairProfiler *prof);
+
 // auxiliary kernels (aux_kernels.hip)
 void launch_weights(const DeviceMesh &m, const double *k0, int n_freq, hipStream_t s);
 // charge[r * count + jj] = scale * x[idx[jj] + r ldx], scale = -s'_f for class G, else 1

@@ -279,9 +279,8 @@ vsie_status vsie_solve(vsie_problem *p, int32_t f, vsie_precision prec, int32_t 
  * it runs on and held until the process ends; its device address is looked
  * up once per device on the first call there.  A product whose work buffers
  * (vsie_workspace_size with VSIE_OP_MATVEC) exceed it is refused with
- * VSIE_E_WORKSPACE before anything is written; the FP32 product with an
- * assembled operator is refused with VSIE_E_INVALID.  The call allocates no
- * device memory and records no profiler events.  The problem's device must
+ * VSIE_E_WORKSPACE before anything is written.  The call allocates no device
+ * memory and records no profiler events.  The problem's device must
  * be current.  All calls on one GPU share its area: calls that overlap in
  * time (other streams, other threads, other problems) race; calls ordered
  * on one stream do not, and nothing in the area needs clearing between

@@ -1,6 +1,7 @@
 // C ABI of libvsie.so: validation, device data, operator application and the
 // GMRES solver with FP64 iterative refinement.  See include/vsie.h.
 #include <algorithm>
+#include <chrono>
 #include <atomic>
 #include <cmath>
 #include <complex>
@@ -1260,6 +1261,65 @@ void parallel_for(int count, double work, Fn fn) {
 }
 
 
+// Y <- R^{-1} Y for an upper triangular R (k x k, column-major, leading
+// dimension ld) and nc right-hand sides (Y column-major k x nc, ldy = k); a
+// zero pivot gives a zero component.  Columns go in blocks of kTriBlock to
+// the host threads; each block is solved column-oriented (y_i /= R_ii, then
+// the rows above lose R(0:i, i) y_i), so R is read one contiguous column at a
+// time, once per block.  (The row-oriented form reads R(i, i+1:k) at stride
+// ld: one cache miss per entry, about 40 times slower at k = 2688.)
+constexpr int kTriBlock = 8;
+
+// col(i) points at column i of R (entries 0..i contiguous)
+template <typename Col>
+void tri_solve_upper_cols_by(Col col, int64_t k, int nc, cd *Y) {
+    if (k <= 0 || nc <= 0) return;
+    const int nblk = (nc + kTriBlock - 1) / kTriBlock;
+    parallel_for(nblk, 4.0 * static_cast<double>(k) * k * nc, [&](int b) {
+        const int c0 = b * kTriBlock, nb = std::min(kTriBlock, nc - c0);
+        // block rows i: kTriBlock interleaved (re, im) pairs
+        std::vector<double> Yb(static_cast<size_t>(k) * 2 * kTriBlock, 0.0);
+        for (int c = 0; c < nb; ++c)
+            for (int64_t i = 0; i < k; ++i) {
+                const cd v = Y[(c0 + c) * k + i];
+                Yb[(i * kTriBlock + c) * 2] = v.real();
+                Yb[(i * kTriBlock + c) * 2 + 1] = v.imag();
+            }
+        for (int64_t i = k - 1; i >= 0; --i) {
+            const cd *Rc = col(i);
+            const cd d = Rc[i];
+            double *yi = &Yb[i * 2 * kTriBlock];
+            for (int c = 0; c < kTriBlock; ++c) {
+                const cd v = d == 0.0 ? cd(0.0) : cd(yi[2 * c], yi[2 * c + 1]) / d;
+                yi[2 * c] = v.real();
+                yi[2 * c + 1] = v.imag();
+            }
+            const double *Ri = reinterpret_cast<const double *>(Rc);
+            for (int64_t t = 0; t < i; ++t) {
+                const double rr = Ri[2 * t], ri = Ri[2 * t + 1];
+                double *yt = &Yb[t * 2 * kTriBlock];
+                for (int c = 0; c < kTriBlock; ++c) {
+                    const double ar = yi[2 * c], ai = yi[2 * c + 1];
+                    yt[2 * c] -= rr * ar - ri * ai;
+                    yt[2 * c + 1] -= rr * ai + ri * ar;
+                }
+            }
+        }
+        for (int c = 0; c < nb; ++c)
+            for (int64_t i = 0; i < k; ++i)
+                Y[(c0 + c) * k + i] = cd(Yb[(i * kTriBlock + c) * 2], Yb[(i * kTriBlock + c) * 2 + 1]);
+    });
+}
+
+// R column-major with leading dimension ld
+void tri_solve_upper_cols(const cd *R, int64_t ld, int64_t k, int nc, cd *Y) {
+    tri_solve_upper_cols_by([&](int64_t i) { return R + i * ld; }, k, nc, Y);
+}
+
+// Upper triangle stored by columns, packed: column c holds its c + 1
+// entries at offset c (c + 1) / 2.
+inline size_t packed_col(int64_t c) { return static_cast<size_t>(c) * (c + 1) / 2; }
+
 // The Krylov space of a finished cycle, kept to deflate later cycles (GCRO):
 // the cycle's Arnoldi relation A V_k = V_{k+1} Hbar with Hbar = Q R by the
 // cycle's own Givens rotations gives C = V_{k+1} Q (orthonormal) and
@@ -1956,14 +2016,11 @@ int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const
     double2 *Dd = kr > 0 ? static_cast<double2 *>(p->brc.get(sizeof(double2) * static_cast<size_t>(kv) * Ra)) : nullptr;
     std::vector<cd> Bm;
     if (kr > 0) {
-        const std::vector<cd> z = use->deflate_coeffs(p, n, Ra, Rres, Dd, s);
+        std::vector<cd> z = use->deflate_coeffs(p, n, Ra, Rres, Dd, s);
         zgemm(p, false, n, Ra, kv, -1.0, use->V, n, Dd, kv, 1.0, Rres, n);
+        tri_solve_upper_cols(use->R.data(), kr, kr, Ra, z.data());
         std::vector<double2> yh(static_cast<size_t>(kr) * Ra);
-        parallel_for(Ra, 4.0 * Ra * kr * kr, [&](int c) {
-            const std::vector<cd> y0 = use->r_solve(std::vector<cd>(z.begin() + static_cast<size_t>(c) * kr,
-                                                                    z.begin() + static_cast<size_t>(c + 1) * kr));
-            for (int64_t i = 0; i < kr; ++i) yh[static_cast<size_t>(c) * kr + i] = make_double2(y0[i].real(), y0[i].imag());
-        });
+        for (size_t q = 0; q < yh.size(); ++q) yh[q] = make_double2(z[q].real(), z[q].imag());
         to_device(Dd, yh, s);
         zgemm(p, false, n, Ra, kr, 1.0, use->V, n, Dd, kr, 0.0, W, n);
         blas_scatter_add(n, Ra, act, W, x, ldx, s);
@@ -1975,17 +2032,32 @@ int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const
     std::vector<cd> G(static_cast<size_t>(ldH) * Ra, 0.0);
     for (int c = 0; c < Ra; ++c)
         for (int i = 0; i <= c; ++i) G[static_cast<size_t>(c) * ldH + i] = S0[static_cast<size_t>(c) * Ra + i];
-    std::vector<cd> Rf(static_cast<size_t>(m) * Ra * m * Ra, 0.0);
-    const int64_t ldR = static_cast<int64_t>(m) * Ra;
+    // R factor of the block Hessenberg, packed by columns and grown one block
+    // column per step (the full (m Ra)^2 array would be several GB to zero)
+    std::vector<cd> Rf;
     std::vector<cd> U(static_cast<size_t>(m) * Ra * (Ra + 1), 0.0);  // reflector of column c at c (Ra + 1)
     std::vector<double> UU(static_cast<size_t>(m) * Ra, 0.0);
     std::vector<double2> hh;
     int jdone = 0;
+    // progress mode: wall time of the sections of each block step (the
+    // stream is synchronised at each mark, so these runs are diagnostic)
+    using clk = std::chrono::steady_clock;
+    double sec[4] = {0, 0, 0, 0};  // operator, Gram-Schmidt, CholeskyQR, host QR
+    auto mark = [&](clk::time_point &t, int which) {
+        if (!p->progress) return;
+        VSIE_HIP(hipStreamSynchronize(s));
+        const clk::time_point now = clk::now();
+        sec[which] += std::chrono::duration<double>(now - t).count();
+        t = now;
+    };
     for (int j = 0; j < m; ++j) {
         bool capped = false;
         for (int r : rhs) capped = capped || cnt.it[r] >= iter_cap;
         if (capped) break;
+        clk::time_point tm = clk::now();
+        if (p->progress) VSIE_HIP(hipStreamSynchronize(s));
         apply_op(p, f, prec, adjoint, Ra, V + static_cast<int64_t>(j) * Ra * n, n, W, n, s);
+        mark(tm, 0);
         for (int r : rhs) (prec == VSIE_FP64 ? cnt.mv64 : cnt.mv32)[r]++;
         const int64_t kb = static_cast<int64_t>(j + 1) * Ra;
         std::vector<cd> Hc(static_cast<size_t>(kb + Ra) * Ra, 0.0);  // new block column, rows 0..kb+Ra
@@ -2005,8 +2077,10 @@ int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const
                 for (int64_t i = 0; i < kb; ++i)
                     Hc[static_cast<size_t>(c) * (kb + Ra) + i] += cd(hh[c * kb + i].x, hh[c * kb + i].y);
         }
+        mark(tm, 1);
         std::vector<cd> T;
         cholqr2(p, n, Ra, W, Z, V + kb * n, T, s);
+        mark(tm, 2);
         for (int c = 0; c < Ra; ++c)
             for (int i = 0; i <= c; ++i) Hc[static_cast<size_t>(c) * (kb + Ra) + kb + i] = T[static_cast<size_t>(c) * Ra + i];
         // previous reflectors on the new columns (independent per column)
@@ -2016,6 +2090,7 @@ int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const
             for (int64_t k = 0; k < c0; ++k) apply_reflector(&U[static_cast<size_t>(k) * (Ra + 1)], UU[k], Ra + 1, h + k);
         });
         // this block's reflectors, column by column
+        Rf.resize(packed_col(c0 + Ra));
         for (int cl = 0; cl < Ra; ++cl) {
             const int64_t c = c0 + cl;
             cd *h = &Hc[static_cast<size_t>(cl) * (kb + Ra)];
@@ -2024,10 +2099,12 @@ int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const
             for (int t = 0; t <= Ra; ++t) u[t] = h[c + t];
             cd alpha;
             UU[c] = make_reflector(u, Ra + 1, alpha);
-            for (int64_t i = 0; i < c; ++i) Rf[static_cast<size_t>(c) * ldR + i] = h[i];
-            Rf[static_cast<size_t>(c) * ldR + c] = UU[c] == 0.0 ? h[c] : alpha;
+            cd *rc_ = &Rf[packed_col(c)];
+            for (int64_t i = 0; i < c; ++i) rc_[i] = h[i];
+            rc_[c] = UU[c] == 0.0 ? h[c] : alpha;
             for (int rc = 0; rc < Ra; ++rc) apply_reflector(u, UU[c], Ra + 1, &G[static_cast<size_t>(rc) * ldH + c]);
         }
+        mark(tm, 3);
         for (int r : rhs) cnt.it[r]++;
         jdone = j + 1;
         bool all = true;
@@ -2040,34 +2117,38 @@ int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const
             worst = std::max(worst, std::sqrt(res) / rn[rc]);
         }
         if (p->progress) {
-            std::fprintf(stderr, "[vsie] block step %d (%d columns): max residual estimate %.3e of the cycle start\n",
-                         j + 1, Ra, worst);
+            std::fprintf(stderr,
+                         "[vsie] block step %d (%d columns): max residual estimate %.3e of the cycle start "
+                         "(seconds so far: operator %.3f, Gram-Schmidt %.3f, CholeskyQR %.3f, host QR %.3f)\n",
+                         j + 1, Ra, worst, sec[0], sec[1], sec[2], sec[3]);
             std::fflush(stderr);
         }
         if (all) break;
     }
     if (jdone == 0) return 0;
-    // Y = R^{-1} G(0 : jdone Ra, :), per column; with deflation also
-    // Wc = R_use^{-1} (Bm Y), the coefficients of U (Bm Y) in the recycled basis
+    // Y = R^{-1} G(0 : jdone Ra, :); with deflation also Wc = R_use^{-1} (Bm Y),
+    // the coefficients of U (Bm Y) in the recycled basis
     const int64_t kk = static_cast<int64_t>(jdone) * Ra;
+    std::vector<cd> Ycol(static_cast<size_t>(kk) * Ra);
+    for (int rc = 0; rc < Ra; ++rc)
+        std::copy(G.begin() + static_cast<size_t>(rc) * ldH, G.begin() + static_cast<size_t>(rc) * ldH + kk,
+                  Ycol.begin() + static_cast<size_t>(rc) * kk);
+    tri_solve_upper_cols_by([&](int64_t i) { return Rf.data() + packed_col(i); }, kk, Ra, Ycol.data());
     std::vector<double2> Yh(static_cast<size_t>(kk) * Ra), Wc(static_cast<size_t>(kr) * Ra);
-    parallel_for(Ra, 4.0 * Ra * (kk * kk + 2 * kr * kk + kr * kr), [&](int rc) {
-        std::vector<cd> y(kk);
-        for (int64_t i = kk - 1; i >= 0; --i) {
-            cd acc = G[static_cast<size_t>(rc) * ldH + i];
-            for (int64_t t = i + 1; t < kk; ++t) acc -= Rf[static_cast<size_t>(t) * ldR + i] * y[t];
-            const cd d = Rf[static_cast<size_t>(i) * ldR + i];
-            y[i] = d == 0.0 ? 0.0 : acc / d;
-        }
-        for (int64_t i = 0; i < kk; ++i) Yh[static_cast<size_t>(rc) * kk + i] = make_double2(y[i].real(), y[i].imag());
-        if (kr > 0) {
-            std::vector<cd> by(kr, 0.0);
-            for (int64_t t = 0; t < kk; ++t)
-                for (int64_t i = 0; i < kr; ++i) by[i] += Bm[static_cast<size_t>(t) * kr + i] * y[t];
-            const std::vector<cd> w = use->r_solve(by);
-            for (int64_t i = 0; i < kr; ++i) Wc[static_cast<size_t>(rc) * kr + i] = make_double2(w[i].real(), w[i].imag());
-        }
-    });
+    for (size_t q = 0; q < Yh.size(); ++q) Yh[q] = make_double2(Ycol[q].real(), Ycol[q].imag());
+    if (kr > 0) {
+        std::vector<cd> by(static_cast<size_t>(kr) * Ra, 0.0);
+        parallel_for(Ra, 8.0 * Ra * kk * kr, [&](int rc) {
+            cd *o = &by[static_cast<size_t>(rc) * kr];
+            for (int64_t t = 0; t < kk; ++t) {
+                const cd yt = Ycol[static_cast<size_t>(rc) * kk + t];
+                const cd *bm = &Bm[static_cast<size_t>(t) * kr];
+                for (int64_t i = 0; i < kr; ++i) o[i] += bm[i] * yt;
+            }
+        });
+        tri_solve_upper_cols(use->R.data(), kr, kr, Ra, by.data());
+        for (size_t q = 0; q < Wc.size(); ++q) Wc[q] = make_double2(by[q].real(), by[q].imag());
+    }
     double2 *Yd = static_cast<double2 *>(p->bh.get(sizeof(double2) * static_cast<size_t>(std::max(kk, ldH)) * Ra));
     to_device(Yd, Yh, s);
     zgemm(p, false, n, Ra, kk, 1.0, V, n, Yd, kk, 0.0, W, n);
@@ -2085,7 +2166,7 @@ int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const
         save->UU.assign(UU.begin(), UU.begin() + kk);
         save->R.assign(static_cast<size_t>(kk) * kk, 0.0);
         for (int64_t c = 0; c < kk; ++c)
-            for (int64_t i = 0; i <= c; ++i) save->R[static_cast<size_t>(c) * kk + i] = Rf[static_cast<size_t>(c) * ldR + i];
+            for (int64_t i = 0; i <= c; ++i) save->R[static_cast<size_t>(c) * kk + i] = Rf[packed_col(c) + i];
     }
     return jdone;
 }

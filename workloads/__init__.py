@@ -27,6 +27,7 @@ import numpy as np
 
 __all__ = [
     "Mesh", "Materials", "voxel_mesh", "tensor_mesh", "nested_balls", "cube_with_ellipsoid", "nested_cubes",
+    "kuhn_tet_mesh", "nested_cubes_tets", "nested_balls_tets", "cube_to_ball",
     "benchmark1_problem", "benchmark2_problem", "benchmark3_density", "benchmark3_density_gradient",
     "benchmark3_problem", "benchmark4_density", "benchmark4_density_gradient", "benchmark4_problem",
     "materials_piecewise", "materials_config", "fibonacci_sphere",
@@ -249,6 +250,179 @@ def nested_cubes(n_shell: int, n_inner: int, L1: float = 7.0, L2: float = 5.0) -
         inner = (i >= lo) & (i < hi) & (j >= lo) & (j < hi) & (k >= lo) & (k < hi)
         return np.where(inner, 2, 1)
     return tensor_mesh(edges, dom)
+
+
+# the 6 monotone lattice paths from corner (0,0,0) to (1,1,1) of a cuboid, one
+# per Kuhn tetrahedron (the axis moved at each of the three steps)
+KUHN_PATHS = ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0))
+
+
+def kuhn_tet_mesh(edges, domain_of_index, vertex_map=None) -> Mesh:
+    """Conforming tetrahedral mesh of the cells of the tensor grid
+    edges x edges x edges that ``domain_of_index(I, J, K)`` puts in Omega_1 or
+    Omega_2 (0 = exterior), for the "conforming tetrahedral meshes" the paper
+    leaves to future implementations (section 2.3.1).
+
+    Each cuboid is split into the 6 Kuhn tetrahedra around its main diagonal
+    (corner (i,j,k) to (i+1,j+1,k+1); tetrahedron p has the vertices visited by
+    the path KUHN_PATHS[p]).  Every cell uses the same diagonal direction, so
+    each rectangular cell face is split by its (low, low)-(high, high) diagonal
+    from both sides and the mesh is conforming.  ``vertex_map(V) -> V'``
+    optionally moves the grid vertices (curved interfaces); elements stay
+    straight-sided.
+
+    Volume elements: the tetrahedra (centroid = vertex mean, volume), Omega_1
+    first, each subdomain ordered by (path, cell).  Surface elements: the two
+    triangles of every cell face between Omega_1 and the exterior (Gamma_1)
+    and between Omega_2 and Omega_1 (Gamma_2), with the unit normal of the
+    triangle pointing away from the inside tetrahedron, and the tetrahedra on
+    both sides as srf_cell_in / srf_cell_out.  vol_nb is -1 everywhere (no
+    face-neighbour stencil: densities are piecewise constant or come with an
+    analytic gradient).
+    """
+    e = np.asarray(edges, dtype=np.float64)
+    N = e.size - 1
+    I, J, K = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
+    flat = np.asarray(domain_of_index(I.ravel(), J.ravel(), K.ravel()), dtype=np.int32)
+    g = np.arange(N + 1)
+    VI, VJ, VK = np.meshgrid(g, g, g, indexing="ij")
+    V = np.stack([e[VI.ravel()], e[VJ.ravel()], e[VK.ravel()]], axis=1)
+    if vertex_map is not None:
+        V = np.asarray(vertex_map(V), dtype=np.float64)
+
+    def vid(ijk):
+        return (ijk[..., 0] * (N + 1) + ijk[..., 1]) * (N + 1) + ijk[..., 2]
+
+    cells = {d: np.nonzero(flat == d)[0] for d in (1, 2)}
+    rank = -np.ones(N ** 3, dtype=np.int64)
+    for d in (1, 2):
+        rank[cells[d]] = np.arange(cells[d].size)
+    start = {1: 0, 2: 6 * cells[1].size}
+
+    def tet_index(c, path):
+        d = flat[c]
+        cnt = np.where(d == 1, cells[1].size, cells[2].size)
+        st = np.where(d == 1, start[1], start[2])
+        return st + KUHN_PATHS.index(path) * cnt + rank[c]
+
+    tv, tdom = [], []
+    for d in (1, 2):
+        ijk = np.stack(np.unravel_index(cells[d], (N, N, N)), axis=1)
+        for path in KUHN_PATHS:
+            cur = ijk.copy()
+            vs = [vid(cur)]
+            for ax in path:
+                cur = cur.copy()
+                cur[:, ax] += 1
+                vs.append(vid(cur))
+            tv.append(np.stack(vs, axis=1))
+            tdom.append(np.full(cells[d].size, d, dtype=np.int32))
+    T = np.concatenate(tv)
+    P = V[T]
+    cen = P.mean(axis=1)
+    vol = np.abs(np.einsum("ij,ij->i", P[:, 1] - P[:, 0], np.cross(P[:, 2] - P[:, 0], P[:, 3] - P[:, 0]))) / 6.0
+
+    tris = {1: [], 2: []}
+    for ax in range(3):
+        a, b = [q for q in range(3) if q != ax]
+        for step in (-1, 1):
+            own = np.nonzero(flat > 0)[0]
+            ijk = np.stack(np.unravel_index(own, (N, N, N)), axis=1)
+            q = ijk.copy()
+            q[:, ax] += step
+            inside = (q[:, ax] >= 0) & (q[:, ax] < N)
+            oc = np.full(own.size, -1, dtype=np.int64)
+            oc[inside] = np.ravel_multi_index(q[inside].T, (N, N, N))
+            od = np.where(oc >= 0, flat[np.maximum(oc, 0)], 0)
+            d = flat[own]
+            for iface, sel in ((1, (d == 1) & (od == 0)), (2, (d == 2) & (od == 1))):
+                if not np.any(sel):
+                    continue
+                c_in, c_out, base = own[sel], oc[sel], ijk[sel].copy()
+                if step > 0:
+                    base[:, ax] += 1
+                # the two triangles of the face: path a-then-b and b-then-a
+                for first, second in ((a, b), (b, a)):
+                    p1 = base.copy()
+                    p1[:, first] += 1
+                    p2 = p1.copy()
+                    p2[:, second] += 1
+                    tri = np.stack([vid(base), vid(p1), vid(p2)], axis=1)
+                    # owning tetrahedra: on the low side of a cell the path ends
+                    # along ax, on the high side it starts along ax
+                    path_lo, path_hi = (first, second, ax), (ax, first, second)
+                    t_in = tet_index(c_in, path_lo if step < 0 else path_hi)
+                    t_out = np.full(c_in.size, -1, dtype=np.int64)
+                    if iface == 2:
+                        t_out = tet_index(c_out, path_hi if step < 0 else path_lo)
+                    tris[iface].append((tri, t_in, t_out))
+
+    out = []
+    for iface in (1, 2):
+        if not tris[iface]:
+            out.append((np.zeros((0, 3), np.int64), np.zeros(0, np.int64), np.zeros(0, np.int64)))
+            continue
+        tri = np.concatenate([t[0] for t in tris[iface]])
+        ti = np.concatenate([t[1] for t in tris[iface]])
+        to = np.concatenate([t[2] for t in tris[iface]])
+        q = V[tri].mean(axis=1)
+        o = np.lexsort((q[:, 0], q[:, 1], q[:, 2]))
+        out.append((tri[o], ti[o], to[o]))
+    tri = np.concatenate([o[0] for o in out])
+    Q = V[tri]
+    cr = np.cross(Q[:, 1] - Q[:, 0], Q[:, 2] - Q[:, 0])
+    area = 0.5 * np.linalg.norm(cr, axis=1)
+    nrm = cr / (2.0 * area[:, None])
+    sx = Q.mean(axis=1)
+    t_in = np.concatenate([o[1] for o in out])
+    flip = np.einsum("ij,ij->i", nrm, sx - cen[t_in]) < 0
+    nrm[flip] = -nrm[flip]
+    iface = np.concatenate([np.full(out[0][0].shape[0], 1, np.int32), np.full(out[1][0].shape[0], 2, np.int32)])
+    return Mesh(h=float(np.max(np.diff(e))), vol_xyz=cen, vol_w=vol, vol_dom=np.concatenate(tdom),
+                vol_nb=-np.ones((T.shape[0], 6), dtype=np.int32), srf_xyz=sx, srf_n=nrm, srf_area=area,
+                srf_iface=iface, srf_cell_in=t_in.astype(np.int32),
+                srf_cell_out=np.concatenate([o[2] for o in out]).astype(np.int32))
+
+
+def nested_cubes_tets(n_shell: int, n_inner: int, L1: float = 7.0, L2: float = 5.0) -> Mesh:
+    """The nested-cube grid of nested_cubes, every cuboid split into 6 Kuhn
+    tetrahedra (planar interfaces: the tetrahedra are not distorted)."""
+    a, b = 0.5 * L1, 0.5 * L2
+    edges = np.concatenate([np.linspace(-a, -b, n_shell + 1), np.linspace(-b, b, n_inner + 1)[1:],
+                            np.linspace(b, a, n_shell + 1)[1:]])
+
+    def dom(i, j, k):
+        lo, hi = n_shell, n_shell + n_inner
+        inner = (i >= lo) & (i < hi) & (j >= lo) & (j < hi) & (k >= lo) & (k < hi)
+        return np.where(inner, 2, 1)
+    return kuhn_tet_mesh(edges, dom)
+
+
+def cube_to_ball(V):
+    """Radial map taking the cube surface of sup-norm s onto the sphere of
+    radius s: x -> x |x|_inf / |x|_2 (the origin stays)."""
+    V = np.asarray(V, dtype=np.float64)
+    r2 = np.linalg.norm(V, axis=1)
+    ri = np.max(np.abs(V), axis=1)
+    s = np.where(r2 > 0, ri / np.where(r2 > 0, r2, 1.0), 1.0)
+    return V * s[:, None]
+
+
+def nested_balls_tets(N: int, R1: float = 1.0, R2: float = 0.5) -> Mesh:
+    """Concentric balls with curved interfaces: the N^3 grid of [-R1, R1]^3
+    (N a multiple of 4 when R2 = R1/2, so that the cube of sup-norm R2 lies on
+    grid planes), split into Kuhn tetrahedra, vertices mapped by cube_to_ball:
+    the cube shells of sup-norm R2 and R1 become the spheres of radii R2 and
+    R1, triangulated by the mapped face triangles."""
+    e = np.linspace(-R1, R1, N + 1)
+    m = int(round(N * (1.0 - R2 / R1) / 2.0))
+    if abs(e[m] + R2) > 1e-12 * R1:
+        raise ValueError("the inner sphere must lie on a grid plane (N a multiple of 4 for R2 = R1/2)")
+
+    def dom(i, j, k):
+        inner = (i >= m) & (i < N - m) & (j >= m) & (j < N - m) & (k >= m) & (k < N - m)
+        return np.where(inner, 2, 1)
+    return kuhn_tet_mesh(e, dom, cube_to_ball)
 
 
 def nested_balls(N: int, R1: float = 1.0, R2: float = 0.5) -> Mesh:

@@ -201,7 +201,15 @@ typedef struct {
                                   complex multiply-add (Kr Qr, Ki Qi, Kr Qi, Ki Qr),
                                   1 = three (Kr Qr, Ki Qi, (Kr + Ki)(Qr + Qi); the
                                   imaginary part as the difference of FP32 sums);
-                                  default 1 */
+                                  default 1; the FP64 matrix-core products follow
+                                  the same choice */
+    int32_t mfma64_min_rhs;    /* FP64 forward products (vsie_matvec, vsie_matvec_multi,
+                                  the FP64 products and residuals of vsie_solve) with at
+                                  least this many right-hand sides evaluate each pair
+                                  kernel once in FP64 on the vector ALUs and apply it to
+                                  16, 32 or 64 columns on the FP64 matrix cores
+                                  (v_mfma_f64_16x16x4_f64, FP64 accumulation); 0 = never;
+                                  default 16 */
 } vsie_tuning;
 
 vsie_status vsie_get_tuning(const vsie_problem *p, vsie_tuning *out);
@@ -415,7 +423,8 @@ vsie_status vsie_release_dense(vsie_problem *p, int32_t f);
  * pair in FP64 and FP32 (pairs = n_srf (n_srf - 1)); kind 20 the product with
  * the assembled FP32 operator on the matrix cores (pairs = n^2 entries,
  * rhs_pairs = n^2 nrhs complex multiply-adds per pass of at most 128
- * columns). */
+ * columns); kind 21 and 22 the FP64 matrix-core forward single layer and
+ * double layers (pairs as kinds 8 and 9). */
 typedef struct {
     int64_t launches;
     double ms;

@@ -46,7 +46,7 @@ MODES = {0: "fwd_single_layer", 1: "fwd_double_layers", 2: "adj_double_layers", 
 
 def assemble(src: str) -> str:
     out = os.path.join(tempfile.mkdtemp(), src + ".s")
-    cmd = [B._hipcc(), *B.FLAGS, "--cuda-device-only", "-S",
+    cmd = [B._hipcc(), *B.flags_for(src), "--cuda-device-only", "-S",
            os.path.join(B.CSRC, src), "-o", out]
     subprocess.run(cmd, check=True, capture_output=True)
     return open(out).read()

@@ -72,7 +72,7 @@ class SolveOpts(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("mfma_min_rhs", _I32), ("mfma_tg", _I32), ("mfma_nb", _I32),
                 ("items_per_wave", _I32), ("vec_target_waves", _I64), ("graph", _I32),
-                ("sym_groups", _I32), ("cell_face", _I32), ("mfma_3m", _I32)]
+                ("sym_groups", _I32), ("cell_face", _I32), ("mfma_3m", _I32), ("mfma64_min_rhs", _I32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -150,7 +150,8 @@ KIND_NAMES = {0: "fwd_single_layer_fp64", 1: "fwd_single_layer_fp32", 2: "fwd_do
               12: "cell_face_fp64", 13: "cell_face_fp32",
               14: "far_field_single_layer_fp64", 15: "far_field_single_layer_fp32",
               16: "far_field_double_layers_fp64", 17: "far_field_double_layers_fp32",
-              18: "face_face_fp64", 19: "face_face_fp32", 20: "dense_product_fp32"}
+              18: "face_face_fp64", 19: "face_face_fp32", 20: "dense_product_fp32",
+              21: "mfma_fwd_single_layer_fp64", 22: "mfma_fwd_double_layers_fp64"}
 
 
 def vsie_last_error() -> str:

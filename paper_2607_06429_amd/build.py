@@ -34,6 +34,17 @@ FLAGS = [
 ]
 
 
+# Per-file device options.  The matrix-core pair kernels keep their MFMA
+# accumulators in VGPRs: with the compiler's default register classes the
+# loop-carried accumulators were copied between AGPRs and VGPRs on every
+# source step (192 v_accvgpr moves per step in the FP64 kernel).
+FILE_FLAGS = {"mfma_kernels.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
+def flags_for(src: str) -> list:
+    return FLAGS + FILE_FLAGS.get(src, [])
+
+
 def _hipcc() -> str:
     exe = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if not os.path.exists(exe):
@@ -43,7 +54,7 @@ def _hipcc() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc(), *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [_hipcc(), *flags_for(src), "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), res.stdout, res.stderr))

@@ -200,7 +200,7 @@ struct vsie_problem {
     HostPinned hpin;      // per-iteration Hessenberg columns and norms on their way to the host
     int progress = 0;     // vsie_solve_opts::progress of the running solve
     PairProfiler prof;
-    vsie_tuning tune{8, 2, 1, 16, 32768, 1, 4, 1, 1};
+    vsie_tuning tune{8, 2, 1, 16, 32768, 1, 4, 1, 1, 16};
     // every cell is a single-layer source and the sources are the cells in
     // canonical order (the symmetric cell-cell kernel applies)
     bool g_is_cells = false;
@@ -1097,6 +1097,97 @@ bool use_mfma(const vsie_problem *p, vsie_precision prec, int nrhs) {
     return prec == VSIE_FP32 && p->tune.mfma_min_rhs > 0 && nrhs >= p->tune.mfma_min_rhs;
 }
 
+bool use_mfma64(const vsie_problem *p, vsie_precision prec, int nrhs) {
+    return prec == VSIE_FP64 && p->tune.mfma64_min_rhs > 0 && nrhs >= p->tune.mfma64_min_rhs;
+}
+
+// FP64 forward products on the FP64 matrix cores for the nf frequencies f0 ..
+// (layout as apply_forward_mfma): 16, 32 or 64 columns per kernel evaluation
+// by the width of the block, at most kMfmaMaxCols columns per pass.
+struct Mfma64Layout {
+    int nb, ncol;
+    int64_t chG, chF;
+    int ncG, ncF;
+    int64_t fstride, ldqG, ldqF;
+    size_t part, qG, qF;
+};
+Mfma64Layout mfma64_layout(const vsie_problem *p, int nf, int nrhs) {
+    const int64_t n = p->m.n;
+    Mfma64Layout L;
+    L.nb = nrhs <= 16 ? 1 : (nrhs <= 32 ? 2 : 4);
+    const int cbw = 16 * L.nb;
+    L.ncol = (nrhs + cbw - 1) / cbw * cbw;
+    const int64_t want = static_cast<int64_t>(mfma_grid(2, 1)) * (kBlock / 64) * p->tune.items_per_wave;
+    const int64_t tiles = (n + 31) / 32;
+    const int64_t items_per_chunk = static_cast<int64_t>(nf) * (L.ncol / cbw) * tiles;
+    auto chunking = [&](int64_t ns, int64_t &chunk, int &nc) {
+        if (ns <= 0) {
+            chunk = 4;
+            nc = 0;
+            return;
+        }
+        int64_t c = (want + items_per_chunk - 1) / items_per_chunk;
+        c = std::max<int64_t>(1, std::min<int64_t>(c, std::max<int64_t>(1, ns / 512)));
+        chunk = ((ns + c - 1) / c + 3) / 4 * 4;
+        nc = static_cast<int>((ns + chunk - 1) / chunk);
+    };
+    chunking(p->G.count, L.chG, L.ncG);
+    chunking(p->F.count, L.chF, L.ncF);
+    L.fstride = static_cast<int64_t>(L.ncG + L.ncF) * nrhs * n;
+    L.part = sizeof(double2) * static_cast<size_t>(std::max<int64_t>(1, L.fstride * nf));
+    L.ldqG = (p->G.count + kMfmaPad) * L.ncol;
+    L.ldqF = (p->F.count + kMfmaPad) * L.ncol;
+    L.qG = sizeof(double2) * static_cast<size_t>(L.ldqG * nf);
+    L.qF = sizeof(double2) * static_cast<size_t>(L.ldqF * nf);
+    return L;
+}
+
+void apply_forward_mfma64_block(vsie_problem *p, int f0, int nf, int nrhs, const double2 *x, int64_t ldx,
+                                int64_t xfs, double2 *y, int64_t ldy, int64_t yfs, hipStream_t s) {
+    const int64_t n = p->m.n;
+    const Mfma64Layout L = mfma64_layout(p, nf, nrhs);
+    const int parts = L.ncG + L.ncF;
+    double2 *part = static_cast<double2 *>(p->partial.get(L.part));
+    double2 *qG = static_cast<double2 *>(p->chargeG.get(L.qG));
+    double2 *qF = static_cast<double2 *>(p->chargeF.get(L.qF));
+    const double *kf = p->d_k0 + f0;
+    const bool m3 = p->tune.mfma_3m != 0;
+    if (L.ncG > 0) {
+        launch_pack_mfma64(kClassG, p->G, p->m.sp + static_cast<int64_t>(f0) * n, n, nf, nrhs, L.ncol, x, ldx, xfs,
+                           qG, L.ldqG, s);
+        Mfma64Job J{kClassG, n, p->m.px, p->m.py, p->m.pz, p->G.count, p->G.pk, nullptr, qG, L.ldqG, L.ncol, nrhs,
+                    kf, nf, L.chG, L.ncG, part, L.fstride, 0, L.nb, m3};
+        launch_mfma64_forward(J, s, &p->prof);
+    }
+    if (L.ncF > 0) {
+        launch_pack_mfma64(kClassF, p->F, nullptr, n, nf, nrhs, L.ncol, x, ldx, xfs, qF, L.ldqF, s);
+        Mfma64Job J{kClassF, n, p->m.px, p->m.py, p->m.pz, p->F.count, p->F.pk, p->F.pv, qF, L.ldqF, L.ncol, nrhs,
+                    kf, nf, L.chF, L.ncF, part, L.fstride, L.ncG, L.nb, m3};
+        launch_mfma64_forward(J, s, &p->prof);
+    }
+    for (int t = 0; t < nf; ++t)
+        launch_reduce_partials(n, nrhs, parts, part + t * L.fstride, p->m.diag + static_cast<int64_t>(f0 + t) * n,
+                               false, x + t * xfs, ldx, y + t * yfs, ldy, nullptr, s);
+}
+
+void apply_forward_mfma64(vsie_problem *p, int f0, int nf, int nrhs, const double2 *x, int64_t ldx, int64_t xfs,
+                          double2 *y, int64_t ldy, int64_t yfs, hipStream_t s) {
+    for (int r0 = 0; r0 < nrhs; r0 += kMfmaMaxCols) {
+        const int blk = std::min(kMfmaMaxCols, nrhs - r0);
+        apply_forward_mfma64_block(p, f0, nf, blk, x + static_cast<int64_t>(r0) * ldx, ldx, xfs,
+                                   y + static_cast<int64_t>(r0) * ldy, ldy, yfs, s);
+    }
+}
+
+void plan_forward_mfma64(vsie_problem *p, int nf, int nrhs, WsPlan &pl) {
+    for (int r0 = 0; r0 < nrhs; r0 += kMfmaMaxCols) {
+        const Mfma64Layout L = mfma64_layout(p, nf, std::min(kMfmaMaxCols, nrhs - r0));
+        pl.need(p->partial, L.part);
+        pl.need(p->chargeG, L.qG);
+        pl.need(p->chargeF, L.qF);
+    }
+}
+
 void check_tuning(const vsie_tuning &t) {
     require(t.mfma_min_rhs >= 0, "mfma_min_rhs must be >= 0");
     require((t.mfma_tg == 2 || t.mfma_tg == 4) && (t.mfma_nb == 1 || t.mfma_nb == 2) &&
@@ -1109,6 +1200,7 @@ void check_tuning(const vsie_tuning &t) {
     require(t.sym_groups == 0 || (t.sym_groups > 1 && sym_groups_ok(t.sym_groups)), "sym_groups must be 0, 2, 4 or 8");
     require(t.cell_face == 0 || t.cell_face == 1, "cell_face must be 0 or 1");
     require(t.mfma_3m == 0 || t.mfma_3m == 1, "mfma_3m must be 0 or 1");
+    require(t.mfma64_min_rhs >= 0, "mfma64_min_rhs must be >= 0");
 }
 
 // The work buffers of apply_op (same dispatch).
@@ -1116,6 +1208,7 @@ void plan_op(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int nrhs
     if (prec == VSIE_FP32 && p->dense[f].A) plan_dense(p, nrhs, pl);
     else if (adjoint) plan_adjoint(p, prec, nrhs, pl);
     else if (use_mfma(p, prec, nrhs)) plan_forward_mfma(p, 1, nrhs, pl);
+    else if (use_mfma64(p, prec, nrhs)) plan_forward_mfma64(p, 1, nrhs, pl);
     else plan_forward(p, prec, nrhs, pl);
 }
 
@@ -1127,6 +1220,10 @@ void plan_multi(vsie_problem *p, int f0, int nf, vsie_precision prec, int nrhs, 
         plan_forward_mfma(p, nf, nrhs, pl);
         return;
     }
+    if (use_mfma64(p, prec, nrhs)) {
+        plan_forward_mfma64(p, nf, nrhs, pl);
+        return;
+    }
     for (int t = 0; t < nf; ++t) plan_op(p, f0 + t, prec, false, nrhs, pl);
 }
 
@@ -1135,6 +1232,7 @@ void apply_op(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int nrh
     if (prec == VSIE_FP32 && p->dense[f].A) apply_dense(p, f, adjoint, nrhs, x, ldx, y, ldy, s);
     else if (adjoint) apply_adjoint(p, f, prec, nrhs, x, ldx, y, ldy, s);
     else if (use_mfma(p, prec, nrhs)) apply_forward_mfma(p, f, 1, nrhs, x, ldx, 0, y, ldy, 0, s);
+    else if (use_mfma64(p, prec, nrhs)) apply_forward_mfma64(p, f, 1, nrhs, x, ldx, 0, y, ldy, 0, s);
     else apply_forward(p, f, prec, nrhs, x, ldx, y, ldy, s);
 }
 
@@ -2530,6 +2628,10 @@ vsie_status vsie_matvec_multi(vsie_problem *p, int32_t f0, int32_t nf, vsie_prec
             apply_forward_mfma(p, f0, nf, R, xv, ldx, nrhs * ldx, yv, ldy, nrhs * ldy, s);
             return;
         }
+        if (use_mfma64(p, prec, R)) {
+            apply_forward_mfma64(p, f0, nf, R, xv, ldx, nrhs * ldx, yv, ldy, nrhs * ldy, s);
+            return;
+        }
         for (int t = 0; t < nf; ++t)
             apply_op(p, f0 + t, prec, false, R, xv + t * nrhs * ldx, ldx, yv + t * nrhs * ldy, ldy, s);
     });
@@ -2931,7 +3033,7 @@ vsie_status vsie_profile(vsie_problem *p, int32_t enable) {
 vsie_status vsie_profile_read(vsie_problem *p, int32_t kind, vsie_kernel_stats *out) {
     return guarded([&] {
         require(p != nullptr && out != nullptr, "NULL argument");
-        require(kind >= 0 && kind < 21, "kernel kind out of range");
+        require(kind >= 0 && kind < 23, "kernel kind out of range");
         vsie_kernel_stats st{0, 0.0, 0.0, 0.0};
         for (auto &r : p->prof.recs) {
             if (r.kind != kind) continue;

@@ -173,6 +173,33 @@ struct MfmaJob {
     bool m3;  // three real matrix-core products per complex product instead of four
 };
 void launch_mfma_forward(const MfmaJob &J, hipStream_t s, PairProfiler *prof);
+// The same product in FP64 on the FP64 matrix cores: FP64 kernel values and
+// charges (double2, q[fl * ldq_f + j * ncol + col]), FP64 accumulation, two
+// 16-target groups per wave, nb in {1, 2, 4} 16-column blocks per item.
+struct Mfma64Job {
+    int cls;
+    int64_t n_t;
+    const double *tx, *ty, *tz;
+    int64_t n_s;
+    const double4 *pk, *pv;
+    const double2 *q;
+    int64_t ldq_f;
+    int ncol, nrhs;
+    const double *kf;
+    int nf;
+    int64_t chunk;
+    int n_chunks;
+    double2 *out;
+    int64_t out_fstride;
+    int part0;
+    int nb;
+    bool m3;
+};
+void launch_mfma64_forward(const Mfma64Job &J, hipStream_t s, PairProfiler *prof);
+bool mfma64_nb_ok(int nb);
+void launch_pack_mfma64(SrcClass cls, const SourceSet &src, const double *sp, int64_t sp_fstride, int nf,
+                        int nrhs, int ncol, const double2 *x, int64_t ldx, int64_t xfs, double2 *q, int64_t ldq_f,
+                        hipStream_t s);
 bool mfma_variant_ok(int tg, int nb);
 int mfma_grid(int tg, int nb);
 // Workgroups (a multiple of 8) that give each wave of an XCD-ranged item list

@@ -163,3 +163,63 @@ def test_tuning_validation(V):
         with pytest.raises(V.VsieError):
             P.set_tuning(**bad)
         assert P.tuning == before
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("R", [16, 33, 64])
+def test_mfma64_matvec_parity(V, name, R):
+    """FP64 products on the FP64 matrix cores (16, 32 or 64 columns per kernel
+    evaluation by the width of the block; 33 leaves a ragged last block), with
+    three and four real products per complex multiply-add, against the oracle
+    at the FP64 bar and against the vector kernel."""
+    mesh, mat, k0 = case(name)
+    d = O.discretise(mesh, mat, k0)
+    P = V.Problem.from_mesh(mesh, mat, [k0])
+    x = W.seeded_complex((d.n, R), seed=93)
+    ref = O.matvec(d, x)
+    P.set_tuning(mfma64_min_rhs=0)
+    yv = host(P.matvec(dev(x).contiguous(), prec=V.VSIE_FP64)).reshape(d.n, R)
+    for m3 in (0, 1):
+        P.set_tuning(mfma64_min_rhs=16, mfma_3m=m3)
+        P.profile(True)
+        y = host(P.matvec(dev(x).contiguous(), prec=V.VSIE_FP64)).reshape(d.n, R)
+        st = P.kernel_stats()
+        P.profile(False)
+        e, ev = parity_err(y, ref), parity_err(y, yv)
+        say("  %s R %d 3m %d: rel err %.2e, vs vector kernel %.2e" % (name, R, m3, e, ev))
+        assert "mfma_fwd_single_layer_fp64" in st and "fwd_single_layer_fp64" not in st
+        assert e <= TOL64 and ev <= TOL64
+    P.close()
+
+
+def test_mfma64_c2_sampled_rows_and_multi_frequency(V):
+    """The c2 residual product (n = 116,445, 128 columns) in FP64 on the
+    matrix cores against the oracle on sampled rows; and a multi-frequency
+    FP64 launch (3 wavenumbers x 16 columns) against per-frequency products."""
+    import torch
+    mesh, mat, k0s, dirs, _ = W.config_problem("c2")
+    d = O.discretise(mesh, mat, k0s[0])
+    P = V.Problem.from_mesh(mesh, mat, k0s)
+    x = W.seeded_complex((d.n, 128), seed=94)
+    rows = np.unique(np.concatenate([np.random.default_rng(95).choice(d.n, 96, replace=False),
+                                     [0, d.n_vol - 1, d.n_vol, d.n - 1]]))
+    P.profile(True)
+    y = host(P.matvec(dev(x).contiguous(), prec=V.VSIE_FP64))
+    st = P.kernel_stats()
+    P.profile(False)
+    cols = [0, 63, 127]
+    e = parity_err(y[rows][:, cols], O.matvec(d, x[:, cols], rows=rows))
+    say("  c2 FP64 128 columns on the matrix cores: sampled rows rel err %.2e, single layer %.1f ms" %
+        (e, st["mfma_fwd_single_layer_fp64"]["ms"]))
+    assert e <= TOL64
+    P.close()
+    mesh, mat, _ = case("lognormal")
+    ks = [2.0, 5.0, 7.5]
+    P = V.Problem.from_mesh(mesh, mat, ks)
+    X = dev(W.seeded_complex((mesh.n, 48), seed=96)).contiguous()
+    Y = P.matvec_multi(X, 0, 3, prec=V.VSIE_FP64)
+    for f in range(3):
+        dd = O.discretise(mesh, mat, ks[f])
+        e = parity_err(host(Y[16 * f:16 * (f + 1)].contiguous()), O.matvec(dd, host(X[16 * f:16 * (f + 1)].contiguous())))
+        assert e <= TOL64, (f, e)
+    P.close()

@@ -278,6 +278,30 @@ vsie_status vsie_solve(vsie_problem *p, int32_t f, vsie_precision prec, int32_t 
                        const vsie_solve_opts *opts, vsie_solve_info *info, void *workspace, size_t ws_bytes,
                        void *stream);
 
+/* Solve A_f x = b for the nf frequencies f = f0 .. f0 + nf - 1 of one
+ * problem together (forward operator; the scattering problem of section 3.1 at
+ * several wavenumbers).  Layout as vsie_matvec_multi: frequency f0 + t owns
+ * columns t nrhs .. (t + 1) nrhs - 1 of b and x (leading dimensions ldb,
+ * ldx >= n).  Each frequency runs its own block GMRES -- for VSIE_FP32 inside
+ * FP64 iterative refinement -- exactly as vsie_solve with opts->block = 1
+ * would, except for the restart length; the processes advance in lockstep and
+ * share the operator launches: every block step applies the operators of all
+ * frequencies still iterating as one multi-frequency launch per source class
+ * (one per run of consecutive frequencies of equal block width; widths below
+ * the matrix-core thresholds of vsie_tuning fall back to one product per
+ * frequency), and every FP64 refinement residual likewise.  A frequency whose
+ * cycle has ended waits for the others before its next refinement step.  The
+ * nf bases share the Krylov budget of one solve, so a frequency's cycle is
+ * capped at the block steps a single solve of nf nrhs columns would get.
+ * opts->block and opts->relax are ignored; opts->tol, max_iter, restart,
+ * inner_tol, max_outer and progress apply to every frequency.  info: NULL or
+ * an array of nf entries, one per frequency.  nrhs <= 4096.  workspace,
+ * ws_bytes: as for vsie_solve (VSIE_OP_SOLVE_MULTI).  Returns VSIE_E_NOCONV
+ * when any frequency missed the tolerance (its x holds the last iterate). */
+vsie_status vsie_solve_multi(vsie_problem *p, int32_t f0, int32_t nf, vsie_precision prec, int64_t nrhs,
+                             const double *b, int64_t ldb, double *x, int64_t ldx, const vsie_solve_opts *opts,
+                             vsie_solve_info *info, void *workspace, size_t ws_bytes, void *stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): y = A_f x
  * exactly as vsie_matvec computes it (same kernels, same results), with its
@@ -302,11 +326,12 @@ typedef enum {
     VSIE_OP_MATVEC_ADJOINT = 1,  /* vsie_matvec_adjoint */
     VSIE_OP_MATVEC_MULTI = 2,    /* vsie_matvec_multi over nf frequencies from f */
     VSIE_OP_SOLVE = 3,           /* vsie_solve, adjoint = 0 */
-    VSIE_OP_SOLVE_ADJOINT = 4    /* vsie_solve, adjoint = 1 */
+    VSIE_OP_SOLVE_ADJOINT = 4,   /* vsie_solve, adjoint = 1 */
+    VSIE_OP_SOLVE_MULTI = 5      /* vsie_solve_multi over nf frequencies from f */
 } vsie_op;
 
 /* Bytes of workspace the call `op` needs on problem p for frequency f (nf
- * frequencies for VSIE_OP_MATVEC_MULTI, else 1), precision prec and nrhs
+ * frequencies for VSIE_OP_MATVEC_MULTI and VSIE_OP_SOLVE_MULTI, else 1), precision prec and nrhs
  * right-hand sides, with solver options opts (solves only; NULL = defaults)
  * and the problem's current tuning, materials and assembled operators.  A
  * change of any of these may change the size.  Writes *bytes. */

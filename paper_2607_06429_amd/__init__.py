@@ -25,7 +25,7 @@ __all__ = [
     "vsie_profile_read", "vsie_destroy", "vsie_last_error",
     "vsie_size", "vsie_num_cells", "vsie_matvec_multi", "vsie_get_tuning", "vsie_set_tuning", "vsie_autotune",
     "vsie_workspace_size", "VSIE_OP_MATVEC", "VSIE_OP_MATVEC_ADJOINT", "VSIE_OP_MATVEC_MULTI", "VSIE_OP_SOLVE",
-    "VSIE_OP_SOLVE_ADJOINT", "vsie_matvec_noalloc",
+    "VSIE_OP_SOLVE_ADJOINT", "VSIE_OP_SOLVE_MULTI", "vsie_matvec_noalloc", "vsie_solve_multi",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -33,7 +33,8 @@ library_path = os.path.join(_HERE, "libvsie.so")
 
 VSIE_OK, VSIE_E_INVALID, VSIE_E_DEVICE, VSIE_E_NOMEM, VSIE_E_NOCONV, VSIE_E_NAN, VSIE_E_WORKSPACE = range(7)
 VSIE_FP64, VSIE_FP32 = 0, 1
-VSIE_OP_MATVEC, VSIE_OP_MATVEC_ADJOINT, VSIE_OP_MATVEC_MULTI, VSIE_OP_SOLVE, VSIE_OP_SOLVE_ADJOINT = range(5)
+VSIE_OP_MATVEC, VSIE_OP_MATVEC_ADJOINT, VSIE_OP_MATVEC_MULTI, VSIE_OP_SOLVE, VSIE_OP_SOLVE_ADJOINT, \
+    VSIE_OP_SOLVE_MULTI = range(6)
 _STATUS = {0: "VSIE_OK", 1: "VSIE_E_INVALID", 2: "VSIE_E_DEVICE", 3: "VSIE_E_NOMEM",
            4: "VSIE_E_NOCONV", 5: "VSIE_E_NAN", 6: "VSIE_E_WORKSPACE"}
 _SZ = ctypes.c_size_t
@@ -101,6 +102,8 @@ def _load():
     L.vsie_matvec_noalloc.argtypes = [_P, _I32, _I32, _I64, _P, _I64, _P, _I64, _P]
     L.vsie_solve.argtypes = [_P, _I32, _I32, _I32, _I64, _P, _I64, _P, _I64,
                              ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P, _SZ, _P]
+    L.vsie_solve_multi.argtypes = [_P, _I32, _I32, _I32, _I64, _P, _I64, _P, _I64,
+                                   ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P, _SZ, _P]
     L.vsie_workspace_size.argtypes = [_P, _I32, _I32, _I32, _I32, _I64, ctypes.POINTER(SolveOpts),
                                       ctypes.POINTER(_SZ)]
     L.vsie_plane_wave.argtypes = [_P, _I32, _I64, _P, _P, _I64, _P]
@@ -139,7 +142,7 @@ EXPORTED = ("vsie_assemble", "vsie_set_materials", "vsie_size", "vsie_num_cells"
             "vsie_source_sums", "vsie_plane_wave_at", "vsie_adjoint_rhs", "vsie_param_gradient",
             "vsie_assemble_dense", "vsie_release_dense", "vsie_profile", "vsie_profile_read",
             "vsie_destroy", "vsie_last_error", "vsie_matvec_multi", "vsie_get_tuning",
-            "vsie_set_tuning", "vsie_autotune", "vsie_workspace_size", "vsie_matvec_noalloc")
+            "vsie_set_tuning", "vsie_autotune", "vsie_workspace_size", "vsie_matvec_noalloc", "vsie_solve_multi")
 
 # pair-kernel kinds reported by vsie_profile_read: 2 * mode + precision
 KIND_NAMES = {0: "fwd_single_layer_fp64", 1: "fwd_single_layer_fp32", 2: "fwd_double_layers_fp64",
@@ -359,6 +362,25 @@ def vsie_solve(h, f, prec, adjoint, b, x, tol=1e-10, max_iter=3000, restart=500,
     return d
 
 
+def vsie_solve_multi(h, f0, nf, prec, b, x, tol=1e-10, max_iter=3000, restart=500, inner_tol=1e-5,
+                     max_outer=20, stream=None, allow_noconv=False, progress=False, workspace=None):
+    """Solve the nf frequencies f0 .. f0 + nf - 1 in lockstep, in place into x
+    (initial guess on entry).  b, x: (nf * R, n) -- rows t R .. t R + R - 1
+    belong to frequency f0 + t.  Returns one SolveInfo dict per frequency and
+    the status."""
+    n = vsie_size(h)
+    pb, C, ldb = _cols(b, n)
+    px, Cx, ldx = _cols(x, n)
+    if Cx != C or C % nf:
+        raise ValueError("b and x must hold nf blocks of equally many columns")
+    o = _opts(tol, max_iter, restart, inner_tol, max_outer, True, 0.0, progress)
+    infos = (SolveInfo * nf)()
+    st = _check(lib.vsie_solve_multi(h, f0, nf, prec, C // nf, pb, ldb, px, ldx, ctypes.byref(o), infos,
+                                     *_ws(workspace), _stream(stream)),
+                allow=(VSIE_E_NOCONV,) if allow_noconv else ())
+    return [i.as_dict() for i in infos], st
+
+
 def vsie_plane_wave(h, f, dirs, b, stream=None):
     n = vsie_size(h)
     pb, R, ldb = _cols(b, n)
@@ -562,6 +584,18 @@ class Problem:
         x = torch.zeros_like(b) if x0 is None else x0.clone()
         info = vsie_solve(self.handle, f, prec, adjoint, b, x, **kw)
         return x, info
+
+    def solve_multi(self, b, f0=0, nf=None, prec=VSIE_FP32, x0=None, **kw):
+        """Lockstep block GMRES over the frequencies f0 .. f0 + nf - 1 (all the
+        problem's frequencies from f0 by default); b: (nf * R, n).  Returns x
+        and a list of per-frequency info dicts (each with the overall status)."""
+        import torch
+        nf = len(self.k0) - f0 if nf is None else nf
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        infos, st = vsie_solve_multi(self.handle, f0, nf, prec, b, x, **kw)
+        for d in infos:
+            d["status"] = st
+        return x, infos
 
     def plane_wave(self, dirs, f=0):
         import torch

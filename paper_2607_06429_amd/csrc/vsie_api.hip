@@ -5,6 +5,7 @@
 #include <atomic>
 #include <cmath>
 #include <complex>
+#include <functional>
 #include <cstdio>
 #include <cstring>
 #include <initializer_list>
@@ -2091,147 +2092,209 @@ inline void apply_reflector(const cd *u, double uu, int len, cd *y) {
 }
 
 // One block GMRES cycle for the right-hand sides rhs[0..Ra) with residual
-// block Rres (n x Ra, column norms rn) and per-column tolerances; adds the
-// corrections to x.  Returns the number of block steps.
-int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const std::vector<int32_t> &rhs,
-                double2 *Rres, const std::vector<double> &rn, const std::vector<double> &ctol, int m,
-                int iter_cap, double2 *x, int64_t ldx, SolveCounters &cnt, hipStream_t s, double2 *V,
-                BlockRecycle *save, const BlockRecycle *use) {
-    const int64_t n = p->m.n;
-    const int Ra = static_cast<int>(rhs.size());
-    const int64_t ldH = static_cast<int64_t>(m + 1) * Ra;  // rows of the block Hessenberg / G
-    double2 *W = static_cast<double2 *>(p->w.get(sizeof(double2) * static_cast<size_t>(n) * Ra));
-    double2 *Z = static_cast<double2 *>(p->ax.get(sizeof(double2) * static_cast<size_t>(n) * Ra));
-    double2 *Hd = static_cast<double2 *>(p->bh.get(sizeof(double2) * static_cast<size_t>(ldH) * Ra));
-    if (!p->blas) check_blas(rocblas_create_handle(&p->blas), "rocblas_create_handle");
-    check_blas(rocblas_set_stream(p->blas, s), "rocblas_set_stream");
-    int32_t *act = static_cast<int32_t *>(p->act.get(sizeof(int32_t) * Ra));
-    to_device(act, rhs, s);
+// block Rres (n x Ra, column norms rn) and per-column tolerances, driven one
+// block step at a time so that the cycles of several frequencies can share
+// one operator launch per step: begin(); then, while wants_product(), the
+// caller writes op(A) input() to output() and calls after_product(); finally
+// finish() adds the corrections to x and returns the number of block steps.
+// V holds the basis (n x Ra (m + 1)); W (n x Ra) receives each product and is
+// overwritten by the step.  The shared work buffers (Z, the block Hessenberg
+// column, the Gram matrix, the slab partials, the deflation coefficients and
+// the column index array) are taken from the problem at each use, so cycles
+// of several frequencies advanced one after another on one stream can share
+// them.
+class BlockCycle {
+  public:
+    BlockCycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, std::vector<int32_t> rhs, double2 *Rres,
+               std::vector<double> rn, std::vector<double> ctol, int m, int iter_cap, double2 *x, int64_t ldx,
+               SolveCounters &cnt, hipStream_t s, double2 *V, double2 *W, BlockRecycle *save,
+               const BlockRecycle *use, bool report)
+        : p_(p), f_(f), prec_(prec), adjoint_(adjoint), rhs_(std::move(rhs)), Rres_(Rres), rn_(std::move(rn)),
+          ctol_(std::move(ctol)), m_(m), iter_cap_(iter_cap), x_(x), ldx_(ldx), cnt_(cnt), s_(s), V_(V), W_(W),
+          save_(save), use_(use), report_(report), n_(p->m.n), Ra_(static_cast<int>(rhs_.size())),
+          ldH_(static_cast<int64_t>(m + 1) * Ra_), kr_(use ? use->k : 0), kv_(use ? use->k + use->Ra : 0) {}
 
+    void begin();
+    bool wants_product() const {
+        if (done_ || j_ >= m_) return false;
+        for (int r : rhs_)
+            if (cnt_.it[r] >= iter_cap_) return false;
+        return true;
+    }
+    const double2 *input() const { return V_ + static_cast<int64_t>(j_) * Ra_ * n_; }
+    double2 *output() const { return W_; }
+    int width() const { return Ra_; }
+    int freq() const { return f_; }
+    void after_product();
+    int finish();
+    void add_operator_seconds(double t) { sec_[0] += t; }
+    // largest residual estimate after the last step, relative to the cycle start
+    double worst() const { return worst_; }
+
+  private:
+    using clk = std::chrono::steady_clock;
+    double2 *Dd() const { return static_cast<double2 *>(p_->brc.get(sizeof(double2) * static_cast<size_t>(kv_) * Ra_)); }
+    int32_t *act() const {
+        int32_t *a = static_cast<int32_t *>(p_->act.get(sizeof(int32_t) * Ra_));
+        to_device(a, rhs_, s_);
+        return a;
+    }
+    // progress mode: wall time of the sections of each block step (the stream
+    // is synchronised at each mark, so these runs are diagnostic)
+    void mark(clk::time_point &t, int which) {
+        if (!p_->progress) return;
+        VSIE_HIP(hipStreamSynchronize(s_));
+        const clk::time_point now = clk::now();
+        sec_[which] += std::chrono::duration<double>(now - t).count();
+        t = now;
+    }
+
+    vsie_problem *p_;
+    int f_;
+    vsie_precision prec_;
+    bool adjoint_;
+    std::vector<int32_t> rhs_;
+    double2 *Rres_;
+    std::vector<double> rn_, ctol_;
+    int m_, iter_cap_;
+    double2 *x_;
+    int64_t ldx_;
+    SolveCounters &cnt_;
+    hipStream_t s_;
+    double2 *V_, *W_;
+    BlockRecycle *save_;
+    const BlockRecycle *use_;
+    bool report_;
+    int64_t n_;
+    int Ra_;
+    int64_t ldH_, kr_, kv_;
+    // transformed right-hand sides (column-major, ldH_ rows), the R factor of
+    // the block Hessenberg packed by columns and grown one block column per
+    // step (the full (m Ra)^2 array would be several GB to zero), and one
+    // Householder reflector per column (Ra + 1 long, at c (Ra + 1))
+    std::vector<cd> G_, Rf_, U_, Bm_;
+    std::vector<double> UU_;
+    int j_ = 0, jdone_ = 0;
+    bool done_ = false;
+    double worst_ = 0.0;
+    double sec_[4] = {0, 0, 0, 0};  // operator, Gram-Schmidt, CholeskyQR, host QR
+};
+
+void BlockCycle::begin() {
+    if (!p_->blas) check_blas(rocblas_create_handle(&p_->blas), "rocblas_create_handle");
+    check_blas(rocblas_set_stream(p_->blas, s_), "rocblas_set_stream");
     // deflation by an earlier cycle's space: x += U C^H r, r -= C C^H r, and
     // Bm = C^H A v for every new basis column (column-major, kr rows)
-    const int64_t kr = use ? use->k : 0, kv = use ? use->k + use->Ra : 0;
-    double2 *Dd = kr > 0 ? static_cast<double2 *>(p->brc.get(sizeof(double2) * static_cast<size_t>(kv) * Ra)) : nullptr;
-    std::vector<cd> Bm;
-    if (kr > 0) {
-        std::vector<cd> z = use->deflate_coeffs(p, n, Ra, Rres, Dd, s);
-        zgemm(p, false, n, Ra, kv, -1.0, use->V, n, Dd, kv, 1.0, Rres, n);
-        tri_solve_upper_cols(use->R.data(), kr, kr, Ra, z.data());
-        std::vector<double2> yh(static_cast<size_t>(kr) * Ra);
+    if (kr_ > 0) {
+        std::vector<cd> z = use_->deflate_coeffs(p_, n_, Ra_, Rres_, Dd(), s_);
+        zgemm(p_, false, n_, Ra_, kv_, -1.0, use_->V, n_, Dd(), kv_, 1.0, Rres_, n_);
+        tri_solve_upper_cols(use_->R.data(), kr_, kr_, Ra_, z.data());
+        std::vector<double2> yh(static_cast<size_t>(kr_) * Ra_);
         for (size_t q = 0; q < yh.size(); ++q) yh[q] = make_double2(z[q].real(), z[q].imag());
-        to_device(Dd, yh, s);
-        zgemm(p, false, n, Ra, kr, 1.0, use->V, n, Dd, kr, 0.0, W, n);
-        blas_scatter_add(n, Ra, act, W, x, ldx, s);
+        to_device(Dd(), yh, s_);
+        zgemm(p_, false, n_, Ra_, kr_, 1.0, use_->V, n_, Dd(), kr_, 0.0, W_, n_);
+        blas_scatter_add(n_, Ra_, act(), W_, x_, ldx_, s_);
     }
-
     std::vector<cd> S0;
-    cholqr2(p, n, Ra, Rres, Z, V, S0, s);
-    // transformed right-hand sides and the R factor of the block Hessenberg (column-major)
-    std::vector<cd> G(static_cast<size_t>(ldH) * Ra, 0.0);
-    for (int c = 0; c < Ra; ++c)
-        for (int i = 0; i <= c; ++i) G[static_cast<size_t>(c) * ldH + i] = S0[static_cast<size_t>(c) * Ra + i];
-    // R factor of the block Hessenberg, packed by columns and grown one block
-    // column per step (the full (m Ra)^2 array would be several GB to zero)
-    std::vector<cd> Rf;
-    std::vector<cd> U(static_cast<size_t>(m) * Ra * (Ra + 1), 0.0);  // reflector of column c at c (Ra + 1)
-    std::vector<double> UU(static_cast<size_t>(m) * Ra, 0.0);
+    double2 *Z = static_cast<double2 *>(p_->ax.get(sizeof(double2) * static_cast<size_t>(n_) * Ra_));
+    cholqr2(p_, n_, Ra_, Rres_, Z, V_, S0, s_);
+    G_.assign(static_cast<size_t>(ldH_) * Ra_, 0.0);
+    for (int c = 0; c < Ra_; ++c)
+        for (int i = 0; i <= c; ++i) G_[static_cast<size_t>(c) * ldH_ + i] = S0[static_cast<size_t>(c) * Ra_ + i];
+    U_.assign(static_cast<size_t>(m_) * Ra_ * (Ra_ + 1), 0.0);
+    UU_.assign(static_cast<size_t>(m_) * Ra_, 0.0);
+}
+
+void BlockCycle::after_product() {
+    const int j = j_;
+    const int Ra = Ra_;
+    const int64_t n = n_, kr = kr_, kv = kv_;
+    clk::time_point tm = clk::now();
+    for (int r : rhs_) (prec_ == VSIE_FP64 ? cnt_.mv64 : cnt_.mv32)[r]++;
+    const int64_t kb = static_cast<int64_t>(j + 1) * Ra;
+    double2 *W = W_;
+    std::vector<cd> Hc(static_cast<size_t>(kb + Ra) * Ra, 0.0);  // new block column, rows 0..kb+Ra
     std::vector<double2> hh;
-    int jdone = 0;
-    // progress mode: wall time of the sections of each block step (the
-    // stream is synchronised at each mark, so these runs are diagnostic)
-    using clk = std::chrono::steady_clock;
-    double sec[4] = {0, 0, 0, 0};  // operator, Gram-Schmidt, CholeskyQR, host QR
-    auto mark = [&](clk::time_point &t, int which) {
-        if (!p->progress) return;
-        VSIE_HIP(hipStreamSynchronize(s));
-        const clk::time_point now = clk::now();
-        sec[which] += std::chrono::duration<double>(now - t).count();
-        t = now;
-    };
-    for (int j = 0; j < m; ++j) {
-        bool capped = false;
-        for (int r : rhs) capped = capped || cnt.it[r] >= iter_cap;
-        if (capped) break;
-        clk::time_point tm = clk::now();
-        if (p->progress) VSIE_HIP(hipStreamSynchronize(s));
-        apply_op(p, f, prec, adjoint, Ra, V + static_cast<int64_t>(j) * Ra * n, n, W, n, s);
-        mark(tm, 0);
-        for (int r : rhs) (prec == VSIE_FP64 ? cnt.mv64 : cnt.mv32)[r]++;
-        const int64_t kb = static_cast<int64_t>(j + 1) * Ra;
-        std::vector<cd> Hc(static_cast<size_t>(kb + Ra) * Ra, 0.0);  // new block column, rows 0..kb+Ra
-        for (int pass = 0; pass < 2; ++pass) {
-            if (kr > 0) {
-                const std::vector<cd> z = use->deflate_coeffs(p, n, Ra, W, Dd, s);
-                Bm.resize(static_cast<size_t>(j + 1) * Ra * kr, 0.0);
-                for (int c = 0; c < Ra; ++c)
-                    for (int64_t i = 0; i < kr; ++i)
-                        Bm[(static_cast<size_t>(j) * Ra + c) * kr + i] += z[static_cast<size_t>(c) * kr + i];
-                zgemm(p, false, n, Ra, kv, -1.0, use->V, n, Dd, kv, 1.0, W, n);
-            }
-            zgemm_tall_cn(p, kb, Ra, n, V, n, W, n, Hd, kb, s);
-            zgemm(p, false, n, Ra, kb, -1.0, V, n, Hd, kb, 1.0, W, n);
-            to_host(hh, Hd, static_cast<size_t>(kb) * Ra, s);
+    for (int pass = 0; pass < 2; ++pass) {
+        if (kr > 0) {
+            const std::vector<cd> z = use_->deflate_coeffs(p_, n, Ra, W, Dd(), s_);
+            Bm_.resize(static_cast<size_t>(j + 1) * Ra * kr, 0.0);
             for (int c = 0; c < Ra; ++c)
-                for (int64_t i = 0; i < kb; ++i)
-                    Hc[static_cast<size_t>(c) * (kb + Ra) + i] += cd(hh[c * kb + i].x, hh[c * kb + i].y);
+                for (int64_t i = 0; i < kr; ++i)
+                    Bm_[(static_cast<size_t>(j) * Ra + c) * kr + i] += z[static_cast<size_t>(c) * kr + i];
+            zgemm(p_, false, n, Ra, kv, -1.0, use_->V, n, Dd(), kv, 1.0, W, n);
         }
-        mark(tm, 1);
-        std::vector<cd> T;
-        cholqr2(p, n, Ra, W, Z, V + kb * n, T, s);
-        mark(tm, 2);
+        double2 *Hd = static_cast<double2 *>(p_->bh.get(sizeof(double2) * static_cast<size_t>(ldH_) * Ra));
+        zgemm_tall_cn(p_, kb, Ra, n, V_, n, W, n, Hd, kb, s_);
+        zgemm(p_, false, n, Ra, kb, -1.0, V_, n, Hd, kb, 1.0, W, n);
+        to_host(hh, Hd, static_cast<size_t>(kb) * Ra, s_);
         for (int c = 0; c < Ra; ++c)
-            for (int i = 0; i <= c; ++i) Hc[static_cast<size_t>(c) * (kb + Ra) + kb + i] = T[static_cast<size_t>(c) * Ra + i];
-        // previous reflectors on the new columns (independent per column)
-        const int64_t c0 = static_cast<int64_t>(j) * Ra;
-        parallel_for(Ra, 8.0 * Ra * c0 * (Ra + 1), [&](int c) {
-            cd *h = &Hc[static_cast<size_t>(c) * (kb + Ra)];
-            for (int64_t k = 0; k < c0; ++k) apply_reflector(&U[static_cast<size_t>(k) * (Ra + 1)], UU[k], Ra + 1, h + k);
-        });
-        // this block's reflectors, column by column
-        Rf.resize(packed_col(c0 + Ra));
-        for (int cl = 0; cl < Ra; ++cl) {
-            const int64_t c = c0 + cl;
-            cd *h = &Hc[static_cast<size_t>(cl) * (kb + Ra)];
-            for (int64_t k = c0; k < c; ++k) apply_reflector(&U[static_cast<size_t>(k) * (Ra + 1)], UU[k], Ra + 1, h + k);
-            cd *u = &U[static_cast<size_t>(c) * (Ra + 1)];
-            for (int t = 0; t <= Ra; ++t) u[t] = h[c + t];
-            cd alpha;
-            UU[c] = make_reflector(u, Ra + 1, alpha);
-            cd *rc_ = &Rf[packed_col(c)];
-            for (int64_t i = 0; i < c; ++i) rc_[i] = h[i];
-            rc_[c] = UU[c] == 0.0 ? h[c] : alpha;
-            for (int rc = 0; rc < Ra; ++rc) apply_reflector(u, UU[c], Ra + 1, &G[static_cast<size_t>(rc) * ldH + c]);
-        }
-        mark(tm, 3);
-        for (int r : rhs) cnt.it[r]++;
-        jdone = j + 1;
-        bool all = true;
-        double worst = 0.0;
-        for (int rc = 0; rc < Ra; ++rc) {
-            double res = 0.0;
-            for (int t = 0; t < Ra; ++t) res += std::norm(G[static_cast<size_t>(rc) * ldH + kb + t]);
-            if (!std::isfinite(res)) fail(VSIE_E_NAN, "non-finite block residual");
-            all = all && std::sqrt(res) <= ctol[rc] * rn[rc];
-            worst = std::max(worst, std::sqrt(res) / rn[rc]);
-        }
-        if (p->progress) {
-            std::fprintf(stderr,
-                         "[vsie] block step %d (%d columns): max residual estimate %.3e of the cycle start "
-                         "(seconds so far: operator %.3f, Gram-Schmidt %.3f, CholeskyQR %.3f, host QR %.3f)\n",
-                         j + 1, Ra, worst, sec[0], sec[1], sec[2], sec[3]);
-            std::fflush(stderr);
-        }
-        if (all) break;
+            for (int64_t i = 0; i < kb; ++i)
+                Hc[static_cast<size_t>(c) * (kb + Ra) + i] += cd(hh[c * kb + i].x, hh[c * kb + i].y);
     }
-    if (jdone == 0) return 0;
+    mark(tm, 1);
+    std::vector<cd> T;
+    double2 *Z = static_cast<double2 *>(p_->ax.get(sizeof(double2) * static_cast<size_t>(n) * Ra));
+    cholqr2(p_, n, Ra, W, Z, V_ + kb * n, T, s_);
+    mark(tm, 2);
+    for (int c = 0; c < Ra; ++c)
+        for (int i = 0; i <= c; ++i) Hc[static_cast<size_t>(c) * (kb + Ra) + kb + i] = T[static_cast<size_t>(c) * Ra + i];
+    // previous reflectors on the new columns (independent per column)
+    const int64_t c0 = static_cast<int64_t>(j) * Ra;
+    parallel_for(Ra, 8.0 * Ra * c0 * (Ra + 1), [&](int c) {
+        cd *h = &Hc[static_cast<size_t>(c) * (kb + Ra)];
+        for (int64_t k = 0; k < c0; ++k) apply_reflector(&U_[static_cast<size_t>(k) * (Ra + 1)], UU_[k], Ra + 1, h + k);
+    });
+    // this block's reflectors, column by column
+    Rf_.resize(packed_col(c0 + Ra));
+    for (int cl = 0; cl < Ra; ++cl) {
+        const int64_t c = c0 + cl;
+        cd *h = &Hc[static_cast<size_t>(cl) * (kb + Ra)];
+        for (int64_t k = c0; k < c; ++k) apply_reflector(&U_[static_cast<size_t>(k) * (Ra + 1)], UU_[k], Ra + 1, h + k);
+        cd *u = &U_[static_cast<size_t>(c) * (Ra + 1)];
+        for (int t = 0; t <= Ra; ++t) u[t] = h[c + t];
+        cd alpha;
+        UU_[c] = make_reflector(u, Ra + 1, alpha);
+        cd *rc_ = &Rf_[packed_col(c)];
+        for (int64_t i = 0; i < c; ++i) rc_[i] = h[i];
+        rc_[c] = UU_[c] == 0.0 ? h[c] : alpha;
+        for (int rc = 0; rc < Ra; ++rc) apply_reflector(u, UU_[c], Ra + 1, &G_[static_cast<size_t>(rc) * ldH_ + c]);
+    }
+    mark(tm, 3);
+    for (int r : rhs_) cnt_.it[r]++;
+    jdone_ = j + 1;
+    j_ = j + 1;
+    bool all = true;
+    worst_ = 0.0;
+    for (int rc = 0; rc < Ra; ++rc) {
+        double res = 0.0;
+        for (int t = 0; t < Ra; ++t) res += std::norm(G_[static_cast<size_t>(rc) * ldH_ + kb + t]);
+        if (!std::isfinite(res)) fail(VSIE_E_NAN, "non-finite block residual");
+        all = all && std::sqrt(res) <= ctol_[rc] * rn_[rc];
+        worst_ = std::max(worst_, std::sqrt(res) / rn_[rc]);
+    }
+    if (p_->progress && report_) {
+        std::fprintf(stderr,
+                     "[vsie] block step %d (%d columns): max residual estimate %.3e of the cycle start "
+                     "(seconds so far: operator %.3f, Gram-Schmidt %.3f, CholeskyQR %.3f, host QR %.3f)\n",
+                     j + 1, Ra, worst_, sec_[0], sec_[1], sec_[2], sec_[3]);
+        std::fflush(stderr);
+    }
+    done_ = all;
+}
+
+int BlockCycle::finish() {
+    if (jdone_ == 0) return 0;
+    const int Ra = Ra_;
+    const int64_t n = n_, kr = kr_;
     // Y = R^{-1} G(0 : jdone Ra, :); with deflation also Wc = R_use^{-1} (Bm Y),
     // the coefficients of U (Bm Y) in the recycled basis
-    const int64_t kk = static_cast<int64_t>(jdone) * Ra;
+    const int64_t kk = static_cast<int64_t>(jdone_) * Ra;
     std::vector<cd> Ycol(static_cast<size_t>(kk) * Ra);
     for (int rc = 0; rc < Ra; ++rc)
-        std::copy(G.begin() + static_cast<size_t>(rc) * ldH, G.begin() + static_cast<size_t>(rc) * ldH + kk,
+        std::copy(G_.begin() + static_cast<size_t>(rc) * ldH_, G_.begin() + static_cast<size_t>(rc) * ldH_ + kk,
                   Ycol.begin() + static_cast<size_t>(rc) * kk);
-    tri_solve_upper_cols_by([&](int64_t i) { return Rf.data() + packed_col(i); }, kk, Ra, Ycol.data());
+    tri_solve_upper_cols_by([&](int64_t i) { return Rf_.data() + packed_col(i); }, kk, Ra, Ycol.data());
     std::vector<double2> Yh(static_cast<size_t>(kk) * Ra), Wc(static_cast<size_t>(kr) * Ra);
     for (size_t q = 0; q < Yh.size(); ++q) Yh[q] = make_double2(Ycol[q].real(), Ycol[q].imag());
     if (kr > 0) {
@@ -2240,33 +2303,327 @@ int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const
             cd *o = &by[static_cast<size_t>(rc) * kr];
             for (int64_t t = 0; t < kk; ++t) {
                 const cd yt = Ycol[static_cast<size_t>(rc) * kk + t];
-                const cd *bm = &Bm[static_cast<size_t>(t) * kr];
+                const cd *bm = &Bm_[static_cast<size_t>(t) * kr];
                 for (int64_t i = 0; i < kr; ++i) o[i] += bm[i] * yt;
             }
         });
-        tri_solve_upper_cols(use->R.data(), kr, kr, Ra, by.data());
+        tri_solve_upper_cols(use_->R.data(), kr, kr, Ra, by.data());
         for (size_t q = 0; q < Wc.size(); ++q) Wc[q] = make_double2(by[q].real(), by[q].imag());
     }
-    double2 *Yd = static_cast<double2 *>(p->bh.get(sizeof(double2) * static_cast<size_t>(std::max(kk, ldH)) * Ra));
-    to_device(Yd, Yh, s);
-    zgemm(p, false, n, Ra, kk, 1.0, V, n, Yd, kk, 0.0, W, n);
+    double2 *Yd = static_cast<double2 *>(p_->bh.get(sizeof(double2) * static_cast<size_t>(std::max(kk, ldH_)) * Ra));
+    to_device(Yd, Yh, s_);
+    zgemm(p_, false, n, Ra, kk, 1.0, V_, n, Yd, kk, 0.0, W_, n);
     if (kr > 0) {  // x += V y - U (Bm y)
-        to_device(Dd, Wc, s);
-        zgemm(p, false, n, Ra, kr, -1.0, use->V, n, Dd, kr, 1.0, W, n);
+        double2 *D = Dd();
+        to_device(D, Wc, s_);
+        zgemm(p_, false, n, Ra, kr, -1.0, use_->V, n, D, kr, 1.0, W_, n);
     }
-    blas_scatter_add(n, Ra, act, W, x, ldx, s);
-    VSIE_HIP(hipStreamSynchronize(s));
-    if (save && kk <= kBlockRecycleMax) {
-        save->V = V;
-        save->Ra = Ra;
-        save->k = kk;
-        save->U.assign(U.begin(), U.begin() + static_cast<size_t>(kk) * (Ra + 1));
-        save->UU.assign(UU.begin(), UU.begin() + kk);
-        save->R.assign(static_cast<size_t>(kk) * kk, 0.0);
+    blas_scatter_add(n, Ra, act(), W_, x_, ldx_, s_);
+    VSIE_HIP(hipStreamSynchronize(s_));
+    if (save_ && kk <= kBlockRecycleMax) {
+        save_->V = V_;
+        save_->Ra = Ra;
+        save_->k = kk;
+        save_->U.assign(U_.begin(), U_.begin() + static_cast<size_t>(kk) * (Ra + 1));
+        save_->UU.assign(UU_.begin(), UU_.begin() + kk);
+        save_->R.assign(static_cast<size_t>(kk) * kk, 0.0);
         for (int64_t c = 0; c < kk; ++c)
-            for (int64_t i = 0; i <= c; ++i) save->R[static_cast<size_t>(c) * kk + i] = Rf[packed_col(c) + i];
+            for (int64_t i = 0; i <= c; ++i) save_->R[static_cast<size_t>(c) * kk + i] = Rf_[packed_col(c) + i];
     }
-    return jdone;
+    return jdone_;
+}
+
+// One block GMRES cycle of one frequency (the product of each step is one
+// operator application of width Ra into the problem's W buffer).
+int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const std::vector<int32_t> &rhs,
+                double2 *Rres, const std::vector<double> &rn, const std::vector<double> &ctol, int m,
+                int iter_cap, double2 *x, int64_t ldx, SolveCounters &cnt, hipStream_t s, double2 *V,
+                BlockRecycle *save, const BlockRecycle *use) {
+    const int64_t n = p->m.n;
+    const int Ra = static_cast<int>(rhs.size());
+    double2 *W = static_cast<double2 *>(p->w.get(sizeof(double2) * static_cast<size_t>(n) * Ra));
+    BlockCycle c(p, f, prec, adjoint, rhs, Rres, rn, ctol, m, iter_cap, x, ldx, cnt, s, V, W, save, use, true);
+    c.begin();
+    while (c.wants_product()) {
+        const auto t0 = std::chrono::steady_clock::now();
+        if (p->progress) VSIE_HIP(hipStreamSynchronize(s));
+        apply_op(p, f, prec, adjoint, Ra, c.input(), n, c.output(), n, s);
+        if (p->progress) {
+            VSIE_HIP(hipStreamSynchronize(s));
+            c.add_operator_seconds(std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+        }
+        c.after_product();
+    }
+    return c.finish();
+}
+
+// ---------------------------------------------------------------------------
+// Several frequencies solved in lockstep.  Each frequency runs its own block
+// GMRES (with FP64 refinement for VSIE_FP32) exactly as a one-frequency block
+// solve would; the processes share only the operator launches: every block
+// step and every refinement residual applies the operators of all
+// frequencies still iterating together.
+
+// One forward operator application y = A_f x of width R (x, y: n x R,
+// leading dimension n).
+struct ProdItem {
+    int f;
+    int R;
+    const double2 *x;
+    double2 *y;
+};
+
+// The products of items (ascending f).  Each maximal run of consecutive
+// frequencies with one width whose inputs and outputs lie at constant
+// strides (outputs disjoint) is one multi-frequency launch per source class
+// when a matrix-core path takes that width; anything else is one application
+// per item.  Returns the number of applications issued.
+int apply_items(vsie_problem *p, vsie_precision prec, const std::vector<ProdItem> &items, hipStream_t s) {
+    const int64_t n = p->m.n;
+    auto batchable = [&](const ProdItem &it) {
+        if (prec == VSIE_FP32) return use_mfma(p, prec, it.R) && !p->dense[it.f].A;
+        return use_mfma64(p, prec, it.R);
+    };
+    int launches = 0;
+    size_t i = 0;
+    while (i < items.size()) {
+        const ProdItem &a = items[i];
+        size_t j = i + 1;
+        if (batchable(a)) {
+            const int64_t xs = j < items.size() ? items[j].x - a.x : 0;
+            const int64_t ys = j < items.size() ? items[j].y - a.y : 0;
+            const int64_t blk = n * a.R;
+            while (j < items.size()) {
+                const ProdItem &b = items[j];
+                const int64_t d = static_cast<int64_t>(j - i);
+                if (b.f != a.f + d || b.R != a.R || !batchable(b) || xs <= 0 || ys < blk || b.x - a.x != d * xs ||
+                    b.y - a.y != d * ys)
+                    break;
+                ++j;
+            }
+            const int nf = static_cast<int>(j - i);
+            if (prec == VSIE_FP32) apply_forward_mfma(p, a.f, nf, a.R, a.x, n, xs, a.y, n, ys, s);
+            else apply_forward_mfma64(p, a.f, nf, a.R, a.x, n, xs, a.y, n, ys, s);
+        } else {
+            apply_op(p, a.f, prec, false, a.R, a.x, n, a.y, n, s);
+        }
+        ++launches;
+        i = j;
+    }
+    return launches;
+}
+
+// Block steps per cycle when nf frequencies iterate together: their nf bases
+// share the Krylov budget of one solve (and the host R factor stays as in
+// block_restart).
+int multi_restart(int64_t n, int Ra, int restart, int nf) { return block_restart(n * nf, Ra, restart); }
+
+// Columns of one frequency's basis region: enough for any block width up to R.
+int64_t multi_basis_cols(int64_t n, int R, int restart, int nf) {
+    int64_t vcols = 0;
+    for (int Ra = 1; Ra <= R; ++Ra)
+        vcols = std::max<int64_t>(vcols, static_cast<int64_t>(Ra) * (multi_restart(n, Ra, restart, nf) + 1));
+    return vcols;
+}
+
+// Solve A_{f0+t} x_t = b_t for t < nf, R columns each (column t R + r of b
+// and x).  Per frequency: counters, relative residuals and status.
+void solve_multi_batch(vsie_problem *p, int f0, int nf, vsie_precision prec, int R, const double2 *b, int64_t ldb,
+                       double2 *x, int64_t ldx, const vsie_solve_opts &o, std::vector<SolveCounters> &cnt,
+                       std::vector<std::vector<double>> &relres, std::vector<vsie_status> &status, hipStream_t s) {
+    const int64_t n = p->m.n;
+    const size_t z = sizeof(double2);
+    const int64_t blk = n * R;  // one frequency's n x R block
+    const int64_t region = multi_basis_cols(n, R, o.restart, nf) * n;
+    double2 *Vb = static_cast<double2 *>(p->V.get(z * static_cast<size_t>(region) * nf));
+    double2 *V2b = static_cast<double2 *>(p->V2.get(z * static_cast<size_t>(region) * nf));
+    double2 *Wb = static_cast<double2 *>(p->w.get(z * static_cast<size_t>(blk) * nf));
+    double2 *Xa = static_cast<double2 *>(p->xa.get(z * static_cast<size_t>(blk) * nf));
+    double2 *AX = static_cast<double2 *>(p->axa.get(z * static_cast<size_t>(blk) * nf));
+    double2 *Rres = static_cast<double2 *>(p->rres.get(z * static_cast<size_t>(blk) * nf));
+    double2 *tmp = static_cast<double2 *>(p->r.get(z * static_cast<size_t>(blk)));
+    int32_t *act = static_cast<int32_t *>(p->act2.get(sizeof(int32_t) * R));
+    auto bcol = [&](int t) { return b + static_cast<int64_t>(t) * R * ldb; };
+    auto xcol = [&](int t) { return x + static_cast<int64_t>(t) * R * ldx; };
+
+    struct Freq {
+        std::vector<double> bn;
+        std::vector<char> xzero;
+        std::vector<int32_t> active;
+        BlockRecycle first;  // first cycle's space, deflates the later cycles
+        bool have_first = false;
+    };
+    std::vector<Freq> F(nf);
+    std::vector<int32_t> all(R);
+    for (int r = 0; r < R; ++r) all[r] = r;
+    to_device(act, all, s);
+    for (int t = 0; t < nf; ++t) {
+        Freq &q = F[t];
+        relres[t].assign(R, 0.0);
+        status[t] = VSIE_OK;
+        bblas_gather(n, R, act, bcol(t), ldb, tmp, s);
+        q.bn = column_norms(p, tmp, R, s);
+        bblas_gather(n, R, act, xcol(t), ldx, tmp, s);
+        const std::vector<double> xn = column_norms(p, tmp, R, s);
+        q.xzero.assign(R, 0);
+        for (int r = 0; r < R; ++r) {
+            if (!std::isfinite(q.bn[r])) fail(VSIE_E_NAN, "right-hand side is not finite");
+            if (!std::isfinite(xn[r])) fail(VSIE_E_NAN, "initial guess is not finite");
+            q.xzero[r] = xn[r] == 0.0;
+            if (q.bn[r] == 0.0) blas_zero(n, xcol(t) + static_cast<int64_t>(r) * ldx, s);
+            else q.active.push_back(r);
+        }
+    }
+    for (;;) {
+        // FP64 residuals r = b - A x of every frequency's active columns
+        // (frequency t's block at offset t n R of Xa, AX and Rres)
+        std::vector<ProdItem> items;
+        std::vector<int> live;
+        for (int t = 0; t < nf; ++t) {
+            Freq &q = F[t];
+            if (q.active.empty()) continue;
+            live.push_back(t);
+            const int na = static_cast<int>(q.active.size());
+            bool any_x = false;
+            for (int r : q.active) any_x = any_x || !q.xzero[r];
+            to_device(act, q.active, s);
+            if (any_x) {
+                bblas_gather(n, na, act, xcol(t), ldx, Xa + t * blk, s);
+                items.push_back({f0 + t, na, Xa + t * blk, AX + t * blk});
+            } else {
+                bblas_gather(n, na, act, bcol(t), ldb, Rres + t * blk, s);
+            }
+        }
+        if (live.empty()) break;
+        apply_items(p, VSIE_FP64, items, s);
+        for (const ProdItem &it : items) {
+            const int t = it.f - f0;
+            for (int r : F[t].active) cnt[t].mv64[r]++;
+            to_device(act, F[t].active, s);
+            bblas_sub(n, it.R, act, bcol(t), ldb, AX + t * blk, Rres + t * blk, s);
+        }
+        // the cycles of this refinement step
+        std::vector<std::unique_ptr<BlockCycle>> cyc(nf);
+        std::vector<std::vector<int32_t>> next(nf);
+        double worst_start = 0.0;
+        for (int t : live) {
+            Freq &q = F[t];
+            const int na = static_cast<int>(q.active.size());
+            const std::vector<double> rn = column_norms(p, Rres + t * blk, na, s);
+            std::vector<int32_t> keep_slot;
+            std::vector<double> next_rn, next_tol;
+            for (int sl = 0; sl < na; ++sl) {
+                const int r = q.active[sl];
+                if (!std::isfinite(rn[sl])) fail(VSIE_E_NAN, "non-finite residual");
+                relres[t][r] = rn[sl] / q.bn[r];
+                worst_start = std::max(worst_start, relres[t][r]);
+                if (relres[t][r] <= o.tol) continue;
+                if (cnt[t].it[r] >= o.max_iter || (prec == VSIE_FP32 && cnt[t].outer[r] >= o.max_outer)) {
+                    status[t] = VSIE_E_NOCONV;
+                    continue;
+                }
+                double tl = o.tol * q.bn[r] / rn[sl];
+                if (prec == VSIE_FP32) tl = std::max(tl, o.inner_tol);
+                next[t].push_back(r);
+                keep_slot.push_back(sl);
+                next_rn.push_back(rn[sl]);
+                next_tol.push_back(tl);
+            }
+            if (next[t].empty()) continue;
+            double2 *cyc_res = Rres + t * blk;
+            if (static_cast<int>(next[t].size()) != na) {  // compact the residual block
+                to_device(act, keep_slot, s);
+                bblas_gather(n, static_cast<int>(next[t].size()), act, Rres + t * blk, n, Xa + t * blk, s);
+                cyc_res = Xa + t * blk;
+            }
+            for (int r : next[t]) cnt[t].outer[r]++;
+            const int Ra = static_cast<int>(next[t].size());
+            const int mb = multi_restart(n, Ra, o.restart, nf);
+            double2 *V = (q.have_first ? V2b : Vb) + t * region;
+            cyc[t] = std::make_unique<BlockCycle>(p, f0 + t, prec, false, next[t], cyc_res, next_rn, next_tol, mb,
+                                                  o.max_iter, xcol(t), ldx, cnt[t], s, V, Wb + t * blk,
+                                                  q.have_first ? nullptr : &q.first,
+                                                  q.have_first && q.first.k > 0 ? &q.first : nullptr, false);
+            cyc[t]->begin();
+        }
+        if (p->progress) {
+            int nl = 0;
+            for (int t = 0; t < nf; ++t) nl += cyc[t] != nullptr;
+            std::fprintf(stderr, "[vsie] lockstep refinement step: %d of %d frequencies iterate, max FP64 relative "
+                                 "residual %.3e\n", nl, nf, worst_start);
+            std::fflush(stderr);
+        }
+        // block steps in lockstep; a cycle that stops is finished at once
+        std::vector<int> done(nf, -1);
+        for (int step = 1;; ++step) {
+            std::vector<ProdItem> prod;
+            for (int t = 0; t < nf; ++t)
+                if (cyc[t] && done[t] < 0) {
+                    if (cyc[t]->wants_product()) prod.push_back({f0 + t, cyc[t]->width(), cyc[t]->input(), cyc[t]->output()});
+                    else done[t] = cyc[t]->finish();
+                }
+            if (prod.empty()) break;
+            const auto t0 = std::chrono::steady_clock::now();
+            const int launches = apply_items(p, prec, prod, s);
+            double op_s = 0.0;
+            if (p->progress) {
+                VSIE_HIP(hipStreamSynchronize(s));
+                op_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            }
+            double worst = 0.0;
+            for (const ProdItem &it : prod) {
+                BlockCycle &c = *cyc[it.f - f0];
+                c.after_product();
+                worst = std::max(worst, c.worst());
+            }
+            if (p->progress) {
+                std::fprintf(stderr, "[vsie] lockstep block step %d: %zu frequencies in %d multi-frequency "
+                                     "product%s (%.3f s), max residual estimate %.3e of the cycle start\n",
+                             step, prod.size(), launches, launches == 1 ? "" : "s", op_s, worst);
+                std::fflush(stderr);
+            }
+        }
+        for (int t : live) {
+            Freq &q = F[t];
+            if (!cyc[t]) {
+                q.active.clear();
+                continue;
+            }
+            q.have_first = true;
+            for (int r : next[t]) q.xzero[r] = 0;
+            if (done[t] == 0) {  // breakdown at the first step: no progress possible
+                status[t] = VSIE_E_NOCONV;
+                q.active.clear();
+            } else {
+                q.active = next[t];
+            }
+        }
+    }
+}
+
+// Work buffers of solve_multi_batch: its own blocks and bases, every
+// multi-frequency or single product it can issue, and the block cycles'
+// shared buffers for every width up to R.
+void plan_block_cycles(vsie_problem *p, int R, const std::function<int(int)> &steps, WsPlan &pl);
+
+void plan_solve_multi(vsie_problem *p, int f0, int nf, vsie_precision prec, int R, const vsie_solve_opts &o,
+                      WsPlan &pl) {
+    const int64_t n = p->m.n;
+    const size_t z = sizeof(double2), blk = z * static_cast<size_t>(n) * R;
+    const int64_t region = multi_basis_cols(n, R, o.restart, nf) * n;
+    pl.need(p->V, z * static_cast<size_t>(region) * nf);
+    pl.need(p->V2, z * static_cast<size_t>(region) * nf);
+    for (Scratch *b : {&p->w, &p->xa, &p->axa, &p->rres}) pl.need(*b, blk * nf);
+    pl.need(p->r, blk);
+    pl.need(p->act2, sizeof(int32_t) * R);
+    pl.need(p->npart, sizeof(double) * norm_chunks(n) * R);
+    pl.need(p->nrm, sizeof(double) * R);
+    for (int Ra = 1; Ra <= R; ++Ra)
+        for (vsie_precision pr : {VSIE_FP64, prec}) {
+            for (int len = 1; len <= nf; ++len) plan_multi(p, f0, len, pr, Ra, pl);
+            for (int t = 0; t < nf; ++t) plan_op(p, f0 + t, pr, false, Ra, pl);
+        }
+    plan_block_cycles(p, R, [&](int Ra) { return multi_restart(n, Ra, o.restart, nf); }, pl);
 }
 
 void BlockRecycle::qh(std::vector<cd> &t) const {
@@ -2346,10 +2703,23 @@ void plan_solve(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
         for (Scratch *b : {&p->act, &p->live, &p->kc, &p->kd, &p->defk, &p->lslot}) pl.need(*b, sizeof(int32_t) * ns);
         return;
     }
-    int64_t vcols = 0, kmax = 0;
+    int64_t vcols = 0;
+    for (int Ra = 1; Ra <= R; ++Ra)
+        vcols = std::max<int64_t>(vcols, static_cast<int64_t>(Ra) * (block_restart(n, Ra, o.restart) + 1));
+    plan_block_cycles(p, R, [&](int Ra) { return block_restart(n, Ra, o.restart); }, pl);
+    pl.need(p->V, z * static_cast<size_t>(n) * vcols);
+    pl.need(p->V2, z * static_cast<size_t>(n) * vcols);
+    pl.need(p->w, nR);
+}
+
+// The shared buffers of block cycles of every width up to R, steps(Ra) block
+// steps per cycle of width Ra.
+void plan_block_cycles(vsie_problem *p, int R, const std::function<int(int)> &steps, WsPlan &pl) {
+    const int64_t n = p->m.n;
+    const size_t z = sizeof(double2);
+    int64_t kmax = 0;
     for (int Ra = 1; Ra <= R; ++Ra) {
-        const int mb = block_restart(n, Ra, o.restart);
-        vcols = std::max<int64_t>(vcols, static_cast<int64_t>(Ra) * (mb + 1));
+        const int mb = steps(Ra);
         kmax = std::max<int64_t>(kmax, static_cast<int64_t>(Ra) * mb);
         pl.need(p->bh, z * static_cast<size_t>(mb + 1) * Ra * Ra);
         pl.need(p->bg, z * static_cast<size_t>(Ra) * Ra);
@@ -2361,10 +2731,7 @@ void plan_solve(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
     for (int Ra = 1; Ra <= R; ++Ra)
         for (int64_t k = 1; k <= kv; ++k) pl.need(p->bsk, tall_bytes(k, Ra, n));
     pl.need(p->brc, z * static_cast<size_t>(kv) * R);
-    pl.need(p->V, z * static_cast<size_t>(n) * vcols);
-    pl.need(p->V2, z * static_cast<size_t>(n) * vcols);
-    pl.need(p->w, nR);
-    pl.need(p->ax, nR);
+    pl.need(p->ax, z * static_cast<size_t>(n) * R);
     pl.need(p->act, sizeof(int32_t) * R);
 }
 
@@ -2778,6 +3145,50 @@ vsie_status vsie_solve(vsie_problem *p, int32_t f, vsie_precision prec, int32_t 
     return st != VSIE_OK ? st : result;
 }
 
+vsie_status vsie_solve_multi(vsie_problem *p, int32_t f0, int32_t nf, vsie_precision prec, int64_t nrhs,
+                             const double *b, int64_t ldb, double *x, int64_t ldx, const vsie_solve_opts *opts,
+                             vsie_solve_info *info, void *workspace, size_t ws_bytes, void *stream) {
+    if (info && nf > 0)
+        for (int t = 0; t < nf; ++t) info[t] = vsie_solve_info{0, 0, 0, 0, 0.0};
+    vsie_status result = VSIE_OK;
+    const vsie_status st = guarded([&] {
+        require(p != nullptr, "problem handle is NULL");
+        require(nf >= 1 && f0 >= 0 && static_cast<int64_t>(f0) + nf <= static_cast<int64_t>(p->k0.size()),
+                "frequency range out of bounds");
+        require(prec == VSIE_FP64 || prec == VSIE_FP32, "unknown precision");
+        require(nrhs >= 1 && nrhs <= 4096, "nrhs must be in [1, 4096]");
+        check_vec(b, ldb, p->m.n, "b");
+        check_vec(x, ldx, p->m.n, "x");
+        const vsie_solve_opts o = solve_options(opts);
+        const int R = static_cast<int>(nrhs);
+        WsPlan pl;
+        if (workspace) plan_solve_multi(p, f0, nf, prec, R, o, pl);
+        WsScope ws(pl, workspace, ws_bytes);
+        p->progress = o.progress;
+        hipStream_t s = as_stream(stream);
+        std::vector<SolveCounters> cnt(nf, SolveCounters(R));
+        std::vector<std::vector<double>> rr(nf);
+        std::vector<vsie_status> fs(nf, VSIE_OK);
+        solve_multi_batch(p, f0, nf, prec, R, reinterpret_cast<const double2 *>(b), ldb,
+                          reinterpret_cast<double2 *>(x), ldx, o, cnt, rr, fs, s);
+        VSIE_HIP(hipStreamSynchronize(s));
+        for (int t = 0; t < nf; ++t) {
+            vsie_solve_info tot{0, 0, 0, 0, 0.0};
+            for (int r = 0; r < R; ++r) {
+                tot.iterations += cnt[t].it[r];
+                tot.matvecs_fp64 += cnt[t].mv64[r];
+                tot.matvecs_fp32 += cnt[t].mv32[r];
+                tot.outer_steps = std::max(tot.outer_steps, cnt[t].outer[r]);
+                tot.rel_residual = std::max(tot.rel_residual, rr[t][r]);
+            }
+            if (info) info[t] = tot;
+            if (fs[t] != VSIE_OK) result = fs[t];
+        }
+        if (result == VSIE_E_NOCONV) g_last_error = "GMRES did not reach the tolerance at every frequency";
+    });
+    return st != VSIE_OK ? st : result;
+}
+
 vsie_status vsie_workspace_size(vsie_problem *p, vsie_op op, int32_t f, int32_t nf, vsie_precision prec,
                                 int64_t nrhs, const vsie_solve_opts *opts, size_t *bytes) {
     if (bytes) *bytes = 0;
@@ -2786,11 +3197,11 @@ vsie_status vsie_workspace_size(vsie_problem *p, vsie_op op, int32_t f, int32_t 
         check_problem(p, f);
         require(prec == VSIE_FP64 || prec == VSIE_FP32, "unknown precision");
         require(nrhs >= 1 && nrhs <= 4096, "nrhs must be in [1, 4096]");
-        if (op == VSIE_OP_MATVEC_MULTI)
+        if (op == VSIE_OP_MATVEC_MULTI || op == VSIE_OP_SOLVE_MULTI)
             require(nf >= 1 && static_cast<int64_t>(f) + nf <= static_cast<int64_t>(p->k0.size()),
                     "frequency range out of bounds");
         else
-            require(nf == 1, "nf must be 1 except for VSIE_OP_MATVEC_MULTI");
+            require(nf == 1, "nf must be 1 except for the multi-frequency calls");
         const int R = static_cast<int>(nrhs);
         WsPlan pl;
         switch (op) {
@@ -2799,6 +3210,7 @@ vsie_status vsie_workspace_size(vsie_problem *p, vsie_op op, int32_t f, int32_t 
         case VSIE_OP_MATVEC_MULTI: plan_multi(p, f, nf, prec, R, pl); break;
         case VSIE_OP_SOLVE:
         case VSIE_OP_SOLVE_ADJOINT: plan_solve(p, f, prec, op == VSIE_OP_SOLVE_ADJOINT, R, solve_options(opts), pl); break;
+        case VSIE_OP_SOLVE_MULTI: plan_solve_multi(p, f, nf, prec, R, solve_options(opts), pl); break;
         default: fail(VSIE_E_INVALID, "unknown operation");
         }
         *bytes = pl.total();

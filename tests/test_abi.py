@@ -86,6 +86,10 @@ def test_null_handles(V):
     info = V.SolveInfo()
     st = lib.vsie_solve(None, 0, 0, 0, 1, None, 1, None, 1, None, ctypes.byref(info), None, 0, None)
     assert st == V.VSIE_E_INVALID and info.iterations == 0
+    infos = (V.SolveInfo * 2)()
+    infos[1].iterations = 5
+    st = lib.vsie_solve_multi(None, 0, 2, 0, 1, None, 1, None, 1, None, infos, None, 0, None)
+    assert st == V.VSIE_E_INVALID and infos[1].iterations == 0 and "NULL" in V.vsie_last_error()
     g = V.Geometry()
     h = ctypes.c_void_p(1234)
     st = lib.vsie_assemble(ctypes.byref(g), None, None, None, 0, None, ctypes.byref(h))

@@ -58,10 +58,16 @@ def parse():
                     help="target CPU time of the oracle sample")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched workloads")
     ap.add_argument("--c4-solve", action="store_true",
-                    help="instead of the steps: the block GMRES solves of the 100^3 cube-with-ellipsoid "
-                         "medium (n = 1,076,336) at k0 = 40 for 16 plane waves, FP32 operator in FP64 "
-                         "refinement and plain FP64, to rel. residual 1e-10 (about 17 minutes; the "
-                         "solver prints a progress line per block step on stderr)")
+                    help="instead of the steps: the lockstep multi-frequency block GMRES solve of the "
+                         "100^3 cube-with-ellipsoid medium (n = 1,076,336), 16 plane waves at each of the "
+                         "wavenumbers --c4-freqs, FP32 operator in FP64 refinement to rel. residual 1e-10, "
+                         "with the oracle's residual on sampled rows of every frequency (the solver "
+                         "prints a progress line per block step on stderr)")
+    ap.add_argument("--c4-freqs", default="0-7", metavar="A-B",
+                    help="frequency indices of --c4-solve (k0 = 40 - 2 i), default all eight")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also time the oracle's full FP64 GMRES solve of the headline workload "
+                         "(several minutes on the host cores)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the steps, copy MIB MiB device-to-device three times (a kernel of "
                          "known traffic for scaling HBM byte counters)")
@@ -149,29 +155,89 @@ def c3_gradient(V, W, n_cells=3):
                          "rel_err_grad_rho": errs["rho"]}}
 
 
-def c4_block_solve(V, W):
-    """The largest configuration solved at its first wavenumber: 16 plane
-    waves by block GMRES, FP32 operator (matrix cores) in FP64 refinement and
-    plain FP64, both to relative residual 1e-10; the two solutions compared."""
+def c4_block_solve(V, W, freqs, checks):
+    """The largest configuration in its batched form: 16 plane waves at each
+    wavenumber of freqs solved together by the lockstep multi-frequency block
+    GMRES (FP32 operator on the matrix cores inside FP64 refinement, to
+    relative residual 1e-10), one multi-frequency product per block step.
+    Two columns of every frequency's solution are kept for the oracle's
+    sampled-row residual."""
     import torch
     mesh, mat, k0s, dirs, _ = W.config_problem("c4")
+    f0, f1 = freqs
+    nf = f1 - f0 + 1
     P = V.Problem.from_mesh(mesh, mat, k0s)
-    B = P.plane_wave(dirs, f=0).contiguous()
-    out, sols = {}, {}
-    for name, prec in (("fp32_refine", V.VSIE_FP32), ("fp64", V.VSIE_FP64)):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        x, info = P.solve(B, f=0, prec=prec, tol=TOL, block=True, progress=True)
-        torch.cuda.synchronize()
-        out[name] = {"solve_s": time.perf_counter() - t0, "iterations": info}
-        sols[name] = x
-    out["speedup_fp32_refine_vs_fp64"] = out["fp64"]["solve_s"] / out["fp32_refine"]["solve_s"]
-    out["rel_diff_fp32_refine_vs_fp64_solution"] = float(
-        torch.linalg.norm(sols["fp32_refine"] - sols["fp64"]) / torch.linalg.norm(sols["fp64"]))
+    R = dirs.shape[0]
+    B = torch.cat([P.plane_wave(dirs, f=f) for f in range(f0, f1 + 1)], dim=0).contiguous()
+    torch.cuda.synchronize()
+    P.profile(True)
+    t0 = time.perf_counter()
+    X, infos = P.solve_multi(B, f0=f0, nf=nf, prec=V.VSIE_FP32, tol=TOL, progress=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = P.kernel_stats()
+    P.profile(False)
+    note("c4 lockstep solve of %d frequencies: %.1f s" % (nf, dt))
+    mv32 = sum(i["matvecs_fp32"] for i in infos)
+    mv64 = sum(i["matvecs_fp64"] for i in infos)
+    for t in range(nf):
+        checks.append({"label": "c4_k0_%g" % k0s[f0 + t], "problem": ("c4", None), "f": f0 + t,
+                       "x": X[t * R:t * R + 2].cpu().numpy().T, "b": B[t * R:t * R + 2].cpu().numpy().T})
     P.close()
-    return {"c4_block_solve": {
-        "workload": "cube with ellipsoid, 100^3 grid, n=%d, k0=%.0f, %d plane waves, block GMRES to rel. "
-                    "residual 1e-10" % (mesh.n, k0s[0], dirs.shape[0]), **out}}
+    return {"c4_lockstep_solve": {
+        "workload": "cube with ellipsoid, 100^3 grid, n=%d, k0 = %s, %d plane waves each; lockstep "
+                    "multi-frequency block GMRES, FP32 operator (matrix cores) in FP64 refinement to "
+                    "rel. residual 1e-10" % (mesh.n, k0s[f0:f1 + 1], R),
+        "solve_s": dt, "per_frequency": dict(zip(["%g" % k for k in k0s[f0:f1 + 1]], infos)),
+        "gpair_col_evals_per_s": float(mesh.n) * mesh.n * (mv32 + mv64) / dt / 1e9,
+        "pair_kernels": {k: {"launches": v["launches"], "ms": v["ms"]} for k, v in st.items()}}}
+
+
+def c4_lockstep_reduced(V, W, N, checks):
+    """The cube-with-ellipsoid workload on an N^3 grid with the wavenumbers
+    scaled by N/100 (the sampling per wavelength of the 100^3 grid): all 8
+    frequencies x 16 plane waves by the lockstep multi-frequency block GMRES,
+    and the same systems frequency by frequency with the one-frequency block
+    solver, both FP32 operator in FP64 refinement to 1e-10."""
+    import torch
+    mesh, mat, k0s, dirs, _ = W.config_problem("c4", N=N)
+    ks = [k * N / 100.0 for k in k0s]
+    nf, R = len(ks), dirs.shape[0]
+    P = V.Problem.from_mesh(mesh, mat, ks)
+    B = torch.cat([P.plane_wave(dirs, f=f) for f in range(nf)], dim=0).contiguous()
+    # untimed short runs size the work buffers of both paths
+    P.solve_multi(B, prec=V.VSIE_FP32, tol=TOL, max_iter=R, allow_noconv=True)
+    P.solve(B[:R].contiguous(), f=0, prec=V.VSIE_FP32, tol=TOL, block=True, max_iter=R, allow_noconv=True)
+    torch.cuda.synchronize()
+    P.profile(True)
+    t0 = time.perf_counter()
+    X, infos = P.solve_multi(B, prec=V.VSIE_FP32, tol=TOL)
+    torch.cuda.synchronize()
+    t_lock = time.perf_counter() - t0
+    st = P.kernel_stats()
+    P.profile(False)
+    t0 = time.perf_counter()
+    seq = []
+    for f in range(nf):
+        x1, i1 = P.solve(B[f * R:(f + 1) * R].contiguous(), f=f, prec=V.VSIE_FP32, tol=TOL, block=True)
+        seq.append((x1, i1))
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    diff = max(float(torch.linalg.norm(X[f * R:(f + 1) * R] - seq[f][0]) / torch.linalg.norm(seq[f][0]))
+               for f in range(nf))
+    for f in range(nf):
+        checks.append({"label": "c4_%d_k0_%.2f" % (N, ks[f]), "problem": ("c4", N), "f": f,
+                       "x": X[f * R:f * R + 2].cpu().numpy().T, "b": B[f * R:f * R + 2].cpu().numpy().T})
+    note("c4 at %d^3 (n = %d): lockstep %.2f s, frequency by frequency %.2f s" % (N, mesh.n, t_lock, t_seq))
+    P.close()
+    return {"workload": "cube with ellipsoid, %d^3 grid, n=%d, k0 = %s (the 100^3 wavenumbers x %d/100), "
+                        "%d plane waves each, FP32 operator in FP64 refinement to rel. residual 1e-10"
+                        % (N, mesh.n, ["%.2f" % k for k in ks], N, R),
+            "lockstep_solve_s": t_lock, "one_frequency_solves_s": t_seq, "speedup_lockstep": t_seq / t_lock,
+            "per_frequency": dict(zip(["%.2f" % k for k in ks], infos)),
+            "one_frequency_iterations": [i for _, i in seq],
+            "max_rel_diff_lockstep_vs_one_frequency": diff,
+            "lockstep_pair_kernels": {k: {"launches": v["launches"], "ms": v["ms"]} for k, v in st.items()}}
 
 
 def far_field_pattern(V, P, x):
@@ -239,7 +305,7 @@ def exterior_slice(V, P, x, dirs):
     return res
 
 
-def paper_benchmark_solves(V, W):
+def paper_benchmark_solves(V, W, checks):
     """The paper's four benchmarks (section 3) at the resolutions of its
     figures, each solved with the FP32 operator in FP64 refinement and with
     the FP64 operator: the sphere in a cube at 8 cells per interior
@@ -274,6 +340,9 @@ def paper_benchmark_solves(V, W):
             torch.linalg.norm(sols["fp32_refine"] - sols["fp64"]) / torch.linalg.norm(sols["fp64"]))
         note("%s: FP32+refinement %.3f s, FP64 %.3f s" % (label, out["fp32_refine"]["solve_s"], out["fp64"]["solve_s"]))
         if label == "b4_3d_run":
+            checks.append({"label": "b4_3d_run_fp32_refine", "problem": ("b4", None), "f": 0,
+                           "x": sols["fp32_refine"].cpu().numpy().reshape(-1, 1),
+                           "b": b.cpu().numpy().reshape(-1, 1)})
             out["far_field_pattern"] = far_field_pattern(V, P, sols["fp64"])
             out["exterior_field_slice"] = exterior_slice(V, P, sols["fp64"].reshape(-1), dirs)
         P.close()
@@ -296,9 +365,11 @@ def dense_roofline(st, tuning):
             "mfma_executed_tflops": mfma, "mfma_busy_frac": mfma / 157.3}
 
 
-def batched_workloads(V, W):
-    """Block GMRES over 128 directions (assembled and matrix-free) and one
-    multi-frequency product over 8 wavenumbers x 16 directions."""
+def batched_workloads(V, W, checks):
+    """Block GMRES over 128 directions (assembled and matrix-free), the
+    gradient workload, the paper's benchmarks, one multi-frequency product over
+    8 wavenumbers x 16 directions and the lockstep multi-frequency solve on
+    reduced grids.  Columns of the solutions go to checks for the oracle."""
     import torch
     out = {}
     mesh, mat, k0s, dirs, _ = W.config_problem("c2")
@@ -321,6 +392,10 @@ def batched_workloads(V, W):
         st = P.kernel_stats()
         P.profile(False)
         sols[name] = x
+        if name != "matrix_free_fp64":
+            cols = [0, 42, 85, 127]
+            checks.append({"label": "c2_block_gmres_" + name, "problem": ("c2", None), "f": 0,
+                           "x": x[cols].cpu().numpy().T, "b": B[cols].cpu().numpy().T})
         mv = info["matvecs_fp32"] + info["matvecs_fp64"]
         op = ("FP32 operator %s in FP64 refinement" % ("assembled (%.1f GB)" % (8.0 * n * n / 1e9)
                                                        if A is not None else "matrix-free")
@@ -349,7 +424,7 @@ def batched_workloads(V, W):
     del B
     out["c3_adjoint_gradient"] = c3_gradient(V, W)
     note("c3 gradient done")
-    out["paper_benchmarks"] = paper_benchmark_solves(V, W)
+    out["paper_benchmarks"] = paper_benchmark_solves(V, W, checks)
     mesh, mat, k0s, dirs, _ = W.config_problem("c4")
     P = V.Problem.from_mesh(mesh, mat, k0s)
     n, nf, R = P.n, len(k0s), dirs.shape[0]
@@ -372,11 +447,15 @@ def batched_workloads(V, W):
         "tuning": P.tuning,
         "pair_kernels": {k: {"launches": v["launches"], "ms": v["ms"]} for k, v in st.items()}}
     P.close()
+    del X, Y
+    torch.cuda.empty_cache()
+    out["c4_lockstep_reduced"] = {"N%d" % N: c4_lockstep_reduced(V, W, N, checks) for N in (32, 48)}
     return out
 
 
 def cpu_baseline(mesh, mat, k0, n, target_s):
-    """The FP64 oracle's direct summation on a bounded sample of rows."""
+    """The FP64 oracle's direct summation on a bounded sample of rows of the
+    headline workload: the reported CPU baseline."""
     import oracle as O
     import workloads as W
     d = O.discretise(mesh, mat, k0)
@@ -399,6 +478,115 @@ def cpu_baseline(mesh, mat, k0, n, target_s):
             "seconds": dt}
 
 
+def cpu_baseline_discretisation(problem, f):
+    """The oracle's discretisation of a workload named by a check record."""
+    import oracle as O
+    import workloads as W
+    name, N = problem
+    if name == "b4":
+        mesh, mat, k0s, _, grad = W.benchmark4_problem()
+        return O.discretise(mesh, mat, k0s[f], grad_rho=grad)
+    mesh, mat, k0s, _, _ = W.config_problem(name, N=N)
+    k = k0s[f] * (N / 100.0 if N is not None else 1.0)
+    return O.discretise(mesh, mat, k)
+
+
+def cpu_baseline_checks(checks, rows_per_check=256):
+    """The oracle's residual ||(b - A x)[rows]|| / ||b[rows]|| of GPU solution
+    columns on 256 seeded rows (plus the first and last cell and face) of the
+    Theorem 3 system."""
+    import oracle as O
+    out = {}
+    cache = {}
+    for c in checks:
+        key = (c["problem"], c["f"])
+        if key not in cache:
+            cache.clear()
+            cache[key] = cpu_baseline_discretisation(*key)
+        d = cache[key]
+        rng = np.random.default_rng(71)
+        rows = np.unique(np.concatenate([rng.choice(d.n, rows_per_check, replace=False),
+                                         [0, d.n_vol - 1, d.n_vol, d.n - 1]]))
+        X, B = np.asarray(c["x"]).reshape(d.n, -1), np.asarray(c["b"]).reshape(d.n, -1)
+        r = B[rows] - O.matvec(d, X, rows=rows)
+        out[c["label"]] = {"rel_residual": float(np.linalg.norm(r) / np.linalg.norm(B[rows])),
+                           "rows": int(rows.size), "columns": int(X.shape[1])}
+    return out
+
+
+def cpu_baseline_plan(full_c1_gmres=False):
+    """The oracle timed on the other workloads, each bounded: c0 solved by
+    dense LU; c2's operator on 2,048 seeded rows with 1 and with 4 columns;
+    c3's forward (8 incidences) and adjoint (256 receivers) problems on the
+    24^3 grid by one dense LU; 4,096 seeded rows of c4's operator (the full
+    product extrapolated); and, when asked, the full FP64 GMRES solve of c1."""
+    import scipy.linalg as sla
+    import oracle as O
+    import workloads as W
+    plan = {}
+
+    def timed(fn):
+        t = time.perf_counter()
+        r = fn()
+        return r, time.perf_counter() - t
+
+    mesh, mat, k0s, dirs, _ = W.config_problem("c0")
+    d = O.discretise(mesh, mat, k0s[0])
+    b = O.plane_wave(d.pts, k0s[0], dirs[0])
+    A, t_asm = timed(lambda: O.assemble(d))
+    lu, t_lu = timed(lambda: sla.lu_factor(A))
+    _, t_sol = timed(lambda: sla.lu_solve(lu, b))
+    plan["c0_lu"] = {"n": d.n, "assemble_s": t_asm, "factor_s": t_lu, "solve_s": t_sol,
+                     "total_s": t_asm + t_lu + t_sol}
+    note("oracle c0 LU: %.2f s" % (t_asm + t_lu + t_sol))
+
+    mesh, mat, k0s, dirs, _ = W.config_problem("c2")
+    d = O.discretise(mesh, mat, k0s[0])
+    rows = np.sort(np.random.default_rng(33).choice(d.n, 2048, replace=False))
+    for R in (1, 4):
+        x = W.seeded_complex((d.n, R), seed=34)
+        _, t = timed(lambda: O.matvec(d, x, rows=rows))
+        plan["c2_matvec_%drhs" % R] = {"rows": int(rows.size), "n": d.n, "seconds": t,
+                                       "gpair_evals_per_s": rows.size * float(d.n) / t / 1e9,
+                                       "gpair_col_evals_per_s": rows.size * float(d.n) * R / t / 1e9,
+                                       "full_matvec_s_extrapolated": t * d.n / rows.size}
+    note("oracle c2 rows done")
+
+    mesh, mat, k0s, dirs, rec = W.config_problem("c3", N=24)
+    d = O.discretise(mesh, mat, k0s[0])
+    A, t_asm = timed(lambda: O.assemble(d))
+    lu, t_lu = timed(lambda: sla.lu_factor(A))
+    B = O.plane_wave(d.pts, k0s[0], dirs)
+    _, t_fwd = timed(lambda: sla.lu_solve(lu, B))
+    lam = W.seeded_complex((d.n, rec.shape[0]), seed=35)
+    _, t_adj = timed(lambda: sla.lu_solve(lu, lam, trans=2))
+    plan["c3_24"] = {"n": d.n, "assemble_s": t_asm, "factor_s": t_lu, "forward_solve_s": t_fwd,
+                     "adjoint_solve_s": t_adj, "incidences": int(dirs.shape[0]), "receivers": int(rec.shape[0])}
+    del A, lu
+    note("oracle c3 at 24^3: %.1f s" % (t_asm + t_lu + t_fwd + t_adj))
+
+    mesh, mat, k0s, dirs, _ = W.config_problem("c4")
+    d = O.discretise(mesh, mat, k0s[0])
+    rows = np.sort(np.random.default_rng(36).choice(d.n, 4096, replace=False))
+    x = W.seeded_complex(d.n, seed=37)
+    _, t = timed(lambda: O.matvec(d, x, rows=rows))
+    plan["c4_rows"] = {"rows": int(rows.size), "n": d.n, "seconds": t,
+                       "gpair_evals_per_s": rows.size * float(d.n) / t / 1e9,
+                       "full_matvec_s_extrapolated": t * d.n / rows.size,
+                       "note": "the full product time is an extrapolation from the sampled rows"}
+    note("oracle c4 rows: %.1f s" % t)
+
+    if full_c1_gmres:
+        mesh, mat, k0s, dirs, _ = W.config_problem("c1")
+        d = O.discretise(mesh, mat, k0s[0])
+        b = O.plane_wave(d.pts, k0s[0], dirs[0])
+        (_, its, rr), t = timed(lambda: O.solve_gmres(d, b, tol=1e-12))
+        plan["c1_gmres"] = {"n": d.n, "tol": 1e-12, "iterations": its, "rel_residual": rr, "seconds": t,
+                            "restart": 200}
+        note("oracle c1 GMRES: %.1f s" % t)
+    return plan
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -411,8 +599,12 @@ def main():
 
     assert torch.cuda.is_available(), "needs a GPU"
     torch.cuda.set_device(0)
+    checks = []
     if args.c4_solve:
-        print(json.dumps(c4_block_solve(V, W)), flush=True)
+        f0, f1 = (int(v) for v in args.c4_freqs.split("-"))
+        res = c4_block_solve(V, W, (f0, f1), checks)
+        res["cpu_baseline"] = {"kind": "oracle", "oracle_checks": cpu_baseline_checks(checks)}
+        print(json.dumps(res), flush=True)
         return
     mesh, mat, k0s, dirs, _ = W.config_problem("c1")
     k0 = k0s[0]
@@ -522,10 +714,12 @@ def main():
         "roofline": roofline,
     }
     if not args.no_batched:
-        out["batched"] = batched_workloads(V, W)
+        out["batched"] = batched_workloads(V, W, checks)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(mesh, mat, k0, n, args.cpu_seconds)
         cb["solve_s_extrapolated_fp64"] = float(n) * n * info64["matvecs_fp64"] / (cb["value"] * 1e9)
+        cb["plan"] = cpu_baseline_plan(args.cpu_full)
+        cb["oracle_checks"] = cpu_baseline_checks(checks)
         out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
     P.close()

@@ -210,6 +210,14 @@ typedef struct {
                                   16, 32 or 64 columns on the FP64 matrix cores
                                   (v_mfma_f64_16x16x4_f64, FP64 accumulation); 0 = never;
                                   default 16 */
+    int32_t mfma_chunk_max;    /* matrix-core products (FP32 and FP64): at most this many
+                                  sources per chunk, 0 = no cap (>= 1024 otherwise).
+                                  The waves of one XCD walk the target tiles of one
+                                  chunk, so a cap keeps the source positions and charges
+                                  they stream within the last-level cache on large
+                                  problems; every chunk adds one FP64 partial per
+                                  target and column (frequencies x columns x n x 16
+                                  bytes per chunk) */
 } vsie_tuning;
 
 vsie_status vsie_get_tuning(const vsie_problem *p, vsie_tuning *out);

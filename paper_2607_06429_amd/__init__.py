@@ -73,7 +73,8 @@ class SolveOpts(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("mfma_min_rhs", _I32), ("mfma_tg", _I32), ("mfma_nb", _I32),
                 ("items_per_wave", _I32), ("vec_target_waves", _I64), ("graph", _I32),
-                ("sym_groups", _I32), ("cell_face", _I32), ("mfma_3m", _I32), ("mfma64_min_rhs", _I32)]
+                ("sym_groups", _I32), ("cell_face", _I32), ("mfma_3m", _I32), ("mfma64_min_rhs", _I32),
+                ("mfma_chunk_max", _I32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

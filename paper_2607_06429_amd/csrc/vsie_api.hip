@@ -201,7 +201,7 @@ struct vsie_problem {
     HostPinned hpin;      // per-iteration Hessenberg columns and norms on their way to the host
     int progress = 0;     // vsie_solve_opts::progress of the running solve
     PairProfiler prof;
-    vsie_tuning tune{8, 2, 1, 16, 32768, 1, 4, 1, 1, 16};
+    vsie_tuning tune{8, 2, 1, 16, 32768, 1, 4, 1, 1, 16, 0};
     // every cell is a single-layer source and the sources are the cells in
     // canonical order (the symmetric cell-cell kernel applies)
     bool g_is_cells = false;
@@ -1030,6 +1030,8 @@ MfmaLayout mfma_layout(const vsie_problem *p, int nf, int nrhs) {
         }
         int64_t c = (want + items_per_chunk - 1) / items_per_chunk;
         c = std::max<int64_t>(1, std::min<int64_t>(c, std::max<int64_t>(1, ns / 512)));
+        const int64_t cap = p->tune.mfma_chunk_max;
+        if (cap > 0) c = std::max<int64_t>(c, (ns + cap - 1) / cap);
         chunk = ((ns + c - 1) / c + 3) / 4 * 4;
         nc = static_cast<int>((ns + chunk - 1) / chunk);
     };
@@ -1129,6 +1131,8 @@ Mfma64Layout mfma64_layout(const vsie_problem *p, int nf, int nrhs) {
         }
         int64_t c = (want + items_per_chunk - 1) / items_per_chunk;
         c = std::max<int64_t>(1, std::min<int64_t>(c, std::max<int64_t>(1, ns / 512)));
+        const int64_t cap = p->tune.mfma_chunk_max;
+        if (cap > 0) c = std::max<int64_t>(c, (ns + cap - 1) / cap);
         chunk = ((ns + c - 1) / c + 3) / 4 * 4;
         nc = static_cast<int>((ns + chunk - 1) / chunk);
     };
@@ -1202,6 +1206,7 @@ void check_tuning(const vsie_tuning &t) {
     require(t.cell_face == 0 || t.cell_face == 1, "cell_face must be 0 or 1");
     require(t.mfma_3m == 0 || t.mfma_3m == 1, "mfma_3m must be 0 or 1");
     require(t.mfma64_min_rhs >= 0, "mfma64_min_rhs must be >= 0");
+    require(t.mfma_chunk_max == 0 || t.mfma_chunk_max >= 1024, "mfma_chunk_max must be 0 or >= 1024");
 }
 
 // The work buffers of apply_op (same dispatch).

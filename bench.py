@@ -155,6 +155,33 @@ def c3_gradient(V, W, n_cells=3):
                          "rel_err_grad_rho": errs["rho"]}}
 
 
+def matrix_core_issue(st, tuning, widths):
+    """Issue-cycle fraction of the matrix-core pair launches in the profiler
+    stats st: cycles per pair and per column block from isa_counts.json (the
+    variant the tuning and the column widths select) x pair-column
+    evaluations / column-block width, over the launches' measured time,
+    against 256 CUs x 4 SIMDs x 2.4 GHz."""
+    counts = json.load(open(os.path.join(ROOT, "measurement", "isa_counts.json")))
+    out = {}
+    for name, v in st.items():
+        if not name.startswith("mfma_fwd_"):
+            continue
+        mode = name[len("mfma_"):].rsplit("_", 1)[0]
+        m3 = "_3m" if tuning["mfma_3m"] else ""
+        if name.endswith("fp32"):
+            key = "mfma_%s_fp32_tg%d_nb%d%s" % (mode, tuning["mfma_tg"], tuning["mfma_nb"], m3)
+        else:
+            w = max(widths)
+            key = "mfma64_%s_fp64_nb%d%s" % (mode, 1 if w <= 16 else 2 if w <= 32 else 4, m3)
+        c = counts.get(key)
+        if c is None:
+            continue
+        cyc = c["cycles_per_pair"] * v["rhs_pairs"] / c["rhs_per_trip"]
+        out[name] = {"isa_variant": key, "cycles_per_pair_block": c["cycles_per_pair"],
+                     "issue_frac": cyc / (v["ms"] * 1e-3) / ISSUE_PEAK}
+    return out
+
+
 def c4_block_solve(V, W, freqs, checks):
     """The largest configuration in its batched form: 16 plane waves at each
     wavenumber of freqs solved together by the lockstep multi-frequency block
@@ -178,6 +205,7 @@ def c4_block_solve(V, W, freqs, checks):
     st = P.kernel_stats()
     P.profile(False)
     note("c4 lockstep solve of %d frequencies: %.1f s" % (nf, dt))
+    P_tuning = P.tuning
     mv32 = sum(i["matvecs_fp32"] for i in infos)
     mv64 = sum(i["matvecs_fp64"] for i in infos)
     for t in range(nf):
@@ -190,7 +218,8 @@ def c4_block_solve(V, W, freqs, checks):
                     "rel. residual 1e-10" % (mesh.n, k0s[f0:f1 + 1], R),
         "solve_s": dt, "per_frequency": dict(zip(["%g" % k for k in k0s[f0:f1 + 1]], infos)),
         "gpair_col_evals_per_s": float(mesh.n) * mesh.n * (mv32 + mv64) / dt / 1e9,
-        "pair_kernels": {k: {"launches": v["launches"], "ms": v["ms"]} for k, v in st.items()}}}
+        "pair_kernels": {k: {"launches": v["launches"], "ms": v["ms"]} for k, v in st.items()},
+        "matrix_core_issue": matrix_core_issue(st, P_tuning, [R])}}
 
 
 def c4_lockstep_reduced(V, W, N, checks):
@@ -229,6 +258,7 @@ def c4_lockstep_reduced(V, W, N, checks):
         checks.append({"label": "c4_%d_k0_%.2f" % (N, ks[f]), "problem": ("c4", N), "f": f,
                        "x": X[f * R:f * R + 2].cpu().numpy().T, "b": B[f * R:f * R + 2].cpu().numpy().T})
     note("c4 at %d^3 (n = %d): lockstep %.2f s, frequency by frequency %.2f s" % (N, mesh.n, t_lock, t_seq))
+    issue = matrix_core_issue(st, P.tuning, [R])
     P.close()
     return {"workload": "cube with ellipsoid, %d^3 grid, n=%d, k0 = %s (the 100^3 wavenumbers x %d/100), "
                         "%d plane waves each, FP32 operator in FP64 refinement to rel. residual 1e-10"
@@ -237,7 +267,8 @@ def c4_lockstep_reduced(V, W, N, checks):
             "per_frequency": dict(zip(["%.2f" % k for k in ks], infos)),
             "one_frequency_iterations": [i for _, i in seq],
             "max_rel_diff_lockstep_vs_one_frequency": diff,
-            "lockstep_pair_kernels": {k: {"launches": v["launches"], "ms": v["ms"]} for k, v in st.items()}}
+            "lockstep_pair_kernels": {k: {"launches": v["launches"], "ms": v["ms"]} for k, v in st.items()},
+            "matrix_core_issue": issue}
 
 
 def far_field_pattern(V, P, x):
@@ -406,7 +437,8 @@ def batched_workloads(V, W, checks):
                         "%s to rel. residual 1e-10" % (n, R, op),
             "solve_s": dt, "iterations": info, "gpair_col_evals_per_s": float(n) * n * mv / dt / 1e9,
             "tuning": P.tuning if name == "matrix_free_fp32" else None,
-            "pair_kernels": {k: {"launches": v["launches"], "ms": v["ms"]} for k, v in st.items()}}
+            "pair_kernels": {k: {"launches": v["launches"], "ms": v["ms"]} for k, v in st.items()},
+            "matrix_core_issue": matrix_core_issue(st, P.tuning, [R])}
         if A is not None and "dense_product_fp32" in st:
             out["c2_block_gmres_" + name]["dense_product"] = dense_roofline(st["dense_product_fp32"], P.tuning)
         if A is not None:
@@ -445,7 +477,8 @@ def batched_workloads(V, W, checks):
                     "one matrix-core launch per source class" % (n, k0s, R),
         "product_s": dt, "gpair_col_evals_per_s": float(n) * n * nf * R / dt / 1e9,
         "tuning": P.tuning,
-        "pair_kernels": {k: {"launches": v["launches"], "ms": v["ms"]} for k, v in st.items()}}
+        "pair_kernels": {k: {"launches": v["launches"], "ms": v["ms"]} for k, v in st.items()},
+        "matrix_core_issue": matrix_core_issue(st, P.tuning, [R])}
     P.close()
     del X, Y
     torch.cuda.empty_cache()

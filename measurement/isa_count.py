@@ -3,8 +3,8 @@ kernels' inner loops.
 
     python measurement/isa_count.py
 
-Compiles csrc/pair_kernels.hip, csrc/mfma_kernels.hip, csrc/sym_kernels.hip
-and csrc/far_field.hip to gfx950 assembly
+Compiles csrc/pair_kernels.hip, csrc/mfma_kernels.hip (FP32 and FP64 matrix-core
+kernels), csrc/sym_kernels.hip and csrc/far_field.hip to gfx950 assembly
 (the same flags as the library build) and, for each kernel variant, finds the
 innermost loop that evaluates the most pairs per trip (the unrolled
 steady-state loop; one v_rsq per pair and lane, in the far-field kernels one
@@ -20,6 +20,7 @@ Issue-cycle model (SIMD cycles one wave64 instruction occupies; the chip has
   FP32 transcendental (rsq sin cos) 8   (quarter of the FP32 rate)
   FP64 transcendental (rsq_f64)    16
   v_mfma_f32_16x16x4_f32           32   (2048 FLOP at 64 FLOP/cycle/SIMD)
+  v_mfma_f64_16x16x4_f64           64   (2048 FLOP at 78.6 TFLOP/s FP64 matrix = 32 FLOP/cycle/SIMD)
   DPP moves (v_mov_b32_dpp)         4   (measured)
 Microbenchmarks on MI355X give 2.5-2.8, 4.4-5.8, 8.5, 16.3, 32.5 and 4.1 cycles
 with 8 independent chains per lane, and show matrix-core and VALU time adding
@@ -54,6 +55,8 @@ def assemble(src: str) -> str:
 
 def cycles(op: str) -> int:
     """Issue cycles of one wave64 instruction (the model above)."""
+    if op.startswith("v_mfma_f64"):
+        return 64
     if op.startswith("v_mfma"):
         return 32
     if "_dpp" in op:
@@ -102,6 +105,10 @@ def kernels(asm: str):
     for nm in re.findall(r"^(_Z\w+mfma_fwd_kernel\w+):", asm, re.M):
         cls, tg, nb, m3 = re.search(r"kernelILi(\d)ELi(\d)ELi(\d)ELb(\d)E", nm).groups()
         yield nm, "mfma_%s_fp32_tg%s_nb%s%s" % (MODES[int(cls)], tg, nb, "_3m" if m3 == "1" else ""), 16 * int(nb)
+    for nm in re.findall(r"^(_Z\w+mfma64_fwd_kernel\w+):", asm, re.M):
+        cls, nb, m3 = re.search(r"kernelILi(\d)ELi(\d)ELb(\d)E", nm).groups()
+        yield (nm, "mfma64_%s_fp64_nb%s%s" % (MODES[int(cls)], nb, "_3m" if m3 == "1" else ""), 16 * int(nb),
+               r"v_rsq_f64")
     for nm in re.findall(r"^(_Z\w+sym_kernel\w+):", asm, re.M):
         g, acc, t, adj = re.search(r"sym_kernelILi(\d)E(\w)Lb(\d)ELb(\d)E", nm).groups()
         if g == "4":   # the default group size; the inner loop is the same for every size

@@ -65,6 +65,10 @@ def parse():
                          "prints a progress line per block step on stderr)")
     ap.add_argument("--c4-freqs", default="0-7", metavar="A-B",
                     help="frequency indices of --c4-solve (k0 = 40 - 2 i), default all eight")
+    ap.add_argument("--krylov-gib", type=int, default=0,
+                    help="device memory of the Krylov bases of --c4-solve in GiB (0: the library default, "
+                         "96); the frequencies share it, so the cycle length per frequency falls with "
+                         "their number")
     ap.add_argument("--cpu-full", action="store_true",
                     help="also time the oracle's full FP64 GMRES solve of the headline workload "
                          "(several minutes on the host cores)")
@@ -182,7 +186,7 @@ def matrix_core_issue(st, tuning, widths):
     return out
 
 
-def c4_block_solve(V, W, freqs, checks):
+def c4_block_solve(V, W, freqs, checks, krylov_gib=0):
     """The largest configuration in its batched form: 16 plane waves at each
     wavenumber of freqs solved together by the lockstep multi-frequency block
     GMRES (FP32 operator on the matrix cores inside FP64 refinement, to
@@ -199,7 +203,7 @@ def c4_block_solve(V, W, freqs, checks):
     torch.cuda.synchronize()
     P.profile(True)
     t0 = time.perf_counter()
-    X, infos = P.solve_multi(B, f0=f0, nf=nf, prec=V.VSIE_FP32, tol=TOL, progress=True)
+    X, infos = P.solve_multi(B, f0=f0, nf=nf, prec=V.VSIE_FP32, tol=TOL, progress=True, krylov_gib=krylov_gib)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st = P.kernel_stats()
@@ -215,7 +219,7 @@ def c4_block_solve(V, W, freqs, checks):
     return {"c4_lockstep_solve": {
         "workload": "cube with ellipsoid, 100^3 grid, n=%d, k0 = %s, %d plane waves each; lockstep "
                     "multi-frequency block GMRES, FP32 operator (matrix cores) in FP64 refinement to "
-                    "rel. residual 1e-10" % (mesh.n, k0s[f0:f1 + 1], R),
+                    "rel. residual 1e-10; Krylov budget %s GiB" % (mesh.n, k0s[f0:f1 + 1], R, krylov_gib or 96),
         "solve_s": dt, "per_frequency": dict(zip(["%g" % k for k in k0s[f0:f1 + 1]], infos)),
         "gpair_col_evals_per_s": float(mesh.n) * mesh.n * (mv32 + mv64) / dt / 1e9,
         "pair_kernels": {k: {"launches": v["launches"], "ms": v["ms"]} for k, v in st.items()},
@@ -635,7 +639,7 @@ def main():
     checks = []
     if args.c4_solve:
         f0, f1 = (int(v) for v in args.c4_freqs.split("-"))
-        res = c4_block_solve(V, W, (f0, f1), checks)
+        res = c4_block_solve(V, W, (f0, f1), checks, args.krylov_gib)
         res["cpu_baseline"] = {"kind": "oracle", "oracle_checks": cpu_baseline_checks(checks)}
         print(json.dumps(res), flush=True)
         return

@@ -236,9 +236,9 @@ typedef struct {
     double tol;          /* stop when ||b - A x|| <= tol ||b|| (FP64 residual); default 1e-10 */
     int32_t max_iter;    /* total GMRES iterations (all cycles, all outer steps); default 3000 */
     int32_t restart;     /* Krylov dimension per cycle; default 500, lowered when the
-                            basis of all nrhs right-hand sides would exceed 48 GiB
-                            (two bases of at most 48 GiB each: the first cycle's is kept
-                            to deflate the later cycles) */
+                            basis of all nrhs right-hand sides would exceed half of the
+                            Krylov budget (krylov_gib: two bases of half of it each, the
+                            first cycle's kept to deflate the later cycles) */
     double inner_tol;    /* VSIE_FP32 only: relative tolerance of each inner solve; default 1e-5 */
     int32_t max_outer;   /* VSIE_FP32 only: refinement steps; default 20 */
     int32_t block;       /* 0: an independent GMRES per right-hand side, advanced in
@@ -259,6 +259,12 @@ typedef struct {
     int32_t progress;    /* 1: one line on stderr per outer step (FP64 residual), per block
                             step and every 25 GMRES iterations (residual estimate), for long
                             solves; 0: silent (default) */
+    int32_t krylov_gib;  /* device memory of the two Krylov bases together, in GiB (half
+                            each); it caps the restart length as described under restart.
+                            0: 96 (default), which leaves room for an assembled operator;
+                            at most 4096.  A large problem without an assembled operator
+                            (and a multi-frequency solve, whose frequencies share it) may
+                            raise it toward the free device memory. */
 } vsie_solve_opts;
 
 typedef struct {

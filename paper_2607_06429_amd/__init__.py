@@ -67,7 +67,8 @@ class KernelStats(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", _D), ("max_iter", _I32), ("restart", _I32), ("inner_tol", _D),
-                ("max_outer", _I32), ("block", _I32), ("relax", _D), ("progress", _I32)]
+                ("max_outer", _I32), ("block", _I32), ("relax", _D), ("progress", _I32),
+                ("krylov_gib", _I32)]
 
 
 class Tuning(ctypes.Structure):
@@ -308,8 +309,9 @@ def vsie_matvec_multi(h, f0, nf, prec, x, y, stream=None, workspace=None):
 
 
 def _opts(tol=1e-10, max_iter=3000, restart=500, inner_tol=1e-5, max_outer=20, block=False, relax=0.0,
-          progress=False):
-    return SolveOpts(tol, max_iter, restart, inner_tol, max_outer, 1 if block else 0, relax, 1 if progress else 0)
+          progress=False, krylov_gib=0):
+    return SolveOpts(tol, max_iter, restart, inner_tol, max_outer, 1 if block else 0, relax, 1 if progress else 0,
+                     krylov_gib)
 
 
 def vsie_workspace_size(h, op, f, prec, nrhs, nf=1, **opts) -> int:
@@ -345,7 +347,7 @@ def vsie_autotune(h, f, nrhs, stream=None) -> dict:
 
 def vsie_solve(h, f, prec, adjoint, b, x, tol=1e-10, max_iter=3000, restart=500, inner_tol=1e-5,
                max_outer=20, block=False, stream=None, allow_noconv=False, relax=0.0, progress=False,
-               workspace=None):
+               workspace=None, krylov_gib=0):
     """Solve in place into x (initial guess on entry).  Returns SolveInfo as a dict
     plus the status."""
     n = vsie_size(h)
@@ -353,7 +355,7 @@ def vsie_solve(h, f, prec, adjoint, b, x, tol=1e-10, max_iter=3000, restart=500,
     px, Rx, ldx = _cols(x, n)
     if Rx != R:
         raise ValueError("b and x hold different numbers of columns")
-    o = _opts(tol, max_iter, restart, inner_tol, max_outer, block, relax, progress)
+    o = _opts(tol, max_iter, restart, inner_tol, max_outer, block, relax, progress, krylov_gib)
     info = SolveInfo()
     st = _check(lib.vsie_solve(h, f, prec, int(adjoint), R, pb, ldb, px, ldx, ctypes.byref(o),
                                ctypes.byref(info), *_ws(workspace), _stream(stream)),
@@ -364,7 +366,8 @@ def vsie_solve(h, f, prec, adjoint, b, x, tol=1e-10, max_iter=3000, restart=500,
 
 
 def vsie_solve_multi(h, f0, nf, prec, b, x, tol=1e-10, max_iter=3000, restart=500, inner_tol=1e-5,
-                     max_outer=20, stream=None, allow_noconv=False, progress=False, workspace=None):
+                     max_outer=20, stream=None, allow_noconv=False, progress=False, workspace=None,
+                     krylov_gib=0):
     """Solve the nf frequencies f0 .. f0 + nf - 1 in lockstep, in place into x
     (initial guess on entry).  b, x: (nf * R, n) -- rows t R .. t R + R - 1
     belong to frequency f0 + t.  Returns one SolveInfo dict per frequency and
@@ -374,7 +377,7 @@ def vsie_solve_multi(h, f0, nf, prec, b, x, tol=1e-10, max_iter=3000, restart=50
     px, Cx, ldx = _cols(x, n)
     if Cx != C or C % nf:
         raise ValueError("b and x must hold nf blocks of equally many columns")
-    o = _opts(tol, max_iter, restart, inner_tol, max_outer, True, 0.0, progress)
+    o = _opts(tol, max_iter, restart, inner_tol, max_outer, True, 0.0, progress, krylov_gib)
     infos = (SolveInfo * nf)()
     st = _check(lib.vsie_solve_multi(h, f0, nf, prec, C // nf, pb, ldb, px, ldx, ctypes.byref(o), infos,
                                      *_ws(workspace), _stream(stream)),

@@ -198,6 +198,7 @@ struct vsie_problem {
     Scratch V, V2, w, r, ax, h1, tc, nrm, dpart, npart, yv, act, act2, live, kd, kc, xa, axa, rres, brc;
     Scratch defP, defM, defB, defk, lslot;  // deflation of GMRES cycles (gmres_cycle)
     Scratch bh, bg, bsk;  // block GMRES: Hessenberg block column, Gram / inverse factor, slab partials
+    Scratch bqk, bbm, bzt;  // block deflation: Q E of each kept space, C^H A V per cycle, coefficients
     HostPinned hpin;      // per-iteration Hessenberg columns and norms on their way to the host
     int progress = 0;     // vsie_solve_opts::progress of the running solve
     PairProfiler prof;
@@ -296,7 +297,7 @@ struct vsie_problem {
         for (void *p : owned) (void)hipFree(p);
         for (Scratch *s : {&partial, &chargeG, &chargeF, &chargeAll, &sums_part, &grad_work, &V, &V2, &w, &r, &ax,
                            &h1, &tc, &nrm, &dpart, &npart, &yv, &act, &act2, &live, &kd, &kc, &xa, &axa, &brc,
-                           &rres, &bh, &bg, &bsk, &defP, &defM, &defB, &defk, &lslot, &ctile,
+                           &rres, &bh, &bg, &bsk, &bqk, &bbm, &bzt, &defP, &defM, &defB, &defk, &lslot, &ctile,
                            &ftile, &fzero})
             s->release();
     }
@@ -1323,7 +1324,12 @@ void to_device(T *d, const std::vector<T> &h, hipStream_t s) {
     VSIE_HIP(hipStreamSynchronize(s));  // h may change right after
 }
 
-constexpr int64_t kKrylovBytes = int64_t(96) << 30;  // cap on the two Krylov bases (96 GiB of the 288 GB)
+// Cap on the two Krylov bases together: vsie_solve_opts.krylov_gib GiB, by
+// default 96 GiB of the 288 GB (room for c2's 108.5 GB assembled operator).
+constexpr int64_t kKrylovDefaultGiB = 96;
+int64_t krylov_bytes(const vsie_solve_opts &o) {
+    return (o.krylov_gib > 0 ? static_cast<int64_t>(o.krylov_gib) : kKrylovDefaultGiB) << 30;
+}
 
 int norm_chunks(int64_t n) { return static_cast<int>(std::min<int64_t>(256, std::max<int64_t>(1, n / 2048))); }
 
@@ -1756,49 +1762,62 @@ int gmres_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
 // cycles (block GCRO, as Recycle for one column): the block Arnoldi relation
 // A V_k = V_{k+Ra} Hbar with Hbar = Q R by the cycle's Householder reflectors
 // gives C = V_{k+Ra} Q(:, 0:k) (orthonormal) and U = V_k R^{-1} with A U = C.
-// Kept only while k <= kBlockRecycleMax: the deflation runs on the host at
-// O(k (Ra + 1)) per column and step (16 threads), and R^{-1} at O(k^2) per column.
+// Kept only while k <= kBlockRecycleMax: Q(:, 0:k) is formed once on the host
+// (O(k^2 (Ra + 1)), 16 threads) and held on the device ((k + Ra) k complex),
+// and R^{-1} runs on the host at O(k^2) per column once per cycle.
 constexpr int64_t kBlockRecycleMax = 4096;
 
 struct BlockRecycle {
     const double2 *V = nullptr;  // basis of the recycled cycle: n x (k + Ra)
     int Ra = 0;                  // block width of that cycle
     int64_t k = 0;               // columns of U and C (0: nothing kept)
-    std::vector<cd> U;           // reflector of column c at c (Ra + 1), rows c .. c + Ra
-    std::vector<double> UU;
-    std::vector<cd> R;           // k x k upper triangle, column-major
-
-    void qh(std::vector<cd> &t) const;               // t <- Q^H t (length k + Ra)
-    void q(std::vector<cd> &v) const;                // v <- Q v (length k + Ra)
-    std::vector<cd> r_solve(const std::vector<cd> &z) const;  // R^{-1} z (length k)
-    // coefficients of the deflation of the n x Ra2 block W (on the stream):
-    // Dd <- V^H W ((k + Ra) x Ra2) on the device; on the host per column
-    // z = C^H w (k entries, returned column-major) and the coefficients
-    // Q [z; 0] of C z in the basis V (written to Dd, (k + Ra) x Ra2)
-    std::vector<cd> deflate_coeffs(vsie_problem *p, int64_t n, int Ra2, const double2 *W, double2 *Dd,
-                                   hipStream_t s) const;
+    std::vector<cd> R;           // k x k upper triangle, column-major (host)
+    // Q E on the device ((k + Ra) x k, column-major): the first k columns of
+    // the product of the cycle's Householder reflectors, so that C = V (Q E)
+    // and every deflation is three GEMMs on the device
+    double2 *Qk = nullptr;
 };
 int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const std::vector<int32_t> &rhs,
                 double2 *Rres, const std::vector<double> &rn, const std::vector<double> &ctol, int m,
                 int iter_cap, double2 *x, int64_t ldx, SolveCounters &cnt, hipStream_t s, double2 *V,
-                BlockRecycle *save, const BlockRecycle *use);
+                BlockRecycle *save, const BlockRecycle *use, double2 *Bm, double2 *qk);
+
+// Device memory of the block deflation for block widths up to R with
+// steps(Ra) block steps per cycle of width Ra: the Q E of one kept space
+// (qk bytes), the C^H A V of one cycle (bm bytes) and the per-pass
+// coefficients (zt bytes).  A kept space has at most kcap columns.
+struct DeflateCaps {
+    int64_t kcap = 0, jmax = 0;
+    size_t qk = 0, bm = 0, zt = 0;
+};
+DeflateCaps deflate_caps(int R, const std::function<int(int)> &steps) {
+    DeflateCaps c;
+    for (int Ra = 1; Ra <= R; ++Ra) c.jmax = std::max<int64_t>(c.jmax, static_cast<int64_t>(Ra) * steps(Ra));
+    c.kcap = std::min<int64_t>(c.jmax, kBlockRecycleMax);
+    const size_t z = sizeof(double2);
+    c.qk = z * static_cast<size_t>(c.kcap + R) * static_cast<size_t>(c.kcap);
+    c.bm = z * static_cast<size_t>(c.kcap) * static_cast<size_t>(c.jmax);
+    c.zt = z * static_cast<size_t>(c.kcap) * R;
+    return c;
+}
 
 // Restart length of the independent-GMRES path: as asked, but the two bases
-// of all R right-hand sides must fit kKrylovBytes.
-int gmres_restart(int64_t n, int R, int restart) {
+// of all R right-hand sides must fit the Krylov budget.
+int gmres_restart(int64_t n, int R, const vsie_solve_opts &o) {
     const int64_t col_bytes = static_cast<int64_t>(sizeof(double2)) * n * R;
     return static_cast<int>(std::max<int64_t>(
-        1, std::min<int64_t>(std::max(1, restart), kKrylovBytes / 2 / col_bytes - 1)));
+        1, std::min<int64_t>(std::max(1, o.restart), krylov_bytes(o) / 2 / col_bytes - 1)));
 }
 
 // Block steps per cycle of block GMRES with Ra columns: the requested restart,
 // but the host R factor of the block Hessenberg ((m Ra)^2 complex) stays near
-// 2 GB and the basis within the budget (half of kKrylovBytes each: the first
-// cycle's basis is kept to deflate the later ones).
-int block_restart(int64_t n, int Ra, int restart) {
+// 2 GB and the basis within the budget (half of the Krylov budget each: the
+// first cycle's basis is kept to deflate the later ones).
+int block_restart(int64_t n, int Ra, const vsie_solve_opts &o) {
     const int64_t mb_host = std::max<int64_t>(1, 11585 / Ra);
-    const int64_t mb_dev = std::max<int64_t>(1, kKrylovBytes / 2 / (static_cast<int64_t>(sizeof(double2)) * n * Ra) - 1);
-    return static_cast<int>(std::min<int64_t>({static_cast<int64_t>(std::max(1, restart)), mb_host, mb_dev}));
+    const int64_t mb_dev =
+        std::max<int64_t>(1, krylov_bytes(o) / 2 / (static_cast<int64_t>(sizeof(double2)) * n * Ra) - 1);
+    return static_cast<int>(std::min<int64_t>({static_cast<int64_t>(std::max(1, o.restart)), mb_host, mb_dev}));
 }
 
 // Solve op(A) x_r = b_r for r < R.  FP64: restarted GMRES(m), each restart
@@ -1811,10 +1830,12 @@ vsie_status solve_batch(vsie_problem *p, int f, vsie_precision prec, bool adjoin
                         hipStream_t s) {
     const int64_t n = p->m.n;
     const int64_t col_bytes = static_cast<int64_t>(sizeof(double2)) * n * R;
-    const int m = gmres_restart(n, R, o.restart);
+    const int m = gmres_restart(n, R, o);
     double2 *V1 = static_cast<double2 *>(p->V.get(static_cast<size_t>(col_bytes) * (m + 1)));
     Recycle first;            // space of the first cycle, deflates every later cycle
     BlockRecycle bfirst;      // the same for block GMRES
+    DeflateCaps dcaps;        // block GMRES: its device buffers (sized at the first block cycle)
+    double2 *bqk = nullptr, *bbm = nullptr;
     bool have_first = false;
     relres.assign(R, 0.0);
     std::vector<int32_t> all(R);
@@ -1889,16 +1910,21 @@ vsie_status solve_batch(vsie_problem *p, int f, vsie_precision prec, bool adjoin
         int done;
         if (o.block) {
             const int Ra = static_cast<int>(next.size());
-            const int mb = block_restart(n, Ra, o.restart);
+            const int mb = block_restart(n, Ra, o);
             const size_t vbytes = sizeof(double2) * static_cast<size_t>(n) * Ra * (mb + 1);
+            if (!dcaps.kcap) {
+                dcaps = deflate_caps(R, [&](int w) { return block_restart(n, w, o); });
+                bqk = static_cast<double2 *>(p->bqk.get(dcaps.qk));
+                bbm = static_cast<double2 *>(p->bbm.get(dcaps.bm));
+            }
             if (!have_first) {
                 done = block_cycle(p, f, prec, adjoint, next, cyc_res, next_rn, next_tol, mb, o.max_iter, x, ldx,
-                                   cnt, s, static_cast<double2 *>(p->V.get(vbytes)), &bfirst, nullptr);
+                                   cnt, s, static_cast<double2 *>(p->V.get(vbytes)), &bfirst, nullptr, nullptr, bqk);
                 have_first = true;
             } else {
                 done = block_cycle(p, f, prec, adjoint, next, cyc_res, next_rn, next_tol, mb, o.max_iter, x, ldx,
                                    cnt, s, static_cast<double2 *>(p->V2.get(vbytes)), nullptr,
-                                   bfirst.k > 0 ? &bfirst : nullptr);
+                                   bfirst.k > 0 ? &bfirst : nullptr, bbm, nullptr);
             }
         } else if (!have_first) {
             done = gmres_cycle(p, f, prec, adjoint, R, next, cyc_res, next_rn, next_tol, m, o.max_iter,
@@ -2110,13 +2136,16 @@ inline void apply_reflector(const cd *u, double uu, int len, cd *y) {
 // them.
 class BlockCycle {
   public:
-    BlockCycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, std::vector<int32_t> rhs, double2 *Rres,
+    // Bm: device C^H A V of this cycle (kr x m Ra, used when use holds a
+    // space); qk: device memory for the Q E of the space this cycle keeps in
+    // save (kBlockRecycleMax x (kBlockRecycleMax + Ra) at most)
+    BlockCycle(vsie_problem *p, int f, vsie_precision prec, std::vector<int32_t> rhs, double2 *Rres,
                std::vector<double> rn, std::vector<double> ctol, int m, int iter_cap, double2 *x, int64_t ldx,
                SolveCounters &cnt, hipStream_t s, double2 *V, double2 *W, BlockRecycle *save,
-               const BlockRecycle *use, bool report)
-        : p_(p), f_(f), prec_(prec), adjoint_(adjoint), rhs_(std::move(rhs)), Rres_(Rres), rn_(std::move(rn)),
+               const BlockRecycle *use, double2 *Bm, double2 *qk, bool report)
+        : p_(p), f_(f), prec_(prec), rhs_(std::move(rhs)), Rres_(Rres), rn_(std::move(rn)),
           ctol_(std::move(ctol)), m_(m), iter_cap_(iter_cap), x_(x), ldx_(ldx), cnt_(cnt), s_(s), V_(V), W_(W),
-          save_(save), use_(use), report_(report), n_(p->m.n), Ra_(static_cast<int>(rhs_.size())),
+          save_(save), use_(use), Bm_(Bm), qk_(qk), report_(report), n_(p->m.n), Ra_(static_cast<int>(rhs_.size())),
           ldH_(static_cast<int64_t>(m + 1) * Ra_), kr_(use ? use->k : 0), kv_(use ? use->k + use->Ra : 0) {}
 
     void begin();
@@ -2139,6 +2168,7 @@ class BlockCycle {
   private:
     using clk = std::chrono::steady_clock;
     double2 *Dd() const { return static_cast<double2 *>(p_->brc.get(sizeof(double2) * static_cast<size_t>(kv_) * Ra_)); }
+    double2 *Zt() const { return static_cast<double2 *>(p_->bzt.get(sizeof(double2) * static_cast<size_t>(kr_) * Ra_)); }
     int32_t *act() const {
         int32_t *a = static_cast<int32_t *>(p_->act.get(sizeof(int32_t) * Ra_));
         to_device(a, rhs_, s_);
@@ -2157,7 +2187,6 @@ class BlockCycle {
     vsie_problem *p_;
     int f_;
     vsie_precision prec_;
-    bool adjoint_;
     std::vector<int32_t> rhs_;
     double2 *Rres_;
     std::vector<double> rn_, ctol_;
@@ -2169,6 +2198,7 @@ class BlockCycle {
     double2 *V_, *W_;
     BlockRecycle *save_;
     const BlockRecycle *use_;
+    double2 *Bm_, *qk_;
     bool report_;
     int64_t n_;
     int Ra_;
@@ -2177,7 +2207,7 @@ class BlockCycle {
     // the block Hessenberg packed by columns and grown one block column per
     // step (the full (m Ra)^2 array would be several GB to zero), and one
     // Householder reflector per column (Ra + 1 long, at c (Ra + 1))
-    std::vector<cd> G_, Rf_, U_, Bm_;
+    std::vector<cd> G_, Rf_, U_;
     std::vector<double> UU_;
     int j_ = 0, jdone_ = 0;
     bool done_ = false;
@@ -2188,16 +2218,23 @@ class BlockCycle {
 void BlockCycle::begin() {
     if (!p_->blas) check_blas(rocblas_create_handle(&p_->blas), "rocblas_create_handle");
     check_blas(rocblas_set_stream(p_->blas, s_), "rocblas_set_stream");
-    // deflation by an earlier cycle's space: x += U C^H r, r -= C C^H r, and
-    // Bm = C^H A v for every new basis column (column-major, kr rows)
+    // deflation by an earlier cycle's space (C = V Qk, U = V_k R^{-1}):
+    // z = C^H r, r -= C z, x += U z; later Bm = C^H A v for every new basis
+    // column (column-major, kr rows, on the device)
     if (kr_ > 0) {
-        std::vector<cd> z = use_->deflate_coeffs(p_, n_, Ra_, Rres_, Dd(), s_);
-        zgemm(p_, false, n_, Ra_, kv_, -1.0, use_->V, n_, Dd(), kv_, 1.0, Rres_, n_);
+        double2 *D = Dd(), *Z = Zt();
+        zgemm_tall_cn(p_, kv_, Ra_, n_, use_->V, n_, Rres_, n_, D, kv_, s_);
+        zgemm(p_, true, kr_, Ra_, kv_, 1.0, use_->Qk, kv_, D, kv_, 0.0, Z, kr_);
+        zgemm(p_, false, kv_, Ra_, kr_, 1.0, use_->Qk, kv_, Z, kr_, 0.0, D, kv_);
+        zgemm(p_, false, n_, Ra_, kv_, -1.0, use_->V, n_, D, kv_, 1.0, Rres_, n_);
+        std::vector<double2> zh;
+        to_host(zh, Z, static_cast<size_t>(kr_) * Ra_, s_);
+        std::vector<cd> z(zh.size());
+        for (size_t q = 0; q < z.size(); ++q) z[q] = cd(zh[q].x, zh[q].y);
         tri_solve_upper_cols(use_->R.data(), kr_, kr_, Ra_, z.data());
-        std::vector<double2> yh(static_cast<size_t>(kr_) * Ra_);
-        for (size_t q = 0; q < yh.size(); ++q) yh[q] = make_double2(z[q].real(), z[q].imag());
-        to_device(Dd(), yh, s_);
-        zgemm(p_, false, n_, Ra_, kr_, 1.0, use_->V, n_, Dd(), kr_, 0.0, W_, n_);
+        for (size_t q = 0; q < z.size(); ++q) zh[q] = make_double2(z[q].real(), z[q].imag());
+        to_device(D, zh, s_);
+        zgemm(p_, false, n_, Ra_, kr_, 1.0, use_->V, n_, D, kr_, 0.0, W_, n_);
         blas_scatter_add(n_, Ra_, act(), W_, x_, ldx_, s_);
     }
     std::vector<cd> S0;
@@ -2222,12 +2259,20 @@ void BlockCycle::after_product() {
     std::vector<double2> hh;
     for (int pass = 0; pass < 2; ++pass) {
         if (kr > 0) {
-            const std::vector<cd> z = use_->deflate_coeffs(p_, n, Ra, W, Dd(), s_);
-            Bm_.resize(static_cast<size_t>(j + 1) * Ra * kr, 0.0);
-            for (int c = 0; c < Ra; ++c)
-                for (int64_t i = 0; i < kr; ++i)
-                    Bm_[(static_cast<size_t>(j) * Ra + c) * kr + i] += z[static_cast<size_t>(c) * kr + i];
-            zgemm(p_, false, n, Ra, kv, -1.0, use_->V, n, Dd(), kv, 1.0, W, n);
+            // D = V^H W, z = Qk^H D (summed over both passes into this step's
+            // block of Bm), W -= V (Qk z)
+            double2 *D = Dd();
+            double2 *Bj = Bm_ + static_cast<int64_t>(j) * Ra * kr;
+            zgemm_tall_cn(p_, kv, Ra, n, use_->V, n, W, n, D, kv, s_);
+            zgemm(p_, true, kr, Ra, kv, 1.0, use_->Qk, kv, D, kv, pass == 0 ? 0.0 : 1.0, Bj, kr);
+            const double2 *zp = Bj;
+            if (pass == 1) {
+                double2 *Z = Zt();
+                zgemm(p_, true, kr, Ra, kv, 1.0, use_->Qk, kv, D, kv, 0.0, Z, kr);
+                zp = Z;
+            }
+            zgemm(p_, false, kv, Ra, kr, 1.0, use_->Qk, kv, zp, kr, 0.0, D, kv);
+            zgemm(p_, false, n, Ra, kv, -1.0, use_->V, n, D, kv, 1.0, W, n);
         }
         double2 *Hd = static_cast<double2 *>(p_->bh.get(sizeof(double2) * static_cast<size_t>(ldH_) * Ra));
         zgemm_tall_cn(p_, kb, Ra, n, V_, n, W, n, Hd, kb, s_);
@@ -2300,23 +2345,20 @@ int BlockCycle::finish() {
         std::copy(G_.begin() + static_cast<size_t>(rc) * ldH_, G_.begin() + static_cast<size_t>(rc) * ldH_ + kk,
                   Ycol.begin() + static_cast<size_t>(rc) * kk);
     tri_solve_upper_cols_by([&](int64_t i) { return Rf_.data() + packed_col(i); }, kk, Ra, Ycol.data());
-    std::vector<double2> Yh(static_cast<size_t>(kk) * Ra), Wc(static_cast<size_t>(kr) * Ra);
+    std::vector<double2> Yh(static_cast<size_t>(kk) * Ra);
     for (size_t q = 0; q < Yh.size(); ++q) Yh[q] = make_double2(Ycol[q].real(), Ycol[q].imag());
+    double2 *Yd = static_cast<double2 *>(p_->bh.get(sizeof(double2) * static_cast<size_t>(std::max(kk, ldH_)) * Ra));
+    to_device(Yd, Yh, s_);
+    std::vector<double2> Wc;
     if (kr > 0) {
-        std::vector<cd> by(static_cast<size_t>(kr) * Ra, 0.0);
-        parallel_for(Ra, 8.0 * Ra * kk * kr, [&](int rc) {
-            cd *o = &by[static_cast<size_t>(rc) * kr];
-            for (int64_t t = 0; t < kk; ++t) {
-                const cd yt = Ycol[static_cast<size_t>(rc) * kk + t];
-                const cd *bm = &Bm_[static_cast<size_t>(t) * kr];
-                for (int64_t i = 0; i < kr; ++i) o[i] += bm[i] * yt;
-            }
-        });
+        double2 *Z = Zt();
+        zgemm(p_, false, kr, Ra, kk, 1.0, Bm_, kr, Yd, kk, 0.0, Z, kr);
+        to_host(Wc, Z, static_cast<size_t>(kr) * Ra, s_);
+        std::vector<cd> by(Wc.size());
+        for (size_t q = 0; q < by.size(); ++q) by[q] = cd(Wc[q].x, Wc[q].y);
         tri_solve_upper_cols(use_->R.data(), kr, kr, Ra, by.data());
         for (size_t q = 0; q < Wc.size(); ++q) Wc[q] = make_double2(by[q].real(), by[q].imag());
     }
-    double2 *Yd = static_cast<double2 *>(p_->bh.get(sizeof(double2) * static_cast<size_t>(std::max(kk, ldH_)) * Ra));
-    to_device(Yd, Yh, s_);
     zgemm(p_, false, n, Ra, kk, 1.0, V_, n, Yd, kk, 0.0, W_, n);
     if (kr > 0) {  // x += V y - U (Bm y)
         double2 *D = Dd();
@@ -2329,11 +2371,25 @@ int BlockCycle::finish() {
         save_->V = V_;
         save_->Ra = Ra;
         save_->k = kk;
-        save_->U.assign(U_.begin(), U_.begin() + static_cast<size_t>(kk) * (Ra + 1));
-        save_->UU.assign(UU_.begin(), UU_.begin() + kk);
         save_->R.assign(static_cast<size_t>(kk) * kk, 0.0);
         for (int64_t c = 0; c < kk; ++c)
             for (int64_t i = 0; i <= c; ++i) save_->R[static_cast<size_t>(c) * kk + i] = Rf_[packed_col(c) + i];
+        // Q E: column j is the reflectors j, j - 1, ..., 0 applied to e_j (the
+        // later ones act on rows below j, where e_j is zero)
+        const int64_t kv = kk + Ra;
+        std::vector<double2> qh(static_cast<size_t>(kv) * kk);
+        parallel_for(static_cast<int>(kk), 4.0 * kk * kk * (Ra + 1), [&](int j) {
+            std::vector<cd> v(kv, 0.0);
+            v[j] = 1.0;
+            for (int64_t c = j; c >= 0; --c)
+                apply_reflector(&U_[static_cast<size_t>(c) * (Ra + 1)], UU_[c], Ra + 1, &v[c]);
+            for (int64_t i = 0; i < kv; ++i)
+                qh[static_cast<size_t>(j) * kv + i] = make_double2(v[i].real(), v[i].imag());
+        });
+        to_device(qk_, qh, s_);
+        save_->Qk = qk_;
+    } else if (save_) {
+        save_->k = 0;
     }
     return jdone_;
 }
@@ -2343,11 +2399,11 @@ int BlockCycle::finish() {
 int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const std::vector<int32_t> &rhs,
                 double2 *Rres, const std::vector<double> &rn, const std::vector<double> &ctol, int m,
                 int iter_cap, double2 *x, int64_t ldx, SolveCounters &cnt, hipStream_t s, double2 *V,
-                BlockRecycle *save, const BlockRecycle *use) {
+                BlockRecycle *save, const BlockRecycle *use, double2 *Bm, double2 *qk) {
     const int64_t n = p->m.n;
     const int Ra = static_cast<int>(rhs.size());
     double2 *W = static_cast<double2 *>(p->w.get(sizeof(double2) * static_cast<size_t>(n) * Ra));
-    BlockCycle c(p, f, prec, adjoint, rhs, Rres, rn, ctol, m, iter_cap, x, ldx, cnt, s, V, W, save, use, true);
+    BlockCycle c(p, f, prec, rhs, Rres, rn, ctol, m, iter_cap, x, ldx, cnt, s, V, W, save, use, Bm, qk, true);
     c.begin();
     while (c.wants_product()) {
         const auto t0 = std::chrono::steady_clock::now();
@@ -2421,13 +2477,13 @@ int apply_items(vsie_problem *p, vsie_precision prec, const std::vector<ProdItem
 // Block steps per cycle when nf frequencies iterate together: their nf bases
 // share the Krylov budget of one solve (and the host R factor stays as in
 // block_restart).
-int multi_restart(int64_t n, int Ra, int restart, int nf) { return block_restart(n * nf, Ra, restart); }
+int multi_restart(int64_t n, int Ra, const vsie_solve_opts &o, int nf) { return block_restart(n * nf, Ra, o); }
 
 // Columns of one frequency's basis region: enough for any block width up to R.
-int64_t multi_basis_cols(int64_t n, int R, int restart, int nf) {
+int64_t multi_basis_cols(int64_t n, int R, const vsie_solve_opts &o, int nf) {
     int64_t vcols = 0;
     for (int Ra = 1; Ra <= R; ++Ra)
-        vcols = std::max<int64_t>(vcols, static_cast<int64_t>(Ra) * (multi_restart(n, Ra, restart, nf) + 1));
+        vcols = std::max<int64_t>(vcols, static_cast<int64_t>(Ra) * (multi_restart(n, Ra, o, nf) + 1));
     return vcols;
 }
 
@@ -2439,7 +2495,7 @@ void solve_multi_batch(vsie_problem *p, int f0, int nf, vsie_precision prec, int
     const int64_t n = p->m.n;
     const size_t z = sizeof(double2);
     const int64_t blk = n * R;  // one frequency's n x R block
-    const int64_t region = multi_basis_cols(n, R, o.restart, nf) * n;
+    const int64_t region = multi_basis_cols(n, R, o, nf) * n;
     double2 *Vb = static_cast<double2 *>(p->V.get(z * static_cast<size_t>(region) * nf));
     double2 *V2b = static_cast<double2 *>(p->V2.get(z * static_cast<size_t>(region) * nf));
     double2 *Wb = static_cast<double2 *>(p->w.get(z * static_cast<size_t>(blk) * nf));
@@ -2447,6 +2503,11 @@ void solve_multi_batch(vsie_problem *p, int f0, int nf, vsie_precision prec, int
     double2 *AX = static_cast<double2 *>(p->axa.get(z * static_cast<size_t>(blk) * nf));
     double2 *Rres = static_cast<double2 *>(p->rres.get(z * static_cast<size_t>(blk) * nf));
     double2 *tmp = static_cast<double2 *>(p->r.get(z * static_cast<size_t>(blk)));
+    const DeflateCaps dc = deflate_caps(R, [&](int Ra) { return multi_restart(n, Ra, o, nf); });
+    double2 *Qb = static_cast<double2 *>(p->bqk.get(dc.qk * nf));
+    double2 *Bb = static_cast<double2 *>(p->bbm.get(dc.bm * nf));
+    const int64_t qk_stride = static_cast<int64_t>(dc.qk / sizeof(double2));
+    const int64_t bm_stride = static_cast<int64_t>(dc.bm / sizeof(double2));
     int32_t *act = static_cast<int32_t *>(p->act2.get(sizeof(int32_t) * R));
     auto bcol = [&](int t) { return b + static_cast<int64_t>(t) * R * ldb; };
     auto xcol = [&](int t) { return x + static_cast<int64_t>(t) * R * ldx; };
@@ -2543,12 +2604,13 @@ void solve_multi_batch(vsie_problem *p, int f0, int nf, vsie_precision prec, int
             }
             for (int r : next[t]) cnt[t].outer[r]++;
             const int Ra = static_cast<int>(next[t].size());
-            const int mb = multi_restart(n, Ra, o.restart, nf);
+            const int mb = multi_restart(n, Ra, o, nf);
             double2 *V = (q.have_first ? V2b : Vb) + t * region;
-            cyc[t] = std::make_unique<BlockCycle>(p, f0 + t, prec, false, next[t], cyc_res, next_rn, next_tol, mb,
+            cyc[t] = std::make_unique<BlockCycle>(p, f0 + t, prec, next[t], cyc_res, next_rn, next_tol, mb,
                                                   o.max_iter, xcol(t), ldx, cnt[t], s, V, Wb + t * blk,
                                                   q.have_first ? nullptr : &q.first,
-                                                  q.have_first && q.first.k > 0 ? &q.first : nullptr, false);
+                                                  q.have_first && q.first.k > 0 ? &q.first : nullptr,
+                                                  Bb + t * bm_stride, Qb + t * qk_stride, false);
             cyc[t]->begin();
         }
         if (p->progress) {
@@ -2609,13 +2671,13 @@ void solve_multi_batch(vsie_problem *p, int f0, int nf, vsie_precision prec, int
 // Work buffers of solve_multi_batch: its own blocks and bases, every
 // multi-frequency or single product it can issue, and the block cycles'
 // shared buffers for every width up to R.
-void plan_block_cycles(vsie_problem *p, int R, const std::function<int(int)> &steps, WsPlan &pl);
+void plan_block_cycles(vsie_problem *p, int R, int nf, const std::function<int(int)> &steps, WsPlan &pl);
 
 void plan_solve_multi(vsie_problem *p, int f0, int nf, vsie_precision prec, int R, const vsie_solve_opts &o,
                       WsPlan &pl) {
     const int64_t n = p->m.n;
     const size_t z = sizeof(double2), blk = z * static_cast<size_t>(n) * R;
-    const int64_t region = multi_basis_cols(n, R, o.restart, nf) * n;
+    const int64_t region = multi_basis_cols(n, R, o, nf) * n;
     pl.need(p->V, z * static_cast<size_t>(region) * nf);
     pl.need(p->V2, z * static_cast<size_t>(region) * nf);
     for (Scratch *b : {&p->w, &p->xa, &p->axa, &p->rres}) pl.need(*b, blk * nf);
@@ -2628,50 +2690,7 @@ void plan_solve_multi(vsie_problem *p, int f0, int nf, vsie_precision prec, int 
             for (int len = 1; len <= nf; ++len) plan_multi(p, f0, len, pr, Ra, pl);
             for (int t = 0; t < nf; ++t) plan_op(p, f0 + t, pr, false, Ra, pl);
         }
-    plan_block_cycles(p, R, [&](int Ra) { return multi_restart(n, Ra, o.restart, nf); }, pl);
-}
-
-void BlockRecycle::qh(std::vector<cd> &t) const {
-    for (int64_t c = 0; c < k; ++c) apply_reflector(&U[static_cast<size_t>(c) * (Ra + 1)], UU[c], Ra + 1, &t[c]);
-}
-
-void BlockRecycle::q(std::vector<cd> &v) const {
-    for (int64_t c = k - 1; c >= 0; --c) apply_reflector(&U[static_cast<size_t>(c) * (Ra + 1)], UU[c], Ra + 1, &v[c]);
-}
-
-std::vector<cd> BlockRecycle::r_solve(const std::vector<cd> &z) const {
-    std::vector<cd> y(k);
-    for (int64_t i = k - 1; i >= 0; --i) {
-        cd acc = z[i];
-        for (int64_t t = i + 1; t < k; ++t) acc -= R[static_cast<size_t>(t) * k + i] * y[t];
-        const cd d = R[static_cast<size_t>(i) * k + i];
-        y[i] = d == 0.0 ? 0.0 : acc / d;
-    }
-    return y;
-}
-
-std::vector<cd> BlockRecycle::deflate_coeffs(vsie_problem *p, int64_t n, int Ra2, const double2 *W, double2 *Dd,
-                                             hipStream_t s) const {
-    const int64_t kv = k + Ra;
-    zgemm_tall_cn(p, kv, Ra2, n, V, n, W, n, Dd, kv, s);
-    std::vector<double2> th;
-    to_host(th, Dd, static_cast<size_t>(kv) * Ra2, s);
-    std::vector<cd> z(static_cast<size_t>(k) * Ra2);
-    std::vector<double2> vh(static_cast<size_t>(kv) * Ra2);
-    parallel_for(Ra2, 16.0 * Ra2 * kv * (Ra + 1), [&](int c) {
-        std::vector<cd> t(kv);
-        for (int64_t i = 0; i < kv; ++i) t[i] = cd(th[static_cast<size_t>(c) * kv + i].x, th[static_cast<size_t>(c) * kv + i].y);
-        qh(t);
-        std::vector<cd> v(kv, 0.0);
-        for (int64_t i = 0; i < k; ++i) {
-            z[static_cast<size_t>(c) * k + i] = t[i];
-            v[i] = t[i];
-        }
-        q(v);
-        for (int64_t i = 0; i < kv; ++i) vh[static_cast<size_t>(c) * kv + i] = make_double2(v[i].real(), v[i].imag());
-    });
-    to_device(Dd, vh, s);
-    return z;
+    plan_block_cycles(p, R, nf, [&](int Ra) { return multi_restart(n, Ra, o, nf); }, pl);
 }
 
 // The work buffers of solve_batch (either path) for R right-hand sides: upper
@@ -2692,7 +2711,7 @@ void plan_solve(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
         if (prec == VSIE_FP32) plan_op(p, f, VSIE_FP32, adjoint, nl, pl);
     }
     if (!o.block) {
-        const int m = gmres_restart(n, R, o.restart);
+        const int m = gmres_restart(n, R, o);
         const size_t ns = R, hs = m + 2, cs = m + 2;  // recycled dimensions are at most m
         pl.need(p->V, nR * (m + 1));
         pl.need(p->V2, nR * (m + 1));
@@ -2710,16 +2729,16 @@ void plan_solve(vsie_problem *p, int f, vsie_precision prec, bool adjoint, int R
     }
     int64_t vcols = 0;
     for (int Ra = 1; Ra <= R; ++Ra)
-        vcols = std::max<int64_t>(vcols, static_cast<int64_t>(Ra) * (block_restart(n, Ra, o.restart) + 1));
-    plan_block_cycles(p, R, [&](int Ra) { return block_restart(n, Ra, o.restart); }, pl);
+        vcols = std::max<int64_t>(vcols, static_cast<int64_t>(Ra) * (block_restart(n, Ra, o) + 1));
+    plan_block_cycles(p, R, 1, [&](int Ra) { return block_restart(n, Ra, o); }, pl);
     pl.need(p->V, z * static_cast<size_t>(n) * vcols);
     pl.need(p->V2, z * static_cast<size_t>(n) * vcols);
     pl.need(p->w, nR);
 }
 
 // The shared buffers of block cycles of every width up to R, steps(Ra) block
-// steps per cycle of width Ra.
-void plan_block_cycles(vsie_problem *p, int R, const std::function<int(int)> &steps, WsPlan &pl) {
+// steps per cycle of width Ra, and the deflation buffers of nf frequencies.
+void plan_block_cycles(vsie_problem *p, int R, int nf, const std::function<int(int)> &steps, WsPlan &pl) {
     const int64_t n = p->m.n;
     const size_t z = sizeof(double2);
     int64_t kmax = 0;
@@ -2738,15 +2757,20 @@ void plan_block_cycles(vsie_problem *p, int R, const std::function<int(int)> &st
     pl.need(p->brc, z * static_cast<size_t>(kv) * R);
     pl.need(p->ax, z * static_cast<size_t>(n) * R);
     pl.need(p->act, sizeof(int32_t) * R);
+    const DeflateCaps dc = deflate_caps(R, steps);
+    pl.need(p->bqk, dc.qk * nf);
+    pl.need(p->bbm, dc.bm * nf);
+    pl.need(p->bzt, dc.zt);
 }
 
 // Solver options with defaults, validated.
 vsie_solve_opts solve_options(const vsie_solve_opts *opts) {
-    vsie_solve_opts o{1e-10, 3000, 500, 1e-5, 20, 0, 0.0, 0};
+    vsie_solve_opts o{1e-10, 3000, 500, 1e-5, 20, 0, 0.0, 0, 0};
     if (opts) o = *opts;
     require(o.tol > 0 && o.max_iter >= 0 && o.restart >= 1 && o.restart <= 20000 && o.inner_tol > 0 &&
                 o.inner_tol < 1 && o.max_outer >= 1 && (o.block == 0 || o.block == 1) && o.relax >= 0 &&
-                o.relax < 1 && (o.progress == 0 || o.progress == 1),
+                o.relax < 1 && (o.progress == 0 || o.progress == 1) && o.krylov_gib >= 0 &&
+                o.krylov_gib <= 4096,
             "invalid solver options");
     return o;
 }

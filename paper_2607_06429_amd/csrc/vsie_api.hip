@@ -383,7 +383,10 @@ void validate_geometry(const vsie_geometry *g, const double *vrho, const double 
 
 // Rebuild the class lists (which elements carry a single-layer weight, which a
 // v' weight) from the device weights, and pack their coordinates and v'.
-void build_sources(vsie_problem *p) {
+// Returns whether anything a captured operator graph holds changed: a class
+// list (its device arrays and counts) or the grad-alpha tile flags (and with
+// them the XCD ranges of the kernels).  The weights are rewritten in place.
+bool build_sources(vsie_problem *p) {
     const int64_t n = p->m.n;
     const int nf = static_cast<int>(p->k0.size());
     std::vector<double> sp(static_cast<size_t>(n) * nf), vp(3 * static_cast<size_t>(n));
@@ -432,15 +435,18 @@ void build_sources(vsie_problem *p) {
     p->f_is_faces = static_cast<int64_t>(fi.size()) == p->m.n_srf && p->m.n_srf > 0 && fi[0] == p->m.n_vol;
     p->f_cells = 0;
     for (int32_t e : fi) p->f_cells += e < p->m.n_vol ? 1 : 0;
+    bool flags_changed = true;
     {
         const int64_t tiles = (p->m.n_vol + 63) / 64;
         std::vector<int32_t> flag(static_cast<size_t>(std::max<int64_t>(1, tiles)), 0);
         for (int64_t e = 0; e < p->m.n_vol; ++e)
             if (vp[e] != 0.0 || vp[n + e] != 0.0 || vp[2 * n + e] != 0.0) flag[static_cast<size_t>(e / 64)] = 1;
+        flags_changed = flag != p->ctile_h;
         void *d = p->ctile.get(sizeof(int32_t) * flag.size());
         VSIE_HIP(hipMemcpy(d, flag.data(), sizeof(int32_t) * flag.size(), hipMemcpyHostToDevice));
         p->ctile_h = flag;
-        for (auto &r : p->tranges) r.g = -1;
+        if (flags_changed)
+            for (auto &r : p->tranges) r.g = -1;
     }
     if (p->m.n_srf > 0 && !p->ftile.p) {
         const std::vector<int32_t> ones(static_cast<size_t>((p->m.n_srf + 63) / 64), 1);
@@ -505,6 +511,7 @@ void build_sources(vsie_problem *p) {
     }
     p->gi_built = gi;
     p->fi_built = fi;
+    return !keep_g || !keep_f || flags_changed;
 }
 
 void check_problem(const vsie_problem *p, int32_t f) {
@@ -2959,10 +2966,17 @@ vsie_status vsie_set_materials(vsie_problem *p, const double *vrho_dev, const do
         }
         launch_weights(p->m, p->d_k0, static_cast<int>(p->k0.size()), s);
         VSIE_HIP(hipStreamSynchronize(s));
-        build_sources(p);
+        const bool changed = build_sources(p);
         // assembled operators describe the old materials
-        for (auto &d : p->dense) d = vsie_problem::Dense{};
-        ++g_graph_epoch;
+        bool had_dense = false;
+        for (auto &d : p->dense) {
+            had_dense = had_dense || d.A != nullptr;
+            d = vsie_problem::Dense{};
+        }
+        // captured operator graphs stay valid while the source lists, their
+        // arrays and the tile flags are the same (the weights, the diagonal and
+        // v' are rewritten in place)
+        if (changed || had_dense) ++g_graph_epoch;
     });
 }
 

@@ -125,3 +125,24 @@ def test_backward_after_another_forward_uses_its_own_materials(V):
     loss2.backward()
     assert torch.isfinite(c2.grad).all()
     P.close()
+
+
+@pytest.mark.parametrize("bad", [dict(krylov_gib=-1), dict(krylov_gib=5000), dict(restart=0),
+                                 dict(inner_tol=1.0), dict(max_outer=0)])
+def test_invalid_solver_options_are_rejected(V, bad):
+    """Solver options outside their documented ranges are refused with
+    VSIE_E_INVALID before any work, by the one-frequency and the lockstep
+    multi-frequency solves and by the workspace query; x is left as given."""
+    import torch
+    mesh, mat, k0 = case("ragged")
+    P = V.Problem.from_mesh(mesh, mat, [k0, 1.5 * k0])
+    b = P.plane_wave(W.fibonacci_sphere(2))
+    x0 = torch.full_like(b, 0.25)
+    for call in (lambda: P.solve(b, x0=x0, **bad),
+                 lambda: P.solve_multi(torch.cat([b, b]).contiguous(), x0=torch.cat([x0, x0]), **bad),
+                 lambda: P.workspace_size(V.VSIE_OP_SOLVE, nrhs=2, **bad)):
+        with pytest.raises(V.VsieError) as e:
+            call()
+        assert e.value.status == V.VSIE_E_INVALID, bad
+    assert torch.all(x0 == 0.25)
+    P.close()

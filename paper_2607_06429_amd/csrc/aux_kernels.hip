@@ -566,6 +566,104 @@ __global__ void sum_slabs_kernel(int64_t m, int64_t cnt, int parts, const double
     C[j * ldc + i] = make_double2(sx, sy);
 }
 
+// Cholesky factor of a small Hermitian Gram matrix G = T^H T (r x r,
+// column-major, r <= kSmallChol), T upper triangular, in one workgroup: the
+// right-looking (outer-product) form, one pivot per step.  As the host
+// factorisation of block GMRES: a diagonal shift (0, then 1e-14 dmax, times
+// 100 up to 1e-4 dmax, dmax the largest diagonal entry) is added only when a
+// pivot is not safely positive.  Writes T, Ti = T^{-1} and, when Tprev is
+// given, Tout = T Tprev (all r x r column-major); status 0 on success, 1 for
+// a zero or non-finite block, 2 when no shift gives a positive factor (then
+// nothing else is written).
+__global__ __launch_bounds__(256) void small_chol_kernel(const double2 *__restrict__ G, int r,
+                                                         double2 *__restrict__ T, double2 *__restrict__ Ti,
+                                                         const double2 *__restrict__ Tprev,
+                                                         double2 *__restrict__ Tout, int *__restrict__ status) {
+    __shared__ double2 A[kSmallChol * kSmallChol];
+    __shared__ double2 U[kSmallChol * kSmallChol];
+    __shared__ int ok;
+    __shared__ double dmax_s;
+    const int tid = threadIdx.x, nt = blockDim.x, rr = r * r;
+    if (tid == 0) {
+        double d = 0.0;
+        for (int i = 0; i < r; ++i) d = fmax(d, G[i * r + i].x);
+        dmax_s = d;
+    }
+    __syncthreads();
+    const double dmax = dmax_s;
+    if (!(dmax > 0.0) || !isfinite(dmax)) {
+        if (tid == 0) *status = 1;
+        return;
+    }
+    for (double shift = 0.0;; shift = shift == 0.0 ? 1e-14 * dmax : shift * 100.0) {
+        if (shift > 1e-4 * dmax) {
+            if (tid == 0) *status = 2;
+            return;
+        }
+        for (int e = tid; e < rr; e += nt) {
+            A[e] = G[e];
+            U[e] = make_double2(0.0, 0.0);
+        }
+        if (tid == 0) ok = 1;
+        __syncthreads();
+        for (int k = 0; k < r; ++k) {
+            if (tid == 0) {
+                const double akk = A[k * r + k].x + shift;
+                if (akk > 1e-15 * dmax) U[k * r + k] = make_double2(sqrt(akk), 0.0);
+                else ok = 0;
+            }
+            __syncthreads();
+            if (!ok) break;
+            const double ukk = U[k * r + k].x;
+            for (int j = k + 1 + tid; j < r; j += nt) {  // row k: U(k, j) = A(k, j) / U(k, k)
+                const double2 a = A[j * r + k];
+                U[j * r + k] = make_double2(a.x / ukk, a.y / ukk);
+            }
+            __syncthreads();
+            for (int e = tid; e < rr; e += nt) {  // A(i, j) -= conj(U(k, i)) U(k, j), k < i <= j
+                const int j = e / r, i = e - j * r;
+                if (i > k && i <= j) {
+                    const double2 ui = U[i * r + k], uj = U[j * r + k];
+                    A[e].x -= ui.x * uj.x + ui.y * uj.y;
+                    A[e].y -= ui.x * uj.y - ui.y * uj.x;
+                }
+            }
+            __syncthreads();
+        }
+        if (ok) break;
+        __syncthreads();
+    }
+    for (int e = tid; e < rr; e += nt) T[e] = U[e];
+    if (tid < r) {  // column j of T^{-1} by back substitution (into A, no longer needed)
+        const int j = tid;
+        double2 *x = A + j * r;
+        for (int i = j; i >= 0; --i) {
+            double sx = i == j ? 1.0 : 0.0, sy = 0.0;
+            for (int m = i + 1; m <= j; ++m) {
+                const double2 u = U[m * r + i];
+                sx -= u.x * x[m].x - u.y * x[m].y;
+                sy -= u.x * x[m].y + u.y * x[m].x;
+            }
+            const double d = U[i * r + i].x;
+            x[i] = make_double2(sx / d, sy / d);
+        }
+        for (int i = 0; i < r; ++i) Ti[j * r + i] = i <= j ? x[i] : make_double2(0.0, 0.0);
+    }
+    if (Tprev) {
+        for (int e = tid; e < rr; e += nt) {  // Tout(i, j) = sum_{i <= m <= j} U(i, m) Tprev(m, j)
+            const int j = e / r, i = e - j * r;
+            double sx = 0.0, sy = 0.0;
+            for (int m = i; m <= j; ++m) {
+                const double2 u = U[m * r + i], t = Tprev[j * r + m];
+                sx += u.x * t.x - u.y * t.y;
+                sy += u.x * t.y + u.y * t.x;
+            }
+            Tout[e] = make_double2(sx, sy);
+        }
+    }
+    if (tid == 0) *status = 0;
+}
+
 }  // namespace
 
 #define LAUNCH_CHECK() VSIE_HIP(hipGetLastError())
@@ -793,6 +891,13 @@ void blas_scatter_add(int64_t n, int nslots, const int32_t *act, const double2 *
                       hipStream_t s) {
     if (nslots == 0 || n == 0) return;
     hipLaunchKernelGGL(scatter_add_kernel, dim3(blocks_for(n), nslots), dim3(kT), 0, s, n, act, W, x, ldx);
+    LAUNCH_CHECK();
+}
+
+void launch_small_chol(const double2 *G, int r, double2 *T, double2 *Ti, const double2 *Tprev, double2 *Tout,
+                       int *status, hipStream_t s) {
+    if (r < 1 || r > kSmallChol) fail(VSIE_E_INVALID, "small Cholesky: block width out of range");
+    hipLaunchKernelGGL(small_chol_kernel, dim3(1), dim3(256), 0, s, G, r, T, Ti, Tprev, Tout, status);
     LAUNCH_CHECK();
 }
 

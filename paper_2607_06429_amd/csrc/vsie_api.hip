@@ -199,6 +199,7 @@ struct vsie_problem {
     Scratch defP, defM, defB, defk, lslot;  // deflation of GMRES cycles (gmres_cycle)
     Scratch bh, bg, bsk;  // block GMRES: Hessenberg block column, Gram / inverse factor, slab partials
     Scratch bqk, bbm, bzt;  // block deflation: Q E of each kept space, C^H A V per cycle, coefficients
+    Scratch bst;            // block steps of small width: the coefficients of a step, copied at once
     HostPinned hpin;      // per-iteration Hessenberg columns and norms on their way to the host
     int progress = 0;     // vsie_solve_opts::progress of the running solve
     PairProfiler prof;
@@ -297,7 +298,7 @@ struct vsie_problem {
         for (void *p : owned) (void)hipFree(p);
         for (Scratch *s : {&partial, &chargeG, &chargeF, &chargeAll, &sums_part, &grad_work, &V, &V2, &w, &r, &ax,
                            &h1, &tc, &nrm, &dpart, &npart, &yv, &act, &act2, &live, &kd, &kc, &xa, &axa, &brc,
-                           &rres, &bh, &bg, &bsk, &bqk, &bbm, &bzt, &defP, &defM, &defB, &defk, &lslot, &ctile,
+                           &rres, &bh, &bg, &bsk, &bqk, &bbm, &bzt, &bst, &defP, &defM, &defB, &defk, &lslot, &ctile,
                            &ftile, &fzero})
             s->release();
     }
@@ -2103,6 +2104,32 @@ void cholqr2(vsie_problem *p, int64_t n, int r, const double2 *Wsrc, double2 *tm
         }
 }
 
+// CholeskyQR2 of the n x r block Wsrc entirely on the device (r <= kSmallChol):
+// dst = Wsrc T^{-1}; T = T2 T1 goes to Tdev (r x r) and the two passes'
+// status words to status[0], status[1] (0: factorised; see small_chol_kernel).
+// Nothing is copied to the host: the caller reads T and the status together
+// with the step's other coefficients.
+void cholqr2_dev(vsie_problem *p, int64_t n, int r, const double2 *Wsrc, double2 *tmp, double2 *dst, double2 *Tdev,
+                 int *status, hipStream_t s) {
+    const int64_t rr = static_cast<int64_t>(r) * r;
+    double2 *buf = static_cast<double2 *>(p->bg.get(sizeof(double2) * static_cast<size_t>(5 * rr)));
+    double2 *G = buf, *T1 = buf + rr, *Ti = buf + 2 * rr, *T2 = buf + 3 * rr;
+    zgemm_tall_cn(p, r, r, n, Wsrc, n, Wsrc, n, G, r, s);
+    launch_small_chol(G, r, T1, Ti, nullptr, nullptr, status, s);
+    zgemm(p, false, n, r, r, 1.0, Wsrc, n, Ti, r, 0.0, tmp, n);
+    zgemm_tall_cn(p, r, r, n, tmp, n, tmp, n, G, r, s);
+    launch_small_chol(G, r, T2, Ti, T1, Tdev, status + 1, s);
+    zgemm(p, false, n, r, r, 1.0, tmp, n, Ti, r, 0.0, dst, n);
+}
+
+// The host's reading of the two status words of cholqr2_dev.
+void check_chol_status(const int *st) {
+    for (int q = 0; q < 2; ++q) {
+        if (st[q] == 1) fail(VSIE_E_NAN, "block QR: zero or non-finite block");
+        if (st[q] != 0) fail(VSIE_E_NAN, "block QR: Cholesky failed");
+    }
+}
+
 // Householder reflector P = I - 2 u u^H / (u^H u) with P x = alpha e_1; u overwrites x.
 // Returns u^H u (0 when x = 0: P = I).
 double make_reflector(cd *x, int len, cd &alpha) {
@@ -2141,6 +2168,12 @@ inline void apply_reflector(const cd *u, double uu, int len, cd *y) {
 // the column index array) are taken from the problem at each use, so cycles
 // of several frequencies advanced one after another on one stream can share
 // them.
+// Entries (double2) of the per-step stage of small-block cycles: two
+// Gram-Schmidt coefficient blocks, the R block and the status words.
+inline size_t stage_len(int64_t ldH, int Ra) {
+    return static_cast<size_t>(2 * ldH * Ra + static_cast<int64_t>(Ra) * Ra + 1);
+}
+
 class BlockCycle {
   public:
     // Bm: device C^H A V of this cycle (kr x m Ra, used when use holds a
@@ -2176,6 +2209,13 @@ class BlockCycle {
     using clk = std::chrono::steady_clock;
     double2 *Dd() const { return static_cast<double2 *>(p_->brc.get(sizeof(double2) * static_cast<size_t>(kv_) * Ra_)); }
     double2 *Zt() const { return static_cast<double2 *>(p_->bzt.get(sizeof(double2) * static_cast<size_t>(kr_) * Ra_)); }
+    // small blocks: both Gram-Schmidt passes' coefficients (ldH_ x Ra each),
+    // the new R block (Ra x Ra) and two status words, brought to the host in
+    // one copy per step
+    bool dev_qr() const { return Ra_ <= kSmallChol; }
+    double2 *stage() const {
+        return static_cast<double2 *>(p_->bst.get(sizeof(double2) * stage_len(ldH_, Ra_)));
+    }
     int32_t *act() const {
         int32_t *a = static_cast<int32_t *>(p_->act.get(sizeof(int32_t) * Ra_));
         to_device(a, rhs_, s_);
@@ -2246,7 +2286,18 @@ void BlockCycle::begin() {
     }
     std::vector<cd> S0;
     double2 *Z = static_cast<double2 *>(p_->ax.get(sizeof(double2) * static_cast<size_t>(n_) * Ra_));
-    cholqr2(p_, n_, Ra_, Rres_, Z, V_, S0, s_);
+    if (dev_qr()) {
+        const int64_t rr = static_cast<int64_t>(Ra_) * Ra_;
+        double2 *st = stage();
+        cholqr2_dev(p_, n_, Ra_, Rres_, Z, V_, st, reinterpret_cast<int *>(st + rr), s_);
+        std::vector<double2> h;
+        to_host(h, st, static_cast<size_t>(rr + 1), s_);
+        check_chol_status(reinterpret_cast<const int *>(h.data() + rr));
+        S0.resize(static_cast<size_t>(rr));
+        for (int64_t q = 0; q < rr; ++q) S0[q] = cd(h[q].x, h[q].y);
+    } else {
+        cholqr2(p_, n_, Ra_, Rres_, Z, V_, S0, s_);
+    }
     G_.assign(static_cast<size_t>(ldH_) * Ra_, 0.0);
     for (int c = 0; c < Ra_; ++c)
         for (int i = 0; i <= c; ++i) G_[static_cast<size_t>(c) * ldH_ + i] = S0[static_cast<size_t>(c) * Ra_ + i];
@@ -2281,6 +2332,12 @@ void BlockCycle::after_product() {
             zgemm(p_, false, kv, Ra, kr, 1.0, use_->Qk, kv, zp, kr, 0.0, D, kv);
             zgemm(p_, false, n, Ra, kv, -1.0, use_->V, n, D, kv, 1.0, W, n);
         }
+        if (dev_qr()) {  // this pass's coefficients stay in the stage until the step's one copy
+            double2 *Hd = stage() + static_cast<int64_t>(pass) * kb * Ra;
+            zgemm_tall_cn(p_, kb, Ra, n, V_, n, W, n, Hd, kb, s_);
+            zgemm(p_, false, n, Ra, kb, -1.0, V_, n, Hd, kb, 1.0, W, n);
+            continue;
+        }
         double2 *Hd = static_cast<double2 *>(p_->bh.get(sizeof(double2) * static_cast<size_t>(ldH_) * Ra));
         zgemm_tall_cn(p_, kb, Ra, n, V_, n, W, n, Hd, kb, s_);
         zgemm(p_, false, n, Ra, kb, -1.0, V_, n, Hd, kb, 1.0, W, n);
@@ -2292,7 +2349,22 @@ void BlockCycle::after_product() {
     mark(tm, 1);
     std::vector<cd> T;
     double2 *Z = static_cast<double2 *>(p_->ax.get(sizeof(double2) * static_cast<size_t>(n) * Ra));
-    cholqr2(p_, n, Ra, W, Z, V_ + kb * n, T, s_);
+    if (dev_qr()) {
+        const int64_t hb = kb * Ra, rr = static_cast<int64_t>(Ra) * Ra;
+        double2 *st = stage();
+        cholqr2_dev(p_, n, Ra, W, Z, V_ + kb * n, st + 2 * hb, reinterpret_cast<int *>(st + 2 * hb + rr), s_);
+        to_host(hh, st, static_cast<size_t>(2 * hb + rr + 1), s_);
+        check_chol_status(reinterpret_cast<const int *>(hh.data() + 2 * hb + rr));
+        for (int c = 0; c < Ra; ++c)
+            for (int64_t i = 0; i < kb; ++i) {
+                const double2 a = hh[c * kb + i], b = hh[hb + c * kb + i];
+                Hc[static_cast<size_t>(c) * (kb + Ra) + i] = cd(a.x + b.x, a.y + b.y);
+            }
+        T.resize(static_cast<size_t>(rr));
+        for (int64_t q = 0; q < rr; ++q) T[q] = cd(hh[2 * hb + q].x, hh[2 * hb + q].y);
+    } else {
+        cholqr2(p_, n, Ra, W, Z, V_ + kb * n, T, s_);
+    }
     mark(tm, 2);
     for (int c = 0; c < Ra; ++c)
         for (int i = 0; i <= c; ++i) Hc[static_cast<size_t>(c) * (kb + Ra) + kb + i] = T[static_cast<size_t>(c) * Ra + i];
@@ -2753,7 +2825,8 @@ void plan_block_cycles(vsie_problem *p, int R, int nf, const std::function<int(i
         const int mb = steps(Ra);
         kmax = std::max<int64_t>(kmax, static_cast<int64_t>(Ra) * mb);
         pl.need(p->bh, z * static_cast<size_t>(mb + 1) * Ra * Ra);
-        pl.need(p->bg, z * static_cast<size_t>(Ra) * Ra);
+        pl.need(p->bg, z * static_cast<size_t>(Ra) * Ra * (Ra <= kSmallChol ? 5 : 1));
+        if (Ra <= kSmallChol) pl.need(p->bst, z * stage_len(static_cast<int64_t>(mb + 1) * Ra, Ra));
         pl.need(p->bsk, tall_bytes(Ra, Ra, n));
         for (int j = 0; j < mb; ++j) pl.need(p->bsk, tall_bytes(static_cast<int64_t>(j + 1) * Ra, Ra, n));
     }

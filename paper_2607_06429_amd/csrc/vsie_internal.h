@@ -423,6 +423,12 @@ void blas_scatter_add(int64_t n, int nslots, const int32_t *act, const double2 *
                       hipStream_t s);
 // C (m x nn, leading dimension ldc) = sum of parts consecutive m x nn column-major slabs of P
 void blas_sum_slabs(int64_t m, int64_t nn, int parts, const double2 *P, double2 *C, int64_t ldc, hipStream_t s);
+// Cholesky factor G = T^H T of a Hermitian r x r Gram matrix on the device
+// (r <= kSmallChol, one workgroup), with T^{-1} and optionally T Tprev; see
+// small_chol_kernel for the shift and the status codes.
+constexpr int kSmallChol = 32;
+void launch_small_chol(const double2 *G, int r, double2 *T, double2 *Ti, const double2 *Tprev, double2 *Tout,
+                       int *status, hipStream_t s);
 void bblas_sub(int64_t n, int nslots, const int32_t *act, const double2 *b, int64_t ldb,
                const double2 *ax, double2 *out, hipStream_t s);
 

@@ -143,4 +143,11 @@ def test_workspace_size_argument_checks(V):
     assert st == V.VSIE_E_INVALID and b.value == 0
     st = V.lib.vsie_workspace_size(None, V.VSIE_OP_MATVEC, 0, 1, 0, 1, None, None)
     assert st == V.VSIE_E_INVALID
+    b.value = 5
+    st = V.lib.vsie_workspace_size(None, V.VSIE_OP_SOLVE_MULTI, 0, 2, 1, 16, None, ctypes.byref(b))
+    assert st == V.VSIE_E_INVALID and b.value == 0
+    assert V.VSIE_OP_SOLVE_MULTI == 5
+    # the solver options structure carries the Krylov budget after progress
+    names = [f[0] for f in V.SolveOpts._fields_]
+    assert names[-2:] == ["progress", "krylov_gib"]
     assert V._STATUS[V.VSIE_E_WORKSPACE] == "VSIE_E_WORKSPACE"

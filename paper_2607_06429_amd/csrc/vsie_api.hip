@@ -2148,12 +2148,28 @@ double make_reflector(cd *x, int len, cd &alpha) {
     return uu;
 }
 
+// y <- (I - 2 u u^H / uu) y for vectors of length len.  Written on the real
+// and imaginary parts (std::complex stores them interleaved) so that the
+// compiler vectorises both loops: the block QR applies thousands of these
+// per column and step.
 inline void apply_reflector(const cd *u, double uu, int len, cd *y) {
     if (uu == 0.0) return;
-    cd d = 0.0;
-    for (int i = 0; i < len; ++i) d += std::conj(u[i]) * y[i];
-    d *= 2.0 / uu;
-    for (int i = 0; i < len; ++i) y[i] -= d * u[i];
+    const double *ur = reinterpret_cast<const double *>(u);
+    double *yr = reinterpret_cast<double *>(y);
+    double sr = 0.0, si = 0.0;  // u^H y
+    for (int i = 0; i < len; ++i) {
+        const double a = ur[2 * i], b = ur[2 * i + 1], c = yr[2 * i], e = yr[2 * i + 1];
+        sr += a * c + b * e;
+        si += a * e - b * c;
+    }
+    const double f = 2.0 / uu;
+    sr *= f;
+    si *= f;
+    for (int i = 0; i < len; ++i) {
+        const double a = ur[2 * i], b = ur[2 * i + 1];
+        yr[2 * i] -= sr * a - si * b;
+        yr[2 * i + 1] -= sr * b + si * a;
+    }
 }
 
 // One block GMRES cycle for the right-hand sides rhs[0..Ra) with residual
@@ -2387,8 +2403,15 @@ void BlockCycle::after_product() {
         cd *rc_ = &Rf_[packed_col(c)];
         for (int64_t i = 0; i < c; ++i) rc_[i] = h[i];
         rc_[c] = UU_[c] == 0.0 ? h[c] : alpha;
-        for (int rc = 0; rc < Ra; ++rc) apply_reflector(u, UU_[c], Ra + 1, &G_[static_cast<size_t>(rc) * ldH_ + c]);
     }
+    // the same reflectors, in order, on the transformed right-hand sides
+    // (independent per column; they do not feed back into the reflectors)
+    parallel_for(Ra, 8.0 * Ra * Ra * (Ra + 1), [&](int rc) {
+        for (int cl = 0; cl < Ra; ++cl) {
+            const int64_t c = c0 + cl;
+            apply_reflector(&U_[static_cast<size_t>(c) * (Ra + 1)], UU_[c], Ra + 1, &G_[static_cast<size_t>(rc) * ldH_ + c]);
+        }
+    });
     mark(tm, 3);
     for (int r : rhs_) cnt_.it[r]++;
     jdone_ = j + 1;

@@ -63,12 +63,14 @@ def parse():
                          "wavenumbers --c4-freqs, FP32 operator in FP64 refinement to rel. residual 1e-10, "
                          "with the oracle's residual on sampled rows of every frequency (the solver "
                          "prints a progress line per block step on stderr)")
-    ap.add_argument("--c4-freqs", default="0-7", metavar="A-B",
-                    help="frequency indices of --c4-solve (k0 = 40 - 2 i), default all eight")
-    ap.add_argument("--krylov-gib", type=int, default=0,
+    ap.add_argument("--c4-freqs", default="0-1", metavar="A-B",
+                    help="frequency indices of --c4-solve (k0 = 40 - 2 i); default 0-1: two wavenumbers, "
+                         "about 9 minutes (0-1, 2-3, 4-5 and 6-7 cover all eight)")
+    ap.add_argument("--krylov-gib", type=int, default=200,
                     help="device memory of the Krylov bases of --c4-solve in GiB (0: the library default, "
                          "96); the frequencies share it, so the cycle length per frequency falls with "
-                         "their number")
+                         "their number: 200 GiB gives two wavenumbers 181 block steps per cycle, "
+                         "enough for k0 = 40 without a restart")
     ap.add_argument("--cpu-full", action="store_true",
                     help="also time the oracle's full FP64 GMRES solve of the headline workload "
                          "(several minutes on the host cores)")

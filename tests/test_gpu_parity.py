@@ -688,3 +688,24 @@ def test_relaxed_products_solve(V, name):
         infos.append(info)
     assert infos[1]["matvecs_fp64"] >= infos[0]["matvecs_fp64"]
     P.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_block_solve_with_dependent_right_hand_sides(V, prec):
+    """Block GMRES whose right-hand sides are linearly dependent: an exact
+    duplicate (the first block's Gram matrix is singular, so the Cholesky
+    factorisation of CholeskyQR needs its diagonal shift) and a column that
+    differs from another by 1e-9.  Every column must still reach the oracle's
+    LU solution."""
+    mesh, mat, k0 = case("ragged")
+    d = O.discretise(mesh, mat, k0)
+    b0 = O.plane_wave(d.pts, k0, W.fibonacci_sphere(3))
+    b = np.stack([b0[:, 0], b0[:, 1], b0[:, 0], b0[:, 2], b0[:, 1] + 1e-9 * W.seeded_complex(d.n, seed=96)], axis=1)
+    ref = O.solve_lu(d, b)
+    P = V.Problem.from_mesh(mesh, mat, [k0])
+    pr = V.VSIE_FP64 if prec == "fp64" else V.VSIE_FP32
+    x, info = P.solve(dev(b).contiguous(), prec=pr, tol=1e-10, block=True)
+    e = parity_err(host(x), ref)
+    say("  dependent columns, %s: %s, vs LU %.2e" % (prec, info, e))
+    assert info["status"] == V.VSIE_OK and e <= TOL_SOLVE
+    P.close()

@@ -66,6 +66,9 @@ def parse():
     ap.add_argument("--c4-freqs", default="0-1", metavar="A-B",
                     help="frequency indices of --c4-solve (k0 = 40 - 2 i); default 0-1: two wavenumbers, "
                          "about 9 minutes (0-1, 2-3, 4-5 and 6-7 cover all eight)")
+    ap.add_argument("--c4-fp64", action="store_true",
+                    help="--c4-solve with the plain FP64 operator (the FP64 matrix cores) instead of the "
+                         "FP32 operator in FP64 refinement")
     ap.add_argument("--krylov-gib", type=int, default=200,
                     help="device memory of the Krylov bases of --c4-solve in GiB (0: the library default, "
                          "96); the frequencies share it, so the cycle length per frequency falls with "
@@ -188,7 +191,7 @@ def matrix_core_issue(st, tuning, widths):
     return out
 
 
-def c4_block_solve(V, W, freqs, checks, krylov_gib=0):
+def c4_block_solve(V, W, freqs, checks, krylov_gib=0, fp64=False):
     """The largest configuration in its batched form: 16 plane waves at each
     wavenumber of freqs solved together by the lockstep multi-frequency block
     GMRES (FP32 operator on the matrix cores inside FP64 refinement, to
@@ -205,7 +208,8 @@ def c4_block_solve(V, W, freqs, checks, krylov_gib=0):
     torch.cuda.synchronize()
     P.profile(True)
     t0 = time.perf_counter()
-    X, infos = P.solve_multi(B, f0=f0, nf=nf, prec=V.VSIE_FP32, tol=TOL, progress=True, krylov_gib=krylov_gib)
+    prec = V.VSIE_FP64 if fp64 else V.VSIE_FP32
+    X, infos = P.solve_multi(B, f0=f0, nf=nf, prec=prec, tol=TOL, progress=True, krylov_gib=krylov_gib)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st = P.kernel_stats()
@@ -220,8 +224,9 @@ def c4_block_solve(V, W, freqs, checks, krylov_gib=0):
     P.close()
     return {"c4_lockstep_solve": {
         "workload": "cube with ellipsoid, 100^3 grid, n=%d, k0 = %s, %d plane waves each; lockstep "
-                    "multi-frequency block GMRES, FP32 operator (matrix cores) in FP64 refinement to "
-                    "rel. residual 1e-10; Krylov budget %s GiB" % (mesh.n, k0s[f0:f1 + 1], R, krylov_gib or 96),
+                    "multi-frequency block GMRES, %s to rel. residual 1e-10; Krylov budget %s GiB"
+                    % (mesh.n, k0s[f0:f1 + 1], R, "plain FP64 operator (FP64 matrix cores)" if fp64 else
+                       "FP32 operator (matrix cores) in FP64 refinement", krylov_gib or 96),
         "solve_s": dt, "per_frequency": dict(zip(["%g" % k for k in k0s[f0:f1 + 1]], infos)),
         "gpair_col_evals_per_s": float(mesh.n) * mesh.n * (mv32 + mv64) / dt / 1e9,
         "pair_kernels": {k: {"launches": v["launches"], "ms": v["ms"]} for k, v in st.items()},
@@ -641,7 +646,7 @@ def main():
     checks = []
     if args.c4_solve:
         f0, f1 = (int(v) for v in args.c4_freqs.split("-"))
-        res = c4_block_solve(V, W, (f0, f1), checks, args.krylov_gib)
+        res = c4_block_solve(V, W, (f0, f1), checks, args.krylov_gib, args.c4_fp64)
         res["cpu_baseline"] = {"kind": "oracle", "oracle_checks": cpu_baseline_checks(checks)}
         print(json.dumps(res), flush=True)
         return

@@ -188,7 +188,11 @@ typedef struct {
                                   single-layer source, the cell-cell single layer runs
                                   once per unordered pair (e_ij = e_ji), in work items
                                   of sym_groups x sym_groups 64-cell tiles; 0 = off,
-                                  2, 4 or 8; default 4 */
+                                  2, 4 or 8; default 4.  Each cell keeps one partial
+                                  sum per partner group: the group size is doubled
+                                  (up to 8) while these would exceed 8 GiB at the
+                                  FP64 size, and above 64 GiB the one-sided kernels
+                                  run instead */
     int32_t cell_face;         /* with sym_groups on: the cell-face pairs also run
                                   once per pair (single layer and adjoint double
                                   layer of the cell at the face, double layer of the

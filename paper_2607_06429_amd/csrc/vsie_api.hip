@@ -623,12 +623,39 @@ SlotBuffers slot_buffers(vsie_problem *p, vsie_precision prec, std::initializer_
 // cells), cell-face kernel (single layer at faces, double layers at cells),
 // face-face double layers on the symmetric kernel, one reduction.
 
+// The once-per-pair kernels write one partial per point and partner group:
+// about n_cells^2 / (64 G) for the cell-cell pairs.  The group size G is the
+// tuned one, doubled (up to 8) while the partials would exceed
+// kSymPartialSoft at the FP64 size: meshes that large have items enough for
+// bigger groups (at c1 size, groups of 8 leave too few items to fill the
+// chip).  Above kSymPartialCap (counted at the FP64 size) the one-sided
+// kernels are used.
+constexpr double kSymPartialSoft = 8.0 * (1 << 30);
+constexpr double kSymPartialCap = 64.0 * (1 << 30);
+constexpr int kFaceGroups = 1;
+
+// slot partials of a one-column product with cell groups of g tiles
+double sym_partial_entries(const vsie_problem *p, int g) {
+    const int64_t nv = p->m.n_vol, ns = p->m.n - nv;
+    double e = static_cast<double>(sym_slots(nv, g)) * nv;
+    if (p->tune.cell_face && ns > 0)
+        e += static_cast<double>(cf_groups(ns)) * nv + static_cast<double>(cf_groups(nv)) * ns +
+             static_cast<double>(sym_slots(ns, kFaceGroups)) * ns;
+    return e;
+}
+
+int sym_group(const vsie_problem *p) {
+    int g = p->tune.sym_groups;
+    while (g > 0 && g < 8 && sym_partial_entries(p, g) * sizeof(double2) > kSymPartialSoft) g *= 2;
+    return g;
+}
+
 // XCD item ranges of the once-per-pair kernels with grad-alpha cells, cached
 // per precision and group size.  Issue cycles per pair of the grad-alpha loops
 // relative to the single-layer ones (counted in the compiled loops):
 // symmetric kernel 1.53 (FP32) and 1.42 (FP64), cell-face kernel 1.17 and 1.42.
 const vsie_problem::TRanges &t_ranges(vsie_problem *p, vsie_precision prec) {
-    const int g = p->tune.sym_groups;
+    const int g = sym_group(p);
     vsie_problem::TRanges &tr = p->tranges[prec == VSIE_FP32 ? 1 : 0];
     if (tr.g != g) {
         const bool f32 = prec == VSIE_FP32;
@@ -642,10 +669,10 @@ const vsie_problem::TRanges &t_ranges(vsie_problem *p, vsie_precision prec) {
 // Face-face double layers once per pair: the symmetric kernel's grad-alpha
 // loop over the faces, with the faces' v' (zero where a face carries no jump)
 // and zero single-layer charges (forward) or weights (adjoint); every face
-// tile is flagged.  Group size 1 (one tile pair per item) gives enough work
-// items for the few face tiles: on 212 face tiles 0.140 ms in FP32, against
-// 0.159 ms with groups of 2 and 0.255 ms with groups of 4.
-constexpr int kFaceGroups = 1;
+// tile is flagged.  Group size 1 (one tile pair per item, kFaceGroups)
+// gives enough work items for the few face tiles: on 212 face tiles
+// 0.140 ms in FP32, against 0.159 ms with groups of 2 and 0.255 ms with
+// groups of 4.
 
 SymJob face_face_job(vsie_problem *p, vsie_precision prec, double k, const void *q, const double2 *xf, void *part) {
     const int64_t nv = p->m.n_vol, ns = p->m.n - nv;
@@ -668,7 +695,7 @@ struct CfCounts {
 };
 CfCounts cf_counts(const vsie_problem *p) {
     const int64_t nv = p->m.n_vol, ns = p->m.n - nv;
-    return CfCounts{sym_slots(nv, p->tune.sym_groups), cf_groups(ns), cf_groups(nv),
+    return CfCounts{sym_slots(nv, sym_group(p)), cf_groups(ns), cf_groups(nv),
                     ns > 0 ? sym_slots(ns, kFaceGroups) : 0};
 }
 size_t cf_slot_bytes(const vsie_problem *p, vsie_precision prec) {
@@ -684,7 +711,7 @@ void plan_forward_cf(vsie_problem *p, vsie_precision prec, WsPlan &pl) {
 
 void apply_forward_cf(vsie_problem *p, int f, vsie_precision prec, const double2 *x, double2 *y, hipStream_t s) {
     const int64_t n = p->m.n, nv = p->m.n_vol, ns = n - nv;
-    const int g = p->tune.sym_groups;
+    const int g = sym_group(p);
     const CfCounts cc = cf_counts(p);
     const int64_t slots = cc.slots, cs = cc.cs, fs = cc.fs, ffs = cc.ffs;
     const SlotBuffers sb = slot_buffers(p, prec, {slots * nv, cs * nv, fs * ns, ffs * ns}, 0);
@@ -738,7 +765,7 @@ struct SymLayout {
 SymLayout sym_layout(const vsie_problem *p, vsie_precision prec) {
     const int64_t n = p->m.n, nv = p->m.n_vol, ns = n - nv;
     SymLayout L;
-    L.slots = sym_slots(nv, p->tune.sym_groups);
+    L.slots = sym_slots(nv, sym_group(p));
     if (ns > 0) choose_chunks(ns, p->G.count, p->tune.vec_target_waves, L.chGf, L.ncGf);
     choose_chunks(n, p->F.count, p->tune.vec_target_waves, L.chF, L.ncF);
     size_t off[5];
@@ -763,7 +790,7 @@ void apply_forward_sym(vsie_problem *p, int f, vsie_precision prec, const double
         return;
     }
     const int64_t n = p->m.n, nv = p->m.n_vol, ns = n - nv;
-    const int g = p->tune.sym_groups;
+    const int g = sym_group(p);
     const SymLayout L = sym_layout(p, prec);
     const int64_t slots = L.slots, chGf = L.chGf, chF = L.chF;
     const int ncGf = L.ncGf, ncF = L.ncF;
@@ -793,19 +820,9 @@ void apply_forward_sym(vsie_problem *p, int f, vsie_precision prec, const double
                       p->m.diag + static_cast<int64_t>(f) * n, x, y, s);
 }
 
-// The once-per-pair kernels write one partial per point and partner group
-// (counted here at the FP64 size); above this size (c4-scale meshes) the
-// one-sided kernels are used.
-constexpr double kSymPartialCap = 8.0 * (1 << 30);
-
 bool use_sym(const vsie_problem *p, int nrhs) {
     if (nrhs != 1 || p->tune.sym_groups <= 0 || !p->g_is_cells) return false;
-    const int64_t nv = p->m.n_vol, ns = p->m.n - nv;
-    double bytes = static_cast<double>(sym_slots(nv, p->tune.sym_groups)) * nv;
-    if (p->tune.cell_face && ns > 0)
-        bytes += static_cast<double>(cf_groups(ns)) * nv + static_cast<double>(cf_groups(nv)) * ns +
-                 static_cast<double>(sym_slots(ns, kFaceGroups)) * ns;
-    return bytes * sizeof(double2) <= kSymPartialCap;
+    return sym_partial_entries(p, sym_group(p)) * sizeof(double2) <= kSymPartialCap;
 }
 
 void plan_forward(vsie_problem *p, vsie_precision prec, int nrhs, WsPlan &pl) {
@@ -903,7 +920,7 @@ void plan_adjoint_sym(vsie_problem *p, vsie_precision prec, WsPlan &pl) {
 
 void apply_adjoint_sym(vsie_problem *p, int f, vsie_precision prec, const double2 *x, double2 *y, hipStream_t s) {
     const int64_t n = p->m.n, nv = p->m.n_vol, ns = n - nv;
-    const int g = p->tune.sym_groups;
+    const int g = sym_group(p);
     const CfCounts cc = cf_counts(p);
     const int64_t slots = cc.slots, cs = cc.cs, fs = cc.fs, ffs = cc.ffs;
     const SlotBuffers sb = slot_buffers(p, prec, {slots * nv, cs * nv, fs * ns, ffs * ns}, 0);

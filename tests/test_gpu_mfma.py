@@ -103,7 +103,8 @@ def test_matvec_multi_frequency(V, prec):
 def test_c4_multi_frequency_sampled_rows(V):
     """Cube + ellipsoid on the 100^3 grid (n = 1,076,336): 8 frequencies x 16
     plane-wave incidences in one multi-frequency FP32 product; sampled rows of
-    every frequency against the oracle."""
+    every frequency against the oracle.  Then one column in FP64 and FP32 on
+    the once-per-pair kernels at this size."""
     import torch
     mesh, mat, k0s, dirs, _ = W.config_problem("c4")
     say("c4 multi-frequency: n", mesh.n, "k0", k0s)
@@ -120,19 +121,27 @@ def test_c4_multi_frequency_sampled_rows(V):
         e = parity_err(host(Y[f * R:(f + 1) * R])[rows], ref)
         say("  k0 %.0f: rel err %.3e" % (k, e))
         assert e <= TOL32
-    # the FP64 operator at this size (the refinement residual of the c4
-    # solves): one column, where the once-per-pair kernels would need more
-    # than their partial-sum cap and the one-sided kernels run
+    # one column at this size in both precisions: the once-per-pair kernels,
+    # with cell groups of 8 tiles so that their slot partials stay within
+    # the cap (about 3.2e9 partials: 52 GB in FP64, against 83 GB with the
+    # default groups of 4)
     d = O.discretise(mesh, mat, k0s[0])
     x1 = host(X[:1])
-    P.profile(True)
-    y1 = host(P.matvec(X[:1].contiguous(), f=0, prec=V.VSIE_FP64))
-    st = P.kernel_stats()
-    P.profile(False)
-    e64 = parity_err(y1.reshape(-1)[rows], O.matvec(d, x1.reshape(-1, 1), rows=rows)[:, 0])
-    say("  FP64, one column: rel err %.3e, kernels %s" % (e64, sorted(st)))
-    assert e64 <= TOL64
-    assert "fwd_single_layer_fp64" in st and not any(k.startswith("sym_") for k in st)
+    ref1 = O.matvec(d, x1.reshape(-1, 1), rows=rows)[:, 0]
+    ws = P.workspace_size(V.VSIE_OP_MATVEC, nrhs=1, prec=V.VSIE_FP64)
+    say("  one-column FP64 workspace %.1f GB" % (ws / 1e9))
+    assert 50e9 < ws < 56e9
+    for prec, tol, key in ((V.VSIE_FP64, TOL64, "sym_single_layer_fp64"),
+                           (V.VSIE_FP32, TOL32, "sym_single_layer_fp32")):
+        P.profile(True)
+        y1 = host(P.matvec(X[:1].contiguous(), f=0, prec=prec))
+        st = P.kernel_stats()
+        P.profile(False)
+        e1 = parity_err(y1.reshape(-1)[rows], ref1)
+        say("  %s, one column: rel err %.3e, cell-cell %.1f ms, kernels %s"
+            % (key[-4:], e1, st[key]["ms"], sorted(st)))
+        assert e1 <= tol
+        assert not any(k.startswith("fwd_single_layer") for k in st)
     P.close()
     del X, Y
     torch.cuda.empty_cache()

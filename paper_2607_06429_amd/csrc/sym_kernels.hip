@@ -174,8 +174,14 @@ __device__ __forceinline__ void store_slot(void *base, int64_t i, double re, dou
         static_cast<double2 *>(base)[i] = make_double2(re, im);
 }
 
+// Waves per SIMD the compiler must leave room for: the FP64 single-layer
+// variant with groups of 8 (one-column products of the largest meshes) needs
+// two registers fewer than it would take to keep 4 waves resident.
+constexpr int sym_min_waves(int g, bool f64, bool t) { return (g == 8 && f64 && !t) ? 4 : 1; }
+
 template <int G, typename AT, bool T, bool ADJ>
-__global__ __launch_bounds__(kBlock) void sym_kernel(SymArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sym_min_waves(G, sizeof(AT) == 8, T))))
+void sym_kernel(SymArgs a) {
     static_assert(T || !ADJ, "the adjoint variant of the symmetric kernel is the grad-alpha one");
     using C2 = typename c2_of<AT>::type;
     // per-wave copies of the B tile, stored twice in a row (entries 0..127) so
@@ -224,13 +230,17 @@ __global__ __launch_bounds__(kBlock) void sym_kernel(SymArgs a) {
             }
         }
 
-        double accAr[G], accAi[G], accBr[G], accBi[G];
+        // B-side sums per tile of group J; the A side of tile ta is complete
+        // when its row of tile pairs ends (on the diagonal, I = J, its B-side
+        // sum from the rows before is complete by then too) and is stored there
+        double accBr[G], accBi[G];
 #pragma unroll
-        for (int t = 0; t < G; ++t) accAr[t] = accAi[t] = accBr[t] = accBi[t] = 0.0;
+        for (int t = 0; t < G; ++t) accBr[t] = accBi[t] = 0.0;
 
         for (int ta = 0; ta < G; ++ta) {
             const int at = I * G + ta;
             if (at >= a.tiles) break;
+            double accAr = 0.0, accAi = 0.0;
             double xa, ya, za;
             AT uar, uai;
             load_point<AT>(a, static_cast<int64_t>(at) * 64 + lane, lane, xa, ya, za, uar, uai);
@@ -392,34 +402,36 @@ __global__ __launch_bounds__(kBlock) void sym_kernel(SymArgs a) {
                         sBi *= sbh;
                     }
                 }
+                accAr += static_cast<double>(sAr);
+                accAi += static_cast<double>(sAi);
                 // tile-indexed accumulators with compile-time register indices
 #pragma unroll
                 for (int t = 0; t < G; ++t) {
-                    if (t == ta) {
-                        accAr[t] += static_cast<double>(sAr);
-                        accAi[t] += static_cast<double>(sAi);
-                    }
                     if (t == tb) {
                         accBr[t] += static_cast<double>(sBr);
                         accBi[t] += static_cast<double>(sBi);
                     }
                 }
             }
-        }
-        // group I receives slot J, group J receives slot I (one slot for I = J)
-#pragma unroll
-        for (int t = 0; t < G; ++t) {
-            const int at = I * G + t;
+            // group I receives slot J (on the diagonal with its B-side sums)
             const int64_t pa = static_cast<int64_t>(at) * 64 + lane;
-            if (at < a.tiles && pa < a.ng) {
-                double r = accAr[t], i = accAi[t];
+            if (pa < a.ng) {
                 if (I == J) {
-                    r += accBr[t];
-                    i += accBi[t];
+#pragma unroll
+                    for (int t = 0; t < G; ++t) {
+                        if (t == ta) {
+                            accAr += accBr[t];
+                            accAi += accBi[t];
+                        }
+                    }
                 }
-                store_slot<AT>(a.part, static_cast<int64_t>(J) * a.ldp + pa, r, i);
+                store_slot<AT>(a.part, static_cast<int64_t>(J) * a.ldp + pa, accAr, accAi);
             }
-            if (I != J) {
+        }
+        // group J receives slot I
+        if (I != J) {
+#pragma unroll
+            for (int t = 0; t < G; ++t) {
                 const int bt = J * G + t;
                 const int64_t pb = static_cast<int64_t>(bt) * 64 + lane;
                 if (bt < a.tiles && pb < a.ng) store_slot<AT>(a.part, static_cast<int64_t>(I) * a.ldp + pb, accBr[t], accBi[t]);

@@ -174,13 +174,16 @@ __device__ __forceinline__ void store_slot(void *base, int64_t i, double re, dou
         static_cast<double2 *>(base)[i] = make_double2(re, im);
 }
 
-// Waves per SIMD the compiler must leave room for: the FP64 single-layer
-// variant with groups of 8 (one-column products of the largest meshes) needs
-// two registers fewer than it would take to keep 4 waves resident.
-constexpr int sym_min_waves(int g, bool f64, bool t) { return (g == 8 && f64 && !t) ? 4 : 1; }
+// Waves per SIMD the compiler must leave room for, where that costs no
+// instruction in the pair loop: the FP64 single-layer variant with groups of
+// 8 (one-column products of the largest meshes) and the FP32 forward
+// grad-alpha variants (6 waves, which their LDS tile allows too).
+constexpr int sym_min_waves(int g, bool f64, bool t, bool adj) {
+    return (g == 8 && f64 && !t) ? 4 : ((t && !adj && !f64) ? 6 : 1);
+}
 
 template <int G, typename AT, bool T, bool ADJ>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sym_min_waves(G, sizeof(AT) == 8, T))))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sym_min_waves(G, sizeof(AT) == 8, T, ADJ))))
 void sym_kernel(SymArgs a) {
     static_assert(T || !ADJ, "the adjoint variant of the symmetric kernel is the grad-alpha one");
     using C2 = typename c2_of<AT>::type;
@@ -196,9 +199,15 @@ void sym_kernel(SymArgs a) {
         C2 u[128];
         AT vx[128], vy[128], vz[128];
         C2 w[128];
-        AT s[128];  // adjoint: -s' of the B points
     };
-    using BTile = typename std::conditional<T, BTileT, BTileS>::type;
+    struct BTileA {
+        double x[128], y[128], z[128];
+        C2 u[128];
+        AT vx[128], vy[128], vz[128];
+        C2 w[128];
+        AT s[128];  // -s' of the B points
+    };
+    using BTile = typename std::conditional<ADJ, BTileA, typename std::conditional<T, BTileT, BTileS>::type>::type;
     __shared__ BTile lb[kWavesPerBlock];
     const int lane = threadIdx.x & 63;
     const int wib = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
@@ -598,14 +607,17 @@ __global__ __launch_bounds__(kBlock) void cf_kernel(CfArgs a) {
                 if (ti < a.ctiles && a.ctile_t[ti]) item_t = true;
             }
         }
-        double accAr[G], accAi[G], accBr[G], accBi[G];
+        // the faces' sums per tile of group J; a cell tile's sum is complete
+        // when its row of tile pairs ends and is stored there
+        double accBr[G], accBi[G];
 #pragma unroll
-        for (int t = 0; t < G; ++t) accAr[t] = accAi[t] = accBr[t] = accBi[t] = 0.0;
+        for (int t = 0; t < G; ++t) accBr[t] = accBi[t] = 0.0;
 
         for (int ta = 0; ta < G; ++ta) {
             const int at = I * G + ta;
             if (at >= a.ctiles) break;
             const int64_t c = static_cast<int64_t>(at) * 64 + lane;
+            double accAr = 0.0, accAi = 0.0;
             double xa, ya, za;
             AT uar, uai;
             if (c < a.nc) {
@@ -771,24 +783,20 @@ __global__ __launch_bounds__(kBlock) void cf_kernel(CfArgs a) {
                     sBr = rot1(fma(er, uar, fma(-ei, uai, sBr)));
                     sBi = rot1(fma(er, uai, fma(ei, uar, sBi)));
                 }
+                accAr += static_cast<double>(sAr);
+                accAi += static_cast<double>(sAi);
 #pragma unroll
                 for (int t = 0; t < G; ++t) {
-                    if (t == ta) {
-                        accAr[t] += static_cast<double>(sAr);
-                        accAi[t] += static_cast<double>(sAi);
-                    }
                     if (t == tb) {
                         accBr[t] += static_cast<double>(sBr);
                         accBi[t] += static_cast<double>(sBi);
                     }
                 }
             }
+            if (c < a.nc) store_slot<AT>(a.pc, static_cast<int64_t>(J) * a.ldc + c, accAr, accAi);
         }
 #pragma unroll
         for (int t = 0; t < G; ++t) {
-            const int at = I * G + t;
-            const int64_t c = static_cast<int64_t>(at) * 64 + lane;
-            if (at < a.ctiles && c < a.nc) store_slot<AT>(a.pc, static_cast<int64_t>(J) * a.ldc + c, accAr[t], accAi[t]);
             const int bt = J * G + t;
             const int64_t f = static_cast<int64_t>(bt) * 64 + lane;
             if (bt < a.ftiles && f < a.nf) store_slot<AT>(a.pf, static_cast<int64_t>(I) * a.ldf + f, accBr[t], accBi[t]);

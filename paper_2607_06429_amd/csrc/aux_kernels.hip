@@ -566,6 +566,157 @@ __global__ void sum_slabs_kernel(int64_t m, int64_t cnt, int parts, const double
     C[j * ldc + i] = make_double2(sx, sy);
 }
 
+// Tall-skinny block products of block GMRES for blocks of at most
+// kTsMaxCols columns (the Gram-Schmidt projections V^H W and updates
+// W -= V H, CholeskyQR's Gram matrices and W T^{-1}, the deflation).  n is
+// long (the unknowns), the other two sizes are small, and the operands are
+// column-major.  Both products are bound by reading the tall operand once.
+//
+// ts_cn_kernel: slab partials of C = A^H B, A rows x m, B rows x nn
+// (nn <= 8 NQ).  Workgroup (slab, tile) takes 32 columns of A and every
+// column of B over the rows of its slab, 32 rows at a time staged in LDS
+// (each column's 32 rows are one 512-byte read); thread t owns A column
+// t % 32 of the tile and B columns t / 32 + 8 u.  The partials go to
+// P[slab][r][j] (an m x nn column-major block per slab) and are added in slab
+// order by sum_slabs_kernel.
+constexpr int kTsTile = 32;
+
+template <int NQ>
+__global__ __launch_bounds__(kT) void ts_cn_kernel(int64_t rows, int m, int nn, const double2 *__restrict__ A,
+                                                   int64_t lda, const double2 *__restrict__ B, int64_t ldb,
+                                                   int64_t slab_rows, double2 *__restrict__ P) {
+    __shared__ double2 sa[kTsTile][kTsTile + 1];
+    __shared__ double2 sb[kTsTile][8 * NQ + 1];
+    const int t = threadIdx.x, j = t & 31, q = t >> 5, i = t & 31;
+    const int j0 = blockIdx.y * kTsTile;
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * slab_rows;
+    const int64_t r1 = r0 + slab_rows < rows ? r0 + slab_rows : rows;
+    double ar[NQ], ai[NQ];
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) ar[u] = ai[u] = 0.0;
+    for (int64_t base = r0; base < r1; base += kTsTile) {
+        const int len = static_cast<int>(r1 - base < kTsTile ? r1 - base : kTsTile);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = q + 8 * u;
+            double2 v = make_double2(0.0, 0.0);
+            if (i < len && j0 + c < m) v = A[static_cast<int64_t>(j0 + c) * lda + base + i];
+            sa[i][c] = v;
+        }
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) {
+            const int c = q + 8 * u;
+            double2 v = make_double2(0.0, 0.0);
+            if (i < len && c < nn) v = B[static_cast<int64_t>(c) * ldb + base + i];
+            sb[i][c] = v;
+        }
+        __syncthreads();
+        // rows past the slab's end were staged as zeros
+#pragma unroll 8
+        for (int ii = 0; ii < kTsTile; ++ii) {
+            const double2 a = sa[ii][j];
+#pragma unroll
+            for (int u = 0; u < NQ; ++u) {
+                const double2 b = sb[ii][q + 8 * u];
+                // conj(a) b
+                ar[u] = fma(a.x, b.x, fma(a.y, b.y, ar[u]));
+                ai[u] = fma(a.x, b.y, fma(-a.y, b.x, ai[u]));
+            }
+        }
+        __syncthreads();
+    }
+    double2 *Ps = P + static_cast<int64_t>(blockIdx.x) * m * nn;
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+        const int r = q + 8 * u;
+        if (j0 + j < m && r < nn) Ps[static_cast<int64_t>(r) * m + j0 + j] = make_double2(ar[u], ai[u]);
+    }
+}
+
+// ts_nn_kernel: C = alpha A B (+ C when accumulate), A rows x k, B k x nn
+// (nn <= 8 NQ, on the device), C rows x nn.  One thread per row keeps the
+// row's nn sums; B is staged 64 rows at a time in LDS and read as broadcasts.
+template <int NQ>
+__global__ __launch_bounds__(kT) void ts_nn_kernel(int64_t rows, int k, int nn, double alpha, int accumulate,
+                                                   const double2 *__restrict__ A, int64_t lda,
+                                                   const double2 *__restrict__ B, int64_t ldb,
+                                                   double2 *__restrict__ C, int64_t ldc) {
+    constexpr int NC = 8 * NQ;
+    __shared__ double2 sb[64][NC];
+    const int t = threadIdx.x;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kT + t;
+    double cr[NC], ci[NC];
+#pragma unroll
+    for (int r = 0; r < NC; ++r) cr[r] = ci[r] = 0.0;
+    for (int j0 = 0; j0 < k; j0 += 64) {
+        const int len = k - j0 < 64 ? k - j0 : 64;
+        __syncthreads();
+        for (int e = t; e < 64 * NC; e += kT) {
+            const int jj = e & 63, r = e >> 6;
+            sb[jj][r] = (jj < len && r < nn) ? B[static_cast<int64_t>(r) * ldb + j0 + jj] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        if (i < rows) {
+            const double2 *Ac = A + static_cast<int64_t>(j0) * lda + i;
+#pragma unroll 4
+            for (int jj = 0; jj < len; ++jj) {
+                const double2 a = Ac[static_cast<int64_t>(jj) * lda];
+#pragma unroll
+                for (int r = 0; r < NC; ++r) {
+                    const double2 b = sb[jj][r];
+                    cr[r] = fma(a.x, b.x, fma(-a.y, b.y, cr[r]));
+                    ci[r] = fma(a.x, b.y, fma(a.y, b.x, ci[r]));
+                }
+            }
+        }
+    }
+    if (i >= rows) return;
+#pragma unroll
+    for (int r = 0; r < NC; ++r) {
+        if (r < nn) {
+            double2 *c = C + static_cast<int64_t>(r) * ldc + i;
+            double2 v = make_double2(alpha * cr[r], alpha * ci[r]);
+            if (accumulate) {
+                const double2 o = *c;
+                v.x += o.x;
+                v.y += o.y;
+            }
+            *c = v;
+        }
+    }
+}
+
+// The same sum for many slabs (the tall-skinny products' partials: a few
+// hundred slabs of a small block): a workgroup takes 16 outputs, its 16 groups
+// of 16 threads add every 16th slab (consecutive outputs, so each load is one
+// 256-byte run), and the group sums are added in group order in LDS.
+__global__ __launch_bounds__(kT) void sum_slabs_grouped_kernel(int64_t m, int64_t cnt, int parts,
+                                                               const double2 *__restrict__ P,
+                                                               double2 *__restrict__ C, int64_t ldc) {
+    __shared__ double2 part[16][17];
+    const int t = threadIdx.x, o = t & 15, g = t >> 4;
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * 16 + o;
+    double sx = 0.0, sy = 0.0;
+    if (e < cnt) {
+#pragma unroll 4
+        for (int q = g; q < parts; q += 16) {
+            const double2 v = P[static_cast<int64_t>(q) * cnt + e];
+            sx += v.x;
+            sy += v.y;
+        }
+    }
+    part[g][o] = make_double2(sx, sy);
+    __syncthreads();
+    if (g == 0 && e < cnt) {
+        for (int q = 1; q < 16; ++q) {
+            sx += part[q][o].x;
+            sy += part[q][o].y;
+        }
+        const int64_t j = e / m, i = e - j * m;
+        C[j * ldc + i] = make_double2(sx, sy);
+    }
+}
+
 // Cholesky factor of a small Hermitian Gram matrix G = T^H T (r x r,
 // column-major, r <= kSmallChol), T upper triangular, in one workgroup: the
 // right-looking (outer-product) form, one pivot per step.  As the host
@@ -901,10 +1052,61 @@ void launch_small_chol(const double2 *G, int r, double2 *T, double2 *Ti, const d
     LAUNCH_CHECK();
 }
 
+// Rows per slab of ts_cn: about 2048 workgroups over the slabs and 32-column
+// tiles, at least 256 rows (8 staged tiles) per slab, a multiple of 32.
+int64_t ts_cn_slab_rows(int64_t m, int64_t rows) {
+    const int64_t tiles = (m + kTsTile - 1) / kTsTile;
+    int64_t slabs = (2048 + tiles - 1) / tiles;
+    slabs = std::max<int64_t>(1, std::min(slabs, rows / 256));
+    const int64_t sr = (rows + slabs - 1) / slabs;
+    return std::max<int64_t>(kTsTile, (sr + kTsTile - 1) / kTsTile * kTsTile);
+}
+
+size_t ts_cn_bytes(int64_t m, int64_t nn, int64_t rows) {
+    if (rows <= 0) return 0;
+    const int64_t sr = ts_cn_slab_rows(m, rows);
+    return sizeof(double2) * static_cast<size_t>(m * nn * ((rows + sr - 1) / sr));
+}
+
+void ts_cn(int64_t rows, int64_t m, int64_t nn, const double2 *A, int64_t lda, const double2 *B, int64_t ldb,
+           double2 *P, double2 *C, int64_t ldc, hipStream_t s) {
+    if (m <= 0 || nn <= 0) return;
+    if (rows < 1 || nn > kTsMaxCols || m > INT32_MAX || lda < rows || ldb < rows || ldc < m)
+        fail(VSIE_E_INVALID, "tall-skinny product: operand shapes out of range");
+    const int64_t sr = ts_cn_slab_rows(m, rows);
+    const int64_t slabs = (rows + sr - 1) / sr;
+    const int64_t tiles = (m + kTsTile - 1) / kTsTile;
+    if (slabs > 0x7fffffff || tiles > 65535) fail(VSIE_E_INVALID, "tall-skinny product: grid too large");
+    const dim3 grid(static_cast<unsigned>(slabs), static_cast<unsigned>(tiles));
+    const int mi = static_cast<int>(m), ni = static_cast<int>(nn);
+    if (nn <= 8) hipLaunchKernelGGL(ts_cn_kernel<1>, grid, dim3(kT), 0, s, rows, mi, ni, A, lda, B, ldb, sr, P);
+    else if (nn <= 16) hipLaunchKernelGGL(ts_cn_kernel<2>, grid, dim3(kT), 0, s, rows, mi, ni, A, lda, B, ldb, sr, P);
+    else hipLaunchKernelGGL(ts_cn_kernel<4>, grid, dim3(kT), 0, s, rows, mi, ni, A, lda, B, ldb, sr, P);
+    LAUNCH_CHECK();
+    blas_sum_slabs(m, nn, static_cast<int>(slabs), P, C, ldc, s);
+}
+
+void ts_nn(int64_t rows, int64_t k, int64_t nn, double alpha, bool accumulate, const double2 *A, int64_t lda,
+           const double2 *B, int64_t ldb, double2 *C, int64_t ldc, hipStream_t s) {
+    if (rows <= 0 || nn <= 0) return;
+    if (nn > kTsMaxCols || k > INT32_MAX || (k > 0 && (lda < rows || ldb < k)) || ldc < rows)
+        fail(VSIE_E_INVALID, "tall-skinny product: operand shapes out of range");
+    const unsigned blocks = blocks_for(rows);
+    const int ki = static_cast<int>(k), ni = static_cast<int>(nn), acc = accumulate ? 1 : 0;
+    if (nn <= 8) hipLaunchKernelGGL(ts_nn_kernel<1>, dim3(blocks), dim3(kT), 0, s, rows, ki, ni, alpha, acc, A, lda, B, ldb, C, ldc);
+    else if (nn <= 16) hipLaunchKernelGGL(ts_nn_kernel<2>, dim3(blocks), dim3(kT), 0, s, rows, ki, ni, alpha, acc, A, lda, B, ldb, C, ldc);
+    else hipLaunchKernelGGL(ts_nn_kernel<4>, dim3(blocks), dim3(kT), 0, s, rows, ki, ni, alpha, acc, A, lda, B, ldb, C, ldc);
+    LAUNCH_CHECK();
+}
+
 void blas_sum_slabs(int64_t m, int64_t nn, int parts, const double2 *P, double2 *C, int64_t ldc, hipStream_t s) {
     const int64_t cnt = m * nn;
     if (cnt == 0) return;
-    hipLaunchKernelGGL(sum_slabs_kernel, dim3(blocks_for(cnt)), dim3(kT), 0, s, m, cnt, parts, P, C, ldc);
+    if (parts > 16)
+        hipLaunchKernelGGL(sum_slabs_grouped_kernel, dim3(blocks_for(cnt, 16)), dim3(kT), 0, s, m, cnt, parts, P, C,
+                           ldc);
+    else
+        hipLaunchKernelGGL(sum_slabs_kernel, dim3(blocks_for(cnt)), dim3(kT), 0, s, m, cnt, parts, P, C, ldc);
     LAUNCH_CHECK();
 }
 }  // namespace vsie

@@ -2056,6 +2056,7 @@ int64_t tall_slabs(int64_t m, int64_t nn, int64_t k) {
 }
 // bytes of the slab partials of zgemm_tall_cn (0 when one GEMM does it)
 size_t tall_bytes(int64_t m, int64_t nn, int64_t k) {
+    if (nn <= kTsMaxCols) return ts_cn_bytes(m, nn, k);
     const int64_t slabs = tall_slabs(m, nn, k);
     if (slabs <= 1) return 0;
     const int64_t rows = (k + slabs - 1) / slabs;
@@ -2065,6 +2066,13 @@ size_t tall_bytes(int64_t m, int64_t nn, int64_t k) {
 
 void zgemm_tall_cn(vsie_problem *p, int64_t m, int64_t nn, int64_t k, const double2 *A, int64_t lda,
                    const double2 *B, int64_t ldb, double2 *C, int64_t ldc, hipStream_t s) {
+    if (nn <= kTsMaxCols) {
+        // blocks of few columns: the hand-written slab kernel (rocBLAS tiles are
+        // 64 columns wide and would leave most of each tile empty)
+        double2 *P = static_cast<double2 *>(p->bsk.get(ts_cn_bytes(m, nn, k)));
+        ts_cn(k, m, nn, A, lda, B, ldb, P, C, ldc, s);
+        return;
+    }
     const int64_t slabs = tall_slabs(m, nn, k);
     if (slabs <= 1) {
         zgemm(p, true, m, nn, k, 1.0, A, lda, B, ldb, 0.0, C, ldc);
@@ -2089,6 +2097,18 @@ void zgemm_tall_cn(vsie_problem *p, int64_t m, int64_t nn, int64_t k, const doub
     blas_sum_slabs(m, nn, parts, P, C, ldc, s);
 }
 
+// C = alpha A B + beta C for tall A (n x k) and a block of nn columns: the
+// hand-written kernel for nn <= kTsMaxCols (alpha = 1 or -1, beta = 0 or 1,
+// the only forms the block solver uses), rocBLAS otherwise.
+void zgemm_tall_nn(vsie_problem *p, int64_t n, int64_t nn, int64_t k, double alpha, const double2 *A, int64_t lda,
+                   const double2 *B, int64_t ldb, double beta, double2 *C, int64_t ldc, hipStream_t s) {
+    if (nn <= kTsMaxCols && (alpha == 1.0 || alpha == -1.0) && (beta == 0.0 || beta == 1.0)) {
+        ts_nn(n, k, nn, alpha, beta == 1.0, A, lda, B, ldb, C, ldc, s);
+        return;
+    }
+    zgemm(p, false, n, nn, k, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
 // CholeskyQR2 of the n x r block Wsrc: dst = Wsrc T^{-1} with orthonormal
 // columns and T upper triangular (host).  tmp is an n x r scratch block.
 void cholqr2(vsie_problem *p, int64_t n, int r, const double2 *Wsrc, double2 *tmp, double2 *dst,
@@ -2108,7 +2128,7 @@ void cholqr2(vsie_problem *p, int64_t n, int r, const double2 *Wsrc, double2 *tm
         std::vector<double2> th(Ti.size());
         for (size_t t = 0; t < Ti.size(); ++t) th[t] = make_double2(Ti[t].real(), Ti[t].imag());
         to_device(Gd, th, s);
-        zgemm(p, false, n, r, r, 1.0, src, n, Gd, r, 0.0, out, n);
+        zgemm_tall_nn(p, n, r, r, 1.0, src, n, Gd, r, 0.0, out, n, s);
         src = out;
     }
     // T = T2 T1
@@ -2133,10 +2153,10 @@ void cholqr2_dev(vsie_problem *p, int64_t n, int r, const double2 *Wsrc, double2
     double2 *G = buf, *T1 = buf + rr, *Ti = buf + 2 * rr, *T2 = buf + 3 * rr;
     zgemm_tall_cn(p, r, r, n, Wsrc, n, Wsrc, n, G, r, s);
     launch_small_chol(G, r, T1, Ti, nullptr, nullptr, status, s);
-    zgemm(p, false, n, r, r, 1.0, Wsrc, n, Ti, r, 0.0, tmp, n);
+    zgemm_tall_nn(p, n, r, r, 1.0, Wsrc, n, Ti, r, 0.0, tmp, n, s);
     zgemm_tall_cn(p, r, r, n, tmp, n, tmp, n, G, r, s);
     launch_small_chol(G, r, T2, Ti, T1, Tdev, status + 1, s);
-    zgemm(p, false, n, r, r, 1.0, tmp, n, Ti, r, 0.0, dst, n);
+    zgemm_tall_nn(p, n, r, r, 1.0, tmp, n, Ti, r, 0.0, dst, n, s);
 }
 
 // The host's reading of the two status words of cholqr2_dev.
@@ -2306,7 +2326,7 @@ void BlockCycle::begin() {
         zgemm_tall_cn(p_, kv_, Ra_, n_, use_->V, n_, Rres_, n_, D, kv_, s_);
         zgemm(p_, true, kr_, Ra_, kv_, 1.0, use_->Qk, kv_, D, kv_, 0.0, Z, kr_);
         zgemm(p_, false, kv_, Ra_, kr_, 1.0, use_->Qk, kv_, Z, kr_, 0.0, D, kv_);
-        zgemm(p_, false, n_, Ra_, kv_, -1.0, use_->V, n_, D, kv_, 1.0, Rres_, n_);
+        zgemm_tall_nn(p_, n_, Ra_, kv_, -1.0, use_->V, n_, D, kv_, 1.0, Rres_, n_, s_);
         std::vector<double2> zh;
         to_host(zh, Z, static_cast<size_t>(kr_) * Ra_, s_);
         std::vector<cd> z(zh.size());
@@ -2314,7 +2334,7 @@ void BlockCycle::begin() {
         tri_solve_upper_cols(use_->R.data(), kr_, kr_, Ra_, z.data());
         for (size_t q = 0; q < z.size(); ++q) zh[q] = make_double2(z[q].real(), z[q].imag());
         to_device(D, zh, s_);
-        zgemm(p_, false, n_, Ra_, kr_, 1.0, use_->V, n_, D, kr_, 0.0, W_, n_);
+        zgemm_tall_nn(p_, n_, Ra_, kr_, 1.0, use_->V, n_, D, kr_, 0.0, W_, n_, s_);
         blas_scatter_add(n_, Ra_, act(), W_, x_, ldx_, s_);
     }
     std::vector<cd> S0;
@@ -2363,17 +2383,17 @@ void BlockCycle::after_product() {
                 zp = Z;
             }
             zgemm(p_, false, kv, Ra, kr, 1.0, use_->Qk, kv, zp, kr, 0.0, D, kv);
-            zgemm(p_, false, n, Ra, kv, -1.0, use_->V, n, D, kv, 1.0, W, n);
+            zgemm_tall_nn(p_, n, Ra, kv, -1.0, use_->V, n, D, kv, 1.0, W, n, s_);
         }
         if (dev_qr()) {  // this pass's coefficients stay in the stage until the step's one copy
             double2 *Hd = stage() + static_cast<int64_t>(pass) * kb * Ra;
             zgemm_tall_cn(p_, kb, Ra, n, V_, n, W, n, Hd, kb, s_);
-            zgemm(p_, false, n, Ra, kb, -1.0, V_, n, Hd, kb, 1.0, W, n);
+            zgemm_tall_nn(p_, n, Ra, kb, -1.0, V_, n, Hd, kb, 1.0, W, n, s_);
             continue;
         }
         double2 *Hd = static_cast<double2 *>(p_->bh.get(sizeof(double2) * static_cast<size_t>(ldH_) * Ra));
         zgemm_tall_cn(p_, kb, Ra, n, V_, n, W, n, Hd, kb, s_);
-        zgemm(p_, false, n, Ra, kb, -1.0, V_, n, Hd, kb, 1.0, W, n);
+        zgemm_tall_nn(p_, n, Ra, kb, -1.0, V_, n, Hd, kb, 1.0, W, n, s_);
         to_host(hh, Hd, static_cast<size_t>(kb) * Ra, s_);
         for (int c = 0; c < Ra; ++c)
             for (int64_t i = 0; i < kb; ++i)
@@ -2478,11 +2498,11 @@ int BlockCycle::finish() {
         tri_solve_upper_cols(use_->R.data(), kr, kr, Ra, by.data());
         for (size_t q = 0; q < Wc.size(); ++q) Wc[q] = make_double2(by[q].real(), by[q].imag());
     }
-    zgemm(p_, false, n, Ra, kk, 1.0, V_, n, Yd, kk, 0.0, W_, n);
+    zgemm_tall_nn(p_, n, Ra, kk, 1.0, V_, n, Yd, kk, 0.0, W_, n, s_);
     if (kr > 0) {  // x += V y - U (Bm y)
         double2 *D = Dd();
         to_device(D, Wc, s_);
-        zgemm(p_, false, n, Ra, kr, -1.0, use_->V, n, D, kr, 1.0, W_, n);
+        zgemm_tall_nn(p_, n, Ra, kr, -1.0, use_->V, n, D, kr, 1.0, W_, n, s_);
     }
     blas_scatter_add(n, Ra, act(), W_, x_, ldx_, s_);
     VSIE_HIP(hipStreamSynchronize(s_));

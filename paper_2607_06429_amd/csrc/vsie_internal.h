@@ -423,6 +423,16 @@ void blas_scatter_add(int64_t n, int nslots, const int32_t *act, const double2 *
                       hipStream_t s);
 // C (m x nn, leading dimension ldc) = sum of parts consecutive m x nn column-major slabs of P
 void blas_sum_slabs(int64_t m, int64_t nn, int parts, const double2 *P, double2 *C, int64_t ldc, hipStream_t s);
+// Tall-skinny block products for blocks of at most kTsMaxCols columns (see
+// ts_cn_kernel and ts_nn_kernel): C (m x nn) = A^H B with A rows x m and B
+// rows x nn, through ts_cn_bytes(m, nn, rows) bytes of slab partials P; and
+// C = alpha A B (+ C when accumulate) with A rows x k, B k x nn on the device.
+constexpr int kTsMaxCols = 32;
+size_t ts_cn_bytes(int64_t m, int64_t nn, int64_t rows);
+void ts_cn(int64_t rows, int64_t m, int64_t nn, const double2 *A, int64_t lda, const double2 *B, int64_t ldb,
+           double2 *P, double2 *C, int64_t ldc, hipStream_t s);
+void ts_nn(int64_t rows, int64_t k, int64_t nn, double alpha, bool accumulate, const double2 *A, int64_t lda,
+           const double2 *B, int64_t ldb, double2 *C, int64_t ldc, hipStream_t s);
 // Cholesky factor G = T^H T of a Hermitian r x r Gram matrix on the device
 // (r <= kSmallChol, one workgroup), with T^{-1} and optionally T Tprev; see
 // small_chol_kernel for the shift and the status codes.

@@ -414,6 +414,26 @@ def test_block_gmres(V, prec, restart):
     assert parity_err(got[:, :5], ref[:, :5]) <= TOL_SOLVE
 
 
+@pytest.mark.parametrize("R", [12, 24, 40])
+def test_block_gmres_widths(V, R):
+    """Block widths on each path of the tall block products: 12 and 24
+    columns on the hand-written kernels (two and four groups of 8 columns,
+    ragged), 40 on rocBLAS; FP32 + refinement with short cycles (restarts and
+    block deflation) against LU, on c0 (n = 3,736: 14 row slabs)."""
+    mesh, mat, k0 = case("c0")
+    d = O.discretise(mesh, mat, k0)
+    b = np.concatenate([O.plane_wave(d.pts, k0, W.fibonacci_sphere(R - 2)),
+                        W.seeded_complex((d.n, 2), seed=83)], axis=1)
+    ref = O.solve_lu(d, b)
+    P = V.Problem.from_mesh(mesh, mat, [k0])
+    x, info = P.solve(dev(b).contiguous(), prec=V.VSIE_FP32, tol=1e-11, restart=6, block=True, max_outer=400)
+    e = parity_err(host(x), ref)
+    say("  block width %d: %s, rel err vs LU %.2e" % (R, info, e))
+    assert info["status"] == V.VSIE_OK
+    assert e <= TOL_SOLVE
+    P.close()
+
+
 def test_block_gmres_dense_adjoint(V):
     say("block gmres, assembled FP32, adjoint")
     mesh, mat, k0 = case("cube")

@@ -2252,7 +2252,19 @@ class BlockCycle {
     double2 *output() const { return W_; }
     int width() const { return Ra_; }
     int freq() const { return f_; }
-    void after_product();
+    void after_product() {
+        step_device();
+        step_host();
+    }
+    // after_product in two halves: the device work of the step (Gram-Schmidt
+    // and CholeskyQR; the next basis block is queued when it returns) and the
+    // host's QR of the block Hessenberg with the convergence test.  Between
+    // them the caller may queue the next step's product on input_ahead()
+    // when lookahead_ok(): the host QR then overlaps the product.
+    void step_device();
+    void step_host();
+    bool lookahead_ok() const;
+    const double2 *input_ahead() const { return V_ + static_cast<int64_t>(j_ + 1) * Ra_ * n_; }
     int finish();
     void add_operator_seconds(double t) { sec_[0] += t; }
     // largest residual estimate after the last step, relative to the cycle start
@@ -2311,8 +2323,12 @@ class BlockCycle {
     std::vector<double> UU_;
     int j_ = 0, jdone_ = 0;
     bool done_ = false;
-    double worst_ = 0.0;
+    double worst_ = 1.0;
     double sec_[4] = {0, 0, 0, 0};  // operator, Gram-Schmidt, CholeskyQR, host QR
+    // the step's new block column of the Hessenberg matrix and R block, from
+    // step_device to step_host
+    std::vector<cd> Hc_, T_;
+    clk::time_point tm_;
 };
 
 void BlockCycle::begin() {
@@ -2358,15 +2374,17 @@ void BlockCycle::begin() {
     UU_.assign(static_cast<size_t>(m_) * Ra_, 0.0);
 }
 
-void BlockCycle::after_product() {
+void BlockCycle::step_device() {
     const int j = j_;
     const int Ra = Ra_;
     const int64_t n = n_, kr = kr_, kv = kv_;
-    clk::time_point tm = clk::now();
+    clk::time_point &tm = tm_;
+    tm = clk::now();
     for (int r : rhs_) (prec_ == VSIE_FP64 ? cnt_.mv64 : cnt_.mv32)[r]++;
     const int64_t kb = static_cast<int64_t>(j + 1) * Ra;
     double2 *W = W_;
-    std::vector<cd> Hc(static_cast<size_t>(kb + Ra) * Ra, 0.0);  // new block column, rows 0..kb+Ra
+    std::vector<cd> &Hc = Hc_;
+    Hc.assign(static_cast<size_t>(kb + Ra) * Ra, 0.0);  // new block column, rows 0..kb+Ra
     std::vector<double2> hh;
     for (int pass = 0; pass < 2; ++pass) {
         if (kr > 0) {
@@ -2400,7 +2418,7 @@ void BlockCycle::after_product() {
                 Hc[static_cast<size_t>(c) * (kb + Ra) + i] += cd(hh[c * kb + i].x, hh[c * kb + i].y);
     }
     mark(tm, 1);
-    std::vector<cd> T;
+    std::vector<cd> &T = T_;
     double2 *Z = static_cast<double2 *>(p_->ax.get(sizeof(double2) * static_cast<size_t>(n) * Ra));
     if (dev_qr()) {
         const int64_t hb = kb * Ra, rr = static_cast<int64_t>(Ra) * Ra;
@@ -2419,6 +2437,29 @@ void BlockCycle::after_product() {
         cholqr2(p_, n, Ra, W, Z, V_ + kb * n, T, s_);
     }
     mark(tm, 2);
+}
+
+// A step whose residual estimate (the previous step's) is still this far above
+// the tolerance is not expected to end the cycle, so the next product may be
+// queued before the host QR; a wrong guess only costs the unused product.
+constexpr double kLookaheadMargin = 1e3;
+
+bool BlockCycle::lookahead_ok() const {
+    if (p_->progress || j_ + 1 >= m_) return false;
+    for (int r : rhs_)
+        if (cnt_.it[r] + 1 >= iter_cap_) return false;
+    double tmax = 0.0;
+    for (double t : ctol_) tmax = std::max(tmax, t);
+    return worst_ > kLookaheadMargin * tmax;
+}
+
+void BlockCycle::step_host() {
+    const int j = j_;
+    const int Ra = Ra_;
+    const int64_t kb = static_cast<int64_t>(j + 1) * Ra;
+    clk::time_point &tm = tm_;
+    std::vector<cd> &Hc = Hc_;
+    const std::vector<cd> &T = T_;
     for (int c = 0; c < Ra; ++c)
         for (int i = 0; i <= c; ++i) Hc[static_cast<size_t>(c) * (kb + Ra) + kb + i] = T[static_cast<size_t>(c) * Ra + i];
     // previous reflectors on the new columns (independent per column)
@@ -2544,16 +2585,24 @@ int block_cycle(vsie_problem *p, int f, vsie_precision prec, bool adjoint, const
     double2 *W = static_cast<double2 *>(p->w.get(sizeof(double2) * static_cast<size_t>(n) * Ra));
     BlockCycle c(p, f, prec, rhs, Rres, rn, ctol, m, iter_cap, x, ldx, cnt, s, V, W, save, use, Bm, qk, true);
     c.begin();
+    bool queued = false;  // the product of the current step is already on the stream
     while (c.wants_product()) {
-        const auto t0 = std::chrono::steady_clock::now();
-        if (p->progress) VSIE_HIP(hipStreamSynchronize(s));
-        apply_op(p, f, prec, adjoint, Ra, c.input(), n, c.output(), n, s);
-        if (p->progress) {
-            VSIE_HIP(hipStreamSynchronize(s));
-            c.add_operator_seconds(std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+        if (!queued) {
+            const auto t0 = std::chrono::steady_clock::now();
+            if (p->progress) VSIE_HIP(hipStreamSynchronize(s));
+            apply_op(p, f, prec, adjoint, Ra, c.input(), n, c.output(), n, s);
+            if (p->progress) {
+                VSIE_HIP(hipStreamSynchronize(s));
+                c.add_operator_seconds(std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+            }
         }
-        c.after_product();
+        c.step_device();
+        // far from convergence, queue the next product before the host QR
+        queued = c.lookahead_ok();
+        if (queued) apply_op(p, f, prec, adjoint, Ra, c.input_ahead(), n, c.output(), n, s);
+        c.step_host();
     }
+    // a queued product the cycle did not use only wrote W
     return c.finish();
 }
 

@@ -32,6 +32,9 @@
  *   then Omega_2, Gamma_1 then Gamma_2, the paper's block order).
  * * `stream` is a hipStream_t (NULL selects the null stream).  Calls enqueue
  *   work on it; vsie_solve synchronises it to read scalars each iteration.
+ *   When a product returns an error, work it queued before the error may
+ *   still run on `stream`; the solves synchronise `stream` before returning,
+ *   also on error.
  * * No exception crosses the ABI: every call returns a vsie_status, and
  *   vsie_last_error() gives a message for the calling thread's last failure.
  * * Memory: input host arrays are copied during vsie_assemble; the problem

@@ -3367,6 +3367,8 @@ vsie_status vsie_solve(vsie_problem *p, int32_t f, vsie_precision prec, int32_t 
         if (info) *info = total;
         if (result == VSIE_E_NOCONV) g_last_error = "GMRES did not reach the tolerance";
     });
+    // an error part-way leaves no queued work behind the return
+    if (st != VSIE_OK && p) (void)hipStreamSynchronize(as_stream(stream));
     return st != VSIE_OK ? st : result;
 }
 
@@ -3411,6 +3413,7 @@ vsie_status vsie_solve_multi(vsie_problem *p, int32_t f0, int32_t nf, vsie_preci
         }
         if (result == VSIE_E_NOCONV) g_last_error = "GMRES did not reach the tolerance at every frequency";
     });
+    if (st != VSIE_OK && p) (void)hipStreamSynchronize(as_stream(stream));
     return st != VSIE_OK ? st : result;
 }
 

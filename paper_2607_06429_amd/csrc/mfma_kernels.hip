@@ -259,9 +259,10 @@ struct Mfma64Args {
     int part0;
 };
 
+
 template <int CLS, int NB, bool M3>
 __global__ __launch_bounds__(kBlock) void mfma64_fwd_kernel(Mfma64Args a) {
-    constexpr int TG = 2;
+    constexpr int TG = mfma64_groups(CLS, NB);
     constexpr int TT = 16 * TG;
     const int lane = threadIdx.x & 63;
     const int wib = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
@@ -524,7 +525,7 @@ bool mfma64_nb_ok(int nb) { return nb == 1 || nb == 2 || nb == 4; }
 
 void launch_mfma64_forward(const Mfma64Job &J, hipStream_t s, PairProfiler *prof) {
     if (J.n_t == 0 || J.n_s == 0 || J.nf == 0) return;
-    constexpr int TT = 32;
+    const int TT = 16 * mfma64_groups(J.cls, J.nb);
     const int cbw = 16 * J.nb;
     if (!mfma64_nb_ok(J.nb)) fail(VSIE_E_INVALID, "FP64 matrix-core pair kernel: unsupported column blocking");
     if (J.ncol % cbw != 0 || J.ncol < J.nrhs || J.nrhs <= 0)

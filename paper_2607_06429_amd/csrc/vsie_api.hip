@@ -1147,14 +1147,14 @@ Mfma64Layout mfma64_layout(const vsie_problem *p, int nf, int nrhs) {
     const int cbw = 16 * L.nb;
     L.ncol = (nrhs + cbw - 1) / cbw * cbw;
     const int64_t want = static_cast<int64_t>(mfma_grid(2, 1)) * (kBlock / 64) * p->tune.items_per_wave;
-    const int64_t tiles = (n + 31) / 32;
-    const int64_t items_per_chunk = static_cast<int64_t>(nf) * (L.ncol / cbw) * tiles;
-    auto chunking = [&](int64_t ns, int64_t &chunk, int &nc) {
+    // target tiles of 16 mfma64_groups points
+    auto chunking = [&](int64_t ns, int64_t tile_pts, int64_t &chunk, int &nc) {
         if (ns <= 0) {
             chunk = 4;
             nc = 0;
             return;
         }
+        const int64_t items_per_chunk = static_cast<int64_t>(nf) * (L.ncol / cbw) * ((n + tile_pts - 1) / tile_pts);
         int64_t c = (want + items_per_chunk - 1) / items_per_chunk;
         c = std::max<int64_t>(1, std::min<int64_t>(c, std::max<int64_t>(1, ns / 512)));
         const int64_t cap = p->tune.mfma_chunk_max;
@@ -1162,8 +1162,8 @@ Mfma64Layout mfma64_layout(const vsie_problem *p, int nf, int nrhs) {
         chunk = ((ns + c - 1) / c + 3) / 4 * 4;
         nc = static_cast<int>((ns + chunk - 1) / chunk);
     };
-    chunking(p->G.count, L.chG, L.ncG);
-    chunking(p->F.count, L.chF, L.ncF);
+    chunking(p->G.count, 16 * mfma64_groups(kClassG, L.nb), L.chG, L.ncG);
+    chunking(p->F.count, 16 * mfma64_groups(kClassF, L.nb), L.chF, L.ncF);
     L.fstride = static_cast<int64_t>(L.ncG + L.ncF) * nrhs * n;
     L.part = sizeof(double2) * static_cast<size_t>(std::max<int64_t>(1, L.fstride * nf));
     L.ldqG = (p->G.count + kMfmaPad) * L.ncol;

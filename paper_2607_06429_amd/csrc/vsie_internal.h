@@ -197,6 +197,13 @@ struct Mfma64Job {
 };
 void launch_mfma64_forward(const Mfma64Job &J, hipStream_t s, PairProfiler *prof);
 bool mfma64_nb_ok(int nb);
+// 16-target groups per wave: two (one source load and one charge load serve
+// 32 targets), except for the double layers with 64 columns per evaluation,
+// whose extra source record and FP64 terms leave two groups at one wave per
+// SIMD: one group there (measured on c2, 128 columns: 37.2 ms against 42.0 ms
+// with two groups, although the loop issues 12% more per pair; the single
+// layer took 177.2 ms with one group against 160.5 ms with two)
+constexpr int mfma64_groups(int cls, int nb) { return (cls == kClassF && nb == 4) ? 1 : 2; }
 void launch_pack_mfma64(SrcClass cls, const SourceSet &src, const double *sp, int64_t sp_fstride, int nf,
                         int nrhs, int ncol, const double2 *x, int64_t ldx, int64_t xfs, double2 *q, int64_t ldq_f,
                         hipStream_t s);

@@ -24,7 +24,7 @@ Acoustics"):
 * exterior field by the representation formula (m = 1 in Omega_0) ... section 2.3.1
 * its far-field pattern (leading terms of G and grad G as |x| -> inf) ... section 2.3.1
 
-Readings where the paper is silent (also listed in the design doc):
+Readings where the paper is silent:
 
 * the T and K self-terms are zero (a flat face has (y - x).n = 0; the gradient
   of a ball's potential vanishes at its centre);

@@ -434,6 +434,32 @@ def test_block_gmres_widths(V, R):
     P.close()
 
 
+@pytest.mark.parametrize("R", [8, 40])
+def test_block_lookahead_keeps_results(V, capfd, R):
+    """Far from convergence the block solver queues the next product before
+    the host QR; progress mode turns that off.  Both runs must give the same
+    iterations and bit-identical solutions (8 columns: device CholeskyQR; 40:
+    the host's)."""
+    import torch
+    mesh, mat, k0 = case("c0")
+    d = O.discretise(mesh, mat, k0)
+    b = np.concatenate([O.plane_wave(d.pts, k0, W.fibonacci_sphere(R - 1)),
+                        W.seeded_complex((d.n, 1), seed=84)], axis=1)
+    P = V.Problem.from_mesh(mesh, mat, [k0])
+    runs = []
+    for progress in (False, True):
+        x, info = P.solve(dev(b).contiguous(), prec=V.VSIE_FP32, tol=1e-11, block=True, progress=progress)
+        runs.append((x, info))
+    err = capfd.readouterr().err
+    assert "block step" in err
+    (x0, i0), (x1, i1) = runs
+    say("  width %d: %s / %s" % (R, i0, i1))
+    assert i0 == i1
+    assert torch.equal(x0, x1)
+    assert parity_err(host(x0), O.solve_lu(d, b)) <= TOL_SOLVE
+    P.close()
+
+
 def test_block_gmres_dense_adjoint(V):
     say("block gmres, assembled FP32, adjoint")
     mesh, mat, k0 = case("cube")

@@ -90,6 +90,11 @@ def test_adjoint_one_column(V, name, prec):
     say("  adjoint one column %s %s: once per pair %s, rel err %.2e, vs one-sided %.2e" % (name, prec, pairs, e, e0))
     assert pairs
     assert e <= tol and e0 <= 2 * tol
+    # groups of 8 tiles (what the library picks for the largest meshes)
+    P.set_tuning(sym_groups=8)
+    y8 = host(P.matvec_adjoint(dev(lam), prec=pr))
+    P.set_tuning(sym_groups=4)
+    assert parity_err(y8, ref) <= tol
     if name in ("c0", "lognormal"):
         # an adjoint solve through the same path, against LU
         import scipy.linalg as sla
